@@ -1,0 +1,256 @@
+#!/usr/bin/env python3
+"""Throughput of the spin/polarisation-resolved SF-QED particle step on one MI355X.
+
+Workload (the focused-pulse configuration): 1e7 electrons, gamma0 = 2000 (10 % spread),
+1 mrad divergence, unpolarised, colliding head-on with a circularly polarised focused
+pulse (w0 = 3 um, a0 = 100, 10 cycles), dt = T0/500, NCS with spin flip and photon Stokes
+output.  The bunch is placed at the collision (step 2400 of the 6000-step run) so the
+timed steps see the peak field.  One step = one fused gather + Boris + T-BMT + NCS pass
+over all electrons, with photons appended in order.
+
+Prints one JSON line: mixed-precision particle-steps/s (the headline), the FP64 GPU path
+on the same input and draws, their spectrum / spin / polarisation differences, the
+roofline of the fused kernel and the CPU oracle on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes per lepton-step of the fused kernel: read x, p (48 B), S, id (8 B);
+# write x, p (48 B), S.  S is 3 x 4 B (mixed) or 3 x 8 B (FP64).
+BYTES_LEPTON = {"mixed": 48 + 12 + 8 + 48 + 12, "fp64": 48 + 24 + 8 + 48 + 24}
+# per emitted photon: read the parent weight (8 B); write x, k, w (56 B), xi and e1
+# (6 x 4 or 6 x 8 B), id (8 B), alive (1 B)
+BYTES_PHOTON = {"mixed": 8 + 56 + 24 + 8 + 1, "fp64": 8 + 56 + 48 + 8 + 1}
+KERNEL_SOURCES = ["qed_kernels.hip", "qed_dev.hpp", "qed_internal.hpp"]
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2306_11288_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(prec: str):
+    """HBM bytes per launch from the committed counter summary, if it was taken on the
+    current kernel sources; else None."""
+    p = os.path.join(ROOT, "profiles", "traffic_fused_lepton_step_c2.json")
+    try:
+        d = json.load(open(p))
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_hash") != kernel_hash():
+        return None
+    return d.get(prec, {}).get("bytes_per_launch")
+
+
+def run_gpu(prec, cfg, steps, warmup, torch, Q, per_launch_events=True):
+    precision = Q.QED_MIXED if prec == "mixed" else Q.QED_FP64
+    n = len(cfg["leptons"]["x"])
+    ctx = Q.Context(dt=cfg["dt"], procs=cfg["procs"], seed=cfg["seed"], id_start=cfg["next_id"],
+                    precision=precision)
+    L = Q.Leptons.from_state(cfg["leptons"], precision=precision)
+    cap = int(n * 0.03 * (steps + warmup)) + 1_000_000
+    G = Q.Photons(cap, precision=precision)
+    segs = Q.whole(cfg["field"])
+    s0 = cfg["start_step"]
+    for s in range(s0, s0 + warmup):
+        ctx.step_leptons(segs, L, G, s)
+    torch.cuda.synchronize()
+    n_before = G.count
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)] if per_launch_events else []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    if per_launch_events:
+        ev[0].record(stream)
+    for k, s in enumerate(range(s0 + warmup, s0 + warmup + steps)):
+        ctx.step_leptons(segs, L, G, s)
+        if per_launch_events:
+            ev[k + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    launch_ms = [ev[k].elapsed_time(ev[k + 1]) for k in range(steps)] if per_launch_events else []
+    status = ctx.read_status()
+    return {"ctx": ctx, "L": L, "G": G, "wall": wall, "launch_ms": launch_ms, "n": n,
+            "photons_timed": G.count - n_before, "photons_total": G.count, "photon_start": n_before,
+            "status": status}
+
+
+def detector_stokes(G, start, torch):
+    """Stokes vectors of photons [start, count) rotated to the detector basis (y, z)
+    projected transverse to each photon's direction (the post-processing step of
+    Algorithm 1)."""
+    n = G.count
+    sl = slice(start, n)
+    k = torch.stack([G.kx[sl], G.ky[sl], G.kz[sl]]).double()
+    nh = k / torch.linalg.norm(k, dim=0)
+    e1 = torch.stack([G.e1x[sl], G.e1y[sl], G.e1z[sl]]).double()
+    yh = torch.zeros_like(nh)
+    yh[1] = 1.0
+    d1 = yh - nh * (yh * nh).sum(0)
+    d1 = d1 / torch.linalg.norm(d1, dim=0)
+    e2 = torch.cross(nh, e1, dim=0)
+    c, s = (e1 * d1).sum(0), (e2 * d1).sum(0)
+    c2, s2 = c * c - s * s, 2 * c * s
+    x1, x2, x3 = G.xi1[sl].double(), G.xi2[sl].double(), G.xi3[sl].double()
+    return torch.stack([c2 * x1 - s2 * x3, x2, s2 * x1 + c2 * x3])
+
+
+def error_metrics(a, b, gamma0, torch):
+    """Mixed (b) against FP64 (a) after the same steps from the same state and draws."""
+    out = {}
+    La, Lb = a["L"], b["L"]
+    n = a["n"]
+    ea = torch.sqrt(1 + La.px[:n] ** 2 + La.py[:n] ** 2 + La.pz[:n] ** 2)
+    eb = torch.sqrt(1 + Lb.px[:n] ** 2 + Lb.py[:n] ** 2 + Lb.pz[:n] ** 2)
+    out["mean_energy_rel"] = abs(float(eb.mean() / ea.mean()) - 1)
+
+    def hist(x, lo, hi, bins, log=False):
+        x = x.double()
+        if log:
+            x = torch.log10(x.clamp_min(1e-300))
+        h = torch.histc(x.float(), bins=bins, min=lo, max=hi).double()
+        return h / max(float(h.sum()), 1.0)
+
+    def l1(h1, h2):
+        return float((h1 - h2).abs().sum())
+
+    Ga, Gb = a["G"], b["G"]
+    sa, sb = a["photon_start"], b["photon_start"]
+    wa = torch.sqrt(Ga.kx[sa:Ga.count] ** 2 + Ga.ky[sa:Ga.count] ** 2 + Ga.kz[sa:Ga.count] ** 2) / gamma0
+    wb = torch.sqrt(Gb.kx[sb:Gb.count] ** 2 + Gb.ky[sb:Gb.count] ** 2 + Gb.kz[sb:Gb.count] ** 2) / gamma0
+    out["photon_spectrum_L1"] = l1(hist(wa, -5, 0, 100, True), hist(wb, -5, 0, 100, True))
+    out["photon_count_rel"] = abs((Gb.count - sb) / max(Ga.count - sa, 1) - 1)
+    for name, (ta, tb) in {"electron_theta_y_L1": (La.py[:n] / La.px[:n], Lb.py[:n] / Lb.px[:n]),
+                           "electron_theta_z_L1": (La.pz[:n] / La.px[:n], Lb.pz[:n] / Lb.px[:n]),
+                           "photon_theta_y_L1": (Ga.ky[sa:Ga.count] / Ga.kx[sa:Ga.count],
+                                                 Gb.ky[sb:Gb.count] / Gb.kx[sb:Gb.count])}.items():
+        out[name] = l1(hist(ta, -0.05, 0.05, 100), hist(tb, -0.05, 0.05, 100))
+    Sa = torch.stack([La.sx[:n], La.sy[:n], La.sz[:n]]).double().mean(1)
+    Sb = torch.stack([Lb.sx[:n], Lb.sy[:n], Lb.sz[:n]]).double().mean(1)
+    out["mean_spin_abs_diff"] = float(torch.linalg.norm(Sa - Sb))
+    out["polarisation_degree_fp64"] = float(torch.linalg.norm(Sa))
+    out["polarisation_degree_mixed"] = float(torch.linalg.norm(Sb))
+    xa, xb = detector_stokes(Ga, sa, torch).mean(1), detector_stokes(Gb, sb, torch).mean(1)
+    out["photon_xi2_abs_diff"] = abs(float(xa[1] - xb[1]))
+    out["photon_xi3_abs_diff"] = abs(float(xa[2] - xb[2]))
+    out["photon_xi3_detector_fp64"] = float(xa[2])
+    return out
+
+
+def cpu_baseline(cfg_small, budget_s=15.0):
+    """The oracle as it stands (single-threaded C, FP64 tables) on a bounded sample of the
+    same workload: the first `n` electrons of the bunch, stepped until the budget is used."""
+    import numpy as np
+
+    import oracle
+    st = cfg_small["leptons"]
+    n = len(st["x"])
+    L = oracle.LeptonArrays.from_state(st)
+    G = oracle.PhotonArrays.empty(200 * n)
+    sim = oracle.Sim(dt=cfg_small["dt"], procs=cfg_small["procs"], seed=cfg_small["seed"],
+                     next_id=cfg_small["next_id"])
+    f = oracle.make_field(cfg_small["field"])
+    oracle.tables()
+    s0 = cfg_small["start_step"]
+    steps = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < budget_s and steps < 2000:
+        sim.step(f, L, None, G, s0 + steps)
+        steps += 1
+    el = time.perf_counter() - t0
+    del np
+    return {"value": n * steps / el, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n} electrons of the same bunch x {steps} steps from step {s0} "
+                      f"(single-threaded C oracle, FP64 tables), {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--n", type=int, default=10_000_000, help="electrons (default: the full workload)")
+    ap.add_argument("--cpu-sample", type=int, default=4000)
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this benchmark measures one GPU; the particle step shards by index "
+                                   "range with no per-step communication, and no multi-GPU run is part of it",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+
+    import paper_2306_11288_amd as Q
+    import workloads as W
+
+    torch.cuda.set_device(0)
+    start = 2400
+    cfg = W.c2(args.n, start_step=start)
+    print(f"[bench] workload {cfg['name']} n={args.n} steps={args.steps} warmup={args.warmup}", file=sys.stderr,
+          flush=True)
+    mixed = run_gpu("mixed", cfg, args.steps, args.warmup, torch, Q)
+    print(f"[bench] mixed done: {args.steps * args.n / mixed['wall']:.3e} particle-steps/s", file=sys.stderr,
+          flush=True)
+    fp64 = None
+    if not args.no_fp64:
+        fp64 = run_gpu("fp64", cfg, args.steps, args.warmup, torch, Q)
+        print(f"[bench] fp64 done: {args.steps * args.n / fp64['wall']:.3e} particle-steps/s", file=sys.stderr,
+              flush=True)
+
+    ms_per_step = 1e3 * mixed["wall"] / args.steps
+    value = args.n * args.steps / mixed["wall"]
+    launch_ms = sum(mixed["launch_ms"]) / len(mixed["launch_ms"])
+    ph_per_launch = mixed["photons_timed"] / args.steps
+    alg_bytes = args.n * BYTES_LEPTON["mixed"] + ph_per_launch * BYTES_PHOTON["mixed"]
+    achieved = alg_bytes / (launch_ms * 1e-3) / 1e9
+    tr = measured_traffic("mixed")
+    result = {
+        "metric": "particle-steps/s (push+spin+QED) mixed vs FP64 GPU at stated spectrum error",
+        "value": value, "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64 (x, p, event probability f64; rates, sampling, spin, Stokes f32)",
+        "data": "synthetic (seeded numpy Philox bunch; analytic focused pulse)",
+        "config": {"workload": "c2_focused_cp_pulse_a0_100_1e7_electrons_gamma2000", "electrons": args.n,
+                   "gamma0": 2000, "a0": 100, "w0_um": 3.0, "ncycles": 10, "dt": "T0/500",
+                   "start_step": start, "processes": "NCS + spin flip + photon Stokes"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": tr,
+                     "kernel": "k_leptons_emit<float,true> (fused gather+Boris+T-BMT+NCS)",
+                     "avg_launch_ms": launch_ms, "algorithmic_bytes_per_launch": alg_bytes,
+                     "photons_per_launch": ph_per_launch},
+        "status_bits": mixed["status"],
+    }
+    if fp64 is not None:
+        f_launch = sum(fp64["launch_ms"]) / len(fp64["launch_ms"])
+        f_bytes = args.n * BYTES_LEPTON["fp64"] + fp64["photons_timed"] / args.steps * BYTES_PHOTON["fp64"]
+        result["fp64"] = {"value": args.n * args.steps / fp64["wall"], "ms_per_step": 1e3 * fp64["wall"] / args.steps,
+                          "avg_launch_ms": f_launch, "achieved_GBs": f_bytes / (f_launch * 1e-3) / 1e9,
+                          "status_bits": fp64["status"]}
+        result["speedup_mixed_over_fp64"] = result["value"] / result["fp64"]["value"]
+        result["error_vs_fp64"] = error_metrics(fp64, mixed, 2000.0, torch)
+    if not args.no_cpu_baseline:
+        small = W.c2(args.cpu_sample, start_step=start + args.warmup)
+        result["cpu_baseline"] = cpu_baseline(small, args.cpu_budget)
+    print(json.dumps(result))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,191 @@
+/*
+ * qed.h -- C ABI of libqed: the per-particle hot path of spin/polarisation-resolved
+ * strong-field QED in a particle-in-cell step (Wan et al., arXiv:2306.11288), on AMD
+ * Instinct MI355X (gfx950).
+ *
+ * The path, per time step n (t^n = n dt):
+ *   photons : field gather -> basis rotation to the pair-production frame (Sec. III.C.2,
+ *             eq. rotation) -> vacuum birefringence (Sec. III.F, eq. rotation2,
+ *             Algorithm 1) -> nonlinear Breit-Wheeler pair creation (Sec. III.D) ->
+ *             straight-line move
+ *   leptons : field gather (Sec. II.D-E) -> Boris push (Sec. II.A, eqs. boris1-boris6)
+ *             -> T-BMT spin rotation (Sec. III.B, eqs. bmteqn, bmt-boris1-4) ->
+ *             spin/polarisation-resolved nonlinear Compton emission (Sec. III.C.1)
+ * in the order of the paper's Spin-QED chain (Sec. IV) without the radiative-correction
+ * and bremsstrahlung stages.
+ *
+ * Conventions
+ *  - Units: t in 1/omega, x in 1/k, momenta in m c, energies in m c^2, fields in
+ *    m c omega / e (paper Sec. I).
+ *  - Particle buffers are structure-of-arrays in device memory, owned by the caller.
+ *    The library never allocates or frees them.  `count` is a device-resident int64;
+ *    kernels read it and (for output lists) update it, so calls need no host sync.
+ *  - Every call is asynchronous on the given stream and returns synchronously only
+ *    argument errors (nothing is enqueued then; see qed_last_error).  Conditions found
+ *    on the device set sticky bits in a device status word (qed_read_status).
+ *  - Appended particles are stored in parent-index order (photons: order of the
+ *    emitting lepton; pairs: order of the decaying photon) with ids taken from a
+ *    device counter owned by the context (photon: id_base + rank; pair: electron
+ *    id_base + 2 rank, positron id_base + 2 rank + 1).  Appends past `capacity` are
+ *    dropped, still consume ids, and set QED_ST_OVERFLOW.
+ *  - Random numbers: Philox4x32-10 with key = particle id and counter = (step low word,
+ *    step bits 32..47 | stream << 16, seed low, seed high), stream 1 = NCS, 2 = NBW;
+ *    uniforms (u + 1/2) 2^-32 in the order r1 (energy), r2 (event), r3 (spin),
+ *    r4 (photon polarisation).
+ *  - A context is used by one host thread and one stream at a time (the append calls
+ *    share its scan state).
+ */
+#ifndef QED_H
+#define QED_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t *hipStream_t;
+/* opaque context: device tables, constants, id counter, status word, scan state */
+typedef struct qed_ctx qed_ctx_t;
+
+typedef enum { QED_OK = 0, QED_EARG = 1, QED_ENOMEM = 2, QED_EHIP = 3, QED_ESTATE = 4 } qed_status;
+typedef enum { QED_FP64 = 0, QED_MIXED = 1 } qed_precision;
+
+/* process mask (qed_config.procs) */
+enum { QED_PROC_NCS = 1, QED_PROC_NCS_STOKES = 2, QED_PROC_NBW = 4, QED_PROC_VB = 8 };
+/* sticky device status bits */
+enum {
+    QED_ST_OVERFLOW = 1,   /* an append went past capacity (dropped)                   */
+    QED_ST_NAN = 2,        /* non-finite momentum, position or spin after a push        */
+    QED_ST_PMAX = 4,       /* a per-step event probability exceeded cfg.p_max          */
+    QED_ST_EPS_LT1 = 8,    /* a pair member was born with energy below m c^2            */
+    QED_ST_CLAMP = 16,     /* chi above the tabulated range (value clamped)             */
+    QED_ST_SCAN = 32       /* an ordered-append wait hit its spin limit (never expected) */
+};
+/* field kinds */
+enum { QED_FIELD_NONE = 0, QED_FIELD_CONST = 1, QED_FIELD_PW = 2, QED_FIELD_GAUSS = 3,
+       QED_FIELD_GRID2D = 4 };
+/* table ids for qed_table_export */
+enum { QED_TAB_BESSEL = 0, QED_TAB_NCS_RATE = 1, QED_TAB_NCS_CDF = 2, QED_TAB_NBW_RATE = 3,
+       QED_TAB_NBW_CDF = 4, QED_TAB_VB = 5 };
+
+typedef struct {
+    double xi_L;        /* hbar omega / m c^2 of the reference wavelength (Sec. III.A.1)   */
+    double alpha;       /* fine-structure constant                                        */
+    double a_e;         /* anomalous magnetic moment, g = 2 (1 + a_e) (eq. bmteqn)        */
+    double dt;          /* time step                                                      */
+    double p_max;       /* event probability per step above which QED_ST_PMAX is set      */
+    uint64_t seed;      /* Philox seed (counter words 2-3)                                */
+    uint64_t id_start;  /* id of the first particle the library creates                   */
+    int32_t precision;  /* qed_precision: storage/compute type of S, Stokes, basis, rates  */
+    uint32_t procs;     /* QED_PROC_* mask                                                */
+} qed_config;
+
+/* electrons (charge -1) or positrons (+1).  sx, sy, sz are double for QED_FP64 and float
+ * for QED_MIXED contexts.  Momenta live at half steps, positions at integer steps.      */
+typedef struct {
+    double *x, *y, *z, *px, *py, *pz, *w;
+    void *sx, *sy, *sz;
+    uint64_t *id;
+    int64_t *count;     /* device scalar                                                  */
+    int64_t capacity;
+    int32_t charge;
+} qed_leptons;
+
+/* photons: momentum k (|k| = energy), Stokes parameters xi in the basis (e1, n x e1, n),
+ * n = k/|k|; xi and e1 are double (QED_FP64) or float (QED_MIXED).  alive = 0 marks a
+ * photon removed by pair creation (compact with qed_compact_photons).                   */
+typedef struct {
+    double *x, *y, *z, *kx, *ky, *kz, *w;
+    void *xi1, *xi2, *xi3, *e1x, *e1y, *e1z;
+    uint64_t *id;
+    uint8_t *alive;
+    int64_t *count;
+    int64_t capacity;
+} qed_photons;
+
+/* External fields.
+ *  CONST : uniform static E = e0, B = b0.
+ *  PW    : plane wave along -x, A(phi) = a0 sin^2(pi phi/L)[sin(phi+phase0) e1 +
+ *          cos(phi+phase0) e2 (circular only)], phi = t + x - phi_start in [0, L],
+ *          L = 2 pi ncycles, e1 = (0, cos pol_angle, sin pol_angle), e2 = x_hat cross e1;
+ *          E = -dA/dphi, B = -x_hat cross E.
+ *  GAUSS : zeroth-order paraxial Gaussian pulse along -x focused at x_focus, waist w0,
+ *          same envelope; E = a0 (w0/w) exp(-r^2/w^2) env [cos(Theta) e1 + sin(Theta) e2],
+ *          Theta = phi + phase0 + Gouy - curvature phase; B = -x_hat cross E.
+ *  GRID2D: six fp32 arrays [ny][nx] on a 2D Yee cell in the x-y plane, node (i,j) at
+ *          (gx0 + i dx, gy0 + j dy); Ex (i+1/2,j), Ey (i,j+1/2), Ez (i,j), Bx (i,j+1/2),
+ *          By (i+1/2,j), Bz (i+1/2,j+1/2); gathered with TSC weights (Sec. II.D-E), nodes
+ *          outside the grid contribute zero.                                            */
+typedef struct {
+    int32_t kind, circular;
+    double a0, ncycles, phase0, pol_angle, w0, x_focus, phi_start;
+    double e0[3], b0[3];
+    const float *grid[6];
+    int32_t nx, ny;
+    double dx, dy, gx0, gy0;
+} qed_field;
+
+/* a contiguous index range of one particle list under one field (one collision) */
+typedef struct {
+    int64_t begin, end;
+    qed_field field;
+} qed_segment;
+
+/* Create a context and build the rate / spectrum / Bessel / birefringence tables on the
+ * current device (FP64 quadrature, FP32 copies for QED_MIXED).  Synchronises `stream`.
+ * Errors: QED_EARG (null pointers, non-positive dt or xi_L, unknown precision),
+ * QED_ENOMEM, QED_EHIP.                                                                   */
+qed_status qed_init_tables(qed_ctx_t **ctx_out, const qed_config *cfg, hipStream_t stream);
+qed_status qed_destroy(qed_ctx_t *ctx);
+
+/* E6[6 i + (0..5)] = Ex, Ey, Ez, Bx, By, Bz at x_i, t^n (doubles, caller-owned device
+ * buffer of 6 * capacity).  Fields of lepton i come from the segment containing i
+ * (segments sorted by begin; indices outside every segment see no field).               */
+qed_status qed_gather(qed_ctx_t *ctx, const qed_segment *segs, int nseg, const qed_leptons *p,
+                      double *E6, int64_t step, hipStream_t stream);
+/* Boris push and T-BMT rotation: p^{n-1/2} -> p^{n+1/2}, S^{n-1/2} -> S^{n+1/2},
+ * x^n -> x^{n+1}.  Fields from E6 (as written by qed_gather) or, if E6 is NULL, gathered
+ * in the same kernel.                                                                    */
+qed_status qed_push_spin(qed_ctx_t *ctx, const qed_segment *segs, int nseg, qed_leptons *p,
+                         const double *E6, int64_t step, hipStream_t stream);
+/* Nonlinear Compton step for leptons already pushed in this step, using the fields E6 of
+ * x^n (required).  Photons are appended to `out` (may be NULL: recoil and spin only).   */
+qed_status qed_emit(qed_ctx_t *ctx, const qed_segment *segs, int nseg, qed_leptons *p,
+                    const double *E6, qed_photons *out, int64_t step, hipStream_t stream);
+/* Fused gather + push + T-BMT + NCS in one kernel (the production path). */
+qed_status qed_step_leptons(qed_ctx_t *ctx, const qed_segment *segs, int nseg, qed_leptons *p,
+                            qed_photons *out, int64_t step, hipStream_t stream);
+/* Photon polarisation transport: basis rotation to E_red and, if QED_PROC_VB, the
+ * birefringent phase.  Does not move photons.                                           */
+qed_status qed_birefringence(qed_ctx_t *ctx, const qed_segment *segs, int nseg, qed_photons *g,
+                             int64_t step, hipStream_t stream);
+/* Basis rotation, NBW pair creation (if QED_PROC_NBW; pairs appended to em / ep, the
+ * photon marked dead) and the straight-line move x += n dt of surviving photons.        */
+qed_status qed_pair(qed_ctx_t *ctx, const qed_segment *segs, int nseg, qed_photons *g,
+                    qed_leptons *em, qed_leptons *ep, int64_t step, hipStream_t stream);
+/* Whole photon step in one kernel (= qed_birefringence then qed_pair, one rotation). */
+qed_status qed_step_photons(qed_ctx_t *ctx, const qed_segment *segs, int nseg, qed_photons *g,
+                            qed_leptons *em, qed_leptons *ep, int64_t step, hipStream_t stream);
+/* Stable compaction of the live photons of `in` into `out` (distinct buffers). */
+qed_status qed_compact_photons(qed_ctx_t *ctx, const qed_photons *in, qed_photons *out,
+                               hipStream_t stream);
+
+/* Synchronises `stream`, returns the sticky status bits; qed_clear_status zeroes them. */
+qed_status qed_read_status(qed_ctx_t *ctx, uint32_t *flags_out, hipStream_t stream);
+qed_status qed_clear_status(qed_ctx_t *ctx, hipStream_t stream);
+/* id counter (synchronises on read) */
+qed_status qed_get_next_id(qed_ctx_t *ctx, uint64_t *next_id, hipStream_t stream);
+qed_status qed_set_next_id(qed_ctx_t *ctx, uint64_t next_id, hipStream_t stream);
+/* Copies a table (FP64 master) to host memory in the layout of the table specification:
+ * BESSEL b1[NB] b2[NB] b3[NB]; NCS_RATE fa[NR] fk[NR]; NCS_CDF A[rows][cols] B[rows][cols];
+ * NBW_RATE ga[NP] gk[NP]; NBW_CDF A B; VB Mplus[NV] Mminus[NV].  n must equal the size
+ * returned by qed_table_size.                                                           */
+int64_t qed_table_size(int which);
+qed_status qed_table_export(qed_ctx_t *ctx, int which, double *host_out, int64_t n);
+/* Last argument / HIP error of this context as text (empty if none). */
+const char *qed_last_error(const qed_ctx_t *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

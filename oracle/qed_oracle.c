@@ -108,6 +108,25 @@ static void bessel_trio(double x, double *k13, double *k23, double *ik13) {
     *k13 = h * a; *k23 = h * b; *ik13 = h * c;
 }
 
+/* the same trio multiplied by exp(x): the integrand exp(-x (cosh t - 1)) stays finite
+ * where exp(x) itself would overflow                                                    */
+static void bessel_trio_scaled(double x, double *k13, double *k23, double *ik13) {
+    double h = 0.1;
+    if (x > 25.0) h = 0.5 / sqrt(x);
+    double T = acosh(1.0 + 60.0 / x) + 1.0;
+    int n = (int)(T / h) + 1;
+    double a = 0.5, b = 0.5, c = 0.5;
+    for (int i = 1; i <= n; ++i) {
+        double t = i * h, ch = cosh(t), sh = sinh(0.5 * t);
+        double e = exp(-2.0 * x * sh * sh);          /* cosh t - 1 = 2 sinh^2(t/2) */
+        double c13 = cosh(t / 3.0);
+        a += e * c13;
+        b += e * cosh(2.0 * t / 3.0);
+        c += e * c13 / ch;
+    }
+    *k13 = h * a; *k23 = h * b; *ik13 = h * c;
+}
+
 /* Gauss-Legendre nodes on [-1,1] by Newton iteration on P_n */
 #define GLN 10
 static double gl_x[GLN], gl_w[GLN];
@@ -405,11 +424,10 @@ orc_tables *orc_tables_build(void) {
     double hb = grid_h(B_LO, B_HI, NB);
     for (int i = 0; i < NB; ++i) {
         double x = exp(B_LO + i * hb), K1, K2, I;
-        bessel_trio(x, &K1, &K2, &I);
-        double ex = exp(x);
-        T->bes[0][i] = cbrt(x) * ex * K1;
-        T->bes[1][i] = cbrt(x * x) * ex * K2;
-        T->bes[2][i] = ex * I;
+        bessel_trio_scaled(x, &K1, &K2, &I);
+        T->bes[0][i] = cbrt(x) * K1;
+        T->bes[1][i] = cbrt(x * x) * K2;
+        T->bes[2][i] = I;
     }
     /* NCS rates */
     double hr = grid_h(R_LO, R_HI, NR);

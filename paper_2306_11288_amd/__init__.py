@@ -1,0 +1,362 @@
+"""Python binding of libqed (the HIP/gfx950 spin/polarisation-resolved SF-QED particle
+step).  Argument marshalling only: every step of the path runs in the library's kernels.
+PyTorch provides device memory and streams.
+
+The C ABI is declared in include/qed.h; the functions here carry the same names.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqed.so")
+
+QED_OK, QED_EARG, QED_ENOMEM, QED_EHIP, QED_ESTATE = range(5)
+QED_FP64, QED_MIXED = 0, 1
+PROC_NCS, PROC_NCS_STOKES, PROC_NBW, PROC_VB = 1, 2, 4, 8
+ST_OVERFLOW, ST_NAN, ST_PMAX, ST_EPS_LT1, ST_CLAMP, ST_SCAN = 1, 2, 4, 8, 16, 32
+FIELD_NONE, FIELD_CONST, FIELD_PW, FIELD_GAUSS, FIELD_GRID2D = 0, 1, 2, 3, 4
+TAB_BESSEL, TAB_NCS_RATE, TAB_NCS_CDF, TAB_NBW_RATE, TAB_NBW_CDF, TAB_VB = range(6)
+EXPORTED = ["qed_init_tables", "qed_destroy", "qed_gather", "qed_push_spin", "qed_emit", "qed_step_leptons",
+            "qed_birefringence", "qed_pair", "qed_step_photons", "qed_compact_photons", "qed_read_status",
+            "qed_clear_status", "qed_get_next_id", "qed_set_next_id", "qed_table_size", "qed_table_export",
+            "qed_last_error"]
+
+ALPHA = 1.0 / 137.035999084
+XI_L = 2.42631023867e-6
+A_E = 1.15965218128e-3
+
+
+class QedError(RuntimeError):
+    pass
+
+
+class Config(C.Structure):
+    _fields_ = [("xi_L", C.c_double), ("alpha", C.c_double), ("a_e", C.c_double), ("dt", C.c_double),
+                ("p_max", C.c_double), ("seed", C.c_uint64), ("id_start", C.c_uint64),
+                ("precision", C.c_int32), ("procs", C.c_uint32)]
+
+
+class Field(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("circular", C.c_int32),
+                ("a0", C.c_double), ("ncycles", C.c_double), ("phase0", C.c_double), ("pol_angle", C.c_double),
+                ("w0", C.c_double), ("x_focus", C.c_double), ("phi_start", C.c_double),
+                ("e0", C.c_double * 3), ("b0", C.c_double * 3), ("grid", C.c_void_p * 6),
+                ("nx", C.c_int32), ("ny", C.c_int32),
+                ("dx", C.c_double), ("dy", C.c_double), ("gx0", C.c_double), ("gy0", C.c_double)]
+
+
+class Segment(C.Structure):
+    _fields_ = [("begin", C.c_int64), ("end", C.c_int64), ("field", Field)]
+
+
+class CLeptons(C.Structure):
+    _fields_ = [(n, C.c_void_p) for n in ("x", "y", "z", "px", "py", "pz", "w", "sx", "sy", "sz", "id", "count")] + \
+               [("capacity", C.c_int64), ("charge", C.c_int32)]
+
+
+class CPhotons(C.Structure):
+    _fields_ = [(n, C.c_void_p) for n in ("x", "y", "z", "kx", "ky", "kz", "w", "xi1", "xi2", "xi3",
+                                          "e1x", "e1y", "e1z", "id", "alive", "count")] + \
+               [("capacity", C.c_int64)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libqed.so; fails loudly if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise QedError(f"{LIB_PATH} is missing: build it with `python -m paper_2306_11288_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        vp, i64, st = C.c_void_p, C.c_int64, C.c_int
+        sig = {
+            "qed_init_tables": [C.POINTER(vp), vp, vp],
+            "qed_destroy": [vp],
+            "qed_gather": [vp, vp, C.c_int, vp, vp, i64, vp],
+            "qed_push_spin": [vp, vp, C.c_int, vp, vp, i64, vp],
+            "qed_emit": [vp, vp, C.c_int, vp, vp, vp, i64, vp],
+            "qed_step_leptons": [vp, vp, C.c_int, vp, vp, i64, vp],
+            "qed_birefringence": [vp, vp, C.c_int, vp, i64, vp],
+            "qed_pair": [vp, vp, C.c_int, vp, vp, vp, i64, vp],
+            "qed_step_photons": [vp, vp, C.c_int, vp, vp, vp, i64, vp],
+            "qed_compact_photons": [vp, vp, vp, vp],
+            "qed_read_status": [vp, C.POINTER(C.c_uint32), vp],
+            "qed_clear_status": [vp, vp],
+            "qed_get_next_id": [vp, C.POINTER(C.c_uint64), vp],
+            "qed_set_next_id": [vp, C.c_uint64, vp],
+            "qed_table_export": [vp, C.c_int, vp, i64],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.restype = st
+            f.argtypes = args
+        L.qed_table_size.restype = i64
+        L.qed_table_size.argtypes = [C.c_int]
+        L.qed_last_error.restype = C.c_char_p
+        L.qed_last_error.argtypes = [vp]
+        _lib = L
+    return _lib
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+# --------------------------------------------------------------------------- buffers
+LEPTON_KEYS = ("x", "y", "z", "px", "py", "pz", "w", "sx", "sy", "sz")
+PHOTON_KEYS = ("x", "y", "z", "kx", "ky", "kz", "w", "xi1", "xi2", "xi3", "e1x", "e1y", "e1z")
+
+
+class Leptons:
+    """Device SoA electron or positron list (caller-owned memory)."""
+
+    def __init__(self, capacity: int, charge: int, precision: int = QED_FP64, device="cuda"):
+        torch = _torch()
+        self.capacity, self.charge, self.precision = int(capacity), int(charge), precision
+        sd = torch.float32 if precision == QED_MIXED else torch.float64
+        for k in LEPTON_KEYS:
+            setattr(self, k, torch.zeros(self.capacity, dtype=sd if k in ("sx", "sy", "sz") else torch.float64,
+                                         device=device))
+        self.id = torch.zeros(self.capacity, dtype=torch.int64, device=device)
+        self.count_t = torch.zeros(1, dtype=torch.int64, device=device)
+
+    @classmethod
+    def from_state(cls, st: dict, capacity=None, charge=-1, precision=QED_FP64, device="cuda"):
+        torch = _torch()
+        n = len(st["x"])
+        L = cls(capacity or n, charge, precision, device)
+        for k in LEPTON_KEYS:
+            t = getattr(L, k)
+            t[:n] = torch.as_tensor(np.ascontiguousarray(st[k]), dtype=t.dtype).to(device)
+        L.id[:n] = torch.as_tensor(np.asarray(st["id"]).astype(np.uint64).view(np.int64)).to(device)
+        L.count_t.fill_(n)
+        return L
+
+    @property
+    def count(self) -> int:
+        return int(self.count_t.item())
+
+    def c(self) -> CLeptons:
+        if getattr(self, "_c", None) is None:   # buffers never move: build the descriptor once
+            s = CLeptons()
+            for k in LEPTON_KEYS:
+                setattr(s, k, getattr(self, k).data_ptr())
+            s.id, s.count, s.capacity, s.charge = (self.id.data_ptr(), self.count_t.data_ptr(), self.capacity,
+                                                   self.charge)
+            self._c = s
+        return self._c
+
+    def to_numpy(self) -> dict:
+        n = self.count
+        out = {k: getattr(self, k)[:n].double().cpu().numpy() for k in LEPTON_KEYS}
+        out["id"] = self.id[:n].cpu().numpy().view(np.uint64)
+        return out
+
+
+class Photons:
+    """Device SoA photon list (caller-owned memory)."""
+
+    def __init__(self, capacity: int, precision: int = QED_FP64, device="cuda"):
+        torch = _torch()
+        self.capacity, self.precision = int(capacity), precision
+        sd = torch.float32 if precision == QED_MIXED else torch.float64
+        for k in PHOTON_KEYS:
+            low = k.startswith("xi") or k.startswith("e1")
+            setattr(self, k, torch.zeros(self.capacity, dtype=sd if low else torch.float64, device=device))
+        self.id = torch.zeros(self.capacity, dtype=torch.int64, device=device)
+        self.alive = torch.zeros(self.capacity, dtype=torch.uint8, device=device)
+        self.count_t = torch.zeros(1, dtype=torch.int64, device=device)
+
+    @classmethod
+    def from_state(cls, st: dict, capacity=None, precision=QED_FP64, device="cuda"):
+        torch = _torch()
+        n = len(st["x"])
+        G = cls(capacity or n, precision, device)
+        for k in PHOTON_KEYS:
+            t = getattr(G, k)
+            t[:n] = torch.as_tensor(np.ascontiguousarray(st[k]), dtype=t.dtype).to(device)
+        G.id[:n] = torch.as_tensor(np.asarray(st["id"]).astype(np.uint64).view(np.int64)).to(device)
+        G.alive[:n] = torch.as_tensor(np.asarray(st.get("alive", np.ones(n, np.uint8)), dtype=np.uint8)).to(device)
+        G.count_t.fill_(n)
+        return G
+
+    @property
+    def count(self) -> int:
+        return int(self.count_t.item())
+
+    def c(self) -> CPhotons:
+        if getattr(self, "_c", None) is None:
+            s = CPhotons()
+            for k in PHOTON_KEYS:
+                setattr(s, k, getattr(self, k).data_ptr())
+            s.id, s.alive, s.count, s.capacity = (self.id.data_ptr(), self.alive.data_ptr(), self.count_t.data_ptr(),
+                                                  self.capacity)
+            self._c = s
+        return self._c
+
+    def to_numpy(self) -> dict:
+        n = self.count
+        out = {k: getattr(self, k)[:n].double().cpu().numpy() for k in PHOTON_KEYS}
+        out["id"] = self.id[:n].cpu().numpy().view(np.uint64)
+        out["alive"] = self.alive[:n].cpu().numpy()
+        return out
+
+
+def make_field(spec: dict, keep: list | None = None) -> Field:
+    """Field descriptor from a dict (same keys as the workload generators).  For GRID2D,
+    spec['grid'] holds six float32 device tensors [ny][nx]."""
+    f = Field()
+    f.kind = int(spec.get("kind", FIELD_NONE))
+    f.circular = int(spec.get("circular", 0))
+    for k in ("a0", "ncycles", "phase0", "pol_angle", "w0", "x_focus", "phi_start", "dx", "dy", "gx0", "gy0"):
+        setattr(f, k, float(spec.get(k, 0.0)))
+    for i, v in enumerate(spec.get("e0", (0, 0, 0))):
+        f.e0[i] = float(v)
+    for i, v in enumerate(spec.get("b0", (0, 0, 0))):
+        f.b0[i] = float(v)
+    if f.kind == FIELD_GRID2D:
+        f.nx, f.ny = int(spec["nx"]), int(spec["ny"])
+        for c in range(6):
+            g = spec["grid"][c]
+            f.grid[c] = g.data_ptr()
+            if keep is not None:
+                keep.append(g)
+    return f
+
+
+def segments(specs) -> tuple:
+    """[(begin, end, field_spec), ...] -> (ctypes array, n)."""
+    specs = list(specs)
+    arr = (Segment * len(specs))()
+    keep = []
+    for i, (b, e, fs) in enumerate(specs):
+        arr[i].begin, arr[i].end = int(b), int(e)
+        arr[i].field = make_field(fs, keep)
+    arr._keep = keep
+    return arr, len(specs)
+
+
+def whole(field_spec: dict):
+    """One segment covering every particle."""
+    return segments([(0, 1 << 62, field_spec)])
+
+
+# --------------------------------------------------------------------------- context
+class Context:
+    """A libqed context: device tables, constants, id counter, status word."""
+
+    def __init__(self, *, dt, procs, seed, id_start, precision=QED_FP64, p_max=0.1, xi_L=XI_L, alpha=ALPHA,
+                 a_e=A_E, stream=None):
+        self.cfg = Config(xi_L, alpha, a_e, dt, p_max, seed, id_start, precision, procs)
+        h = C.c_void_p()
+        rc = lib().qed_init_tables(C.byref(h), C.byref(self.cfg), _stream(stream))
+        if rc != QED_OK:
+            raise QedError(f"qed_init_tables failed with status {rc}")
+        self.h = h
+        self.precision = precision
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().qed_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, name):
+        if rc != QED_OK:
+            msg = lib().qed_last_error(self.h)
+            raise QedError(f"{name}: status {rc}: {msg.decode() if msg else ''}")
+
+    def gather(self, segs, L: Leptons, E6, step: int, stream=None):
+        arr, n = segs
+        self._check(lib().qed_gather(self.h, arr, n, C.byref(L.c()), _ptr(E6), step, _stream(stream)), "qed_gather")
+
+    def push_spin(self, segs, L: Leptons, step: int, E6=None, stream=None):
+        arr, n = segs
+        self._check(lib().qed_push_spin(self.h, arr, n, C.byref(L.c()), _ptr(E6) if E6 is not None else None, step,
+                                        _stream(stream)), "qed_push_spin")
+
+    def emit(self, segs, L: Leptons, E6, out: Photons | None, step: int, stream=None):
+        arr, n = segs
+        o = C.byref(out.c()) if out is not None else None
+        self._check(lib().qed_emit(self.h, arr, n, C.byref(L.c()), _ptr(E6), o, step, _stream(stream)), "qed_emit")
+
+    def step_leptons(self, segs, L: Leptons, out: Photons | None, step: int, stream=None):
+        arr, n = segs
+        o = C.byref(out.c()) if out is not None else None
+        self._check(lib().qed_step_leptons(self.h, arr, n, C.byref(L.c()), o, step, _stream(stream)),
+                    "qed_step_leptons")
+
+    def birefringence(self, segs, G: Photons, step: int, stream=None):
+        arr, n = segs
+        self._check(lib().qed_birefringence(self.h, arr, n, C.byref(G.c()), step, _stream(stream)),
+                    "qed_birefringence")
+
+    def pair(self, segs, G: Photons, em: Leptons | None, ep: Leptons | None, step: int, stream=None):
+        arr, n = segs
+        self._check(lib().qed_pair(self.h, arr, n, C.byref(G.c()), C.byref(em.c()) if em else None,
+                                   C.byref(ep.c()) if ep else None, step, _stream(stream)), "qed_pair")
+
+    def step_photons(self, segs, G: Photons, em: Leptons | None, ep: Leptons | None, step: int, stream=None):
+        arr, n = segs
+        self._check(lib().qed_step_photons(self.h, arr, n, C.byref(G.c()), C.byref(em.c()) if em else None,
+                                           C.byref(ep.c()) if ep else None, step, _stream(stream)),
+                    "qed_step_photons")
+
+    def compact_photons(self, src: Photons, dst: Photons, stream=None):
+        self._check(lib().qed_compact_photons(self.h, C.byref(src.c()), C.byref(dst.c()), _stream(stream)),
+                    "qed_compact_photons")
+
+    def read_status(self, stream=None) -> int:
+        v = C.c_uint32()
+        self._check(lib().qed_read_status(self.h, C.byref(v), _stream(stream)), "qed_read_status")
+        return int(v.value)
+
+    def clear_status(self, stream=None):
+        self._check(lib().qed_clear_status(self.h, _stream(stream)), "qed_clear_status")
+
+    def next_id(self, stream=None) -> int:
+        v = C.c_uint64()
+        self._check(lib().qed_get_next_id(self.h, C.byref(v), _stream(stream)), "qed_get_next_id")
+        return int(v.value)
+
+    def set_next_id(self, v: int, stream=None):
+        self._check(lib().qed_set_next_id(self.h, int(v), _stream(stream)), "qed_set_next_id")
+
+    def table_export(self, which: int) -> np.ndarray:
+        n = lib().qed_table_size(which)
+        out = np.zeros(n)
+        self._check(lib().qed_table_export(self.h, which, out.ctypes.data_as(C.c_void_p), n), "qed_table_export")
+        return out
+
+    # whole step in the library's order: photons, then electrons, then positrons
+    def step(self, segs, em: Leptons | None, ep: Leptons | None, G: Photons | None, step: int, stream=None,
+             photon_procs: bool | None = None):
+        if photon_procs is None:
+            photon_procs = bool(self.cfg.procs & (PROC_NBW | PROC_VB))
+        if G is not None and photon_procs:
+            self.step_photons(segs, G, em, ep, step, stream)
+        for L in (em, ep):
+            if L is not None:
+                self.step_leptons(segs, L, G, step, stream)

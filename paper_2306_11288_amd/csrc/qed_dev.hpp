@@ -1,0 +1,564 @@
+// Device-side physics of the QED particle step.  Everything here is per particle;
+// templates take the "rate" real type T (double for FP64 contexts, float for mixed).
+// Momenta, positions, event probabilities and their comparison are always double.
+#pragma once
+#include "qed_internal.hpp"
+
+namespace qed {
+
+constexpr double PI = 3.14159265358979323846;
+constexpr double SQRT3 = 1.7320508075688772935;
+constexpr double TWO_PI = 6.28318530717958647692;
+constexpr uint32_t STREAM_NCS = 1, STREAM_NBW = 2;
+
+// ------------------------------------------------------------------------- small vectors
+template <class T>
+struct V3 {
+    T x, y, z;
+};
+template <class T>
+__device__ __forceinline__ T dot(const V3<T> &a, const V3<T> &b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+template <class T>
+__device__ __forceinline__ V3<T> cross(const V3<T> &a, const V3<T> &b) {
+    return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+template <class T>
+__device__ __forceinline__ V3<T> operator+(const V3<T> &a, const V3<T> &b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+template <class T>
+__device__ __forceinline__ V3<T> operator-(const V3<T> &a, const V3<T> &b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+template <class T>
+__device__ __forceinline__ V3<T> operator*(T s, const V3<T> &a) { return {s * a.x, s * a.y, s * a.z}; }
+template <class T, class U>
+__device__ __forceinline__ V3<T> cvt(const V3<U> &a) { return {(T)a.x, (T)a.y, (T)a.z}; }
+
+// ------------------------------------------------------------------------- Philox4x32-10
+// Ten rounds of the Philox S-box (two 32x32 -> 64-bit products) with the Weyl key
+// schedule between rounds (Salmon, Moraes, Dror, Shaw, SC'11).
+__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint32_t lo0 = 0xD2511F53u * c[0], hi0 = __umulhi(0xD2511F53u, c[0]);
+        const uint32_t lo1 = 0xCD9E8D57u * c[2], hi1 = __umulhi(0xCD9E8D57u, c[2]);
+        const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+    }
+}
+// four uniforms in (0,1) for (id, step, stream, seed)
+__device__ __forceinline__ void uniform4(uint64_t id, int64_t step, uint32_t stream, uint64_t seed, double r[4]) {
+    const uint64_t s = (uint64_t)step;
+    uint32_t c[4] = {(uint32_t)s, (uint32_t)((s >> 32) & 0xFFFFu) | (stream << 16), (uint32_t)seed,
+                     (uint32_t)(seed >> 32)};
+    philox4x32_10(c, (uint32_t)id, (uint32_t)(id >> 32));
+#pragma unroll
+    for (int k = 0; k < 4; ++k) r[k] = ((double)c[k] + 0.5) * 2.3283064365386963e-10;
+}
+
+// ------------------------------------------------------------------------- fields
+// FT: real type of the transcendental work (double, or float after an FP64 reduction of
+// the carrier phase).  Output fields are double.
+__device__ __forceinline__ double reduce_2pi(double a) { return a - TWO_PI * rint(a * (1.0 / TWO_PI)); }
+
+__device__ __forceinline__ void tsc_w(double xg, int half, int &j0, double w[3]) {
+    const int j = half ? (int)floor(xg) : (int)floor(xg + 0.5);
+    const double d = xg - ((double)j + (half ? 0.5 : 0.0));
+    w[0] = 0.5 * (0.5 - d) * (0.5 - d);
+    w[1] = 0.75 - d * d;
+    w[2] = 0.5 * (0.5 + d) * (0.5 + d);
+    j0 = j - 1;
+}
+
+template <class FT>
+__device__ __forceinline__ double grid_gather(const qed_field &f, const float *__restrict__ g, int hx, int hy,
+                                              double x, double y) {
+    int i0, j0;
+    double wx[3], wy[3];
+    tsc_w((x - f.gx0) / f.dx, hx, i0, wx);
+    tsc_w((y - f.gy0) / f.dy, hy, j0, wy);
+    FT s = 0;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        const int j = j0 + b;
+        if (j < 0 || j >= f.ny) continue;
+        FT row = 0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const int i = i0 + a;
+            if (i < 0 || i >= f.nx) continue;
+            row += (FT)(wx[a] * wy[b]) * (FT)g[(int64_t)j * f.nx + i];
+        }
+        s += row;
+    }
+    return (double)s;
+}
+
+template <class FT>
+__device__ void field_at(const qed_field &f, double t, double x, double y, double z, V3<double> &E, V3<double> &B) {
+    E = {0, 0, 0};
+    B = {0, 0, 0};
+    if (f.kind == QED_FIELD_CONST) {
+        E = {f.e0[0], f.e0[1], f.e0[2]};
+        B = {f.b0[0], f.b0[1], f.b0[2]};
+        return;
+    }
+    if (f.kind == QED_FIELD_GRID2D) {
+        E.x = grid_gather<FT>(f, f.grid[0], 1, 0, x, y);
+        E.y = grid_gather<FT>(f, f.grid[1], 0, 1, x, y);
+        E.z = grid_gather<FT>(f, f.grid[2], 0, 0, x, y);
+        B.x = grid_gather<FT>(f, f.grid[3], 0, 1, x, y);
+        B.y = grid_gather<FT>(f, f.grid[4], 1, 0, x, y);
+        B.z = grid_gather<FT>(f, f.grid[5], 1, 1, x, y);
+        return;
+    }
+    if (f.kind != QED_FIELD_PW && f.kind != QED_FIELD_GAUSS) return;
+    const double L = TWO_PI * f.ncycles;
+    const double phi = t + x - f.phi_start;
+    if (phi < 0.0 || phi > L) return;
+    const FT sp = (FT)sin(f.pol_angle), cp = (FT)cos(f.pol_angle);
+    const FT arg = (FT)(PI * phi / L);   // in [0, pi]
+    FT env = sin(arg);
+    env *= env;
+    FT c1, c2;
+    if (f.kind == QED_FIELD_PW) {
+        const FT denv = (FT)(PI / L) * sin((FT)2 * arg);
+        FT ss, cs;
+        const double ps = phi + f.phase0;
+        if constexpr (sizeof(FT) == 8) {
+            sincos(ps, &ss, &cs);
+        } else {
+            sincosf((FT)reduce_2pi(ps), &ss, &cs);
+        }
+        const FT a0 = (FT)f.a0;
+        c1 = -a0 * (denv * ss + env * cs);
+        c2 = f.circular ? -a0 * (denv * cs - env * ss) : (FT)0;
+    } else {
+        const FT w0 = (FT)f.w0, zr = (FT)0.5 * w0 * w0;
+        const FT xi = (FT)(f.x_focus - x);
+        const FT rho2 = (FT)(y * y + z * z);
+        const FT q = xi / zr, opq = (FT)1 + q * q;
+        const FT amp = (FT)f.a0 / sqrt(opq) * exp(-rho2 / (w0 * w0 * opq));
+        const FT small = atan(q) - rho2 * xi / ((FT)2 * (xi * xi + zr * zr));
+        FT ss, cs;
+        if constexpr (sizeof(FT) == 8) {
+            sincos(phi + f.phase0 + small, &ss, &cs);
+        } else {
+            sincosf((FT)reduce_2pi(phi + f.phase0) + small, &ss, &cs);
+        }
+        c1 = amp * env * cs;
+        c2 = f.circular ? amp * env * ss : (FT)0;
+    }
+    // e1 = (0, cp, sp), e2 = (0, -sp, cp)
+    E.x = 0.0;
+    E.y = (double)(c1 * cp - c2 * sp);
+    E.z = (double)(c1 * sp + c2 * cp);
+    B.x = 0.0;
+    B.y = E.z;
+    B.z = -E.y;
+}
+
+// ------------------------------------------------------------------------- push + spin
+// Boris rotation (eqs. boris1-boris6): p in/out p^{n-1/2} -> p^{n+1/2}; returns p-, p+.
+__device__ __forceinline__ void boris(double q, double dt, const V3<double> &E, const V3<double> &B, V3<double> &p,
+                                      V3<double> &pm, V3<double> &pp) {
+    const double h = 0.5 * q * dt;
+    pm = p + h * E;
+    const double g = sqrt(1.0 + dot(pm, pm));
+    const V3<double> tau = (h / g) * B;
+    const V3<double> sig = (2.0 / (1.0 + dot(tau, tau))) * tau;
+    const V3<double> pr = pm + cross(pm, tau);
+    pp = pm + cross(pr, sig);
+    p = pp + h * E;
+}
+// T-BMT (eq. bmteqn) by the Boris rotation of eqs. bmt-boris1-4: dS/dt = q S x Omega,
+// gamma^n = sqrt(1+|p-|^2), beta^n = (p- + p+)/(2 gamma^n), g/2 - 1 = a_e.
+template <class T>
+__device__ __forceinline__ void bmt(double q, double a_e, double dt, const V3<double> &E, const V3<double> &B,
+                                    const V3<double> &pm, const V3<double> &pp, V3<T> &S) {
+    const double gd = sqrt(1.0 + dot(pm, pm));
+    const V3<T> beta = cvt<T>((0.5 / gd) * (pm + pp));
+    const V3<T> Et = cvt<T>(E), Bt = cvt<T>(B);
+    const T g = (T)gd, ae = (T)a_e;
+    const T c1 = -ae * g / (g + (T)1) * dot(beta, Bt), c2 = ae + (T)1 / g, c3 = ae + (T)1 / (g + (T)1);
+    const V3<T> om = c1 * beta + c2 * Bt - c3 * cross(beta, Et);
+    const V3<T> tv = (T)(0.5 * q * dt) * om;
+    const V3<T> o = ((T)2 / ((T)1 + dot(tv, tv))) * tv;
+    const V3<T> Sp = S + cross(S, tv);
+    S = S + cross(Sp, o);
+}
+// chi_e = xi_L sqrt((gamma E + p x B)^2 - (p.E)^2)
+__device__ __forceinline__ double chi_e(double xi_L, const V3<double> &p, const V3<double> &E, const V3<double> &B) {
+    const double g = sqrt(1.0 + dot(p, p));
+    const V3<double> v = g * E + cross(p, B);
+    const double pe = dot(p, E);
+    const double s = dot(v, v) - pe * pe;
+    return xi_L * sqrt(s > 0.0 ? s : 0.0);
+}
+
+// ------------------------------------------------------------------------- table lookups
+template <class T>
+__device__ __forceinline__ int lag4(T pos, int n, T w[4]) {
+    pos = pos < (T)0 ? (T)0 : pos;
+    pos = pos > (T)(n - 1) ? (T)(n - 1) : pos;
+    int i = (int)floor(pos);
+    i = i < 1 ? 1 : (i > n - 3 ? n - 3 : i);
+    const T f = pos - (T)i, fm1 = f - (T)1, fm2 = f - (T)2, fp1 = f + (T)1;
+    w[0] = -f * fm1 * fm2 / (T)6;
+    w[1] = fp1 * fm1 * fm2 / (T)2;
+    w[2] = -fp1 * f * fm2 / (T)2;
+    w[3] = fp1 * f * fm1 / (T)6;
+    return i;
+}
+template <class T>
+__device__ __forceinline__ T gridpos(T l, double lo, double hi, int n) {
+    return (l - (T)lo) / (T)((hi - lo) / (n - 1));
+}
+
+// Bessel trio at x, all three multiplied by x^(2/3) e^x (only ratios are used)
+template <class T>
+__device__ __forceinline__ void bessel_scaled(const Tabs<T> &tb, T x, T &I, T &K1, T &K2) {
+    T w[4];
+    const int i = lag4(gridpos<T>(log(x), B_LO, B_HI, NB), NB, w);
+    const T *b = tb.bes() + 4 * (i - 1);
+    T b1 = 0, b2 = 0, b3 = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        b1 += w[k] * b[4 * k];
+        b2 += w[k] * b[4 * k + 1];
+        b3 += w[k] * b[4 * k + 2];
+    }
+    const T x13 = cbrt(x);
+    I = b3 * x13 * x13;
+    K1 = b1 * x13;
+    K2 = b2;
+}
+
+template <class T>
+__device__ __forceinline__ void ncs_rate(const Tabs<T> &tb, double chi, T &Ia, T &Ib, uint32_t &st) {
+    if (!(chi > 0.0)) {
+        Ia = 0;
+        Ib = 0;
+        return;
+    }
+    const T c = (T)chi, l = log(c);
+    const T *r = tb.ncs_rate();
+    if (l < (T)R_LO) {
+        Ia = r[0] * c;
+        Ib = r[1] * (c / (T)1e-6) * Ia;
+        return;
+    }
+    if (l > (T)R_HI) st |= QED_ST_CLAMP;
+    T w[4];
+    const int i = lag4(gridpos<T>(l, R_LO, R_HI, NR), NR, w);
+    T fa = 0, fk = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        fa += w[k] * r[2 * (i - 1 + k)];
+        fk += w[k] * r[2 * (i - 1 + k) + 1];
+    }
+    Ia = fa * c;
+    Ib = fk * Ia;
+}
+
+// Inverse of the piecewise-linear CDF D_j = a_j - m b_j, rows r0 and r0+1 mixed with
+// weight f, at `target`; returns the fractional column.
+template <class T>
+__device__ __forceinline__ T cdf_invert(const T *__restrict__ R0, const T *__restrict__ R1, int ncol, T f, T m,
+                                        T target) {
+    int lo = 0, hi = ncol - 1;
+    const T g = (T)1 - f;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        const T a = g * R0[2 * mid] + f * R1[2 * mid];
+        const T b = g * R0[2 * mid + 1] + f * R1[2 * mid + 1];
+        if (a - m * b <= target) lo = mid;
+        else hi = mid;
+    }
+    const T dlo = (g * R0[2 * lo] + f * R1[2 * lo]) - m * (g * R0[2 * lo + 1] + f * R1[2 * lo + 1]);
+    const T dhi = (g * R0[2 * hi] + f * R1[2 * hi]) - m * (g * R0[2 * hi + 1] + f * R1[2 * hi + 1]);
+    T tau = dhi > dlo ? (target - dlo) / (dhi - dlo) : (T)0;
+    tau = tau < (T)0 ? (T)0 : (tau > (T)1 ? (T)1 : tau);
+    return (T)lo + tau;
+}
+template <class T>
+__device__ __forceinline__ void row_pos(T l, double lo, double hi, int n, int &r0, T &f) {
+    T q = gridpos<T>(l, lo, hi, n);
+    q = q < (T)0 ? (T)0 : (q > (T)(n - 1) ? (T)(n - 1) : q);
+    int r = (int)floor(q);
+    r = r > n - 2 ? n - 2 : (r < 0 ? 0 : r);
+    r0 = r;
+    f = q - (T)r;
+}
+// photon-fraction variable t = (2u/(3chi))^(1/3) sampled from the spin-dependent spectrum
+template <class T>
+__device__ __forceinline__ T ncs_sample_t(const Tabs<T> &tb, double chi, T kappa, T s, T r) {
+    const T m = s * kappa;
+    int r0;
+    T f;
+    row_pos<T>(log((T)chi), C_LO, C_HI, NCR, r0, f);
+    const T *R0 = tb.ncs_cdf() + (int64_t)r0 * NCT * 2;
+    const T col = cdf_invert<T>(R0, R0 + 2 * NCT, NCT, f, m, r * ((T)1 - m));
+    return col * (T)(T_MAX / (NCT - 1));
+}
+
+template <class T>
+__device__ __forceinline__ void nbw_rate(const Tabs<T> &tb, double chi, T &Ja, T &Jb, T &kappa, uint32_t &st) {
+    const T c = (T)chi, l = chi > 0.0 ? log(c) : (T)-1e30;
+    if (l < (T)P_LO) {
+        Ja = 0;
+        Jb = 0;
+        kappa = 0;
+        return;
+    }
+    if (l > (T)P_HI) st |= QED_ST_CLAMP;
+    T w[4];
+    const int i = lag4(gridpos<T>(l, P_LO, P_HI, NP), NP, w);
+    const T *r = tb.nbw_rate();
+    T ga = 0, gk = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        ga += w[k] * r[2 * (i - 1 + k)];
+        gk += w[k] * r[2 * (i - 1 + k) + 1];
+    }
+    Ja = ga * c * exp((T)(-8.0 / 3.0) / c);
+    Jb = gk * Ja;
+    kappa = gk;
+}
+template <class T>
+__device__ __forceinline__ T nbw_sample_delta(const Tabs<T> &tb, double chi, T kappa, T xi3, T r) {
+    const T m = xi3 * kappa;
+    int r0;
+    T f;
+    row_pos<T>(log((T)chi), P_LO, P_HI, NDR, r0, f);
+    const T *R0 = tb.nbw_cdf() + (int64_t)r0 * NDD * 2;
+    const T hd = (T)(0.5 / (NDD - 1));
+    if (r <= (T)0.5) return cdf_invert<T>(R0, R0 + 2 * NDD, NDD, f, m, r * ((T)1 - m)) * hd;
+    return (T)1 - cdf_invert<T>(R0, R0 + 2 * NDD, NDD, f, m, ((T)1 - r) * ((T)1 - m)) * hd;
+}
+template <class T>
+__device__ __forceinline__ void vb_M(const Tabs<T> &tb, double chi, T &Mp, T &Mm, uint32_t &st) {
+    const T c = (T)chi, l = chi > 0.0 ? log(c) : (T)-1e30;
+    if (l < (T)V_LO) {
+        Mp = 4;
+        Mm = 7;
+        return;
+    }
+    if (l > (T)V_HI) st |= QED_ST_CLAMP;
+    T w[4];
+    const int i = lag4(gridpos<T>(l, V_LO, V_HI, NV), NV, w);
+    const T *v = tb.vb();
+    Mp = 0;
+    Mm = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        Mp += w[k] * v[2 * (i - 1 + k)];
+        Mm += w[k] * v[2 * (i - 1 + k) + 1];
+    }
+}
+
+// ------------------------------------------------------------------------- NCS
+// Emitted photon of one event (Sec. III.C.1): momentum k, Stokes xi, basis vector e1.
+template <class T>
+struct NcsPhoton {
+    V3<double> k;
+    V3<T> xi, e1;
+};
+
+// The F functions of eqs. (F0)-(F3) (Bessel values share a common positive factor).
+template <class T>
+__device__ __forceinline__ void ncs_F(T u, T I, T K1, T K2, const V3<T> &Si, const V3<T> &Sf, const V3<T> &a,
+                                      const V3<T> &b, const V3<T> &n, T F[4]) {
+    const T Sif = dot(Si, Sf), sia = dot(Si, a), sfa = dot(Sf, a), sib = dot(Si, b), sfb = dot(Sf, b);
+    const T sin_ = dot(Si, n), sfn = dot(Sf, n);
+    const V3<T> fxs = cross(Sf, Si);
+    const T nfx = dot(n, fxs), afx = dot(a, fxs), u2 = u * u;
+    F[0] = -(2 + u) * (2 + u) * (I - 2 * K2) * (1 + Sif) + u2 * (1 - Sif) * (I + 2 * K2) + 2 * u2 * Sif * I -
+           (4 * u + 2 * u2) * (sfb + sib) * K1 - 2 * u2 * (sfb - sib) * K1 - 4 * u2 * (I - K2) * sin_ * sfn;
+    F[1] = -2 * u2 * I * (sia * sfb + sfa * sib) + 4 * u * (sia * (1 + u) + sfa) * K1 + 2 * u * (2 + u) * nfx * K2;
+    F[2] = -(2 * u2 * (sin_ * sfb + sfn * sib) + 2 * u * (2 + u) * afx) * K1 - 4 * u * (sin_ + sfn * (1 + u)) * I +
+           4 * u * (2 + u) * (sin_ + sfn) * K2;
+    F[3] = 4 * (1 + u + (1 + u + (T)0.5 * u2) * Sif - (T)0.5 * u2 * sin_ * sfn) * K2 +
+           2 * u2 * (sib * sfb - sia * sfa) * I - 4 * u * ((1 + u) * sib + sfb) * K1;
+}
+
+// One NCS step of one lepton with p = p^{n+1/2}, S = S^{n+1/2} and the fields of x^n.
+// Returns true on emission (photon filled, p and S updated); otherwise applies the
+// no-emission spin update.
+template <class T>
+__device__ bool ncs_step(const Consts &c, const Tabs<T> &tb, double q, V3<double> &p, V3<T> &S, const V3<double> &E,
+                         const V3<double> &B, uint64_t id, int64_t step, uint32_t &st, NcsPhoton<T> &ph) {
+    const double pp2 = dot(p, p), g = sqrt(1.0 + pp2), pmag = sqrt(pp2);
+    const double chi = chi_e(c.xi_L, p, E, B);
+    if (!(chi > 0.0) || !(pmag > 0.0)) return false;
+    const V3<double> nd = (1.0 / pmag) * p;
+    const V3<double> beta = (1.0 / g) * p;
+    const double be = dot(beta, E);
+    const V3<double> acc = q * (E + cross(beta, B) - be * beta);
+    const V3<double> ad = acc - dot(nd, acc) * nd;
+    const double an = sqrt(dot(ad, ad));
+    if (!(an > 0.0)) return false;
+    const V3<T> n = cvt<T>(nd), a = cvt<T>((1.0 / an) * ad);
+    const V3<T> b = cross(n, a);
+    const T s = dot(S, b);
+    T Ia, Ib;
+    ncs_rate<T>(tb, chi, Ia, Ib, st);
+    const double C = c.alpha / (SQRT3 * PI * c.xi_L * g);
+    const double W = C * (double)Ia, Wt = C * ((double)Ia - (double)s * (double)Ib), P = Wt * c.dt;
+    if (P > c.p_max) st |= QED_ST_PMAX;
+    double r[4];
+    uniform4(id, step, STREAM_NCS, c.seed, r);
+    if (r[1] < P) {
+        const T kappa = Ib / Ia;
+        const T tt = ncs_sample_t<T>(tb, chi, kappa, s, (T)r[0]);
+        const T t3 = tt * tt * tt;
+        const T u = (T)1.5 * (T)chi * t3, y = u / ((T)1 + u);
+        ph.k = (double)y * p;
+        p = (1.0 - (double)y) * p;
+        T I, K1, K2;
+        bessel_scaled<T>(tb, t3, I, K1, K2);
+        const T w = -(1 + u) * I + (2 + 2 * u + u * u) * K2;
+        const T fS = -u * K1 * s;
+        const T sn = dot(S, n);
+        const V3<T> gv = (-(1 + u) * (I - 2 * K2)) * S + (-u * (1 + u) * K1) * b + (-u * u * (I - K2) * sn) * n;
+        const T gn = sqrt(dot(gv, gv));
+        const V3<T> zeta = gn > (T)0 ? ((T)1 / gn) * gv : S;
+        const T pplus = (T)0.5 * ((T)1 + gn / (w + fS));
+        const V3<T> Sf = (r[2] < (double)pplus ? (T)1 : (T)-1) * zeta;
+        V3<T> xi = {0, 0, 0};
+        if (c.procs & QED_PROC_NCS_STOKES) {
+            T F[4];
+            ncs_F<T>(u, I, K1, K2, S, Sf, a, b, n, F);
+            const T fn = sqrt(F[1] * F[1] + F[2] * F[2] + F[3] * F[3]);
+            if (fn > (T)0) {
+                const T sx = r[3] < (double)((F[0] + fn) / ((T)2 * F[0])) ? (T)1 : (T)-1;
+                xi = {sx * F[1] / fn, sx * F[2] / fn, sx * F[3] / fn};
+            } else {
+                xi.z = r[3] < 0.5 ? (T)1 : (T)-1;
+            }
+        }
+        S = Sf;
+        ph.xi = xi;
+        ph.e1 = a;
+        return true;
+    }
+    const T wdt = (T)(W * c.dt), den = (T)(1.0 - Wt * c.dt), fb = (T)(C * (double)Ib * c.dt);
+    const V3<T> Sb = ((T)1 / den) * (((T)1 - wdt) * S + fb * b);
+    const T nrm = sqrt(dot(Sb, Sb));
+    S = ((T)1 / nrm) * Sb;
+    return false;
+}
+
+// ------------------------------------------------------------------------- photons
+// The G functions of eqs. (G0)-(G3) without W0/2 (a, b, v = a_+, b_+, v_+).
+template <class T>
+__device__ __forceinline__ T nbw_weight(T d, T I, T K1, T K2, const V3<T> &Sp, const V3<T> &Sm, const V3<T> &a,
+                                        const V3<T> &b, const V3<T> &v, const V3<T> &xi) {
+    const T ep = d, em = (T)1 - d;
+    const T rs = (em * em + ep * ep) / (em * ep), ds = (ep * ep - em * em) / (em * ep),
+            sq = (ep - em) * (ep - em) / (em * ep);
+    const T gp = (T)1 / ep, gm = (T)1 / em, g2 = (T)1 / ((T)2 * em * ep);
+    const T spm = dot(Sm, Sp), spa = dot(Sp, a), sma = dot(Sm, a), spb = dot(Sp, b), smb = dot(Sm, b);
+    const T spv = dot(Sp, v), smv = dot(Sm, v);
+    const V3<T> mxp = cross(Sm, Sp);
+    const T mv = dot(mxp, v), ma = dot(mxp, a);
+    const T G0 = I + rs * K2 + (I - 2 * K2) * spm + K1 * (-gp * spb + gm * smb) + (rs * I - sq * K2) * spv * smv;
+    const T G1 = K1 * (-gm * spa + gp * sma) + (T)0.5 * ds * K2 * mv - g2 * I * (spa * smb + sma * spb);
+    const T G2 = g2 * K1 * ma + (T)0.5 * ds * K1 * (smv * spb + spv * smb) + (gm * I - ds * K2) * smv +
+                 (gp * I + ds * K2) * spv;
+    const T G3 = -K2 + (T)0.5 * rs * K2 * spm - K1 * (gp * smb - gm * spb) + g2 * I * (spb * smb - spa * sma) -
+                 (T)0.5 * sq * K2 * spv * smv;
+    const T wv = G0 + xi.x * G1 + xi.y * G2 + xi.z * G3;
+    return wv > (T)0 ? wv : (T)0;
+}
+
+template <class T>
+struct PairOut {
+    V3<double> pm, pp;   // electron, positron momenta
+    V3<T> Sm, Sp;        // spins
+};
+
+// Photon step at x^n (Algorithm 1 + Sec. III.D): basis rotation to E_red, VB phase,
+// NBW test and pair sampling.  Returns true if the photon decays (pair filled).
+template <class T>
+__device__ bool photon_step(const Consts &c, const Tabs<T> &tb, const V3<double> &k, V3<T> &xi, V3<T> &e1,
+                            const V3<double> &E, const V3<double> &B, uint64_t id, int64_t step, bool do_vb,
+                            bool do_nbw, uint32_t &st, PairOut<T> &po) {
+    const double eps = sqrt(dot(k, k));
+    const V3<double> n = (1.0 / eps) * k;
+    const V3<double> er = E - dot(n, E) * n + cross(n, B);
+    const double an = sqrt(dot(er, er));
+    if (!(an > 0.0)) return false;
+    const double chi = c.xi_L * eps * an;
+    const V3<T> nt = cvt<T>(n);
+    const V3<T> e1n = cvt<T>((1.0 / an) * er);
+    const V3<T> e2 = cross(nt, e1);
+    const T cp = dot(e1, e1n), sp = dot(e2, e1n), nn = cp * cp + sp * sp;
+    const T c2 = (cp * cp - sp * sp) / nn, s2 = (T)2 * cp * sp / nn;
+    {
+        const T x1 = c2 * xi.x - s2 * xi.z, x3 = s2 * xi.x + c2 * xi.z;
+        xi.x = x1;
+        xi.z = x3;
+    }
+    e1 = e1n;
+    if (do_vb) {
+        T Mp, Mm;
+        vb_M<T>(tb, chi, Mp, Mm, st);
+        const T dphi = (T)((double)(Mp - Mm) * (c.alpha / (90.0 * PI)) * chi * chi * c.dt / (eps * c.xi_L));
+        T sd, cd;
+        if constexpr (sizeof(T) == 8) sincos(dphi, &sd, &cd);
+        else sincosf(dphi, &sd, &cd);
+        const T y1 = cd * xi.x - sd * xi.y, y2 = sd * xi.x + cd * xi.y;
+        xi.x = y1;
+        xi.y = y2;
+    }
+    if (!do_nbw || eps < 2.0) return false;
+    T Ja, Jb, kappa;
+    nbw_rate<T>(tb, chi, Ja, Jb, kappa, st);
+    const double P = c.alpha / (SQRT3 * PI * c.xi_L * eps) * ((double)Ja - (double)xi.z * (double)Jb) * c.dt;
+    if (P > c.p_max) st |= QED_ST_PMAX;
+    double r[4];
+    uniform4(id, step, STREAM_NBW, c.seed, r);
+    if (!(Ja > (T)0) || !(r[1] < P)) return false;
+    const T d = nbw_sample_delta<T>(tb, chi, kappa, xi.z, (T)r[0]);
+    const double epl = (double)d * eps, emi = eps - epl;
+    T I, K1, K2;
+    bessel_scaled<T>(tb, (T)(2.0 / (3.0 * chi * (double)d * (1.0 - (double)d))), I, K1, K2);
+    const V3<T> a = e1, bb = cross(nt, a);
+    const T ip = (T)(eps / epl), im = (T)(eps / emi), ds = (T)((epl * epl - emi * emi) / (emi * epl));
+    const V3<T> D = (-(ip - xi.z * im) * K1) * bb + (-xi.x * im * K1) * a + (xi.y * (ds * K2 + ip * I)) * nt;
+    const V3<T> Dm = ((im - xi.z * ip) * K1) * bb + (xi.x * ip * K1) * a + (-xi.y * (ds * K2 - im * I)) * nt;
+    const T dn = sqrt(dot(D, D)), dmn = sqrt(dot(Dm, Dm));
+    const V3<T> zp = dn > (T)0 ? ((T)1 / dn) * D : bb;
+    const V3<T> zm = dmn > (T)0 ? ((T)1 / dmn) * Dm : bb;
+    T Pk[4], tot = 0;
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+        const T sgp = kk < 2 ? (T)1 : (T)-1, sgm = (kk & 1) == 0 ? (T)1 : (T)-1;
+        Pk[kk] = nbw_weight<T>(d, I, K1, K2, sgp * zp, sgm * zm, a, bb, nt, xi);
+        tot += Pk[kk];
+    }
+    int sel = 3;
+    T acc = 0;
+    const T thr = (T)r[2] * tot;
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+        acc += Pk[kk];
+        if (sel == 3 && kk < 3 && thr < acc) sel = kk;
+    }
+    if (epl < 1.0 || emi < 1.0) st |= QED_ST_EPS_LT1;
+    double qp = epl * epl - 1.0, qm = emi * emi - 1.0;
+    qp = qp > 0.0 ? sqrt(qp) : 0.0;
+    qm = qm > 0.0 ? sqrt(qm) : 0.0;
+    po.pp = qp * n;
+    po.pm = qm * n;
+    po.Sp = (sel < 2 ? (T)1 : (T)-1) * zp;
+    po.Sm = ((sel & 1) == 0 ? (T)1 : (T)-1) * zm;
+    return true;
+}
+
+}  // namespace qed

@@ -1,0 +1,312 @@
+// GPU construction of the rate, spectrum, Bessel and birefringence tables in FP64.
+//
+// Special functions come from integral representations evaluated by quadrature on the
+// device:  K_nu(x) = int_0^inf exp(-x cosh s) cosh(nu s) ds and int_x^inf K_nu = the same
+// with an extra 1/cosh s (trapezoid rule, geometric convergence for this analytic even
+// integrand); Scorer's Gi'(X) from its integral turned onto the ray arg t = pi/6, where it
+// neither oscillates nor grows.  Integrals over the emitted-photon variable use
+// t = (2u/(3chi))^(1/3) (u = omega/(eps - omega)), in which the integrands are analytic.
+#include "qed_internal.hpp"
+
+namespace qed {
+namespace {
+
+constexpr double PI_ = 3.14159265358979323846;
+constexpr int GQ = 8;   // Gauss-Legendre points per panel
+struct GaussRule {
+    double x[GQ], w[GQ];
+};
+
+// Gauss-Legendre abscissae/weights on [-1, 1]: Newton iteration on P_8 from the
+// asymptotic initial guess.
+GaussRule make_rule() {
+    GaussRule g{};
+    for (int i = 0; i < GQ; ++i) {
+        double z = std::cos(PI_ * (i + 0.75) / (GQ + 0.5)), dp = 0;
+        for (int it = 0; it < 60; ++it) {
+            double p0 = 1.0, p1 = z;
+            for (int k = 2; k <= GQ; ++k) {
+                const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = GQ * (z * p1 - p0) / (z * z - 1.0);
+            const double dz = p1 / dp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-17) break;
+        }
+        g.x[i] = z;
+        g.w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+    return g;
+}
+
+__device__ void bessel3(double x, double &k13, double &k23, double &ik13) {
+    x = x > 1e-300 ? x : 1e-300;              // callers pass x > 0; keep the node count finite
+    const double h = x > 16.0 ? 0.32 / sqrt(x) : 0.08;
+    const double smax = acosh(1.0 + 70.0 / x) + 0.5;
+    const int n = (int)fmin(smax / h, 20000.0) + 1;
+    const double e0 = 0.5 * exp(-x);
+    double a = e0, b = e0, c = e0;
+    for (int i = 1; i <= n; ++i) {
+        const double s = i * h, ch = cosh(s), e = exp(-x * ch);
+        const double c1 = cosh(s * (1.0 / 3.0));
+        a += e * c1;
+        b += e * cosh(s * (2.0 / 3.0));
+        c += e * c1 / ch;
+    }
+    k13 = h * a;
+    k23 = h * b;
+    ik13 = h * c;
+}
+
+// the trio times exp(x), integrating exp(-x (cosh s - 1)) so that large x cannot overflow
+__device__ void bessel3_scaled(double x, double &k13, double &k23, double &ik13) {
+    x = x > 1e-300 ? x : 1e-300;
+    const double h = x > 16.0 ? 0.32 / sqrt(x) : 0.08;
+    const double smax = acosh(1.0 + 70.0 / x) + 0.5;
+    const int n = (int)fmin(smax / h, 20000.0) + 1;
+    double a = 0.5, b = 0.5, c = 0.5;
+    for (int i = 1; i <= n; ++i) {
+        const double s = i * h, ch = cosh(s), sh = sinh(0.5 * s), e = exp(-2.0 * x * sh * sh);
+        const double c1 = cosh(s * (1.0 / 3.0));
+        a += e * c1;
+        b += e * cosh(s * (2.0 / 3.0));
+        c += e * c1 / ch;
+    }
+    k13 = h * a;
+    k23 = h * b;
+    ik13 = h * c;
+}
+
+__device__ double scorer_gip(double X, const GaussRule &g) {
+    double S = 6.0;
+    if (X > 0.0 && 80.0 / X < S) S = 80.0 / X;
+    const int np = 40;
+    const double hp = S / np;
+    double sum = 0.0;
+    for (int p = 0; p < np; ++p)
+        for (int i = 0; i < GQ; ++i) {
+            const double s = hp * (p + 0.5 * (g.x[i] + 1.0));
+            sum += g.w[i] * s * exp(-s * s * s / 3.0 - 0.5 * X * s) * sin(0.8660254037844386 * X * s + 2.6179938779914944);
+        }
+    return 0.5 * hp * sum / PI_;
+}
+
+// NCS integrands in t: Ia-type (photon-summed, spin-independent) and Ib-type (spin part)
+__device__ __forceinline__ void ncs_integrand(double chi, double t, double &fa, double &fb) {
+    double K1, K2, I;
+    bessel3(t * t * t, K1, K2, I);
+    const double u = 1.5 * chi * t * t * t, jac = 4.5 * chi * t * t, o = 1.0 + u, o3 = o * o * o;
+    fa = jac * (-(o)*I + (2.0 + 2.0 * u + u * u) * K2) / o3;
+    fb = jac * u * K1 / o3;
+}
+__device__ __forceinline__ void nbw_integrand(double chi, double d, double &fa, double &fb) {
+    const double dd = d * (1.0 - d), rho = 2.0 / (3.0 * chi * dd);
+    if (!(dd > 0.0) || rho > 700.0) {
+        fa = 0.0;
+        fb = 0.0;
+        return;
+    }
+    double K1, K2, I;
+    bessel3(rho, K1, K2, I);
+    fa = I + (d * d + (1.0 - d) * (1.0 - d)) / dd * K2;
+    fb = K2;
+}
+
+__device__ __forceinline__ double block_sum(double v, double *sh) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += sh[w];
+    return s;
+}
+
+__global__ void k_bessel(double *tab) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= NB) return;
+    const double x = exp(B_LO + i * ((B_HI - B_LO) / (NB - 1)));
+    double K1, K2, I;
+    bessel3_scaled(x, K1, K2, I);
+    const double x13 = cbrt(x);
+    double *o = tab + OFF_BES + 4 * i;
+    o[0] = x13 * K1;
+    o[1] = x13 * x13 * K2;
+    o[2] = I;
+    o[3] = 0.0;
+}
+
+// NCS total-rate integrals: one block per chi node
+__global__ void k_ncs_rate(double *tab, GaussRule g) {
+    __shared__ double sh[8];
+    const int r = blockIdx.x;
+    const double chi = exp(R_LO + r * ((R_HI - R_LO) / (NR - 1)));
+    const double tcut = 3.9148676411688634, hp = 0.04;   // 60^(1/3): exp(-60) tail dropped
+    const int np = (int)ceil(tcut / hp);
+    const double hq = tcut / np;
+    double sa = 0.0, sb = 0.0;
+    for (int q = threadIdx.x; q < np * GQ; q += blockDim.x) {
+        const int p = q / GQ, i = q % GQ;
+        const double t = hq * (p + 0.5 * (g.x[i] + 1.0));
+        double fa, fb;
+        ncs_integrand(chi, t, fa, fb);
+        sa += 0.5 * hq * g.w[i] * fa;
+        sb += 0.5 * hq * g.w[i] * fb;
+    }
+    const double Ia = block_sum(sa, sh);
+    const double Ib = block_sum(sb, sh);
+    if (threadIdx.x == 0) {
+        tab[OFF_NCS_RATE + 2 * r] = Ia / chi;
+        tab[OFF_NCS_RATE + 2 * r + 1] = Ib / Ia;
+    }
+}
+
+// per-interval integrals of the NCS spectrum pieces: scratch[2 * (row * NCT + j + 1)]
+__global__ void k_ncs_panels(double *scratch, GaussRule g) {
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= (int64_t)NCR * (NCT - 1)) return;
+    const int row = (int)(id / (NCT - 1)), j = (int)(id % (NCT - 1));
+    const double chi = exp(C_LO + row * ((C_HI - C_LO) / (NCR - 1)));
+    const double ht = T_MAX / (NCT - 1), t0 = j * ht;
+    double sa = 0.0, sb = 0.0;
+    for (int i = 0; i < GQ; ++i) {
+        double fa, fb;
+        ncs_integrand(chi, t0 + 0.5 * ht * (g.x[i] + 1.0), fa, fb);
+        sa += g.w[i] * fa;
+        sb += g.w[i] * fb;
+    }
+    scratch[2 * ((int64_t)row * NCT + j + 1)] = 0.5 * ht * sa;
+    scratch[2 * ((int64_t)row * NCT + j + 1) + 1] = 0.5 * ht * sb;
+}
+
+__global__ void k_nbw_panels(double *scratch, GaussRule g) {
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= (int64_t)NDR * (NDD - 1)) return;
+    const int row = (int)(id / (NDD - 1)), j = (int)(id % (NDD - 1));
+    const double chi = exp(P_LO + row * ((P_HI - P_LO) / (NDR - 1)));
+    const double hd = 0.5 / (NDD - 1), d0 = j * hd;
+    double sa = 0.0, sb = 0.0;
+    for (int i = 0; i < GQ; ++i) {
+        double fa, fb;
+        nbw_integrand(chi, d0 + 0.5 * hd * (g.x[i] + 1.0), fa, fb);
+        sa += g.w[i] * fa;
+        sb += g.w[i] * fb;
+    }
+    scratch[2 * ((int64_t)row * NDD + j + 1)] = 0.5 * hd * sa;
+    scratch[2 * ((int64_t)row * NDD + j + 1) + 1] = 0.5 * hd * sb;
+}
+
+// running sums along each row, normalised so the last column equals `last`
+__global__ void k_cdf_rows(const double *scratch, double *out, int nrow, int ncol, double last) {
+    const int row = blockIdx.x * blockDim.x + threadIdx.x;
+    if (row >= nrow) return;
+    const double *s = scratch + 2 * (int64_t)row * ncol;
+    double *o = out + 2 * (int64_t)row * ncol;
+    double a = 0.0, b = 0.0;
+    o[0] = 0.0;
+    o[1] = 0.0;
+    for (int j = 1; j < ncol; ++j) {
+        a += s[2 * j];
+        b += s[2 * j + 1];
+        o[2 * j] = a;
+        o[2 * j + 1] = b;
+    }
+    const double na = last / a, nb = last / b;
+    for (int j = 1; j < ncol - 1; ++j) {
+        o[2 * j] *= na;
+        o[2 * j + 1] *= nb;
+    }
+    o[2 * (ncol - 1)] = last;
+    o[2 * (ncol - 1) + 1] = last;
+}
+
+// NBW total-rate integrals: one block per chi node (the spectrum is symmetric in delta)
+__global__ void k_nbw_rate(double *tab, GaussRule g) {
+    __shared__ double sh[8];
+    const int r = blockIdx.x;
+    const double chi = exp(P_LO + r * ((P_HI - P_LO) / (NP - 1)));
+    const int np = 160;
+    const double hq = 0.5 / np;
+    double sa = 0.0, sb = 0.0;
+    for (int q = threadIdx.x; q < np * GQ; q += blockDim.x) {
+        const int p = q / GQ, i = q % GQ;
+        double fa, fb;
+        nbw_integrand(chi, hq * (p + 0.5 * (g.x[i] + 1.0)), fa, fb);
+        sa += 0.5 * hq * g.w[i] * fa;
+        sb += 0.5 * hq * g.w[i] * fb;
+    }
+    const double Ja = 2.0 * block_sum(sa, sh);
+    const double Jb = 2.0 * block_sum(sb, sh);
+    if (threadIdx.x == 0) {
+        tab[OFF_NBW_RATE + 2 * r] = Ja * exp(8.0 / (3.0 * chi)) / chi;
+        tab[OFF_NBW_RATE + 2 * r + 1] = Jb / Ja;
+    }
+}
+
+// VB coefficients M+, M-: one block per chi node, panels graded towards v = 1
+__global__ void k_vb(double *tab, GaussRule g) {
+    __shared__ double sh[8];
+    const int r = blockIdx.x;
+    const double chi = exp(V_LO + r * ((V_HI - V_LO) / (NV - 1)));
+    const int np = 44;      // the last panel [1 - 2^-43, 1] adds O(2^-86)
+    double sp = 0.0, sm = 0.0;
+    for (int q = threadIdx.x; q < np * GQ; q += blockDim.x) {
+        const int p = q / GQ, i = q % GQ;
+        const double lo = 1.0 - ldexp(1.0, -p), hi = (p == np - 1) ? 1.0 : 1.0 - ldexp(1.0, -(p + 1));
+        const double v = lo + 0.5 * (hi - lo) * (g.x[i] + 1.0), om = (1.0 - v) * (1.0 + v);
+        if (!(om > 0.0)) continue;
+        const double x = 4.0 / (om * chi), X = cbrt(x * x);
+        const double core = PI_ * X * X * scorer_gip(X, g);
+        const double wq = 0.5 * (hi - lo) * g.w[i] * om * core;
+        sp += wq * 0.5 * (1.0 + v * v / 3.0);
+        sm += wq * (1.0 - v * v / 3.0);
+    }
+    const double Mp = block_sum(sp, sh);
+    const double Mm = block_sum(sm, sh);
+    if (threadIdx.x == 0) {
+        tab[OFF_VB + 2 * r] = -11.25 * Mp;
+        tab[OFF_VB + 2 * r + 1] = -11.25 * Mm;
+    }
+}
+
+__global__ void k_to_f32(const double *a, float *b, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        b[i] = (float)a[i];
+}
+
+}  // namespace
+
+hipError_t build_tables(qed_ctx *ctx, hipStream_t s) {
+    const GaussRule g = make_rule();
+    double *scratch = nullptr;
+    const int64_t ns = 2LL * NCR * NCT;   // larger of the two spectrum tables
+    hipError_t e = hipMalloc(&scratch, ns * sizeof(double));
+    if (e != hipSuccess) return e;
+    double *tab = ctx->tab64;
+    hipLaunchKernelGGL(k_bessel, dim3((NB + 255) / 256), dim3(256), 0, s, tab);
+    hipLaunchKernelGGL(k_ncs_rate, dim3(NR), dim3(256), 0, s, tab, g);
+    {
+        const int64_t n = (int64_t)NCR * (NCT - 1);
+        hipLaunchKernelGGL(k_ncs_panels, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, scratch, g);
+        hipLaunchKernelGGL(k_cdf_rows, dim3((NCR + 63) / 64), dim3(64), 0, s, (const double *)scratch,
+                           tab + OFF_NCS_CDF, NCR, NCT, 1.0);
+    }
+    hipLaunchKernelGGL(k_nbw_rate, dim3(NP), dim3(256), 0, s, tab, g);
+    {
+        const int64_t n = (int64_t)NDR * (NDD - 1);
+        hipLaunchKernelGGL(k_nbw_panels, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, scratch, g);
+        hipLaunchKernelGGL(k_cdf_rows, dim3((NDR + 63) / 64), dim3(64), 0, s, (const double *)scratch,
+                           tab + OFF_NBW_CDF, NDR, NDD, 0.5);
+    }
+    hipLaunchKernelGGL(k_vb, dim3(NV), dim3(256), 0, s, tab, g);
+    hipLaunchKernelGGL(k_to_f32, dim3(1024), dim3(256), 0, s, (const double *)tab, ctx->tab32, TAB_TOTAL);
+    e = hipGetLastError();
+    const hipError_t e2 = hipStreamSynchronize(s);
+    hipFree(scratch);
+    return e != hipSuccess ? e : e2;
+}
+
+}  // namespace qed

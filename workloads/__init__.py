@@ -82,33 +82,36 @@ def photons(n: int, *, seed: int, eps0: float, eps_rel_spread: float, divergence
 
 
 # --------------------------------------------------------------------------- configurations
-def c1(n: int = 10_000) -> dict:
+def c1(n: int = 10_000, start_step: int = 0) -> dict:
     """Plain FP64 method: 1e4 electrons, gamma0 = 1000 (5 %), 1 mrad, spins +y, head-on
     with a linearly polarised plane wave (lambda = 1 um, a0 = 20, sin^2 envelope of 8
-    cycles), dt = T0/200, 3000 steps, NCS with spin flip, Philox seed 1."""
+    cycles), dt = T0/200, 3000 steps, NCS with spin flip, Philox seed 1.  start_step > 0
+    places the bunch where it would be at that step (ballistic, at c)."""
+    dt = TWO_PI / 200
     return {
         "name": "c1_pw_lp_a0_20_gamma1000",
         "leptons": beam(n, seed=101, gamma0=1000.0, gamma_rel_spread=0.05, divergence=1e-3,
-                        x_mean=-4 * math.pi, x_sigma=math.pi, r_sigma=TWO_PI, spin="y"),
+                        x_mean=-4 * math.pi + start_step * dt, x_sigma=math.pi, r_sigma=TWO_PI, spin="y"),
         "field": {"kind": FIELD_PW, "circular": 0, "a0": 20.0, "ncycles": 8.0, "phase0": 0.0,
                   "pol_angle": 0.0, "phi_start": 0.0},
-        "dt": TWO_PI / 200, "steps": 3000, "procs": PROC_NCS, "seed": 1, "next_id": 1 << 40,
+        "dt": dt, "steps": 3000, "procs": PROC_NCS, "seed": 1, "next_id": 1 << 40, "start_step": start_step,
     }
 
 
-def c2(n: int = 10_000_000) -> dict:
+def c2(n: int = 10_000_000, start_step: int = 0) -> dict:
     """Mixed precision workload: 1e7 electrons, gamma0 = 2000 (10 %), 1 mrad, unpolarised,
     circularly polarised focused pulse (w0 = 3 um, a0 = 100, 10 cycles), dt = T0/500,
     NCS with photon Stokes output.  The bunch centre meets the pulse centre at the focus
     at t = 10 pi (step 2500)."""
+    dt = TWO_PI / 500
     return {
         "name": "c2_gauss_cp_a0_100_gamma2000",
         "leptons": beam(n, seed=202, gamma0=2000.0, gamma_rel_spread=0.10, divergence=1e-3,
-                        x_mean=-10 * math.pi, x_sigma=TWO_PI, r_sigma=TWO_PI, spin="iso"),
+                        x_mean=-10 * math.pi + start_step * dt, x_sigma=TWO_PI, r_sigma=TWO_PI, spin="iso"),
         "field": {"kind": FIELD_GAUSS, "circular": 1, "a0": 100.0, "ncycles": 10.0, "phase0": 0.0,
                   "pol_angle": 0.0, "w0": 3 * TWO_PI, "x_focus": 0.0, "phi_start": 0.0},
-        "dt": TWO_PI / 500, "steps": 6000, "procs": PROC_NCS | PROC_NCS_STOKES, "seed": 2,
-        "next_id": 1 << 40, "interaction_step": 2500,
+        "dt": dt, "steps": 6000, "procs": PROC_NCS | PROC_NCS_STOKES, "seed": 2,
+        "next_id": 1 << 40, "interaction_step": 2500, "start_step": start_step,
     }
 
 
