@@ -33,6 +33,8 @@ BYTES_LEPTON = {"mixed": 48 + 12 + 8 + 48 + 12, "fp64": 48 + 24 + 8 + 48 + 24}
 # (6 x 4 or 6 x 8 B), id (8 B), alive (1 B)
 BYTES_PHOTON = {"mixed": 8 + 56 + 24 + 8 + 1, "fp64": 8 + 56 + 48 + 8 + 1}
 KERNEL_SOURCES = ["qed_kernels.hip", "qed_dev.hpp", "qed_internal.hpp"]
+# one benchmark step = one qed_step_leptons call = three launches on the stream (decide,
+# tile-count scan, event completion); HIP events bracket each call
 
 
 def kernel_hash() -> str:
@@ -233,7 +235,8 @@ def main():
                    "start_step": start, "processes": "NCS + spin flip + photon Stokes"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": tr,
-                     "kernel": "k_leptons_emit<float,true> (fused gather+Boris+T-BMT+NCS)",
+                     "kernel": "lepton step = k_leptons_decide<float,true> + k_scan + k_leptons_events<float> "
+                               "(timed together per step)",
                      "avg_launch_ms": launch_ms, "algorithmic_bytes_per_launch": alg_bytes,
                      "photons_per_launch": ph_per_launch},
         "status_bits": mixed["status"],

@@ -268,17 +268,25 @@ static double nbw_integrand(int which, double chi, double d) {
     if (which == 0) return I + (d * d + (1 - d) * (1 - d)) / dd * K2;
     return K2;
 }
+/* Gauss-Legendre on [lo, hi] */
+static double nbw_gl(int which, double chi, double lo, double hi) {
+    double s = 0, h = hi - lo;
+    for (int i = 0; i < GLN; ++i) s += gl_w[i] * nbw_integrand(which, chi, lo + 0.5 * h * (gl_x[i] + 1));
+    return 0.5 * h * s;
+}
+/* integral over [0, dend]: panels halving towards delta = 0 below min(dend, 0.01), where
+ * at large chi the spectrum switches on within delta ~ 1/chi, then panels <= 0.005      */
 static double nbw_partial(int which, double chi, double dend) {
     gl_init();
     if (dend <= 0) return 0;
     if (dend > 0.5) return 2 * nbw_partial(which, chi, 0.5) - nbw_partial(which, chi, 1 - dend);
-    int np = (int)ceil(dend / 0.005);
-    double hp = dend / np, s = 0;
-    for (int p = 0; p < np; ++p)
-        for (int i = 0; i < GLN; ++i) {
-            double d = hp * (p + 0.5 * (gl_x[i] + 1));
-            s += 0.5 * hp * gl_w[i] * nbw_integrand(which, chi, d);
-        }
+    double g = dend < 0.01 ? dend : 0.01, s = 0;
+    for (int k = 0; k < 48; ++k) s += nbw_gl(which, chi, ldexp(g, -(k + 1)), ldexp(g, -k));
+    if (dend > g) {
+        int np = (int)ceil((dend - g) / 0.005);
+        double hp = (dend - g) / np;
+        for (int p = 0; p < np; ++p) s += nbw_gl(which, chi, g + p * hp, g + (p + 1) * hp);
+    }
     return s;
 }
 double orc_nbw_Ja(double chi) { return chi > 0 ? 2 * nbw_partial(0, chi, 0.5) : 0; }
@@ -488,12 +496,16 @@ orc_tables *orc_tables_build(void) {
             double *A = T->nbw_A + (size_t)r * NDD, *B = T->nbw_B + (size_t)r * NDD;
             A[0] = 0; B[0] = 0;
             for (int j = 0; j < NDD - 1; ++j) {
-                double sa = 0, sb = 0;
-                for (int i = 0; i < GLN; ++i) {
-                    double d = hd * (j + 0.5 * (gl_x[i] + 1));
-                    double wq = 0.5 * hd * gl_w[i];
-                    sa += wq * nbw_integrand(0, chi, d);
-                    sb += wq * nbw_integrand(1, chi, d);
+                double sa, sb;
+                if (j == 0) {            /* first cell: panels halving towards delta = 0 */
+                    sa = sb = 0;
+                    for (int k = 0; k < 48; ++k) {
+                        sa += nbw_gl(0, chi, ldexp(hd, -(k + 1)), ldexp(hd, -k));
+                        sb += nbw_gl(1, chi, ldexp(hd, -(k + 1)), ldexp(hd, -k));
+                    }
+                } else {
+                    sa = nbw_gl(0, chi, j * hd, (j + 1) * hd);
+                    sb = nbw_gl(1, chi, j * hd, (j + 1) * hd);
                 }
                 A[j + 1] = A[j] + sa;
                 B[j + 1] = B[j] + sb;

@@ -100,10 +100,27 @@ void free_ctx(qed_ctx *c) {
     hipFree(c->tab32);
     hipFree(c->status);
     hipFree(c->next_id);
-    hipFree(c->scan.tile_status);
-    hipFree(c->scan.ticket);
-    hipFree(c->scan.info);
+    hipFree(c->tile_counts);
+    hipFree(c->tile_off);
+    hipFree(c->launch);
+    hipFree(c->staging);
     delete c;
+}
+
+// The event staging area holds one record per particle of the largest list passed so far.
+// Growing it synchronises the device (hipFree); lists of a fixed size allocate once.
+qed_status ensure_staging(qed_ctx *ctx, int64_t capacity) {
+    const int64_t need = ((capacity + BLOCK - 1) / BLOCK) * BLOCK;
+    if (need <= ctx->staging_cap) return QED_OK;
+    hipError_t e = hipSuccess;
+    if (ctx->staging) e = hipFree(ctx->staging);
+    ctx->staging = nullptr;
+    ctx->staging_cap = 0;
+    if (e == hipSuccess) e = hipMalloc(&ctx->staging, need * sizeof(EventRec));
+    if (e != hipSuccess) return fail(ctx, QED_ENOMEM, "staging buffer of %lld records: %s", (long long)need,
+                                     hipGetErrorString(e));
+    ctx->staging_cap = need;
+    return QED_OK;
 }
 
 }  // namespace
@@ -124,26 +141,20 @@ qed_status qed_init_tables(qed_ctx_t **out, const qed_config *cfg, hipStream_t s
         free_ctx(c);
         return QED_EHIP;
     }
-    int ncu = 0;
-    hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device);
-    c->grid_blocks = (ncu > 0 ? ncu : 256) * 8;
-    c->scan.max_tiles = MAX_TILES;
+    c->max_tiles = MAX_TILES;
     const bool ok = hipMalloc(&c->tab64, TAB_TOTAL * sizeof(double)) == hipSuccess &&
                     hipMalloc(&c->tab32, TAB_TOTAL * sizeof(float)) == hipSuccess &&
                     hipMalloc(&c->status, sizeof(uint32_t)) == hipSuccess &&
                     hipMalloc(&c->next_id, sizeof(unsigned long long)) == hipSuccess &&
-                    hipMalloc(&c->scan.tile_status, MAX_TILES * sizeof(unsigned long long)) == hipSuccess &&
-                    hipMalloc(&c->scan.ticket, 2 * sizeof(unsigned int)) == hipSuccess &&
-                    hipMalloc(&c->scan.info, 4 * sizeof(long long)) == hipSuccess;
+                    hipMalloc(&c->tile_counts, MAX_TILES * sizeof(int)) == hipSuccess &&
+                    hipMalloc(&c->tile_off, (MAX_TILES + 1) * sizeof(int64_t)) == hipSuccess &&
+                    hipMalloc(&c->launch, 4 * sizeof(int64_t)) == hipSuccess;
     if (!ok) {
         free_ctx(c);
         return QED_ENOMEM;
     }
-    c->scan.exits = c->scan.ticket + 1;
     e = hipMemsetAsync(c->status, 0, sizeof(uint32_t), s);
-    if (e == hipSuccess) e = hipMemsetAsync(c->scan.tile_status, 0, MAX_TILES * sizeof(unsigned long long), s);
-    if (e == hipSuccess) e = hipMemsetAsync(c->scan.ticket, 0, 2 * sizeof(unsigned int), s);
-    if (e == hipSuccess) e = hipMemsetAsync(c->scan.info, 0, 4 * sizeof(long long), s);
+    if (e == hipSuccess) e = hipMemsetAsync(c->launch, 0, 4 * sizeof(int64_t), s);
     if (e == hipSuccess) {
         const unsigned long long v = cfg->id_start;
         e = hipMemcpyAsync(c->next_id, &v, sizeof v, hipMemcpyHostToDevice, s);
@@ -197,6 +208,7 @@ qed_status qed_emit(qed_ctx_t *ctx, const qed_segment *segs, int nseg, qed_lepto
     if (out && (st = check_photons(ctx, out, "photons")) != QED_OK) return st;
     if (!E6) return fail(ctx, QED_EARG, "qed_emit: E6 (fields of x^n) is required");
     if (!(ctx->cfg.procs & QED_PROC_NCS)) return QED_OK;
+    if ((st = ensure_staging(ctx, p->capacity)) != QED_OK) return st;
     return launched(ctx, launch_leptons(ctx, LM_EMIT, sa, *p, const_cast<double *>(E6), out, step, s), "qed_emit");
 }
 
@@ -208,6 +220,7 @@ qed_status qed_step_leptons(qed_ctx_t *ctx, const qed_segment *segs, int nseg, q
     if ((st = seg_args(ctx, segs, nseg, sa)) != QED_OK) return st;
     if ((st = check_leptons(ctx, p, "leptons")) != QED_OK) return st;
     if (out && (st = check_photons(ctx, out, "photons")) != QED_OK) return st;
+    if ((st = ensure_staging(ctx, p->capacity)) != QED_OK) return st;
     return launched(ctx, launch_leptons(ctx, LM_FUSED, sa, *p, nullptr, out, step, s), "qed_step_leptons");
 }
 
@@ -223,6 +236,7 @@ static qed_status photon_call(qed_ctx *ctx, PhotonMode mode, const qed_segment *
     if (ep && (st = check_leptons(ctx, ep, "positrons")) != QED_OK) return st;
     if (em && em->charge != -1) return fail(ctx, QED_EARG, "%s: em must have charge -1", name);
     if (ep && ep->charge != 1) return fail(ctx, QED_EARG, "%s: ep must have charge +1", name);
+    if ((st = ensure_staging(ctx, g->capacity)) != QED_OK) return st;
     return launched(ctx, launch_photons(ctx, mode, sa, *g, em, ep, step, s), name);
 }
 
@@ -246,6 +260,7 @@ qed_status qed_compact_photons(qed_ctx_t *ctx, const qed_photons *in, qed_photon
     if ((st = check_photons(ctx, out, "out")) != QED_OK) return st;
     if (in->x == out->x || in->count == out->count)
         return fail(ctx, QED_EARG, "qed_compact_photons: in and out must be distinct buffers");
+    if ((st = ensure_staging(ctx, in->capacity)) != QED_OK) return st;
     return launched(ctx, launch_compact(ctx, *in, *out, s), "qed_compact_photons");
 }
 

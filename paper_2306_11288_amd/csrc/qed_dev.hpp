@@ -386,15 +386,23 @@ __device__ __forceinline__ void ncs_F(T u, T I, T K1, T K2, const V3<T> &Si, con
            2 * u2 * (sib * sfb - sia * sfa) * I - 4 * u * ((1 + u) * sib + sfb) * K1;
 }
 
-// One NCS step of one lepton with p = p^{n+1/2}, S = S^{n+1/2} and the fields of x^n.
-// Returns true on emission (photon filled, p and S updated); otherwise applies the
-// no-emission spin update.
+// Local frame and rates of one lepton with p = p^{n+1/2}, S = S^{n+1/2} and the fields of
+// x^n (Sec. III.C.1): n = p/|p|, a = unit transverse part of q(E + beta x B - beta(beta.E)),
+// b = n x a, s = S.b, W = C Ia, W_tot = C (Ia - s Ib), C = alpha/(sqrt3 pi xi_L gamma).
+// Returns false where chi = 0 or the acceleration vanishes (nothing happens then).
 template <class T>
-__device__ bool ncs_step(const Consts &c, const Tabs<T> &tb, double q, V3<double> &p, V3<T> &S, const V3<double> &E,
-                         const V3<double> &B, uint64_t id, int64_t step, uint32_t &st, NcsPhoton<T> &ph) {
+struct NcsFrame {
+    double chi, C, W, Wt, P;
+    V3<T> n, a, b;
+    T s, Ia, Ib;
+};
+template <class T>
+__device__ __forceinline__ bool ncs_frame(const Consts &c, const Tabs<T> &tb, double q, const V3<double> &p,
+                                          const V3<T> &S, const V3<double> &E, const V3<double> &B, uint32_t &st,
+                                          NcsFrame<T> &f) {
     const double pp2 = dot(p, p), g = sqrt(1.0 + pp2), pmag = sqrt(pp2);
-    const double chi = chi_e(c.xi_L, p, E, B);
-    if (!(chi > 0.0) || !(pmag > 0.0)) return false;
+    f.chi = chi_e(c.xi_L, p, E, B);
+    if (!(f.chi > 0.0) || !(pmag > 0.0)) return false;
     const V3<double> nd = (1.0 / pmag) * p;
     const V3<double> beta = (1.0 / g) * p;
     const double be = dot(beta, E);
@@ -402,55 +410,63 @@ __device__ bool ncs_step(const Consts &c, const Tabs<T> &tb, double q, V3<double
     const V3<double> ad = acc - dot(nd, acc) * nd;
     const double an = sqrt(dot(ad, ad));
     if (!(an > 0.0)) return false;
-    const V3<T> n = cvt<T>(nd), a = cvt<T>((1.0 / an) * ad);
-    const V3<T> b = cross(n, a);
-    const T s = dot(S, b);
-    T Ia, Ib;
-    ncs_rate<T>(tb, chi, Ia, Ib, st);
-    const double C = c.alpha / (SQRT3 * PI * c.xi_L * g);
-    const double W = C * (double)Ia, Wt = C * ((double)Ia - (double)s * (double)Ib), P = Wt * c.dt;
-    if (P > c.p_max) st |= QED_ST_PMAX;
-    double r[4];
-    uniform4(id, step, STREAM_NCS, c.seed, r);
-    if (r[1] < P) {
-        const T kappa = Ib / Ia;
-        const T tt = ncs_sample_t<T>(tb, chi, kappa, s, (T)r[0]);
-        const T t3 = tt * tt * tt;
-        const T u = (T)1.5 * (T)chi * t3, y = u / ((T)1 + u);
-        ph.k = (double)y * p;
-        p = (1.0 - (double)y) * p;
-        T I, K1, K2;
-        bessel_scaled<T>(tb, t3, I, K1, K2);
-        const T w = -(1 + u) * I + (2 + 2 * u + u * u) * K2;
-        const T fS = -u * K1 * s;
-        const T sn = dot(S, n);
-        const V3<T> gv = (-(1 + u) * (I - 2 * K2)) * S + (-u * (1 + u) * K1) * b + (-u * u * (I - K2) * sn) * n;
-        const T gn = sqrt(dot(gv, gv));
-        const V3<T> zeta = gn > (T)0 ? ((T)1 / gn) * gv : S;
-        const T pplus = (T)0.5 * ((T)1 + gn / (w + fS));
-        const V3<T> Sf = (r[2] < (double)pplus ? (T)1 : (T)-1) * zeta;
-        V3<T> xi = {0, 0, 0};
-        if (c.procs & QED_PROC_NCS_STOKES) {
-            T F[4];
-            ncs_F<T>(u, I, K1, K2, S, Sf, a, b, n, F);
-            const T fn = sqrt(F[1] * F[1] + F[2] * F[2] + F[3] * F[3]);
-            if (fn > (T)0) {
-                const T sx = r[3] < (double)((F[0] + fn) / ((T)2 * F[0])) ? (T)1 : (T)-1;
-                xi = {sx * F[1] / fn, sx * F[2] / fn, sx * F[3] / fn};
-            } else {
-                xi.z = r[3] < 0.5 ? (T)1 : (T)-1;
-            }
-        }
-        S = Sf;
-        ph.xi = xi;
-        ph.e1 = a;
-        return true;
-    }
-    const T wdt = (T)(W * c.dt), den = (T)(1.0 - Wt * c.dt), fb = (T)(C * (double)Ib * c.dt);
-    const V3<T> Sb = ((T)1 / den) * (((T)1 - wdt) * S + fb * b);
+    f.n = cvt<T>(nd);
+    f.a = cvt<T>((1.0 / an) * ad);
+    f.b = cross(f.n, f.a);
+    f.s = dot(S, f.b);
+    ncs_rate<T>(tb, f.chi, f.Ia, f.Ib, st);
+    f.C = c.alpha / (SQRT3 * PI * c.xi_L * g);
+    f.W = f.C * (double)f.Ia;
+    f.Wt = f.C * ((double)f.Ia - (double)f.s * (double)f.Ib);
+    f.P = f.Wt * c.dt;
+    if (f.P > c.p_max) st |= QED_ST_PMAX;
+    return true;
+}
+// no emission: S -> [S(1 - W dt) - f dt]/(1 - W_tot dt), renormalised (f = -C Ib b)
+template <class T>
+__device__ __forceinline__ void ncs_no_event(const Consts &c, const NcsFrame<T> &f, V3<T> &S) {
+    const T wdt = (T)(f.W * c.dt), den = (T)(1.0 - f.Wt * c.dt), fb = (T)(f.C * (double)f.Ib * c.dt);
+    const V3<T> Sb = ((T)1 / den) * (((T)1 - wdt) * S + fb * f.b);
     const T nrm = sqrt(dot(Sb, Sb));
     S = ((T)1 / nrm) * Sb;
-    return false;
+}
+// emission (given the draws r): photon fraction y by the inverse of the spin-dependent
+// spectrum (r1), k = y p, p -> (1-y) p; final spin +-g/|g| with P(+) = (1 + |g|/(w+f.S))/2
+// (r3); photon pure state +-F/|F| with P(+) = (F0 + |F|)/(2 F0) at the chosen S_f (r4).
+template <class T>
+__device__ __forceinline__ void ncs_event(const Consts &c, const Tabs<T> &tb, const NcsFrame<T> &f, const double r[4],
+                                          V3<double> &p, V3<T> &S, NcsPhoton<T> &ph) {
+    const T kappa = f.Ib / f.Ia;
+    const T tt = ncs_sample_t<T>(tb, f.chi, kappa, f.s, (T)r[0]);
+    const T t3 = tt * tt * tt;
+    const T u = (T)1.5 * (T)f.chi * t3, y = u / ((T)1 + u);
+    ph.k = (double)y * p;
+    p = (1.0 - (double)y) * p;
+    T I, K1, K2;
+    bessel_scaled<T>(tb, t3, I, K1, K2);
+    const T w = -(1 + u) * I + (2 + 2 * u + u * u) * K2;
+    const T fS = -u * K1 * f.s;
+    const T sn = dot(S, f.n);
+    const V3<T> gv = (-(1 + u) * (I - 2 * K2)) * S + (-u * (1 + u) * K1) * f.b + (-u * u * (I - K2) * sn) * f.n;
+    const T gn = sqrt(dot(gv, gv));
+    const V3<T> zeta = gn > (T)0 ? ((T)1 / gn) * gv : S;
+    const T pplus = (T)0.5 * ((T)1 + gn / (w + fS));
+    const V3<T> Sf = (r[2] < (double)pplus ? (T)1 : (T)-1) * zeta;
+    V3<T> xi = {0, 0, 0};
+    if (c.procs & QED_PROC_NCS_STOKES) {
+        T F[4];
+        ncs_F<T>(u, I, K1, K2, S, Sf, f.a, f.b, f.n, F);
+        const T fn = sqrt(F[1] * F[1] + F[2] * F[2] + F[3] * F[3]);
+        if (fn > (T)0) {
+            const T sx = r[3] < (double)((F[0] + fn) / ((T)2 * F[0])) ? (T)1 : (T)-1;
+            xi = {sx * F[1] / fn, sx * F[2] / fn, sx * F[3] / fn};
+        } else {
+            xi.z = r[3] < 0.5 ? (T)1 : (T)-1;
+        }
+    }
+    S = Sf;
+    ph.xi = xi;
+    ph.e1 = f.a;
 }
 
 // ------------------------------------------------------------------------- photons
@@ -482,17 +498,18 @@ struct PairOut {
     V3<T> Sm, Sp;        // spins
 };
 
-// Photon step at x^n (Algorithm 1 + Sec. III.D): basis rotation to E_red, VB phase,
-// NBW test and pair sampling.  Returns true if the photon decays (pair filled).
+// Photon transport at x^n (Algorithm 1): basis rotation of the Stokes vector to the frame
+// of E_red = E - n(n.E) + n x B (eq. rotation) and, if do_vb, the birefringent phase
+// (eq. rotation2).  Returns chi_gamma (0 where E_red vanishes: nothing changes then).
 template <class T>
-__device__ bool photon_step(const Consts &c, const Tabs<T> &tb, const V3<double> &k, V3<T> &xi, V3<T> &e1,
-                            const V3<double> &E, const V3<double> &B, uint64_t id, int64_t step, bool do_vb,
-                            bool do_nbw, uint32_t &st, PairOut<T> &po) {
+__device__ __forceinline__ double photon_transport(const Consts &c, const Tabs<T> &tb, const V3<double> &k, V3<T> &xi,
+                                                   V3<T> &e1, const V3<double> &E, const V3<double> &B, bool do_vb,
+                                                   uint32_t &st) {
     const double eps = sqrt(dot(k, k));
     const V3<double> n = (1.0 / eps) * k;
     const V3<double> er = E - dot(n, E) * n + cross(n, B);
     const double an = sqrt(dot(er, er));
-    if (!(an > 0.0)) return false;
+    if (!(an > 0.0)) return 0.0;
     const double chi = c.xi_L * eps * an;
     const V3<T> nt = cvt<T>(n);
     const V3<T> e1n = cvt<T>((1.0 / an) * er);
@@ -516,14 +533,35 @@ __device__ bool photon_step(const Consts &c, const Tabs<T> &tb, const V3<double>
         xi.x = y1;
         xi.y = y2;
     }
-    if (!do_nbw || eps < 2.0) return false;
-    T Ja, Jb, kappa;
+    return chi;
+}
+// chi_gamma from the stored fields (the same arithmetic as photon_transport)
+__device__ __forceinline__ double photon_chi(double xi_L, const V3<double> &k, const V3<double> &E,
+                                             const V3<double> &B) {
+    const double eps = sqrt(dot(k, k));
+    const V3<double> n = (1.0 / eps) * k;
+    const V3<double> er = E - dot(n, E) * n + cross(n, B);
+    return xi_L * eps * sqrt(dot(er, er));
+}
+// NBW event probability W_pair dt (eq. BWprob with the rate normalisation of the readings)
+template <class T>
+__device__ __forceinline__ double nbw_prob(const Consts &c, const Tabs<T> &tb, double eps, double chi, T xi3, T &Ja,
+                                           T &kappa, uint32_t &st) {
+    T Jb;
     nbw_rate<T>(tb, chi, Ja, Jb, kappa, st);
-    const double P = c.alpha / (SQRT3 * PI * c.xi_L * eps) * ((double)Ja - (double)xi.z * (double)Jb) * c.dt;
+    const double P = c.alpha / (SQRT3 * PI * c.xi_L * eps) * ((double)Ja - (double)xi3 * (double)Jb) * c.dt;
     if (P > c.p_max) st |= QED_ST_PMAX;
-    double r[4];
-    uniform4(id, step, STREAM_NBW, c.seed, r);
-    if (!(Ja > (T)0) || !(r[1] < P)) return false;
+    return P;
+}
+// pair creation (given the draws r, the rotated xi and basis e1): delta by the inverse
+// spectrum (r1), SQAs D/|D|, D'/|D'| (eqs. BWposAxis, BWeleAxis), spin pair picked by r3
+// from the weights of eqs. G0-G3 in the order (+,+),(+,-),(-,+),(-,-).
+template <class T>
+__device__ __forceinline__ void nbw_pair(const Tabs<T> &tb, const V3<double> &k, double chi, T kappa, const V3<T> &xi,
+                                         const V3<T> &e1, const double r[4], uint32_t &st, PairOut<T> &po) {
+    const double eps = sqrt(dot(k, k));
+    const V3<double> n = (1.0 / eps) * k;
+    const V3<T> nt = cvt<T>(n);
     const T d = nbw_sample_delta<T>(tb, chi, kappa, xi.z, (T)r[0]);
     const double epl = (double)d * eps, emi = eps - epl;
     T I, K1, K2;
@@ -558,7 +596,6 @@ __device__ bool photon_step(const Consts &c, const Tabs<T> &tb, const V3<double>
     po.pm = qm * n;
     po.Sp = (sel < 2 ? (T)1 : (T)-1) * zp;
     po.Sm = ((sel & 1) == 0 ? (T)1 : (T)-1) * zm;
-    return true;
 }
 
 }  // namespace qed

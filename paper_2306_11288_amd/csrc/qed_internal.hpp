@@ -49,13 +49,11 @@ struct Consts {
     uint32_t procs;
 };
 
-// ordered-append state (decoupled look-back over tiles), one per context
-struct ScanState {
-    unsigned long long *tile_status;   // [max_tiles]: flag << 62 | value
-    unsigned int *ticket;              // tile ticket counter
-    unsigned int *exits;               // blocks that finished
-    long long *info;                   // per-launch bases written by tile 0
-    int64_t max_tiles;
+// staging record of one event (decide kernel -> event kernel): particle index and the
+// fields of x^n at which the event was decided
+struct EventRec {
+    long long idx;
+    double f[6];
 };
 
 constexpr int MAX_SEG = 8;             // segments passed by value in kernel arguments
@@ -75,8 +73,12 @@ struct qed_ctx {
     float *tab32;                      // FP32 copies (mixed precision)
     uint32_t *status;                  // sticky status word
     unsigned long long *next_id;       // id counter
-    qed::ScanState scan;
-    int grid_blocks;                   // persistent grid size for append kernels
+    int *tile_counts;                  // events per 256-particle tile   [max_tiles]
+    int64_t *tile_off;                 // exclusive prefix of tile_counts [max_tiles + 1]
+    int64_t *launch;                   // bases of the last append launch [4]
+    qed::EventRec *staging;            // one slot per particle of the largest list seen
+    int64_t staging_cap;
+    int64_t max_tiles;
     char err[256];
 };
 

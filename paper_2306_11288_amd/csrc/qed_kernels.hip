@@ -1,133 +1,63 @@
 // HIP kernels of the QED particle step for gfx950 and their host launchers.
 //
-// Layout: one thread per particle, 256-thread blocks (4 wave64s).  Kernels that append
-// particles run a persistent grid that takes 256-particle tiles from a ticket counter in
-// index order; each tile ranks its events with a wavefront ballot + popcount, combines
-// the four waves in LDS, and obtains the number of events before it by a decoupled
-// look-back over the earlier tiles.  Output order is therefore the parent index order for
-// any grid size and any scheduling.  The last block to finish publishes the new list
-// counts and the id counter and clears the scan state for the next launch.
+// Every step that can create particles runs as three launches on the caller's stream:
+//   1. decide  (one thread per particle, 256-particle tiles = blocks): gather, push, spin,
+//      event test; particles without an event are finished here.  Event particles are
+//      ranked inside their tile with a wavefront ballot + popcount (waves combined in
+//      LDS) and leave a 56-byte record (index, E, B) in a staging slot tile*256 + rank;
+//      the tile's event count goes to tile_counts[tile].
+//   2. scan    (one block): exclusive prefix sum of the tile counts, launch bases (output
+//      list counts, id counter) and the new counts / id counter.
+//   3. events  (one thread per event, dense): finish each event from its record and write
+//      the new particle(s) at base + global rank.
+// The output order is the parent index order and the result is independent of thread
+// scheduling; there are no atomics on the data path and no inter-block waits, and the
+// event work (inverse-CDF search, spin and Stokes algebra) runs without divergence.
 #include "qed_dev.hpp"
 
 namespace qed {
 
-// ------------------------------------------------------------------------- scan helpers
-constexpr unsigned long long FLAG_AGG = 1ull << 62, FLAG_INC = 2ull << 62, VAL_MASK = (1ull << 62) - 1;
-constexpr int SPIN_LIMIT = 1 << 24;
-
-__device__ __forceinline__ void st_publish(unsigned long long *p, unsigned long long v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+// device list counts are trusted only up to the list capacity
+__device__ __forceinline__ int64_t clamp_count(const int64_t *count, int64_t capacity) {
+    const int64_t n = *count;
+    return n < 0 ? 0 : (n > capacity ? capacity : n);
 }
-__device__ __forceinline__ unsigned long long st_read(unsigned long long *p) {
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Number of events in all tiles before `tile` (called by one thread of the block).
-__device__ long long tile_lookback(const ScanState &sc, long long tile, long long agg, uint32_t *status) {
-    if (tile == 0) {
-        st_publish(sc.tile_status, FLAG_INC | (unsigned long long)agg);
-        return 0;
-    }
-    st_publish(sc.tile_status + tile, FLAG_AGG | (unsigned long long)agg);
-    long long excl = 0, j = tile - 1;
-    int spins = 0;
-    while (j >= 0) {
-        const unsigned long long s = st_read(sc.tile_status + j);
-        const unsigned long long flag = s & ~VAL_MASK;
-        if (flag == 0) {
-            if (++spins > SPIN_LIMIT) {     // cannot happen while earlier tiles progress
-                atomicOr(status, (uint32_t)QED_ST_SCAN);
-                break;
-            }
-            __builtin_amdgcn_s_sleep(1);
-            continue;
-        }
-        excl += (long long)(s & VAL_MASK);
-        if (flag == FLAG_INC) break;
-        --j;
-    }
-    st_publish(sc.tile_status + tile, FLAG_INC | (unsigned long long)(excl + agg));
-    return excl;
-}
-
-struct AppendShared {
-    int wave[BLOCK / 64];
-    long long tile;
-    long long excl;
-    long long base[3];   // launch bases (output counts, id counter) as seen by tile 0
-    int last;
-};
 
 // Block-wide exclusive rank of a 0/1 flag: wave ballot + popcount, waves combined in LDS.
-__device__ __forceinline__ int block_rank(bool flag, int &total, AppendShared &sh) {
+__device__ __forceinline__ int block_rank(bool flag, int &total, int *s_wave) {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const unsigned long long m = __ballot(flag);
     const int below = __popcll(m & ((1ull << lane) - 1ull));
-    if (lane == 0) sh.wave[wid] = __popcll(m);
+    if (lane == 0) s_wave[wid] = __popcll(m);
     __syncthreads();
     int pre = 0;
     total = 0;
 #pragma unroll
     for (int w = 0; w < BLOCK / 64; ++w) {
-        const int v = sh.wave[w];
+        const int v = s_wave[w];
         pre += w < wid ? v : 0;
         total += v;
     }
     return pre + below;
 }
 
-// Next tile from the ticket counter (one atomic per block), broadcast through LDS.
-__device__ __forceinline__ long long next_tile(const ScanState &sc, AppendShared &sh) {
-    __syncthreads();
-    if (threadIdx.x == 0) sh.tile = (long long)atomicAdd(sc.ticket, 1u);
-    __syncthreads();
-    return sh.tile;
+__device__ __forceinline__ void stage(EventRec *stg, int64_t slot, int64_t idx, const V3<double> &E,
+                                      const V3<double> &B) {
+    EventRec &r = stg[slot];
+    r.idx = idx;
+    r.f[0] = E.x; r.f[1] = E.y; r.f[2] = E.z;
+    r.f[3] = B.x; r.f[4] = B.y; r.f[5] = B.z;
 }
 
-// Tile rank -> global rank; tile 0 also records the launch bases (read before any
-// output of this launch is published) for every other block to read after its look-back.
-__device__ __forceinline__ void tile_offsets(const ScanState &sc, long long tile, int total, AppendShared &sh,
-                                             uint32_t *status, long long b0, long long b1, long long b2) {
-    if (threadIdx.x == 0) {
-        if (tile == 0) {
-            sc.info[0] = b0;
-            sc.info[1] = b1;
-            sc.info[2] = b2;
-        }
-        sh.excl = tile_lookback(sc, tile, total, status);
-        // ordered after the look-back's acquire (tile 0 wrote info before its release)
-        sh.base[0] = tile == 0 ? b0 : sc.info[0];
-        sh.base[1] = tile == 0 ? b1 : sc.info[1];
-        sh.base[2] = tile == 0 ? b2 : sc.info[2];
+// tile whose event range [off[t], off[t+1]) holds global event e (last t with off[t] <= e)
+__device__ __forceinline__ int64_t tile_of(const int64_t *off, int64_t ntiles, int64_t e) {
+    int64_t lo = 0, hi = ntiles - 1;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= e) lo = mid;
+        else hi = mid - 1;
     }
-    __syncthreads();
-}
-
-// Last block out: total events = inclusive value of the last tile.  Returns it in sh.excl
-// (or -1 for blocks that are not last); the caller publishes counts, then calls
-// scan_reset.
-__device__ __forceinline__ bool scan_last_block(const ScanState &sc, long long ntiles, AppendShared &sh) {
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const unsigned int e = __hip_atomic_fetch_add(sc.exits, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        sh.last = (e == gridDim.x - 1);
-        if (sh.last) {
-            __threadfence();
-            sh.excl = ntiles > 0 ? (long long)(st_read(sc.tile_status + ntiles - 1) & VAL_MASK) : 0;
-            sh.base[0] = sc.info[0];
-            sh.base[1] = sc.info[1];
-            sh.base[2] = sc.info[2];
-        }
-    }
-    __syncthreads();
-    return sh.last != 0;
-}
-__device__ __forceinline__ void scan_reset(const ScanState &sc, long long ntiles) {
-    for (long long j = threadIdx.x; j < ntiles; j += BLOCK) sc.tile_status[j] = 0;
-    if (threadIdx.x == 0) {
-        *sc.ticket = 0;
-        *sc.exits = 0;
-    }
+    return lo;
 }
 
 // ------------------------------------------------------------------------- segments
@@ -148,6 +78,62 @@ __device__ __forceinline__ void fields_for(const SegArgs &sa, int64_t i, double 
     }
 }
 
+// ------------------------------------------------------------------------- scan kernel
+struct ScanArgs {
+    const int *tile_counts;
+    int64_t *tile_off;        // [ntiles + 1]
+    const int64_t *in_count;  // list whose tiles were counted
+    int64_t in_capacity;
+    int64_t *out_count[2];    // output lists (may be null)
+    int64_t out_cap[2];
+    unsigned long long *next_id;
+    int ids_per_event;        // 0 (compaction), 1 (photon), 2 (pair)
+    int64_t *launch;          // [0] out0 base, [1] out1 base, [2] id base, [3] events
+    uint32_t *status;
+};
+constexpr int SCAN_THREADS = 1024;
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan(ScanArgs a) {
+    __shared__ int64_t s_part[SCAN_THREADS];
+    const int64_t n = clamp_count(a.in_count, a.in_capacity);
+    const int64_t ntiles = (n + BLOCK - 1) / BLOCK;
+    const int64_t per = (ntiles + SCAN_THREADS - 1) / SCAN_THREADS;
+    const int64_t lo = threadIdx.x * per, hi = lo + per < ntiles ? lo + per : ntiles;
+    int64_t sum = 0;
+    for (int64_t t = lo; t < hi; ++t) sum += a.tile_counts[t];
+    s_part[threadIdx.x] = sum;
+    __syncthreads();
+    // Hillis-Steele inclusive scan of the 1024 partial sums
+    for (int o = 1; o < SCAN_THREADS; o <<= 1) {
+        const int64_t v = (int)threadIdx.x >= o ? s_part[threadIdx.x - o] : 0;
+        __syncthreads();
+        s_part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    int64_t run = s_part[threadIdx.x] - sum;
+    for (int64_t t = lo; t < hi; ++t) {
+        a.tile_off[t] = run;
+        run += a.tile_counts[t];
+    }
+    if (threadIdx.x == SCAN_THREADS - 1) {
+        const int64_t tot = s_part[SCAN_THREADS - 1];
+        a.tile_off[ntiles] = tot;
+        uint32_t st = 0;
+        for (int k = 0; k < 2; ++k) {
+            const int64_t base = a.out_count[k] ? *a.out_count[k] : 0;
+            a.launch[k] = base;
+            if (a.out_count[k]) {
+                const int64_t c = base + tot;
+                if (c > a.out_cap[k]) st |= QED_ST_OVERFLOW;
+                *a.out_count[k] = c < a.out_cap[k] ? c : a.out_cap[k];
+            }
+        }
+        a.launch[2] = (int64_t)*a.next_id;
+        a.launch[3] = tot;
+        *a.next_id += (unsigned long long)(a.ids_per_event * tot);
+        if (st) atomicOr(a.status, st);
+    }
+}
+
 // ------------------------------------------------------------------------- leptons
 struct LeptonArgs {
     Consts c;
@@ -159,8 +145,10 @@ struct LeptonArgs {
     double *E6;
     int64_t step;
     uint32_t *status;
-    unsigned long long *next_id;
-    ScanState sc;
+    EventRec *stg;
+    int *tile_counts;
+    const int64_t *tile_off;
+    const int64_t *launch;
 };
 
 template <class T>
@@ -174,13 +162,7 @@ __device__ __forceinline__ void push_one(const LeptonArgs &a, double q, double d
     if (!isfinite(p.x + p.y + p.z + r.x + r.y + r.z) || !isfinite((double)(S.x + S.y + S.z))) st |= QED_ST_NAN;
 }
 
-// device list counts are trusted only up to the list capacity
-__device__ __forceinline__ int64_t clamp_count(const int64_t *count, int64_t capacity) {
-    const int64_t n = *count;
-    return n < 0 ? 0 : (n > capacity ? capacity : n);
-}
-
-// gather and/or push without appends: grid-stride loop
+// gather and/or push, no NCS: grid-stride loop
 template <class T, bool WRITE_E6, bool PUSH, bool E6_IN>
 __global__ __launch_bounds__(BLOCK) void k_leptons_simple(LeptonArgs a) {
     const int64_t n = clamp_count(a.L.count, a.L.capacity);
@@ -213,76 +195,88 @@ __global__ __launch_bounds__(BLOCK) void k_leptons_simple(LeptonArgs a) {
     if (st) atomicOr(a.status, st);
 }
 
-// NCS (optionally fused with gather + push); photons appended in lepton order
+// decide: (gather + push + T-BMT if PUSH, else fields from E6) + NCS test; one tile per block
 template <class T, bool PUSH>
-__global__ __launch_bounds__(BLOCK) void k_leptons_emit(LeptonArgs a) {
-    __shared__ AppendShared sh;
-    const Tabs<T> tb = {(const T *)a.tab};
+__global__ __launch_bounds__(BLOCK) void k_leptons_decide(LeptonArgs a) {
+    __shared__ int s_wave[BLOCK / 64];
     const int64_t n = clamp_count(a.L.count, a.L.capacity);
-    const long long ntiles = (n + BLOCK - 1) / BLOCK;
+    const int64_t tile = blockIdx.x;
+    if (tile * BLOCK >= n) return;
+    const Tabs<T> tb = {(const T *)a.tab};
     const double dt = a.c.dt, t = (double)a.step * dt, q = (double)a.L.charge;
     T *sx = (T *)a.L.sx, *sy = (T *)a.L.sy, *sz = (T *)a.L.sz;
+    const int64_t i = tile * BLOCK + threadIdx.x;
     uint32_t st = 0;
-    for (;;) {
-        const long long tile = next_tile(a.sc, sh);
-        if (tile >= ntiles) break;
-        const int64_t i = tile * BLOCK + threadIdx.x;
-        bool ev = false;
-        NcsPhoton<T> ph;
-        V3<double> r = {0, 0, 0};
-        double w = 0;
-        if (i < n) {
-            r = {a.L.x[i], a.L.y[i], a.L.z[i]};
-            V3<double> E, B, p = {a.L.px[i], a.L.py[i], a.L.pz[i]};
-            V3<T> S = {sx[i], sy[i], sz[i]};
-            if constexpr (PUSH) {
-                fields_for<T>(a.sa, i, t, r, E, B);
-                push_one<T>(a, q, dt, E, B, r, p, S, st);
-                a.L.x[i] = r.x; a.L.y[i] = r.y; a.L.z[i] = r.z;
-            } else {
-                const double *e = a.E6 + 6 * i;
-                E = {e[0], e[1], e[2]};
-                B = {e[3], e[4], e[5]};
-            }
-            ev = ncs_step<T>(a.c, tb, q, p, S, E, B, a.L.id[i], a.step, st, ph);
+    bool ev = false;
+    V3<double> E = {0, 0, 0}, B = {0, 0, 0};
+    if (i < n) {
+        V3<double> r = {a.L.x[i], a.L.y[i], a.L.z[i]}, p = {a.L.px[i], a.L.py[i], a.L.pz[i]};
+        V3<T> S = {sx[i], sy[i], sz[i]};
+        if constexpr (PUSH) {
+            fields_for<T>(a.sa, i, t, r, E, B);
+            push_one<T>(a, q, dt, E, B, r, p, S, st);
+            a.L.x[i] = r.x; a.L.y[i] = r.y; a.L.z[i] = r.z;
             a.L.px[i] = p.x; a.L.py[i] = p.y; a.L.pz[i] = p.z;
-            sx[i] = S.x; sy[i] = S.y; sz[i] = S.z;
-            if (ev) w = a.L.w[i];
+        } else {
+            const double *e = a.E6 + 6 * i;
+            E = {e[0], e[1], e[2]};
+            B = {e[3], e[4], e[5]};
         }
-        int total;
-        const int rank = block_rank(ev, total, sh);
-        long long b0 = 0, b2 = 0;
-        if (tile == 0 && threadIdx.x == 0) {
-            b0 = a.has_out ? (long long)*a.out.count : 0;
-            b2 = (long long)*a.next_id;
+        NcsFrame<T> f;
+        if (ncs_frame<T>(a.c, tb, q, p, S, E, B, st, f)) {
+            double rr[4];
+            uniform4(a.L.id[i], a.step, STREAM_NCS, a.c.seed, rr);
+            ev = rr[1] < f.P;
+            if (!ev) ncs_no_event<T>(a.c, f, S);
         }
-        tile_offsets(a.sc, tile, total, sh, a.status, b0, 0, b2);
-        if (ev && a.has_out) {
-            const long long k = sh.excl + rank, pos = sh.base[0] + k;
+        sx[i] = S.x; sy[i] = S.y; sz[i] = S.z;
+    }
+    int total;
+    const int rank = block_rank(ev, total, s_wave);
+    if (ev) stage(a.stg, tile * BLOCK + rank, i, E, B);
+    if (threadIdx.x == 0) a.tile_counts[tile] = total;
+    if (st) atomicOr(a.status, st);
+}
+
+// events: one thread per emission, photons written in parent order
+template <class T>
+__global__ __launch_bounds__(BLOCK) void k_leptons_events(LeptonArgs a) {
+    const int64_t n = clamp_count(a.L.count, a.L.capacity);
+    const int64_t ntiles = (n + BLOCK - 1) / BLOCK;
+    const int64_t nev = a.launch[3], base = a.launch[0], id0 = a.launch[2];
+    const Tabs<T> tb = {(const T *)a.tab};
+    const double q = (double)a.L.charge;
+    T *sx = (T *)a.L.sx, *sy = (T *)a.L.sy, *sz = (T *)a.L.sz;
+    uint32_t st = 0;
+    for (int64_t e = (int64_t)blockIdx.x * BLOCK + threadIdx.x; e < nev; e += (int64_t)gridDim.x * BLOCK) {
+        const int64_t tile = tile_of(a.tile_off, ntiles, e);
+        const EventRec &rec = a.stg[tile * BLOCK + (e - a.tile_off[tile])];
+        const int64_t i = rec.idx;
+        const V3<double> E = {rec.f[0], rec.f[1], rec.f[2]}, B = {rec.f[3], rec.f[4], rec.f[5]};
+        V3<double> p = {a.L.px[i], a.L.py[i], a.L.pz[i]};
+        V3<T> S = {sx[i], sy[i], sz[i]};
+        NcsFrame<T> f;
+        ncs_frame<T>(a.c, tb, q, p, S, E, B, st, f);
+        double rr[4];
+        uniform4(a.L.id[i], a.step, STREAM_NCS, a.c.seed, rr);
+        NcsPhoton<T> ph;
+        ncs_event<T>(a.c, tb, f, rr, p, S, ph);
+        a.L.px[i] = p.x; a.L.py[i] = p.y; a.L.pz[i] = p.z;
+        sx[i] = S.x; sy[i] = S.y; sz[i] = S.z;
+        if (a.has_out) {
+            const int64_t pos = base + e;
             if (pos < a.out.capacity) {
-                a.out.x[pos] = r.x; a.out.y[pos] = r.y; a.out.z[pos] = r.z;
+                a.out.x[pos] = a.L.x[i]; a.out.y[pos] = a.L.y[i]; a.out.z[pos] = a.L.z[i];
                 a.out.kx[pos] = ph.k.x; a.out.ky[pos] = ph.k.y; a.out.kz[pos] = ph.k.z;
-                a.out.w[pos] = w;
+                a.out.w[pos] = a.L.w[i];
                 ((T *)a.out.xi1)[pos] = ph.xi.x; ((T *)a.out.xi2)[pos] = ph.xi.y; ((T *)a.out.xi3)[pos] = ph.xi.z;
                 ((T *)a.out.e1x)[pos] = ph.e1.x; ((T *)a.out.e1y)[pos] = ph.e1.y; ((T *)a.out.e1z)[pos] = ph.e1.z;
-                a.out.id[pos] = (unsigned long long)(sh.base[2] + k);
+                a.out.id[pos] = (unsigned long long)(id0 + e);
                 a.out.alive[pos] = 1;
-            } else {
-                st |= QED_ST_OVERFLOW;
             }
         }
     }
     if (st) atomicOr(a.status, st);
-    if (!scan_last_block(a.sc, ntiles, sh)) return;
-    if (threadIdx.x == 0 && ntiles > 0) {
-        const long long tot = sh.excl;
-        *a.next_id = (unsigned long long)(sh.base[2] + tot);
-        if (a.has_out) {
-            const long long c = sh.base[0] + tot;
-            *a.out.count = c < a.out.capacity ? c : a.out.capacity;
-        }
-    }
-    scan_reset(a.sc, ntiles);
 }
 
 // ------------------------------------------------------------------------- photons
@@ -296,201 +290,208 @@ struct PhotonArgs {
     int do_vb, do_nbw, do_move;
     int64_t step;
     uint32_t *status;
-    unsigned long long *next_id;
-    ScanState sc;
+    EventRec *stg;
+    int *tile_counts;
+    const int64_t *tile_off;
+    const int64_t *launch;
 };
 
-template <class T>
-__device__ __forceinline__ bool photon_one(const PhotonArgs &a, const Tabs<T> &tb, int64_t j, double t, V3<double> &x,
-                                           uint32_t &st, PairOut<T> &po) {
-    const V3<double> k = {a.G.kx[j], a.G.ky[j], a.G.kz[j]};
+// transport (+ NBW test): one tile per block when NBW is on, grid-stride otherwise
+template <class T, bool NBW>
+__global__ __launch_bounds__(BLOCK) void k_photons_decide(PhotonArgs a) {
+    __shared__ int s_wave[BLOCK / 64];
+    const int64_t n = clamp_count(a.G.count, a.G.capacity);
+    if (NBW && (int64_t)blockIdx.x * BLOCK >= n) return;
+    const Tabs<T> tb = {(const T *)a.tab};
+    const double t = (double)a.step * a.c.dt;
     T *xi1 = (T *)a.G.xi1, *xi2 = (T *)a.G.xi2, *xi3 = (T *)a.G.xi3;
     T *e1x = (T *)a.G.e1x, *e1y = (T *)a.G.e1y, *e1z = (T *)a.G.e1z;
-    V3<T> xi = {xi1[j], xi2[j], xi3[j]}, e1 = {e1x[j], e1y[j], e1z[j]};
-    V3<double> E, B;
-    field_at<T>(a.field, t, x.x, x.y, x.z, E, B);
-    const bool ev = photon_step<T>(a.c, tb, k, xi, e1, E, B, a.G.id[j], a.step, a.do_vb, a.do_nbw, st, po);
-    xi1[j] = xi.x; xi2[j] = xi.y; xi3[j] = xi.z;
-    e1x[j] = e1.x; e1y[j] = e1.y; e1z[j] = e1.z;
-    if (ev) {
-        a.G.alive[j] = 0;
-    } else if (a.do_move) {
-        const double ie = a.c.dt / sqrt(dot(k, k));
-        const V3<double> xn = x + ie * k;
-        a.G.x[j] = xn.x; a.G.y[j] = xn.y; a.G.z[j] = xn.z;
-    }
-    return ev;
-}
-
-// rotation / VB / move without pair creation: grid-stride loop
-template <class T>
-__global__ __launch_bounds__(BLOCK) void k_photons_simple(PhotonArgs a) {
-    const Tabs<T> tb = {(const T *)a.tab};
-    const int64_t n = clamp_count(a.G.count, a.G.capacity);
-    const double t = (double)a.step * a.c.dt;
     uint32_t st = 0;
-    for (int64_t j = (int64_t)blockIdx.x * BLOCK + threadIdx.x; j < n; j += (int64_t)gridDim.x * BLOCK) {
-        if (!a.G.alive[j]) continue;
-        V3<double> x = {a.G.x[j], a.G.y[j], a.G.z[j]};
-        PairOut<T> po;
-        photon_one<T>(a, tb, j, t, x, st, po);
-    }
-    if (st) atomicOr(a.status, st);
-}
-
-// with NBW: pairs appended in photon order
-template <class T>
-__global__ __launch_bounds__(BLOCK) void k_photons_pair(PhotonArgs a) {
-    __shared__ AppendShared sh;
-    const Tabs<T> tb = {(const T *)a.tab};
-    const int64_t n = clamp_count(a.G.count, a.G.capacity);
-    const long long ntiles = (n + BLOCK - 1) / BLOCK;
-    const double t = (double)a.step * a.c.dt;
-    uint32_t st = 0;
-    for (;;) {
-        const long long tile = next_tile(a.sc, sh);
-        if (tile >= ntiles) break;
-        const int64_t j = tile * BLOCK + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    for (int64_t j = (int64_t)blockIdx.x * BLOCK + threadIdx.x;; j += stride) {
+        if (!NBW && j >= n) break;
         bool ev = false;
-        PairOut<T> po;
-        V3<double> x = {0, 0, 0};
-        double w = 0;
+        V3<double> E = {0, 0, 0}, B = {0, 0, 0};
         if (j < n && a.G.alive[j]) {
-            x = {a.G.x[j], a.G.y[j], a.G.z[j]};
-            ev = photon_one<T>(a, tb, j, t, x, st, po);
-            if (ev) w = a.G.w[j];
-        }
-        int total;
-        const int rank = block_rank(ev, total, sh);
-        long long b0 = 0, b1 = 0, b2 = 0;
-        if (tile == 0 && threadIdx.x == 0) {
-            b0 = a.has_em ? (long long)*a.em.count : 0;
-            b1 = a.has_ep ? (long long)*a.ep.count : 0;
-            b2 = (long long)*a.next_id;
-        }
-        tile_offsets(a.sc, tile, total, sh, a.status, b0, b1, b2);
-        if (ev) {
-            const long long k = sh.excl + rank;
-            const unsigned long long id0 = (unsigned long long)(sh.base[2] + 2 * k);
-            const qed_leptons *Ls[2] = {&a.em, &a.ep};
-            const int has[2] = {a.has_em, a.has_ep};
-            for (int s = 0; s < 2; ++s) {
-                if (!has[s]) continue;
-                const qed_leptons &L = *Ls[s];
-                const long long pos = sh.base[s] + k;
-                if (pos >= L.capacity) {
-                    st |= QED_ST_OVERFLOW;
-                    continue;
-                }
-                const V3<double> &p = s == 0 ? po.pm : po.pp;
-                const V3<T> &S = s == 0 ? po.Sm : po.Sp;
-                L.x[pos] = x.x; L.y[pos] = x.y; L.z[pos] = x.z;
-                L.px[pos] = p.x; L.py[pos] = p.y; L.pz[pos] = p.z;
-                ((T *)L.sx)[pos] = S.x; ((T *)L.sy)[pos] = S.y; ((T *)L.sz)[pos] = S.z;
-                L.w[pos] = w;
-                L.id[pos] = id0 + (unsigned long long)s;
+            const V3<double> x = {a.G.x[j], a.G.y[j], a.G.z[j]}, k = {a.G.kx[j], a.G.ky[j], a.G.kz[j]};
+            V3<T> xi = {xi1[j], xi2[j], xi3[j]}, e1 = {e1x[j], e1y[j], e1z[j]};
+            field_at<T>(a.field, t, x.x, x.y, x.z, E, B);
+            const double chi = photon_transport<T>(a.c, tb, k, xi, e1, E, B, a.do_vb, st);
+            const double eps = sqrt(dot(k, k));
+            if (NBW && chi > 0.0 && eps >= 2.0) {
+                T Ja, kappa;
+                const double P = nbw_prob<T>(a.c, tb, eps, chi, xi.z, Ja, kappa, st);
+                double rr[4];
+                uniform4(a.G.id[j], a.step, STREAM_NBW, a.c.seed, rr);
+                ev = Ja > (T)0 && rr[1] < P;
+            }
+            xi1[j] = xi.x; xi2[j] = xi.y; xi3[j] = xi.z;
+            e1x[j] = e1.x; e1y[j] = e1.y; e1z[j] = e1.z;
+            if (ev) {
+                a.G.alive[j] = 0;
+            } else if (a.do_move) {
+                const double ie = a.c.dt / eps;
+                a.G.x[j] = x.x + ie * k.x;
+                a.G.y[j] = x.y + ie * k.y;
+                a.G.z[j] = x.z + ie * k.z;
             }
         }
+        if constexpr (NBW) {
+            int total;
+            const int rank = block_rank(ev, total, s_wave);
+            if (ev) stage(a.stg, (int64_t)blockIdx.x * BLOCK + rank, j, E, B);
+            if (threadIdx.x == 0) a.tile_counts[blockIdx.x] = total;
+            break;   // one tile per block
+        }
     }
     if (st) atomicOr(a.status, st);
-    if (!scan_last_block(a.sc, ntiles, sh)) return;
-    if (threadIdx.x == 0 && ntiles > 0) {
-        const long long tot = sh.excl;
-        *a.next_id = (unsigned long long)(sh.base[2] + 2 * tot);
-        if (a.has_em) {
-            const long long c = sh.base[0] + tot;
-            *a.em.count = c < a.em.capacity ? c : a.em.capacity;
-        }
-        if (a.has_ep) {
-            const long long c = sh.base[1] + tot;
-            *a.ep.count = c < a.ep.capacity ? c : a.ep.capacity;
+}
+
+// pair events: electron to em, positron to ep, in photon order
+template <class T>
+__global__ __launch_bounds__(BLOCK) void k_photons_events(PhotonArgs a) {
+    const int64_t n = clamp_count(a.G.count, a.G.capacity);
+    const int64_t ntiles = (n + BLOCK - 1) / BLOCK;
+    const int64_t nev = a.launch[3], id0 = a.launch[2];
+    const Tabs<T> tb = {(const T *)a.tab};
+    const T *xi1 = (const T *)a.G.xi1, *xi2 = (const T *)a.G.xi2, *xi3 = (const T *)a.G.xi3;
+    const T *e1x = (const T *)a.G.e1x, *e1y = (const T *)a.G.e1y, *e1z = (const T *)a.G.e1z;
+    uint32_t st = 0;
+    for (int64_t e = (int64_t)blockIdx.x * BLOCK + threadIdx.x; e < nev; e += (int64_t)gridDim.x * BLOCK) {
+        const int64_t tile = tile_of(a.tile_off, ntiles, e);
+        const EventRec &rec = a.stg[tile * BLOCK + (e - a.tile_off[tile])];
+        const int64_t j = rec.idx;
+        const V3<double> E = {rec.f[0], rec.f[1], rec.f[2]}, B = {rec.f[3], rec.f[4], rec.f[5]};
+        const V3<double> k = {a.G.kx[j], a.G.ky[j], a.G.kz[j]};
+        const V3<T> xi = {xi1[j], xi2[j], xi3[j]}, e1 = {e1x[j], e1y[j], e1z[j]};
+        const double chi = photon_chi(a.c.xi_L, k, E, B), eps = sqrt(dot(k, k));
+        T Ja, kappa;
+        nbw_prob<T>(a.c, tb, eps, chi, xi.z, Ja, kappa, st);
+        double rr[4];
+        uniform4(a.G.id[j], a.step, STREAM_NBW, a.c.seed, rr);
+        PairOut<T> po;
+        nbw_pair<T>(tb, k, chi, kappa, xi, e1, rr, st, po);
+        const qed_leptons *Ls[2] = {&a.em, &a.ep};
+        const int has[2] = {a.has_em, a.has_ep};
+        for (int s = 0; s < 2; ++s) {
+            if (!has[s]) continue;
+            const qed_leptons &L = *Ls[s];
+            const int64_t pos = a.launch[s] + e;
+            if (pos >= L.capacity) continue;
+            const V3<double> &p = s == 0 ? po.pm : po.pp;
+            const V3<T> &S = s == 0 ? po.Sm : po.Sp;
+            L.x[pos] = a.G.x[j]; L.y[pos] = a.G.y[j]; L.z[pos] = a.G.z[j];
+            L.px[pos] = p.x; L.py[pos] = p.y; L.pz[pos] = p.z;
+            ((T *)L.sx)[pos] = S.x; ((T *)L.sy)[pos] = S.y; ((T *)L.sz)[pos] = S.z;
+            L.w[pos] = a.G.w[j];
+            L.id[pos] = (unsigned long long)(id0 + 2 * e + s);
         }
     }
-    scan_reset(a.sc, ntiles);
+    if (st) atomicOr(a.status, st);
 }
 
 // ------------------------------------------------------------------------- compaction
 struct CompactArgs {
     qed_photons in, out;
-    uint32_t *status;
-    ScanState sc;
+    EventRec *stg;
+    int *tile_counts;
+    const int64_t *tile_off;
+    const int64_t *launch;
 };
-template <class T>
-__global__ __launch_bounds__(BLOCK) void k_compact(CompactArgs a) {
-    __shared__ AppendShared sh;
+__global__ __launch_bounds__(BLOCK) void k_compact_mark(CompactArgs a) {
+    __shared__ int s_wave[BLOCK / 64];
     const int64_t n = clamp_count(a.in.count, a.in.capacity);
-    const long long ntiles = (n + BLOCK - 1) / BLOCK;
-    uint32_t st = 0;
-    for (;;) {
-        const long long tile = next_tile(a.sc, sh);
-        if (tile >= ntiles) break;
-        const int64_t j = tile * BLOCK + threadIdx.x;
-        const bool live = j < n && a.in.alive[j];
-        int total;
-        const int rank = block_rank(live, total, sh);
-        tile_offsets(a.sc, tile, total, sh, a.status, 0, 0, 0);
-        if (live) {
-            const long long pos = sh.excl + rank;
-            if (pos < a.out.capacity) {
-                a.out.x[pos] = a.in.x[j]; a.out.y[pos] = a.in.y[j]; a.out.z[pos] = a.in.z[j];
-                a.out.kx[pos] = a.in.kx[j]; a.out.ky[pos] = a.in.ky[j]; a.out.kz[pos] = a.in.kz[j];
-                a.out.w[pos] = a.in.w[j];
-                ((T *)a.out.xi1)[pos] = ((const T *)a.in.xi1)[j];
-                ((T *)a.out.xi2)[pos] = ((const T *)a.in.xi2)[j];
-                ((T *)a.out.xi3)[pos] = ((const T *)a.in.xi3)[j];
-                ((T *)a.out.e1x)[pos] = ((const T *)a.in.e1x)[j];
-                ((T *)a.out.e1y)[pos] = ((const T *)a.in.e1y)[j];
-                ((T *)a.out.e1z)[pos] = ((const T *)a.in.e1z)[j];
-                a.out.id[pos] = a.in.id[j];
-                a.out.alive[pos] = 1;
-            } else {
-                st |= QED_ST_OVERFLOW;
-            }
-        }
+    const int64_t tile = blockIdx.x;
+    if (tile * BLOCK >= n) return;
+    const int64_t j = tile * BLOCK + threadIdx.x;
+    const bool live = j < n && a.in.alive[j];
+    int total;
+    const int rank = block_rank(live, total, s_wave);
+    if (live) a.stg[tile * BLOCK + rank].idx = j;
+    if (threadIdx.x == 0) a.tile_counts[tile] = total;
+}
+template <class T>
+__global__ __launch_bounds__(BLOCK) void k_compact_copy(CompactArgs a) {
+    const int64_t n = clamp_count(a.in.count, a.in.capacity);
+    const int64_t ntiles = (n + BLOCK - 1) / BLOCK;
+    const int64_t nlive = a.launch[3];
+    for (int64_t e = (int64_t)blockIdx.x * BLOCK + threadIdx.x; e < nlive; e += (int64_t)gridDim.x * BLOCK) {
+        if (e >= a.out.capacity) break;
+        const int64_t tile = tile_of(a.tile_off, ntiles, e);
+        const int64_t j = a.stg[tile * BLOCK + (e - a.tile_off[tile])].idx;
+        a.out.x[e] = a.in.x[j]; a.out.y[e] = a.in.y[j]; a.out.z[e] = a.in.z[j];
+        a.out.kx[e] = a.in.kx[j]; a.out.ky[e] = a.in.ky[j]; a.out.kz[e] = a.in.kz[j];
+        a.out.w[e] = a.in.w[j];
+        ((T *)a.out.xi1)[e] = ((const T *)a.in.xi1)[j];
+        ((T *)a.out.xi2)[e] = ((const T *)a.in.xi2)[j];
+        ((T *)a.out.xi3)[e] = ((const T *)a.in.xi3)[j];
+        ((T *)a.out.e1x)[e] = ((const T *)a.in.e1x)[j];
+        ((T *)a.out.e1y)[e] = ((const T *)a.in.e1y)[j];
+        ((T *)a.out.e1z)[e] = ((const T *)a.in.e1z)[j];
+        a.out.id[e] = a.in.id[j];
+        a.out.alive[e] = 1;
     }
-    if (st) atomicOr(a.status, st);
-    if (!scan_last_block(a.sc, ntiles, sh)) return;
-    if (threadIdx.x == 0) {
-        const long long c = sh.excl;
-        *a.out.count = c < a.out.capacity ? c : a.out.capacity;
-    }
-    scan_reset(a.sc, ntiles);
 }
 
 // ------------------------------------------------------------------------- launchers
 static Consts consts_of(const qed_ctx *ctx) {
     return {ctx->cfg.xi_L, ctx->cfg.alpha, ctx->cfg.a_e, ctx->cfg.dt, ctx->cfg.p_max, ctx->cfg.seed, ctx->cfg.procs};
 }
-static int simple_grid(int64_t cap) {
-    int64_t b = (cap + BLOCK - 1) / BLOCK;
-    if (b > 65536) b = 65536;
+static int tiles_grid(int64_t cap) {
+    const int64_t b = (cap + BLOCK - 1) / BLOCK;
     return b < 1 ? 1 : (int)b;
 }
-static int append_grid(const qed_ctx *ctx, int64_t cap) {
+static int stride_grid(int64_t cap, int64_t limit) {
     int64_t b = (cap + BLOCK - 1) / BLOCK;
-    if (b > ctx->grid_blocks) b = ctx->grid_blocks;
+    if (b > limit) b = limit;
     return b < 1 ? 1 : (int)b;
+}
+static hipError_t launch_scan(qed_ctx *ctx, const int64_t *in_count, int64_t in_cap, int64_t *c0, int64_t cap0,
+                              int64_t *c1, int64_t cap1, int ids, hipStream_t s) {
+    ScanArgs sa{};
+    sa.tile_counts = ctx->tile_counts;
+    sa.tile_off = ctx->tile_off;
+    sa.in_count = in_count;
+    sa.in_capacity = in_cap;
+    sa.out_count[0] = c0;
+    sa.out_cap[0] = cap0;
+    sa.out_count[1] = c1;
+    sa.out_cap[1] = cap1;
+    sa.next_id = ctx->next_id;
+    sa.ids_per_event = ids;
+    sa.launch = ctx->launch;
+    sa.status = ctx->status;
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(SCAN_THREADS), 0, s, sa);
+    return hipGetLastError();
 }
 
 template <class T>
 static hipError_t launch_leptons_t(qed_ctx *ctx, LeptonMode mode, const LeptonArgs &a, hipStream_t s) {
-    const int gs = simple_grid(a.L.capacity), ga = append_grid(ctx, a.L.capacity);
+    const int gs = stride_grid(a.L.capacity, 65536), gt = tiles_grid(a.L.capacity);
     switch (mode) {
     case LM_GATHER:
         hipLaunchKernelGGL((k_leptons_simple<T, true, false, false>), dim3(gs), dim3(BLOCK), 0, s, a);
-        break;
+        return hipGetLastError();
     case LM_PUSH:
         if (a.E6) hipLaunchKernelGGL((k_leptons_simple<T, false, true, true>), dim3(gs), dim3(BLOCK), 0, s, a);
         else hipLaunchKernelGGL((k_leptons_simple<T, false, true, false>), dim3(gs), dim3(BLOCK), 0, s, a);
-        break;
+        return hipGetLastError();
     case LM_EMIT:
-        hipLaunchKernelGGL((k_leptons_emit<T, false>), dim3(ga), dim3(BLOCK), 0, s, a);
-        break;
     case LM_FUSED:
-        if (a.c.procs & QED_PROC_NCS) hipLaunchKernelGGL((k_leptons_emit<T, true>), dim3(ga), dim3(BLOCK), 0, s, a);
-        else hipLaunchKernelGGL((k_leptons_simple<T, false, true, false>), dim3(gs), dim3(BLOCK), 0, s, a);
         break;
     }
+    if (!(a.c.procs & QED_PROC_NCS)) {   // a fused step without NCS is a push
+        hipLaunchKernelGGL((k_leptons_simple<T, false, true, false>), dim3(gs), dim3(BLOCK), 0, s, a);
+        return hipGetLastError();
+    }
+    if (mode == LM_FUSED) hipLaunchKernelGGL((k_leptons_decide<T, true>), dim3(gt), dim3(BLOCK), 0, s, a);
+    else hipLaunchKernelGGL((k_leptons_decide<T, false>), dim3(gt), dim3(BLOCK), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = launch_scan(ctx, a.L.count, a.L.capacity, a.has_out ? a.out.count : nullptr, a.has_out ? a.out.capacity : 0,
+                    nullptr, 0, 1, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_leptons_events<T>, dim3(stride_grid(a.L.capacity, 2048)), dim3(BLOCK), 0, s, a);
     return hipGetLastError();
 }
 
@@ -505,14 +506,32 @@ hipError_t launch_leptons(qed_ctx *ctx, LeptonMode mode, const SegArgs &sa, cons
     a.E6 = E6;
     a.step = step;
     a.status = ctx->status;
-    a.next_id = ctx->next_id;
-    a.sc = ctx->scan;
+    a.stg = ctx->staging;
+    a.tile_counts = ctx->tile_counts;
+    a.tile_off = ctx->tile_off;
+    a.launch = ctx->launch;
     if (ctx->cfg.precision == QED_MIXED) {
         a.tab = ctx->tab32;
         return launch_leptons_t<float>(ctx, mode, a, s);
     }
     a.tab = ctx->tab64;
     return launch_leptons_t<double>(ctx, mode, a, s);
+}
+
+template <class T>
+static hipError_t launch_photons_t(qed_ctx *ctx, const PhotonArgs &a, hipStream_t s) {
+    if (!a.do_nbw) {
+        hipLaunchKernelGGL((k_photons_decide<T, false>), dim3(stride_grid(a.G.capacity, 65536)), dim3(BLOCK), 0, s, a);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL((k_photons_decide<T, true>), dim3(tiles_grid(a.G.capacity)), dim3(BLOCK), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = launch_scan(ctx, a.G.count, a.G.capacity, a.has_em ? a.em.count : nullptr, a.has_em ? a.em.capacity : 0,
+                    a.has_ep ? a.ep.count : nullptr, a.has_ep ? a.ep.capacity : 0, 2, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_photons_events<T>, dim3(stride_grid(a.G.capacity, 2048)), dim3(BLOCK), 0, s, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_photons(qed_ctx *ctx, PhotonMode mode, const SegArgs &sa, const qed_photons &G,
@@ -530,26 +549,29 @@ hipError_t launch_photons(qed_ctx *ctx, PhotonMode mode, const SegArgs &sa, cons
     a.do_move = mode != PM_BIREF;
     a.step = step;
     a.status = ctx->status;
-    a.next_id = ctx->next_id;
-    a.sc = ctx->scan;
-    const bool mixed = ctx->cfg.precision == QED_MIXED;
-    a.tab = mixed ? (const void *)ctx->tab32 : (const void *)ctx->tab64;
-    const int gs = simple_grid(G.capacity), ga = append_grid(ctx, G.capacity);
-    if (a.do_nbw) {
-        if (mixed) hipLaunchKernelGGL(k_photons_pair<float>, dim3(ga), dim3(BLOCK), 0, s, a);
-        else hipLaunchKernelGGL(k_photons_pair<double>, dim3(ga), dim3(BLOCK), 0, s, a);
-    } else {
-        if (mixed) hipLaunchKernelGGL(k_photons_simple<float>, dim3(gs), dim3(BLOCK), 0, s, a);
-        else hipLaunchKernelGGL(k_photons_simple<double>, dim3(gs), dim3(BLOCK), 0, s, a);
+    a.stg = ctx->staging;
+    a.tile_counts = ctx->tile_counts;
+    a.tile_off = ctx->tile_off;
+    a.launch = ctx->launch;
+    if (ctx->cfg.precision == QED_MIXED) {
+        a.tab = ctx->tab32;
+        return launch_photons_t<float>(ctx, a, s);
     }
-    return hipGetLastError();
+    a.tab = ctx->tab64;
+    return launch_photons_t<double>(ctx, a, s);
 }
 
 hipError_t launch_compact(qed_ctx *ctx, const qed_photons &in, const qed_photons &out, hipStream_t s) {
-    CompactArgs a{in, out, ctx->status, ctx->scan};
-    const int ga = append_grid(ctx, in.capacity);
-    if (ctx->cfg.precision == QED_MIXED) hipLaunchKernelGGL(k_compact<float>, dim3(ga), dim3(BLOCK), 0, s, a);
-    else hipLaunchKernelGGL(k_compact<double>, dim3(ga), dim3(BLOCK), 0, s, a);
+    CompactArgs a{in, out, ctx->staging, ctx->tile_counts, ctx->tile_off, ctx->launch};
+    hipLaunchKernelGGL(k_compact_mark, dim3(tiles_grid(in.capacity)), dim3(BLOCK), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = launch_scan(ctx, in.count, in.capacity, out.count, out.capacity, nullptr, 0, 0, s);
+    if (e != hipSuccess) return e;
+    if (ctx->cfg.precision == QED_MIXED)
+        hipLaunchKernelGGL(k_compact_copy<float>, dim3(stride_grid(in.capacity, 2048)), dim3(BLOCK), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_compact_copy<double>, dim3(stride_grid(in.capacity, 2048)), dim3(BLOCK), 0, s, a);
     return hipGetLastError();
 }
 

@@ -182,21 +182,37 @@ __global__ void k_ncs_panels(double *scratch, GaussRule g) {
     scratch[2 * ((int64_t)row * NCT + j + 1) + 1] = 0.5 * ht * sb;
 }
 
+// Gauss-Legendre over [lo, hi] of both NBW integrands
+__device__ __forceinline__ void nbw_panel(double chi, double lo, double hi, const GaussRule &g, double &sa,
+                                          double &sb) {
+    const double h = hi - lo;
+    double a = 0.0, b = 0.0;
+    for (int i = 0; i < GQ; ++i) {
+        double fa, fb;
+        nbw_integrand(chi, lo + 0.5 * h * (g.x[i] + 1.0), fa, fb);
+        a += g.w[i] * fa;
+        b += g.w[i] * fb;
+    }
+    sa += 0.5 * h * a;
+    sb += 0.5 * h * b;
+}
+
+// per-cell integrals; the first cell (from delta = 0) is split into halving panels because
+// at large chi the spectrum switches on within delta ~ 1/chi
 __global__ void k_nbw_panels(double *scratch, GaussRule g) {
     const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= (int64_t)NDR * (NDD - 1)) return;
     const int row = (int)(id / (NDD - 1)), j = (int)(id % (NDD - 1));
     const double chi = exp(P_LO + row * ((P_HI - P_LO) / (NDR - 1)));
-    const double hd = 0.5 / (NDD - 1), d0 = j * hd;
+    const double hd = 0.5 / (NDD - 1);
     double sa = 0.0, sb = 0.0;
-    for (int i = 0; i < GQ; ++i) {
-        double fa, fb;
-        nbw_integrand(chi, d0 + 0.5 * hd * (g.x[i] + 1.0), fa, fb);
-        sa += g.w[i] * fa;
-        sb += g.w[i] * fb;
+    if (j == 0) {
+        for (int k = 0; k < 52; ++k) nbw_panel(chi, ldexp(hd, -(k + 1)), ldexp(hd, -k), g, sa, sb);
+    } else {
+        nbw_panel(chi, j * hd, (j + 1) * hd, g, sa, sb);
     }
-    scratch[2 * ((int64_t)row * NDD + j + 1)] = 0.5 * hd * sa;
-    scratch[2 * ((int64_t)row * NDD + j + 1) + 1] = 0.5 * hd * sb;
+    scratch[2 * ((int64_t)row * NDD + j + 1)] = sa;
+    scratch[2 * ((int64_t)row * NDD + j + 1) + 1] = sb;
 }
 
 // running sums along each row, normalised so the last column equals `last`
@@ -228,15 +244,18 @@ __global__ void k_nbw_rate(double *tab, GaussRule g) {
     __shared__ double sh[8];
     const int r = blockIdx.x;
     const double chi = exp(P_LO + r * ((P_HI - P_LO) / (NP - 1)));
-    const int np = 160;
-    const double hq = 0.5 / np;
+    // [0, 1/64] in halving panels (onset at delta ~ 1/chi), then 124 panels up to 1/2
+    const int ng = 50, nu = 124;
+    const double g0 = 1.0 / 64.0, hq = (0.5 - g0) / nu;
     double sa = 0.0, sb = 0.0;
-    for (int q = threadIdx.x; q < np * GQ; q += blockDim.x) {
+    for (int q = threadIdx.x; q < (ng + nu) * GQ; q += blockDim.x) {
         const int p = q / GQ, i = q % GQ;
+        const double lo = p < ng ? ldexp(g0, -(p + 1)) : g0 + (p - ng) * hq;
+        const double hi = p < ng ? ldexp(g0, -p) : g0 + (p - ng + 1) * hq;
         double fa, fb;
-        nbw_integrand(chi, hq * (p + 0.5 * (g.x[i] + 1.0)), fa, fb);
-        sa += 0.5 * hq * g.w[i] * fa;
-        sb += 0.5 * hq * g.w[i] * fb;
+        nbw_integrand(chi, lo + 0.5 * (hi - lo) * (g.x[i] + 1.0), fa, fb);
+        sa += 0.5 * (hi - lo) * g.w[i] * fa;
+        sb += 0.5 * (hi - lo) * g.w[i] * fb;
     }
     const double Ja = 2.0 * block_sum(sa, sh);
     const double Jb = 2.0 * block_sum(sb, sh);

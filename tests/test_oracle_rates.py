@@ -201,14 +201,16 @@ def test_longitudinal_spin_gives_circular_photons():
 
 
 # ----------------------------------------------------------------------------- NBW
-@pytest.mark.parametrize("chi", [0.3, 1.0, 8.0])
+@pytest.mark.parametrize("chi", [0.3, 1.0, 8.0, 100.0, 900.0])
 def test_nbw_J_vs_scipy(chi):
     def rho(d):
         return 2 / (3 * chi * d * (1 - d))
     fa = lambda d: ik13(rho(d)) + (d * d + (1 - d) ** 2) / (d * (1 - d)) * sp.kv(2 / 3, rho(d))
     fb = lambda d: sp.kv(2 / 3, rho(d))
-    ja = 2 * si.quad(fa, 1e-9, 0.5, epsabs=0, epsrel=1e-11, limit=300)[0]
-    jb = 2 * si.quad(fb, 1e-9, 0.5, epsabs=0, epsrel=1e-12, limit=300)[0]
+    # at large chi the spectrum switches on at delta ~ 1/chi: give quad those breakpoints
+    pts = sorted({1e-12, 0.5} | {v for v in (0.1 / chi, 1 / chi, 10 / chi) if v < 0.5})
+    ja = 2 * sum(si.quad(fa, a, b, epsabs=0, epsrel=1e-11, limit=300)[0] for a, b in zip(pts[:-1], pts[1:]))
+    jb = 2 * sum(si.quad(fb, a, b, epsabs=0, epsrel=1e-12, limit=300)[0] for a, b in zip(pts[:-1], pts[1:]))
     assert oracle.nbw_Ja(chi) == pytest.approx(ja, rel=1e-9)
     assert oracle.nbw_Jb(chi) == pytest.approx(jb, rel=1e-10)
 
