@@ -161,8 +161,9 @@ def cpu_baseline(cfg_small, budget_s=15.0):
     import oracle
     st = cfg_small["leptons"]
     n = len(st["x"])
+    max_steps = 400
     L = oracle.LeptonArrays.from_state(st)
-    G = oracle.PhotonArrays.empty(200 * n)
+    G = oracle.PhotonArrays.empty(int(0.03 * n * max_steps) + 1000)
     sim = oracle.Sim(dt=cfg_small["dt"], procs=cfg_small["procs"], seed=cfg_small["seed"],
                      next_id=cfg_small["next_id"])
     f = oracle.make_field(cfg_small["field"])
@@ -170,7 +171,7 @@ def cpu_baseline(cfg_small, budget_s=15.0):
     s0 = cfg_small["start_step"]
     steps = 0
     t0 = time.perf_counter()
-    while time.perf_counter() - t0 < budget_s and steps < 2000:
+    while time.perf_counter() - t0 < budget_s and steps < max_steps:
         sim.step(f, L, None, G, s0 + steps)
         steps += 1
     el = time.perf_counter() - t0
@@ -186,7 +187,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=10_000_000, help="electrons (default: the full workload)")
-    ap.add_argument("--cpu-sample", type=int, default=4000)
+    ap.add_argument("--cpu-sample", type=int, default=200_000)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
@@ -235,8 +236,8 @@ def main():
                    "start_step": start, "processes": "NCS + spin flip + photon Stokes"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": tr,
-                     "kernel": "lepton step = k_leptons_decide<float,true> + k_scan + k_leptons_events<float> "
-                               "(timed together per step)",
+                     "kernel": "lepton step = k_leptons_decide<float,push,gauss> + k_scan + "
+                               "k_leptons_events<float,push,gauss> (timed together per step)",
                      "avg_launch_ms": launch_ms, "algorithmic_bytes_per_launch": alg_bytes,
                      "photons_per_launch": ph_per_launch},
         "status_bits": mixed["status"],

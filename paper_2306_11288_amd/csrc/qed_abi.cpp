@@ -4,7 +4,9 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <cmath>
 #include <new>
+#include <vector>
 #include "qed_internal.hpp"
 
 using namespace qed;
@@ -12,6 +14,7 @@ using namespace qed;
 namespace {
 
 constexpr int64_t MAX_TILES = 1 << 20;   // ordered-append tiles: lists up to 2^28 particles
+constexpr int64_t GROUP_TOT_LEN = MAX_TILES / EV_GROUP + 1;
 
 qed_status fail(qed_ctx *ctx, qed_status code, const char *fmt, ...) {
     if (ctx) {
@@ -46,10 +49,52 @@ qed_status check_field(qed_ctx *ctx, const qed_field &f) {
     return fail(ctx, QED_EARG, "field: unknown kind %d", f.kind);
 }
 
-qed_status seg_args(qed_ctx *ctx, const qed_segment *segs, int nseg, SegArgs &sa) {
+}  // namespace
+
+FieldDev qed::field_dev(const qed_field &f) {
+    constexpr double PI = 3.141592653589793;
+    FieldDev d;
+    std::memset(&d, 0, sizeof d);
+    d.kind = f.kind;
+    d.circular = f.circular;
+    if (f.kind == QED_FIELD_CONST) {
+        for (int c = 0; c < 3; ++c) {
+            d.c.e0[c] = f.e0[c];
+            d.c.b0[c] = f.b0[c];
+        }
+    } else if (f.kind == QED_FIELD_GRID2D) {
+        for (int c = 0; c < 6; ++c) d.g.g[c] = f.grid[c];
+        d.g.nx = f.nx;
+        d.g.ny = f.ny;
+        d.g.inv_dx = 1.0 / f.dx;
+        d.g.inv_dy = 1.0 / f.dy;
+        d.g.gx0 = f.gx0;
+        d.g.gy0 = f.gy0;
+    } else if (f.kind == QED_FIELD_PW || f.kind == QED_FIELD_GAUSS) {
+        PulseDev &p = d.p;
+        p.a0 = f.a0;
+        p.phase0 = f.phase0;
+        p.phi_start = f.phi_start;
+        p.L = 2.0 * PI * f.ncycles;
+        p.pi_over_L = PI / p.L;
+        p.inv_L = 1.0 / p.L;
+        p.inv_2L = 0.5 * p.inv_L;
+        p.cp = std::cos(f.pol_angle);
+        p.sp = std::sin(f.pol_angle);
+        p.x_focus = f.x_focus;
+        p.w0sq = f.w0 * f.w0;
+        p.zr = 0.5 * p.w0sq;
+        p.inv_zr = p.zr > 0 ? 1.0 / p.zr : 0.0;
+        p.inv_w0sq = p.w0sq > 0 ? 1.0 / p.w0sq : 0.0;
+    }
+    return d;
+}
+
+namespace {
+
+qed_status seg_args(qed_ctx *ctx, const qed_segment *segs, int nseg, SegArgs &sa, hipStream_t stream) {
     if (!segs) return fail(ctx, QED_EARG, "segments: NULL");
     if (nseg < 1 || nseg > MAX_SEG) return fail(ctx, QED_EARG, "segments: nseg must be in [1, %d]", MAX_SEG);
-    sa.nseg = nseg;
     for (int s = 0; s < nseg; ++s) {
         if (segs[s].begin < 0 || segs[s].end < segs[s].begin)
             return fail(ctx, QED_EARG, "segment %d: bad range [%lld, %lld)", s, (long long)segs[s].begin,
@@ -58,8 +103,47 @@ qed_status seg_args(qed_ctx *ctx, const qed_segment *segs, int nseg, SegArgs &sa
             return fail(ctx, QED_EARG, "segment %d: ranges must be sorted and disjoint", s);
         const qed_status st = check_field(ctx, segs[s].field);
         if (st != QED_OK) return st;
-        sa.seg[s] = segs[s];
     }
+    sa.nseg = nseg;
+    sa.begin0 = segs[0].begin;
+    sa.end0 = segs[0].end;
+    sa.f0 = field_dev(segs[0].field);
+    sa.segs = nullptr;
+    if (nseg == 1) return QED_OK;
+    // several segments: upload unless identical to the list already on the device
+    const size_t bytes = sizeof(DevSegment) * (size_t)nseg;
+    std::vector<DevSegment> dev((size_t)nseg);
+    for (int k = 0; k < nseg; ++k) {
+        std::memset(&dev[k], 0, sizeof(DevSegment));   // padding too, for the comparison below
+        dev[k].begin = segs[k].begin;
+        dev[k].end = segs[k].end;
+        dev[k].f = field_dev(segs[k].field);
+    }
+    if (nseg != ctx->nseg_dev || std::memcmp(ctx->hsegs, dev.data(), bytes) != 0) {
+        hipError_t e = hipSuccess;
+        if (ctx->nseg_dev > 0) e = hipEventSynchronize(ctx->seg_copied);   // host staging reusable
+        if (e == hipSuccess && nseg > ctx->nseg_cap) {
+            hipFree(ctx->dsegs);
+            hipHostFree(ctx->hsegs);
+            ctx->dsegs = nullptr;
+            ctx->hsegs = nullptr;
+            ctx->nseg_cap = 0;
+            e = hipMalloc(&ctx->dsegs, bytes);
+            if (e == hipSuccess) e = hipHostMalloc((void **)&ctx->hsegs, bytes, hipHostMallocDefault);
+            if (e == hipSuccess) ctx->nseg_cap = nseg;
+        }
+        if (e == hipSuccess) {
+            std::memcpy(ctx->hsegs, dev.data(), bytes);
+            e = hipMemcpyAsync(ctx->dsegs, ctx->hsegs, bytes, hipMemcpyHostToDevice, stream);
+        }
+        if (e == hipSuccess) e = hipEventRecord(ctx->seg_copied, stream);
+        if (e != hipSuccess) {
+            ctx->nseg_dev = 0;
+            return hip_fail(ctx, e, "segment upload");
+        }
+        ctx->nseg_dev = nseg;
+    }
+    sa.segs = ctx->dsegs;
     return QED_OK;
 }
 
@@ -101,9 +185,13 @@ void free_ctx(qed_ctx *c) {
     hipFree(c->status);
     hipFree(c->next_id);
     hipFree(c->tile_counts);
+    hipFree(c->group_tot);
     hipFree(c->tile_off);
     hipFree(c->launch);
     hipFree(c->staging);
+    hipFree(c->dsegs);
+    if (c->hsegs) hipHostFree(c->hsegs);
+    if (c->seg_copied) hipEventDestroy(c->seg_copied);
     delete c;
 }
 
@@ -116,7 +204,7 @@ qed_status ensure_staging(qed_ctx *ctx, int64_t capacity) {
     if (ctx->staging) e = hipFree(ctx->staging);
     ctx->staging = nullptr;
     ctx->staging_cap = 0;
-    if (e == hipSuccess) e = hipMalloc(&ctx->staging, need * sizeof(EventRec));
+    if (e == hipSuccess) e = hipMalloc(&ctx->staging, (size_t)need * STAGING_SLOT);
     if (e != hipSuccess) return fail(ctx, QED_ENOMEM, "staging buffer of %lld records: %s", (long long)need,
                                      hipGetErrorString(e));
     ctx->staging_cap = need;
@@ -147,14 +235,17 @@ qed_status qed_init_tables(qed_ctx_t **out, const qed_config *cfg, hipStream_t s
                     hipMalloc(&c->status, sizeof(uint32_t)) == hipSuccess &&
                     hipMalloc(&c->next_id, sizeof(unsigned long long)) == hipSuccess &&
                     hipMalloc(&c->tile_counts, MAX_TILES * sizeof(int)) == hipSuccess &&
+                    hipMalloc(&c->group_tot, GROUP_TOT_LEN * sizeof(int)) == hipSuccess &&
                     hipMalloc(&c->tile_off, (MAX_TILES + 1) * sizeof(int64_t)) == hipSuccess &&
-                    hipMalloc(&c->launch, 4 * sizeof(int64_t)) == hipSuccess;
+                    hipMalloc(&c->launch, 4 * sizeof(int64_t)) == hipSuccess &&
+                    hipEventCreateWithFlags(&c->seg_copied, hipEventDisableTiming) == hipSuccess;
     if (!ok) {
         free_ctx(c);
         return QED_ENOMEM;
     }
     e = hipMemsetAsync(c->status, 0, sizeof(uint32_t), s);
     if (e == hipSuccess) e = hipMemsetAsync(c->launch, 0, 4 * sizeof(int64_t), s);
+    if (e == hipSuccess) e = hipMemsetAsync(c->group_tot, 0, GROUP_TOT_LEN * sizeof(int), s);
     if (e == hipSuccess) {
         const unsigned long long v = cfg->id_start;
         e = hipMemcpyAsync(c->next_id, &v, sizeof v, hipMemcpyHostToDevice, s);
@@ -181,7 +272,7 @@ qed_status qed_gather(qed_ctx_t *ctx, const qed_segment *segs, int nseg, const q
     qed_status st = ready(ctx);
     if (st != QED_OK) return st;
     SegArgs sa{};
-    if ((st = seg_args(ctx, segs, nseg, sa)) != QED_OK) return st;
+    if ((st = seg_args(ctx, segs, nseg, sa, s)) != QED_OK) return st;
     if ((st = check_leptons(ctx, p, "leptons")) != QED_OK) return st;
     if (!E6) return fail(ctx, QED_EARG, "qed_gather: E6 is NULL");
     return launched(ctx, launch_leptons(ctx, LM_GATHER, sa, *p, E6, nullptr, step, s), "qed_gather");
@@ -192,7 +283,7 @@ qed_status qed_push_spin(qed_ctx_t *ctx, const qed_segment *segs, int nseg, qed_
     qed_status st = ready(ctx);
     if (st != QED_OK) return st;
     SegArgs sa{};
-    if ((st = seg_args(ctx, segs, nseg, sa)) != QED_OK) return st;
+    if ((st = seg_args(ctx, segs, nseg, sa, s)) != QED_OK) return st;
     if ((st = check_leptons(ctx, p, "leptons")) != QED_OK) return st;
     return launched(ctx, launch_leptons(ctx, LM_PUSH, sa, *p, const_cast<double *>(E6), nullptr, step, s),
                     "qed_push_spin");
@@ -203,7 +294,7 @@ qed_status qed_emit(qed_ctx_t *ctx, const qed_segment *segs, int nseg, qed_lepto
     qed_status st = ready(ctx);
     if (st != QED_OK) return st;
     SegArgs sa{};
-    if ((st = seg_args(ctx, segs, nseg, sa)) != QED_OK) return st;
+    if ((st = seg_args(ctx, segs, nseg, sa, s)) != QED_OK) return st;
     if ((st = check_leptons(ctx, p, "leptons")) != QED_OK) return st;
     if (out && (st = check_photons(ctx, out, "photons")) != QED_OK) return st;
     if (!E6) return fail(ctx, QED_EARG, "qed_emit: E6 (fields of x^n) is required");
@@ -217,7 +308,7 @@ qed_status qed_step_leptons(qed_ctx_t *ctx, const qed_segment *segs, int nseg, q
     qed_status st = ready(ctx);
     if (st != QED_OK) return st;
     SegArgs sa{};
-    if ((st = seg_args(ctx, segs, nseg, sa)) != QED_OK) return st;
+    if ((st = seg_args(ctx, segs, nseg, sa, s)) != QED_OK) return st;
     if ((st = check_leptons(ctx, p, "leptons")) != QED_OK) return st;
     if (out && (st = check_photons(ctx, out, "photons")) != QED_OK) return st;
     if ((st = ensure_staging(ctx, p->capacity)) != QED_OK) return st;
@@ -229,7 +320,7 @@ static qed_status photon_call(qed_ctx *ctx, PhotonMode mode, const qed_segment *
     qed_status st = ready(ctx);
     if (st != QED_OK) return st;
     SegArgs sa{};
-    if ((st = seg_args(ctx, segs, nseg, sa)) != QED_OK) return st;
+    if ((st = seg_args(ctx, segs, nseg, sa, s)) != QED_OK) return st;
     if (nseg != 1) return fail(ctx, QED_EARG, "%s: photon calls take exactly one segment", name);
     if ((st = check_photons(ctx, g, "photons")) != QED_OK) return st;
     if (em && (st = check_leptons(ctx, em, "electrons")) != QED_OK) return st;

@@ -63,7 +63,16 @@ __device__ __forceinline__ void uniform4(uint64_t id, int64_t step, uint32_t str
 // ------------------------------------------------------------------------- fields
 // FT: real type of the transcendental work (double, or float after an FP64 reduction of
 // the carrier phase).  Output fields are double.
-__device__ __forceinline__ double reduce_2pi(double a) { return a - TWO_PI * rint(a * (1.0 / TWO_PI)); }
+// Reciprocal and natural log: FP32 uses the hardware approximations (v_rcp_f32, v_log_f32,
+// about 1 ulp), FP64 the correctly rounded library forms.
+__device__ __forceinline__ float rcp(float v) { return __builtin_amdgcn_rcpf(v); }
+__device__ __forceinline__ double rcp(double v) { return 1.0 / v; }
+__device__ __forceinline__ float lnx(float v) { return __builtin_amdgcn_logf(v) * 0.69314718055994531f; }
+__device__ __forceinline__ double lnx(double v) { return log(v); }
+// a - round(a) for a phase given in revolutions, i.e. the phase reduced to [-1/2, 1/2]
+__device__ __forceinline__ double frac_rev(double a) { return a - rint(a); }
+__device__ __forceinline__ float rsq(float v) { return rsqrtf(v); }
+__device__ __forceinline__ double rsq(double v) { return rsqrt(v); }
 
 __device__ __forceinline__ void tsc_w(double xg, int half, int &j0, double w[3]) {
     const int j = half ? (int)floor(xg) : (int)floor(xg + 0.5);
@@ -75,12 +84,12 @@ __device__ __forceinline__ void tsc_w(double xg, int half, int &j0, double w[3])
 }
 
 template <class FT>
-__device__ __forceinline__ double grid_gather(const qed_field &f, const float *__restrict__ g, int hx, int hy,
+__device__ __forceinline__ double grid_gather(const GridDev &f, const float *__restrict__ g, int hx, int hy,
                                               double x, double y) {
     int i0, j0;
     double wx[3], wy[3];
-    tsc_w((x - f.gx0) / f.dx, hx, i0, wx);
-    tsc_w((y - f.gy0) / f.dy, hy, j0, wy);
+    tsc_w((x - f.gx0) * f.inv_dx, hx, i0, wx);
+    tsc_w((y - f.gy0) * f.inv_dy, hy, j0, wy);
     FT s = 0;
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
@@ -98,105 +107,152 @@ __device__ __forceinline__ double grid_gather(const qed_field &f, const float *_
     return (double)s;
 }
 
-template <class FT>
-__device__ void field_at(const qed_field &f, double t, double x, double y, double z, V3<double> &E, V3<double> &B) {
+// Laser pulses (plane wave E = -dA/dphi with a sin^2 envelope; paraxial Gaussian beam at
+// zeroth order), KIND = QED_FIELD_PW or QED_FIELD_GAUSS.  In single precision every phase
+// is reduced in FP64 and handed to the hardware sine / cosine in revolutions (v_sin_f32
+// and v_cos_f32 return sin(2 pi x), cos(2 pi x)); the Gaussian amplitude uses v_exp_f32,
+// v_rsq_f32 and v_rcp_f32.
+template <class FT, int KIND>
+__device__ __forceinline__ void field_pulse(const FieldDev &f, double t, double x, double y, double z,
+                                            V3<double> &E, V3<double> &B) {
+    const PulseDev &P = f.p;
     E = {0, 0, 0};
     B = {0, 0, 0};
-    if (f.kind == QED_FIELD_CONST) {
-        E = {f.e0[0], f.e0[1], f.e0[2]};
-        B = {f.b0[0], f.b0[1], f.b0[2]};
-        return;
-    }
-    if (f.kind == QED_FIELD_GRID2D) {
-        E.x = grid_gather<FT>(f, f.grid[0], 1, 0, x, y);
-        E.y = grid_gather<FT>(f, f.grid[1], 0, 1, x, y);
-        E.z = grid_gather<FT>(f, f.grid[2], 0, 0, x, y);
-        B.x = grid_gather<FT>(f, f.grid[3], 0, 1, x, y);
-        B.y = grid_gather<FT>(f, f.grid[4], 1, 0, x, y);
-        B.z = grid_gather<FT>(f, f.grid[5], 1, 1, x, y);
-        return;
-    }
-    if (f.kind != QED_FIELD_PW && f.kind != QED_FIELD_GAUSS) return;
-    const double L = TWO_PI * f.ncycles;
-    const double phi = t + x - f.phi_start;
-    if (phi < 0.0 || phi > L) return;
-    const FT sp = (FT)sin(f.pol_angle), cp = (FT)cos(f.pol_angle);
-    const FT arg = (FT)(PI * phi / L);   // in [0, pi]
-    FT env = sin(arg);
-    env *= env;
+    const double phi = t + x - P.phi_start;
+    if (phi < 0.0 || phi > P.L) return;
     FT c1, c2;
-    if (f.kind == QED_FIELD_PW) {
-        const FT denv = (FT)(PI / L) * sin((FT)2 * arg);
-        FT ss, cs;
-        const double ps = phi + f.phase0;
-        if constexpr (sizeof(FT) == 8) {
-            sincos(ps, &ss, &cs);
+    if constexpr (sizeof(FT) == 4) {
+        constexpr double INV_2PI = 0.15915494309189535;
+        const float se = __builtin_amdgcn_sinf((float)(phi * P.inv_2L));   // sin(pi phi / L)
+        const float env = se * se;
+        const double rev = frac_rev((phi + P.phase0) * INV_2PI);
+        if constexpr (KIND == QED_FIELD_PW) {
+            // d env / d phi = (pi/L) sin(2 pi phi / L)
+            const float denv = (float)P.pi_over_L * __builtin_amdgcn_sinf((float)frac_rev(phi * P.inv_L));
+            const float ss = __builtin_amdgcn_sinf((float)rev), cs = __builtin_amdgcn_cosf((float)rev);
+            const float a0 = (float)P.a0;
+            c1 = -a0 * (denv * ss + env * cs);
+            c2 = f.circular ? -a0 * (denv * cs - env * ss) : 0.0f;
         } else {
-            sincosf((FT)reduce_2pi(ps), &ss, &cs);
+            const float zr = (float)P.zr;
+            const float xi = (float)(P.x_focus - x);
+            const float rho2 = (float)(y * y + z * z);
+            const float q = xi * (float)P.inv_zr, opq = 1.0f + q * q, iopq = rcp(opq);
+            constexpr float LOG2E = 1.4426950408889634f;
+            const float amp = (float)P.a0 * __builtin_amdgcn_rsqf(opq) *
+                              __builtin_amdgcn_exp2f(-LOG2E * rho2 * (float)P.inv_w0sq * iopq);
+            const float small = atanf(q) - 0.5f * rho2 * xi * rcp(xi * xi + zr * zr);
+            const float ph = (float)rev + small * (float)INV_2PI;
+            const float ss = __builtin_amdgcn_sinf(ph), cs = __builtin_amdgcn_cosf(ph);
+            c1 = amp * env * cs;
+            c2 = f.circular ? amp * env * ss : 0.0f;
         }
-        const FT a0 = (FT)f.a0;
-        c1 = -a0 * (denv * ss + env * cs);
-        c2 = f.circular ? -a0 * (denv * cs - env * ss) : (FT)0;
     } else {
-        const FT w0 = (FT)f.w0, zr = (FT)0.5 * w0 * w0;
-        const FT xi = (FT)(f.x_focus - x);
-        const FT rho2 = (FT)(y * y + z * z);
-        const FT q = xi / zr, opq = (FT)1 + q * q;
-        const FT amp = (FT)f.a0 / sqrt(opq) * exp(-rho2 / (w0 * w0 * opq));
-        const FT small = atan(q) - rho2 * xi / ((FT)2 * (xi * xi + zr * zr));
-        FT ss, cs;
-        if constexpr (sizeof(FT) == 8) {
-            sincos(phi + f.phase0 + small, &ss, &cs);
+        // phases in half-turns, reduced to [-1, 1] before sinpi / cospi, which then need
+        // no large-argument reduction
+        constexpr double INV_PI = 0.3183098861837907;
+        double env = sinpi(phi * P.inv_L);      // sin(pi phi / L), phi / L in [0, 1]
+        env *= env;
+        if constexpr (KIND == QED_FIELD_PW) {
+            const double denv = P.pi_over_L * sinpi(2.0 * frac_rev(phi * P.inv_L));
+            double ss, cs;
+            sincospi(2.0 * frac_rev((phi + P.phase0) * (0.5 * INV_PI)), &ss, &cs);
+            c1 = -P.a0 * (denv * ss + env * cs);
+            c2 = f.circular ? -P.a0 * (denv * cs - env * ss) : 0.0;
         } else {
-            sincosf((FT)reduce_2pi(phi + f.phase0) + small, &ss, &cs);
+            const double zr = P.zr;
+            const double xi = P.x_focus - x;
+            const double rho2 = y * y + z * z;
+            const double q = xi / zr, opq = 1.0 + q * q;
+            const double amp = P.a0 / sqrt(opq) * exp(-rho2 / (P.w0sq * opq));
+            const double small = atan(q) - rho2 * xi / (2.0 * (xi * xi + zr * zr));
+            double ss, cs;
+            sincospi(2.0 * frac_rev((phi + P.phase0) * (0.5 * INV_PI)) + small * INV_PI, &ss, &cs);
+            c1 = amp * env * cs;
+            c2 = f.circular ? amp * env * ss : 0.0;
         }
-        c1 = amp * env * cs;
-        c2 = f.circular ? amp * env * ss : (FT)0;
     }
-    // e1 = (0, cp, sp), e2 = (0, -sp, cp)
-    E.x = 0.0;
+    const FT cp = (FT)P.cp, sp = (FT)P.sp;
     E.y = (double)(c1 * cp - c2 * sp);
     E.z = (double)(c1 * sp + c2 * cp);
-    B.x = 0.0;
     B.y = E.z;
     B.z = -E.y;
 }
 
+// 2D Yee grid (TSC gather of the six staggered components), uniform field, nothing
+template <class FT, int KIND>
+__device__ __forceinline__ void field_kind(const FieldDev &f, double t, double x, double y, double z,
+                                           V3<double> &E, V3<double> &B) {
+    if constexpr (KIND == QED_FIELD_PW || KIND == QED_FIELD_GAUSS) {
+        field_pulse<FT, KIND>(f, t, x, y, z, E, B);
+    } else if constexpr (KIND == QED_FIELD_GRID2D) {
+        E.x = grid_gather<FT>(f.g, f.g.g[0], 1, 0, x, y);
+        E.y = grid_gather<FT>(f.g, f.g.g[1], 0, 1, x, y);
+        E.z = grid_gather<FT>(f.g, f.g.g[2], 0, 0, x, y);
+        B.x = grid_gather<FT>(f.g, f.g.g[3], 0, 1, x, y);
+        B.y = grid_gather<FT>(f.g, f.g.g[4], 1, 0, x, y);
+        B.z = grid_gather<FT>(f.g, f.g.g[5], 1, 1, x, y);
+    } else if constexpr (KIND == QED_FIELD_CONST) {
+        E = {f.c.e0[0], f.c.e0[1], f.c.e0[2]};
+        B = {f.c.b0[0], f.c.b0[1], f.c.b0[2]};
+    } else {
+        E = {0, 0, 0};
+        B = {0, 0, 0};
+    }
+}
+// field kind chosen at run time
+template <class FT>
+__device__ void field_at(const FieldDev &f, double t, double x, double y, double z, V3<double> &E, V3<double> &B) {
+    switch (f.kind) {
+    case QED_FIELD_CONST: field_kind<FT, QED_FIELD_CONST>(f, t, x, y, z, E, B); return;
+    case QED_FIELD_PW: field_kind<FT, QED_FIELD_PW>(f, t, x, y, z, E, B); return;
+    case QED_FIELD_GAUSS: field_kind<FT, QED_FIELD_GAUSS>(f, t, x, y, z, E, B); return;
+    case QED_FIELD_GRID2D: field_kind<FT, QED_FIELD_GRID2D>(f, t, x, y, z, E, B); return;
+    default: field_kind<FT, QED_FIELD_NONE>(f, t, x, y, z, E, B); return;
+    }
+}
+
 // ------------------------------------------------------------------------- push + spin
-// Boris rotation (eqs. boris1-boris6): p in/out p^{n-1/2} -> p^{n+1/2}; returns p-, p+.
-__device__ __forceinline__ void boris(double q, double dt, const V3<double> &E, const V3<double> &B, V3<double> &p,
-                                      V3<double> &pm, V3<double> &pp) {
+// Boris rotation (eqs. boris1-boris6): p in/out p^{n-1/2} -> p^{n+1/2}; returns p-, p+
+// and 1/gamma^n = 1/sqrt(1 + |p-|^2).
+__device__ __forceinline__ double boris(double q, double dt, const V3<double> &E, const V3<double> &B, V3<double> &p,
+                                        V3<double> &pm, V3<double> &pp) {
     const double h = 0.5 * q * dt;
     pm = p + h * E;
-    const double g = sqrt(1.0 + dot(pm, pm));
-    const V3<double> tau = (h / g) * B;
+    const double ig = rsqrt(1.0 + dot(pm, pm));
+    const V3<double> tau = (h * ig) * B;
     const V3<double> sig = (2.0 / (1.0 + dot(tau, tau))) * tau;
     const V3<double> pr = pm + cross(pm, tau);
     pp = pm + cross(pr, sig);
     p = pp + h * E;
+    return ig;
 }
 // T-BMT (eq. bmteqn) by the Boris rotation of eqs. bmt-boris1-4: dS/dt = q S x Omega,
-// gamma^n = sqrt(1+|p-|^2), beta^n = (p- + p+)/(2 gamma^n), g/2 - 1 = a_e.
+// gamma^n = sqrt(1+|p-|^2) (passed as ig = 1/gamma^n), beta^n = (p- + p+)/(2 gamma^n),
+// g/2 - 1 = a_e.
 template <class T>
 __device__ __forceinline__ void bmt(double q, double a_e, double dt, const V3<double> &E, const V3<double> &B,
-                                    const V3<double> &pm, const V3<double> &pp, V3<T> &S) {
-    const double gd = sqrt(1.0 + dot(pm, pm));
-    const V3<T> beta = cvt<T>((0.5 / gd) * (pm + pp));
+                                    const V3<double> &pm, const V3<double> &pp, double ig, V3<T> &S) {
+    const double gd = (1.0 + dot(pm, pm)) * ig;
+    const V3<T> beta = cvt<T>((0.5 * ig) * (pm + pp));
     const V3<T> Et = cvt<T>(E), Bt = cvt<T>(B);
-    const T g = (T)gd, ae = (T)a_e;
-    const T c1 = -ae * g / (g + (T)1) * dot(beta, Bt), c2 = ae + (T)1 / g, c3 = ae + (T)1 / (g + (T)1);
+    const T g = (T)gd, ae = (T)a_e, igp = rcp(g + (T)1);
+    const T c1 = -ae * g * igp * dot(beta, Bt), c2 = ae + (T)ig, c3 = ae + igp;
     const V3<T> om = c1 * beta + c2 * Bt - c3 * cross(beta, Et);
     const V3<T> tv = (T)(0.5 * q * dt) * om;
-    const V3<T> o = ((T)2 / ((T)1 + dot(tv, tv))) * tv;
+    const V3<T> o = ((T)2 * rcp((T)1 + dot(tv, tv))) * tv;
     const V3<T> Sp = S + cross(S, tv);
     S = S + cross(Sp, o);
 }
 // chi_e = xi_L sqrt((gamma E + p x B)^2 - (p.E)^2)
-__device__ __forceinline__ double chi_e(double xi_L, const V3<double> &p, const V3<double> &E, const V3<double> &B) {
-    const double g = sqrt(1.0 + dot(p, p));
+// (the square root in the precision T of the rates it feeds)
+template <class T>
+__device__ __forceinline__ double chi_e(double xi_L, double g, const V3<double> &p, const V3<double> &E,
+                                        const V3<double> &B) {
     const V3<double> v = g * E + cross(p, B);
     const double pe = dot(p, E);
     const double s = dot(v, v) - pe * pe;
+    if constexpr (sizeof(T) == 4) return xi_L * (double)__builtin_amdgcn_sqrtf(s > 0.0 ? (float)s : 0.0f);
     return xi_L * sqrt(s > 0.0 ? s : 0.0);
 }
 
@@ -208,15 +264,15 @@ __device__ __forceinline__ int lag4(T pos, int n, T w[4]) {
     int i = (int)floor(pos);
     i = i < 1 ? 1 : (i > n - 3 ? n - 3 : i);
     const T f = pos - (T)i, fm1 = f - (T)1, fm2 = f - (T)2, fp1 = f + (T)1;
-    w[0] = -f * fm1 * fm2 / (T)6;
-    w[1] = fp1 * fm1 * fm2 / (T)2;
-    w[2] = -fp1 * f * fm2 / (T)2;
-    w[3] = fp1 * f * fm1 / (T)6;
+    w[0] = -f * fm1 * fm2 * (T)(1.0 / 6.0);
+    w[1] = fp1 * fm1 * fm2 * (T)0.5;
+    w[2] = -fp1 * f * fm2 * (T)0.5;
+    w[3] = fp1 * f * fm1 * (T)(1.0 / 6.0);
     return i;
 }
 template <class T>
 __device__ __forceinline__ T gridpos(T l, double lo, double hi, int n) {
-    return (l - (T)lo) / (T)((hi - lo) / (n - 1));
+    return (l - (T)lo) * (T)((n - 1) / (hi - lo));
 }
 
 // Bessel trio at x, all three multiplied by x^(2/3) e^x (only ratios are used)
@@ -245,7 +301,7 @@ __device__ __forceinline__ void ncs_rate(const Tabs<T> &tb, double chi, T &Ia, T
         Ib = 0;
         return;
     }
-    const T c = (T)chi, l = log(c);
+    const T c = (T)chi, l = lnx(c);
     const T *r = tb.ncs_rate();
     if (l < (T)R_LO) {
         Ia = r[0] * c;
@@ -266,21 +322,43 @@ __device__ __forceinline__ void ncs_rate(const Tabs<T> &tb, double chi, T &Ia, T
 }
 
 // Inverse of the piecewise-linear CDF D_j = a_j - m b_j, rows r0 and r0+1 mixed with
-// weight f, at `target`; returns the fractional column.
+// weight f, at `target`; returns the fractional column.  The bracket [lo, lo + 1] is the
+// last column with D <= target and its successor (D is non-decreasing), found by an
+// 8-way search: each round probes 7 columns with independent loads, so 1024 columns take
+// 4 dependent rounds of memory traffic instead of 10.
+template <class T>
+__device__ __forceinline__ T cdf_at(const T *__restrict__ R0, const T *__restrict__ R1, int j, T g, T f, T m) {
+    const T a = g * R0[2 * j] + f * R1[2 * j];
+    const T b = g * R0[2 * j + 1] + f * R1[2 * j + 1];
+    return a - m * b;
+}
 template <class T>
 __device__ __forceinline__ T cdf_invert(const T *__restrict__ R0, const T *__restrict__ R1, int ncol, T f, T m,
                                         T target) {
+    constexpr int K = 8;
     int lo = 0, hi = ncol - 1;
     const T g = (T)1 - f;
     while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        const T a = g * R0[2 * mid] + f * R1[2 * mid];
-        const T b = g * R0[2 * mid + 1] + f * R1[2 * mid + 1];
-        if (a - m * b <= target) lo = mid;
-        else hi = mid;
+        const int span = hi - lo;
+        int nlo = lo, nhi = hi;
+        T d[K - 1];
+        int pk[K - 1];
+#pragma unroll
+        for (int k = 1; k < K; ++k) {
+            pk[k - 1] = lo + (span * k) / K;
+            d[k - 1] = pk[k - 1] > lo ? cdf_at<T>(R0, R1, pk[k - 1], g, f, m) : target;
+        }
+#pragma unroll
+        for (int k = 0; k < K - 1; ++k) {
+            if (pk[k] <= lo) continue;
+            if (d[k] <= target) nlo = pk[k] > nlo ? pk[k] : nlo;
+            else nhi = pk[k] < nhi ? pk[k] : nhi;
+        }
+        lo = nlo;
+        hi = nhi > nlo ? nhi : nlo + 1;
     }
-    const T dlo = (g * R0[2 * lo] + f * R1[2 * lo]) - m * (g * R0[2 * lo + 1] + f * R1[2 * lo + 1]);
-    const T dhi = (g * R0[2 * hi] + f * R1[2 * hi]) - m * (g * R0[2 * hi + 1] + f * R1[2 * hi + 1]);
+    const T dlo = cdf_at<T>(R0, R1, lo, g, f, m);
+    const T dhi = cdf_at<T>(R0, R1, hi, g, f, m);
     T tau = dhi > dlo ? (target - dlo) / (dhi - dlo) : (T)0;
     tau = tau < (T)0 ? (T)0 : (tau > (T)1 ? (T)1 : tau);
     return (T)lo + tau;
@@ -396,26 +474,27 @@ struct NcsFrame {
     V3<T> n, a, b;
     T s, Ia, Ib;
 };
+// ig = 1/gamma = 1/sqrt(1 + |p|^2), computed by the caller.
 template <class T>
 __device__ __forceinline__ bool ncs_frame(const Consts &c, const Tabs<T> &tb, double q, const V3<double> &p,
-                                          const V3<T> &S, const V3<double> &E, const V3<double> &B, uint32_t &st,
-                                          NcsFrame<T> &f) {
-    const double pp2 = dot(p, p), g = sqrt(1.0 + pp2), pmag = sqrt(pp2);
-    f.chi = chi_e(c.xi_L, p, E, B);
-    if (!(f.chi > 0.0) || !(pmag > 0.0)) return false;
-    const V3<double> nd = (1.0 / pmag) * p;
-    const V3<double> beta = (1.0 / g) * p;
+                                          double ig, const V3<T> &S, const V3<double> &E, const V3<double> &B,
+                                          uint32_t &st, NcsFrame<T> &f) {
+    const double pp2 = dot(p, p), g = (1.0 + pp2) * ig;
+    f.chi = chi_e<T>(c.xi_L, g, p, E, B);
+    if (!(f.chi > 0.0) || !(pp2 > 0.0)) return false;
+    const V3<double> nd = rsqrt(pp2) * p;
+    const V3<double> beta = ig * p;
     const double be = dot(beta, E);
     const V3<double> acc = q * (E + cross(beta, B) - be * beta);
     const V3<double> ad = acc - dot(nd, acc) * nd;
-    const double an = sqrt(dot(ad, ad));
-    if (!(an > 0.0)) return false;
+    const double a2 = dot(ad, ad);
+    if (!(a2 > 0.0)) return false;
     f.n = cvt<T>(nd);
-    f.a = cvt<T>((1.0 / an) * ad);
+    f.a = cvt<T>(rsqrt(a2) * ad);
     f.b = cross(f.n, f.a);
     f.s = dot(S, f.b);
     ncs_rate<T>(tb, f.chi, f.Ia, f.Ib, st);
-    f.C = c.alpha / (SQRT3 * PI * c.xi_L * g);
+    f.C = c.c_ncs * ig;
     f.W = f.C * (double)f.Ia;
     f.Wt = f.C * ((double)f.Ia - (double)f.s * (double)f.Ib);
     f.P = f.Wt * c.dt;
@@ -425,10 +504,11 @@ __device__ __forceinline__ bool ncs_frame(const Consts &c, const Tabs<T> &tb, do
 // no emission: S -> [S(1 - W dt) - f dt]/(1 - W_tot dt), renormalised (f = -C Ib b)
 template <class T>
 __device__ __forceinline__ void ncs_no_event(const Consts &c, const NcsFrame<T> &f, V3<T> &S) {
-    const T wdt = (T)(f.W * c.dt), den = (T)(1.0 - f.Wt * c.dt), fb = (T)(f.C * (double)f.Ib * c.dt);
-    const V3<T> Sb = ((T)1 / den) * (((T)1 - wdt) * S + fb * f.b);
-    const T nrm = sqrt(dot(Sb, Sb));
-    S = ((T)1 / nrm) * Sb;
+    // called only when no emission happened, so 1 - W~ dt > 0 and the common factor
+    // 1/(1 - W~ dt) drops out of the normalised spin
+    const T wdt = (T)(f.W * c.dt), fb = (T)(f.C * (double)f.Ib * c.dt);
+    const V3<T> Sb = ((T)1 - wdt) * S + fb * f.b;
+    S = rsq(dot(Sb, Sb)) * Sb;
 }
 // emission (given the draws r): photon fraction y by the inverse of the spin-dependent
 // spectrum (r1), k = y p, p -> (1-y) p; final spin +-g/|g| with P(+) = (1 + |g|/(w+f.S))/2

@@ -45,8 +45,39 @@ struct Tabs {
 // ------------------------------------------------------------------ constants per context
 struct Consts {
     double xi_L, alpha, a_e, dt, p_max;
+    double c_ncs;      // alpha / (sqrt3 pi xi_L): NCS rate prefactor times gamma
     uint64_t seed;
     uint32_t procs;
+};
+
+// A field as the kernels use it: the quantities that are uniform over a segment
+// (polarisation axes, pi/L, Rayleigh length, inverse grid spacings) are computed once on
+// the host, so the per-particle code has no uniform transcendental or division.  Kernels of
+// the hot path are specialised on the field kind, so only one kind's members are read.
+struct PulseDev {                // QED_FIELD_PW, QED_FIELD_GAUSS
+    double a0, phase0, phi_start, L, pi_over_L;
+    double inv_L, inv_2L;        // 1/L, 1/(2L): the envelope phases in revolutions
+    double cp, sp;               // e1 = (0, cp, sp), e2 = (0, -sp, cp)
+    double x_focus, zr, inv_zr, w0sq, inv_w0sq;
+};
+struct GridDev {                 // QED_FIELD_GRID2D
+    const float *g[6];
+    int32_t nx, ny;
+    double inv_dx, inv_dy, gx0, gy0;
+};
+struct ConstDev {                // QED_FIELD_CONST
+    double e0[3], b0[3];
+};
+struct FieldDev {
+    int32_t kind, circular;
+    PulseDev p;
+    GridDev g;
+    ConstDev c;
+};
+constexpr int FK_MULTI = -1;     // kernel template argument: field kind read per segment
+struct DevSegment {
+    int64_t begin, end;
+    FieldDev f;
 };
 
 // staging record of one event (decide kernel -> event kernel): particle index and the
@@ -56,13 +87,25 @@ struct EventRec {
     double f[6];
 };
 
-constexpr int MAX_SEG = 8;             // segments passed by value in kernel arguments
+// Field selection for a launch.  One segment: its field travels in the kernel arguments
+// and is read at constant offsets.  Several segments: they live in a device buffer owned
+// by the context and each particle finds its own by binary search on `begin` (indexing
+// an argument array at run time would copy it to private memory in every thread).
+constexpr int MAX_SEG = 1 << 16;
 struct SegArgs {
     int nseg;
-    qed_segment seg[MAX_SEG];
+    int64_t begin0, end0;
+    FieldDev f0;
+    const DevSegment *segs;    // device copy when nseg > 1
 };
+FieldDev field_dev(const qed_field &f);   // host: derived constants of a field
 
 constexpr int BLOCK = 256;             // threads per block = particles per tile
+constexpr int EV_GROUP = 8;            // lepton step: tiles per group (one wavefront of the event kernel)
+
+// bytes of one staging slot: an event record of the photon kernels, or the tile-local
+// index (int) of a queued lepton event
+constexpr size_t STAGING_SLOT = sizeof(EventRec);
 
 }  // namespace qed
 
@@ -74,10 +117,16 @@ struct qed_ctx {
     uint32_t *status;                  // sticky status word
     unsigned long long *next_id;       // id counter
     int *tile_counts;                  // events per 256-particle tile   [max_tiles]
+    int *group_tot;                    // events per group of EV_GROUP tiles [max_tiles / EV_GROUP + 1];
+                                       // zero between launches (the scan clears what it reads)
     int64_t *tile_off;                 // exclusive prefix of tile_counts [max_tiles + 1]
     int64_t *launch;                   // bases of the last append launch [4]
-    qed::EventRec *staging;            // one slot per particle of the largest list seen
-    int64_t staging_cap;
+    void *staging;                     // one STAGING_SLOT per particle of the largest list seen,
+    int64_t staging_cap;               // rounded up to whole tiles
+    qed::DevSegment *dsegs;            // device copy of the last multi-segment list
+    qed::DevSegment *hsegs;            // pinned host staging of that copy
+    int nseg_cap, nseg_dev;            // capacity and size of the uploaded list
+    hipEvent_t seg_copied;             // completion of the last upload
     int64_t max_tiles;
     char err[256];
 };

@@ -17,6 +17,12 @@
 
 namespace qed {
 
+// element of an array at a 32-bit byte offset
+template <class T>
+__device__ __forceinline__ T &at(T *base, uint32_t off) {
+    return *(T *)((char *)base + off);
+}
+
 // device list counts are trusted only up to the list capacity
 __device__ __forceinline__ int64_t clamp_count(const int64_t *count, int64_t capacity) {
     const int64_t n = *count;
@@ -61,29 +67,35 @@ __device__ __forceinline__ int64_t tile_of(const int64_t *off, int64_t ntiles, i
 }
 
 // ------------------------------------------------------------------------- segments
-__device__ __forceinline__ const qed_field *seg_field(const SegArgs &sa, int64_t i) {
-    for (int s = 0; s < sa.nseg; ++s)
-        if (i >= sa.seg[s].begin && i < sa.seg[s].end) return &sa.seg[s].field;
-    return nullptr;
-}
-template <class FT>
+// FK: the kind of the single segment (fields read at constant offsets of the kernel
+// arguments) or FK_MULTI (segment found per particle, kind read from it).
+template <class FT, int FK>
 __device__ __forceinline__ void fields_for(const SegArgs &sa, int64_t i, double t, const V3<double> &r,
                                            V3<double> &E, V3<double> &B) {
-    const qed_field *f = seg_field(sa, i);
-    if (f) {
-        field_at<FT>(*f, t, r.x, r.y, r.z, E, B);
+    E = {0, 0, 0};
+    B = {0, 0, 0};
+    if constexpr (FK != FK_MULTI) {
+        if (i >= sa.begin0 && i < sa.end0) field_kind<FT, FK>(sa.f0, t, r.x, r.y, r.z, E, B);
     } else {
-        E = {0, 0, 0};
-        B = {0, 0, 0};
+        int lo = 0, hi = sa.nseg - 1;   // last segment with begin <= i
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (sa.segs[mid].begin <= i) lo = mid;
+            else hi = mid - 1;
+        }
+        const DevSegment &sg = sa.segs[lo];
+        if (i >= sg.begin && i < sg.end) field_at<FT>(sg.f, t, r.x, r.y, r.z, E, B);
     }
 }
 
 // ------------------------------------------------------------------------- scan kernel
 struct ScanArgs {
-    const int *tile_counts;
-    int64_t *tile_off;        // [ntiles + 1]
-    const int64_t *in_count;  // list whose tiles were counted
+    int *counts;              // events per unit (a tile, or a group of tiles)
+    int clear;                // set the counts read back to zero
+    int64_t *off;             // [nunits + 1]: exclusive prefix
+    const int64_t *in_count;  // list whose units were counted
     int64_t in_capacity;
+    int unit;                 // particles per unit
     int64_t *out_count[2];    // output lists (may be null)
     int64_t out_cap[2];
     unsigned long long *next_id;
@@ -91,15 +103,24 @@ struct ScanArgs {
     int64_t *launch;          // [0] out0 base, [1] out1 base, [2] id base, [3] events
     uint32_t *status;
 };
-constexpr int SCAN_THREADS = 1024;
+constexpr int SCAN_THREADS = 1024, SCAN_UNROLL = 8;
+// One block: exclusive prefix sums of the unit counts and the launch bases.  Each thread
+// owns a contiguous run of units.
 __global__ __launch_bounds__(SCAN_THREADS) void k_scan(ScanArgs a) {
     __shared__ int64_t s_part[SCAN_THREADS];
     const int64_t n = clamp_count(a.in_count, a.in_capacity);
-    const int64_t ntiles = (n + BLOCK - 1) / BLOCK;
-    const int64_t per = (ntiles + SCAN_THREADS - 1) / SCAN_THREADS;
-    const int64_t lo = threadIdx.x * per, hi = lo + per < ntiles ? lo + per : ntiles;
+    const int64_t nunits = (n + a.unit - 1) / a.unit;
+    const int64_t per = (nunits + SCAN_THREADS - 1) / SCAN_THREADS;
+    const int64_t lo = threadIdx.x * per, hi = lo + per < nunits ? lo + per : nunits;
+    // each thread sums its run, SCAN_UNROLL loads in flight
     int64_t sum = 0;
-    for (int64_t t = lo; t < hi; ++t) sum += a.tile_counts[t];
+    for (int64_t t0 = lo; t0 < hi; t0 += SCAN_UNROLL) {
+        int v[SCAN_UNROLL];
+#pragma unroll
+        for (int k = 0; k < SCAN_UNROLL; ++k) v[k] = t0 + k < hi ? a.counts[t0 + k] : 0;
+#pragma unroll
+        for (int k = 0; k < SCAN_UNROLL; ++k) sum += v[k];
+    }
     s_part[threadIdx.x] = sum;
     __syncthreads();
     // Hillis-Steele inclusive scan of the 1024 partial sums
@@ -110,13 +131,22 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan(ScanArgs a) {
         __syncthreads();
     }
     int64_t run = s_part[threadIdx.x] - sum;
-    for (int64_t t = lo; t < hi; ++t) {
-        a.tile_off[t] = run;
-        run += a.tile_counts[t];
+    for (int64_t t0 = lo; t0 < hi; t0 += SCAN_UNROLL) {
+        int v[SCAN_UNROLL];
+#pragma unroll
+        for (int k = 0; k < SCAN_UNROLL; ++k) v[k] = t0 + k < hi ? a.counts[t0 + k] : 0;
+#pragma unroll
+        for (int k = 0; k < SCAN_UNROLL; ++k) {
+            if (t0 + k < hi) {
+                a.off[t0 + k] = run;
+                if (a.clear) a.counts[t0 + k] = 0;
+            }
+            run += v[k];
+        }
     }
     if (threadIdx.x == SCAN_THREADS - 1) {
         const int64_t tot = s_part[SCAN_THREADS - 1];
-        a.tile_off[ntiles] = tot;
+        a.off[nunits] = tot;
         uint32_t st = 0;
         for (int k = 0; k < 2; ++k) {
             const int64_t base = a.out_count[k] ? *a.out_count[k] : 0;
@@ -145,25 +175,29 @@ struct LeptonArgs {
     double *E6;
     int64_t step;
     uint32_t *status;
-    EventRec *stg;
+    void *stg;
     int *tile_counts;
+    int *group_tot;
     const int64_t *tile_off;
     const int64_t *launch;
 };
 
+// push + T-BMT + drift; returns 1/gamma^{n+1/2}
 template <class T>
-__device__ __forceinline__ void push_one(const LeptonArgs &a, double q, double dt, const V3<double> &E,
-                                         const V3<double> &B, V3<double> &r, V3<double> &p, V3<T> &S, uint32_t &st) {
+__device__ __forceinline__ double push_one(const LeptonArgs &a, double q, double dt, const V3<double> &E,
+                                           const V3<double> &B, V3<double> &r, V3<double> &p, V3<T> &S,
+                                           uint32_t &st) {
     V3<double> pm, pp;
-    boris(q, dt, E, B, p, pm, pp);
-    bmt<T>(q, a.c.a_e, dt, E, B, pm, pp, S);
-    const double ig = dt / sqrt(1.0 + dot(p, p));
-    r = r + ig * p;
+    const double ign = boris(q, dt, E, B, p, pm, pp);
+    bmt<T>(q, a.c.a_e, dt, E, B, pm, pp, ign, S);
+    const double ig = rsqrt(1.0 + dot(p, p));
+    r = r + (dt * ig) * p;
     if (!isfinite(p.x + p.y + p.z + r.x + r.y + r.z) || !isfinite((double)(S.x + S.y + S.z))) st |= QED_ST_NAN;
+    return ig;
 }
 
 // gather and/or push, no NCS: grid-stride loop
-template <class T, bool WRITE_E6, bool PUSH, bool E6_IN>
+template <class T, bool WRITE_E6, bool PUSH, bool E6_IN, bool MULTI>
 __global__ __launch_bounds__(BLOCK) void k_leptons_simple(LeptonArgs a) {
     const int64_t n = clamp_count(a.L.count, a.L.capacity);
     const double dt = a.c.dt, t = (double)a.step * dt, q = (double)a.L.charge;
@@ -176,7 +210,9 @@ __global__ __launch_bounds__(BLOCK) void k_leptons_simple(LeptonArgs a) {
             E = {e[0], e[1], e[2]};
             B = {e[3], e[4], e[5]};
         } else {
-            fields_for<T>(a.sa, i, t, r, E, B);
+            if constexpr (MULTI) fields_for<T, FK_MULTI>(a.sa, i, t, r, E, B);
+            else if (i >= a.sa.begin0 && i < a.sa.end0) field_at<T>(a.sa.f0, t, r.x, r.y, r.z, E, B);
+            else E = B = {0, 0, 0};
         }
         if constexpr (WRITE_E6) {
             double *e = a.E6 + 6 * i;
@@ -195,83 +231,145 @@ __global__ __launch_bounds__(BLOCK) void k_leptons_simple(LeptonArgs a) {
     if (st) atomicOr(a.status, st);
 }
 
-// decide: (gather + push + T-BMT if PUSH, else fields from E6) + NCS test; one tile per block
-template <class T, bool PUSH>
+// State of lepton i after the push (PUSH: gather at x^n, Boris, T-BMT, drift) or with the
+// fields of x^n taken from E6 (emission only).  The decide and event kernels both call it on
+// the same inputs, so an event particle is rebuilt exactly as it was when its event was
+// decided.
+// Returns 1/gamma of the resulting momentum.  Lepton arrays are addressed with 32-bit byte
+// offsets from the array base (lists hold at most 2^28 particles), which lets every load
+// and store use the scalar-base + vector-offset form.
+template <class T, bool PUSH, int FK>
+__device__ __forceinline__ double lepton_state(const LeptonArgs &a, int64_t i, double t, double q, V3<double> &r,
+                                               V3<double> &p, V3<T> &S, V3<double> &E, V3<double> &B,
+                                               uint32_t &st) {
+    const uint32_t o = (uint32_t)i * 8u, os = (uint32_t)i * (uint32_t)sizeof(T);
+    r = {at(a.L.x, o), at(a.L.y, o), at(a.L.z, o)};
+    p = {at(a.L.px, o), at(a.L.py, o), at(a.L.pz, o)};
+    S = {at((T *)a.L.sx, os), at((T *)a.L.sy, os), at((T *)a.L.sz, os)};
+    if constexpr (PUSH) {
+        fields_for<T, FK>(a.sa, i, t, r, E, B);
+        return push_one<T>(a, q, a.c.dt, E, B, r, p, S, st);
+    } else {
+        const double *e = a.E6 + 6 * i;
+        E = {e[0], e[1], e[2]};
+        B = {e[3], e[4], e[5]};
+        return rsqrt(1.0 + dot(p, p));
+    }
+}
+template <class T>
+__device__ __forceinline__ void store_xp(const LeptonArgs &a, uint32_t o, const V3<double> &r, const V3<double> &p) {
+    at(a.L.x, o) = r.x; at(a.L.y, o) = r.y; at(a.L.z, o) = r.z;
+    at(a.L.px, o) = p.x; at(a.L.py, o) = p.y; at(a.L.pz, o) = p.z;
+}
+template <class T>
+__device__ __forceinline__ void store_s(const LeptonArgs &a, uint32_t os, const V3<T> &S) {
+    at((T *)a.L.sx, os) = S.x; at((T *)a.L.sy, os) = S.y; at((T *)a.L.sz, os) = S.z;
+}
+
+// Decide (lepton step with NCS), one thread per particle, one BLOCK-particle tile per
+// block: state after the push, local frame, rates, event test.  Particles without an
+// event are finished and written back here.  Event particles write nothing: their
+// tile-local indices are queued in index order (wave ballot + popcount, waves combined in
+// LDS) in the tile's staging slots; the tile's event count goes to tile_counts and is
+// added to its group's total (integer atomics: the sum does not depend on their order).
+template <class T, bool PUSH, int FK>
 __global__ __launch_bounds__(BLOCK) void k_leptons_decide(LeptonArgs a) {
     __shared__ int s_wave[BLOCK / 64];
     const int64_t n = clamp_count(a.L.count, a.L.capacity);
-    const int64_t tile = blockIdx.x;
-    if (tile * BLOCK >= n) return;
+    const int64_t tile = blockIdx.x, base = tile * BLOCK;
+    if (base >= n) return;
     const Tabs<T> tb = {(const T *)a.tab};
-    const double dt = a.c.dt, t = (double)a.step * dt, q = (double)a.L.charge;
-    T *sx = (T *)a.L.sx, *sy = (T *)a.L.sy, *sz = (T *)a.L.sz;
-    const int64_t i = tile * BLOCK + threadIdx.x;
+    const double t = (double)a.step * a.c.dt, q = (double)a.L.charge;
+    const int64_t i = base + threadIdx.x;
     uint32_t st = 0;
     bool ev = false;
-    V3<double> E = {0, 0, 0}, B = {0, 0, 0};
     if (i < n) {
-        V3<double> r = {a.L.x[i], a.L.y[i], a.L.z[i]}, p = {a.L.px[i], a.L.py[i], a.L.pz[i]};
-        V3<T> S = {sx[i], sy[i], sz[i]};
-        if constexpr (PUSH) {
-            fields_for<T>(a.sa, i, t, r, E, B);
-            push_one<T>(a, q, dt, E, B, r, p, S, st);
-            a.L.x[i] = r.x; a.L.y[i] = r.y; a.L.z[i] = r.z;
-            a.L.px[i] = p.x; a.L.py[i] = p.y; a.L.pz[i] = p.z;
-        } else {
-            const double *e = a.E6 + 6 * i;
-            E = {e[0], e[1], e[2]};
-            B = {e[3], e[4], e[5]};
-        }
+        V3<double> r, p, E, B;
+        V3<T> S;
+        const double ig = lepton_state<T, PUSH, FK>(a, i, t, q, r, p, S, E, B, st);
         NcsFrame<T> f;
-        if (ncs_frame<T>(a.c, tb, q, p, S, E, B, st, f)) {
+        if (ncs_frame<T>(a.c, tb, q, p, ig, S, E, B, st, f)) {
             double rr[4];
-            uniform4(a.L.id[i], a.step, STREAM_NCS, a.c.seed, rr);
+            uniform4(at(a.L.id, (uint32_t)i * 8u), a.step, STREAM_NCS, a.c.seed, rr);
             ev = rr[1] < f.P;
             if (!ev) ncs_no_event<T>(a.c, f, S);
         }
-        sx[i] = S.x; sy[i] = S.y; sz[i] = S.z;
+        if (!ev) {
+            if constexpr (PUSH) store_xp<T>(a, (uint32_t)i * 8u, r, p);
+            store_s<T>(a, (uint32_t)i * (uint32_t)sizeof(T), S);
+        }
     }
     int total;
     const int rank = block_rank(ev, total, s_wave);
-    if (ev) stage(a.stg, tile * BLOCK + rank, i, E, B);
-    if (threadIdx.x == 0) a.tile_counts[tile] = total;
+    if (ev) ((int *)a.stg)[base + rank] = threadIdx.x;
+    if (threadIdx.x == 0) {
+        a.tile_counts[tile] = total;
+        if (total) atomicAdd(a.group_tot + tile / EV_GROUP, total);
+    }
     if (st) atomicOr(a.status, st);
 }
 
-// events: one thread per emission, photons written in parent order
-template <class T>
+// Events of the last decide, after the scan.  One wavefront per group of EV_GROUP tiles:
+// the tile counts of the group are scanned across lanes, lane
+// k takes the group's events k, k + 64, ..., finds its tile and queue slot, rebuilds the
+// particle from its unchanged inputs exactly as the decide kernel saw it, emits, and
+// writes the photon straight to its ordered place: global rank = group offset + rank in
+// the group, id = id base + global rank.
+template <class T, bool PUSH, int FK>
 __global__ __launch_bounds__(BLOCK) void k_leptons_events(LeptonArgs a) {
+    static_assert(EV_GROUP <= 64 && (EV_GROUP & (EV_GROUP - 1)) == 0, "one group = at most one wave of tiles");
     const int64_t n = clamp_count(a.L.count, a.L.capacity);
     const int64_t ntiles = (n + BLOCK - 1) / BLOCK;
-    const int64_t nev = a.launch[3], base = a.launch[0], id0 = a.launch[2];
+    const int64_t ngroups = (ntiles + EV_GROUP - 1) / EV_GROUP;
+    const int64_t obase = a.launch[0], id0 = a.launch[2];
     const Tabs<T> tb = {(const T *)a.tab};
-    const double q = (double)a.L.charge;
-    T *sx = (T *)a.L.sx, *sy = (T *)a.L.sy, *sz = (T *)a.L.sz;
+    const double t = (double)a.step * a.c.dt, q = (double)a.L.charge;
+    const int lane = threadIdx.x & 63;
     uint32_t st = 0;
-    for (int64_t e = (int64_t)blockIdx.x * BLOCK + threadIdx.x; e < nev; e += (int64_t)gridDim.x * BLOCK) {
-        const int64_t tile = tile_of(a.tile_off, ntiles, e);
-        const EventRec &rec = a.stg[tile * BLOCK + (e - a.tile_off[tile])];
-        const int64_t i = rec.idx;
-        const V3<double> E = {rec.f[0], rec.f[1], rec.f[2]}, B = {rec.f[3], rec.f[4], rec.f[5]};
-        V3<double> p = {a.L.px[i], a.L.py[i], a.L.pz[i]};
-        V3<T> S = {sx[i], sy[i], sz[i]};
-        NcsFrame<T> f;
-        ncs_frame<T>(a.c, tb, q, p, S, E, B, st, f);
-        double rr[4];
-        uniform4(a.L.id[i], a.step, STREAM_NCS, a.c.seed, rr);
-        NcsPhoton<T> ph;
-        ncs_event<T>(a.c, tb, f, rr, p, S, ph);
-        a.L.px[i] = p.x; a.L.py[i] = p.y; a.L.pz[i] = p.z;
-        sx[i] = S.x; sy[i] = S.y; sz[i] = S.z;
-        if (a.has_out) {
-            const int64_t pos = base + e;
-            if (pos < a.out.capacity) {
-                a.out.x[pos] = a.L.x[i]; a.out.y[pos] = a.L.y[i]; a.out.z[pos] = a.L.z[i];
+    const int64_t g = (int64_t)blockIdx.x * (BLOCK / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (g < ngroups) {
+        const int64_t c0 = g * EV_GROUP;
+        const int cnt = (lane < EV_GROUP && c0 + lane < ntiles) ? a.tile_counts[c0 + lane] : 0;
+        int incl = cnt;   // inclusive scan of the tile counts over the lanes
+#pragma unroll
+        for (int d = 1; d < EV_GROUP; d <<= 1) {
+            const int v = __shfl_up(incl, d);
+            incl += lane >= d ? v : 0;
+        }
+        int pre[EV_GROUP];   // wave-uniform inclusive prefix per tile
+#pragma unroll
+        for (int k = 0; k < EV_GROUP; ++k) pre[k] = __builtin_amdgcn_readlane(incl, k);
+        const int gtot = pre[EV_GROUP - 1];
+        const int64_t goff = a.tile_off[g];
+        for (int e = lane; e < gtot; e += 64) {
+            int j = 0, below = 0;   // tile of event e and the events before that tile
+#pragma unroll
+            for (int k = 0; k < EV_GROUP - 1; ++k) {
+                const bool past = pre[k] <= e;
+                j += past ? 1 : 0;
+                below = past ? pre[k] : below;
+            }
+            const int64_t tile = c0 + j;
+            const int64_t i = tile * BLOCK + ((const int *)a.stg)[tile * BLOCK + (e - below)];
+            V3<double> r, p, E, B;
+            V3<T> S;
+            const double ig = lepton_state<T, PUSH, FK>(a, i, t, q, r, p, S, E, B, st);
+            NcsFrame<T> f;
+            ncs_frame<T>(a.c, tb, q, p, ig, S, E, B, st, f);
+            double rr[4];
+            uniform4(a.L.id[i], a.step, STREAM_NCS, a.c.seed, rr);
+            NcsPhoton<T> ph;
+            ncs_event<T>(a.c, tb, f, rr, p, S, ph);
+            store_xp<T>(a, (uint32_t)i * 8u, r, p);
+            store_s<T>(a, (uint32_t)i * (uint32_t)sizeof(T), S);
+            const int64_t ge = goff + e, pos = obase + ge;
+            if (a.has_out && pos < a.out.capacity) {
+                a.out.x[pos] = r.x; a.out.y[pos] = r.y; a.out.z[pos] = r.z;
                 a.out.kx[pos] = ph.k.x; a.out.ky[pos] = ph.k.y; a.out.kz[pos] = ph.k.z;
                 a.out.w[pos] = a.L.w[i];
                 ((T *)a.out.xi1)[pos] = ph.xi.x; ((T *)a.out.xi2)[pos] = ph.xi.y; ((T *)a.out.xi3)[pos] = ph.xi.z;
                 ((T *)a.out.e1x)[pos] = ph.e1.x; ((T *)a.out.e1y)[pos] = ph.e1.y; ((T *)a.out.e1z)[pos] = ph.e1.z;
-                a.out.id[pos] = (unsigned long long)(id0 + e);
+                a.out.id[pos] = (unsigned long long)(id0 + ge);
                 a.out.alive[pos] = 1;
             }
         }
@@ -283,7 +381,7 @@ __global__ __launch_bounds__(BLOCK) void k_leptons_events(LeptonArgs a) {
 struct PhotonArgs {
     Consts c;
     const void *tab;
-    qed_field field;
+    FieldDev field;
     qed_photons G;
     qed_leptons em, ep;
     int has_em, has_ep;
@@ -435,10 +533,11 @@ __global__ __launch_bounds__(BLOCK) void k_compact_copy(CompactArgs a) {
 
 // ------------------------------------------------------------------------- launchers
 static Consts consts_of(const qed_ctx *ctx) {
-    return {ctx->cfg.xi_L, ctx->cfg.alpha, ctx->cfg.a_e, ctx->cfg.dt, ctx->cfg.p_max, ctx->cfg.seed, ctx->cfg.procs};
+    const qed_config &g = ctx->cfg;
+    return {g.xi_L, g.alpha, g.a_e, g.dt, g.p_max, g.alpha / (SQRT3 * PI * g.xi_L), g.seed, g.procs};
 }
-static int tiles_grid(int64_t cap) {
-    const int64_t b = (cap + BLOCK - 1) / BLOCK;
+static int tiles_grid(int64_t cap, int64_t tile = BLOCK) {
+    const int64_t b = (cap + tile - 1) / tile;
     return b < 1 ? 1 : (int)b;
 }
 static int stride_grid(int64_t cap, int64_t limit) {
@@ -446,11 +545,14 @@ static int stride_grid(int64_t cap, int64_t limit) {
     if (b > limit) b = limit;
     return b < 1 ? 1 : (int)b;
 }
-static hipError_t launch_scan(qed_ctx *ctx, const int64_t *in_count, int64_t in_cap, int64_t *c0, int64_t cap0,
-                              int64_t *c1, int64_t cap1, int ids, hipStream_t s) {
+static hipError_t launch_scan(qed_ctx *ctx, const int64_t *in_count, int64_t in_cap, int *counts, int clear,
+                              int unit, int64_t *c0, int64_t cap0, int64_t *c1, int64_t cap1, int ids,
+                              hipStream_t s) {
     ScanArgs sa{};
-    sa.tile_counts = ctx->tile_counts;
-    sa.tile_off = ctx->tile_off;
+    sa.counts = counts;
+    sa.clear = clear;
+    sa.off = ctx->tile_off;
+    sa.unit = unit;
     sa.in_count = in_count;
     sa.in_capacity = in_cap;
     sa.out_count[0] = c0;
@@ -465,34 +567,51 @@ static hipError_t launch_scan(qed_ctx *ctx, const int64_t *in_count, int64_t in_
     return hipGetLastError();
 }
 
-template <class T>
+// decide + scan + events of a step with NCS; FK as in fields_for (PUSH = false: fields
+// from E6, no field evaluation)
+template <class T, bool PUSH, int FK>
+static hipError_t launch_ncs(qed_ctx *ctx, const LeptonArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL((k_leptons_decide<T, PUSH, FK>), dim3(tiles_grid(a.L.capacity)), dim3(BLOCK), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = launch_scan(ctx, a.L.count, a.L.capacity, ctx->group_tot, 1, BLOCK * EV_GROUP,
+                    a.has_out ? a.out.count : nullptr, a.has_out ? a.out.capacity : 0, nullptr, 0, 1, s);
+    if (e != hipSuccess) return e;
+    // one wavefront per group of tiles of the list capacity
+    const int64_t groups = ((a.L.capacity + BLOCK - 1) / BLOCK + EV_GROUP - 1) / EV_GROUP;
+    const int ge = (int)((groups + BLOCK / 64 - 1) / (BLOCK / 64));
+    hipLaunchKernelGGL((k_leptons_events<T, PUSH, FK>), dim3(ge < 1 ? 1 : ge), dim3(BLOCK), 0, s, a);
+    return hipGetLastError();
+}
+
+template <class T, bool M>
 static hipError_t launch_leptons_t(qed_ctx *ctx, LeptonMode mode, const LeptonArgs &a, hipStream_t s) {
-    const int gs = stride_grid(a.L.capacity, 65536), gt = tiles_grid(a.L.capacity);
+    const int gs = stride_grid(a.L.capacity, 65536);
     switch (mode) {
     case LM_GATHER:
-        hipLaunchKernelGGL((k_leptons_simple<T, true, false, false>), dim3(gs), dim3(BLOCK), 0, s, a);
+        hipLaunchKernelGGL((k_leptons_simple<T, true, false, false, M>), dim3(gs), dim3(BLOCK), 0, s, a);
         return hipGetLastError();
     case LM_PUSH:
-        if (a.E6) hipLaunchKernelGGL((k_leptons_simple<T, false, true, true>), dim3(gs), dim3(BLOCK), 0, s, a);
-        else hipLaunchKernelGGL((k_leptons_simple<T, false, true, false>), dim3(gs), dim3(BLOCK), 0, s, a);
+        if (a.E6) hipLaunchKernelGGL((k_leptons_simple<T, false, true, true, false>), dim3(gs), dim3(BLOCK), 0, s, a);
+        else hipLaunchKernelGGL((k_leptons_simple<T, false, true, false, M>), dim3(gs), dim3(BLOCK), 0, s, a);
         return hipGetLastError();
     case LM_EMIT:
     case LM_FUSED:
         break;
     }
     if (!(a.c.procs & QED_PROC_NCS)) {   // a fused step without NCS is a push
-        hipLaunchKernelGGL((k_leptons_simple<T, false, true, false>), dim3(gs), dim3(BLOCK), 0, s, a);
+        hipLaunchKernelGGL((k_leptons_simple<T, false, true, false, M>), dim3(gs), dim3(BLOCK), 0, s, a);
         return hipGetLastError();
     }
-    if (mode == LM_FUSED) hipLaunchKernelGGL((k_leptons_decide<T, true>), dim3(gt), dim3(BLOCK), 0, s, a);
-    else hipLaunchKernelGGL((k_leptons_decide<T, false>), dim3(gt), dim3(BLOCK), 0, s, a);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    e = launch_scan(ctx, a.L.count, a.L.capacity, a.has_out ? a.out.count : nullptr, a.has_out ? a.out.capacity : 0,
-                    nullptr, 0, 1, s);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_leptons_events<T>, dim3(stride_grid(a.L.capacity, 2048)), dim3(BLOCK), 0, s, a);
-    return hipGetLastError();
+    if (mode == LM_EMIT) return launch_ncs<T, false, QED_FIELD_NONE>(ctx, a, s);
+    if (M) return launch_ncs<T, true, FK_MULTI>(ctx, a, s);
+    switch (a.sa.f0.kind) {
+    case QED_FIELD_CONST: return launch_ncs<T, true, QED_FIELD_CONST>(ctx, a, s);
+    case QED_FIELD_PW: return launch_ncs<T, true, QED_FIELD_PW>(ctx, a, s);
+    case QED_FIELD_GAUSS: return launch_ncs<T, true, QED_FIELD_GAUSS>(ctx, a, s);
+    case QED_FIELD_GRID2D: return launch_ncs<T, true, QED_FIELD_GRID2D>(ctx, a, s);
+    default: return launch_ncs<T, true, QED_FIELD_NONE>(ctx, a, s);
+    }
 }
 
 hipError_t launch_leptons(qed_ctx *ctx, LeptonMode mode, const SegArgs &sa, const qed_leptons &L, double *E6,
@@ -506,16 +625,18 @@ hipError_t launch_leptons(qed_ctx *ctx, LeptonMode mode, const SegArgs &sa, cons
     a.E6 = E6;
     a.step = step;
     a.status = ctx->status;
-    a.stg = ctx->staging;
+    a.stg = (EventRec *)ctx->staging;
     a.tile_counts = ctx->tile_counts;
+    a.group_tot = ctx->group_tot;
     a.tile_off = ctx->tile_off;
     a.launch = ctx->launch;
+    const bool multi = sa.nseg > 1;
     if (ctx->cfg.precision == QED_MIXED) {
         a.tab = ctx->tab32;
-        return launch_leptons_t<float>(ctx, mode, a, s);
+        return multi ? launch_leptons_t<float, true>(ctx, mode, a, s) : launch_leptons_t<float, false>(ctx, mode, a, s);
     }
     a.tab = ctx->tab64;
-    return launch_leptons_t<double>(ctx, mode, a, s);
+    return multi ? launch_leptons_t<double, true>(ctx, mode, a, s) : launch_leptons_t<double, false>(ctx, mode, a, s);
 }
 
 template <class T>
@@ -527,7 +648,7 @@ static hipError_t launch_photons_t(qed_ctx *ctx, const PhotonArgs &a, hipStream_
     hipLaunchKernelGGL((k_photons_decide<T, true>), dim3(tiles_grid(a.G.capacity)), dim3(BLOCK), 0, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    e = launch_scan(ctx, a.G.count, a.G.capacity, a.has_em ? a.em.count : nullptr, a.has_em ? a.em.capacity : 0,
+    e = launch_scan(ctx, a.G.count, a.G.capacity, ctx->tile_counts, 0, BLOCK, a.has_em ? a.em.count : nullptr, a.has_em ? a.em.capacity : 0,
                     a.has_ep ? a.ep.count : nullptr, a.has_ep ? a.ep.capacity : 0, 2, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_photons_events<T>, dim3(stride_grid(a.G.capacity, 2048)), dim3(BLOCK), 0, s, a);
@@ -538,7 +659,7 @@ hipError_t launch_photons(qed_ctx *ctx, PhotonMode mode, const SegArgs &sa, cons
                           const qed_leptons *em, const qed_leptons *ep, int64_t step, hipStream_t s) {
     PhotonArgs a{};
     a.c = consts_of(ctx);
-    a.field = sa.seg[0].field;
+    a.field = sa.f0;
     a.G = G;
     a.has_em = em != nullptr;
     a.has_ep = ep != nullptr;
@@ -549,7 +670,7 @@ hipError_t launch_photons(qed_ctx *ctx, PhotonMode mode, const SegArgs &sa, cons
     a.do_move = mode != PM_BIREF;
     a.step = step;
     a.status = ctx->status;
-    a.stg = ctx->staging;
+    a.stg = (EventRec *)ctx->staging;
     a.tile_counts = ctx->tile_counts;
     a.tile_off = ctx->tile_off;
     a.launch = ctx->launch;
@@ -562,11 +683,11 @@ hipError_t launch_photons(qed_ctx *ctx, PhotonMode mode, const SegArgs &sa, cons
 }
 
 hipError_t launch_compact(qed_ctx *ctx, const qed_photons &in, const qed_photons &out, hipStream_t s) {
-    CompactArgs a{in, out, ctx->staging, ctx->tile_counts, ctx->tile_off, ctx->launch};
+    CompactArgs a{in, out, (EventRec *)ctx->staging, ctx->tile_counts, ctx->tile_off, ctx->launch};
     hipLaunchKernelGGL(k_compact_mark, dim3(tiles_grid(in.capacity)), dim3(BLOCK), 0, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    e = launch_scan(ctx, in.count, in.capacity, out.count, out.capacity, nullptr, 0, 0, s);
+    e = launch_scan(ctx, in.count, in.capacity, ctx->tile_counts, 0, BLOCK, out.count, out.capacity, nullptr, 0, 0, s);
     if (e != hipSuccess) return e;
     if (ctx->cfg.precision == QED_MIXED)
         hipLaunchKernelGGL(k_compact_copy<float>, dim3(stride_grid(in.capacity, 2048)), dim3(BLOCK), 0, s, a);

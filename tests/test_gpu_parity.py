@@ -317,6 +317,40 @@ def test_mixed_precision_tracks_fp64():
     assert abs(ga["xi3"].mean() - gb["xi3"].mean()) < 2e-2
 
 
+@pytest.mark.parametrize("kind", ["pw_lp", "pw_cp", "gauss_cp"])
+def test_gathered_fields_both_precisions(kind):
+    """qed_gather against the oracle's field evaluation at the bunch positions inside the
+    pulse: FP64 to rounding, mixed (FP32 pulse after an FP64 phase reduction, hardware
+    sine / cosine / exp) within single-precision error of the amplitude."""
+    _say(f"gather {kind}")
+    specs = {
+        "pw_lp": {"kind": W.FIELD_PW, "circular": 0, "a0": 50.0, "ncycles": 10.0, "phase0": 0.3, "pol_angle": 0.4,
+                  "phi_start": 0.0},
+        "pw_cp": {"kind": W.FIELD_PW, "circular": 1, "a0": 50.0, "ncycles": 10.0, "phase0": -1.1, "pol_angle": 0.0,
+                  "phi_start": 0.0},
+        "gauss_cp": W.c2(10, start_step=0)["field"],
+    }
+    spec = specs[kind]
+    cfg = W.c2(3000, start_step=2500)
+    st = cfg["leptons"]
+    step = 2500
+    t = step * cfg["dt"]
+    want = np.zeros((3000, 6))
+    for j in range(3000):
+        E, B = oracle.field_eval(spec, t, [st["x"][j], st["y"][j], st["z"][j]])
+        want[j, :3], want[j, 3:] = E, B
+    a0 = spec["a0"]
+    assert np.max(np.abs(want)) > 0.3 * a0   # the bunch sits inside the pulse
+    for prec, tol in ((Q.QED_FP64, 1e-12), (Q.QED_MIXED, 4e-6)):
+        ctx = _ctx(cfg, precision=prec)
+        Lg = Q.Leptons.from_state(st, precision=prec)
+        E6 = torch.zeros(3000 * 6, dtype=torch.float64, device="cuda")
+        ctx.gather(Q.whole(spec), Lg, E6, step)
+        got = E6.view(3000, 6).cpu().numpy()
+        err = np.max(np.abs(got - want)) / a0
+        assert err < tol, (prec, err)
+
+
 # ----------------------------------------------------------------------------- full size
 def _sampled_full_size(precision):
     cfg = W.c2(10_000_000, start_step=2500)
@@ -371,3 +405,42 @@ def test_full_size_c2_step_sampled_mixed():
         assert np.median(np.abs(g[k] - o[k]) / pm) < 1e-6
     dS = np.sqrt((g["sx"] - o["sx"]) ** 2 + (g["sy"] - o["sy"]) ** 2 + (g["sz"] - o["sz"]) ** 2)
     assert np.mean(dS < 1e-4) > 0.99
+
+
+def test_multi_segment_collisions_fp64():
+    """Several collisions in one list (one segment each: different lasers, one launch):
+    equal to running every collision separately in index order with one photon list."""
+    _say("multi-segment")
+    specs = [
+        {"kind": W.FIELD_PW, "circular": 0, "a0": 20.0, "ncycles": 8.0, "phase0": 0.0, "pol_angle": 0.0,
+         "phi_start": 0.0},
+        {"kind": W.FIELD_PW, "circular": 1, "a0": 35.0, "ncycles": 6.0, "phase0": 0.5, "pol_angle": 0.3,
+         "phi_start": 2.0},
+        {"kind": W.FIELD_GAUSS, "circular": 1, "a0": 60.0, "ncycles": 8.0, "phase0": 0.0, "pol_angle": 0.0,
+         "w0": 3 * W.TWO_PI, "x_focus": 0.0, "phi_start": 0.0},
+    ]
+    sizes = [700, 1300, 257]
+    states = [W.beam(m, seed=70 + k, gamma0=1500.0, gamma_rel_spread=0.05, divergence=1e-3, x_mean=8.0,
+                     x_sigma=1.0, r_sigma=2.0, spin="iso", id0=sum(sizes[:k])) for k, m in enumerate(sizes)]
+    cfg = {"dt": W.TWO_PI / 400, "procs": oracle.PROC_NCS | oracle.PROC_NCS_STOKES, "seed": 4, "next_id": 1 << 40}
+    # oracle: collisions one after the other, shared photon list and id counter
+    sim = _sim(cfg)
+    G = oracle.PhotonArrays.empty(40000)
+    Ls = [oracle.LeptonArrays.from_state(st) for st in states]
+    fs = [oracle.make_field(sp) for sp in specs]
+    # gpu: one list, three segments
+    full = {k: np.concatenate([st[k] for st in states]) for k in states[0]}
+    ctx = _ctx(cfg)
+    Lg = Q.Leptons.from_state(full)
+    Gg = Q.Photons(40000)
+    bounds = np.cumsum([0] + sizes)
+    segs = Q.segments([(bounds[k], bounds[k + 1], specs[k]) for k in range(3)])
+    for s in range(0, 120):
+        for L, f in zip(Ls, fs):
+            sim.step(f, L, None, G, s)
+        ctx.step_leptons(segs, Lg, Gg, s)
+    assert G.count > 500
+    ov = {k: np.concatenate([L.view()[k] for L in Ls]) for k in Ls[0].view()}
+    _close_lep(Lg.to_numpy(), ov, what="leptons")
+    _close_pho(Gg.to_numpy(), G.view(), what="photons")
+    assert ctx.next_id() == sim.next_id
