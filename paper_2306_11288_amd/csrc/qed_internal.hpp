@@ -80,11 +80,21 @@ struct DevSegment {
     FieldDev f;
 };
 
-// staging record of one event (decide kernel -> event kernel): particle index and the
-// fields of x^n at which the event was decided
+// staging record of one photon event (decide kernel -> event kernel): particle index and
+// the fields of x^n at which the event was decided
 struct EventRec {
     long long idx;
     double f[6];
+};
+// staging record of one lepton event: the state the decide kernel reached for it (index,
+// id, weight, x^{n+1}, p^{n+1/2}, fields of x^n, S^{n+1/2} after the T-BMT rotation)
+template <class T>
+struct LepEvent {
+    int64_t i;
+    unsigned long long id;
+    double w;
+    double r[3], p[3], E[3], B[3];
+    T S[3];
 };
 
 // Field selection for a launch.  One segment: its field travels in the kernel arguments
@@ -103,9 +113,9 @@ FieldDev field_dev(const qed_field &f);   // host: derived constants of a field
 constexpr int BLOCK = 256;             // threads per block = particles per tile
 constexpr int EV_GROUP = 8;            // lepton step: tiles per group (one wavefront of the event kernel)
 
-// bytes of one staging slot: an event record of the photon kernels, or the tile-local
-// index (int) of a queued lepton event
-constexpr size_t STAGING_SLOT = sizeof(EventRec);
+// bytes of one staging slot: the largest record any kernel parks there
+constexpr size_t STAGING_SLOT = sizeof(LepEvent<double>) > sizeof(EventRec) ? sizeof(LepEvent<double>)
+                                                                             : sizeof(EventRec);
 
 }  // namespace qed
 

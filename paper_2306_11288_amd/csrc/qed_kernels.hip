@@ -232,10 +232,7 @@ __global__ __launch_bounds__(BLOCK) void k_leptons_simple(LeptonArgs a) {
 }
 
 // State of lepton i after the push (PUSH: gather at x^n, Boris, T-BMT, drift) or with the
-// fields of x^n taken from E6 (emission only).  The decide and event kernels both call it on
-// the same inputs, so an event particle is rebuilt exactly as it was when its event was
-// decided.
-// Returns 1/gamma of the resulting momentum.  Lepton arrays are addressed with 32-bit byte
+// fields of x^n taken from E6 (emission only).  Returns 1/gamma of the resulting momentum.  Lepton arrays are addressed with 32-bit byte
 // offsets from the array base (lists hold at most 2^28 particles), which lets every load
 // and store use the scalar-base + vector-offset form.
 template <class T, bool PUSH, int FK>
@@ -267,11 +264,12 @@ __device__ __forceinline__ void store_s(const LeptonArgs &a, uint32_t os, const 
 }
 
 // Decide (lepton step with NCS), one thread per particle, one BLOCK-particle tile per
-// block: state after the push, local frame, rates, event test.  Particles without an
-// event are finished and written back here.  Event particles write nothing: their
-// tile-local indices are queued in index order (wave ballot + popcount, waves combined in
-// LDS) in the tile's staging slots; the tile's event count goes to tile_counts and is
-// added to its group's total (integer atomics: the sum does not depend on their order).
+// block: gather, push, T-BMT, local frame, rates, event test.  Every particle writes back
+// x^{n+1}, p^{n+1/2} and its spin (after the no-emission update when nothing happened).
+// Event particles also park their state in a LepEvent record at their tile's staging
+// slot tile*BLOCK + rank (rank in index order: wave ballot + popcount, waves combined in
+// LDS); the tile's event count goes to tile_counts and is added to its group's total
+// (integer atomics: the sum does not depend on their order).
 template <class T, bool PUSH, int FK>
 __global__ __launch_bounds__(BLOCK) void k_leptons_decide(LeptonArgs a) {
     __shared__ int s_wave[BLOCK / 64];
@@ -283,10 +281,11 @@ __global__ __launch_bounds__(BLOCK) void k_leptons_decide(LeptonArgs a) {
     const int64_t i = base + threadIdx.x;
     uint32_t st = 0;
     bool ev = false;
+    V3<double> r, p, E, B;
+    V3<T> S;
     if (i < n) {
-        V3<double> r, p, E, B;
-        V3<T> S;
         const double ig = lepton_state<T, PUSH, FK>(a, i, t, q, r, p, S, E, B, st);
+        if constexpr (PUSH) store_xp<T>(a, (uint32_t)i * 8u, r, p);
         NcsFrame<T> f;
         if (ncs_frame<T>(a.c, tb, q, p, ig, S, E, B, st, f)) {
             double rr[4];
@@ -294,14 +293,21 @@ __global__ __launch_bounds__(BLOCK) void k_leptons_decide(LeptonArgs a) {
             ev = rr[1] < f.P;
             if (!ev) ncs_no_event<T>(a.c, f, S);
         }
-        if (!ev) {
-            if constexpr (PUSH) store_xp<T>(a, (uint32_t)i * 8u, r, p);
-            store_s<T>(a, (uint32_t)i * (uint32_t)sizeof(T), S);
-        }
+        if (!ev) store_s<T>(a, (uint32_t)i * (uint32_t)sizeof(T), S);
     }
     int total;
     const int rank = block_rank(ev, total, s_wave);
-    if (ev) ((int *)a.stg)[base + rank] = threadIdx.x;
+    if (ev) {
+        LepEvent<T> &o = ((LepEvent<T> *)a.stg)[base + rank];
+        o.i = i;
+        o.id = at(a.L.id, (uint32_t)i * 8u);
+        o.w = at(a.L.w, (uint32_t)i * 8u);
+        o.r[0] = r.x; o.r[1] = r.y; o.r[2] = r.z;
+        o.p[0] = p.x; o.p[1] = p.y; o.p[2] = p.z;
+        o.E[0] = E.x; o.E[1] = E.y; o.E[2] = E.z;
+        o.B[0] = B.x; o.B[1] = B.y; o.B[2] = B.z;
+        o.S[0] = S.x; o.S[1] = S.y; o.S[2] = S.z;
+    }
     if (threadIdx.x == 0) {
         a.tile_counts[tile] = total;
         if (total) atomicAdd(a.group_tot + tile / EV_GROUP, total);
@@ -310,20 +316,19 @@ __global__ __launch_bounds__(BLOCK) void k_leptons_decide(LeptonArgs a) {
 }
 
 // Events of the last decide, after the scan.  One wavefront per group of EV_GROUP tiles:
-// the tile counts of the group are scanned across lanes, lane
-// k takes the group's events k, k + 64, ..., finds its tile and queue slot, rebuilds the
-// particle from its unchanged inputs exactly as the decide kernel saw it, emits, and
-// writes the photon straight to its ordered place: global rank = group offset + rank in
-// the group, id = id base + global rank.
-template <class T, bool PUSH, int FK>
+// the tile counts of the group are scanned across lanes, lane k takes the group's events
+// k, k + 64, ..., finds its tile and record, rebuilds the local frame from the parked
+// state, emits, and writes the photon straight to its ordered place: global rank = group
+// offset + rank in the group, id = id base + global rank.
+template <class T>
 __global__ __launch_bounds__(BLOCK) void k_leptons_events(LeptonArgs a) {
-    static_assert(EV_GROUP <= 64 && (EV_GROUP & (EV_GROUP - 1)) == 0, "one group = at most one wave of tiles");
+    static_assert(EV_GROUP <= 64, "one group = at most one wave of tiles");
     const int64_t n = clamp_count(a.L.count, a.L.capacity);
     const int64_t ntiles = (n + BLOCK - 1) / BLOCK;
     const int64_t ngroups = (ntiles + EV_GROUP - 1) / EV_GROUP;
     const int64_t obase = a.launch[0], id0 = a.launch[2];
     const Tabs<T> tb = {(const T *)a.tab};
-    const double t = (double)a.step * a.c.dt, q = (double)a.L.charge;
+    const double q = (double)a.L.charge;
     const int lane = threadIdx.x & 63;
     uint32_t st = 0;
     const int64_t g = (int64_t)blockIdx.x * (BLOCK / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -349,24 +354,25 @@ __global__ __launch_bounds__(BLOCK) void k_leptons_events(LeptonArgs a) {
                 j += past ? 1 : 0;
                 below = past ? pre[k] : below;
             }
-            const int64_t tile = c0 + j;
-            const int64_t i = tile * BLOCK + ((const int *)a.stg)[tile * BLOCK + (e - below)];
-            V3<double> r, p, E, B;
-            V3<T> S;
-            const double ig = lepton_state<T, PUSH, FK>(a, i, t, q, r, p, S, E, B, st);
+            const LepEvent<T> &o = ((const LepEvent<T> *)a.stg)[(c0 + j) * BLOCK + (e - below)];
+            const int64_t i = o.i;
+            V3<double> p = {o.p[0], o.p[1], o.p[2]};
+            const V3<double> E = {o.E[0], o.E[1], o.E[2]}, B = {o.B[0], o.B[1], o.B[2]};
+            V3<T> S = {o.S[0], o.S[1], o.S[2]};
             NcsFrame<T> f;
-            ncs_frame<T>(a.c, tb, q, p, ig, S, E, B, st, f);
+            ncs_frame<T>(a.c, tb, q, p, rsqrt(1.0 + dot(p, p)), S, E, B, st, f);
             double rr[4];
-            uniform4(a.L.id[i], a.step, STREAM_NCS, a.c.seed, rr);
+            uniform4(o.id, a.step, STREAM_NCS, a.c.seed, rr);
             NcsPhoton<T> ph;
             ncs_event<T>(a.c, tb, f, rr, p, S, ph);
-            store_xp<T>(a, (uint32_t)i * 8u, r, p);
+            const uint32_t o8 = (uint32_t)i * 8u;
+            at(a.L.px, o8) = p.x; at(a.L.py, o8) = p.y; at(a.L.pz, o8) = p.z;
             store_s<T>(a, (uint32_t)i * (uint32_t)sizeof(T), S);
             const int64_t ge = goff + e, pos = obase + ge;
             if (a.has_out && pos < a.out.capacity) {
-                a.out.x[pos] = r.x; a.out.y[pos] = r.y; a.out.z[pos] = r.z;
+                a.out.x[pos] = o.r[0]; a.out.y[pos] = o.r[1]; a.out.z[pos] = o.r[2];
                 a.out.kx[pos] = ph.k.x; a.out.ky[pos] = ph.k.y; a.out.kz[pos] = ph.k.z;
-                a.out.w[pos] = a.L.w[i];
+                a.out.w[pos] = o.w;
                 ((T *)a.out.xi1)[pos] = ph.xi.x; ((T *)a.out.xi2)[pos] = ph.xi.y; ((T *)a.out.xi3)[pos] = ph.xi.z;
                 ((T *)a.out.e1x)[pos] = ph.e1.x; ((T *)a.out.e1y)[pos] = ph.e1.y; ((T *)a.out.e1z)[pos] = ph.e1.z;
                 a.out.id[pos] = (unsigned long long)(id0 + ge);
@@ -580,7 +586,7 @@ static hipError_t launch_ncs(qed_ctx *ctx, const LeptonArgs &a, hipStream_t s) {
     // one wavefront per group of tiles of the list capacity
     const int64_t groups = ((a.L.capacity + BLOCK - 1) / BLOCK + EV_GROUP - 1) / EV_GROUP;
     const int ge = (int)((groups + BLOCK / 64 - 1) / (BLOCK / 64));
-    hipLaunchKernelGGL((k_leptons_events<T, PUSH, FK>), dim3(ge < 1 ? 1 : ge), dim3(BLOCK), 0, s, a);
+    hipLaunchKernelGGL(k_leptons_events<T>, dim3(ge < 1 ? 1 : ge), dim3(BLOCK), 0, s, a);
     return hipGetLastError();
 }
 
