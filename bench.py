@@ -26,15 +26,17 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# algorithmic bytes per lepton-step of the fused kernel: read x, p (48 B), S, id (8 B);
-# write x, p (48 B), S.  S is 3 x 4 B (mixed) or 3 x 8 B (FP64).
+# algorithmic bytes per lepton-step (every lepton, the decide kernel): read x, p (48 B),
+# S, id (8 B); write x, p (48 B), S.  S is 3 x 4 B (mixed) or 3 x 8 B (FP64).
 BYTES_LEPTON = {"mixed": 48 + 12 + 8 + 48 + 12, "fp64": 48 + 24 + 8 + 48 + 24}
-# per emitted photon: read the parent weight (8 B); write x, k, w (56 B), xi and e1
-# (6 x 4 or 6 x 8 B), id (8 B), alive (1 B)
+# per emitted photon (the event kernel): read the parent weight (8 B); write x, k, w
+# (56 B), xi and e1 (6 x 4 or 6 x 8 B), id (8 B), alive (1 B)
 BYTES_PHOTON = {"mixed": 8 + 56 + 24 + 8 + 1, "fp64": 8 + 56 + 48 + 8 + 1}
 KERNEL_SOURCES = ["qed_kernels.hip", "qed_dev.hpp", "qed_internal.hpp"]
-# one benchmark step = one qed_step_leptons call = three launches on the stream (decide,
-# tile-count scan, event completion); HIP events bracket each call
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_lepton_decide_c2.json")
+# one benchmark step = one qed_step_leptons call = three launches on the stream: decide
+# (all leptons), scan (event counts), events (emitting leptons).  HIP events bracket each
+# call and, through qed_set_step_events, each launch.
 
 
 def kernel_hash() -> str:
@@ -46,11 +48,10 @@ def kernel_hash() -> str:
 
 
 def measured_traffic(prec: str):
-    """HBM bytes per launch from the committed counter summary, if it was taken on the
-    current kernel sources; else None."""
-    p = os.path.join(ROOT, "profiles", "traffic_fused_lepton_step_c2.json")
+    """HBM bytes per decide launch from the committed counter summary, if it was taken on
+    the current kernel sources; else None."""
     try:
-        d = json.load(open(p))
+        d = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
         return None
     if d.get("kernel_hash") != kernel_hash():
@@ -73,22 +74,45 @@ def run_gpu(prec, cfg, steps, warmup, torch, Q, per_launch_events=True):
     torch.cuda.synchronize()
     n_before = G.count
     stream = torch.cuda.current_stream()
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)] if per_launch_events else []
+    # per step: four events recorded by the library around its launches
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)] if per_launch_events else []
+    for e4 in ev:   # create the HIP events before the timed region
+        for e in e4:
+            e.record(stream)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    if per_launch_events:
-        ev[0].record(stream)
     for k, s in enumerate(range(s0 + warmup, s0 + warmup + steps)):
-        ctx.step_leptons(segs, L, G, s)
         if per_launch_events:
-            ev[k + 1].record(stream)
+            ctx.set_step_events(ev[k])
+        ctx.step_leptons(segs, L, G, s)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    launch_ms = [ev[k].elapsed_time(ev[k + 1]) for k in range(steps)] if per_launch_events else []
+    ctx.set_step_events(None)
+    kern = {}
+    if per_launch_events:
+        kern = {"step": [e[0].elapsed_time(e[3]) for e in ev], "decide": [e[0].elapsed_time(e[1]) for e in ev],
+                "scan": [e[1].elapsed_time(e[2]) for e in ev], "events": [e[2].elapsed_time(e[3]) for e in ev]}
     status = ctx.read_status()
-    return {"ctx": ctx, "L": L, "G": G, "wall": wall, "launch_ms": launch_ms, "n": n,
+    return {"ctx": ctx, "L": L, "G": G, "wall": wall, "kern_ms": kern, "n": n,
             "photons_timed": G.count - n_before, "photons_total": G.count, "photon_start": n_before,
             "status": status}
+
+
+def copy_bandwidth(torch, mib=2048, reps=5):
+    """Achievable HBM bandwidth of a plain elementwise copy (x * 1.0, float64): bytes read +
+    written per second, best of `reps`."""
+    src = torch.ones((mib << 20) // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    best = float("inf")
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        torch.mul(src, 1.0, out=dst)
+        b.record()
+        torch.cuda.synchronize()
+        best = min(best, a.elapsed_time(b))
+    del src, dst
+    return 2 * (mib << 20) / (best * 1e-3) / 1e9
 
 
 def detector_stokes(G, start, torch):
@@ -235,11 +259,14 @@ def main():
 
     ms_per_step = 1e3 * mixed["wall"] / args.steps
     value = args.n * args.steps / mixed["wall"]
-    launch_ms = sum(mixed["launch_ms"]) / len(mixed["launch_ms"])
+    km = {k: sum(v) / len(v) for k, v in mixed["kern_ms"].items()}
     ph_per_launch = mixed["photons_timed"] / args.steps
-    alg_bytes = args.n * BYTES_LEPTON["mixed"] + ph_per_launch * BYTES_PHOTON["mixed"]
-    achieved = alg_bytes / (launch_ms * 1e-3) / 1e9
+    # the dominant kernel is the decide kernel: every lepton, 128 algorithmic bytes each
+    alg_bytes = args.n * BYTES_LEPTON["mixed"]
+    achieved = alg_bytes / (km["decide"] * 1e-3) / 1e9
+    step_bytes = alg_bytes + ph_per_launch * BYTES_PHOTON["mixed"]
     tr = measured_traffic("mixed")
+    copy_gbs = copy_bandwidth(torch)
     result = {
         "metric": "particle-steps/s (push+spin+QED) mixed vs FP64 GPU at stated spectrum error",
         "value": value, "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -251,17 +278,20 @@ def main():
                    "start_step": start, "processes": "NCS + spin flip + photon Stokes"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": tr,
-                     "kernel": "lepton step = k_leptons_decide<float,push,gauss> + k_scan + "
-                               "k_leptons_events<float,push,gauss> (timed together per step)",
-                     "avg_launch_ms": launch_ms, "algorithmic_bytes_per_launch": alg_bytes,
+                     "kernel": "k_leptons_decide<float, push, gauss>",
+                     "avg_launch_ms": km["decide"], "algorithmic_bytes_per_launch": alg_bytes,
+                     "copy_probe_GBs": copy_gbs, "frac_of_copy_probe": achieved / copy_gbs,
+                     "step_ms": {"decide": km["decide"], "scan": km["scan"], "events": km["events"],
+                                 "step": km["step"]},
+                     "step_algorithmic_GBs": step_bytes / (km["step"] * 1e-3) / 1e9,
                      "photons_per_launch": ph_per_launch},
         "status_bits": mixed["status"],
     }
     if fp64 is not None:
-        f_launch = sum(fp64["launch_ms"]) / len(fp64["launch_ms"])
-        f_bytes = args.n * BYTES_LEPTON["fp64"] + fp64["photons_timed"] / args.steps * BYTES_PHOTON["fp64"]
+        fk = {k: sum(v) / len(v) for k, v in fp64["kern_ms"].items()}
         result["fp64"] = {"value": args.n * args.steps / fp64["wall"], "ms_per_step": 1e3 * fp64["wall"] / args.steps,
-                          "avg_launch_ms": f_launch, "achieved_GBs": f_bytes / (f_launch * 1e-3) / 1e9,
+                          "decide_ms": fk["decide"], "step_ms": fk["step"],
+                          "decide_achieved_GBs": args.n * BYTES_LEPTON["fp64"] / (fk["decide"] * 1e-3) / 1e9,
                           "status_bits": fp64["status"]}
         result["speedup_mixed_over_fp64"] = result["value"] / result["fp64"]["value"]
         result["error_vs_fp64"] = error_metrics(fp64, mixed, 2000.0, torch)

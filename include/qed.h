@@ -59,7 +59,7 @@ enum {
     QED_ST_PMAX = 4,       /* a per-step event probability exceeded cfg.p_max          */
     QED_ST_EPS_LT1 = 8,    /* a pair member was born with energy below m c^2            */
     QED_ST_CLAMP = 16,     /* chi above the tabulated range (value clamped)             */
-    QED_ST_SCAN = 32       /* an ordered-append wait hit its spin limit (never expected) */
+    QED_ST_SCAN = 32       /* reserved; not set by this version */
 };
 /* field kinds */
 enum { QED_FIELD_NONE = 0, QED_FIELD_CONST = 1, QED_FIELD_PW = 2, QED_FIELD_GAUSS = 3,
@@ -152,7 +152,8 @@ qed_status qed_push_spin(qed_ctx_t *ctx, const qed_segment *segs, int nseg, qed_
  * x^n (required).  Photons are appended to `out` (may be NULL: recoil and spin only).   */
 qed_status qed_emit(qed_ctx_t *ctx, const qed_segment *segs, int nseg, qed_leptons *p,
                     const double *E6, qed_photons *out, int64_t step, hipStream_t stream);
-/* Fused gather + push + T-BMT + NCS in one kernel (the production path). */
+/* Fused gather + push + T-BMT + NCS (the production path): a decide kernel over all
+ * leptons, a scan of the event counts and an event kernel over the emitting leptons.   */
 qed_status qed_step_leptons(qed_ctx_t *ctx, const qed_segment *segs, int nseg, qed_leptons *p,
                             qed_photons *out, int64_t step, hipStream_t stream);
 /* Photon polarisation transport: basis rotation to E_red and, if QED_PROC_VB, the
@@ -182,6 +183,12 @@ qed_status qed_set_next_id(qed_ctx_t *ctx, uint64_t next_id, hipStream_t stream)
  * returned by qed_table_size.                                                           */
 int64_t qed_table_size(int which);
 qed_status qed_table_export(qed_ctx_t *ctx, int which, double *host_out, int64_t n);
+/* Optional timing of the NCS launches: with ev non-NULL, every later qed_step_leptons /
+ * qed_emit call that runs NCS records ev[0] before its decide kernel, ev[1] after it,
+ * ev[2] after the scan and ev[3] after the event kernel, on the call's stream.  The four
+ * events belong to the caller (created with hipEventCreate, alive while set); the array
+ * is copied.  NULL switches the recording off.                                         */
+qed_status qed_set_step_events(qed_ctx_t *ctx, const hipEvent_t *ev);
 /* Last argument / HIP error of this context as text (empty if none). */
 const char *qed_last_error(const qed_ctx_t *ctx);
 

@@ -23,7 +23,7 @@ TAB_BESSEL, TAB_NCS_RATE, TAB_NCS_CDF, TAB_NBW_RATE, TAB_NBW_CDF, TAB_VB = range
 EXPORTED = ["qed_init_tables", "qed_destroy", "qed_gather", "qed_push_spin", "qed_emit", "qed_step_leptons",
             "qed_birefringence", "qed_pair", "qed_step_photons", "qed_compact_photons", "qed_read_status",
             "qed_clear_status", "qed_get_next_id", "qed_set_next_id", "qed_table_size", "qed_table_export",
-            "qed_last_error"]
+            "qed_set_step_events", "qed_last_error"]
 
 ALPHA = 1.0 / 137.035999084
 XI_L = 2.42631023867e-6
@@ -91,6 +91,7 @@ def lib():
             "qed_get_next_id": [vp, C.POINTER(C.c_uint64), vp],
             "qed_set_next_id": [vp, C.c_uint64, vp],
             "qed_table_export": [vp, C.c_int, vp, i64],
+            "qed_set_step_events": [vp, vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -343,6 +344,18 @@ class Context:
 
     def set_next_id(self, v: int, stream=None):
         self._check(lib().qed_set_next_id(self.h, int(v), _stream(stream)), "qed_set_next_id")
+
+    def set_step_events(self, events=None):
+        """Record four torch.cuda.Event around the decide / scan / event kernels of every
+        later NCS lepton step (None switches it off); the events must outlive their use."""
+        if events is None:
+            self._check(lib().qed_set_step_events(self.h, None), "qed_set_step_events")
+            return
+        for e in events:   # torch creates the HIP event on its first record
+            if not e.cuda_event:
+                e.record()
+        arr = (C.c_void_p * 4)(*[C.c_void_p(e.cuda_event) for e in events])
+        self._check(lib().qed_set_step_events(self.h, arr), "qed_set_step_events")
 
     def table_export(self, which: int) -> np.ndarray:
         n = lib().qed_table_size(which)

@@ -420,6 +420,20 @@ qed_status qed_table_export(qed_ctx_t *ctx, int which, double *host, int64_t n) 
     return e == hipSuccess ? QED_OK : hip_fail(ctx, e, "qed_table_export");
 }
 
+qed_status qed_set_step_events(qed_ctx_t *ctx, const hipEvent_t *ev) {
+    if (!ctx) return QED_EARG;
+    if (!ev) {
+        ctx->step_ev_on = 0;
+        return QED_OK;
+    }
+    for (int k = 0; k < 4; ++k) {
+        if (!ev[k]) return fail(ctx, QED_EARG, "qed_set_step_events: event %d is NULL", k);
+        ctx->step_ev[k] = ev[k];
+    }
+    ctx->step_ev_on = 1;
+    return QED_OK;
+}
+
 const char *qed_last_error(const qed_ctx_t *ctx) { return ctx ? ctx->err : "null context"; }
 
 }  // extern "C"

@@ -138,6 +138,8 @@ struct qed_ctx {
     int nseg_cap, nseg_dev;            // capacity and size of the uploaded list
     hipEvent_t seg_copied;             // completion of the last upload
     int64_t max_tiles;
+    hipEvent_t step_ev[4];             // optional timing events of the NCS launches
+    int step_ev_on;
     char err[256];
 };
 

@@ -577,17 +577,20 @@ static hipError_t launch_scan(qed_ctx *ctx, const int64_t *in_count, int64_t in_
 // from E6, no field evaluation)
 template <class T, bool PUSH, int FK>
 static hipError_t launch_ncs(qed_ctx *ctx, const LeptonArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL((k_leptons_decide<T, PUSH, FK>), dim3(tiles_grid(a.L.capacity)), dim3(BLOCK), 0, s, a);
-    hipError_t e = hipGetLastError();
+    auto mark = [&](int k) { return ctx->step_ev_on ? hipEventRecord(ctx->step_ev[k], s) : hipSuccess; };
+    hipError_t e = mark(0);
     if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_leptons_decide<T, PUSH, FK>), dim3(tiles_grid(a.L.capacity)), dim3(BLOCK), 0, s, a);
+    if ((e = hipGetLastError()) != hipSuccess || (e = mark(1)) != hipSuccess) return e;
     e = launch_scan(ctx, a.L.count, a.L.capacity, ctx->group_tot, 1, BLOCK * EV_GROUP,
                     a.has_out ? a.out.count : nullptr, a.has_out ? a.out.capacity : 0, nullptr, 0, 1, s);
-    if (e != hipSuccess) return e;
+    if (e != hipSuccess || (e = mark(2)) != hipSuccess) return e;
     // one wavefront per group of tiles of the list capacity
     const int64_t groups = ((a.L.capacity + BLOCK - 1) / BLOCK + EV_GROUP - 1) / EV_GROUP;
     const int ge = (int)((groups + BLOCK / 64 - 1) / (BLOCK / 64));
     hipLaunchKernelGGL(k_leptons_events<T>, dim3(ge < 1 ? 1 : ge), dim3(BLOCK), 0, s, a);
-    return hipGetLastError();
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return mark(3);
 }
 
 template <class T, bool M>

@@ -351,6 +351,34 @@ def test_gathered_fields_both_precisions(kind):
         assert err < tol, (prec, err)
 
 
+def test_step_events_bracket_the_launches():
+    """qed_set_step_events: the four events bracket decide, scan and event kernel in order,
+    and switching them off leaves the results unchanged (bitwise)."""
+    _say("step events")
+    cfg = W.c2(5000, start_step=2450)
+    out = []
+    for timed in (False, True):
+        ctx = _ctx(cfg, precision=Q.QED_MIXED)
+        Lg = Q.Leptons.from_state(cfg["leptons"], precision=Q.QED_MIXED)
+        Gg = Q.Photons(20000, precision=Q.QED_MIXED)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        for s in range(2450, 2460):
+            if timed:
+                ctx.set_step_events(ev)
+            ctx.step_leptons(Q.whole(cfg["field"]), Lg, Gg, s)
+        torch.cuda.synchronize()
+        if timed:
+            ctx.set_step_events(None)
+            parts = [ev[k].elapsed_time(ev[k + 1]) for k in range(3)]
+            assert all(x >= 0 for x in parts)
+            assert abs(sum(parts) - ev[0].elapsed_time(ev[3])) < 1e-3 + 1e-6 * sum(parts)
+        out.append((Lg.to_numpy(), Gg.to_numpy()))
+    for k in out[0][0]:
+        assert np.array_equal(out[0][0][k], out[1][0][k]), k
+    for k in out[0][1]:
+        assert np.array_equal(out[0][1][k], out[1][1][k]), k
+
+
 # ----------------------------------------------------------------------------- full size
 def _sampled_full_size(precision):
     cfg = W.c2(10_000_000, start_step=2500)
