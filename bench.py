@@ -69,6 +69,7 @@ def run_gpu(prec, cfg, steps, warmup, torch, Q, per_launch_events=True):
     G = Q.Photons(cap, precision=precision)
     segs = Q.whole(cfg["field"])
     s0 = cfg["start_step"]
+    tuning = ctx.autotune(segs, L, s0, reps=2)
     for s in range(s0, s0 + warmup):
         ctx.step_leptons(segs, L, G, s)
     torch.cuda.synchronize()
@@ -93,7 +94,7 @@ def run_gpu(prec, cfg, steps, warmup, torch, Q, per_launch_events=True):
         kern = {"step": [e[0].elapsed_time(e[3]) for e in ev], "decide": [e[0].elapsed_time(e[1]) for e in ev],
                 "scan": [e[1].elapsed_time(e[2]) for e in ev], "events": [e[2].elapsed_time(e[3]) for e in ev]}
     status = ctx.read_status()
-    return {"ctx": ctx, "L": L, "G": G, "wall": wall, "kern_ms": kern, "n": n,
+    return {"ctx": ctx, "L": L, "G": G, "wall": wall, "kern_ms": kern, "n": n, "tuning": tuning,
             "photons_timed": G.count - n_before, "photons_total": G.count, "photon_start": n_before,
             "status": status}
 
@@ -177,6 +178,81 @@ def error_metrics(a, b, gamma0, torch):
     return out
 
 
+class _Cat:
+    """Concatenated view of several lepton lists (for the error metrics)."""
+
+    def __init__(self, lists, torch):
+        for k in ("x", "y", "z", "px", "py", "pz", "sx", "sy", "sz"):
+            setattr(self, k, torch.cat([getattr(L, k)[:L.count] for L in lists]))
+
+
+def run_batched(args, torch, Q, W):
+    """Many collisions (64, log-uniform 1e3..2e6 electrons, own laser each) in one list:
+    autotuned launch shape, K steps captured in a hipGraph with a device step counter and
+    replayed; against the same collisions stepped one at a time in plain FP64."""
+    start = 100
+    cfg = W.c4(start_step=start)
+    n = len(cfg["leptons"]["x"])
+    K = 10
+    reps = max(1, args.batch_steps // K)
+    steps = K * reps
+    cap = int(n * 0.04 * (steps + 2)) + 100_000
+    segs = Q.segments(cfg["segments"])
+    # batched, mixed precision, graph-replayed
+    ctx = Q.Context(dt=cfg["dt"], procs=cfg["procs"], seed=cfg["seed"], id_start=cfg["next_id"], precision=Q.QED_MIXED)
+    L = Q.Leptons.from_state(cfg["leptons"], precision=Q.QED_MIXED)
+    G = Q.Photons(cap, precision=Q.QED_MIXED)
+    tuning = ctx.autotune(segs, L, start, reps=2)
+    ctx.step_leptons(segs, L, G, start)   # eager step: staging sized, segments uploaded
+    counter = torch.zeros(1, dtype=torch.int64, device="cuda")
+    torch.cuda.synchronize()
+    ctx.set_step_counter(counter)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for _ in range(K):
+            ctx.step_leptons(segs, L, G, start + 1)
+            ctx.advance_step(1)
+    torch.cuda.synchronize()
+    n0 = G.count
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        g.replay()
+    torch.cuda.synchronize()
+    wall_b = time.perf_counter() - t0
+    ctx.set_step_counter(None)
+    status_b = ctx.read_status()
+    # one collision at a time, FP64, eager
+    ctx64 = Q.Context(dt=cfg["dt"], procs=cfg["procs"], seed=cfg["seed"], id_start=cfg["next_id"], precision=Q.QED_FP64)
+    lists, fsegs = [], []
+    for (b, e, spec) in cfg["segments"]:
+        lists.append(Q.Leptons.from_state({k: v[b:e] for k, v in cfg["leptons"].items()}, precision=Q.QED_FP64))
+        fsegs.append(Q.whole(spec))
+    G64 = Q.Photons(cap, precision=Q.QED_FP64)
+    for Lk, sk in zip(lists, fsegs):
+        ctx64.step_leptons(sk, Lk, G64, start)
+    torch.cuda.synchronize()
+    m0 = G64.count
+    t0 = time.perf_counter()
+    for s in range(start + 1, start + 1 + steps):
+        for Lk, sk in zip(lists, fsegs):
+            ctx64.step_leptons(sk, Lk, G64, s)
+    torch.cuda.synchronize()
+    wall_1 = time.perf_counter() - t0
+    a = {"L": _Cat(lists, torch), "G": G64, "n": n, "photon_start": m0}
+    b = {"L": L, "G": G, "n": n, "photon_start": n0}
+    err = error_metrics(a, b, 5000.0, torch)
+    return {"workload": f"{len(cfg['sizes'])} collisions, {n} electrons (log-uniform 1e3..2e6 each), plane-wave "
+                        f"sin^2 8-cycle lasers, a0 U(10,200), gamma0 U(500,5000), LP/CP; dt = T0/400, steps "
+                        f"{start + 1}..{start + steps}",
+            "electrons": n, "steps": steps, "graph_steps_per_replay": K, "tuning": tuning,
+            "batched_graph_mixed": {"value": n * steps / wall_b, "ms_per_step": 1e3 * wall_b / steps,
+                                    "status_bits": status_b},
+            "one_by_one_fp64": {"value": n * steps / wall_1, "ms_per_step": 1e3 * wall_1 / steps,
+                                "launches_per_step": 3 * len(lists)},
+            "speedup": wall_1 / wall_b, "error_vs_fp64": err,
+            "photons_per_step": (G.count - n0) / steps}
+
+
 def cpu_baseline(cfg_small, budget_s=15.0):
     """The oracle as it stands (single-threaded C, FP64 tables) on a bounded sample of the
     same workload: the first `n` electrons of the bunch, stepped until the budget is used."""
@@ -215,6 +291,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--batch-steps", type=int, default=50,
+                    help="steps of the many-collision batching comparison (0: skip it)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device to device three times (a plain copy kernel of known size, "
                          "the reference for the HBM byte counters)")
@@ -278,7 +356,7 @@ def main():
                    "start_step": start, "processes": "NCS + spin flip + photon Stokes"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": tr,
-                     "kernel": "k_leptons_decide<float, push, gauss>",
+                     "kernel": "k_leptons_decide<float, push, gauss>", "tuning": mixed["tuning"],
                      "avg_launch_ms": km["decide"], "algorithmic_bytes_per_launch": alg_bytes,
                      "copy_probe_GBs": copy_gbs, "frac_of_copy_probe": achieved / copy_gbs,
                      "step_ms": {"decide": km["decide"], "scan": km["scan"], "events": km["events"],
@@ -295,6 +373,9 @@ def main():
                           "status_bits": fp64["status"]}
         result["speedup_mixed_over_fp64"] = result["value"] / result["fp64"]["value"]
         result["error_vs_fp64"] = error_metrics(fp64, mixed, 2000.0, torch)
+    if args.batch_steps > 0:
+        print("[bench] batching: many collisions, graph-replayed, vs one at a time in FP64", file=sys.stderr, flush=True)
+        result["batched"] = run_batched(args, torch, Q, W)
     if not args.no_cpu_baseline:
         small = W.c2(args.cpu_sample, start_step=start + args.warmup)
         result["cpu_baseline"] = cpu_baseline(small, args.cpu_budget)

@@ -47,6 +47,15 @@ typedef struct ihipStream_t *hipStream_t;
 /* opaque context: device tables, constants, id counter, status word, scan state */
 typedef struct qed_ctx qed_ctx_t;
 
+/* Launch shape of the lepton step (decide / scan / event kernels).  Every choice gives
+ * bitwise the same results; only the speed differs.  Default {0, 0, 8}.               */
+typedef struct {
+    int32_t blocks_per_cu;   /* 0: one block per 256-lepton tile; k > 0: a persistent grid
+                                of k blocks per compute unit sweeping the tiles            */
+    int32_t rate_lds;        /* 1: each decide block stages the NCS rate table in LDS     */
+    int32_t ev_group;        /* tiles per wavefront of the event kernel: 4, 8 or 16       */
+} qed_tuning;
+
 typedef enum { QED_OK = 0, QED_EARG = 1, QED_ENOMEM = 2, QED_EHIP = 3, QED_ESTATE = 4 } qed_status;
 typedef enum { QED_FP64 = 0, QED_MIXED = 1 } qed_precision;
 
@@ -189,6 +198,25 @@ qed_status qed_table_export(qed_ctx_t *ctx, int which, double *host_out, int64_t
  * events belong to the caller (created with hipEventCreate, alive while set); the array
  * is copied.  NULL switches the recording off.                                         */
 qed_status qed_set_step_events(qed_ctx_t *ctx, const hipEvent_t *ev);
+/* Batching and graph capture (many collisions as segments of one list, step loops
+ * captured in a hipGraph).  With a device step counter registered, every later call uses
+ * step + *dev_step as its step number, so one captured sequence of calls can be replayed
+ * for consecutive steps; qed_advance_step adds `by` to the counter on the stream (a kernel,
+ * capturable).  dev_step is caller-owned device memory (one int64); NULL unregisters.
+ * Calls stay capturable as long as they do not grow the staging area or upload a new
+ * segment list: make one call with the same list sizes and segments before capturing.  */
+qed_status qed_set_step_counter(qed_ctx_t *ctx, int64_t *dev_step);
+qed_status qed_advance_step(qed_ctx_t *ctx, int64_t by, hipStream_t stream);
+/* Current launch shape / set one (rejects unknown values). */
+qed_status qed_get_tuning(qed_ctx_t *ctx, qed_tuning *out);
+qed_status qed_set_tuning(qed_ctx_t *ctx, const qed_tuning *t);
+/* Autotuner: times every launch shape on a copy of `p` (its first *count leptons, step
+ * `step`, photons to a scratch list), `reps` times each, keeps the fastest for this
+ * context and returns it in `chosen` (may be NULL).  Leaves p, the id counter and the
+ * status word as they were.  Synchronises, allocates and frees scratch memory: call it
+ * outside graph capture, typically once per workload.                                  */
+qed_status qed_autotune(qed_ctx_t *ctx, const qed_segment *segs, int nseg, const qed_leptons *p,
+                        int64_t step, int reps, qed_tuning *chosen, hipStream_t stream);
 /* Last argument / HIP error of this context as text (empty if none). */
 const char *qed_last_error(const qed_ctx_t *ctx);
 

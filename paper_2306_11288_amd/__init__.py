@@ -23,7 +23,8 @@ TAB_BESSEL, TAB_NCS_RATE, TAB_NCS_CDF, TAB_NBW_RATE, TAB_NBW_CDF, TAB_VB = range
 EXPORTED = ["qed_init_tables", "qed_destroy", "qed_gather", "qed_push_spin", "qed_emit", "qed_step_leptons",
             "qed_birefringence", "qed_pair", "qed_step_photons", "qed_compact_photons", "qed_read_status",
             "qed_clear_status", "qed_get_next_id", "qed_set_next_id", "qed_table_size", "qed_table_export",
-            "qed_set_step_events", "qed_last_error"]
+            "qed_set_step_events", "qed_set_step_counter", "qed_advance_step", "qed_get_tuning",
+            "qed_set_tuning", "qed_autotune", "qed_last_error"]
 
 ALPHA = 1.0 / 137.035999084
 XI_L = 2.42631023867e-6
@@ -51,6 +52,13 @@ class Field(C.Structure):
 
 class Segment(C.Structure):
     _fields_ = [("begin", C.c_int64), ("end", C.c_int64), ("field", Field)]
+
+
+class Tuning(C.Structure):
+    _fields_ = [("blocks_per_cu", C.c_int32), ("rate_lds", C.c_int32), ("ev_group", C.c_int32)]
+
+    def as_dict(self):
+        return {"blocks_per_cu": self.blocks_per_cu, "rate_lds": self.rate_lds, "ev_group": self.ev_group}
 
 
 class CLeptons(C.Structure):
@@ -92,6 +100,11 @@ def lib():
             "qed_set_next_id": [vp, C.c_uint64, vp],
             "qed_table_export": [vp, C.c_int, vp, i64],
             "qed_set_step_events": [vp, vp],
+            "qed_set_step_counter": [vp, vp],
+            "qed_advance_step": [vp, i64, vp],
+            "qed_get_tuning": [vp, vp],
+            "qed_set_tuning": [vp, vp],
+            "qed_autotune": [vp, vp, C.c_int, vp, i64, C.c_int, vp, vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -344,6 +357,34 @@ class Context:
 
     def set_next_id(self, v: int, stream=None):
         self._check(lib().qed_set_next_id(self.h, int(v), _stream(stream)), "qed_set_next_id")
+
+    def set_step_counter(self, counter=None):
+        """Register a device int64 tensor (one element) whose value is added to the step of
+        every later call (None unregisters); see advance_step."""
+        if counter is not None:
+            assert counter.dtype == _torch().int64 and counter.is_cuda and counter.numel() == 1
+        self._counter = counter
+        self._check(lib().qed_set_step_counter(self.h, _ptr(counter) if counter is not None else None),
+                    "qed_set_step_counter")
+
+    def advance_step(self, by: int = 1, stream=None):
+        self._check(lib().qed_advance_step(self.h, int(by), _stream(stream)), "qed_advance_step")
+
+    def get_tuning(self) -> dict:
+        t = Tuning()
+        self._check(lib().qed_get_tuning(self.h, C.byref(t)), "qed_get_tuning")
+        return t.as_dict()
+
+    def set_tuning(self, blocks_per_cu: int = 0, rate_lds: int = 0, ev_group: int = 8):
+        t = Tuning(blocks_per_cu, rate_lds, ev_group)
+        self._check(lib().qed_set_tuning(self.h, C.byref(t)), "qed_set_tuning")
+
+    def autotune(self, segs, L: Leptons, step: int, reps: int = 3, stream=None) -> dict:
+        arr, n = segs
+        t = Tuning()
+        self._check(lib().qed_autotune(self.h, arr, n, C.byref(L.c()), step, reps, C.byref(t), _stream(stream)),
+                    "qed_autotune")
+        return t.as_dict()
 
     def set_step_events(self, events=None):
         """Record four torch.cuda.Event around the decide / scan / event kernels of every

@@ -14,7 +14,7 @@ using namespace qed;
 namespace {
 
 constexpr int64_t MAX_TILES = 1 << 20;   // ordered-append tiles: lists up to 2^28 particles
-constexpr int64_t GROUP_TOT_LEN = MAX_TILES / EV_GROUP + 1;
+constexpr int64_t GROUP_TOT_LEN = MAX_TILES / 4 + 1;   // the smallest event group is 4 tiles
 
 qed_status fail(qed_ctx *ctx, qed_status code, const char *fmt, ...) {
     if (ctx) {
@@ -230,6 +230,10 @@ qed_status qed_init_tables(qed_ctx_t **out, const qed_config *cfg, hipStream_t s
         return QED_EHIP;
     }
     c->max_tiles = MAX_TILES;
+    c->tune = {0, 0, 8};
+    if (hipDeviceGetAttribute(&c->num_cu, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess ||
+        c->num_cu < 1)
+        c->num_cu = 1;
     const bool ok = hipMalloc(&c->tab64, TAB_TOTAL * sizeof(double)) == hipSuccess &&
                     hipMalloc(&c->tab32, TAB_TOTAL * sizeof(float)) == hipSuccess &&
                     hipMalloc(&c->status, sizeof(uint32_t)) == hipSuccess &&
@@ -418,6 +422,145 @@ qed_status qed_table_export(qed_ctx_t *ctx, int which, double *host, int64_t n) 
             for (int64_t i = 0; i < len; ++i) host[c * len + i] = tmp[stride * i + c];
     delete[] tmp;
     return e == hipSuccess ? QED_OK : hip_fail(ctx, e, "qed_table_export");
+}
+
+qed_status qed_set_step_counter(qed_ctx_t *ctx, int64_t *dev_step) {
+    if (!ctx) return QED_EARG;
+    ctx->step_dev = dev_step;
+    return QED_OK;
+}
+
+qed_status qed_advance_step(qed_ctx_t *ctx, int64_t by, hipStream_t s) {
+    qed_status st = ready(ctx);
+    if (st != QED_OK) return st;
+    if (!ctx->step_dev) return fail(ctx, QED_ESTATE, "qed_advance_step: no device step counter registered");
+    return launched(ctx, launch_advance_step(ctx->step_dev, by, s), "qed_advance_step");
+}
+
+qed_status qed_get_tuning(qed_ctx_t *ctx, qed_tuning *out) {
+    if (!ctx || !out) return QED_EARG;
+    *out = ctx->tune;
+    return QED_OK;
+}
+
+qed_status qed_set_tuning(qed_ctx_t *ctx, const qed_tuning *t) {
+    if (!ctx || !t) return QED_EARG;
+    if (t->blocks_per_cu < 0 || t->blocks_per_cu > 64)
+        return fail(ctx, QED_EARG, "tuning: blocks_per_cu %d outside [0, 64]", t->blocks_per_cu);
+    if (t->rate_lds != 0 && t->rate_lds != 1) return fail(ctx, QED_EARG, "tuning: rate_lds must be 0 or 1");
+    if (t->ev_group != 4 && t->ev_group != 8 && t->ev_group != 16)
+        return fail(ctx, QED_EARG, "tuning: ev_group must be 4, 8 or 16");
+    ctx->tune = *t;
+    return QED_OK;
+}
+
+qed_status qed_autotune(qed_ctx_t *ctx, const qed_segment *segs, int nseg, const qed_leptons *p, int64_t step,
+                        int reps, qed_tuning *chosen, hipStream_t s) {
+    qed_status st = ready(ctx);
+    if (st != QED_OK) return st;
+    if (reps < 1 || reps > 100) return fail(ctx, QED_EARG, "qed_autotune: reps must be in [1, 100]");
+    if ((st = check_leptons(ctx, p, "leptons")) != QED_OK) return st;
+    SegArgs sa{};
+    if ((st = seg_args(ctx, segs, nseg, sa, s)) != QED_OK) return st;
+    if (!(ctx->cfg.procs & QED_PROC_NCS)) {   // nothing to tune: the step is a push
+        if (chosen) *chosen = ctx->tune;
+        return QED_OK;
+    }
+    int64_t n = 0;
+    hipError_t e = hipMemcpyAsync(&n, p->count, sizeof n, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "qed_autotune");
+    n = n < 0 ? 0 : (n > p->capacity ? p->capacity : n);
+    if (n == 0) {
+        if (chosen) *chosen = ctx->tune;
+        return QED_OK;
+    }
+    if ((st = ensure_staging(ctx, n)) != QED_OK) return st;
+    const bool mixed = ctx->cfg.precision == QED_MIXED;
+    const size_t sb = mixed ? sizeof(float) : sizeof(double);
+    // scratch: a copy of the leptons (11 arrays), a photon list of n (14 arrays), two
+    // counts, the saved id counter and status word; every piece 256-byte aligned
+    const size_t nb = (size_t)n;
+    auto al = [](size_t bytes) { return (bytes + 255) / 256 * 256; };
+    const size_t need = 14 * al(nb * 8) + 3 * al(nb * sb) + 6 * al(nb * sb) + 2 * al(nb * 8) + al(nb) + 4 * al(8);
+    void *buf = nullptr;
+    if (hipMalloc(&buf, need) != hipSuccess) return fail(ctx, QED_ENOMEM, "qed_autotune: scratch of %zu bytes", need);
+    char *q = (char *)buf;
+    auto take = [&](size_t bytes) { char *r = q; q += al(bytes); return (void *)r; };
+    qed_leptons L = *p;
+    L.capacity = n;
+    double **ld[7] = {&L.x, &L.y, &L.z, &L.px, &L.py, &L.pz, &L.w};
+    const double *ls[7] = {p->x, p->y, p->z, p->px, p->py, p->pz, p->w};
+    void **lsp[3] = {&L.sx, &L.sy, &L.sz};
+    const void *lss[3] = {p->sx, p->sy, p->sz};
+    for (int k = 0; k < 7; ++k) *ld[k] = (double *)take(nb * 8);
+    for (int k = 0; k < 3; ++k) *lsp[k] = take(nb * sb);
+    L.id = (uint64_t *)take(nb * 8);
+    qed_photons G{};
+    G.x = (double *)take(nb * 8); G.y = (double *)take(nb * 8); G.z = (double *)take(nb * 8);
+    G.kx = (double *)take(nb * 8); G.ky = (double *)take(nb * 8); G.kz = (double *)take(nb * 8);
+    G.w = (double *)take(nb * 8);
+    G.xi1 = take(nb * sb); G.xi2 = take(nb * sb); G.xi3 = take(nb * sb);
+    G.e1x = take(nb * sb); G.e1y = take(nb * sb); G.e1z = take(nb * sb);
+    G.id = (uint64_t *)take(nb * 8);
+    G.alive = (uint8_t *)take(nb);
+    G.capacity = (int64_t)nb;
+    L.count = (int64_t *)take(8);
+    G.count = (int64_t *)take(8);
+    unsigned long long *saved_id = (unsigned long long *)take(8);
+    uint32_t *saved_st = (uint32_t *)take(8);
+
+    e = hipMemcpyAsync(saved_id, ctx->next_id, 8, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(saved_st, ctx->status, 4, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(L.count, p->count, 8, hipMemcpyDeviceToDevice, s);
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    if (e == hipSuccess) e = hipEventCreate(&t0);
+    if (e == hipSuccess) e = hipEventCreate(&t1);
+    const qed_tuning keep = ctx->tune;
+    const int ev_on = ctx->step_ev_on;
+    ctx->step_ev_on = 0;
+    qed_tuning best = keep;
+    float best_ms = 3.0e38f;
+    const int bpc[4] = {0, 2, 4, 8}, grp[3] = {4, 8, 16};
+    for (int ib = 0; ib < 4 && e == hipSuccess; ++ib)
+        for (int lds = 0; lds < 2 && e == hipSuccess; ++lds)
+            for (int ig = 0; ig < 3 && e == hipSuccess; ++ig) {
+                ctx->tune = {bpc[ib], lds, grp[ig]};
+                float cand = 3.0e38f;
+                for (int r = 0; r < reps && e == hipSuccess; ++r) {
+                    for (int k = 0; k < 7 && e == hipSuccess; ++k)
+                        e = hipMemcpyAsync(*ld[k], ls[k], nb * 8, hipMemcpyDeviceToDevice, s);
+                    for (int k = 0; k < 3 && e == hipSuccess; ++k)
+                        e = hipMemcpyAsync(*lsp[k], lss[k], nb * sb, hipMemcpyDeviceToDevice, s);
+                    if (e == hipSuccess) e = hipMemcpyAsync(L.id, p->id, nb * 8, hipMemcpyDeviceToDevice, s);
+                    if (e == hipSuccess) e = hipMemsetAsync(G.count, 0, 8, s);
+                    if (e == hipSuccess) e = hipEventRecord(t0, s);
+                    if (e == hipSuccess) e = launch_leptons(ctx, LM_FUSED, sa, L, nullptr, &G, step, s);
+                    if (e == hipSuccess) e = hipEventRecord(t1, s);
+                    if (e == hipSuccess) e = hipEventSynchronize(t1);
+                    float ms = 0;
+                    if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+                    if (e == hipSuccess && ms < cand) cand = ms;
+                }
+                if (e == hipSuccess && cand < best_ms) {
+                    best_ms = cand;
+                    best = ctx->tune;
+                }
+            }
+    if (e == hipSuccess) e = hipMemcpyAsync(ctx->next_id, saved_id, 8, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(ctx->status, saved_st, 4, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (t0) hipEventDestroy(t0);
+    if (t1) hipEventDestroy(t1);
+    hipFree(buf);
+    ctx->step_ev_on = ev_on;
+    if (e != hipSuccess) {
+        ctx->tune = keep;
+        return hip_fail(ctx, e, "qed_autotune");
+    }
+    ctx->tune = best;
+    if (chosen) *chosen = best;
+    return QED_OK;
 }
 
 qed_status qed_set_step_events(qed_ctx_t *ctx, const hipEvent_t *ev) {

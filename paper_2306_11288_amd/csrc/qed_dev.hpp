@@ -294,15 +294,15 @@ __device__ __forceinline__ void bessel_scaled(const Tabs<T> &tb, T x, T &I, T &K
     K2 = b2;
 }
 
+// r: the NCS rate table (global memory, or a copy staged in LDS)
 template <class T>
-__device__ __forceinline__ void ncs_rate(const Tabs<T> &tb, double chi, T &Ia, T &Ib, uint32_t &st) {
+__device__ __forceinline__ void ncs_rate(const T *r, double chi, T &Ia, T &Ib, uint32_t &st) {
     if (!(chi > 0.0)) {
         Ia = 0;
         Ib = 0;
         return;
     }
     const T c = (T)chi, l = lnx(c);
-    const T *r = tb.ncs_rate();
     if (l < (T)R_LO) {
         Ia = r[0] * c;
         Ib = r[1] * (c / (T)1e-6) * Ia;
@@ -474,9 +474,9 @@ struct NcsFrame {
     V3<T> n, a, b;
     T s, Ia, Ib;
 };
-// ig = 1/gamma = 1/sqrt(1 + |p|^2), computed by the caller.
+// ig = 1/gamma = 1/sqrt(1 + |p|^2), computed by the caller; rate = the NCS rate table.
 template <class T>
-__device__ __forceinline__ bool ncs_frame(const Consts &c, const Tabs<T> &tb, double q, const V3<double> &p,
+__device__ __forceinline__ bool ncs_frame(const Consts &c, const T *rate, double q, const V3<double> &p,
                                           double ig, const V3<T> &S, const V3<double> &E, const V3<double> &B,
                                           uint32_t &st, NcsFrame<T> &f) {
     const double pp2 = dot(p, p), g = (1.0 + pp2) * ig;
@@ -493,7 +493,7 @@ __device__ __forceinline__ bool ncs_frame(const Consts &c, const Tabs<T> &tb, do
     f.a = cvt<T>(rsqrt(a2) * ad);
     f.b = cross(f.n, f.a);
     f.s = dot(S, f.b);
-    ncs_rate<T>(tb, f.chi, f.Ia, f.Ib, st);
+    ncs_rate<T>(rate, f.chi, f.Ia, f.Ib, st);
     f.C = c.c_ncs * ig;
     f.W = f.C * (double)f.Ia;
     f.Wt = f.C * ((double)f.Ia - (double)f.s * (double)f.Ib);

@@ -111,7 +111,7 @@ struct SegArgs {
 FieldDev field_dev(const qed_field &f);   // host: derived constants of a field
 
 constexpr int BLOCK = 256;             // threads per block = particles per tile
-constexpr int EV_GROUP = 8;            // lepton step: tiles per group (one wavefront of the event kernel)
+constexpr int EV_GROUP_MAX = 16;       // lepton step: largest tiles-per-group of the event kernel
 
 // bytes of one staging slot: the largest record any kernel parks there
 constexpr size_t STAGING_SLOT = sizeof(LepEvent<double>) > sizeof(EventRec) ? sizeof(LepEvent<double>)
@@ -140,6 +140,9 @@ struct qed_ctx {
     int64_t max_tiles;
     hipEvent_t step_ev[4];             // optional timing events of the NCS launches
     int step_ev_on;
+    int64_t *step_dev;                 // optional device step counter (caller-owned)
+    int num_cu;                        // compute units of the device
+    qed_tuning tune;                   // launch shape of the lepton step (qed_autotune)
     char err[256];
 };
 
@@ -154,4 +157,5 @@ enum PhotonMode { PM_BIREF = 0, PM_PAIR = 1, PM_FULL = 2 };
 hipError_t launch_photons(qed_ctx *ctx, PhotonMode mode, const SegArgs &sa, const qed_photons &G,
                           const qed_leptons *em, const qed_leptons *ep, int64_t step, hipStream_t s);
 hipError_t launch_compact(qed_ctx *ctx, const qed_photons &in, const qed_photons &out, hipStream_t s);
+hipError_t launch_advance_step(int64_t *step, int64_t by, hipStream_t s);
 }  // namespace qed

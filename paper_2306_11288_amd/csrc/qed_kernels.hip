@@ -17,6 +17,12 @@
 
 namespace qed {
 
+// step number of a launch: the argument plus the optional device counter
+template <class A>
+__device__ __forceinline__ int64_t step_of(const A &a) {
+    return a.step + (a.step_dev ? *a.step_dev : 0);
+}
+
 // element of an array at a 32-bit byte offset
 template <class T>
 __device__ __forceinline__ T &at(T *base, uint32_t off) {
@@ -174,10 +180,12 @@ struct LeptonArgs {
     int has_out;
     double *E6;
     int64_t step;
+    const int64_t *step_dev;   // optional device step counter, added to step
     uint32_t *status;
     void *stg;
     int *tile_counts;
     int *group_tot;
+    int ev_group;              // tiles per event group
     const int64_t *tile_off;
     const int64_t *launch;
 };
@@ -200,7 +208,7 @@ __device__ __forceinline__ double push_one(const LeptonArgs &a, double q, double
 template <class T, bool WRITE_E6, bool PUSH, bool E6_IN, bool MULTI>
 __global__ __launch_bounds__(BLOCK) void k_leptons_simple(LeptonArgs a) {
     const int64_t n = clamp_count(a.L.count, a.L.capacity);
-    const double dt = a.c.dt, t = (double)a.step * dt, q = (double)a.L.charge;
+    const double dt = a.c.dt, t = (double)step_of(a) * dt, q = (double)a.L.charge;
     T *sx = (T *)a.L.sx, *sy = (T *)a.L.sy, *sz = (T *)a.L.sz;
     uint32_t st = 0;
     for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK) {
@@ -263,93 +271,108 @@ __device__ __forceinline__ void store_s(const LeptonArgs &a, uint32_t os, const 
     at((T *)a.L.sx, os) = S.x; at((T *)a.L.sy, os) = S.y; at((T *)a.L.sz, os) = S.z;
 }
 
-// Decide (lepton step with NCS), one thread per particle, one BLOCK-particle tile per
-// block: gather, push, T-BMT, local frame, rates, event test.  Every particle writes back
-// x^{n+1}, p^{n+1/2} and its spin (after the no-emission update when nothing happened).
-// Event particles also park their state in a LepEvent record at their tile's staging
-// slot tile*BLOCK + rank (rank in index order: wave ballot + popcount, waves combined in
-// LDS); the tile's event count goes to tile_counts and is added to its group's total
-// (integer atomics: the sum does not depend on their order).
-template <class T, bool PUSH, int FK>
+// Decide (lepton step with NCS), one thread per particle, BLOCK-particle tiles; a block
+// takes tiles blockIdx.x, blockIdx.x + gridDim.x, ... (one tile per block when the grid
+// covers the list, a persistent sweep when the grid is a few blocks per CU): gather, push,
+// T-BMT, local frame, rates, event test.  Every particle writes back x^{n+1}, p^{n+1/2}
+// and its spin (after the no-emission update when nothing happened).  Event particles
+// also park their state in a LepEvent record at their tile's staging slot tile*BLOCK +
+// rank (rank in index order: wave ballot + popcount, waves combined in LDS); the tile's
+// event count goes to tile_counts and is added to its group's total (integer atomics: the
+// sum does not depend on their order).  RATE_LDS: the NCS rate table is staged in LDS
+// once per block instead of being read through the caches.
+template <class T, bool PUSH, int FK, bool RATE_LDS>
 __global__ __launch_bounds__(BLOCK) void k_leptons_decide(LeptonArgs a) {
-    __shared__ int s_wave[BLOCK / 64];
+    __shared__ int s_wave[2][BLOCK / 64];
+    __shared__ T s_rate[RATE_LDS ? 2 * NR : 1];
     const int64_t n = clamp_count(a.L.count, a.L.capacity);
-    const int64_t tile = blockIdx.x, base = tile * BLOCK;
-    if (base >= n) return;
+    const int64_t ntiles = (n + BLOCK - 1) / BLOCK;
+    if ((int64_t)blockIdx.x >= ntiles) return;
     const Tabs<T> tb = {(const T *)a.tab};
-    const double t = (double)a.step * a.c.dt, q = (double)a.L.charge;
-    const int64_t i = base + threadIdx.x;
+    const T *rate = tb.ncs_rate();
+    if constexpr (RATE_LDS) {
+        for (int k = threadIdx.x; k < 2 * NR; k += BLOCK) s_rate[k] = rate[k];
+        __syncthreads();
+        rate = s_rate;
+    }
+    const int64_t step = step_of(a);
+    const double t = (double)step * a.c.dt, q = (double)a.L.charge;
     uint32_t st = 0;
-    bool ev = false;
-    V3<double> r, p, E, B;
-    V3<T> S;
-    if (i < n) {
-        const double ig = lepton_state<T, PUSH, FK>(a, i, t, q, r, p, S, E, B, st);
-        if constexpr (PUSH) store_xp<T>(a, (uint32_t)i * 8u, r, p);
-        NcsFrame<T> f;
-        if (ncs_frame<T>(a.c, tb, q, p, ig, S, E, B, st, f)) {
-            double rr[4];
-            uniform4(at(a.L.id, (uint32_t)i * 8u), a.step, STREAM_NCS, a.c.seed, rr);
-            ev = rr[1] < f.P;
-            if (!ev) ncs_no_event<T>(a.c, f, S);
+    int par = 0;
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x, par ^= 1) {
+        const int64_t base = tile * BLOCK, i = base + threadIdx.x;
+        bool ev = false;
+        V3<double> r, p, E, B;
+        V3<T> S;
+        if (i < n) {
+            const double ig = lepton_state<T, PUSH, FK>(a, i, t, q, r, p, S, E, B, st);
+            if constexpr (PUSH) store_xp<T>(a, (uint32_t)i * 8u, r, p);
+            NcsFrame<T> f;
+            if (ncs_frame<T>(a.c, rate, q, p, ig, S, E, B, st, f)) {
+                double rr[4];
+                uniform4(at(a.L.id, (uint32_t)i * 8u), step, STREAM_NCS, a.c.seed, rr);
+                ev = rr[1] < f.P;
+                if (!ev) ncs_no_event<T>(a.c, f, S);
+            }
+            if (!ev) store_s<T>(a, (uint32_t)i * (uint32_t)sizeof(T), S);
         }
-        if (!ev) store_s<T>(a, (uint32_t)i * (uint32_t)sizeof(T), S);
-    }
-    int total;
-    const int rank = block_rank(ev, total, s_wave);
-    if (ev) {
-        LepEvent<T> &o = ((LepEvent<T> *)a.stg)[base + rank];
-        o.i = i;
-        o.id = at(a.L.id, (uint32_t)i * 8u);
-        o.w = at(a.L.w, (uint32_t)i * 8u);
-        o.r[0] = r.x; o.r[1] = r.y; o.r[2] = r.z;
-        o.p[0] = p.x; o.p[1] = p.y; o.p[2] = p.z;
-        o.E[0] = E.x; o.E[1] = E.y; o.E[2] = E.z;
-        o.B[0] = B.x; o.B[1] = B.y; o.B[2] = B.z;
-        o.S[0] = S.x; o.S[1] = S.y; o.S[2] = S.z;
-    }
-    if (threadIdx.x == 0) {
-        a.tile_counts[tile] = total;
-        if (total) atomicAdd(a.group_tot + tile / EV_GROUP, total);
+        int total;
+        const int rank = block_rank(ev, total, s_wave[par]);
+        if (ev) {
+            LepEvent<T> &o = ((LepEvent<T> *)a.stg)[base + rank];
+            o.i = i;
+            o.id = at(a.L.id, (uint32_t)i * 8u);
+            o.w = at(a.L.w, (uint32_t)i * 8u);
+            o.r[0] = r.x; o.r[1] = r.y; o.r[2] = r.z;
+            o.p[0] = p.x; o.p[1] = p.y; o.p[2] = p.z;
+            o.E[0] = E.x; o.E[1] = E.y; o.E[2] = E.z;
+            o.B[0] = B.x; o.B[1] = B.y; o.B[2] = B.z;
+            o.S[0] = S.x; o.S[1] = S.y; o.S[2] = S.z;
+        }
+        if (threadIdx.x == 0) {
+            a.tile_counts[tile] = total;
+            if (total) atomicAdd(a.group_tot + tile / a.ev_group, total);
+        }
     }
     if (st) atomicOr(a.status, st);
 }
 
-// Events of the last decide, after the scan.  One wavefront per group of EV_GROUP tiles:
-// the tile counts of the group are scanned across lanes, lane k takes the group's events
-// k, k + 64, ..., finds its tile and record, rebuilds the local frame from the parked
-// state, emits, and writes the photon straight to its ordered place: global rank = group
-// offset + rank in the group, id = id base + global rank.
-template <class T>
+// Events of the last decide, after the scan.  One wavefront per group of G tiles: the
+// tile counts of the group are scanned across lanes, lane k takes the group's events k,
+// k + 64, ..., finds its tile and record, rebuilds the local frame from the parked state,
+// emits, and writes the photon straight to its ordered place: global rank = group offset
+// + rank in the group, id = id base + global rank.
+template <class T, int G>
 __global__ __launch_bounds__(BLOCK) void k_leptons_events(LeptonArgs a) {
-    static_assert(EV_GROUP <= 64, "one group = at most one wave of tiles");
+    static_assert(G <= 64, "one group = at most one wave of tiles");
     const int64_t n = clamp_count(a.L.count, a.L.capacity);
     const int64_t ntiles = (n + BLOCK - 1) / BLOCK;
-    const int64_t ngroups = (ntiles + EV_GROUP - 1) / EV_GROUP;
+    const int64_t ngroups = (ntiles + G - 1) / G;
     const int64_t obase = a.launch[0], id0 = a.launch[2];
     const Tabs<T> tb = {(const T *)a.tab};
+    const int64_t step = step_of(a);
     const double q = (double)a.L.charge;
     const int lane = threadIdx.x & 63;
     uint32_t st = 0;
     const int64_t g = (int64_t)blockIdx.x * (BLOCK / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (g < ngroups) {
-        const int64_t c0 = g * EV_GROUP;
-        const int cnt = (lane < EV_GROUP && c0 + lane < ntiles) ? a.tile_counts[c0 + lane] : 0;
+        const int64_t c0 = g * G;
+        const int cnt = (lane < G && c0 + lane < ntiles) ? a.tile_counts[c0 + lane] : 0;
         int incl = cnt;   // inclusive scan of the tile counts over the lanes
 #pragma unroll
-        for (int d = 1; d < EV_GROUP; d <<= 1) {
+        for (int d = 1; d < G; d <<= 1) {
             const int v = __shfl_up(incl, d);
             incl += lane >= d ? v : 0;
         }
-        int pre[EV_GROUP];   // wave-uniform inclusive prefix per tile
+        int pre[G];   // wave-uniform inclusive prefix per tile
 #pragma unroll
-        for (int k = 0; k < EV_GROUP; ++k) pre[k] = __builtin_amdgcn_readlane(incl, k);
-        const int gtot = pre[EV_GROUP - 1];
+        for (int k = 0; k < G; ++k) pre[k] = __builtin_amdgcn_readlane(incl, k);
+        const int gtot = pre[G - 1];
         const int64_t goff = a.tile_off[g];
         for (int e = lane; e < gtot; e += 64) {
             int j = 0, below = 0;   // tile of event e and the events before that tile
 #pragma unroll
-            for (int k = 0; k < EV_GROUP - 1; ++k) {
+            for (int k = 0; k < G - 1; ++k) {
                 const bool past = pre[k] <= e;
                 j += past ? 1 : 0;
                 below = past ? pre[k] : below;
@@ -360,9 +383,9 @@ __global__ __launch_bounds__(BLOCK) void k_leptons_events(LeptonArgs a) {
             const V3<double> E = {o.E[0], o.E[1], o.E[2]}, B = {o.B[0], o.B[1], o.B[2]};
             V3<T> S = {o.S[0], o.S[1], o.S[2]};
             NcsFrame<T> f;
-            ncs_frame<T>(a.c, tb, q, p, rsqrt(1.0 + dot(p, p)), S, E, B, st, f);
+            ncs_frame<T>(a.c, tb.ncs_rate(), q, p, rsqrt(1.0 + dot(p, p)), S, E, B, st, f);
             double rr[4];
-            uniform4(o.id, a.step, STREAM_NCS, a.c.seed, rr);
+            uniform4(o.id, step, STREAM_NCS, a.c.seed, rr);
             NcsPhoton<T> ph;
             ncs_event<T>(a.c, tb, f, rr, p, S, ph);
             const uint32_t o8 = (uint32_t)i * 8u;
@@ -383,6 +406,11 @@ __global__ __launch_bounds__(BLOCK) void k_leptons_events(LeptonArgs a) {
     if (st) atomicOr(a.status, st);
 }
 
+// advance the device step counter
+__global__ void k_advance_step(int64_t *step, int64_t by) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *step += by;
+}
+
 // ------------------------------------------------------------------------- photons
 struct PhotonArgs {
     Consts c;
@@ -393,6 +421,7 @@ struct PhotonArgs {
     int has_em, has_ep;
     int do_vb, do_nbw, do_move;
     int64_t step;
+    const int64_t *step_dev;   // optional device step counter, added to step
     uint32_t *status;
     EventRec *stg;
     int *tile_counts;
@@ -407,7 +436,8 @@ __global__ __launch_bounds__(BLOCK) void k_photons_decide(PhotonArgs a) {
     const int64_t n = clamp_count(a.G.count, a.G.capacity);
     if (NBW && (int64_t)blockIdx.x * BLOCK >= n) return;
     const Tabs<T> tb = {(const T *)a.tab};
-    const double t = (double)a.step * a.c.dt;
+    const int64_t step = step_of(a);
+    const double t = (double)step * a.c.dt;
     T *xi1 = (T *)a.G.xi1, *xi2 = (T *)a.G.xi2, *xi3 = (T *)a.G.xi3;
     T *e1x = (T *)a.G.e1x, *e1y = (T *)a.G.e1y, *e1z = (T *)a.G.e1z;
     uint32_t st = 0;
@@ -426,7 +456,7 @@ __global__ __launch_bounds__(BLOCK) void k_photons_decide(PhotonArgs a) {
                 T Ja, kappa;
                 const double P = nbw_prob<T>(a.c, tb, eps, chi, xi.z, Ja, kappa, st);
                 double rr[4];
-                uniform4(a.G.id[j], a.step, STREAM_NBW, a.c.seed, rr);
+                uniform4(a.G.id[j], step, STREAM_NBW, a.c.seed, rr);
                 ev = Ja > (T)0 && rr[1] < P;
             }
             xi1[j] = xi.x; xi2[j] = xi.y; xi3[j] = xi.z;
@@ -472,7 +502,7 @@ __global__ __launch_bounds__(BLOCK) void k_photons_events(PhotonArgs a) {
         T Ja, kappa;
         nbw_prob<T>(a.c, tb, eps, chi, xi.z, Ja, kappa, st);
         double rr[4];
-        uniform4(a.G.id[j], a.step, STREAM_NBW, a.c.seed, rr);
+        uniform4(a.G.id[j], step_of(a), STREAM_NBW, a.c.seed, rr);
         PairOut<T> po;
         nbw_pair<T>(tb, k, chi, kappa, xi, e1, rr, st, po);
         const qed_leptons *Ls[2] = {&a.em, &a.ep};
@@ -575,21 +605,43 @@ static hipError_t launch_scan(qed_ctx *ctx, const int64_t *in_count, int64_t in_
 
 // decide + scan + events of a step with NCS; FK as in fields_for (PUSH = false: fields
 // from E6, no field evaluation)
+template <class T, int G>
+static hipError_t launch_events(const LeptonArgs &a, hipStream_t s) {
+    const int64_t groups = ((a.L.capacity + BLOCK - 1) / BLOCK + G - 1) / G;
+    const int64_t nb = (groups + BLOCK / 64 - 1) / (BLOCK / 64);
+    hipLaunchKernelGGL((k_leptons_events<T, G>), dim3(nb < 1 ? 1 : (int)nb), dim3(BLOCK), 0, s, a);
+    return hipGetLastError();
+}
+
+// decide + scan + events of a step with NCS; FK as in fields_for (PUSH = false: fields
+// from E6, no field evaluation).  The launch shape and the rate-table placement follow
+// the context's tuning (qed_autotune); every choice gives bitwise the same results.
 template <class T, bool PUSH, int FK>
-static hipError_t launch_ncs(qed_ctx *ctx, const LeptonArgs &a, hipStream_t s) {
+static hipError_t launch_ncs(qed_ctx *ctx, const LeptonArgs &a0, hipStream_t s) {
+    LeptonArgs a = a0;
+    a.ev_group = ctx->tune.ev_group;
     auto mark = [&](int k) { return ctx->step_ev_on ? hipEventRecord(ctx->step_ev[k], s) : hipSuccess; };
     hipError_t e = mark(0);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_leptons_decide<T, PUSH, FK>), dim3(tiles_grid(a.L.capacity)), dim3(BLOCK), 0, s, a);
+    const int64_t ntiles = (a.L.capacity + BLOCK - 1) / BLOCK;
+    int64_t grid = ntiles;
+    if (ctx->tune.blocks_per_cu > 0) {
+        const int64_t pg = (int64_t)ctx->tune.blocks_per_cu * ctx->num_cu;
+        grid = pg < ntiles ? pg : ntiles;
+    }
+    const dim3 gd((unsigned)(grid < 1 ? 1 : grid));
+    if (ctx->tune.rate_lds) hipLaunchKernelGGL((k_leptons_decide<T, PUSH, FK, true>), gd, dim3(BLOCK), 0, s, a);
+    else hipLaunchKernelGGL((k_leptons_decide<T, PUSH, FK, false>), gd, dim3(BLOCK), 0, s, a);
     if ((e = hipGetLastError()) != hipSuccess || (e = mark(1)) != hipSuccess) return e;
-    e = launch_scan(ctx, a.L.count, a.L.capacity, ctx->group_tot, 1, BLOCK * EV_GROUP,
+    e = launch_scan(ctx, a.L.count, a.L.capacity, ctx->group_tot, 1, BLOCK * a.ev_group,
                     a.has_out ? a.out.count : nullptr, a.has_out ? a.out.capacity : 0, nullptr, 0, 1, s);
     if (e != hipSuccess || (e = mark(2)) != hipSuccess) return e;
-    // one wavefront per group of tiles of the list capacity
-    const int64_t groups = ((a.L.capacity + BLOCK - 1) / BLOCK + EV_GROUP - 1) / EV_GROUP;
-    const int ge = (int)((groups + BLOCK / 64 - 1) / (BLOCK / 64));
-    hipLaunchKernelGGL(k_leptons_events<T>, dim3(ge < 1 ? 1 : ge), dim3(BLOCK), 0, s, a);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    switch (a.ev_group) {
+    case 4: e = launch_events<T, 4>(a, s); break;
+    case 16: e = launch_events<T, 16>(a, s); break;
+    default: e = launch_events<T, 8>(a, s); break;
+    }
+    if (e != hipSuccess) return e;
     return mark(3);
 }
 
@@ -633,12 +685,14 @@ hipError_t launch_leptons(qed_ctx *ctx, LeptonMode mode, const SegArgs &sa, cons
     if (out) a.out = *out;
     a.E6 = E6;
     a.step = step;
+    a.step_dev = ctx->step_dev;
     a.status = ctx->status;
     a.stg = (EventRec *)ctx->staging;
     a.tile_counts = ctx->tile_counts;
     a.group_tot = ctx->group_tot;
     a.tile_off = ctx->tile_off;
     a.launch = ctx->launch;
+    a.step_dev = ctx->step_dev;
     const bool multi = sa.nseg > 1;
     if (ctx->cfg.precision == QED_MIXED) {
         a.tab = ctx->tab32;
@@ -678,6 +732,7 @@ hipError_t launch_photons(qed_ctx *ctx, PhotonMode mode, const SegArgs &sa, cons
     a.do_nbw = (mode != PM_BIREF) && (ctx->cfg.procs & QED_PROC_NBW);
     a.do_move = mode != PM_BIREF;
     a.step = step;
+    a.step_dev = ctx->step_dev;
     a.status = ctx->status;
     a.stg = (EventRec *)ctx->staging;
     a.tile_counts = ctx->tile_counts;
@@ -689,6 +744,11 @@ hipError_t launch_photons(qed_ctx *ctx, PhotonMode mode, const SegArgs &sa, cons
     }
     a.tab = ctx->tab64;
     return launch_photons_t<double>(ctx, a, s);
+}
+
+hipError_t launch_advance_step(int64_t *step, int64_t by, hipStream_t s) {
+    hipLaunchKernelGGL(k_advance_step, dim3(1), dim3(64), 0, s, step, by);
+    return hipGetLastError();
 }
 
 hipError_t launch_compact(qed_ctx *ctx, const qed_photons &in, const qed_photons &out, hipStream_t s) {

@@ -131,6 +131,41 @@ def c3(n: int = 1_000_000, nx: int = 2048, ny: int = 512) -> dict:
     }
 
 
+def c4(n_collisions: int = 64, n_min: float = 1e3, n_max: float = 2e6, start_step: int = 0, seed: int = 4) -> dict:
+    """Batching: independent beam-laser collisions of uneven sizes, N_i = floor(10^U(log10
+    n_min, log10 n_max)) (log-uniform), a0 ~ U(10, 200), gamma0 ~ U(500, 5000) with 5 %
+    spread, linear or circular polarisation with probability 1/2, each a sin^2 plane-wave
+    pulse of 8 cycles at its own random polarisation angle; dt = T0/400, NCS with photon
+    Stokes.  The collisions are concatenated into one list (ids disjoint); `segments`
+    gives (begin, end, field) per collision.  At `start_step` every bunch centre sits at
+    the middle of its pulse (phase 8 pi)."""
+    dt = TWO_PI / 400
+    g = _rng(seed)
+    sizes = np.floor(10.0 ** g.uniform(math.log10(n_min), math.log10(n_max), n_collisions)).astype(np.int64)
+    a0s = g.uniform(10.0, 200.0, n_collisions)
+    gammas = g.uniform(500.0, 5000.0, n_collisions)
+    circ = g.uniform(0.0, 1.0, n_collisions) < 0.5
+    pol = g.uniform(0.0, math.pi, n_collisions)
+    t0 = start_step * dt
+    parts, segs, begin = [], [], 0
+    for k in range(n_collisions):
+        m = int(sizes[k])
+        st = beam(m, seed=1000 + seed * 100 + k, gamma0=float(gammas[k]), gamma_rel_spread=0.05, divergence=1e-3,
+                  x_mean=4 * TWO_PI - t0, x_sigma=math.pi, r_sigma=TWO_PI, spin="iso", id0=begin)
+        parts.append(st)
+        field = {"kind": FIELD_PW, "circular": int(circ[k]), "a0": float(a0s[k]), "ncycles": 8.0, "phase0": 0.0,
+                 "pol_angle": float(pol[k]), "phi_start": 0.0}
+        segs.append((begin, begin + m, field))
+        begin += m
+    leptons = {key: np.concatenate([p[key] for p in parts]) for key in parts[0]}
+    return {
+        "name": f"c4_{n_collisions}_collisions_pw",
+        "leptons": leptons, "segments": segs, "sizes": sizes.tolist(),
+        "dt": dt, "steps": 6000, "procs": PROC_NCS | PROC_NCS_STOKES, "seed": seed, "next_id": 1 << 40,
+        "start_step": start_step,
+    }
+
+
 def grid_fill(grid: dict, pulse: dict, t: float) -> list:
     """Harness fill of the six staggered field arrays (fp32, row-major [ny][nx]) with a
     linearly polarised (along y) pulse travelling along -x: transverse Gaussian profile
