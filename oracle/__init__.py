@@ -69,6 +69,7 @@ def lib():
             "orc_tab_bessel": (None, [vp, d, vp]),
             "orc_tab_ncs_rate": (None, [vp, d, dp, dp]),
             "orc_tab_ncs_sample_t": (d, [vp, d, d, d]),
+            "orc_sampler_targets_n": (None, [vp, i64, vp, vp, vp, vp, vp]),
             "orc_tab_nbw_rate": (None, [vp, d, dp, dp]),
             "orc_tab_nbw_sample_delta": (d, [vp, d, d, d]),
             "orc_tab_vb_M": (None, [vp, d, vp]),
@@ -241,6 +242,13 @@ class Tables:
 
     def ncs_sample_t(self, chi, s, r):
         return lib().orc_tab_ncs_sample_t(self.h, float(chi), float(s), float(r))
+
+    def sampler_targets(self, chi, s, c, r) -> np.ndarray:
+        """[n, 3]: table-sampler t and spin-summed mean xi3, xi2 (orc_sampler_targets)."""
+        chi, s, c, r = (_f64(v) for v in (chi, s, c, r))
+        out = np.zeros((len(chi), 3))
+        lib().orc_sampler_targets_n(self.h, len(chi), _p(chi), _p(s), _p(c), _p(r), _p(out))
+        return out
 
     def nbw_rate(self, chi):
         a, b = C.c_double(), C.c_double()

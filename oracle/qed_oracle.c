@@ -647,6 +647,31 @@ double orc_tab_ncs_sample_t(const orc_tables *T, double chi, double s, double r)
     double col = cdf_invert(A0, A1, B0, B1, NCT, f, m, r * (1 - m));
     return col * (T_MAX / (NCT - 1));
 }
+
+/* Targets of the learned NCS sampler (a function the library's network is trained to
+ * reproduce; not a step of the paper's algorithm).  For an emission at chi with initial
+ * spin components s = S.b and c = S.n in the local frame (Sec. III.C.1) and energy draw r:
+ * out[0] = t = (2u/(3 chi))^(1/3) from the tabulated spin-dependent spectrum (the table
+ * sampler), out[1], out[2] = F3/F0, F2/F0 of eqs. (F0)-(F3) at that u, summed over the two
+ * final spins (terms linear in S_f cancel, so the sum is the S_f = 0 value): the mean
+ * photon Stokes parameters xi3, xi2 at that energy.  S.a enters only F1 and is not needed. */
+void orc_sampler_targets(const orc_tables *T, double chi, double s, double c, double r, double out[3]) {
+    const double tt = orc_tab_ncs_sample_t(T, chi, s, r);
+    const double x = tt * tt * tt, u = 1.5 * chi * x;
+    double I, K1, K2;
+    tab_bessel_scaled(T, x, &I, &K1, &K2);
+    const double a[3] = {1, 0, 0}, b[3] = {0, 1, 0}, n[3] = {0, 0, 1};
+    const double Si[3] = {0, s, c}, Sf[3] = {0, 0, 0};
+    double F[4];
+    ncs_F_bessel(u, I, K1, K2, Si, Sf, a, b, n, F);
+    out[0] = tt;
+    out[1] = F[3] / F[0];
+    out[2] = F[2] / F[0];
+}
+void orc_sampler_targets_n(const orc_tables *T, int64_t n, const double *chi, const double *s, const double *c,
+                           const double *r, double *out) {
+    for (int64_t k = 0; k < n; ++k) orc_sampler_targets(T, chi[k], s[k], c[k], r[k], out + 3 * k);
+}
 static void nbw_rate_lookup(const orc_tables *T, double chi, double *Ja, double *Jb, uint32_t *st) {
     double l = chi > 0 ? log(chi) : -1e300;
     if (l < P_LO) { *Ja = 0; *Jb = 0; return; }

@@ -70,6 +70,10 @@ void orc_tables_export(const orc_tables *t, int which, double *out);
 void orc_tab_bessel(const orc_tables *t, double x, double out[3]);  /* K13, K23, IntK13 */
 void orc_tab_ncs_rate(const orc_tables *t, double chi, double *Ia, double *Ib);
 double orc_tab_ncs_sample_t(const orc_tables *t, double chi, double s, double r);
+/* learned-sampler targets: t, mean xi3, mean xi2 (see the definition) */
+void orc_sampler_targets(const orc_tables *t, double chi, double s, double c, double r, double out[3]);
+void orc_sampler_targets_n(const orc_tables *t, int64_t n, const double *chi, const double *s, const double *c,
+                           const double *r, double *out);
 void orc_tab_nbw_rate(const orc_tables *t, double chi, double *Ja, double *Jb);
 double orc_tab_nbw_sample_delta(const orc_tables *t, double chi, double xi3, double r);
 void orc_tab_vb_M(const orc_tables *t, double chi, double M[2]);
