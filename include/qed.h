@@ -217,6 +217,40 @@ qed_status qed_set_tuning(qed_ctx_t *ctx, const qed_tuning *t);
  * outside graph capture, typically once per workload.                                  */
 qed_status qed_autotune(qed_ctx_t *ctx, const qed_segment *segs, int nseg, const qed_leptons *p,
                         int64_t step, int reps, qed_tuning *chosen, hipStream_t stream);
+/* ---- learned NCS sampler ------------------------------------------------------------
+ * A 4-128-128-128-3 perceptron (SiLU after each hidden layer) per context.  Inputs of an
+ * emission: x0 = (log10 chi + 0.65)/2.35 (chi in [1e-3, 50]), x1 = S.b, x2 = S.n (spin in
+ * the local frame of Sec. III.C.1), x3 = 2 r - 1 (the energy draw); outputs: y0 = t/40^(1/3)
+ * with t = (2u/(3 chi))^(1/3) the photon-fraction variable of the spectrum tables, y1, y2 =
+ * the mean photon Stokes xi3, xi2 at that energy summed over the final spins (eqs. F0-F3).
+ * Parameters: one flat FP32 vector of QED_MLP_NPARAM = 34051 numbers, W1 (4 x 128, row =
+ * input), b1, W2 (128 x 128), b2, W3, b3, W4 (128 x 3), b4.  Inference runs on BF16
+ * matrix cores with FP32 accumulation; training (gradient, Adam) in FP32.  All pointers
+ * below are device pointers unless stated; X is [n][4], Y / T are [n][3] floats.        */
+#define QED_MLP_NPARAM 34051
+#define QED_SAMPLER_TABLE 0
+#define QED_SAMPLER_MLP 1
+/* fresh weights (uniform +-1/sqrt(fan-in) from Philox(seed)), zero biases and Adam state */
+qed_status qed_mlp_init(qed_ctx_t *ctx, uint64_t seed, hipStream_t stream);
+/* copy parameters in / out (QED_MLP_NPARAM floats each) */
+qed_status qed_mlp_set_params(qed_ctx_t *ctx, const float *params, hipStream_t stream);
+qed_status qed_mlp_get_params(qed_ctx_t *ctx, float *params_out, hipStream_t stream);
+/* n training pairs from the library's FP64 tables: inputs drawn with Philox(seed) (chi
+ * log-uniform on [1e-3, 50], isotropic spin, uniform draw), targets = the table sampler's
+ * t and the exact spin-summed mean Stokes at that energy, computed from the rounded X   */
+qed_status qed_mlp_samples(qed_ctx_t *ctx, int64_t n, uint64_t seed, float *X, float *Y, hipStream_t stream);
+/* inference: Y = net(X) */
+qed_status qed_mlp_forward(qed_ctx_t *ctx, const float *X, float *Y, int64_t n, hipStream_t stream);
+/* loss (1/n) sum_i sum_o w_o (net(X)_io - T_io)^2 into *loss_out (device float) and its
+ * gradient into grad_out (QED_MLP_NPARAM floats, may be NULL); w is a host array of 3   */
+qed_status qed_mlp_gradient(qed_ctx_t *ctx, const float *X, const float *T, int64_t n, const float *w,
+                            float *grad_out, float *loss_out, hipStream_t stream);
+/* one Adam step (beta 0.9, 0.999, eps 1e-8) on that gradient with learning rate lr */
+qed_status qed_mlp_train_step(qed_ctx_t *ctx, const float *X, const float *T, int64_t n, const float *w, float lr,
+                              float *loss_out, hipStream_t stream);
+/* which sampler later NCS emissions use: QED_SAMPLER_TABLE (default) or QED_SAMPLER_MLP
+ * (the network inside its trained chi range, the table outside it)                     */
+qed_status qed_set_sampler(qed_ctx_t *ctx, int sampler);
 /* Last argument / HIP error of this context as text (empty if none). */
 const char *qed_last_error(const qed_ctx_t *ctx);
 

@@ -100,3 +100,20 @@ def bf16_round(a: np.ndarray) -> np.ndarray:
     u = f.view(np.uint32)
     u = (u + np.uint32(0x7FFF) + ((u >> np.uint32(16)) & np.uint32(1))) & np.uint32(0xFFFF0000)
     return u.view(np.float32).astype(np.float64)
+
+
+def forward_bf16(theta: np.ndarray, X: np.ndarray) -> np.ndarray:
+    """The same network with the two 128 x 128 weight matrices and the inputs of layers
+    2, 3 and 4 rounded to bfloat16 (the storage precision of a matrix-core forward pass);
+    every product and sum in FP64."""
+    layers = unpack(np.asarray(theta, dtype=np.float64))
+    h = np.asarray(X, dtype=np.float64)
+    for k, (W, b) in enumerate(layers):
+        if k > 0:
+            h = bf16_round(h)
+        if k in (1, 2):
+            W = bf16_round(W)
+        z = h @ W + b
+        h = silu(z) if k < len(layers) - 1 else z
+    return h
+

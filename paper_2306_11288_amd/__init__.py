@@ -24,7 +24,12 @@ EXPORTED = ["qed_init_tables", "qed_destroy", "qed_gather", "qed_push_spin", "qe
             "qed_birefringence", "qed_pair", "qed_step_photons", "qed_compact_photons", "qed_read_status",
             "qed_clear_status", "qed_get_next_id", "qed_set_next_id", "qed_table_size", "qed_table_export",
             "qed_set_step_events", "qed_set_step_counter", "qed_advance_step", "qed_get_tuning",
-            "qed_set_tuning", "qed_autotune", "qed_last_error"]
+            "qed_set_tuning", "qed_autotune", "qed_mlp_init", "qed_mlp_set_params", "qed_mlp_get_params",
+            "qed_mlp_samples", "qed_mlp_forward", "qed_mlp_gradient", "qed_mlp_train_step", "qed_set_sampler",
+            "qed_last_error"]
+
+MLP_NPARAM = 34051
+SAMPLER_TABLE, SAMPLER_MLP = 0, 1
 
 ALPHA = 1.0 / 137.035999084
 XI_L = 2.42631023867e-6
@@ -105,6 +110,14 @@ def lib():
             "qed_get_tuning": [vp, vp],
             "qed_set_tuning": [vp, vp],
             "qed_autotune": [vp, vp, C.c_int, vp, i64, C.c_int, vp, vp],
+            "qed_mlp_init": [vp, C.c_uint64, vp],
+            "qed_mlp_set_params": [vp, vp, vp],
+            "qed_mlp_get_params": [vp, vp, vp],
+            "qed_mlp_samples": [vp, i64, C.c_uint64, vp, vp, vp],
+            "qed_mlp_forward": [vp, vp, vp, i64, vp],
+            "qed_mlp_gradient": [vp, vp, vp, i64, vp, vp, vp, vp],
+            "qed_mlp_train_step": [vp, vp, vp, i64, vp, C.c_float, vp, vp],
+            "qed_set_sampler": [vp, C.c_int],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -385,6 +398,59 @@ class Context:
         self._check(lib().qed_autotune(self.h, arr, n, C.byref(L.c()), step, reps, C.byref(t), _stream(stream)),
                     "qed_autotune")
         return t.as_dict()
+
+    # ---- learned sampler ------------------------------------------------------------
+    def mlp_init(self, seed: int = 0, stream=None):
+        self._check(lib().qed_mlp_init(self.h, int(seed), _stream(stream)), "qed_mlp_init")
+
+    def mlp_set_params(self, params, stream=None):
+        t = _torch()
+        p = t.as_tensor(params, dtype=t.float32, device="cuda").contiguous()
+        assert p.numel() == MLP_NPARAM
+        self._check(lib().qed_mlp_set_params(self.h, _ptr(p), _stream(stream)), "qed_mlp_set_params")
+        _torch().cuda.current_stream().synchronize()
+
+    def mlp_get_params(self, stream=None):
+        t = _torch()
+        out = t.empty(MLP_NPARAM, dtype=t.float32, device="cuda")
+        self._check(lib().qed_mlp_get_params(self.h, _ptr(out), _stream(stream)), "qed_mlp_get_params")
+        return out
+
+    def mlp_samples(self, n: int, seed: int, stream=None):
+        t = _torch()
+        X = t.empty((n, 4), dtype=t.float32, device="cuda")
+        Y = t.empty((n, 3), dtype=t.float32, device="cuda")
+        self._check(lib().qed_mlp_samples(self.h, n, int(seed), _ptr(X), _ptr(Y), _stream(stream)), "qed_mlp_samples")
+        return X, Y
+
+    def mlp_forward(self, X, Y=None, stream=None):
+        t = _torch()
+        n = X.shape[0]
+        if Y is None:
+            Y = t.empty((n, 3), dtype=t.float32, device="cuda")
+        self._check(lib().qed_mlp_forward(self.h, _ptr(X), _ptr(Y), n, _stream(stream)), "qed_mlp_forward")
+        return Y
+
+    def mlp_gradient(self, X, T, w=(1.0, 1.0, 1.0), stream=None):
+        t = _torch()
+        g = t.empty(MLP_NPARAM, dtype=t.float32, device="cuda")
+        loss = t.empty(1, dtype=t.float32, device="cuda")
+        wa = (C.c_float * 3)(*w)
+        self._check(lib().qed_mlp_gradient(self.h, _ptr(X), _ptr(T), X.shape[0], wa, _ptr(g), _ptr(loss),
+                                           _stream(stream)), "qed_mlp_gradient")
+        return loss, g
+
+    def mlp_train_step(self, X, T, lr: float, w=(1.0, 1.0, 1.0), loss=None, stream=None):
+        t = _torch()
+        if loss is None:
+            loss = t.empty(1, dtype=t.float32, device="cuda")
+        wa = (C.c_float * 3)(*w)
+        self._check(lib().qed_mlp_train_step(self.h, _ptr(X), _ptr(T), X.shape[0], wa, C.c_float(lr), _ptr(loss),
+                                             _stream(stream)), "qed_mlp_train_step")
+        return loss
+
+    def set_sampler(self, sampler: int):
+        self._check(lib().qed_set_sampler(self.h, int(sampler)), "qed_set_sampler")
 
     def set_step_events(self, events=None):
         """Record four torch.cuda.Event around the decide / scan / event kernels of every

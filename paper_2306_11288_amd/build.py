@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libqed.so")
-SOURCES = ["qed_abi.cpp", "qed_tables.hip", "qed_kernels.hip"]
+SOURCES = ["qed_abi.cpp", "qed_tables.hip", "qed_kernels.hip", "qed_mlp.hip"]
 ARCH = os.environ.get("QED_OFFLOAD_ARCH", "gfx950")
 
 
@@ -28,7 +28,7 @@ def hipcc() -> str:
 # constants of the inlined math out of the per-event loops keeps dozens of them live in
 # registers for the whole kernel and halves the occupancy; rematerialising them in the
 # loop costs a few scalar moves.
-EXTRA = {"qed_kernels.hip": ["-mllvm", "-disable-machine-licm"]}
+EXTRA = {"qed_kernels.hip": ["-mllvm", "-disable-machine-licm"], "qed_mlp.hip": ["-mllvm", "-disable-machine-licm"]}
 
 
 def build(verbose: bool = False) -> str:

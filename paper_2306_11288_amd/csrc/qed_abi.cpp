@@ -190,6 +190,14 @@ void free_ctx(qed_ctx *c) {
     hipFree(c->launch);
     hipFree(c->staging);
     hipFree(c->dsegs);
+    hipFree(c->mlp_P);
+    hipFree(c->mlp_m);
+    hipFree(c->mlp_v);
+    hipFree(c->mlp_G);
+    hipFree(c->mlp_WT);
+    hipFree(c->mlp_work);
+    hipFree(c->ev_in);
+    hipFree(c->ev_out);
     if (c->hsegs) hipHostFree(c->hsegs);
     if (c->seg_copied) hipEventDestroy(c->seg_copied);
     delete c;
@@ -560,6 +568,83 @@ qed_status qed_autotune(qed_ctx_t *ctx, const qed_segment *segs, int nseg, const
     }
     ctx->tune = best;
     if (chosen) *chosen = best;
+    return QED_OK;
+}
+
+qed_status qed_mlp_init(qed_ctx_t *ctx, uint64_t seed, hipStream_t s) {
+    qed_status st = ready(ctx);
+    if (st != QED_OK) return st;
+    return launched(ctx, mlp_init(ctx, seed, s), "qed_mlp_init");
+}
+
+qed_status qed_mlp_set_params(qed_ctx_t *ctx, const float *params, hipStream_t s) {
+    qed_status st = ready(ctx);
+    if (st != QED_OK) return st;
+    if (!params) return fail(ctx, QED_EARG, "qed_mlp_set_params: NULL");
+    hipError_t e = mlp_alloc(ctx);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(ctx->mlp_P, params, MLP_NPARAM * sizeof(float), hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = hipMemsetAsync(ctx->mlp_m, 0, MLP_NPARAM * sizeof(float), s);
+    if (e == hipSuccess) e = hipMemsetAsync(ctx->mlp_v, 0, MLP_NPARAM * sizeof(float), s);
+    if (e == hipSuccess) e = mlp_pack(ctx, s);
+    ctx->mlp_t = 0;
+    return launched(ctx, e, "qed_mlp_set_params");
+}
+
+qed_status qed_mlp_get_params(qed_ctx_t *ctx, float *out, hipStream_t s) {
+    qed_status st = ready(ctx);
+    if (st != QED_OK) return st;
+    if (!out) return fail(ctx, QED_EARG, "qed_mlp_get_params: NULL");
+    if (!ctx->mlp_P) return fail(ctx, QED_ESTATE, "qed_mlp_get_params: no network (qed_mlp_init first)");
+    return launched(ctx, hipMemcpyAsync(out, ctx->mlp_P, MLP_NPARAM * sizeof(float), hipMemcpyDeviceToDevice, s),
+                    "qed_mlp_get_params");
+}
+
+qed_status qed_mlp_samples(qed_ctx_t *ctx, int64_t n, uint64_t seed, float *X, float *Y, hipStream_t s) {
+    qed_status st = ready(ctx);
+    if (st != QED_OK) return st;
+    if (n < 0 || (n > 0 && (!X || !Y))) return fail(ctx, QED_EARG, "qed_mlp_samples: bad arguments");
+    if (n == 0) return QED_OK;
+    return launched(ctx, mlp_samples(ctx, n, seed, X, Y, s), "qed_mlp_samples");
+}
+
+qed_status qed_mlp_forward(qed_ctx_t *ctx, const float *X, float *Y, int64_t n, hipStream_t s) {
+    qed_status st = ready(ctx);
+    if (st != QED_OK) return st;
+    if (!ctx->mlp_P) return fail(ctx, QED_ESTATE, "qed_mlp_forward: no network (qed_mlp_init first)");
+    if (n < 0 || (n > 0 && (!X || !Y))) return fail(ctx, QED_EARG, "qed_mlp_forward: bad arguments");
+    if (n == 0) return QED_OK;
+    return launched(ctx, mlp_forward(ctx, X, Y, n, nullptr, n, s), "qed_mlp_forward");
+}
+
+qed_status qed_mlp_gradient(qed_ctx_t *ctx, const float *X, const float *T, int64_t n, const float *w,
+                            float *grad_out, float *loss_out, hipStream_t s) {
+    qed_status st = ready(ctx);
+    if (st != QED_OK) return st;
+    if (!ctx->mlp_P) return fail(ctx, QED_ESTATE, "qed_mlp_gradient: no network (qed_mlp_init first)");
+    if (n < 1 || n > (1 << 24) || !X || !T || !w || !loss_out)
+        return fail(ctx, QED_EARG, "qed_mlp_gradient: bad arguments (1 <= n <= 2^24)");
+    hipError_t e = mlp_grad(ctx, X, T, n, w, loss_out, s);
+    if (e == hipSuccess && grad_out)
+        e = hipMemcpyAsync(grad_out, ctx->mlp_G, MLP_NPARAM * sizeof(float), hipMemcpyDeviceToDevice, s);
+    return launched(ctx, e, "qed_mlp_gradient");
+}
+
+qed_status qed_mlp_train_step(qed_ctx_t *ctx, const float *X, const float *T, int64_t n, const float *w, float lr,
+                              float *loss_out, hipStream_t s) {
+    qed_status st = qed_mlp_gradient(ctx, X, T, n, w, nullptr, loss_out, s);
+    if (st != QED_OK) return st;
+    if (!(lr > 0)) return fail(ctx, QED_EARG, "qed_mlp_train_step: lr must be positive");
+    return launched(ctx, mlp_adam(ctx, lr, s), "qed_mlp_train_step");
+}
+
+qed_status qed_set_sampler(qed_ctx_t *ctx, int sampler) {
+    if (!ctx) return QED_EARG;
+    if (sampler != QED_SAMPLER_TABLE && sampler != QED_SAMPLER_MLP)
+        return fail(ctx, QED_EARG, "qed_set_sampler: unknown sampler %d", sampler);
+    if (sampler == QED_SAMPLER_MLP && !ctx->mlp_P)
+        return fail(ctx, QED_ESTATE, "qed_set_sampler: no network (qed_mlp_init or qed_mlp_set_params first)");
+    ctx->sampler = sampler;
     return QED_OK;
 }
 

@@ -9,7 +9,7 @@ namespace qed {
 constexpr double PI = 3.14159265358979323846;
 constexpr double SQRT3 = 1.7320508075688772935;
 constexpr double TWO_PI = 6.28318530717958647692;
-constexpr uint32_t STREAM_NCS = 1, STREAM_NBW = 2;
+constexpr uint32_t STREAM_NCS = 1, STREAM_NBW = 2, STREAM_MLP = 7;   // STREAM_MLP: learned-sampler data
 
 // ------------------------------------------------------------------------- small vectors
 template <class T>

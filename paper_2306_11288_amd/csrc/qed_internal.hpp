@@ -110,6 +110,13 @@ struct SegArgs {
 };
 FieldDev field_dev(const qed_field &f);   // host: derived constants of a field
 
+// learned sampler: 4-128-128-128-3 perceptron, flat FP32 parameters W1 b1 W2 b2 W3 b3 W4 b4
+constexpr int MLP_OW1 = 0, MLP_OB1 = 512, MLP_OW2 = 640, MLP_OB2 = 17024, MLP_OW3 = 17152, MLP_OB3 = 33536,
+              MLP_OW4 = 33664, MLP_OB4 = 34048, MLP_NPARAM = 34051;
+// input normalisation: x0 = (log10 chi - MID) / HALF over the trained range chi in [1e-3, 50]
+constexpr double MLP_L10_MID = -0.65, MLP_L10_HALF = 2.35, MLP_L10_HI = 1.6989700043360187;
+constexpr double MLP_CHI_LO = 1e-3, MLP_CHI_HI = 50.0;
+
 constexpr int BLOCK = 256;             // threads per block = particles per tile
 constexpr int EV_GROUP_MAX = 16;       // lepton step: largest tiles-per-group of the event kernel
 
@@ -143,6 +150,14 @@ struct qed_ctx {
     int64_t *step_dev;                 // optional device step counter (caller-owned)
     int num_cu;                        // compute units of the device
     qed_tuning tune;                   // launch shape of the lepton step (qed_autotune)
+    // learned sampler
+    float *mlp_P, *mlp_m, *mlp_v, *mlp_G;   // parameters, Adam moments, gradient [MLP_NPARAM]
+    void *mlp_WT;                      // bf16 transposed W2, W3 for the forward kernel
+    int mlp_t;                         // Adam step count
+    float *mlp_work;                   // training work buffers
+    int64_t mlp_work_len;
+    int sampler;                       // QED_SAMPLER_TABLE or QED_SAMPLER_MLP
+    float *ev_in, *ev_out;             // per-event network inputs / outputs [staging capacity][4]
     char err[256];
 };
 
@@ -158,4 +173,14 @@ hipError_t launch_photons(qed_ctx *ctx, PhotonMode mode, const SegArgs &sa, cons
                           const qed_leptons *em, const qed_leptons *ep, int64_t step, hipStream_t s);
 hipError_t launch_compact(qed_ctx *ctx, const qed_photons &in, const qed_photons &out, hipStream_t s);
 hipError_t launch_advance_step(int64_t *step, int64_t by, hipStream_t s);
+// learned sampler (qed_mlp.hip)
+hipError_t mlp_alloc(qed_ctx *ctx);
+hipError_t mlp_init(qed_ctx *ctx, uint64_t seed, hipStream_t s);
+hipError_t mlp_pack(qed_ctx *ctx, hipStream_t s);
+hipError_t mlp_samples(qed_ctx *ctx, int64_t n, uint64_t seed, float *X, float *Y, hipStream_t s);
+hipError_t mlp_forward(qed_ctx *ctx, const float *X, float *Y, int64_t n, const int64_t *n_dev, int64_t n_max,
+                       hipStream_t s);
+hipError_t mlp_grad(qed_ctx *ctx, const float *X, const float *T, int64_t n, const float w[3], float *loss,
+                    hipStream_t s);
+hipError_t mlp_adam(qed_ctx *ctx, float lr, hipStream_t s);
 }  // namespace qed
