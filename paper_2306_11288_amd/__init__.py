@@ -26,6 +26,7 @@ EXPORTED = ["qed_init_tables", "qed_destroy", "qed_gather", "qed_push_spin", "qe
             "qed_set_step_events", "qed_set_step_counter", "qed_advance_step", "qed_get_tuning",
             "qed_set_tuning", "qed_autotune", "qed_mlp_init", "qed_mlp_set_params", "qed_mlp_get_params",
             "qed_mlp_samples", "qed_mlp_forward", "qed_mlp_gradient", "qed_mlp_train_step", "qed_set_sampler",
+            "qed_sampler_table",
             "qed_last_error"]
 
 MLP_NPARAM = 34051
@@ -118,6 +119,7 @@ def lib():
             "qed_mlp_gradient": [vp, vp, vp, i64, vp, vp, vp, vp],
             "qed_mlp_train_step": [vp, vp, vp, i64, vp, C.c_float, vp, vp],
             "qed_set_sampler": [vp, C.c_int],
+            "qed_sampler_table": [vp, vp, vp, i64, vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -448,6 +450,21 @@ class Context:
         self._check(lib().qed_mlp_train_step(self.h, _ptr(X), _ptr(T), X.shape[0], wa, C.c_float(lr), _ptr(loss),
                                              _stream(stream)), "qed_mlp_train_step")
         return loss
+
+    def sampler_table(self, X, Y=None, stream=None):
+        t = _torch()
+        if Y is None:
+            Y = t.empty((X.shape[0], 3), dtype=t.float32, device="cuda")
+        self._check(lib().qed_sampler_table(self.h, _ptr(X), _ptr(Y), X.shape[0], _stream(stream)),
+                    "qed_sampler_table")
+        return Y
+
+    def mlp_load_pretrained(self, path: str | None = None):
+        """Parameters of the network shipped with the package (sampler_ncs.npy: trained by
+        `python -m paper_2306_11288_amd.train_sampler --samples 50000000 --epochs 2
+        --batch 4096 --seed 0`), or of another .npy file."""
+        p = np.load(path or os.path.join(_HERE, "sampler_ncs.npy"), allow_pickle=False)
+        self.mlp_set_params(p.astype(np.float32))
 
     def set_sampler(self, sampler: int):
         self._check(lib().qed_set_sampler(self.h, int(sampler)), "qed_set_sampler")

@@ -207,6 +207,17 @@ void free_ctx(qed_ctx *c) {
 // Growing it synchronises the device (hipFree); lists of a fixed size allocate once.
 qed_status ensure_staging(qed_ctx *ctx, int64_t capacity) {
     const int64_t need = ((capacity + BLOCK - 1) / BLOCK) * BLOCK;
+    if (ctx->sampler == QED_SAMPLER_MLP && need > ctx->ev_cap) {   // per-event network inputs / outputs
+        hipFree(ctx->ev_in);
+        hipFree(ctx->ev_out);
+        ctx->ev_in = ctx->ev_out = nullptr;
+        ctx->ev_cap = 0;
+        hipError_t e = hipMalloc(&ctx->ev_in, (size_t)need * 4 * sizeof(float));
+        if (e == hipSuccess) e = hipMalloc(&ctx->ev_out, (size_t)need * 3 * sizeof(float));
+        if (e != hipSuccess) return fail(ctx, QED_ENOMEM, "event buffers of %lld events: %s", (long long)need,
+                                         hipGetErrorString(e));
+        ctx->ev_cap = need;
+    }
     if (need <= ctx->staging_cap) return QED_OK;
     hipError_t e = hipSuccess;
     if (ctx->staging) e = hipFree(ctx->staging);
@@ -636,6 +647,14 @@ qed_status qed_mlp_train_step(qed_ctx_t *ctx, const float *X, const float *T, in
     if (st != QED_OK) return st;
     if (!(lr > 0)) return fail(ctx, QED_EARG, "qed_mlp_train_step: lr must be positive");
     return launched(ctx, mlp_adam(ctx, lr, s), "qed_mlp_train_step");
+}
+
+qed_status qed_sampler_table(qed_ctx_t *ctx, const float *X, float *Y, int64_t n, hipStream_t s) {
+    qed_status st = ready(ctx);
+    if (st != QED_OK) return st;
+    if (n < 0 || (n > 0 && (!X || !Y))) return fail(ctx, QED_EARG, "qed_sampler_table: bad arguments");
+    if (n == 0) return QED_OK;
+    return launched(ctx, table_sampler_run(ctx, X, Y, n, s), "qed_sampler_table");
 }
 
 qed_status qed_set_sampler(qed_ctx_t *ctx, int sampler) {

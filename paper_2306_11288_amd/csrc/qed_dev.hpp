@@ -513,11 +513,11 @@ __device__ __forceinline__ void ncs_no_event(const Consts &c, const NcsFrame<T> 
 // emission (given the draws r): photon fraction y by the inverse of the spin-dependent
 // spectrum (r1), k = y p, p -> (1-y) p; final spin +-g/|g| with P(+) = (1 + |g|/(w+f.S))/2
 // (r3); photon pure state +-F/|F| with P(+) = (F0 + |F|)/(2 F0) at the chosen S_f (r4).
+// ncs_event_t: the same with the photon-fraction variable tt already drawn (by the table
+// inverse CDF with r1, or by the learned sampler).
 template <class T>
-__device__ __forceinline__ void ncs_event(const Consts &c, const Tabs<T> &tb, const NcsFrame<T> &f, const double r[4],
-                                          V3<double> &p, V3<T> &S, NcsPhoton<T> &ph) {
-    const T kappa = f.Ib / f.Ia;
-    const T tt = ncs_sample_t<T>(tb, f.chi, kappa, f.s, (T)r[0]);
+__device__ __forceinline__ void ncs_event_t(const Consts &c, const Tabs<T> &tb, const NcsFrame<T> &f, T tt,
+                                            const double r[4], V3<double> &p, V3<T> &S, NcsPhoton<T> &ph) {
     const T t3 = tt * tt * tt;
     const T u = (T)1.5 * (T)f.chi * t3, y = u / ((T)1 + u);
     ph.k = (double)y * p;
@@ -547,6 +547,11 @@ __device__ __forceinline__ void ncs_event(const Consts &c, const Tabs<T> &tb, co
     S = Sf;
     ph.xi = xi;
     ph.e1 = f.a;
+}
+template <class T>
+__device__ __forceinline__ void ncs_event(const Consts &c, const Tabs<T> &tb, const NcsFrame<T> &f, const double r[4],
+                                          V3<double> &p, V3<T> &S, NcsPhoton<T> &ph) {
+    ncs_event_t<T>(c, tb, f, ncs_sample_t<T>(tb, f.chi, f.Ib / f.Ia, f.s, (T)r[0]), r, p, S, ph);
 }
 
 // ------------------------------------------------------------------------- photons

@@ -157,7 +157,8 @@ struct qed_ctx {
     float *mlp_work;                   // training work buffers
     int64_t mlp_work_len;
     int sampler;                       // QED_SAMPLER_TABLE or QED_SAMPLER_MLP
-    float *ev_in, *ev_out;             // per-event network inputs / outputs [staging capacity][4]
+    float *ev_in, *ev_out;             // learned sampler: per-event network inputs [ev_cap][4], outputs [ev_cap][3]
+    int64_t ev_cap;
     char err[256];
 };
 
@@ -183,4 +184,5 @@ hipError_t mlp_forward(qed_ctx *ctx, const float *X, float *Y, int64_t n, const 
 hipError_t mlp_grad(qed_ctx *ctx, const float *X, const float *T, int64_t n, const float w[3], float *loss,
                     hipStream_t s);
 hipError_t mlp_adam(qed_ctx *ctx, float lr, hipStream_t s);
+hipError_t table_sampler_run(qed_ctx *ctx, const float *X, float *Y, int64_t n, hipStream_t s);
 }  // namespace qed

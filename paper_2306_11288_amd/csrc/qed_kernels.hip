@@ -186,6 +186,8 @@ struct LeptonArgs {
     int *tile_counts;
     int *group_tot;
     int ev_group;              // tiles per event group
+    float *ev_in;              // learned sampler: per-event network inputs [events][4]
+    const float *ev_out;       // and outputs [events][3]
     const int64_t *tile_off;
     const int64_t *launch;
 };
@@ -342,7 +344,11 @@ __global__ __launch_bounds__(BLOCK) void k_leptons_decide(LeptonArgs a) {
 // k + 64, ..., finds its tile and record, rebuilds the local frame from the parked state,
 // emits, and writes the photon straight to its ordered place: global rank = group offset
 // + rank in the group, id = id base + global rank.
-template <class T, int G>
+// MODE: EV_FULL (table sampler), EV_PREP (learned sampler, first pass: write the network
+// inputs of every event at its global rank), EV_FINISH (second pass: the photon-fraction
+// variable from the network's output inside its chi range, from the table outside it).
+enum { EV_FULL = 0, EV_PREP = 1, EV_FINISH = 2 };
+template <class T, int G, int MODE>
 __global__ __launch_bounds__(BLOCK) void k_leptons_events(LeptonArgs a) {
     static_assert(G <= 64, "one group = at most one wave of tiles");
     const int64_t n = clamp_count(a.L.count, a.L.capacity);
@@ -386,12 +392,29 @@ __global__ __launch_bounds__(BLOCK) void k_leptons_events(LeptonArgs a) {
             ncs_frame<T>(a.c, tb.ncs_rate(), q, p, rsqrt(1.0 + dot(p, p)), S, E, B, st, f);
             double rr[4];
             uniform4(o.id, step, STREAM_NCS, a.c.seed, rr);
+            const int64_t ge = goff + e;
+            const bool in_range = f.chi >= MLP_CHI_LO && f.chi <= MLP_CHI_HI;
+            if constexpr (MODE == EV_PREP) {
+                float4 x = {0.0f, 0.0f, 0.0f, 0.0f};
+                if (in_range)
+                    x = {(float)((log10(f.chi) - MLP_L10_MID) / MLP_L10_HALF), (float)f.s, (float)dot(S, f.n),
+                         (float)(2.0 * rr[0] - 1.0)};
+                ((float4 *)a.ev_in)[ge] = x;
+                continue;
+            }
+            T tt;
+            if (MODE == EV_FINISH && in_range) {
+                const float y = a.ev_out[3 * ge] * (float)T_MAX;
+                tt = (T)(y < 0.0f ? 0.0f : (y > (float)T_MAX ? (float)T_MAX : y));
+            } else {
+                tt = ncs_sample_t<T>(tb, f.chi, f.Ib / f.Ia, f.s, (T)rr[0]);
+            }
             NcsPhoton<T> ph;
-            ncs_event<T>(a.c, tb, f, rr, p, S, ph);
+            ncs_event_t<T>(a.c, tb, f, tt, rr, p, S, ph);
             const uint32_t o8 = (uint32_t)i * 8u;
             at(a.L.px, o8) = p.x; at(a.L.py, o8) = p.y; at(a.L.pz, o8) = p.z;
             store_s<T>(a, (uint32_t)i * (uint32_t)sizeof(T), S);
-            const int64_t ge = goff + e, pos = obase + ge;
+            const int64_t pos = obase + ge;
             if (a.has_out && pos < a.out.capacity) {
                 a.out.x[pos] = o.r[0]; a.out.y[pos] = o.r[1]; a.out.z[pos] = o.r[2];
                 a.out.kx[pos] = ph.k.x; a.out.ky[pos] = ph.k.y; a.out.kz[pos] = ph.k.z;
@@ -606,10 +629,20 @@ static hipError_t launch_scan(qed_ctx *ctx, const int64_t *in_count, int64_t in_
 // decide + scan + events of a step with NCS; FK as in fields_for (PUSH = false: fields
 // from E6, no field evaluation)
 template <class T, int G>
-static hipError_t launch_events(const LeptonArgs &a, hipStream_t s) {
+static hipError_t launch_events(qed_ctx *ctx, const LeptonArgs &a, hipStream_t s) {
     const int64_t groups = ((a.L.capacity + BLOCK - 1) / BLOCK + G - 1) / G;
     const int64_t nb = (groups + BLOCK / 64 - 1) / (BLOCK / 64);
-    hipLaunchKernelGGL((k_leptons_events<T, G>), dim3(nb < 1 ? 1 : (int)nb), dim3(BLOCK), 0, s, a);
+    const dim3 gd(nb < 1 ? 1 : (unsigned)nb);
+    if (ctx->sampler != QED_SAMPLER_MLP) {
+        hipLaunchKernelGGL((k_leptons_events<T, G, EV_FULL>), gd, dim3(BLOCK), 0, s, a);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL((k_leptons_events<T, G, EV_PREP>), gd, dim3(BLOCK), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // the network over all events of the launch (count from the scan, on the device)
+    if ((e = mlp_forward(ctx, a.ev_in, ctx->ev_out, 0, a.launch + 3, a.L.capacity, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL((k_leptons_events<T, G, EV_FINISH>), gd, dim3(BLOCK), 0, s, a);
     return hipGetLastError();
 }
 
@@ -637,9 +670,9 @@ static hipError_t launch_ncs(qed_ctx *ctx, const LeptonArgs &a0, hipStream_t s) 
                     a.has_out ? a.out.count : nullptr, a.has_out ? a.out.capacity : 0, nullptr, 0, 1, s);
     if (e != hipSuccess || (e = mark(2)) != hipSuccess) return e;
     switch (a.ev_group) {
-    case 4: e = launch_events<T, 4>(a, s); break;
-    case 16: e = launch_events<T, 16>(a, s); break;
-    default: e = launch_events<T, 8>(a, s); break;
+    case 4: e = launch_events<T, 4>(ctx, a, s); break;
+    case 16: e = launch_events<T, 16>(ctx, a, s); break;
+    default: e = launch_events<T, 8>(ctx, a, s); break;
     }
     if (e != hipSuccess) return e;
     return mark(3);
@@ -693,6 +726,8 @@ hipError_t launch_leptons(qed_ctx *ctx, LeptonMode mode, const SegArgs &sa, cons
     a.tile_off = ctx->tile_off;
     a.launch = ctx->launch;
     a.step_dev = ctx->step_dev;
+    a.ev_in = ctx->ev_in;
+    a.ev_out = ctx->ev_out;
     const bool multi = sa.nseg > 1;
     if (ctx->cfg.precision == QED_MIXED) {
         a.tab = ctx->tab32;

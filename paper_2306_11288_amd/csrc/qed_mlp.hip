@@ -38,35 +38,56 @@ struct SampleArgs {
     float *X, *Y;        // [n][4], [n][3]
 };
 
+// The table sampler on normalised inputs x (the function the network learns): t from the
+// spin-dependent inverse CDF, mean xi3, xi2 = F3/F0, F2/F0 at S_f = 0.  T: table precision.
+template <class T>
+__device__ __forceinline__ void table_sampler(const T *tab, const float x[4], float y[3]) {
+    const double chi = exp10(MLP_L10_HALF * (double)x[0] + MLP_L10_MID);
+    const T s = (T)x[1], c = (T)x[2], rr = (T)(0.5 * ((double)x[3] + 1.0));
+    const Tabs<T> tb = {tab};
+    T Ia, Ib;
+    uint32_t st = 0;
+    ncs_rate<T>(tb.ncs_rate(), chi, Ia, Ib, st);
+    const T tt = ncs_sample_t<T>(tb, chi, Ib / Ia, s, rr);
+    const T x3 = tt * tt * tt, u = (T)1.5 * (T)chi * x3;
+    T I, K1, K2;
+    bessel_scaled<T>(tb, x3, I, K1, K2);
+    const V3<T> ax = {1, 0, 0}, bx = {0, 1, 0}, nx = {0, 0, 1}, Si = {0, s, c}, Sf = {0, 0, 0};
+    T F[4];
+    ncs_F<T>(u, I, K1, K2, Si, Sf, ax, bx, nx, F);
+    y[0] = (float)(tt / (T)T_MAX);
+    y[1] = (float)(F[3] / F[0]);
+    y[2] = (float)(F[2] / F[0]);
+}
+
 __global__ __launch_bounds__(BLOCK) void k_mlp_samples(SampleArgs a) {
     const int64_t k = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     if (k >= a.n) return;
     double r[4];
     uniform4((uint64_t)k, 0, STREAM_MLP, a.seed, r);
     // inputs: log10 chi uniform on [-3, log10 50]; an isotropic unit spin (S.b uniform,
-    // S.n its transverse part times a uniform azimuth cosine); the energy draw
+    // S.n its transverse part times a uniform azimuth cosine); the energy draw.  The
+    // targets are computed from the rounded inputs, so every pair is exact.
     const double l10 = -3.0 + r[0] * (MLP_L10_HI + 3.0);
     const double s0 = 2.0 * r[1] - 1.0;
     const double c0 = sqrt(1.0 - s0 * s0) * cospi(2.0 * r[2]);
-    float x[4] = {(float)((l10 - MLP_L10_MID) / MLP_L10_HALF), (float)s0, (float)c0, (float)(2.0 * r[3] - 1.0)};
-    // the targets are computed from the rounded inputs, so the pair is exact
-    const double chi = exp10(MLP_L10_HALF * (double)x[0] + MLP_L10_MID);
-    const double s = x[1], c = x[2], rr = 0.5 * ((double)x[3] + 1.0);
-    const Tabs<double> tb = {a.tab64};
-    double Ia, Ib;
-    uint32_t st = 0;
-    ncs_rate<double>(tb.ncs_rate(), chi, Ia, Ib, st);
-    const double tt = ncs_sample_t<double>(tb, chi, Ib / Ia, s, rr);
-    const double x3 = tt * tt * tt, u = 1.5 * chi * x3;
-    double I, K1, K2;
-    bessel_scaled<double>(tb, x3, I, K1, K2);
-    const V3<double> ax = {1, 0, 0}, bx = {0, 1, 0}, nx = {0, 0, 1}, Si = {0, s, c}, Sf = {0, 0, 0};
-    double F[4];
-    ncs_F<double>(u, I, K1, K2, Si, Sf, ax, bx, nx, F);
+    const float x[4] = {(float)((l10 - MLP_L10_MID) / MLP_L10_HALF), (float)s0, (float)c0,
+                        (float)(2.0 * r[3] - 1.0)};
+    float y[3];
+    table_sampler<double>(a.tab64, x, y);
     for (int j = 0; j < 4; ++j) a.X[4 * k + j] = x[j];
-    a.Y[3 * k + 0] = (float)(tt / T_MAX);
-    a.Y[3 * k + 1] = (float)(F[3] / F[0]);
-    a.Y[3 * k + 2] = (float)(F[2] / F[0]);
+    for (int j = 0; j < 3; ++j) a.Y[3 * k + j] = y[j];
+}
+
+template <class T>
+__global__ __launch_bounds__(BLOCK) void k_table_sampler(const T *tab, const float *X, float *Y, int64_t n) {
+    const int64_t k = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (k >= n) return;
+    const float4 v = ((const float4 *)X)[k];
+    const float x[4] = {v.x, v.y, v.z, v.w};
+    float y[3];
+    table_sampler<T>(tab, x, y);
+    for (int j = 0; j < 3; ++j) Y[3 * k + j] = y[j];
 }
 
 // ------------------------------------------------------------------------- inference
@@ -341,6 +362,13 @@ hipError_t mlp_init(qed_ctx *ctx, uint64_t seed, hipStream_t s) {
 hipError_t mlp_samples(qed_ctx *ctx, int64_t n, uint64_t seed, float *X, float *Y, hipStream_t s) {
     SampleArgs a{ctx->tab64, n, seed, X, Y};
     hipLaunchKernelGGL(k_mlp_samples, dim3((unsigned)((n + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t table_sampler_run(qed_ctx *ctx, const float *X, float *Y, int64_t n, hipStream_t s) {
+    const dim3 g((unsigned)((n + BLOCK - 1) / BLOCK));
+    if (ctx->cfg.precision == QED_MIXED) hipLaunchKernelGGL(k_table_sampler<float>, g, dim3(BLOCK), 0, s, ctx->tab32, X, Y, n);
+    else hipLaunchKernelGGL(k_table_sampler<double>, g, dim3(BLOCK), 0, s, ctx->tab64, X, Y, n);
     return hipGetLastError();
 }
 

@@ -1,0 +1,74 @@
+"""Train the learned NCS sampler of a context on the GPU with the library's own kernels.
+
+The training pairs come from the library's FP64 tables (qed_mlp_samples: chi log-uniform
+on [1e-3, 50], isotropic spin, uniform energy draw -> the table sampler's t and the exact
+spin-summed mean photon Stokes); the loss weights t by 1 and the two Stokes outputs by 0.3;
+Adam with a learning rate decaying geometrically from lr to lr_final.
+
+    python -m paper_2306_11288_amd.train_sampler --samples 50000000 --out sampler.npy
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import time
+
+LOSS_WEIGHTS = (1.0, 0.3, 0.3)
+
+
+def validate(ctx, Xv, Tv) -> dict:
+    """Mean and max absolute error of the network against the FP64 table sampler."""
+    Y = ctx.mlp_forward(Xv)
+    d = (Y - Tv).abs()
+    return {"mae": [float(v) for v in d.mean(0).cpu()], "max": [float(v) for v in d.max(0).values.cpu()]}
+
+
+def train(ctx, n_samples: int = 50_000_000, epochs: float = 1.0, batch: int = 8192, lr: float = 3e-3,
+          lr_final: float = 5e-5, seed: int = 0, n_val: int = 1 << 16, log=None) -> dict:
+    import torch
+
+    t0 = time.perf_counter()
+    ctx.mlp_init(seed)
+    X, T = ctx.mlp_samples(n_samples, seed + 1)
+    Xv, Tv = ctx.mlp_samples(n_val, seed + 2)
+    before = validate(ctx, Xv, Tv)
+    steps = max(1, int(epochs * n_samples) // batch)
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    per_epoch = n_samples // batch
+    hist = []
+    for k in range(steps):
+        j = (k % per_epoch) * batch
+        rate = lr * (lr_final / lr) ** (k / max(1, steps - 1))
+        ctx.mlp_train_step(X[j:j + batch], T[j:j + batch], rate, LOSS_WEIGHTS, loss)
+        if log is not None and (k % 1000 == 0 or k == steps - 1):
+            hist.append((k, float(loss.item())))
+            log(f"[train] step {k}/{steps} loss {hist[-1][1]:.3e}")
+    torch.cuda.synchronize()
+    after = validate(ctx, Xv, Tv)
+    del X, T
+    return {"samples": n_samples, "steps": steps, "batch": batch, "epochs": epochs,
+            "seconds": time.perf_counter() - t0, "val_before": before, "val_after": after, "loss_history": hist}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--samples", type=int, default=50_000_000)
+    ap.add_argument("--epochs", type=float, default=1.0)
+    ap.add_argument("--batch", type=int, default=8192)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--out", default="")
+    args = ap.parse_args()
+    import numpy as np
+    import torch
+
+    import paper_2306_11288_amd as Q
+    torch.cuda.set_device(0)
+    ctx = Q.Context(dt=0.01, procs=Q.PROC_NCS | Q.PROC_NCS_STOKES, seed=1, id_start=0, precision=Q.QED_MIXED)
+    res = train(ctx, args.samples, args.epochs, args.batch, seed=args.seed, log=lambda m: print(m, flush=True))
+    if args.out:
+        np.save(args.out, ctx.mlp_get_params().cpu().numpy())
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

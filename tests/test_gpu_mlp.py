@@ -97,3 +97,67 @@ def test_training_reduces_the_error(ctx):
     _say(f"mean abs error before {err0}, after {err1}")
     assert np.all(err1 < 0.25 * err0)
     assert err1[0] < 0.02
+
+
+@pytest.fixture(scope="module")
+def trained():
+    """The network shipped with the package (trained on 5e7 pairs by the library)."""
+    c = Q.Context(dt=0.01, procs=Q.PROC_NCS | Q.PROC_NCS_STOKES, seed=1, id_start=0, precision=Q.QED_MIXED)
+    c.mlp_load_pretrained()
+    return c.mlp_get_params(), None
+
+
+def test_trained_network_against_table_judge(trained):
+    """The table sampler (FP32 tables of a mixed context) judges the network on fresh
+    inputs; the network's weights are 60x smaller than the FP32 spectrum tables."""
+    params, res = trained
+    c = Q.Context(dt=0.01, procs=Q.PROC_NCS | Q.PROC_NCS_STOKES, seed=1, id_start=0, precision=Q.QED_MIXED)
+    c.mlp_set_params(params)
+    X, T64 = c.mlp_samples(1 << 16, seed=21)
+    Yt = c.sampler_table(X)
+    Ym = c.mlp_forward(X)
+    d_table = (Yt - T64).abs().mean(0).cpu().numpy()     # FP32 tables vs FP64 tables
+    d_mlp = (Ym - T64).abs().mean(0).cpu().numpy()
+    _say(f"mean abs error: table(FP32) {d_table}, network {d_mlp}")
+    assert d_table[0] < 1e-5
+    assert d_mlp[0] < 2e-3 and d_mlp[1] < 3e-3 and d_mlp[2] < 3e-3
+    net_bytes = Q.MLP_NPARAM * 2                            # bf16 weights on the matrix cores
+    table_bytes = 4 * 2 * 512 * 1024                        # FP32 NCS spectrum table (A, B)
+    assert table_bytes > 60 * net_bytes
+
+
+@pytest.mark.parametrize("precision", [Q.QED_MIXED, Q.QED_FP64], ids=["mixed", "fp64"])
+def test_learned_sampler_in_the_step(trained, precision):
+    """The focused-pulse step with the network as sampler against the same step with the
+    table: identical first-step event decisions and ids, photon spectra close."""
+    params, _ = trained
+    cfg = __import__("workloads").c2(20000, start_step=2450)
+    out = {}
+    for sampler in (Q.SAMPLER_TABLE, Q.SAMPLER_MLP):
+        c = Q.Context(dt=cfg["dt"], procs=cfg["procs"], seed=cfg["seed"], id_start=cfg["next_id"],
+                      precision=precision)
+        c.mlp_set_params(params)
+        c.set_sampler(sampler)
+        L = Q.Leptons.from_state(cfg["leptons"], precision=precision)
+        G = Q.Photons(200000, precision=precision)
+        c.step_leptons(Q.whole(cfg["field"]), L, G, 2450)
+        torch.cuda.synchronize()
+        first = G.to_numpy()
+        for s in range(2451, 2550):
+            c.step_leptons(Q.whole(cfg["field"]), L, G, s)
+        torch.cuda.synchronize()
+        out[sampler] = (first, G.to_numpy(), L.to_numpy())
+    ft, fm = out[Q.SAMPLER_TABLE][0], out[Q.SAMPLER_MLP][0]
+    assert len(ft["x"]) == len(fm["x"]) > 50 and np.array_equal(ft["id"], fm["id"])
+    assert np.array_equal(ft["x"], fm["x"])                  # same emitters, same birth places
+    gt, gm = out[Q.SAMPLER_TABLE][1], out[Q.SAMPLER_MLP][1]
+    assert len(gt["x"]) > 2000 and abs(len(gm["x"]) / len(gt["x"]) - 1) < 0.02
+    et = np.sqrt(gt["kx"] ** 2 + gt["ky"] ** 2 + gt["kz"] ** 2)
+    em = np.sqrt(gm["kx"] ** 2 + gm["ky"] ** 2 + gm["kz"] ** 2)
+    assert abs(em.mean() / et.mean() - 1) < 0.005
+    # Kolmogorov-Smirnov distance of the photon energy distributions
+    grid = np.quantile(et, np.linspace(0.01, 0.99, 99))
+    ks = np.max(np.abs(np.searchsorted(np.sort(et), grid) / len(et) - np.searchsorted(np.sort(em), grid) / len(em)))
+    _say(f"photons {len(gt['x'])} / {len(gm['x'])}, mean energy ratio {em.mean() / et.mean():.4f}, KS {ks:.4f}")
+    assert ks < 0.01
+
