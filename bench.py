@@ -59,11 +59,14 @@ def measured_traffic(prec: str):
     return d.get(prec, {}).get("bytes_per_launch")
 
 
-def run_gpu(prec, cfg, steps, warmup, torch, Q, per_launch_events=True):
+def run_gpu(prec, cfg, steps, warmup, torch, Q, per_launch_events=True, learned=False):
     precision = Q.QED_MIXED if prec == "mixed" else Q.QED_FP64
     n = len(cfg["leptons"]["x"])
     ctx = Q.Context(dt=cfg["dt"], procs=cfg["procs"], seed=cfg["seed"], id_start=cfg["next_id"],
                     precision=precision)
+    if learned:
+        ctx.mlp_load_pretrained()
+        ctx.set_sampler(Q.SAMPLER_MLP)
     L = Q.Leptons.from_state(cfg["leptons"], precision=precision)
     cap = int(n * 0.03 * (steps + warmup)) + 1_000_000
     G = Q.Photons(cap, precision=precision)
@@ -253,6 +256,60 @@ def run_batched(args, torch, Q, W):
             "photons_per_step": (G.count - n0) / steps}
 
 
+MLP_FLOP = 2 * (4 * 128 + 2 * 128 * 128 + 128 * 3)   # multiply-adds x 2 per sample (forward)
+MFMA_BF16_PEAK_TFLOPS = 2500.0
+
+
+def run_learned(args, torch, Q, W, cfg, fp64):
+    """The learned sampler: matrix-core inference against the table sampler on the same
+    inputs, training throughput of the library's kernels, and the focused-pulse step with
+    the network (the shipped one) as sampler against the FP64 table path."""
+    from paper_2306_11288_amd.train_sampler import train
+    out = {}
+    ctx = Q.Context(dt=cfg["dt"], procs=cfg["procs"], seed=cfg["seed"], id_start=cfg["next_id"],
+                    precision=Q.QED_MIXED)
+    ctx.mlp_load_pretrained()
+    n = 1 << 23
+    X, T64 = ctx.mlp_samples(n, seed=77)
+    Y = torch.empty((n, 3), dtype=torch.float32, device="cuda")
+
+    def best_ms(fn, reps=5):
+        b = float("inf")
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            b = min(b, e0.elapsed_time(e1))
+        return b
+    t_mlp = best_ms(lambda: ctx.mlp_forward(X, Y))
+    err_mlp = (Y - T64).abs().mean(0).cpu().tolist()
+    t_tab = best_ms(lambda: ctx.sampler_table(X, Y))
+    err_tab = (Y - T64).abs().mean(0).cpu().tolist()
+    tflops = MLP_FLOP * n / (t_mlp * 1e-3) / 1e12
+    out["sampler"] = {
+        "samples": n, "network_samples_per_s": n / (t_mlp * 1e-3), "table_samples_per_s": n / (t_tab * 1e-3),
+        "network_mean_abs_error_vs_fp64_table": err_mlp, "fp32_table_mean_abs_error_vs_fp64_table": err_tab,
+        "network_bytes_bf16": Q.MLP_NPARAM * 2, "table_bytes_fp32": 4 * 2 * 512 * 1024,
+        "roofline": {"bound": "mfma", "achieved": tflops, "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": tflops / MFMA_BF16_PEAK_TFLOPS, "kernel": "k_mlp_forward (bf16 MFMA 32x32x16)",
+                     "flop_per_sample": MLP_FLOP, "avg_launch_ms": t_mlp},
+    }
+    del X, T64, Y
+    c2 = Q.Context(dt=0.01, procs=Q.PROC_NCS | Q.PROC_NCS_STOKES, seed=1, id_start=0, precision=Q.QED_MIXED)
+    tr = train(c2, n_samples=args.train_samples, epochs=1.0, batch=8192, seed=5)
+    out["training"] = {"samples": tr["samples"], "steps": tr["steps"], "batch": tr["batch"], "seconds": tr["seconds"],
+                       "samples_per_s": tr["samples"] / tr["seconds"], "val_mae_after": tr["val_after"]["mae"],
+                       "note": "one epoch from fresh weights, timing includes generating the pairs"}
+    learned = run_gpu("mixed", cfg, args.steps, args.warmup, torch, Q, per_launch_events=False, learned=True)
+    out["step"] = {"value": args.n * args.steps / learned["wall"], "ms_per_step": 1e3 * learned["wall"] / args.steps,
+                   "status_bits": learned["status"], "network": "sampler_ncs.npy (5e7 pairs, 2 epochs)"}
+    if fp64 is not None:
+        out["step"]["error_vs_fp64"] = error_metrics(fp64, learned, 2000.0, torch)
+    return out
+
+
 def cpu_baseline(cfg_small, budget_s=15.0):
     """The oracle as it stands (single-threaded C, FP64 tables) on a bounded sample of the
     same workload: the first `n` electrons of the bunch, stepped until the budget is used."""
@@ -293,6 +350,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=50,
                     help="steps of the many-collision batching comparison (0: skip it)")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-sampler measurements")
+    ap.add_argument("--train-samples", type=int, default=10_000_000)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device to device three times (a plain copy kernel of known size, "
                          "the reference for the HBM byte counters)")
@@ -373,6 +432,9 @@ def main():
                           "status_bits": fp64["status"]}
         result["speedup_mixed_over_fp64"] = result["value"] / result["fp64"]["value"]
         result["error_vs_fp64"] = error_metrics(fp64, mixed, 2000.0, torch)
+    if not args.no_learned:
+        print("[bench] learned sampler", file=sys.stderr, flush=True)
+        result["learned"] = run_learned(args, torch, Q, W, cfg, fp64)
     if args.batch_steps > 0:
         print("[bench] batching: many collisions, graph-replayed, vs one at a time in FP64", file=sys.stderr, flush=True)
         result["batched"] = run_batched(args, torch, Q, W)

@@ -402,13 +402,12 @@ __global__ __launch_bounds__(BLOCK) void k_leptons_events(LeptonArgs a) {
                 ((float4 *)a.ev_in)[ge] = x;
                 continue;
             }
-            T tt;
-            if (MODE == EV_FINISH && in_range) {
-                const float y = a.ev_out[3 * ge] * (float)T_MAX;
-                tt = (T)(y < 0.0f ? 0.0f : (y > (float)T_MAX ? (float)T_MAX : y));
-            } else {
-                tt = ncs_sample_t<T>(tb, f.chi, f.Ib / f.Ia, f.s, (T)rr[0]);
-            }
+            // the network's t is used where it is a valid sample (0 < t < t_max) inside its
+            // trained chi range; the table decides everywhere else
+            const float yn = MODE == EV_FINISH ? a.ev_out[3 * ge] : -1.0f;
+            const T tt = (MODE == EV_FINISH && in_range && yn > 0.0f && yn < 1.0f)
+                             ? (T)(yn * (float)T_MAX)
+                             : ncs_sample_t<T>(tb, f.chi, f.Ib / f.Ia, f.s, (T)rr[0]);
             NcsPhoton<T> ph;
             ncs_event_t<T>(a.c, tb, f, tt, rr, p, S, ph);
             const uint32_t o8 = (uint32_t)i * 8u;
