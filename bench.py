@@ -72,7 +72,7 @@ def run_gpu(prec, cfg, steps, warmup, torch, Q, per_launch_events=True, learned=
     G = Q.Photons(cap, precision=precision)
     segs = Q.whole(cfg["field"])
     s0 = cfg["start_step"]
-    tuning = ctx.autotune(segs, L, s0, reps=2)
+    tuning = ctx.autotune(segs, L, s0, reps=3)
     for s in range(s0, s0 + warmup):
         ctx.step_leptons(segs, L, G, s)
     torch.cuda.synchronize()
@@ -310,6 +310,67 @@ def run_learned(args, torch, Q, W, cfg, fp64):
     return out
 
 
+BYTES_PHOTON_STEP = {"mixed": 24 + 24 + 12 + 12 + 8 + 1 + 24 + 12 + 12, "fp64": 24 + 24 + 24 + 24 + 8 + 1 + 24 + 24 + 24}
+
+
+def run_cascade(args, torch, Q, W):
+    """Cascade on a 2D Yee grid (2048 x 512 cells, 40 per wavelength, fp32 fields of a
+    linearly polarised a0 = 300 pulse, a static snapshot at its peak): 1e6 electrons at
+    gamma 4000 emit photons (NCS + Stokes), photons rotate their Stokes basis, evolve by
+    vacuum birefringence and create pairs (NBW); electrons, positrons and photons all
+    stepped.  A warm-up builds the photon population, then the timed steps."""
+    cfg = W.c3()
+    grid, pulse = cfg["grid"], dict(cfg["pulse"])
+    pulse["phi_start"] = -pulse["ncycles"] * math.pi          # pulse centre at x = 0 for t = 0
+    comps = [torch.as_tensor(c).cuda() for c in W.grid_fill(grid, pulse, 0.0)]
+    spec = dict(kind=Q.FIELD_GRID2D, grid=comps, **grid)
+    n = len(cfg["leptons"]["x"])
+    st = dict(cfg["leptons"])
+    st["x"] = st["x"] - st["x"].mean()                          # bunch at the pulse centre
+    prec = Q.QED_MIXED
+    ctx = Q.Context(dt=cfg["dt"], procs=cfg["procs"], seed=cfg["seed"], id_start=cfg["next_id"], precision=prec)
+    cap_g, cap_l = 20_000_000, 4_000_000
+    em = Q.Leptons.from_state(st, capacity=cap_l, charge=-1, precision=prec)
+    ep = Q.Leptons(cap_l, 1, precision=prec)
+    G = Q.Photons(cap_g, precision=prec)
+    segs = Q.whole(spec)
+    warm, steps = args.cascade_warmup, args.cascade_steps
+    for s in range(warm):
+        ctx.step(segs, em, ep, G, s)
+    torch.cuda.synchronize()
+    counts0 = (em.count, ep.count, G.count)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    t_ph = t_all = 0.0
+    t0 = time.perf_counter()
+    for s in range(warm, warm + steps):
+        ev[0].record()
+        ctx.step_photons(segs, G, em, ep, s)
+        ev[1].record()
+        ctx.step_leptons(segs, em, G, s)
+        ctx.step_leptons(segs, ep, G, s)
+        ev[2].record()
+        torch.cuda.synchronize()
+        t_ph += ev[0].elapsed_time(ev[1])
+        t_all += ev[0].elapsed_time(ev[2])
+    wall = time.perf_counter() - t0
+    counts1 = (em.count, ep.count, G.count)
+    lep_steps = sum((counts0[k] + counts1[k]) / 2 * steps for k in (0, 1))
+    pho_steps = (counts0[2] + counts1[2]) / 2 * steps
+    ph_ms = t_ph / steps
+    ph_bytes = (counts0[2] + counts1[2]) / 2 * BYTES_PHOTON_STEP["mixed"]
+    return {"workload": f"{n} electrons gamma 4000 in an LP a0 = 300 pulse on a 2048 x 512 grid (static snapshot); "
+                        f"NCS + Stokes + NBW + VB; steps {warm}..{warm + steps - 1}",
+            "counts_start": {"electrons": counts0[0], "positrons": counts0[1], "photons": counts0[2]},
+            "counts_end": {"electrons": counts1[0], "positrons": counts1[1], "photons": counts1[2]},
+            "particle_steps_per_s": (lep_steps + pho_steps) / (t_all * 1e-3),
+            "photon_steps_per_s": pho_steps / (t_ph * 1e-3), "ms_per_step": t_all / steps,
+            "photon_step_ms": ph_ms, "wall_ms_per_step": 1e3 * wall / steps,
+            "photon_step_roofline": {"bound": "hbm", "achieved": ph_bytes / (ph_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                                     "unit": "GB/s", "frac": ph_bytes / (ph_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                     "bytes_per_photon_step": BYTES_PHOTON_STEP["mixed"]},
+            "status_bits": ctx.read_status()}
+
+
 def cpu_baseline(cfg_small, budget_s=15.0):
     """The oracle as it stands (single-threaded C, FP64 tables) on a bounded sample of the
     same workload: the first `n` electrons of the bunch, stepped until the budget is used."""
@@ -351,6 +412,8 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=50,
                     help="steps of the many-collision batching comparison (0: skip it)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-sampler measurements")
+    ap.add_argument("--cascade-steps", type=int, default=40, help="timed steps of the cascade (0: skip it)")
+    ap.add_argument("--cascade-warmup", type=int, default=150)
     ap.add_argument("--train-samples", type=int, default=10_000_000)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device to device three times (a plain copy kernel of known size, "
@@ -432,6 +495,9 @@ def main():
                           "status_bits": fp64["status"]}
         result["speedup_mixed_over_fp64"] = result["value"] / result["fp64"]["value"]
         result["error_vs_fp64"] = error_metrics(fp64, mixed, 2000.0, torch)
+    if args.cascade_steps > 0:
+        print("[bench] cascade on the grid", file=sys.stderr, flush=True)
+        result["cascade"] = run_cascade(args, torch, Q, W)
     if not args.no_learned:
         print("[bench] learned sampler", file=sys.stderr, flush=True)
         result["learned"] = run_learned(args, torch, Q, W, cfg, fp64)

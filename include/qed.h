@@ -124,7 +124,7 @@ typedef struct {
  *  GRID2D: six fp32 arrays [ny][nx] on a 2D Yee cell in the x-y plane, node (i,j) at
  *          (gx0 + i dx, gy0 + j dy); Ex (i+1/2,j), Ey (i,j+1/2), Ez (i,j), Bx (i,j+1/2),
  *          By (i+1/2,j), Bz (i+1/2,j+1/2); gathered with TSC weights (Sec. II.D-E), nodes
- *          outside the grid contribute zero.                                            */
+ *          outside the grid contribute zero.  nx >= 3, ny >= 1, at most 2^29 nodes.   */
 typedef struct {
     int32_t kind, circular;
     double a0, ncycles, phase0, pol_angle, w0, x_focus, phi_start;
@@ -211,8 +211,9 @@ qed_status qed_advance_step(qed_ctx_t *ctx, int64_t by, hipStream_t stream);
 qed_status qed_get_tuning(qed_ctx_t *ctx, qed_tuning *out);
 qed_status qed_set_tuning(qed_ctx_t *ctx, const qed_tuning *t);
 /* Autotuner: times every launch shape on a copy of `p` (its first *count leptons, step
- * `step`, photons to a scratch list), `reps` times each, keeps the fastest for this
- * context and returns it in `chosen` (may be NULL).  Leaves p, the id counter and the
+ * `step`, photons to a scratch list): one warm-up round, then `reps` rounds over all
+ * shapes in turn, fastest time per shape; the context switches to the fastest shape if it
+ * beats its current one by at least 3 %, and returns the result in `chosen` (may be NULL).  Leaves p, the id counter and the
  * status word as they were.  Synchronises, allocates and frees scratch memory: call it
  * outside graph capture, typically once per workload.                                  */
 qed_status qed_autotune(qed_ctx_t *ctx, const qed_segment *segs, int nseg, const qed_leptons *p,

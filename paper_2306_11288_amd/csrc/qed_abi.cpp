@@ -42,7 +42,8 @@ qed_status check_field(qed_ctx *ctx, const qed_field &f) {
     case QED_FIELD_GRID2D:
         for (int c = 0; c < 6; ++c)
             if (!f.grid[c]) return fail(ctx, QED_EARG, "field: grid component %d is NULL", c);
-        if (f.nx <= 0 || f.ny <= 0) return fail(ctx, QED_EARG, "field: grid size must be positive");
+        if (f.nx < 3 || f.ny <= 0) return fail(ctx, QED_EARG, "field: grid needs nx >= 3 and ny >= 1");
+        if ((int64_t)f.nx * f.ny > (int64_t)1 << 29) return fail(ctx, QED_EARG, "field: grid larger than 2^29 nodes");
         if (!(f.dx > 0) || !(f.dy > 0)) return fail(ctx, QED_EARG, "field: grid spacing must be positive");
         return QED_OK;
     }
@@ -538,34 +539,44 @@ qed_status qed_autotune(qed_ctx_t *ctx, const qed_segment *segs, int nseg, const
     const qed_tuning keep = ctx->tune;
     const int ev_on = ctx->step_ev_on;
     ctx->step_ev_on = 0;
-    qed_tuning best = keep;
-    float best_ms = 3.0e38f;
+    // candidates: every launch shape; the rounds visit all of them in turn (round 0 only
+    // warms each up), each keeps its fastest time, and the context's current shape is
+    // replaced only by one at least 3 % faster
+    constexpr int NC = 24;
+    qed_tuning cand[NC];
+    float tbest[NC];
     const int bpc[4] = {0, 2, 4, 8}, grp[3] = {4, 8, 16};
-    for (int ib = 0; ib < 4 && e == hipSuccess; ++ib)
-        for (int lds = 0; lds < 2 && e == hipSuccess; ++lds)
-            for (int ig = 0; ig < 3 && e == hipSuccess; ++ig) {
-                ctx->tune = {bpc[ib], lds, grp[ig]};
-                float cand = 3.0e38f;
-                for (int r = 0; r < reps && e == hipSuccess; ++r) {
-                    for (int k = 0; k < 7 && e == hipSuccess; ++k)
-                        e = hipMemcpyAsync(*ld[k], ls[k], nb * 8, hipMemcpyDeviceToDevice, s);
-                    for (int k = 0; k < 3 && e == hipSuccess; ++k)
-                        e = hipMemcpyAsync(*lsp[k], lss[k], nb * sb, hipMemcpyDeviceToDevice, s);
-                    if (e == hipSuccess) e = hipMemcpyAsync(L.id, p->id, nb * 8, hipMemcpyDeviceToDevice, s);
-                    if (e == hipSuccess) e = hipMemsetAsync(G.count, 0, 8, s);
-                    if (e == hipSuccess) e = hipEventRecord(t0, s);
-                    if (e == hipSuccess) e = launch_leptons(ctx, LM_FUSED, sa, L, nullptr, &G, step, s);
-                    if (e == hipSuccess) e = hipEventRecord(t1, s);
-                    if (e == hipSuccess) e = hipEventSynchronize(t1);
-                    float ms = 0;
-                    if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
-                    if (e == hipSuccess && ms < cand) cand = ms;
-                }
-                if (e == hipSuccess && cand < best_ms) {
-                    best_ms = cand;
-                    best = ctx->tune;
-                }
+    int nc = 0, icur = -1;
+    for (int ib = 0; ib < 4; ++ib)
+        for (int lds = 0; lds < 2; ++lds)
+            for (int ig = 0; ig < 3; ++ig) {
+                cand[nc] = {bpc[ib], lds, grp[ig]};
+                if (cand[nc].blocks_per_cu == keep.blocks_per_cu && cand[nc].rate_lds == keep.rate_lds &&
+                    cand[nc].ev_group == keep.ev_group)
+                    icur = nc;
+                tbest[nc++] = 3.0e38f;
             }
+    for (int round = 0; round <= reps && e == hipSuccess; ++round)
+        for (int c = 0; c < nc && e == hipSuccess; ++c) {
+            ctx->tune = cand[c];
+            for (int k = 0; k < 7 && e == hipSuccess; ++k)
+                e = hipMemcpyAsync(*ld[k], ls[k], nb * 8, hipMemcpyDeviceToDevice, s);
+            for (int k = 0; k < 3 && e == hipSuccess; ++k)
+                e = hipMemcpyAsync(*lsp[k], lss[k], nb * sb, hipMemcpyDeviceToDevice, s);
+            if (e == hipSuccess) e = hipMemcpyAsync(L.id, p->id, nb * 8, hipMemcpyDeviceToDevice, s);
+            if (e == hipSuccess) e = hipMemsetAsync(G.count, 0, 8, s);
+            if (e == hipSuccess) e = hipEventRecord(t0, s);
+            if (e == hipSuccess) e = launch_leptons(ctx, LM_FUSED, sa, L, nullptr, &G, step, s);
+            if (e == hipSuccess) e = hipEventRecord(t1, s);
+            if (e == hipSuccess) e = hipEventSynchronize(t1);
+            float ms = 0;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+            if (e == hipSuccess && round > 0 && ms < tbest[c]) tbest[c] = ms;
+        }
+    int ib = 0;
+    for (int c = 1; c < nc; ++c)
+        if (tbest[c] < tbest[ib]) ib = c;
+    const qed_tuning best = (icur >= 0 && !(tbest[ib] < 0.97f * tbest[icur])) ? keep : cand[ib];
     if (e == hipSuccess) e = hipMemcpyAsync(ctx->next_id, saved_id, 8, hipMemcpyDeviceToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(ctx->status, saved_st, 4, hipMemcpyDeviceToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);

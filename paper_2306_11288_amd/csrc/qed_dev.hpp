@@ -90,21 +90,32 @@ __device__ __forceinline__ double grid_gather(const GridDev &f, const float *__r
     double wx[3], wy[3];
     tsc_w((x - f.gx0) * f.inv_dx, hx, i0, wx);
     tsc_w((y - f.gy0) * f.inv_dy, hy, j0, wy);
-    FT s = 0;
+    // A row's three taps are read by one load of three consecutive nodes s, s+1, s+2, with
+    // s = i0 clamped into [0, nx - 3] (nx >= 3).  Node s + k is tap k - (i0 - s); every tap
+    // on the grid falls in this window and every tap off it falls outside, so slot k takes
+    // that tap's weight, or zero when there is no such tap.  Rows off the grid are read at
+    // row 0 with weight zero.  Zero-weighted terms add exactly zero.
+    const int s = min(max(i0, 0), f.nx - 3), d = i0 - s;
+    FT ws[3], wr[3];
+    int jj[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int a = k - d, j = j0 + k;
+        ws[k] = (FT)(a == 0 ? wx[0] : a == 1 ? wx[1] : a == 2 ? wx[2] : 0.0);
+        const bool iny = j >= 0 && j < f.ny;
+        jj[k] = iny ? j : 0;
+        wr[k] = iny ? (FT)wy[k] : (FT)0;
+    }
+    // 32-bit byte offsets from the array base (grids hold fewer than 2^29 nodes)
+    const char *gb = (const char *)g;
+    FT sum = 0;
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
-        const int j = j0 + b;
-        if (j < 0 || j >= f.ny) continue;
-        FT row = 0;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            const int i = i0 + a;
-            if (i < 0 || i >= f.nx) continue;
-            row += (FT)(wx[a] * wy[b]) * (FT)g[(int64_t)j * f.nx + i];
-        }
-        s += row;
+        const float *row = (const float *)(gb + 4u * ((uint32_t)jj[b] * (uint32_t)f.nx + (uint32_t)s));
+        const float v0 = row[0], v1 = row[1], v2 = row[2];
+        sum += wr[b] * (ws[0] * (FT)v0 + ws[1] * (FT)v1 + ws[2] * (FT)v2);
     }
-    return (double)s;
+    return (double)sum;
 }
 
 // Laser pulses (plane wave E = -dA/dphi with a sin^2 envelope; paraxial Gaussian beam at

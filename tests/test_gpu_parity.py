@@ -351,6 +351,43 @@ def test_gathered_fields_both_precisions(kind):
         assert err < tol, (prec, err)
 
 
+@pytest.mark.parametrize("nx,ny", [(3, 1), (7, 5), (40, 24)])
+def test_grid_gather_edges(nx, ny):
+    """TSC gather from a 2D grid of random values at positions inside, on the border of and
+    beyond the grid in both directions (taps partly or wholly off the grid), for the
+    narrowest grid the kernels accept and ragged ones: FP64 to rounding, mixed within
+    single-precision error."""
+    _say(f"grid gather edges {nx}x{ny}")
+    rng = np.random.default_rng(7 + nx)
+    dx, dy, gx0, gy0 = 0.7, 0.45, -1.3, 2.1
+    comps = [rng.uniform(-1.0, 1.0, (ny, nx)).astype(np.float32) for _ in range(6)]
+    spec_o = dict(kind=W.FIELD_GRID2D, grid=comps, nx=nx, ny=ny, dx=dx, dy=dy, gx0=gx0, gy0=gy0)
+    spec_g = dict(spec_o, grid=[torch.as_tensor(c).cuda() for c in comps])
+    n = 1500
+    st = W.beam(n, seed=70 + nx, gamma0=10.0, gamma_rel_spread=0.1, divergence=1e-2, x_mean=0.0, x_sigma=1.0,
+                r_sigma=1.0)
+    st["x"] = gx0 + dx * rng.uniform(-3.0, nx + 2.0, n)
+    st["y"] = gy0 + dy * rng.uniform(-3.0, ny + 2.0, n)
+    want = np.zeros((n, 6))
+    for j in range(n):
+        E, B = oracle.field_eval(spec_o, 0.0, [st["x"][j], st["y"][j], st["z"][j]])
+        want[j, :3], want[j, 3:] = E, B
+    off = np.all(want == 0.0, axis=1)
+    assert off.any() and np.sum(~off) > 300    # both wholly-off and on-grid positions
+    cfg = W.c1(10)
+    for prec, tol in ((Q.QED_FP64, 1e-12), (Q.QED_MIXED, 2e-6)):
+        ctx = _ctx(cfg, precision=prec)
+        Lg = Q.Leptons.from_state(st, precision=prec)
+        E6 = torch.zeros(n * 6, dtype=torch.float64, device="cuda")
+        ctx.gather(Q.whole(spec_g), Lg, E6, 0)
+        got = E6.view(n, 6).cpu().numpy()
+        err = np.max(np.abs(got - want))
+        assert err < tol, (prec, err)
+    with pytest.raises(RuntimeError):
+        narrow = dict(spec_g, nx=2, grid=[c[:, :2].contiguous() for c in spec_g["grid"]])
+        ctx.gather(Q.whole(narrow), Lg, E6, 0)
+
+
 def test_step_events_bracket_the_launches():
     """qed_set_step_events: the four events bracket decide, scan and event kernel in order,
     and switching them off leaves the results unchanged (bitwise)."""
