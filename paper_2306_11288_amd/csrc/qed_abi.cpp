@@ -87,6 +87,13 @@ FieldDev qed::field_dev(const qed_field &f) {
         p.zr = 0.5 * p.w0sq;
         p.inv_zr = p.zr > 0 ? 1.0 / p.zr : 0.0;
         p.inv_w0sq = p.w0sq > 0 ? 1.0 / p.w0sq : 0.0;
+        p.f_a0 = (float)p.a0;
+        p.f_pi_over_L = (float)p.pi_over_L;
+        p.f_cp = (float)p.cp;
+        p.f_sp = (float)p.sp;
+        p.f_zr = (float)p.zr;
+        p.f_inv_zr = (float)p.inv_zr;
+        p.f_inv_w0sq = (float)p.inv_w0sq;
     }
     return d;
 }

@@ -41,8 +41,10 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32
             k0 += 0x9E3779B9u;
             k1 += 0xBB67AE85u;
         }
-        const uint32_t lo0 = 0xD2511F53u * c[0], hi0 = __umulhi(0xD2511F53u, c[0]);
-        const uint32_t lo1 = 0xCD9E8D57u * c[2], hi1 = __umulhi(0xCD9E8D57u, c[2]);
+        // one 32 x 32 -> 64-bit product gives both halves (a single v_mad_u64_u32)
+        const uint64_t m0 = (uint64_t)0xD2511F53u * c[0], m1 = (uint64_t)0xCD9E8D57u * c[2];
+        const uint32_t lo0 = (uint32_t)m0, hi0 = (uint32_t)(m0 >> 32);
+        const uint32_t lo1 = (uint32_t)m1, hi1 = (uint32_t)(m1 >> 32);
         const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
         c[0] = n0;
         c[1] = lo1;
@@ -139,19 +141,19 @@ __device__ __forceinline__ void field_pulse(const FieldDev &f, double t, double 
         const double rev = frac_rev((phi + P.phase0) * INV_2PI);
         if constexpr (KIND == QED_FIELD_PW) {
             // d env / d phi = (pi/L) sin(2 pi phi / L)
-            const float denv = (float)P.pi_over_L * __builtin_amdgcn_sinf((float)frac_rev(phi * P.inv_L));
+            const float denv = P.f_pi_over_L * __builtin_amdgcn_sinf((float)frac_rev(phi * P.inv_L));
             const float ss = __builtin_amdgcn_sinf((float)rev), cs = __builtin_amdgcn_cosf((float)rev);
-            const float a0 = (float)P.a0;
+            const float a0 = P.f_a0;
             c1 = -a0 * (denv * ss + env * cs);
             c2 = f.circular ? -a0 * (denv * cs - env * ss) : 0.0f;
         } else {
-            const float zr = (float)P.zr;
+            const float zr = P.f_zr;
             const float xi = (float)(P.x_focus - x);
             const float rho2 = (float)(y * y + z * z);
-            const float q = xi * (float)P.inv_zr, opq = 1.0f + q * q, iopq = rcp(opq);
+            const float q = xi * P.f_inv_zr, opq = 1.0f + q * q, iopq = rcp(opq);
             constexpr float LOG2E = 1.4426950408889634f;
-            const float amp = (float)P.a0 * __builtin_amdgcn_rsqf(opq) *
-                              __builtin_amdgcn_exp2f(-LOG2E * rho2 * (float)P.inv_w0sq * iopq);
+            const float amp = P.f_a0 * __builtin_amdgcn_rsqf(opq) *
+                              __builtin_amdgcn_exp2f(-LOG2E * rho2 * P.f_inv_w0sq * iopq);
             const float small = atanf(q) - 0.5f * rho2 * xi * rcp(xi * xi + zr * zr);
             const float ph = (float)rev + small * (float)INV_2PI;
             const float ss = __builtin_amdgcn_sinf(ph), cs = __builtin_amdgcn_cosf(ph);
@@ -183,7 +185,14 @@ __device__ __forceinline__ void field_pulse(const FieldDev &f, double t, double 
             c2 = f.circular ? amp * env * ss : 0.0;
         }
     }
-    const FT cp = (FT)P.cp, sp = (FT)P.sp;
+    FT cp, sp;
+    if constexpr (sizeof(FT) == 4) {
+        cp = P.f_cp;
+        sp = P.f_sp;
+    } else {
+        cp = P.cp;
+        sp = P.sp;
+    }
     E.y = (double)(c1 * cp - c2 * sp);
     E.z = (double)(c1 * sp + c2 * cp);
     B.y = E.z;
@@ -242,26 +251,33 @@ __device__ __forceinline__ double boris(double q, double dt, const V3<double> &E
 // gamma^n = sqrt(1+|p-|^2) (passed as ig = 1/gamma^n), beta^n = (p- + p+)/(2 gamma^n),
 // g/2 - 1 = a_e.
 template <class T>
-__device__ __forceinline__ void bmt(double q, double a_e, double dt, const V3<double> &E, const V3<double> &B,
+__device__ __forceinline__ void bmt(const Consts &c, double q, const V3<double> &E, const V3<double> &B,
                                     const V3<double> &pm, const V3<double> &pp, double ig, V3<T> &S) {
     const double gd = (1.0 + dot(pm, pm)) * ig;
     const V3<T> beta = cvt<T>((0.5 * ig) * (pm + pp));
     const V3<T> Et = cvt<T>(E), Bt = cvt<T>(B);
-    const T g = (T)gd, ae = (T)a_e, igp = rcp(g + (T)1);
+    // q = +-1, so (T)(q dt/2) = q (T)(dt/2) exactly
+    T ae, hqdt;
+    if constexpr (sizeof(T) == 4) {
+        ae = c.f_a_e;
+        hqdt = (float)q * c.f_half_dt;
+    } else {
+        ae = c.a_e;
+        hqdt = 0.5 * q * c.dt;
+    }
+    const T g = (T)gd, igp = rcp(g + (T)1);
     const T c1 = -ae * g * igp * dot(beta, Bt), c2 = ae + (T)ig, c3 = ae + igp;
     const V3<T> om = c1 * beta + c2 * Bt - c3 * cross(beta, Et);
-    const V3<T> tv = (T)(0.5 * q * dt) * om;
+    const V3<T> tv = hqdt * om;
     const V3<T> o = ((T)2 * rcp((T)1 + dot(tv, tv))) * tv;
     const V3<T> Sp = S + cross(S, tv);
     S = S + cross(Sp, o);
 }
 // chi_e = xi_L sqrt((gamma E + p x B)^2 - (p.E)^2)
 // (the square root in the precision T of the rates it feeds)
+// from v = gamma E + p x B and p.E
 template <class T>
-__device__ __forceinline__ double chi_e(double xi_L, double g, const V3<double> &p, const V3<double> &E,
-                                        const V3<double> &B) {
-    const V3<double> v = g * E + cross(p, B);
-    const double pe = dot(p, E);
+__device__ __forceinline__ double chi_of(double xi_L, const V3<double> &v, double pe) {
     const double s = dot(v, v) - pe * pe;
     if constexpr (sizeof(T) == 4) return xi_L * (double)__builtin_amdgcn_sqrtf(s > 0.0 ? (float)s : 0.0f);
     return xi_L * sqrt(s > 0.0 ? s : 0.0);
@@ -479,6 +495,9 @@ __device__ __forceinline__ void ncs_F(T u, T I, T K1, T K2, const V3<T> &Si, con
 // x^n (Sec. III.C.1): n = p/|p|, a = unit transverse part of q(E + beta x B - beta(beta.E)),
 // b = n x a, s = S.b, W = C Ia, W_tot = C (Ia - s Ib), C = alpha/(sqrt3 pi xi_L gamma).
 // Returns false where chi = 0 or the acceleration vanishes (nothing happens then).
+// Both chi and a come from v = gamma E + p x B: chi = xi_L sqrt(|v|^2 - (p.E)^2), and as
+// beta is parallel to n, the part of E + beta x B - beta(beta.E) transverse to n is the
+// transverse part of v divided by gamma.
 template <class T>
 struct NcsFrame {
     double chi, C, W, Wt, P;
@@ -491,17 +510,15 @@ __device__ __forceinline__ bool ncs_frame(const Consts &c, const T *rate, double
                                           double ig, const V3<T> &S, const V3<double> &E, const V3<double> &B,
                                           uint32_t &st, NcsFrame<T> &f) {
     const double pp2 = dot(p, p), g = (1.0 + pp2) * ig;
-    f.chi = chi_e<T>(c.xi_L, g, p, E, B);
+    const V3<double> v = g * E + cross(p, B);
+    f.chi = chi_of<T>(c.xi_L, v, dot(p, E));
     if (!(f.chi > 0.0) || !(pp2 > 0.0)) return false;
     const V3<double> nd = rsqrt(pp2) * p;
-    const V3<double> beta = ig * p;
-    const double be = dot(beta, E);
-    const V3<double> acc = q * (E + cross(beta, B) - be * beta);
-    const V3<double> ad = acc - dot(nd, acc) * nd;
+    const V3<double> ad = v - dot(nd, v) * nd;
     const double a2 = dot(ad, ad);
     if (!(a2 > 0.0)) return false;
     f.n = cvt<T>(nd);
-    f.a = cvt<T>(rsqrt(a2) * ad);
+    f.a = cvt<T>((q * rsqrt(a2)) * ad);
     f.b = cross(f.n, f.a);
     f.s = dot(S, f.b);
     ncs_rate<T>(rate, f.chi, f.Ia, f.Ib, st);

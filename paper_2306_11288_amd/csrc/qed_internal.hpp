@@ -48,6 +48,7 @@ struct Consts {
     double c_ncs;      // alpha / (sqrt3 pi xi_L): NCS rate prefactor times gamma
     uint64_t seed;
     uint32_t procs;
+    float f_a_e, f_half_dt;   // a_e and dt/2 rounded to single precision
 };
 
 // A field as the kernels use it: the quantities that are uniform over a segment
@@ -59,6 +60,9 @@ struct PulseDev {                // QED_FIELD_PW, QED_FIELD_GAUSS
     double inv_L, inv_2L;        // 1/L, 1/(2L): the envelope phases in revolutions
     double cp, sp;               // e1 = (0, cp, sp), e2 = (0, -sp, cp)
     double x_focus, zr, inv_zr, w0sq, inv_w0sq;
+    // single-precision copies for the FP32 pulse (rounded once here: uniform conversions
+    // in a kernel would run on the vector unit of every wave)
+    float f_a0, f_pi_over_L, f_cp, f_sp, f_zr, f_inv_zr, f_inv_w0sq;
 };
 struct GridDev {                 // QED_FIELD_GRID2D
     const float *g[6];

@@ -185,7 +185,7 @@ struct LeptonArgs {
     void *stg;
     int *tile_counts;
     int *group_tot;
-    int ev_group;              // tiles per event group
+    int ev_group, ev_shift;    // tiles per event group and its log2
     float *ev_in;              // learned sampler: per-event network inputs [events][4]
     const float *ev_out;       // and outputs [events][3]
     const int64_t *tile_off;
@@ -199,7 +199,7 @@ __device__ __forceinline__ double push_one(const LeptonArgs &a, double q, double
                                            uint32_t &st) {
     V3<double> pm, pp;
     const double ign = boris(q, dt, E, B, p, pm, pp);
-    bmt<T>(q, a.c.a_e, dt, E, B, pm, pp, ign, S);
+    bmt<T>(a.c, q, E, B, pm, pp, ign, S);
     const double ig = rsqrt(1.0 + dot(p, p));
     r = r + (dt * ig) * p;
     if (!isfinite(p.x + p.y + p.z + r.x + r.y + r.z) || !isfinite((double)(S.x + S.y + S.z))) st |= QED_ST_NAN;
@@ -287,9 +287,10 @@ template <class T, bool PUSH, int FK, bool RATE_LDS>
 __global__ __launch_bounds__(BLOCK) void k_leptons_decide(LeptonArgs a) {
     __shared__ int s_wave[2][BLOCK / 64];
     __shared__ T s_rate[RATE_LDS ? 2 * NR : 1];
-    const int64_t n = clamp_count(a.L.count, a.L.capacity);
-    const int64_t ntiles = (n + BLOCK - 1) / BLOCK;
-    if ((int64_t)blockIdx.x >= ntiles) return;
+    // 32-bit indices: lists hold at most 2^28 particles
+    const int n = (int)clamp_count(a.L.count, a.L.capacity);
+    const int ntiles = (n + BLOCK - 1) / BLOCK;
+    if ((int)blockIdx.x >= ntiles) return;
     const Tabs<T> tb = {(const T *)a.tab};
     const T *rate = tb.ncs_rate();
     if constexpr (RATE_LDS) {
@@ -301,8 +302,8 @@ __global__ __launch_bounds__(BLOCK) void k_leptons_decide(LeptonArgs a) {
     const double t = (double)step * a.c.dt, q = (double)a.L.charge;
     uint32_t st = 0;
     int par = 0;
-    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x, par ^= 1) {
-        const int64_t base = tile * BLOCK, i = base + threadIdx.x;
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x, par ^= 1) {
+        const int base = tile * BLOCK, i = base + (int)threadIdx.x;
         bool ev = false;
         V3<double> r, p, E, B;
         V3<T> S;
@@ -321,7 +322,7 @@ __global__ __launch_bounds__(BLOCK) void k_leptons_decide(LeptonArgs a) {
         int total;
         const int rank = block_rank(ev, total, s_wave[par]);
         if (ev) {
-            LepEvent<T> &o = ((LepEvent<T> *)a.stg)[base + rank];
+            LepEvent<T> &o = ((LepEvent<T> *)a.stg)[(int64_t)(base + rank)];
             o.i = i;
             o.id = at(a.L.id, (uint32_t)i * 8u);
             o.w = at(a.L.w, (uint32_t)i * 8u);
@@ -333,7 +334,7 @@ __global__ __launch_bounds__(BLOCK) void k_leptons_decide(LeptonArgs a) {
         }
         if (threadIdx.x == 0) {
             a.tile_counts[tile] = total;
-            if (total) atomicAdd(a.group_tot + tile / a.ev_group, total);
+            if (total) atomicAdd(a.group_tot + (tile >> a.ev_shift), total);
         }
     }
     if (st) atomicOr(a.status, st);
@@ -592,7 +593,8 @@ __global__ __launch_bounds__(BLOCK) void k_compact_copy(CompactArgs a) {
 // ------------------------------------------------------------------------- launchers
 static Consts consts_of(const qed_ctx *ctx) {
     const qed_config &g = ctx->cfg;
-    return {g.xi_L, g.alpha, g.a_e, g.dt, g.p_max, g.alpha / (SQRT3 * PI * g.xi_L), g.seed, g.procs};
+    return {g.xi_L, g.alpha, g.a_e, g.dt, g.p_max, g.alpha / (SQRT3 * PI * g.xi_L), g.seed, g.procs,
+            (float)g.a_e, (float)(0.5 * g.dt)};
 }
 static int tiles_grid(int64_t cap, int64_t tile = BLOCK) {
     const int64_t b = (cap + tile - 1) / tile;
@@ -652,6 +654,7 @@ template <class T, bool PUSH, int FK>
 static hipError_t launch_ncs(qed_ctx *ctx, const LeptonArgs &a0, hipStream_t s) {
     LeptonArgs a = a0;
     a.ev_group = ctx->tune.ev_group;
+    a.ev_shift = a.ev_group == 4 ? 2 : (a.ev_group == 16 ? 4 : 3);
     auto mark = [&](int k) { return ctx->step_ev_on ? hipEventRecord(ctx->step_ev[k], s) : hipSuccess; };
     hipError_t e = mark(0);
     if (e != hipSuccess) return e;
