@@ -352,7 +352,9 @@ __device__ __forceinline__ void ncs_rate(const T *r, double chi, T &Ia, T &Ib, u
 // weight f, at `target`; returns the fractional column.  The bracket [lo, lo + 1] is the
 // last column with D <= target and its successor (D is non-decreasing), found by an
 // 8-way search: each round probes 7 columns with independent loads, so 1024 columns take
-// 4 dependent rounds of memory traffic instead of 10.
+// 4 dependent rounds of memory traffic instead of 10.  The values of D at the bracket
+// ends are carried along from the probes (the end columns are loaded with the first
+// round), so the interpolation needs no further round.
 template <class T>
 __device__ __forceinline__ T cdf_at(const T *__restrict__ R0, const T *__restrict__ R1, int j, T g, T f, T m) {
     const T a = g * R0[2 * j] + f * R1[2 * j];
@@ -365,9 +367,12 @@ __device__ __forceinline__ T cdf_invert(const T *__restrict__ R0, const T *__res
     constexpr int K = 8;
     int lo = 0, hi = ncol - 1;
     const T g = (T)1 - f;
+    T dlo = cdf_at<T>(R0, R1, lo, g, f, m), dhi = cdf_at<T>(R0, R1, hi, g, f, m);
+    bool hi_known = true;
     while (hi - lo > 1) {
         const int span = hi - lo;
         int nlo = lo, nhi = hi;
+        T nd_lo = dlo, nd_hi = dhi;
         T d[K - 1];
         int pk[K - 1];
 #pragma unroll
@@ -378,14 +383,24 @@ __device__ __forceinline__ T cdf_invert(const T *__restrict__ R0, const T *__res
 #pragma unroll
         for (int k = 0; k < K - 1; ++k) {
             if (pk[k] <= lo) continue;
-            if (d[k] <= target) nlo = pk[k] > nlo ? pk[k] : nlo;
-            else nhi = pk[k] < nhi ? pk[k] : nhi;
+            if (d[k] <= target) {
+                if (pk[k] > nlo) { nlo = pk[k]; nd_lo = d[k]; }
+            } else if (pk[k] < nhi) {
+                nhi = pk[k];
+                nd_hi = d[k];
+            }
         }
         lo = nlo;
-        hi = nhi > nlo ? nhi : nlo + 1;
+        dlo = nd_lo;
+        if (nhi > nlo) {
+            hi = nhi;
+            dhi = nd_hi;
+        } else {   // probes out of order (D flat within rounding): step past lo
+            hi = nlo + 1;
+            hi_known = false;
+        }
     }
-    const T dlo = cdf_at<T>(R0, R1, lo, g, f, m);
-    const T dhi = cdf_at<T>(R0, R1, hi, g, f, m);
+    if (!hi_known) dhi = cdf_at<T>(R0, R1, hi, g, f, m);
     T tau = dhi > dlo ? (target - dlo) / (dhi - dlo) : (T)0;
     tau = tau < (T)0 ? (T)0 : (tau > (T)1 ? (T)1 : tau);
     return (T)lo + tau;
