@@ -211,14 +211,17 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
     const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
     const int kb = blockIdx.z * g.kslice, ke = kb + g.kslice < g.K ? kb + g.kslice : g.K;
+    const bool a_k_fast = g.sak == 1 && g.sam != 1, b_k_fast = g.sbk == 1 && g.sbn != 1;
     float acc[4][4] = {};
     for (int k0 = kb; k0 < ke; k0 += 16) {
+        // consecutive threads walk the operand's contiguous dimension (coalesced loads)
         for (int e = threadIdx.x; e < 16 * 64; e += 256) {
-            const int kk = e / 64, mm = e % 64;
+            const int kk = a_k_fast ? e % 16 : e / 64, mm = a_k_fast ? e / 16 : e % 64;
             const int m = m0 + mm, k = k0 + kk;
             sA[kk][mm] = (m < g.M && k < ke) ? g.A[(int64_t)m * g.sam + (int64_t)k * g.sak] : 0.0f;
-            const int nn = e % 64, n = n0 + nn;
-            sBt[kk][nn] = (n < g.N && k < ke) ? g.B[(int64_t)k * g.sbk + (int64_t)n * g.sbn] : 0.0f;
+            const int kb2 = b_k_fast ? e % 16 : e / 64, nn = b_k_fast ? e / 16 : e % 64;
+            const int n = n0 + nn, k2 = k0 + kb2;
+            sBt[kb2][nn] = (n < g.N && k2 < ke) ? g.B[(int64_t)k2 * g.sbk + (int64_t)n * g.sbn] : 0.0f;
         }
         __syncthreads();
 #pragma unroll
@@ -280,16 +283,23 @@ __global__ void k_silu_back(const float *dH, const float *Z, float *dZ, int64_t 
     if (k < n) dZ[k] = dH[k] * silu_prime(Z[k]);
 }
 
-// column sums of D [rows][ncol] in slices of rows: part[slice][col]
+// column sums of D [rows][ncol] in slices of rows: part[slice][col].  A block covers 64
+// columns of one slice; its four row lanes take every fourth row and are added in a fixed
+// order, so the sums do not depend on scheduling.
 __global__ __launch_bounds__(256) void k_colsum(const float *D, int64_t rows, int ncol, int rows_per_slice,
                                                 float *part) {
-    const int col = blockIdx.x * 256 + threadIdx.x;
-    if (col >= ncol) return;
+    __shared__ float s_part[4][64];
+    const int cl = threadIdx.x & 63, rl = threadIdx.x >> 6;
+    const int col = blockIdx.x * 64 + cl;
     const int64_t r0 = (int64_t)blockIdx.y * rows_per_slice;
     const int64_t r1 = r0 + rows_per_slice < rows ? r0 + rows_per_slice : rows;
     float s = 0;
-    for (int64_t r = r0; r < r1; ++r) s += D[r * ncol + col];
-    part[(int64_t)blockIdx.y * ncol + col] = s;
+    if (col < ncol)
+        for (int64_t r = r0 + rl; r < r1; r += 4) s += D[r * ncol + col];
+    s_part[rl][cl] = s;
+    __syncthreads();
+    if (rl == 0 && col < ncol)
+        part[(int64_t)blockIdx.y * ncol + col] = ((s_part[0][cl] + s_part[1][cl]) + s_part[2][cl]) + s_part[3][cl];
 }
 // out[k] = sum over slices of part[slice][k], slices in order (deterministic)
 __global__ void k_sum_slices(const float *part, int nslice, int64_t len, float *out) {
@@ -398,7 +408,9 @@ hipError_t gemm(const float *A, int64_t sam, int64_t sak, const float *B, int64_
 hipError_t mlp_grad(qed_ctx *ctx, const float *X, const float *T, int64_t n, const float w[3], float *loss,
                     hipStream_t s) {
     const int64_t B = n;
-    constexpr int NS = 16;   // K slices of the weight gradients
+    constexpr int NS = 64;    // K slices of the weight gradients (64 x 64 tiles x slices fill the chip)
+    constexpr int NSB = 128;  // row slices of the bias gradients
+    static_assert(NSB * 128 <= NS * 128 * 128, "bias partial sums fit the slice buffer");
     const int64_t need = (int64_t)(3 * 2 * B * 128 + 2 * B * 3 + NS * 128 * 128 + 1024 + 64);
     if (need > ctx->mlp_work_len) {
         hipFree(ctx->mlp_work);
@@ -441,10 +453,10 @@ hipError_t mlp_grad(qed_ctx *ctx, const float *X, const float *T, int64_t n, con
         hipLaunchKernelGGL(k_sum_slices, dim3((l.in * l.out + 255) / 256), dim3(256), 0, s, part, NS,
                            (int64_t)l.in * l.out, G + l.ow);
         QED_TRY(hipGetLastError());
-        const int rps = (int)((B + NS - 1) / NS);
-        hipLaunchKernelGGL(k_colsum, dim3((l.out + 255) / 256, NS), dim3(256), 0, s, dZ, B, l.out, rps, part);
+        const int rps = (int)((B + NSB - 1) / NSB);
+        hipLaunchKernelGGL(k_colsum, dim3((l.out + 63) / 64, NSB), dim3(256), 0, s, dZ, B, l.out, rps, part);
         QED_TRY(hipGetLastError());
-        hipLaunchKernelGGL(k_sum_slices, dim3((l.out + 255) / 256), dim3(256), 0, s, part, NS, (int64_t)l.out,
+        hipLaunchKernelGGL(k_sum_slices, dim3((l.out + 255) / 256), dim3(256), 0, s, part, NSB, (int64_t)l.out,
                            G + l.ob);
         QED_TRY(hipGetLastError());
         if (L == 0) break;
