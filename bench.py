@@ -310,6 +310,7 @@ def run_learned(args, torch, Q, W, cfg, fp64):
     return out
 
 
+# photon step: read x, k, xi, e1, id, alive; write x, xi, e1
 BYTES_PHOTON_STEP = {"mixed": 24 + 24 + 12 + 12 + 8 + 1 + 24 + 12 + 12, "fp64": 24 + 24 + 24 + 24 + 8 + 1 + 24 + 24 + 24}
 
 
