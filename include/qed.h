@@ -250,7 +250,7 @@ qed_status qed_mlp_gradient(qed_ctx_t *ctx, const float *X, const float *T, int6
 qed_status qed_mlp_train_step(qed_ctx_t *ctx, const float *X, const float *T, int64_t n, const float *w, float lr,
                               float *loss_out, hipStream_t stream);
 /* the table sampler on the same normalised inputs and outputs (tables of the context's
- * precision): the judge of the network and its fallback                               */
+ * precision): the reference for the network's error and its fallback                */
 qed_status qed_sampler_table(qed_ctx_t *ctx, const float *X, float *Y, int64_t n, hipStream_t stream);
 /* which sampler later NCS emissions use: QED_SAMPLER_TABLE (default) or QED_SAMPLER_MLP
  * (the network inside its trained chi range, the table outside it)                     */

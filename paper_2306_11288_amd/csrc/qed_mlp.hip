@@ -2,7 +2,7 @@
 // (log chi, S.b, S.n, energy draw) to the photon-fraction variable t = (2u/(3 chi))^(1/3)
 // and the spin-summed mean photon Stokes xi3, xi2 (eqs. F0-F3 of Sec. III.C.1 summed over
 // the final spins).  It replaces the table inverse-CDF search of an emission; the table
-// sampler stays as the fallback outside the trained range and as the judge of its error.
+// sampler stays as the fallback outside the trained range and as the reference for its error.
 //
 //   * inference: k_mlp_forward, BF16 MFMA (v_mfma_f32_32x32x16_bf16) with FP32
 //     accumulation for the two 128 x 128 layers, weights and activations in LDS;
@@ -91,7 +91,13 @@ __global__ __launch_bounds__(BLOCK) void k_table_sampler(const T *tab, const flo
 }
 
 // ------------------------------------------------------------------------- inference
-// One block = 8 wavefronts; a wavefront takes 32 samples at a time (one 32-row MFMA tile).
+// One block = 8 wavefronts; a wavefront takes 32 samples at a time (one 32-column MFMA
+// tile).  The matrix-core layers compute the transposed product D[out][sample] =
+// W^T[out][in] H^T[in][sample]: the weights are the A operand (rows of the transposed
+// weights in LDS), the activations the B operand (rows of the wavefront's activation tile
+// in LDS), so a lane's 16 results per 32 outputs are four runs of four consecutive
+// outputs of one sample and go back to LDS as four 8-byte stores.  Layer 3's outputs stay
+// in registers and feed layer 4 (FP32 weights) directly.
 // LDS: the two 128 x 128 weight matrices transposed ([out][in], bf16, rows padded to HS)
 // and one activation tile per wavefront (32 x 128 bf16, padded).
 struct FwdArgs {
@@ -103,10 +109,15 @@ struct FwdArgs {
     const int64_t *n_dev;  // optional device count (used when non-null)
 };
 
+typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
+
 __global__ __launch_bounds__(MB) void k_mlp_forward(FwdArgs a) {
     __shared__ __attribute__((aligned(16))) __bf16 sW[2 * 128 * HS];
     __shared__ __attribute__((aligned(16))) __bf16 sH[(MB / 64) * 32 * HS];
-    __shared__ float sW1[4 * 128], sB[3 * 128], sW4[128 * 3], sB4[4];
+    __shared__ __attribute__((aligned(16))) float sW1[4 * 128];
+    __shared__ __attribute__((aligned(16))) float sB[3 * 128];
+    __shared__ __attribute__((aligned(16))) float sW4[128 * 4];   // [in][4]: W4 row, then 0
+    __shared__ float sB4[4];
     const int64_t n = a.n_dev ? *a.n_dev : a.n;
     const int64_t ntile = (n + 31) / 32;
     if ((int64_t)blockIdx.x * (MB / 64) >= ntile) return;
@@ -117,7 +128,7 @@ __global__ __launch_bounds__(MB) void k_mlp_forward(FwdArgs a) {
         sB[128 + k] = a.P[MLP_OB2 + k];
         sB[256 + k] = a.P[MLP_OB3 + k];
     }
-    for (int k = threadIdx.x; k < 128 * 3; k += MB) sW4[k] = a.P[MLP_OW4 + k];
+    for (int k = threadIdx.x; k < 128 * 4; k += MB) sW4[k] = (k & 3) < 3 ? a.P[MLP_OW4 + (k >> 2) * 3 + (k & 3)] : 0.0f;
     if (threadIdx.x < 3) sB4[threadIdx.x] = a.P[MLP_OB4 + threadIdx.x];
     __syncthreads();
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -130,54 +141,89 @@ __global__ __launch_bounds__(MB) void k_mlp_forward(FwdArgs a) {
             const float4 v = ((const float4 *)a.X)[smp];
             x[0] = v.x; x[1] = v.y; x[2] = v.z; x[3] = v.w;
         }
-        // layer 1 (4 -> 128) on the VALU: this lane's row, 64 of the 128 columns
-        for (int j = 0; j < 64; ++j) {
-            const int col = half * 64 + j;
-            float z = sB[col];
+        // layer 1 (4 -> 128, FP32 on the VALU): this lane's sample, columns half 64 .. +64,
+        // eight at a time (vector LDS reads of the weights, one 16-byte store)
+        for (int j0 = 0; j0 < 64; j0 += 8) {
+            const int c0 = half * 64 + j0;
+            float z[8];
+            const float4 b0 = *(const float4 *)(sB + c0), b1 = *(const float4 *)(sB + c0 + 4);
+            z[0] = b0.x; z[1] = b0.y; z[2] = b0.z; z[3] = b0.w;
+            z[4] = b1.x; z[5] = b1.y; z[6] = b1.z; z[7] = b1.w;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) z += x[i] * sW1[i * 128 + col];
-            H[row * HS + col] = (__bf16)silu(z);
+            for (int i = 0; i < 4; ++i) {
+                const float4 w0 = *(const float4 *)(sW1 + i * 128 + c0), w1 = *(const float4 *)(sW1 + i * 128 + c0 + 4);
+                z[0] += x[i] * w0.x; z[1] += x[i] * w0.y; z[2] += x[i] * w0.z; z[3] += x[i] * w0.w;
+                z[4] += x[i] * w1.x; z[5] += x[i] * w1.y; z[6] += x[i] * w1.z; z[7] += x[i] * w1.w;
+            }
+            bf16x8 hv;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) hv[j] = (__bf16)silu(z[j]);
+            *(bf16x8 *)(H + row * HS + c0) = hv;
         }
-        // layers 2, 3 (128 -> 128) on the matrix cores
+        // layers 2, 3 (128 -> 128) on the matrix cores; D element v of this lane is output
+        // ct 32 + 8 (v / 4) + 4 half + v % 4 of sample `row`
+        float y[3] = {0.0f, 0.0f, 0.0f};
         for (int L = 0; L < 2; ++L) {
             const __bf16 *WL = sW + L * 128 * HS;
+            const float *bL = sB + (L + 1) * 128;
             f32x16 acc[4];
-#pragma unroll
-            for (int ct = 0; ct < 4; ++ct) {
-                const float bv = sB[(L + 1) * 128 + ct * 32 + row];
-#pragma unroll
-                for (int v = 0; v < 16; ++v) acc[ct][v] = bv;
-            }
-#pragma unroll
-            for (int kk = 0; kk < 8; ++kk) {
-                const bf16x8 av = *(const bf16x8 *)(H + row * HS + kk * 16 + half * 8);
-#pragma unroll
-                for (int ct = 0; ct < 4; ++ct) {
-                    const bf16x8 bv = *(const bf16x8 *)(WL + (ct * 32 + row) * HS + kk * 16 + half * 8);
-                    acc[ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[ct], 0, 0, 0);
-                }
-            }
-            // D element v of this lane: row 8 (v / 4) + 4 half + v % 4, column ct 32 + row
 #pragma unroll
             for (int ct = 0; ct < 4; ++ct)
 #pragma unroll
-                for (int v = 0; v < 16; ++v)
-                    H[(8 * (v >> 2) + 4 * half + (v & 3)) * HS + ct * 32 + row] = (__bf16)silu(acc[ct][v]);
-        }
-        // layer 4 (128 -> 3) on the VALU: half 0 computes outputs 0 and 1, half 1 output 2
-        float y0 = sB4[half == 0 ? 0 : 2], y1 = sB4[1];
-        for (int i = 0; i < 128; ++i) {
-            const float h = (float)H[row * HS + i];
-            y0 += h * sW4[i * 3 + (half == 0 ? 0 : 2)];
-            y1 += h * sW4[i * 3 + 1];
-        }
-        if (smp < n) {
-            if (half == 0) {
-                a.Y[3 * smp + 0] = y0;
-                a.Y[3 * smp + 1] = y1;
-            } else {
-                a.Y[3 * smp + 2] = y0;
+                for (int g = 0; g < 4; ++g) {
+                    const float4 bv = *(const float4 *)(bL + ct * 32 + 8 * g + 4 * half);
+                    acc[ct][4 * g + 0] = bv.x; acc[ct][4 * g + 1] = bv.y;
+                    acc[ct][4 * g + 2] = bv.z; acc[ct][4 * g + 3] = bv.w;
+                }
+#pragma unroll
+            for (int kk = 0; kk < 8; ++kk) {
+                const bf16x8 hv = *(const bf16x8 *)(H + row * HS + kk * 16 + half * 8);
+#pragma unroll
+                for (int ct = 0; ct < 4; ++ct) {
+                    const bf16x8 wv = *(const bf16x8 *)(WL + (ct * 32 + row) * HS + kk * 16 + half * 8);
+                    acc[ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wv, hv, acc[ct], 0, 0, 0);
+                }
             }
+            if (L == 0) {
+                // layer-2 activations back over the tile (every read of it above is done)
+#pragma unroll
+                for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+                    for (int g = 0; g < 4; ++g) {
+                        bf16x4 q;
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) q[r] = (__bf16)silu(acc[ct][4 * g + r]);
+                        *(bf16x4 *)(H + row * HS + ct * 32 + 8 * g + 4 * half) = q;
+                    }
+            } else {
+                // layer 4 (128 -> 3): this lane's 64 layer-3 outputs (rounded to bf16 like a
+                // stored activation) times the FP32 weights; the other half holds the rest
+#pragma unroll
+                for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+                    for (int g = 0; g < 4; ++g) {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const int o = ct * 32 + 8 * g + 4 * half + r;
+                            const float h = (float)(__bf16)silu(acc[ct][4 * g + r]);
+                            const float4 w4 = *(const float4 *)(sW4 + 4 * o);
+                            y[0] += h * w4.x;
+                            y[1] += h * w4.y;
+                            y[2] += h * w4.z;
+                        }
+                        // keep the weight reads of later groups from being hoisted here
+                        // (all 64 at once would not fit in registers)
+                        __builtin_amdgcn_sched_barrier(0);
+                    }
+            }
+        }
+        // the two halves of the wavefront hold the two halves of the layer-4 sums
+#pragma unroll
+        for (int o = 0; o < 3; ++o) y[o] = sB4[o] + (y[o] + __shfl_xor(y[o], 32));
+        if (smp < n && half == 0) {
+            a.Y[3 * smp + 0] = y[0];
+            a.Y[3 * smp + 1] = y[1];
+            a.Y[3 * smp + 2] = y[2];
         }
     }
 }
@@ -413,7 +459,7 @@ hipError_t mlp_grad(qed_ctx *ctx, const float *X, const float *T, int64_t n, con
     static_assert(NSB * 128 <= NS * 128 * 128, "bias partial sums fit the slice buffer");
     const int64_t need = (int64_t)(3 * 2 * B * 128 + 2 * B * 3 + NS * 128 * 128 + 1024 + 64);
     if (need > ctx->mlp_work_len) {
-        hipFree(ctx->mlp_work);
+        (void)hipFree(ctx->mlp_work);
         ctx->mlp_work = nullptr;
         ctx->mlp_work_len = 0;
         hipError_t e = hipMalloc(&ctx->mlp_work, need * sizeof(float));

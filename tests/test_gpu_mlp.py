@@ -107,8 +107,8 @@ def trained():
     return c.mlp_get_params(), None
 
 
-def test_trained_network_against_table_judge(trained):
-    """The table sampler (FP32 tables of a mixed context) judges the network on fresh
+def test_trained_network_against_table_sampler(trained):
+    """The table sampler (FP32 tables of a mixed context) as the reference for the network on fresh
     inputs; the network's weights are 60x smaller than the FP32 spectrum tables."""
     params, res = trained
     c = Q.Context(dt=0.01, procs=Q.PROC_NCS | Q.PROC_NCS_STOKES, seed=1, id_start=0, precision=Q.QED_MIXED)
