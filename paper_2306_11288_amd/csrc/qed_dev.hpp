@@ -626,24 +626,54 @@ struct PairOut {
     V3<T> Sm, Sp;        // spins
 };
 
-// Photon transport at x^n (Algorithm 1): basis rotation of the Stokes vector to the frame
-// of E_red = E - n(n.E) + n x B (eq. rotation) and, if do_vb, the birefringent phase
-// (eq. rotation2).  Returns chi_gamma (0 where E_red vanishes: nothing changes then).
+// A photon's direction, reduced transverse field and chi_gamma: n = k/|k|, E_red =
+// E - n(n.E) + n x B, chi = xi_L eps |E_red| (eps = |k|).  The reciprocal lengths come
+// from one reciprocal square root each (no square root, no division).
+struct PhotonFrame {
+    double eps, inv_eps, an, inv_an, chi;
+    V3<double> n, er;
+};
+__device__ __forceinline__ void photon_frame(double xi_L, const V3<double> &k, const V3<double> &E,
+                                             const V3<double> &B, PhotonFrame &f) {
+    const double kk = dot(k, k);
+    f.inv_eps = rsqrt(kk);
+    f.eps = kk * f.inv_eps;
+    f.n = f.inv_eps * k;
+    f.er = E - dot(f.n, E) * f.n + cross(f.n, B);
+    const double a2 = dot(f.er, f.er);
+    f.inv_an = a2 > 0.0 ? rsqrt(a2) : 0.0;
+    f.an = a2 * f.inv_an;
+    f.chi = xi_L * f.eps * f.an;
+}
+// sin and cos of a small angle |d| < 0.02 by their Taylor series (the first omitted term
+// is below 1e-19 of the result there), of a larger one by the library
 template <class T>
-__device__ __forceinline__ double photon_transport(const Consts &c, const Tabs<T> &tb, const V3<double> &k, V3<T> &xi,
-                                                   V3<T> &e1, const V3<double> &E, const V3<double> &B, bool do_vb,
-                                                   uint32_t &st) {
-    const double eps = sqrt(dot(k, k));
-    const V3<double> n = (1.0 / eps) * k;
-    const V3<double> er = E - dot(n, E) * n + cross(n, B);
-    const double an = sqrt(dot(er, er));
-    if (!(an > 0.0)) return 0.0;
-    const double chi = c.xi_L * eps * an;
-    const V3<T> nt = cvt<T>(n);
-    const V3<T> e1n = cvt<T>((1.0 / an) * er);
+__device__ __forceinline__ void sincos_small(T d, T &sd, T &cd) {
+    if (fabs(d) < (T)0.02) {
+        const T d2 = d * d;
+        sd = d * ((T)1 - d2 * ((T)(1.0 / 6.0) - d2 * ((T)(1.0 / 120.0) - d2 * (T)(1.0 / 5040.0))));
+        cd = (T)1 - d2 * ((T)0.5 - d2 * ((T)(1.0 / 24.0) - d2 * ((T)(1.0 / 720.0) - d2 * (T)(1.0 / 40320.0))));
+    } else if constexpr (sizeof(T) == 8) {
+        sincos(d, &sd, &cd);
+    } else {
+        sincosf(d, &sd, &cd);
+    }
+}
+
+// Photon transport at x^n (Algorithm 1): basis rotation of the Stokes vector to the frame
+// of E_red (eq. rotation) and, if do_vb, the birefringent phase (eq. rotation2), whose
+// chi^2 / (eps xi_L) is written chi |E_red|.  Returns chi_gamma (0 where E_red vanishes:
+// nothing changes then).
+template <class T>
+__device__ __forceinline__ double photon_transport(const Consts &c, const Tabs<T> &tb, const PhotonFrame &f, V3<T> &xi,
+                                                   V3<T> &e1, bool do_vb, uint32_t &st) {
+    if (!(f.an > 0.0)) return 0.0;
+    const double chi = f.chi;
+    const V3<T> nt = cvt<T>(f.n);
+    const V3<T> e1n = cvt<T>(f.inv_an * f.er);
     const V3<T> e2 = cross(nt, e1);
-    const T cp = dot(e1, e1n), sp = dot(e2, e1n), nn = cp * cp + sp * sp;
-    const T c2 = (cp * cp - sp * sp) / nn, s2 = (T)2 * cp * sp / nn;
+    const T cp = dot(e1, e1n), sp = dot(e2, e1n), inn = rcp(cp * cp + sp * sp);
+    const T c2 = (cp * cp - sp * sp) * inn, s2 = (T)2 * cp * sp * inn;
     {
         const T x1 = c2 * xi.x - s2 * xi.z, x3 = s2 * xi.x + c2 * xi.z;
         xi.x = x1;
@@ -653,23 +683,15 @@ __device__ __forceinline__ double photon_transport(const Consts &c, const Tabs<T
     if (do_vb) {
         T Mp, Mm;
         vb_M<T>(tb, chi, Mp, Mm, st);
-        const T dphi = (T)((double)(Mp - Mm) * (c.alpha / (90.0 * PI)) * chi * chi * c.dt / (eps * c.xi_L));
+        constexpr double VB = 1.0 / (90.0 * PI);
+        const T dphi = (T)((double)(Mp - Mm) * (c.alpha * VB) * chi * f.an * c.dt);
         T sd, cd;
-        if constexpr (sizeof(T) == 8) sincos(dphi, &sd, &cd);
-        else sincosf(dphi, &sd, &cd);
+        sincos_small<T>(dphi, sd, cd);
         const T y1 = cd * xi.x - sd * xi.y, y2 = sd * xi.x + cd * xi.y;
         xi.x = y1;
         xi.y = y2;
     }
     return chi;
-}
-// chi_gamma from the stored fields (the same arithmetic as photon_transport)
-__device__ __forceinline__ double photon_chi(double xi_L, const V3<double> &k, const V3<double> &E,
-                                             const V3<double> &B) {
-    const double eps = sqrt(dot(k, k));
-    const V3<double> n = (1.0 / eps) * k;
-    const V3<double> er = E - dot(n, E) * n + cross(n, B);
-    return xi_L * eps * sqrt(dot(er, er));
 }
 // NBW event probability W_pair dt (eq. BWprob with the rate normalisation of the readings)
 template <class T>

@@ -452,8 +452,9 @@ struct PhotonArgs {
     const int64_t *launch;
 };
 
-// transport (+ NBW test): one tile per block when NBW is on, grid-stride otherwise
-template <class T, bool NBW>
+// transport (+ NBW test): one tile per block when NBW is on, grid-stride otherwise;
+// specialised on the field kind
+template <class T, bool NBW, int FK>
 __global__ __launch_bounds__(BLOCK) void k_photons_decide(PhotonArgs a) {
     __shared__ int s_wave[BLOCK / 64];
     const int64_t n = clamp_count(a.G.count, a.G.capacity);
@@ -472,9 +473,11 @@ __global__ __launch_bounds__(BLOCK) void k_photons_decide(PhotonArgs a) {
         if (j < n && a.G.alive[j]) {
             const V3<double> x = {a.G.x[j], a.G.y[j], a.G.z[j]}, k = {a.G.kx[j], a.G.ky[j], a.G.kz[j]};
             V3<T> xi = {xi1[j], xi2[j], xi3[j]}, e1 = {e1x[j], e1y[j], e1z[j]};
-            field_at<T>(a.field, t, x.x, x.y, x.z, E, B);
-            const double chi = photon_transport<T>(a.c, tb, k, xi, e1, E, B, a.do_vb, st);
-            const double eps = sqrt(dot(k, k));
+            field_kind<T, FK>(a.field, t, x.x, x.y, x.z, E, B);
+            PhotonFrame f;
+            photon_frame(a.c.xi_L, k, E, B, f);
+            const double chi = photon_transport<T>(a.c, tb, f, xi, e1, a.do_vb, st);
+            const double eps = f.eps;
             if (NBW && chi > 0.0 && eps >= 2.0) {
                 T Ja, kappa;
                 const double P = nbw_prob<T>(a.c, tb, eps, chi, xi.z, Ja, kappa, st);
@@ -487,7 +490,7 @@ __global__ __launch_bounds__(BLOCK) void k_photons_decide(PhotonArgs a) {
             if (ev) {
                 a.G.alive[j] = 0;
             } else if (a.do_move) {
-                const double ie = a.c.dt / eps;
+                const double ie = a.c.dt * f.inv_eps;
                 a.G.x[j] = x.x + ie * k.x;
                 a.G.y[j] = x.y + ie * k.y;
                 a.G.z[j] = x.z + ie * k.z;
@@ -521,7 +524,9 @@ __global__ __launch_bounds__(BLOCK) void k_photons_events(PhotonArgs a) {
         const V3<double> E = {rec.f[0], rec.f[1], rec.f[2]}, B = {rec.f[3], rec.f[4], rec.f[5]};
         const V3<double> k = {a.G.kx[j], a.G.ky[j], a.G.kz[j]};
         const V3<T> xi = {xi1[j], xi2[j], xi3[j]}, e1 = {e1x[j], e1y[j], e1z[j]};
-        const double chi = photon_chi(a.c.xi_L, k, E, B), eps = sqrt(dot(k, k));
+        PhotonFrame f;   // the same arithmetic as in the decide kernel
+        photon_frame(a.c.xi_L, k, E, B, f);
+        const double chi = f.chi, eps = f.eps;
         T Ja, kappa;
         nbw_prob<T>(a.c, tb, eps, chi, xi.z, Ja, kappa, st);
         double rr[4];
@@ -739,15 +744,25 @@ hipError_t launch_leptons(qed_ctx *ctx, LeptonMode mode, const SegArgs &sa, cons
     return multi ? launch_leptons_t<double, true>(ctx, mode, a, s) : launch_leptons_t<double, false>(ctx, mode, a, s);
 }
 
+template <class T, int FK>
+static void launch_photons_decide(const PhotonArgs &a, hipStream_t s) {
+    if (!a.do_nbw)
+        hipLaunchKernelGGL((k_photons_decide<T, false, FK>), dim3(stride_grid(a.G.capacity, 65536)), dim3(BLOCK), 0, s,
+                           a);
+    else
+        hipLaunchKernelGGL((k_photons_decide<T, true, FK>), dim3(tiles_grid(a.G.capacity)), dim3(BLOCK), 0, s, a);
+}
 template <class T>
 static hipError_t launch_photons_t(qed_ctx *ctx, const PhotonArgs &a, hipStream_t s) {
-    if (!a.do_nbw) {
-        hipLaunchKernelGGL((k_photons_decide<T, false>), dim3(stride_grid(a.G.capacity, 65536)), dim3(BLOCK), 0, s, a);
-        return hipGetLastError();
+    switch (a.field.kind) {
+    case QED_FIELD_CONST: launch_photons_decide<T, QED_FIELD_CONST>(a, s); break;
+    case QED_FIELD_PW: launch_photons_decide<T, QED_FIELD_PW>(a, s); break;
+    case QED_FIELD_GAUSS: launch_photons_decide<T, QED_FIELD_GAUSS>(a, s); break;
+    case QED_FIELD_GRID2D: launch_photons_decide<T, QED_FIELD_GRID2D>(a, s); break;
+    default: launch_photons_decide<T, QED_FIELD_NONE>(a, s); break;
     }
-    hipLaunchKernelGGL((k_photons_decide<T, true>), dim3(tiles_grid(a.G.capacity)), dim3(BLOCK), 0, s, a);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if (e != hipSuccess || !a.do_nbw) return e;
     e = launch_scan(ctx, a.G.count, a.G.capacity, ctx->tile_counts, 0, BLOCK, a.has_em ? a.em.count : nullptr, a.has_em ? a.em.capacity : 0,
                     a.has_ep ? a.ep.count : nullptr, a.has_ep ? a.ep.capacity : 0, 2, s);
     if (e != hipSuccess) return e;
