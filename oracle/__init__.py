@@ -23,7 +23,8 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 PROC_NCS, PROC_NCS_STOKES, PROC_NBW, PROC_VB = 1, 2, 4, 8
 ST_OVERFLOW, ST_NAN, ST_PMAX, ST_EPS_LT1, ST_CLAMP = 1, 2, 4, 8, 16
 FIELD_NONE, FIELD_CONST, FIELD_PW, FIELD_GAUSS, FIELD_GRID2D = 0, 1, 2, 3, 4
-TAB_BESSEL, TAB_NCS_RATE, TAB_NCS_CDF, TAB_NBW_RATE, TAB_NBW_CDF, TAB_VB = range(6)
+TAB_BESSEL, TAB_NCS_RATE, TAB_NCS_CDF, TAB_NBW_RATE, TAB_NBW_CDF, TAB_VB, TAB_RAD = range(7)
+RR_LL, RR_MLL, RR_RBMT = 1, 2, 4
 
 ALPHA = 1.0 / 137.035999084          # CODATA 2018
 XI_L = 2.42631023867e-6              # hbar omega / m c^2 at lambda = 1 um (= lambda_C/lambda)
@@ -75,6 +76,9 @@ def lib():
             "orc_tab_vb_M": (None, [vp, d, vp]),
             "orc_field_eval": (None, [vp, d, vp, vp, vp]),
             "orc_push_spin": (None, [vp, vp, vp, i64, vp]),
+            "orc_push_radiative": (None, [vp, vp, vp, vp, i64, u32]),
+            "orc_ll_force": (None, [d, d, d, vp, vp, vp, vp]),
+            "orc_tab_rad": (None, [vp, d, vp]),
             "orc_emit": (None, [vp, vp, vp, vp, vp, i64]),
             "orc_photon_step": (None, [vp, vp, vp, vp, vp, vp, i64]),
             "orc_compact_photons": (i64, [vp]),
@@ -168,6 +172,15 @@ def nbw_Kb(chi, d):
     return lib().orc_nbw_Kb(float(chi), float(d))
 
 
+def ll_force(g, p, E, B, alpha=None, xi_L=None) -> np.ndarray:
+    """Classical Landau-Lifshitz force (two leading terms, Sec. III.A.1) at momentum p
+    with Lorentz factor g."""
+    F = np.zeros(3)
+    lib().orc_ll_force(float(alpha if alpha is not None else ALPHA), float(xi_L if xi_L is not None else XI_L),
+                       float(g), _p(_f64(p)), _p(_f64(E)), _p(_f64(B)), _p(F))
+    return F
+
+
 def vb_M(chi) -> np.ndarray:
     o = np.zeros(2)
     lib().orc_vb_M(float(chi), _p(o))
@@ -257,6 +270,12 @@ class Tables:
 
     def nbw_sample_delta(self, chi, xi3, r):
         return lib().orc_tab_nbw_sample_delta(self.h, float(chi), float(xi3), float(r))
+
+    def rad(self, chi) -> np.ndarray:
+        """g(chi) (emitted / Larmor power) and psi1..psi3 from the RAD table."""
+        o = np.zeros(4)
+        lib().orc_tab_rad(self.h, float(chi), _p(o))
+        return o
 
     def vb_M(self, chi) -> np.ndarray:
         o = np.zeros(2)
@@ -449,6 +468,12 @@ class Sim:
         s = L.ctype()
         lib().orc_push_spin(C.byref(self.cfg), C.byref(field), C.byref(s), step,
                             _p(E6) if E6 is not None else None)
+
+    def push_radiative(self, field, L: LeptonArrays, step: int, mode: int):
+        """Lorentz or radiative push (mode: RR_LL or RR_MLL, | RR_RBMT) and spin."""
+        s = L.ctype()
+        tab = self.tab if self.tab is not None else tables()
+        lib().orc_push_radiative(C.byref(self.cfg), tab.h, C.byref(field), C.byref(s), step, mode)
 
     def emit(self, L: LeptonArrays, E6: np.ndarray, G: PhotonArrays | None, step: int):
         s = L.ctype()

@@ -389,7 +389,12 @@ void orc_nbw_G(double d, double chi, const double Sp[3], const double Sm[3], con
  *                    4-point Lagrange; chi < 0.05: no pairs.
  *  NBW_CDF  256 rows ln chi in [ln 0.05, ln 1e3] x 512 columns delta in [0, 1/2];
  *                    Ka/Ja, Kb/Jb (value 1/2 at delta = 1/2); as NCS_CDF, mirrored.
- *  VB       NV=1024  ln chi in [ln 1e-4, ln 1e3]; M+, M-; 4-point Lagrange; below: 4, 7.  */
+ *  VB       NV=1024  ln chi in [ln 1e-4, ln 1e3]; M+, M-; 4-point Lagrange; below: 4, 7.
+ *  RAD      NR=512   grid of NCS_RATE; h0 = g (1+chi)^(4/3) with g = emitted / Larmor power,
+ *                    h_k = psi_k (1+chi)^(7/3) / chi^3 (k = 1, 2, 3): flat at both ends
+ *                    (g ~ chi^(-4/3), psi ~ chi^(2/3) or less at large chi); 4-point
+ *                    Lagrange, (1+chi)^(1/3) by cbrt.  chi < 1e-6: g = 1 - (55 sqrt3/16) chi,
+ *                    psi_k = h_k(first node) chi^3 / (1+chi)^(7/3).  chi > 1e3: clamp + flag. */
 #define NB 2048
 #define B_LO (-34.538776394910684)   /* ln 1e-15 */
 #define B_HI (6.907755278982137)     /* ln 1e3   */
@@ -417,6 +422,7 @@ struct orc_tables {
     double nbw_ga[NP], nbw_gk[NP];
     double *nbw_A, *nbw_B;     /* NDR x NDD each */
     double vb[2][NV];
+    double rad[4][NR];         /* g, psi1/chi^3, psi2/chi^3, psi3/chi^3 */
 };
 
 static double grid_h(double lo, double hi, int n) { return (hi - lo) / (n - 1); }
@@ -523,6 +529,13 @@ orc_tables *orc_tables_build(void) {
         T->vb[0][i] = M[0];
         T->vb[1][i] = M[1];
     }
+    /* radiative-correction coefficients on the NCS rate grid */
+    for (int i = 0; i < NR; ++i) {
+        double chi = exp(R_LO + i * hr), psi[3], o = 1 + chi, oc = cbrt(o);
+        T->rad[0][i] = orc_ncs_power_ratio(chi) * o * oc;
+        orc_rbmt_psi(chi, psi);
+        for (int k = 0; k < 3; ++k) T->rad[k + 1][i] = psi[k] * (o * o * oc) / (chi * chi * chi);
+    }
     return T;
 }
 void orc_tables_free(orc_tables *T) {
@@ -538,6 +551,7 @@ int64_t orc_tables_size(int which) {
     case ORC_TAB_NBW_RATE: return 2 * NP;
     case ORC_TAB_NBW_CDF: return 2 * (int64_t)NDR * NDD;
     case ORC_TAB_VB: return 2 * NV;
+    case ORC_TAB_RAD: return 4 * NR;
     }
     return 0;
 }
@@ -553,6 +567,7 @@ void orc_tables_export(const orc_tables *T, int which, double *o) {
         memcpy(o, T->nbw_A, sizeof(double) * NDR * NDD);
         memcpy(o + (size_t)NDR * NDD, T->nbw_B, sizeof(double) * NDR * NDD); break;
     case ORC_TAB_VB: memcpy(o, T->vb, sizeof T->vb); break;
+    case ORC_TAB_RAD: memcpy(o, T->rad, sizeof T->rad); break;
     }
 }
 
@@ -706,6 +721,22 @@ static void vb_lookup(const orc_tables *T, double chi, double M[2], uint32_t *st
     M[1] = lag_eval(T->vb[1], i, w);
 }
 void orc_tab_vb_M(const orc_tables *T, double chi, double M[2]) { vb_lookup(T, chi, M, &g_status_scratch); }
+/* g(chi) and psi_1..3(chi) from the RAD table (specification in section 4) */
+static void rad_lookup(const orc_tables *T, double chi, double out[4], uint32_t *st) {
+    if (!(chi > 0)) { out[0] = 1; out[1] = out[2] = out[3] = 0; return; }
+    double l = log(chi), o = 1 + chi, oc = cbrt(o), sp = chi * chi * chi / (o * o * oc);
+    if (l < R_LO) {
+        out[0] = 1 - 55 * SQRT3 / 16 * chi;
+        for (int k = 1; k < 4; ++k) out[k] = T->rad[k][0] * sp;
+        return;
+    }
+    if (l > R_HI) *st |= ORC_ST_CLAMP;
+    double w[4];
+    int i = lagrange4((l - R_LO) / grid_h(R_LO, R_HI, NR), NR, w);
+    out[0] = lag_eval(T->rad[0], i, w) / (o * oc);
+    for (int k = 1; k < 4; ++k) out[k] = lag_eval(T->rad[k], i, w) * sp;
+}
+void orc_tab_rad(const orc_tables *T, double chi, double out[4]) { rad_lookup(T, chi, out, &g_status_scratch); }
 
 /* =========================================================================== 5. fields */
 /* Plane wave travelling along -x (phase t + x, as in the pulse of Fig. "pusher"):
@@ -863,6 +894,95 @@ void orc_push_spin(orc_config *c, const orc_field *f, orc_leptons *L, int64_t st
         orc_bmt(q, c->a_e, dt, E, B, pm, pp, S);
         double g = sqrt(1 + dot3(p, p));
         for (int k = 0; k < 3; ++k) r[k] += dt * p[k] / g;
+        if (!finite3(p) || !finite3(r) || !finite3(S)) c->status |= ORC_ST_NAN;
+        L->x[i] = r[0]; L->y[i] = r[1]; L->z[i] = r[2];
+        L->px[i] = p[0]; L->py[i] = p[1]; L->pz[i] = p[2];
+        L->sx[i] = S[0]; L->sy[i] = S[1]; L->sz[i] = S[2];
+    }
+}
+
+/* ============================================ 6b. radiation reaction (Sec. III.A, III.B) */
+/* Classical Landau-Lifshitz force of eq. (eq1-1), its two leading terms (the paper names
+ * them dominant; the field-derivative term is not included), with the 1/gamma of the
+ * Gaussian-unit form (eq1) on E(p.E):
+ *   F = (2/3) alpha xi_L { E x B + [B x (B x p) + E (p.E)] / gamma
+ *                          - gamma p [(E + beta x B)^2 - (beta.E)^2] },  beta = p/gamma. */
+void orc_ll_force(double alpha, double xi_L, double g, const double p[3], const double E[3],
+                  const double B[3], double F[3]) {
+    double beta[3], exb[3], bxp[3], bbp[3], bxb[3], v[3];
+    for (int k = 0; k < 3; ++k) beta[k] = p[k] / g;
+    cross3(E, B, exb);
+    cross3(B, p, bxp);
+    cross3(B, bxp, bbp);
+    cross3(beta, B, bxb);
+    for (int k = 0; k < 3; ++k) v[k] = E[k] + bxb[k];
+    double pe = dot3(p, E), be = pe / g, s = dot3(v, v) - be * be;
+    double c = 2.0 / 3.0 * alpha * xi_L;
+    for (int k = 0; k < 3; ++k) F[k] = c * (exb[k] + (bbp[k] + E[k] * pe) / g - g * p[k] * s);
+}
+
+/* S += dt/2 R(S), R(S) = -P [psi1 S + psi2 (S.beta) beta + psi3 b]  (rc = {g, psi1..3}) */
+static void rbmt_half_kick(double P, const double rc[4], const double beta[3], const double b[3], double dt,
+                           double S[3]) {
+    double sb = dot3(S, beta), R[3];
+    for (int k = 0; k < 3; ++k) R[k] = -P * (rc[1] * S[k] + rc[2] * sb * beta[k] + rc[3] * b[k]);
+    for (int k = 0; k < 3; ++k) S[k] += 0.5 * dt * R[k];
+}
+/* Radiative push (Sec. III.A.3) and radiative T-BMT (Sec. III.B.3) for every lepton:
+ *   Boris with E^n, B^n: p^{n-1/2} -> p_L^{n+1/2};
+ *   time-centred gamma^n = sqrt(1 + |p-|^2), beta^n = (p- + p+)/(2 gamma^n), p^n = gamma^n beta^n,
+ *   chi^n = xi_L gamma^n sqrt((E + beta^n x B)^2 - (beta^n.E)^2);
+ *   LL:  p^{n+1/2} = p_L^{n+1/2} + F(p^n) dt;  MLL: the same with g(chi^n) F;
+ *   RBMT: S += dt/2 R(S), T-BMT rotation, S += dt/2 R(S), with
+ *         R(S) = -P [psi1 S + psi2 (S.beta^n) beta^n + psi3 b],  P = alpha/(sqrt3 pi xi_L gamma^n),
+ *         b = n x a of the local frame at time n (n = beta^n/|beta^n|, a = unit transverse part
+ *         of q(E + beta^n x B)); S is not renormalised (it is the mean polarisation);
+ *   x^{n+1} = x^n + dt p^{n+1/2}/gamma^{n+1/2}.                                          */
+void orc_push_radiative(orc_config *c, const orc_tables *T, const orc_field *f, orc_leptons *L, int64_t step,
+                        uint32_t mode) {
+    double dt = c->dt, t = step * dt, q = (double)L->charge;
+    const int force = mode & (ORC_RR_LL | ORC_RR_MLL), rbmt = (mode & ORC_RR_RBMT) != 0;
+    for (int64_t i = 0; i < L->count; ++i) {
+        double r[3] = {L->x[i], L->y[i], L->z[i]}, E[3], B[3];
+        orc_field_eval(f, t, r, E, B);
+        double p[3] = {L->px[i], L->py[i], L->pz[i]}, pm[3], pp[3];
+        double S[3] = {L->sx[i], L->sy[i], L->sz[i]};
+        orc_boris(q, dt, E, B, p, pm, pp);
+        double g = sqrt(1 + dot3(pm, pm)), beta[3], pn[3], bxb[3], v[3];
+        for (int k = 0; k < 3; ++k) { beta[k] = (pm[k] + pp[k]) / (2 * g); pn[k] = g * beta[k]; }
+        cross3(beta, B, bxb);
+        for (int k = 0; k < 3; ++k) v[k] = E[k] + bxb[k];
+        double be = dot3(beta, E), s2 = dot3(v, v) - be * be;
+        double chi = c->xi_L * g * sqrt(s2 > 0 ? s2 : 0), rc[4] = {1, 0, 0, 0};
+        if ((force & ORC_RR_MLL) || rbmt) rad_lookup(T, chi, rc, &c->status);
+        if (force) {
+            double F[3];
+            orc_ll_force(c->alpha, c->xi_L, g, pn, E, B, F);
+            double scale = (force & ORC_RR_MLL) ? rc[0] : 1.0;
+            for (int k = 0; k < 3; ++k) p[k] += scale * F[k] * dt;
+        }
+        if (rbmt) {
+            double bn = norm3(beta), b[3] = {0, 0, 0};
+            if (bn > 0) {
+                double n[3], ad[3];
+                for (int k = 0; k < 3; ++k) n[k] = beta[k] / bn;
+                double nv = dot3(n, v);
+                for (int k = 0; k < 3; ++k) ad[k] = q * (v[k] - nv * n[k]);
+                double an = norm3(ad);
+                if (an > 0) {
+                    for (int k = 0; k < 3; ++k) ad[k] /= an;
+                    cross3(n, ad, b);
+                }
+            }
+            double P = c->alpha / (SQRT3 * PI * c->xi_L * g);
+            rbmt_half_kick(P, rc, beta, b, dt, S);
+            orc_bmt(q, c->a_e, dt, E, B, pm, pp, S);
+            rbmt_half_kick(P, rc, beta, b, dt, S);
+        } else {
+            orc_bmt(q, c->a_e, dt, E, B, pm, pp, S);
+        }
+        double gp = sqrt(1 + dot3(p, p));
+        for (int k = 0; k < 3; ++k) r[k] += dt * p[k] / gp;
         if (!finite3(p) || !finite3(r) || !finite3(S)) c->status |= ORC_ST_NAN;
         L->x[i] = r[0]; L->y[i] = r[1]; L->z[i] = r[2];
         L->px[i] = p[0]; L->py[i] = p[1]; L->pz[i] = p[2];

@@ -63,7 +63,7 @@ orc_tables *orc_tables_build(void);
 void orc_tables_free(orc_tables *t);
 /* table ids for export */
 enum { ORC_TAB_BESSEL = 0, ORC_TAB_NCS_RATE = 1, ORC_TAB_NCS_CDF = 2, ORC_TAB_NBW_RATE = 3,
-       ORC_TAB_NBW_CDF = 4, ORC_TAB_VB = 5 };
+       ORC_TAB_NBW_CDF = 4, ORC_TAB_VB = 5, ORC_TAB_RAD = 6 };
 int64_t orc_tables_size(int which);                    /* number of doubles           */
 void orc_tables_export(const orc_tables *t, int which, double *out);
 /* lookups that follow the specification exactly                                    */
@@ -77,6 +77,8 @@ void orc_sampler_targets_n(const orc_tables *t, int64_t n, const double *chi, co
 void orc_tab_nbw_rate(const orc_tables *t, double chi, double *Ja, double *Jb);
 double orc_tab_nbw_sample_delta(const orc_tables *t, double chi, double xi3, double r);
 void orc_tab_vb_M(const orc_tables *t, double chi, double M[2]);
+/* radiative coefficients: out = {g(chi), psi1, psi2, psi3}                          */
+void orc_tab_rad(const orc_tables *t, double chi, double out[4]);
 
 /* ---------------- fields, particles, segments ------------------------------------ */
 enum { ORC_FIELD_NONE = 0, ORC_FIELD_CONST = 1, ORC_FIELD_PW = 2, ORC_FIELD_GAUSS = 3,
@@ -121,6 +123,13 @@ typedef struct {
 /* Lorentz + T-BMT for every lepton (fields at x^n, t^n = step*dt).  If E6 is not
  * NULL the fields used are written there (6 doubles per particle).                 */
 void orc_push_spin(orc_config *c, const orc_field *f, orc_leptons *L, int64_t step, double *E6);
+/* radiation reaction (Sec. III.A-B): Landau-Lifshitz force (LL), the same scaled by the
+ * emitted/Larmor power ratio g(chi) (MLL), radiative T-BMT (RBMT); see the definition.   */
+enum { ORC_RR_LL = 1, ORC_RR_MLL = 2, ORC_RR_RBMT = 4 };
+void orc_ll_force(double alpha, double xi_L, double g, const double p[3], const double E[3],
+                  const double B[3], double F[3]);
+void orc_push_radiative(orc_config *c, const orc_tables *tab, const orc_field *f, orc_leptons *L, int64_t step,
+                        uint32_t mode);
 /* NCS for every lepton that existed at the start of the step; E6 holds E^n,B^n.
  * Photons are appended in parent order.                                            */
 void orc_emit(orc_config *c, const orc_tables *tab, orc_leptons *L, const double *E6,
