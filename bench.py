@@ -372,6 +372,44 @@ def run_cascade(args, torch, Q, W):
             "status_bits": ctx.read_status()}
 
 
+BYTES_RADIATIVE = {"mixed": 48 + 12 + 48 + 12, "fp64": 48 + 24 + 48 + 24}   # read x, p, S; write x, p, S
+
+
+def run_radiative(args, torch, Q, cfg):
+    """Radiative push (MLL force + radiative T-BMT, qed_push_radiative) on the focused-pulse
+    workload's 1e7 electrons at the peak field, mixed and FP64: throughput against the HBM
+    roofline of its 120 / 144 algorithmic bytes per lepton-step, and the mean energy the
+    radiation reaction removed."""
+    out = {}
+    mode = Q.RR_MLL | Q.RR_RBMT
+    segs = Q.whole(cfg["field"])
+    s0 = cfg["start_step"]
+    for prec, name in ((Q.QED_MIXED, "mixed"), (Q.QED_FP64, "fp64")):
+        ctx = Q.Context(dt=cfg["dt"], procs=cfg["procs"], seed=cfg["seed"], id_start=0, precision=prec)
+        L = Q.Leptons.from_state(cfg["leptons"], precision=prec)
+        n = L.count
+        e0 = float(torch.sqrt(1 + L.px[:n] ** 2 + L.py[:n] ** 2 + L.pz[:n] ** 2).mean())
+        for s in range(s0, s0 + 3):
+            ctx.push_radiative(segs, L, mode, s)
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * args.radiative_steps)]
+        for k in range(args.radiative_steps):
+            ev[2 * k].record()
+            ctx.push_radiative(segs, L, mode, s0 + 3 + k)
+            ev[2 * k + 1].record()
+        torch.cuda.synchronize()
+        ms = sum(ev[2 * k].elapsed_time(ev[2 * k + 1]) for k in range(args.radiative_steps)) / args.radiative_steps
+        e1 = float(torch.sqrt(1 + L.px[:n] ** 2 + L.py[:n] ** 2 + L.pz[:n] ** 2).mean())
+        gbs = n * BYTES_RADIATIVE[name] / (ms * 1e-3) / 1e9
+        out[name] = {"lepton_steps_per_s": n / (ms * 1e-3), "ms_per_step": ms,
+                     "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                  "frac": gbs / HBM_PEAK_GBS, "bytes_per_lepton_step": BYTES_RADIATIVE[name]},
+                     "mean_gamma_change_rel": e1 / e0 - 1, "status_bits": ctx.read_status()}
+    out["mode"] = "MLL force + radiative T-BMT"
+    out["workload"] = "1e7 electrons, focused CP pulse a0 = 100, gamma0 = 2000, steps from 2400"
+    return out
+
+
 def cpu_baseline(cfg_small, budget_s=15.0):
     """The oracle as it stands (single-threaded C, FP64 tables) on a bounded sample of the
     same workload: the first `n` electrons of the bunch, stepped until the budget is used."""
@@ -415,6 +453,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-sampler measurements")
     ap.add_argument("--cascade-steps", type=int, default=40, help="timed steps of the cascade (0: skip it)")
     ap.add_argument("--cascade-warmup", type=int, default=150)
+    ap.add_argument("--radiative-steps", type=int, default=20,
+                    help="timed steps of the radiative push (MLL + radiative T-BMT; 0: skip it)")
     ap.add_argument("--train-samples", type=int, default=10_000_000)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device to device three times (a plain copy kernel of known size, "
@@ -496,6 +536,9 @@ def main():
                           "status_bits": fp64["status"]}
         result["speedup_mixed_over_fp64"] = result["value"] / result["fp64"]["value"]
         result["error_vs_fp64"] = error_metrics(fp64, mixed, 2000.0, torch)
+    if args.radiative_steps > 0:
+        print("[bench] radiative push", file=sys.stderr, flush=True)
+        result["radiative"] = run_radiative(args, torch, Q, cfg)
     if args.cascade_steps > 0:
         print("[bench] cascade on the grid", file=sys.stderr, flush=True)
         result["cascade"] = run_cascade(args, torch, Q, W)

@@ -75,7 +75,7 @@ enum { QED_FIELD_NONE = 0, QED_FIELD_CONST = 1, QED_FIELD_PW = 2, QED_FIELD_GAUS
        QED_FIELD_GRID2D = 4 };
 /* table ids for qed_table_export */
 enum { QED_TAB_BESSEL = 0, QED_TAB_NCS_RATE = 1, QED_TAB_NCS_CDF = 2, QED_TAB_NBW_RATE = 3,
-       QED_TAB_NBW_CDF = 4, QED_TAB_VB = 5 };
+       QED_TAB_NBW_CDF = 4, QED_TAB_VB = 5, QED_TAB_RAD = 6 };
 
 typedef struct {
     double xi_L;        /* hbar omega / m c^2 of the reference wavelength (Sec. III.A.1)   */
@@ -157,6 +157,20 @@ qed_status qed_gather(qed_ctx_t *ctx, const qed_segment *segs, int nseg, const q
  * in the same kernel.                                                                    */
 qed_status qed_push_spin(qed_ctx_t *ctx, const qed_segment *segs, int nseg, qed_leptons *p,
                          const double *E6, int64_t step, hipStream_t stream);
+/* Radiative push (Sec. III.A.3) and radiative T-BMT (Sec. III.B.3): the push of
+ * qed_push_spin (fields gathered in the kernel) with, at the time-centred gamma^n =
+ * sqrt(1+|p-|^2), beta^n = (p- + p+)/(2 gamma^n) and chi^n,
+ *   QED_RR_LL  : p^{n+1/2} += F dt, F the Landau-Lifshitz force of eq. (eq1-1) (its two
+ *                leading terms; the E(p.E) term with the 1/gamma of eq. (eq1));
+ *   QED_RR_MLL : the same with g(chi^n) F, g the emitted / Larmor power ratio (Sec. III.A.2);
+ *   QED_RR_RBMT: the spin gets dt/2 R(S) before and after the T-BMT rotation,
+ *                R = -P [psi1 S + psi2 (S.beta) beta + psi3 b], P = alpha/(sqrt3 pi xi_L gamma),
+ *                b = n x a of the NCS local frame; S then is a mean polarisation (|S| <= 1).
+ * mode = 0 is qed_push_spin.  LL and MLL exclude each other (QED_EARG).  Deterministic: no
+ * random numbers, no events.  chi beyond 1e3 sets QED_ST_CLAMP.                          */
+enum { QED_RR_LL = 1, QED_RR_MLL = 2, QED_RR_RBMT = 4 };
+qed_status qed_push_radiative(qed_ctx_t *ctx, const qed_segment *segs, int nseg, qed_leptons *p, uint32_t mode,
+                              int64_t step, hipStream_t stream);
 /* Nonlinear Compton step for leptons already pushed in this step, using the fields E6 of
  * x^n (required).  Photons are appended to `out` (may be NULL: recoil and spin only).   */
 qed_status qed_emit(qed_ctx_t *ctx, const qed_segment *segs, int nseg, qed_leptons *p,
@@ -188,7 +202,8 @@ qed_status qed_get_next_id(qed_ctx_t *ctx, uint64_t *next_id, hipStream_t stream
 qed_status qed_set_next_id(qed_ctx_t *ctx, uint64_t next_id, hipStream_t stream);
 /* Copies a table (FP64 master) to host memory in the layout of the table specification:
  * BESSEL b1[NB] b2[NB] b3[NB]; NCS_RATE fa[NR] fk[NR]; NCS_CDF A[rows][cols] B[rows][cols];
- * NBW_RATE ga[NP] gk[NP]; NBW_CDF A B; VB Mplus[NV] Mminus[NV].  n must equal the size
+ * NBW_RATE ga[NP] gk[NP]; NBW_CDF A B; VB Mplus[NV] Mminus[NV]; RAD g (1+chi)^(4/3) [NR],
+ * psi1..3 (1+chi)^(7/3) / chi^3 [NR] each (NCS rate grid).  n must equal the size
  * returned by qed_table_size.                                                           */
 int64_t qed_table_size(int which);
 qed_status qed_table_export(qed_ctx_t *ctx, int which, double *host_out, int64_t n);

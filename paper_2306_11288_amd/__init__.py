@@ -19,8 +19,10 @@ QED_FP64, QED_MIXED = 0, 1
 PROC_NCS, PROC_NCS_STOKES, PROC_NBW, PROC_VB = 1, 2, 4, 8
 ST_OVERFLOW, ST_NAN, ST_PMAX, ST_EPS_LT1, ST_CLAMP, ST_SCAN = 1, 2, 4, 8, 16, 32
 FIELD_NONE, FIELD_CONST, FIELD_PW, FIELD_GAUSS, FIELD_GRID2D = 0, 1, 2, 3, 4
-TAB_BESSEL, TAB_NCS_RATE, TAB_NCS_CDF, TAB_NBW_RATE, TAB_NBW_CDF, TAB_VB = range(6)
-EXPORTED = ["qed_init_tables", "qed_destroy", "qed_gather", "qed_push_spin", "qed_emit", "qed_step_leptons",
+TAB_BESSEL, TAB_NCS_RATE, TAB_NCS_CDF, TAB_NBW_RATE, TAB_NBW_CDF, TAB_VB, TAB_RAD = range(7)
+RR_LL, RR_MLL, RR_RBMT = 1, 2, 4
+EXPORTED = ["qed_init_tables", "qed_destroy", "qed_gather", "qed_push_spin", "qed_push_radiative", "qed_emit",
+            "qed_step_leptons",
             "qed_birefringence", "qed_pair", "qed_step_photons", "qed_compact_photons", "qed_read_status",
             "qed_clear_status", "qed_get_next_id", "qed_set_next_id", "qed_table_size", "qed_table_export",
             "qed_set_step_events", "qed_set_step_counter", "qed_advance_step", "qed_get_tuning",
@@ -94,6 +96,7 @@ def lib():
             "qed_destroy": [vp],
             "qed_gather": [vp, vp, C.c_int, vp, vp, i64, vp],
             "qed_push_spin": [vp, vp, C.c_int, vp, vp, i64, vp],
+            "qed_push_radiative": [vp, vp, C.c_int, vp, C.c_uint32, i64, vp],
             "qed_emit": [vp, vp, C.c_int, vp, vp, vp, i64, vp],
             "qed_step_leptons": [vp, vp, C.c_int, vp, vp, i64, vp],
             "qed_birefringence": [vp, vp, C.c_int, vp, i64, vp],
@@ -325,6 +328,12 @@ class Context:
         arr, n = segs
         self._check(lib().qed_push_spin(self.h, arr, n, C.byref(L.c()), _ptr(E6) if E6 is not None else None, step,
                                         _stream(stream)), "qed_push_spin")
+
+    def push_radiative(self, segs, L: Leptons, mode: int, step: int, stream=None):
+        """Push with radiation reaction: mode = RR_LL or RR_MLL, optionally | RR_RBMT."""
+        arr, n = segs
+        self._check(lib().qed_push_radiative(self.h, arr, n, C.byref(L.c()), int(mode), step, _stream(stream)),
+                    "qed_push_radiative")
 
     def emit(self, segs, L: Leptons, E6, out: Photons | None, step: int, stream=None):
         arr, n = segs

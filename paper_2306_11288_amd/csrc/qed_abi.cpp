@@ -320,6 +320,20 @@ qed_status qed_push_spin(qed_ctx_t *ctx, const qed_segment *segs, int nseg, qed_
                     "qed_push_spin");
 }
 
+qed_status qed_push_radiative(qed_ctx_t *ctx, const qed_segment *segs, int nseg, qed_leptons *p, uint32_t mode,
+                              int64_t step, hipStream_t s) {
+    qed_status st = ready(ctx);
+    if (st != QED_OK) return st;
+    if (mode & ~(uint32_t)(QED_RR_LL | QED_RR_MLL | QED_RR_RBMT))
+        return fail(ctx, QED_EARG, "qed_push_radiative: unknown mode bits 0x%x", mode);
+    if ((mode & QED_RR_LL) && (mode & QED_RR_MLL))
+        return fail(ctx, QED_EARG, "qed_push_radiative: QED_RR_LL and QED_RR_MLL exclude each other");
+    SegArgs sa{};
+    if ((st = seg_args(ctx, segs, nseg, sa, s)) != QED_OK) return st;
+    if ((st = check_leptons(ctx, p, "leptons")) != QED_OK) return st;
+    return launched(ctx, launch_radiative(ctx, sa, *p, mode, step, s), "qed_push_radiative");
+}
+
 qed_status qed_emit(qed_ctx_t *ctx, const qed_segment *segs, int nseg, qed_leptons *p, const double *E6,
                     qed_photons *out, int64_t step, hipStream_t s) {
     qed_status st = ready(ctx);
@@ -421,6 +435,7 @@ int64_t qed_table_size(int which) {
     case QED_TAB_NBW_RATE: return 2 * NP;
     case QED_TAB_NBW_CDF: return 2LL * NDR * NDD;
     case QED_TAB_VB: return 2 * NV;
+    case QED_TAB_RAD: return 4 * NR;
     }
     return -1;
 }
@@ -439,8 +454,9 @@ qed_status qed_table_export(qed_ctx_t *ctx, int which, double *host, int64_t n) 
     case QED_TAB_NBW_RATE: off = OFF_NBW_RATE; break;
     case QED_TAB_NBW_CDF: off = OFF_NBW_CDF; break;
     case QED_TAB_VB: off = OFF_VB; break;
+    case QED_TAB_RAD: off = OFF_RAD; stride = 4; len = NR; break;
     }
-    const int nc = which == QED_TAB_BESSEL ? 3 : 2;
+    const int nc = which == QED_TAB_BESSEL ? 3 : (which == QED_TAB_RAD ? 4 : 2);
     double *tmp = new (std::nothrow) double[stride * len];
     if (!tmp) return QED_ENOMEM;
     const hipError_t e = hipMemcpy(tmp, ctx->tab64 + off, stride * len * sizeof(double), hipMemcpyDeviceToHost);

@@ -481,6 +481,34 @@ __device__ __forceinline__ void vb_M(const Tabs<T> &tb, double chi, T &Mp, T &Mm
     }
 }
 
+// Radiation-reaction coefficients {g, psi1, psi2, psi3} at chi from the RAD table (stored
+// as g (1+chi)^(4/3) and psi (1+chi)^(7/3)/chi^3; below the grid g = 1 - (55 sqrt3/16) chi
+// and the psi scale from the first node; above: clamp + flag).
+template <class T>
+struct RadCoef {
+    T g, p1, p2, p3;
+};
+template <class T>
+__device__ __forceinline__ RadCoef<T> rad_coeffs(const Tabs<T> &tb, double chi, uint32_t &st) {
+    if (!(chi > 0.0)) return {(T)1, (T)0, (T)0, (T)0};
+    const T c = (T)chi, l = lnx(c), o = (T)1 + c, oc = cbrt(o), sp = c * c * c / (o * o * oc);
+    const T *r = tb.rad();
+    if (l < (T)R_LO) return {(T)1 - (T)(55.0 * 1.7320508075688772 / 16.0) * c, r[1] * sp, r[2] * sp, r[3] * sp};
+    if (l > (T)R_HI) st |= QED_ST_CLAMP;
+    T w[4];
+    const int i = lag4(gridpos<T>(l, R_LO, R_HI, NR), NR, w);
+    T h0 = 0, h1 = 0, h2 = 0, h3 = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const T *q = r + 4 * (i - 1 + j);
+        h0 += w[j] * q[0];
+        h1 += w[j] * q[1];
+        h2 += w[j] * q[2];
+        h3 += w[j] * q[3];
+    }
+    return {h0 / (o * oc), h1 * sp, h2 * sp, h3 * sp};
+}
+
 // ------------------------------------------------------------------------- NCS
 // Emitted photon of one event (Sec. III.C.1): momentum k, Stokes xi, basis vector e1.
 template <class T>

@@ -29,7 +29,9 @@ constexpr int64_t OFF_NCS_CDF = OFF_NCS_RATE + 2 * NR;            // [NCR][NCT][
 constexpr int64_t OFF_NBW_RATE = OFF_NCS_CDF + 2LL * NCR * NCT;   // [NP][2]  ga gk
 constexpr int64_t OFF_NBW_CDF = OFF_NBW_RATE + 2 * NP;            // [NDR][NDD][2] A B
 constexpr int64_t OFF_VB = OFF_NBW_CDF + 2LL * NDR * NDD;         // [NV][2]  M+ M-
-constexpr int64_t TAB_TOTAL = OFF_VB + 2 * NV;
+constexpr int64_t OFF_RAD = OFF_VB + 2 * NV;                      // [NR][4]  g (1+chi)^(4/3),
+                                                                  //          psi1..3 (1+chi)^(7/3) / chi^3
+constexpr int64_t TAB_TOTAL = OFF_RAD + 4 * NR;
 
 template <class T>
 struct Tabs {
@@ -40,6 +42,7 @@ struct Tabs {
     __device__ __forceinline__ const T *nbw_rate() const { return base + OFF_NBW_RATE; }
     __device__ __forceinline__ const T *nbw_cdf() const { return base + OFF_NBW_CDF; }
     __device__ __forceinline__ const T *vb() const { return base + OFF_VB; }
+    __device__ __forceinline__ const T *rad() const { return base + OFF_RAD; }
 };
 
 // ------------------------------------------------------------------ constants per context
@@ -178,6 +181,8 @@ hipError_t launch_photons(qed_ctx *ctx, PhotonMode mode, const SegArgs &sa, cons
                           const qed_leptons *em, const qed_leptons *ep, int64_t step, hipStream_t s);
 hipError_t launch_compact(qed_ctx *ctx, const qed_photons &in, const qed_photons &out, hipStream_t s);
 hipError_t launch_advance_step(int64_t *step, int64_t by, hipStream_t s);
+hipError_t launch_radiative(qed_ctx *ctx, const SegArgs &sa, const qed_leptons &L, uint32_t mode, int64_t step,
+                            hipStream_t s);
 // learned sampler (qed_mlp.hip)
 hipError_t mlp_alloc(qed_ctx *ctx);
 hipError_t mlp_init(qed_ctx *ctx, uint64_t seed, hipStream_t s);

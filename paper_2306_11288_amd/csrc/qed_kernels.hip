@@ -273,6 +273,74 @@ __device__ __forceinline__ void store_s(const LeptonArgs &a, uint32_t os, const 
     at((T *)a.L.sx, os) = S.x; at((T *)a.L.sy, os) = S.y; at((T *)a.L.sz, os) = S.z;
 }
 
+// Radiative push (Sec. III.A.3) and radiative T-BMT (Sec. III.B.3), grid-stride over the
+// leptons: Boris with E^n, B^n gives p_L^{n+1/2}; at the time-centred gamma^n, beta^n =
+// (p- + p+)/(2 gamma^n) and chi^n, the Landau-Lifshitz force (its two leading terms,
+// eq. eq1-1, with the 1/gamma of eq. eq1 on E(p.E)) adds F dt, scaled by the emitted /
+// Larmor power ratio g(chi^n) for MLL; the spin takes half kicks dt/2 R(S),
+// R = -P [psi1 S + psi2 (S.beta) beta + psi3 b], P = alpha/(sqrt3 pi xi_L gamma^n), around
+// the T-BMT rotation (b = n x a of the local frame at time n).  S is not renormalised.
+template <class T>
+__device__ __forceinline__ void rbmt_half_kick(T P, const RadCoef<T> &rc, const V3<T> &beta, const V3<T> &b, T hdt,
+                                               V3<T> &S) {
+    const T sb = dot(S, beta);
+    S = S - (hdt * P) * (rc.p1 * S + (rc.p2 * sb) * beta + rc.p3 * b);
+}
+template <class T, int FK>
+__global__ __launch_bounds__(BLOCK) void k_leptons_radiative(LeptonArgs a, uint32_t mode) {
+    const int64_t n = clamp_count(a.L.count, a.L.capacity);
+    const double dt = a.c.dt, t = (double)step_of(a) * dt, q = (double)a.L.charge;
+    const Tabs<T> tb = {(const T *)a.tab};
+    const uint32_t force = mode & (QED_RR_LL | QED_RR_MLL);
+    const bool rbmt = (mode & QED_RR_RBMT) != 0;
+    uint32_t st = 0;
+    for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK) {
+        const uint32_t o = (uint32_t)i * 8u, os = (uint32_t)i * (uint32_t)sizeof(T);
+        V3<double> r = {at(a.L.x, o), at(a.L.y, o), at(a.L.z, o)}, p = {at(a.L.px, o), at(a.L.py, o), at(a.L.pz, o)};
+        V3<T> S = {at((T *)a.L.sx, os), at((T *)a.L.sy, os), at((T *)a.L.sz, os)};
+        V3<double> E, B, pm, pp;
+        fields_for<T, FK>(a.sa, i, t, r, E, B);
+        const double ign = boris(q, dt, E, B, p, pm, pp);
+        const double g = 1.0 / ign;
+        const V3<double> beta = (0.5 * ign) * (pm + pp);
+        const V3<double> v = E + cross(beta, B);
+        const double be = dot(beta, E), s2 = dot(v, v) - be * be;
+        const double chi = a.c.xi_L * g * sqrt(s2 > 0.0 ? s2 : 0.0);
+        RadCoef<T> rc = {(T)1, (T)0, (T)0, (T)0};
+        if ((force & QED_RR_MLL) || rbmt) rc = rad_coeffs<T>(tb, chi, st);
+        if (force) {
+            const V3<double> pn = g * beta;
+            const V3<double> F = (2.0 / 3.0 * a.c.alpha * a.c.xi_L) *
+                                 (cross(E, B) + ign * (cross(B, cross(B, pn)) + dot(pn, E) * E) - (g * s2) * pn);
+            const double scale = (force & QED_RR_MLL) ? (double)rc.g : 1.0;
+            p = p + (scale * dt) * F;
+        }
+        if (rbmt) {
+            V3<double> bd = {0, 0, 0};
+            const double bn2 = dot(beta, beta);
+            if (bn2 > 0.0) {
+                const V3<double> nd = rsqrt(bn2) * beta;
+                const V3<double> ad = v - dot(nd, v) * nd;
+                const double a2 = dot(ad, ad);
+                if (a2 > 0.0) bd = cross(nd, (q * rsqrt(a2)) * ad);
+            }
+            const V3<T> bt = cvt<T>(beta), b = cvt<T>(bd);
+            const T P = (T)(a.c.c_ncs * ign), hdt = (T)(0.5 * dt);
+            rbmt_half_kick<T>(P, rc, bt, b, hdt, S);
+            bmt<T>(a.c, q, E, B, pm, pp, ign, S);
+            rbmt_half_kick<T>(P, rc, bt, b, hdt, S);
+        } else {
+            bmt<T>(a.c, q, E, B, pm, pp, ign, S);
+        }
+        const double igp = rsqrt(1.0 + dot(p, p));
+        r = r + (dt * igp) * p;
+        if (!isfinite(p.x + p.y + p.z + r.x + r.y + r.z) || !isfinite((double)(S.x + S.y + S.z))) st |= QED_ST_NAN;
+        store_xp<T>(a, o, r, p);
+        store_s<T>(a, os, S);
+    }
+    if (st) atomicOr(a.status, st);
+}
+
 // Decide (lepton step with NCS), one thread per particle, BLOCK-particle tiles; a block
 // takes tiles blockIdx.x, blockIdx.x + gridDim.x, ... (one tile per block when the grid
 // covers the list, a persistent sweep when the grid is a few blocks per CU): gather, push,
@@ -796,6 +864,42 @@ hipError_t launch_photons(qed_ctx *ctx, PhotonMode mode, const SegArgs &sa, cons
     }
     a.tab = ctx->tab64;
     return launch_photons_t<double>(ctx, a, s);
+}
+
+template <class T>
+static hipError_t launch_radiative_t(const LeptonArgs &a, uint32_t mode, hipStream_t s) {
+    const dim3 gd(stride_grid(a.L.capacity, 65536)), bd(BLOCK);
+    if (a.sa.nseg > 1) {
+        hipLaunchKernelGGL((k_leptons_radiative<T, FK_MULTI>), gd, bd, 0, s, a, mode);
+        return hipGetLastError();
+    }
+    switch (a.sa.f0.kind) {
+    case QED_FIELD_CONST: hipLaunchKernelGGL((k_leptons_radiative<T, QED_FIELD_CONST>), gd, bd, 0, s, a, mode); break;
+    case QED_FIELD_PW: hipLaunchKernelGGL((k_leptons_radiative<T, QED_FIELD_PW>), gd, bd, 0, s, a, mode); break;
+    case QED_FIELD_GAUSS: hipLaunchKernelGGL((k_leptons_radiative<T, QED_FIELD_GAUSS>), gd, bd, 0, s, a, mode); break;
+    case QED_FIELD_GRID2D:
+        hipLaunchKernelGGL((k_leptons_radiative<T, QED_FIELD_GRID2D>), gd, bd, 0, s, a, mode);
+        break;
+    default: hipLaunchKernelGGL((k_leptons_radiative<T, QED_FIELD_NONE>), gd, bd, 0, s, a, mode); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_radiative(qed_ctx *ctx, const SegArgs &sa, const qed_leptons &L, uint32_t mode, int64_t step,
+                            hipStream_t s) {
+    LeptonArgs a{};
+    a.c = consts_of(ctx);
+    a.sa = sa;
+    a.L = L;
+    a.step = step;
+    a.step_dev = ctx->step_dev;
+    a.status = ctx->status;
+    if (ctx->cfg.precision == QED_MIXED) {
+        a.tab = ctx->tab32;
+        return launch_radiative_t<float>(a, mode, s);
+    }
+    a.tab = ctx->tab64;
+    return launch_radiative_t<double>(a, mode, s);
 }
 
 hipError_t launch_advance_step(int64_t *step, int64_t by, hipStream_t s) {

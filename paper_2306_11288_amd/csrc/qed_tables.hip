@@ -164,6 +164,44 @@ __global__ void k_ncs_rate(double *tab, GaussRule g) {
     }
 }
 
+// Radiation-reaction coefficients on the NCS rate grid: the emitted power over the Larmor
+// power (2/3) alpha chi^2 / xi_L, g = 3/(2 sqrt3 pi chi^2) int u w/(1+u)^4 du, and the
+// radiative T-BMT integrals psi1 = int u''K23(u'), psi2 = int u''IntK13(u') - psi1,
+// psi3 = int u''K13(u') with u'' = u^2/(1+u)^3, u' = 2u/(3chi) = t^3.  Stored as
+// g (1+chi)^(4/3) and psi (1+chi)^(7/3)/chi^3, functions that are flat at both ends.
+__global__ void k_rad_rate(double *tab, GaussRule g) {
+    __shared__ double sh[8];
+    const int r = blockIdx.x;
+    const double chi = exp(R_LO + r * ((R_HI - R_LO) / (NR - 1)));
+    const double tcut = 3.9148676411688634, hp = 0.04;   // as the NCS rates
+    const int np = (int)ceil(tcut / hp);
+    const double hq = tcut / np;
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int q = threadIdx.x; q < np * GQ; q += blockDim.x) {
+        const int p = q / GQ, i = q % GQ;
+        const double t = hq * (p + 0.5 * (g.x[i] + 1.0));
+        double K1, K2, I;
+        bessel3(t * t * t, K1, K2, I);
+        const double u = 1.5 * chi * t * t * t, jac = 4.5 * chi * t * t, o = 1.0 + u, o3 = o * o * o;
+        const double wq = 0.5 * hq * g.w[i] * jac;
+        s[0] += wq * u * (-o * I + (2.0 + 2.0 * u + u * u) * K2) / (o3 * o);
+        s[1] += wq * u * u * K2 / o3;
+        s[2] += wq * u * u * I / o3;
+        s[3] += wq * u * u * K1 / o3;
+    }
+    double v[4];
+    for (int k = 0; k < 4; ++k) v[k] = block_sum(s[k], sh);
+    if (threadIdx.x == 0) {
+        const double oc = cbrt(1.0 + chi), o43 = (1.0 + chi) * oc, o73 = (1.0 + chi) * (1.0 + chi) * oc;
+        const double c3 = chi * chi * chi;
+        double *o = tab + OFF_RAD + 4 * r;
+        o[0] = 3.0 / (2.0 * 1.7320508075688772 * PI_ * chi * chi) * v[0] * o43;
+        o[1] = v[1] * o73 / c3;
+        o[2] = (v[2] - v[1]) * o73 / c3;
+        o[3] = v[3] * o73 / c3;
+    }
+}
+
 // per-interval integrals of the NCS spectrum pieces: scratch[2 * (row * NCT + j + 1)]
 __global__ void k_ncs_panels(double *scratch, GaussRule g) {
     const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -321,6 +359,7 @@ hipError_t build_tables(qed_ctx *ctx, hipStream_t s) {
                            tab + OFF_NBW_CDF, NDR, NDD, 0.5);
     }
     hipLaunchKernelGGL(k_vb, dim3(NV), dim3(256), 0, s, tab, g);
+    hipLaunchKernelGGL(k_rad_rate, dim3(NR), dim3(256), 0, s, tab, g);
     hipLaunchKernelGGL(k_to_f32, dim3(1024), dim3(256), 0, s, (const double *)tab, ctx->tab32, TAB_TOTAL);
     e = hipGetLastError();
     const hipError_t e2 = hipStreamSynchronize(s);

@@ -82,7 +82,7 @@ def test_tables_match_oracle():
     _say("tables")
     ctx = Q.Context(dt=0.01, procs=15, seed=1, id_start=0)
     T = oracle.tables()
-    for which in range(6):
+    for which in range(7):
         g, o = ctx.table_export(which), T.export(which)
         err = np.abs(g - o)
         bound = 1e-12 * np.abs(o) + 1e-14 * np.abs(o).max()
