@@ -77,6 +77,8 @@ def lib():
             "orc_field_eval": (None, [vp, d, vp, vp, vp]),
             "orc_push_spin": (None, [vp, vp, vp, i64, vp]),
             "orc_push_radiative": (None, [vp, vp, vp, vp, i64, u32]),
+            "orc_hist_photons": (None, [vp, i64, vp, vp]),
+            "orc_hist_leptons": (None, [vp, i64, vp, vp]),
             "orc_ll_force": (None, [d, d, d, vp, vp, vp, vp]),
             "orc_tab_rad": (None, [vp, d, vp]),
             "orc_emit": (None, [vp, vp, vp, vp, vp, i64]),
@@ -170,6 +172,40 @@ def nbw_Ka(chi, d):
 
 def nbw_Kb(chi, d):
     return lib().orc_nbw_Kb(float(chi), float(d))
+
+
+AX_SLOPE_Y, AX_SLOPE_Z, AX_SLOPE_R, AX_ENERGY = 0, 1, 2, 3
+
+
+class HistSpec(C.Structure):
+    _fields_ = [("axis", C.c_int32 * 2), ("n", C.c_int32 * 2), ("lo", C.c_double * 2), ("hi", C.c_double * 2),
+                ("pol_ref", C.c_double * 3)]
+
+
+def hist_spec(axes, n, lo, hi, pol_ref=(0.0, 1.0, 0.0)) -> HistSpec:
+    h = HistSpec()
+    for k in range(2):
+        h.axis[k], h.n[k], h.lo[k], h.hi[k] = int(axes[k]), int(n[k]), float(lo[k]), float(hi[k])
+    for k in range(3):
+        h.pol_ref[k] = float(pol_ref[k])
+    return h
+
+
+def hist_photons(G, begin: int, h: HistSpec) -> np.ndarray:
+    """Detector histogram of photons [begin, count): array [n1][n0][5] of
+    (w, w eps, w xi1, w xi2, w xi3) with the Stokes vector in the detector basis."""
+    out = np.zeros(h.n[0] * h.n[1] * 5)
+    s = G.ctype()
+    lib().orc_hist_photons(C.byref(s), int(begin), C.byref(h), _p(out))
+    return out.reshape(h.n[1], h.n[0], 5)
+
+
+def hist_leptons(L, begin: int, h: HistSpec) -> np.ndarray:
+    """The same for leptons: (w, w gamma, w Sx, w Sy, w Sz)."""
+    out = np.zeros(h.n[0] * h.n[1] * 5)
+    s = L.ctype()
+    lib().orc_hist_leptons(C.byref(s), int(begin), C.byref(h), _p(out))
+    return out.reshape(h.n[1], h.n[0], 5)
 
 
 def ll_force(g, p, E, B, alpha=None, xi_L=None) -> np.ndarray:

@@ -1227,3 +1227,72 @@ int64_t orc_compact_photons(orc_photons *G) {
     G->count = o;
     return o;
 }
+
+/* ============================================================ 10. detector diagnostics */
+/* bin of value v on axis k of h (energy axes: by comparison with the log10-spaced edges);
+ * -1 outside                                                                            */
+static int hist_bin(const orc_hist_spec *h, int k, double v) {
+    if (h->axis[k] == ORC_AX_ENERGY) {
+        int n = h->n[k];
+        double w = (h->hi[k] - h->lo[k]) / n;
+        if (!(v >= pow(10.0, h->lo[k])) || !(v < pow(10.0, h->lo[k] + n * w))) return -1;
+        int i = 0;
+        while (i + 1 < n && pow(10.0, h->lo[k] + (i + 1) * w) <= v) ++i;
+        return i;
+    }
+    double x = floor((v - h->lo[k]) * (h->n[k] / (h->hi[k] - h->lo[k])));
+    return (x >= 0 && x < h->n[k]) ? (int)x : -1;
+}
+static double axis_value(int axis, const double p[3], double energy) {
+    switch (axis) {
+    case ORC_AX_SLOPE_Y: return p[1] / p[0];
+    case ORC_AX_SLOPE_Z: return p[2] / p[0];
+    case ORC_AX_SLOPE_R: return sqrt(p[1] * p[1] + p[2] * p[2]) / p[0];
+    default: return energy;
+    }
+}
+static int hist_cell(const orc_hist_spec *h, const double p[3], double energy) {
+    if (!(p[0] > 0)) return -1;
+    int a = hist_bin(h, 0, axis_value(h->axis[0], p, energy));
+    int b = hist_bin(h, 1, axis_value(h->axis[1], p, energy));
+    return (a < 0 || b < 0) ? -1 : b * h->n[0] + a;
+}
+void orc_hist_photons(const orc_photons *G, int64_t begin, const orc_hist_spec *h, double *out) {
+    for (int64_t j = begin; j < G->count; ++j) {
+        if (!G->alive[j]) continue;
+        double k[3] = {G->kx[j], G->ky[j], G->kz[j]}, eps = norm3(k);
+        int cell = hist_cell(h, k, eps);
+        if (cell < 0) continue;
+        double n[3], e1[3] = {G->e1x[j], G->e1y[j], G->e1z[j]}, e2[3], d[3];
+        for (int q = 0; q < 3; ++q) n[q] = k[q] / eps;
+        double nd = dot3(n, h->pol_ref);
+        for (int q = 0; q < 3; ++q) d[q] = h->pol_ref[q] - nd * n[q];
+        double dn = norm3(d);
+        for (int q = 0; q < 3; ++q) d[q] /= dn;
+        cross3(n, e1, e2);
+        /* rotation from (e1, n x e1) to (d, n x d): eq. (rotation) with cos psi = e1.d,
+         * sin psi = e2.d, applied through cos 2psi, sin 2psi                              */
+        double c = dot3(e1, d), s = dot3(e2, d), c2 = c * c - s * s, s2 = 2 * c * s;
+        double x1 = G->xi1[j], x2 = G->xi2[j], x3 = G->xi3[j], w = G->w[j];
+        double *o = out + 5 * (int64_t)cell;
+        o[0] += w;
+        o[1] += w * eps;
+        o[2] += w * (c2 * x1 - s2 * x3);
+        o[3] += w * x2;
+        o[4] += w * (s2 * x1 + c2 * x3);
+    }
+}
+void orc_hist_leptons(const orc_leptons *L, int64_t begin, const orc_hist_spec *h, double *out) {
+    for (int64_t i = begin; i < L->count; ++i) {
+        double p[3] = {L->px[i], L->py[i], L->pz[i]}, g = sqrt(1 + dot3(p, p));
+        int cell = hist_cell(h, p, g);
+        if (cell < 0) continue;
+        double w = L->w[i], *o = out + 5 * (int64_t)cell;
+        o[0] += w;
+        o[1] += w * g;
+        o[2] += w * L->sx[i];
+        o[3] += w * L->sy[i];
+        o[4] += w * L->sz[i];
+    }
+}
+

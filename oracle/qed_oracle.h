@@ -141,6 +141,24 @@ void orc_photon_step(orc_config *c, const orc_tables *tab, const orc_field *f, o
 /* stable removal of dead photons; returns the new count                             */
 int64_t orc_compact_photons(orc_photons *G);
 
+/* detector diagnostics (the post-processing step of the VB algorithm, Sec. III.F):
+ * particles heading to +x are binned on two axes and, per bin, w, w eps, and w times the
+ * photon Stokes vector in the detector basis (or the lepton spin) are summed.  Axes:
+ * slopes p_y/p_x, p_z/p_x, sqrt(p_y^2+p_z^2)/p_x (linear bins: i = floor((v - lo) n/(hi-lo)))
+ * or the energy (|k| or gamma) on bins uniform in log10 between 10^lo and 10^hi (edges
+ * 10^(lo + k (hi-lo)/n), found by comparison).  Photon detector basis: e1 = unit part of
+ * pol_ref transverse to k, e2 = n x e1; xi rotated from (e1, n x e1) of the photon.       */
+enum { ORC_AX_SLOPE_Y = 0, ORC_AX_SLOPE_Z = 1, ORC_AX_SLOPE_R = 2, ORC_AX_ENERGY = 3 };
+typedef struct {
+    int32_t axis[2], n[2];
+    double lo[2], hi[2];
+    double pol_ref[3];
+} orc_hist_spec;
+/* out[((b n[0]) + a) 5 + q] += (w, w eps, w xi1', w xi2', w xi3') for photons [begin, count) */
+void orc_hist_photons(const orc_photons *G, int64_t begin, const orc_hist_spec *h, double *out);
+/* the same for leptons: (w, w gamma, w Sx, w Sy, w Sz)                                 */
+void orc_hist_leptons(const orc_leptons *L, int64_t begin, const orc_hist_spec *h, double *out);
+
 /* single-particle pieces used by the pins */
 void orc_boris(double q, double dt, const double E[3], const double B[3], double p[3],
                double pminus_out[3], double pplus_out[3]);
