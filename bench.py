@@ -372,6 +372,36 @@ def run_cascade(args, torch, Q, W):
             "status_bits": ctx.read_status()}
 
 
+BYTES_HIST_PHOTON = {"mixed": 24 + 12 + 12 + 8 + 1, "fp64": 24 + 24 + 24 + 8 + 1}   # read k, xi, e1, w, alive
+
+
+def run_detector(torch, Q, run, reps=5):
+    """Detector histogram (qed_hist_photons) over the photon list the mixed headline run
+    produced: angular map (p_y/p_x, p_z/p_x in +-10 mrad, 200 x 200) of counts, energy and
+    the Stokes vector in the (y, z) detector basis; best of `reps` launches."""
+    ctx, G = run["ctx"], run["G"]
+    n = G.count
+    h = Q.hist_spec((Q.AX_SLOPE_Y, Q.AX_SLOPE_Z), (200, 200), (-0.01, -0.01), (0.01, 0.01), (0, 1, 0))
+    out = torch.zeros((200, 200, 5), dtype=torch.float64, device="cuda")
+    best = float("inf")
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        out.zero_()
+        a.record()
+        ctx.hist_photons(G, 0, h, out=out)
+        b.record()
+        torch.cuda.synchronize()
+        best = min(best, a.elapsed_time(b))
+    binned = float(out[..., 0].sum())
+    gbs = n * BYTES_HIST_PHOTON["mixed"] / (best * 1e-3) / 1e9
+    xi3 = float(out[..., 4].sum()) / max(binned, 1.0)
+    return {"photons": n, "binned": binned, "ms": best, "photons_per_s": n / (best * 1e-3),
+            "mean_xi3_detector": xi3,
+            "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": gbs / HBM_PEAK_GBS, "bytes_per_photon": BYTES_HIST_PHOTON["mixed"]},
+            "bins": "200 x 200 in p_y/p_x, p_z/p_x over +-10 mrad"}
+
+
 BYTES_RADIATIVE = {"mixed": 48 + 12 + 48 + 12, "fp64": 48 + 24 + 48 + 24}   # read x, p, S; write x, p, S
 
 
@@ -536,6 +566,8 @@ def main():
                           "status_bits": fp64["status"]}
         result["speedup_mixed_over_fp64"] = result["value"] / result["fp64"]["value"]
         result["error_vs_fp64"] = error_metrics(fp64, mixed, 2000.0, torch)
+    print("[bench] detector histogram", file=sys.stderr, flush=True)
+    result["detector"] = run_detector(torch, Q, mixed)
     if args.radiative_steps > 0:
         print("[bench] radiative push", file=sys.stderr, flush=True)
         result["radiative"] = run_radiative(args, torch, Q, cfg)

@@ -194,6 +194,31 @@ qed_status qed_step_photons(qed_ctx_t *ctx, const qed_segment *segs, int nseg, q
 qed_status qed_compact_photons(qed_ctx_t *ctx, const qed_photons *in, qed_photons *out,
                                hipStream_t stream);
 
+/* Detector diagnostics: the post-processing step of the VB algorithm (Sec. III.F) on the
+ * device.  Particles [begin, count) heading to +x (p_x > 0; photons also alive) are
+ * binned on two axes and, per bin, added to out[((b * n[0]) + a) * 5 + q] (caller-owned
+ * device FP64 array of n[0] n[1] 5, not cleared):
+ *   photons: w, w eps, w xi1', w xi2', w xi3' with xi' the Stokes vector rotated from the
+ *            photon's basis (e1, n x e1) to the detector basis (d, n x d), d = unit part of
+ *            pol_ref transverse to k (eq. rotation);
+ *   leptons: w, w gamma, w Sx, w Sy, w Sz.
+ * Axes: QED_AX_SLOPE_Y = p_y/p_x, QED_AX_SLOPE_Z = p_z/p_x, QED_AX_SLOPE_R =
+ * sqrt(p_y^2+p_z^2)/p_x, each with bins floor((v - lo) n/(hi - lo)); QED_AX_ENERGY = |k| or
+ * gamma on n <= 256 bins uniform in log10 between 10^lo and 10^hi (edges computed on the host
+ * and compared against).  At most one energy axis; n[0] n[1] <= 2^24; lo < hi.  Sums use
+ * floating-point atomics: counts of unit weights are exact, the other sums are correct to
+ * rounding in an order that may change from run to run.                                  */
+enum { QED_AX_SLOPE_Y = 0, QED_AX_SLOPE_Z = 1, QED_AX_SLOPE_R = 2, QED_AX_ENERGY = 3 };
+typedef struct {
+    int32_t axis[2], n[2];
+    double lo[2], hi[2];
+    double pol_ref[3];
+} qed_hist_spec;
+qed_status qed_hist_photons(qed_ctx_t *ctx, const qed_photons *g, int64_t begin, const qed_hist_spec *h, double *out,
+                            hipStream_t stream);
+qed_status qed_hist_leptons(qed_ctx_t *ctx, const qed_leptons *l, int64_t begin, const qed_hist_spec *h, double *out,
+                            hipStream_t stream);
+
 /* Synchronises `stream`, returns the sticky status bits; qed_clear_status zeroes them. */
 qed_status qed_read_status(qed_ctx_t *ctx, uint32_t *flags_out, hipStream_t stream);
 qed_status qed_clear_status(qed_ctx_t *ctx, hipStream_t stream);

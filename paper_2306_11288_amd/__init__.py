@@ -28,7 +28,7 @@ EXPORTED = ["qed_init_tables", "qed_destroy", "qed_gather", "qed_push_spin", "qe
             "qed_set_step_events", "qed_set_step_counter", "qed_advance_step", "qed_get_tuning",
             "qed_set_tuning", "qed_autotune", "qed_mlp_init", "qed_mlp_set_params", "qed_mlp_get_params",
             "qed_mlp_samples", "qed_mlp_forward", "qed_mlp_gradient", "qed_mlp_train_step", "qed_set_sampler",
-            "qed_sampler_table",
+            "qed_sampler_table", "qed_hist_photons", "qed_hist_leptons",
             "qed_last_error"]
 
 MLP_NPARAM = 34051
@@ -60,6 +60,25 @@ class Field(C.Structure):
 
 class Segment(C.Structure):
     _fields_ = [("begin", C.c_int64), ("end", C.c_int64), ("field", Field)]
+
+
+AX_SLOPE_Y, AX_SLOPE_Z, AX_SLOPE_R, AX_ENERGY = 0, 1, 2, 3
+
+
+class HistSpec(C.Structure):
+    _fields_ = [("axis", C.c_int32 * 2), ("n", C.c_int32 * 2), ("lo", C.c_double * 2), ("hi", C.c_double * 2),
+                ("pol_ref", C.c_double * 3)]
+
+
+def hist_spec(axes, n, lo, hi, pol_ref=(0.0, 1.0, 0.0)) -> HistSpec:
+    """Detector histogram axes (AX_*), bins, ranges (energy axes: log10 of the energy) and
+    the lab vector that fixes the detector's polarisation basis."""
+    h = HistSpec()
+    for k in range(2):
+        h.axis[k], h.n[k], h.lo[k], h.hi[k] = int(axes[k]), int(n[k]), float(lo[k]), float(hi[k])
+    for k in range(3):
+        h.pol_ref[k] = float(pol_ref[k])
+    return h
 
 
 class Tuning(C.Structure):
@@ -97,6 +116,8 @@ def lib():
             "qed_gather": [vp, vp, C.c_int, vp, vp, i64, vp],
             "qed_push_spin": [vp, vp, C.c_int, vp, vp, i64, vp],
             "qed_push_radiative": [vp, vp, C.c_int, vp, C.c_uint32, i64, vp],
+            "qed_hist_photons": [vp, vp, i64, vp, vp, vp],
+            "qed_hist_leptons": [vp, vp, i64, vp, vp, vp],
             "qed_emit": [vp, vp, C.c_int, vp, vp, vp, i64, vp],
             "qed_step_leptons": [vp, vp, C.c_int, vp, vp, i64, vp],
             "qed_birefringence": [vp, vp, C.c_int, vp, i64, vp],
@@ -334,6 +355,25 @@ class Context:
         arr, n = segs
         self._check(lib().qed_push_radiative(self.h, arr, n, C.byref(L.c()), int(mode), step, _stream(stream)),
                     "qed_push_radiative")
+
+    def hist_photons(self, G: "Photons", begin: int, h: HistSpec, out=None, stream=None):
+        """Add photons [begin, count) to a detector histogram [n1][n0][5] (float64 device
+        tensor; allocated zeroed if not given) and return it."""
+        torch = _torch()
+        if out is None:
+            out = torch.zeros((h.n[1], h.n[0], 5), dtype=torch.float64, device="cuda")
+        self._check(lib().qed_hist_photons(self.h, C.byref(G.c()), int(begin), C.byref(h), _ptr(out),
+                                           _stream(stream)), "qed_hist_photons")
+        return out
+
+    def hist_leptons(self, L: "Leptons", begin: int, h: HistSpec, out=None, stream=None):
+        """The same for leptons (w, w gamma, w S)."""
+        torch = _torch()
+        if out is None:
+            out = torch.zeros((h.n[1], h.n[0], 5), dtype=torch.float64, device="cuda")
+        self._check(lib().qed_hist_leptons(self.h, C.byref(L.c()), int(begin), C.byref(h), _ptr(out),
+                                           _stream(stream)), "qed_hist_leptons")
+        return out
 
     def emit(self, segs, L: Leptons, E6, out: Photons | None, step: int, stream=None):
         arr, n = segs

@@ -334,6 +334,61 @@ qed_status qed_push_radiative(qed_ctx_t *ctx, const qed_segment *segs, int nseg,
     return launched(ctx, launch_radiative(ctx, sa, *p, mode, step, s), "qed_push_radiative");
 }
 
+static qed_status hist_args(qed_ctx *ctx, const qed_hist_spec *h, int64_t begin, double *out, bool photon,
+                            HistArgs &a, const char *name) {
+    if (!h || !out) return fail(ctx, QED_EARG, "%s: NULL histogram spec or output", name);
+    if (begin < 0) return fail(ctx, QED_EARG, "%s: begin must be >= 0", name);
+    a.begin = begin;
+    a.out = out;
+    a.eaxis = -1;
+    for (int k = 0; k < 2; ++k) {
+        if (h->axis[k] < QED_AX_SLOPE_Y || h->axis[k] > QED_AX_ENERGY)
+            return fail(ctx, QED_EARG, "%s: unknown axis %d", name, h->axis[k]);
+        if (h->n[k] < 1) return fail(ctx, QED_EARG, "%s: bins per axis must be >= 1", name);
+        if (!(h->lo[k] < h->hi[k])) return fail(ctx, QED_EARG, "%s: axis %d needs lo < hi", name, k);
+        a.axis[k] = h->axis[k];
+        a.n[k] = h->n[k];
+        a.lo[k] = h->lo[k];
+        a.inv_w[k] = h->n[k] / (h->hi[k] - h->lo[k]);
+        if (h->axis[k] == QED_AX_ENERGY) {
+            if (a.eaxis >= 0) return fail(ctx, QED_EARG, "%s: at most one energy axis", name);
+            if (h->n[k] > HIST_EMAX) return fail(ctx, QED_EARG, "%s: energy axis allows at most %d bins", name, HIST_EMAX);
+            a.eaxis = k;
+            const double w = (h->hi[k] - h->lo[k]) / h->n[k];
+            for (int i = 0; i <= h->n[k]; ++i) a.edges[i] = std::pow(10.0, h->lo[k] + i * w);
+        }
+    }
+    if ((int64_t)h->n[0] * h->n[1] > ((int64_t)1 << 24)) return fail(ctx, QED_EARG, "%s: more than 2^24 bins", name);
+    for (int k = 0; k < 3; ++k) a.pol_ref[k] = h->pol_ref[k];
+    if (photon && !(h->pol_ref[0] != 0 || h->pol_ref[1] != 0 || h->pol_ref[2] != 0))
+        return fail(ctx, QED_EARG, "%s: pol_ref must be non-zero", name);
+    return QED_OK;
+}
+
+qed_status qed_hist_photons(qed_ctx_t *ctx, const qed_photons *g, int64_t begin, const qed_hist_spec *h, double *out,
+                            hipStream_t s) {
+    qed_status st = ready(ctx);
+    if (st != QED_OK) return st;
+    if ((st = check_photons(ctx, g, "photons")) != QED_OK) return st;
+    HistArgs a{};
+    if ((st = hist_args(ctx, h, begin, out, true, a, "qed_hist_photons")) != QED_OK) return st;
+    a.G = *g;
+    if (begin >= g->capacity) return QED_OK;
+    return launched(ctx, launch_hist(ctx, a, true, g->capacity, s), "qed_hist_photons");
+}
+
+qed_status qed_hist_leptons(qed_ctx_t *ctx, const qed_leptons *l, int64_t begin, const qed_hist_spec *h, double *out,
+                            hipStream_t s) {
+    qed_status st = ready(ctx);
+    if (st != QED_OK) return st;
+    if ((st = check_leptons(ctx, l, "leptons")) != QED_OK) return st;
+    HistArgs a{};
+    if ((st = hist_args(ctx, h, begin, out, false, a, "qed_hist_leptons")) != QED_OK) return st;
+    a.L = *l;
+    if (begin >= l->capacity) return QED_OK;
+    return launched(ctx, launch_hist(ctx, a, false, l->capacity, s), "qed_hist_leptons");
+}
+
 qed_status qed_emit(qed_ctx_t *ctx, const qed_segment *segs, int nseg, qed_leptons *p, const double *E6,
                     qed_photons *out, int64_t step, hipStream_t s) {
     qed_status st = ready(ctx);

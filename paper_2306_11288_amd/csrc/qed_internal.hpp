@@ -124,6 +124,20 @@ constexpr int MLP_OW1 = 0, MLP_OB1 = 512, MLP_OW2 = 640, MLP_OB2 = 17024, MLP_OW
 constexpr double MLP_L10_MID = -0.65, MLP_L10_HALF = 2.35, MLP_L10_HI = 1.6989700043360187;
 constexpr double MLP_CHI_LO = 1e-3, MLP_CHI_HI = 50.0;
 
+// detector histogram launch (one energy axis at most, HIST_EMAX bins on it)
+constexpr int HIST_EMAX = 256;
+struct HistArgs {
+    qed_photons G;
+    qed_leptons L;
+    int64_t begin;
+    int32_t axis[2], n[2];
+    double lo[2], inv_w[2];       // linear axes: bin = floor((v - lo) inv_w), inv_w = n / (hi - lo)
+    double pol_ref[3];
+    int32_t eaxis;                // index of the energy axis, or -1
+    double *out;
+    double edges[HIST_EMAX + 1];  // energy axis: 10^(lo + k (hi - lo)/n), k = 0..n
+};
+
 constexpr int BLOCK = 256;             // threads per block = particles per tile
 constexpr int EV_GROUP_MAX = 16;       // lepton step: largest tiles-per-group of the event kernel
 
@@ -183,6 +197,8 @@ hipError_t launch_compact(qed_ctx *ctx, const qed_photons &in, const qed_photons
 hipError_t launch_advance_step(int64_t *step, int64_t by, hipStream_t s);
 hipError_t launch_radiative(qed_ctx *ctx, const SegArgs &sa, const qed_leptons &L, uint32_t mode, int64_t step,
                             hipStream_t s);
+// detector histograms (qed_detector.hip)
+hipError_t launch_hist(qed_ctx *ctx, const HistArgs &a, bool photons, int64_t capacity, hipStream_t s);
 // learned sampler (qed_mlp.hip)
 hipError_t mlp_alloc(qed_ctx *ctx);
 hipError_t mlp_init(qed_ctx *ctx, uint64_t seed, hipStream_t s);
