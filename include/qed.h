@@ -194,6 +194,15 @@ qed_status qed_step_photons(qed_ctx_t *ctx, const qed_segment *segs, int nseg, q
 qed_status qed_compact_photons(qed_ctx_t *ctx, const qed_photons *in, qed_photons *out,
                                hipStream_t stream);
 
+/* 2D vacuum field solver (Sec. II.B curl equations with z squeezed, no current; leapfrog of
+ * Sec. II.F): advances the six FP32 arrays of a GRID2D field ([ny][nx], the staggering of
+ * qed_field) in place by `steps` steps of dt, each  B -= dt/2 curl E;  E += dt curl B;
+ * B -= dt/2 curl E  (E and B both at integer times for the gather), with periodic wrap in
+ * x and y.  dt must satisfy the Courant limit dt < 1/sqrt(1/dx^2 + 1/dy^2) (QED_EARG
+ * otherwise); nx, ny >= 2.  Asynchronous on `stream`; 3 launches per step.             */
+qed_status qed_field_advance(qed_ctx_t *ctx, float *const grid[6], int32_t nx, int32_t ny, double dx, double dy,
+                             double dt, int64_t steps, hipStream_t stream);
+
 /* Detector diagnostics: the post-processing step of the VB algorithm (Sec. III.F) on the
  * device.  Particles [begin, count) heading to +x (p_x > 0; photons also alive) are
  * binned on two axes and, per bin, added to out[((b * n[0]) + a) * 5 + q] (caller-owned

@@ -28,7 +28,7 @@ EXPORTED = ["qed_init_tables", "qed_destroy", "qed_gather", "qed_push_spin", "qe
             "qed_set_step_events", "qed_set_step_counter", "qed_advance_step", "qed_get_tuning",
             "qed_set_tuning", "qed_autotune", "qed_mlp_init", "qed_mlp_set_params", "qed_mlp_get_params",
             "qed_mlp_samples", "qed_mlp_forward", "qed_mlp_gradient", "qed_mlp_train_step", "qed_set_sampler",
-            "qed_sampler_table", "qed_hist_photons", "qed_hist_leptons",
+            "qed_sampler_table", "qed_hist_photons", "qed_hist_leptons", "qed_field_advance",
             "qed_last_error"]
 
 MLP_NPARAM = 34051
@@ -117,6 +117,7 @@ def lib():
             "qed_push_spin": [vp, vp, C.c_int, vp, vp, i64, vp],
             "qed_push_radiative": [vp, vp, C.c_int, vp, C.c_uint32, i64, vp],
             "qed_hist_photons": [vp, vp, i64, vp, vp, vp],
+            "qed_field_advance": [vp, vp, C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_double, i64, vp],
             "qed_hist_leptons": [vp, vp, i64, vp, vp, vp],
             "qed_emit": [vp, vp, C.c_int, vp, vp, vp, i64, vp],
             "qed_step_leptons": [vp, vp, C.c_int, vp, vp, i64, vp],
@@ -355,6 +356,14 @@ class Context:
         arr, n = segs
         self._check(lib().qed_push_radiative(self.h, arr, n, C.byref(L.c()), int(mode), step, _stream(stream)),
                     "qed_push_radiative")
+
+    def field_advance(self, grid: dict, dt: float, steps: int = 1, stream=None):
+        """Advance a GRID2D field (dict with 'grid' = six float32 device tensors [ny][nx],
+        'nx', 'ny', 'dx', 'dy') in place by `steps` steps of the vacuum Yee solver."""
+        arr = (C.c_void_p * 6)(*[g.data_ptr() for g in grid["grid"]])
+        self._check(lib().qed_field_advance(self.h, arr, int(grid["nx"]), int(grid["ny"]), float(grid["dx"]),
+                                            float(grid["dy"]), float(dt), int(steps), _stream(stream)),
+                    "qed_field_advance")
 
     def hist_photons(self, G: "Photons", begin: int, h: HistSpec, out=None, stream=None):
         """Add photons [begin, count) to a detector histogram [n1][n0][5] (float64 device

@@ -334,6 +334,23 @@ qed_status qed_push_radiative(qed_ctx_t *ctx, const qed_segment *segs, int nseg,
     return launched(ctx, launch_radiative(ctx, sa, *p, mode, step, s), "qed_push_radiative");
 }
 
+qed_status qed_field_advance(qed_ctx_t *ctx, float *const grid[6], int32_t nx, int32_t ny, double dx, double dy,
+                             double dt, int64_t steps, hipStream_t s) {
+    qed_status st = ready(ctx);
+    if (st != QED_OK) return st;
+    if (!grid) return fail(ctx, QED_EARG, "qed_field_advance: NULL grid");
+    for (int c = 0; c < 6; ++c)
+        if (!grid[c]) return fail(ctx, QED_EARG, "qed_field_advance: grid component %d is NULL", c);
+    if (nx < 2 || ny < 2) return fail(ctx, QED_EARG, "qed_field_advance: nx, ny must be >= 2");
+    if ((int64_t)nx * ny > (int64_t)1 << 29) return fail(ctx, QED_EARG, "qed_field_advance: more than 2^29 nodes");
+    if (!(dx > 0) || !(dy > 0) || !(dt > 0)) return fail(ctx, QED_EARG, "qed_field_advance: dx, dy, dt must be > 0");
+    if (!(dt * std::sqrt(1.0 / (dx * dx) + 1.0 / (dy * dy)) < 1.0))
+        return fail(ctx, QED_EARG, "qed_field_advance: dt beyond the Courant limit");
+    if (steps < 0) return fail(ctx, QED_EARG, "qed_field_advance: steps must be >= 0");
+    if (steps == 0) return QED_OK;
+    return launched(ctx, launch_yee(grid, nx, ny, dx, dy, dt, steps, s), "qed_field_advance");
+}
+
 static qed_status hist_args(qed_ctx *ctx, const qed_hist_spec *h, int64_t begin, double *out, bool photon,
                             HistArgs &a, const char *name) {
     if (!h || !out) return fail(ctx, QED_EARG, "%s: NULL histogram spec or output", name);

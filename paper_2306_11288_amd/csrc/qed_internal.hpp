@@ -197,6 +197,9 @@ hipError_t launch_compact(qed_ctx *ctx, const qed_photons &in, const qed_photons
 hipError_t launch_advance_step(int64_t *step, int64_t by, hipStream_t s);
 hipError_t launch_radiative(qed_ctx *ctx, const SegArgs &sa, const qed_leptons &L, uint32_t mode, int64_t step,
                             hipStream_t s);
+// 2D vacuum Yee solver (qed_fdtd.hip): steps of dt, periodic
+hipError_t launch_yee(float *const g[6], int nx, int ny, double dx, double dy, double dt, int64_t steps,
+                      hipStream_t s);
 // detector histograms (qed_detector.hip)
 hipError_t launch_hist(qed_ctx *ctx, const HistArgs &a, bool photons, int64_t capacity, hipStream_t s);
 // learned sampler (qed_mlp.hip)
