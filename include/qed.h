@@ -216,7 +216,11 @@ qed_status qed_field_advance(qed_ctx_t *ctx, float *const grid[6], int32_t nx, i
  * gamma on n <= 256 bins uniform in log10 between 10^lo and 10^hi (edges computed on the host
  * and compared against).  At most one energy axis; n[0] n[1] <= 2^24; lo < hi.  Sums use
  * floating-point atomics: counts of unit weights are exact, the other sums are correct to
- * rounding in an order that may change from run to run.                                  */
+ * rounding in an order that may change from run to run.  When the list holds at least four
+ * particles per bin the blocks spread their atomics over 16 copies of the histogram
+ * (context-owned device memory of 16 n[0] n[1] 5 doubles, at most 2^25, kept for later
+ * calls; hipMalloc on first use or growth), added to `out` in copy order by a last launch.
+ * Calls on one context must not overlap.                                                  */
 enum { QED_AX_SLOPE_Y = 0, QED_AX_SLOPE_Z = 1, QED_AX_SLOPE_R = 2, QED_AX_ENERGY = 3 };
 typedef struct {
     int32_t axis[2], n[2];

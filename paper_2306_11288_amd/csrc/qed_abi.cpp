@@ -204,6 +204,7 @@ void free_ctx(qed_ctx *c) {
     hipFree(c->mlp_G);
     hipFree(c->mlp_WT);
     hipFree(c->mlp_work);
+    hipFree(c->hist_rep);
     hipFree(c->ev_in);
     hipFree(c->ev_out);
     if (c->hsegs) hipHostFree(c->hsegs);

@@ -58,6 +58,11 @@ __device__ __forceinline__ double gamma_exact(const V3<double> &p) {
     return sqrt(1.0 + (p.x * p.x + p.y * p.y + p.z * p.z));
 }
 
+// the block's histogram: one of a.rep replicas (blocks spread their atomics over the
+// replicas, which a final pass adds up in a fixed order), or the output itself
+__device__ __forceinline__ double *block_hist(const HistArgs &a) {
+    return a.rep > 1 ? a.acc + (int64_t)(blockIdx.x % a.rep) * a.rep_stride : a.out;
+}
 __device__ __forceinline__ void add5(double *out, int cell, double a0, double a1, double a2, double a3, double a4) {
     double *o = out + 5 * (int64_t)cell;
     unsafeAtomicAdd(o + 0, a0);
@@ -78,6 +83,7 @@ __global__ __launch_bounds__(BLOCK) void k_hist_photons(HistArgs a) {
     const T *xi1 = (const T *)a.G.xi1, *xi2 = (const T *)a.G.xi2, *xi3 = (const T *)a.G.xi3;
     const T *e1x = (const T *)a.G.e1x, *e1y = (const T *)a.G.e1y, *e1z = (const T *)a.G.e1z;
     const V3<double> ref = {a.pol_ref[0], a.pol_ref[1], a.pol_ref[2]};
+    double *hist = block_hist(a);
     for (int64_t j = a.begin + (int64_t)blockIdx.x * BLOCK + threadIdx.x; j < n; j += (int64_t)gridDim.x * BLOCK) {
         if (!a.G.alive[j]) continue;
         const V3<double> k = {a.G.kx[j], a.G.ky[j], a.G.kz[j]};
@@ -93,7 +99,7 @@ __global__ __launch_bounds__(BLOCK) void k_hist_photons(HistArgs a) {
         const V3<double> e2 = cross(nn, e1);
         const double c = dot(e1, d), s = dot(e2, d), c2 = c * c - s * s, s2 = 2.0 * c * s;
         const double x1 = (double)xi1[j], x2 = (double)xi2[j], x3 = (double)xi3[j], w = a.G.w[j];
-        add5(a.out, cell, w, w * eps, w * (c2 * x1 - s2 * x3), w * x2, w * (s2 * x1 + c2 * x3));
+        add5(hist, cell, w, w * eps, w * (c2 * x1 - s2 * x3), w * x2, w * (s2 * x1 + c2 * x3));
     }
 }
 
@@ -106,21 +112,58 @@ __global__ __launch_bounds__(BLOCK) void k_hist_leptons(HistArgs a) {
     }
     const int64_t n = clamp_count64(a.L.count, a.L.capacity);
     const T *sx = (const T *)a.L.sx, *sy = (const T *)a.L.sy, *sz = (const T *)a.L.sz;
+    double *hist = block_hist(a);
     for (int64_t i = a.begin + (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK) {
         const V3<double> p = {a.L.px[i], a.L.py[i], a.L.pz[i]};
         const double g = gamma_exact(p);
         const int cell = hist_cell(a, s_edges, p, g);
         if (cell < 0) continue;
         const double w = a.L.w[i];
-        add5(a.out, cell, w, w * g, w * (double)sx[i], w * (double)sy[i], w * (double)sz[i]);
+        add5(hist, cell, w, w * g, w * (double)sx[i], w * (double)sy[i], w * (double)sz[i]);
+    }
+}
+
+__global__ void k_zero(double *p, int64_t n) {
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+        p[k] = 0.0;
+}
+// out[k] += rep[0][k] + rep[1][k] + ... (in replica order)
+__global__ void k_hist_reduce(const double *rep, int R, int64_t len, double *out) {
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < len; k += (int64_t)gridDim.x * blockDim.x) {
+        double v = 0.0;
+        for (int r = 0; r < R; ++r) v += rep[(int64_t)r * len + k];
+        out[k] += v;
     }
 }
 
 }  // namespace
 
-hipError_t launch_hist(qed_ctx *ctx, const HistArgs &a, bool photons, int64_t capacity, hipStream_t s) {
+// Replicas: when the list can hold several times as many particles as there are bins, the
+// atomics of the bins a beam concentrates on contend; HIST_REP copies (context-owned,
+// grown on demand, at most HIST_REP_MAX doubles) spread them.
+constexpr int HIST_REP = 16;
+constexpr int64_t HIST_REP_MAX = (int64_t)1 << 25;
+
+hipError_t launch_hist(qed_ctx *ctx, const HistArgs &a0, bool photons, int64_t capacity, hipStream_t s) {
+    HistArgs a = a0;
+    const int64_t len = 5LL * a.n[0] * a.n[1];
     int64_t b = (capacity - a.begin + BLOCK - 1) / BLOCK;
     b = b < 1 ? 1 : (b > 65536 ? 65536 : b);
+    a.rep = 1;
+    if (capacity - a.begin >= 4 * (int64_t)a.n[0] * a.n[1] && HIST_REP * len <= HIST_REP_MAX && b >= HIST_REP) {
+        if (ctx->hist_rep_len < HIST_REP * len) {
+            (void)hipFree(ctx->hist_rep);
+            ctx->hist_rep = nullptr;
+            ctx->hist_rep_len = 0;
+            const hipError_t e = hipMalloc(&ctx->hist_rep, HIST_REP * len * sizeof(double));
+            if (e != hipSuccess) return e;
+            ctx->hist_rep_len = HIST_REP * len;
+        }
+        a.rep = HIST_REP;
+        a.acc = ctx->hist_rep;
+        a.rep_stride = len;
+        hipLaunchKernelGGL(k_zero, dim3(1024), dim3(256), 0, s, a.acc, HIST_REP * len);
+    }
     const dim3 gd((unsigned)b), bd(BLOCK);
     const bool mixed = ctx->cfg.precision == QED_MIXED;
     if (photons) {
@@ -130,6 +173,7 @@ hipError_t launch_hist(qed_ctx *ctx, const HistArgs &a, bool photons, int64_t ca
         if (mixed) hipLaunchKernelGGL(k_hist_leptons<float>, gd, bd, 0, s, a);
         else hipLaunchKernelGGL(k_hist_leptons<double>, gd, bd, 0, s, a);
     }
+    if (a.rep > 1) hipLaunchKernelGGL(k_hist_reduce, dim3(1024), dim3(256), 0, s, (const double *)a.acc, a.rep, len, a.out);
     return hipGetLastError();
 }
 

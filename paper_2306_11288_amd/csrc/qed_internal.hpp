@@ -135,6 +135,9 @@ struct HistArgs {
     double pol_ref[3];
     int32_t eaxis;                // index of the energy axis, or -1
     double *out;
+    double *acc;                  // replicas [rep][bins][5] when rep > 1 (then added to out)
+    int32_t rep;
+    int64_t rep_stride;
     double edges[HIST_EMAX + 1];  // energy axis: 10^(lo + k (hi - lo)/n), k = 0..n
 };
 
@@ -179,6 +182,8 @@ struct qed_ctx {
     int64_t mlp_work_len;
     int sampler;                       // QED_SAMPLER_TABLE or QED_SAMPLER_MLP
     float *ev_in, *ev_out;             // learned sampler: per-event network inputs [ev_cap][4], outputs [ev_cap][3]
+    double *hist_rep;                  // detector histogram replicas
+    int64_t hist_rep_len;
     int64_t ev_cap;
     char err[256];
 };
