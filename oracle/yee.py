@@ -5,9 +5,11 @@ Maxwell's curl equations in normalised units on the 2D Yee grid of Sec. II.B (z
 squeezed, d/dz = 0), with the staggering of the grid field: array index [j][i] holds
   Ex at (i+1/2, j), Ey at (i, j+1/2), Ez at (i, j),
   Bx at (i, j+1/2), By at (i+1/2, j), Bz at (i+1/2, j+1/2),
-periodic in both directions, no current.  One step of dt (leapfrog, Sec. II.F, with B
-split into two half steps so that E and B are both known at integer times):
-  B -= dt/2 curl E;  E += dt curl B;  B -= dt/2 curl E.
+periodic in both directions.  One step of dt (leapfrog, Sec. II.F, with B split into two
+half steps so that E and B are both known at integer times):
+  B -= dt/2 curl E;  E += dt (curl B - J);  B -= dt/2 curl E,
+with J = (Jx, Jy, Jz) at the staggering of E and the half-integer time of the step (zero
+when no current is given).
 The differences are written out with numpy's roll (periodic wrap).
 """
 from __future__ import annotations
@@ -45,21 +47,26 @@ def b_half(F, dx, dy, h):
     F[BZ] = F[BZ] - h * (_dxf(Ey, dx) - _dyf(Ex, dy))
 
 
-def e_full(F, dx, dy, dt):
-    """E += dt curl B:
-    Ex(i+1/2, j) += dt dBz/dy;  Ey(i, j+1/2) -= dt dBz/dx;
-    Ez(i, j) += dt (dBy/dx - dBx/dy)."""
+def e_full(F, dx, dy, dt, J=None):
+    """E += dt (curl B - J):
+    Ex(i+1/2, j) += dt (dBz/dy - Jx);  Ey(i, j+1/2) -= dt (dBz/dx + Jy);
+    Ez(i, j) += dt (dBy/dx - dBx/dy - Jz)."""
     Bx, By, Bz = F[BX], F[BY], F[BZ]
     F[EX] = F[EX] + dt * _dyb(Bz, dy)
     F[EY] = F[EY] - dt * _dxb(Bz, dx)
     F[EZ] = F[EZ] + dt * (_dxb(By, dx) - _dyb(Bx, dy))
+    if J is not None:
+        F[EX] = F[EX] - dt * J[0]
+        F[EY] = F[EY] - dt * J[1]
+        F[EZ] = F[EZ] - dt * J[2]
 
 
-def advance(F, dx: float, dy: float, dt: float, steps: int = 1):
-    """Advance the six FP64 arrays F[0..5] (each [ny][nx]) by `steps` steps in place."""
+def advance(F, dx: float, dy: float, dt: float, steps: int = 1, J=None):
+    """Advance the six FP64 arrays F[0..5] (each [ny][nx]) by `steps` steps in place, with
+    the current J (three [ny][nx] arrays, held fixed over the steps) if given."""
     for _ in range(steps):
         b_half(F, dx, dy, 0.5 * dt)
-        e_full(F, dx, dy, dt)
+        e_full(F, dx, dy, dt, J)
         b_half(F, dx, dy, 0.5 * dt)
     return F
 
