@@ -312,16 +312,24 @@ def run_learned(args, torch, Q, W, cfg, fp64):
 
 # Yee step: three passes, each reading 6 components and writing 3 (FP32)
 BYTES_YEE_NODE = 3 * (6 + 3) * 4
+# current deposition per lepton: read the start and end positions and the weight (FP64); the
+# atomics land in the 12.6 MB current grid, which stays in the caches
+BYTES_DEPOSIT = 7 * 8
+# charge of a unit-weight macro-particle in the field equations' units for the cascade: the
+# beam's own field stays far below the laser's (the cost does not depend on it)
+CASCADE_QSCALE = 1e-4
 # photon step: read x, k, xi, e1, id, alive; write x, xi, e1
 BYTES_PHOTON_STEP = {"mixed": 24 + 24 + 12 + 12 + 8 + 1 + 24 + 12 + 12, "fp64": 24 + 24 + 24 + 24 + 8 + 1 + 24 + 24 + 24}
 
 
 def run_cascade(args, torch, Q, W):
     """Cascade on a 2D Yee grid (2048 x 512 cells, 40 per wavelength, fp32 fields of a
-    linearly polarised a0 = 300 pulse, a static snapshot at its peak): 1e6 electrons at
-    gamma 4000 emit photons (NCS + Stokes), photons rotate their Stokes basis, evolve by
-    vacuum birefringence and create pairs (NBW); electrons, positrons and photons all
-    stepped.  A warm-up builds the photon population, then the timed steps."""
+    linearly polarised a0 = 300 pulse filled at t = 0): 1e6 electrons at gamma 4000 emit
+    photons (NCS + Stokes), photons rotate their Stokes basis, evolve by vacuum
+    birefringence and create pairs (NBW); electrons, positrons and photons all stepped, the
+    leptons' current deposited and the field advanced by the Yee solver every step (the
+    PIC loop; --no-deposit: vacuum solver, --static-grid: the snapshot at t = 0).  A
+    warm-up builds the photon population, then the timed steps."""
     cfg = W.c3()
     grid, pulse = cfg["grid"], dict(cfg["pulse"])
     pulse["phi_start"] = -pulse["ncycles"] * math.pi          # pulse centre at x = 0 for t = 0
@@ -339,29 +347,46 @@ def run_cascade(args, torch, Q, W):
     segs = Q.whole(spec)
     warm, steps = args.cascade_warmup, args.cascade_steps
     solver = not args.static_grid
-    for s in range(warm):
-        ctx.step(segs, em, ep, G, s)
-        if solver:
-            ctx.field_advance(spec, cfg["dt"], 1)
-    torch.cuda.synchronize()
-    counts0 = (em.count, ep.count, G.count)
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
-    t_ph = t_all = t_f = 0.0
-    t0 = time.perf_counter()
-    for s in range(warm, warm + steps):
-        ev[0].record()
+    deposit = solver and not args.no_deposit
+    J = [torch.zeros((grid["ny"], grid["nx"]), dtype=torch.float32, device="cuda") for _ in range(3)]
+    start = {"em": ctx.save_start(em), "ep": ctx.save_start(ep)}
+
+    def pic_step(s, ev=None):
+        """photons; save the lepton positions; leptons; current; field (the order of the
+        PIC loop: pairs born this step are pushed and deposited from their birth point)"""
+        if ev: ev[0].record()
         ctx.step_photons(segs, G, em, ep, s)
-        ev[1].record()
+        if ev: ev[1].record()
+        if deposit:
+            ctx.save_start(em, start["em"])
+            ctx.save_start(ep, start["ep"])
         ctx.step_leptons(segs, em, G, s)
         ctx.step_leptons(segs, ep, G, s)
-        ev[2].record()
+        if ev: ev[2].record()
+        if deposit:
+            for j in J:
+                j.zero_()
+            ctx.deposit_current(em, start["em"], grid, J, CASCADE_QSCALE)
+            ctx.deposit_current(ep, start["ep"], grid, J, CASCADE_QSCALE)
+        if ev: ev[3].record()
         if solver:
-            ctx.field_advance(spec, cfg["dt"], 1)
-        ev[3].record()
+            ctx.field_advance(spec, cfg["dt"], 1, current=J if deposit else None)
+        if ev: ev[4].record()
+
+    for s in range(warm):
+        pic_step(s)
+    torch.cuda.synchronize()
+    counts0 = (em.count, ep.count, G.count)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+    t_ph = t_all = t_f = t_d = 0.0
+    t0 = time.perf_counter()
+    for s in range(warm, warm + steps):
+        pic_step(s, ev)
         torch.cuda.synchronize()
         t_ph += ev[0].elapsed_time(ev[1])
-        t_all += ev[0].elapsed_time(ev[3])
-        t_f += ev[2].elapsed_time(ev[3])
+        t_all += ev[0].elapsed_time(ev[4])
+        t_d += ev[2].elapsed_time(ev[3])
+        t_f += ev[3].elapsed_time(ev[4])
     wall = time.perf_counter() - t0
     counts1 = (em.count, ep.count, G.count)
     lep_steps = sum((counts0[k] + counts1[k]) / 2 * steps for k in (0, 1))
@@ -370,8 +395,17 @@ def run_cascade(args, torch, Q, W):
     ph_bytes = (counts0[2] + counts1[2]) / 2 * BYTES_PHOTON_STEP["mixed"]
     nodes = grid["nx"] * grid["ny"]
     fgbs = nodes * BYTES_YEE_NODE / (t_f / steps * 1e-3) / 1e9 if solver and t_f > 0 else None
-    field = ({"solver": "2D vacuum Yee, periodic (the pulse filled at t = 0 and propagated on the grid)",
+    lep_mean = sum((counts0[k] + counts1[k]) / 2 for k in (0, 1))
+    dgbs = lep_mean * BYTES_DEPOSIT / (t_d / steps * 1e-3) / 1e9 if deposit and t_d > 0 else None
+    field = ({"solver": ("2D Yee, periodic, with the current the leptons deposit each step (charge-conserving, "
+                         f"qscale {CASCADE_QSCALE})" if deposit else
+                         "2D vacuum Yee, periodic (the pulse filled at t = 0 and propagated on the grid)"),
               "ms_per_step": t_f / steps,
+              "deposit": ({"ms_per_step": t_d / steps, "leptons": lep_mean,
+                           "leptons_per_s": lep_mean / (t_d / steps * 1e-3),
+                           "roofline": {"bound": "hbm", "achieved": dgbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                        "frac": dgbs / HBM_PEAK_GBS, "bytes_per_lepton": BYTES_DEPOSIT},
+                           "note": "includes zeroing J and saving the start positions"} if deposit else None),
               "roofline": {"bound": "hbm", "achieved": fgbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": fgbs / HBM_PEAK_GBS, "bytes_per_node_step": BYTES_YEE_NODE}}
              if solver else {"solver": "none (static snapshot of the pulse)"})
@@ -500,6 +534,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-sampler measurements")
     ap.add_argument("--cascade-steps", type=int, default=40, help="timed steps of the cascade (0: skip it)")
     ap.add_argument("--cascade-warmup", type=int, default=150)
+    ap.add_argument("--no-deposit", action="store_true",
+                    help="cascade: vacuum field solver, no current deposition")
     ap.add_argument("--static-grid", action="store_true",
                     help="cascade on a static snapshot of the pulse instead of the Yee-propagated field")
     ap.add_argument("--radiative-steps", type=int, default=20,

@@ -68,7 +68,9 @@ enum {
     QED_ST_PMAX = 4,       /* a per-step event probability exceeded cfg.p_max          */
     QED_ST_EPS_LT1 = 8,    /* a pair member was born with energy below m c^2            */
     QED_ST_CLAMP = 16,     /* chi above the tabulated range (value clamped)             */
-    QED_ST_SCAN = 32       /* reserved; not set by this version */
+    QED_ST_SCAN = 32,      /* reserved; not set by this version */
+    QED_ST_DEPOSIT = 64    /* current deposition skipped a particle that moved a cell or more
+                              in one step, or whose position or weight is not finite     */
 };
 /* field kinds */
 enum { QED_FIELD_NONE = 0, QED_FIELD_CONST = 1, QED_FIELD_PW = 2, QED_FIELD_GAUSS = 3,
@@ -194,14 +196,41 @@ qed_status qed_step_photons(qed_ctx_t *ctx, const qed_segment *segs, int nseg, q
 qed_status qed_compact_photons(qed_ctx_t *ctx, const qed_photons *in, qed_photons *out,
                                hipStream_t stream);
 
-/* 2D vacuum field solver (Sec. II.B curl equations with z squeezed, no current; leapfrog of
- * Sec. II.F): advances the six FP32 arrays of a GRID2D field ([ny][nx], the staggering of
- * qed_field) in place by `steps` steps of dt, each  B -= dt/2 curl E;  E += dt curl B;
+/* 2D field solver (Sec. II.B curl equations with z squeezed; leapfrog of Sec. II.F):
+ * advances the six FP32 arrays of a GRID2D field ([ny][nx], the staggering of qed_field) in
+ * place by `steps` steps of dt, each  B -= dt/2 curl E;  E += dt (curl B - J);
  * B -= dt/2 curl E  (E and B both at integer times for the gather), with periodic wrap in
- * x and y.  dt must satisfy the Courant limit dt < 1/sqrt(1/dx^2 + 1/dy^2) (QED_EARG
+ * x and y.  `current` is NULL (vacuum) or three FP32 arrays Jx, Jy, Jz [ny][nx] at the
+ * staggering of Ex, Ey, Ez (as qed_deposit_current writes them), held fixed over the
+ * steps.  dt must satisfy the Courant limit dt < 1/sqrt(1/dx^2 + 1/dy^2) (QED_EARG
  * otherwise); nx, ny >= 2.  Asynchronous on `stream`; 3 launches per step.             */
-qed_status qed_field_advance(qed_ctx_t *ctx, float *const grid[6], int32_t nx, int32_t ny, double dx, double dy,
-                             double dt, int64_t steps, hipStream_t stream);
+qed_status qed_field_advance(qed_ctx_t *ctx, float *const grid[6], const float *const current[3], int32_t nx,
+                             int32_t ny, double dx, double dy, double dt, int64_t steps, hipStream_t stream);
+
+/* Charge-conserving current deposition (Sec. II.C, Esirkepov's decomposition with the TSC
+ * shapes of Sec. II.E): leptons [0, *n0) that moved from (x0[0], x0[1], x0[2]) (device FP64
+ * arrays of the positions at the start of the step, caller-saved) to their current
+ * positions over one step dt ADD their current to `current` (three caller-owned device FP32
+ * arrays [ny][nx], not cleared: Jx at (i+1/2, j), Jy at (i, j+1/2), Jz at (i, j), node (i, j)
+ * at (gx0 + i dx, gy0 + j dy), periodic in x and y).  A particle of weight w carries charge
+ * Q = charge w qscale (qscale: the charge of a unit weight in the units of the field
+ * equations); its current satisfies (rho1 - rho0)/dt + div J = 0 at every node with
+ * rho = Q Sx Sy/(dx dy), so the solver keeps Gauss's law.  n0 is a device scalar (the
+ * list's count at the start of the step: particles appended during the step start with
+ * the next one).  A move of a cell or more per axis, or a non-finite position or weight,
+ * skips the particle and sets QED_ST_DEPOSIT.  FP32 sums, correct to FP32 rounding in an
+ * order that may change from run to run.  nx, ny >= 2, at most 2^29 nodes.  Grids of at
+ * most 4096 tiles of 64 x 64 nodes take a binned path with context-owned work memory (tile
+ * counters; 56 bytes per lepton of the largest list seen, hipMalloc on first use or
+ * growth); calls on one context must not overlap.                                        */
+qed_status qed_deposit_current(qed_ctx_t *ctx, const qed_leptons *l, const double *const x0[3], const int64_t *n0,
+                               float *const current[3], int32_t nx, int32_t ny, double dx, double dy, double gx0,
+                               double gy0, double dt, double qscale, hipStream_t stream);
+/* The start state qed_deposit_current needs: copies positions [0, count) of `l` into the
+ * device FP64 arrays x0[0..2] (capacity entries each, caller-owned) and the count into the
+ * device scalar *n0.  Asynchronous on `stream`; call it before the step that moves them.  */
+qed_status qed_save_start(qed_ctx_t *ctx, const qed_leptons *l, double *const x0[3], int64_t *n0,
+                          hipStream_t stream);
 
 /* Detector diagnostics: the post-processing step of the VB algorithm (Sec. III.F) on the
  * device.  Particles [begin, count) heading to +x (p_x > 0; photons also alive) are

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libqed.so")
 QED_OK, QED_EARG, QED_ENOMEM, QED_EHIP, QED_ESTATE = range(5)
 QED_FP64, QED_MIXED = 0, 1
 PROC_NCS, PROC_NCS_STOKES, PROC_NBW, PROC_VB = 1, 2, 4, 8
-ST_OVERFLOW, ST_NAN, ST_PMAX, ST_EPS_LT1, ST_CLAMP, ST_SCAN = 1, 2, 4, 8, 16, 32
+ST_OVERFLOW, ST_NAN, ST_PMAX, ST_EPS_LT1, ST_CLAMP, ST_SCAN, ST_DEPOSIT = 1, 2, 4, 8, 16, 32, 64
 FIELD_NONE, FIELD_CONST, FIELD_PW, FIELD_GAUSS, FIELD_GRID2D = 0, 1, 2, 3, 4
 TAB_BESSEL, TAB_NCS_RATE, TAB_NCS_CDF, TAB_NBW_RATE, TAB_NBW_CDF, TAB_VB, TAB_RAD = range(7)
 RR_LL, RR_MLL, RR_RBMT = 1, 2, 4
@@ -29,7 +29,7 @@ EXPORTED = ["qed_init_tables", "qed_destroy", "qed_gather", "qed_push_spin", "qe
             "qed_set_tuning", "qed_autotune", "qed_mlp_init", "qed_mlp_set_params", "qed_mlp_get_params",
             "qed_mlp_samples", "qed_mlp_forward", "qed_mlp_gradient", "qed_mlp_train_step", "qed_set_sampler",
             "qed_sampler_table", "qed_hist_photons", "qed_hist_leptons", "qed_field_advance",
-            "qed_last_error"]
+            "qed_deposit_current", "qed_save_start", "qed_last_error"]
 
 MLP_NPARAM = 34051
 SAMPLER_TABLE, SAMPLER_MLP = 0, 1
@@ -117,7 +117,10 @@ def lib():
             "qed_push_spin": [vp, vp, C.c_int, vp, vp, i64, vp],
             "qed_push_radiative": [vp, vp, C.c_int, vp, C.c_uint32, i64, vp],
             "qed_hist_photons": [vp, vp, i64, vp, vp, vp],
-            "qed_field_advance": [vp, vp, C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_double, i64, vp],
+            "qed_field_advance": [vp, vp, vp, C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_double, i64, vp],
+            "qed_deposit_current": [vp, vp, vp, vp, vp, C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_double,
+                                    C.c_double, C.c_double, C.c_double, vp],
+            "qed_save_start": [vp, vp, vp, vp, vp],
             "qed_hist_leptons": [vp, vp, i64, vp, vp, vp],
             "qed_emit": [vp, vp, C.c_int, vp, vp, vp, i64, vp],
             "qed_step_leptons": [vp, vp, C.c_int, vp, vp, i64, vp],
@@ -357,13 +360,40 @@ class Context:
         self._check(lib().qed_push_radiative(self.h, arr, n, C.byref(L.c()), int(mode), step, _stream(stream)),
                     "qed_push_radiative")
 
-    def field_advance(self, grid: dict, dt: float, steps: int = 1, stream=None):
+    def field_advance(self, grid: dict, dt: float, steps: int = 1, current=None, stream=None):
         """Advance a GRID2D field (dict with 'grid' = six float32 device tensors [ny][nx],
-        'nx', 'ny', 'dx', 'dy') in place by `steps` steps of the vacuum Yee solver."""
+        'nx', 'ny', 'dx', 'dy') in place by `steps` steps of the Yee solver, with the current
+        `current` (three float32 device tensors [ny][nx]: Jx, Jy, Jz) if given."""
         arr = (C.c_void_p * 6)(*[g.data_ptr() for g in grid["grid"]])
-        self._check(lib().qed_field_advance(self.h, arr, int(grid["nx"]), int(grid["ny"]), float(grid["dx"]),
+        cur = None if current is None else (C.c_void_p * 3)(*[j.data_ptr() for j in current])
+        self._check(lib().qed_field_advance(self.h, arr, cur, int(grid["nx"]), int(grid["ny"]), float(grid["dx"]),
                                             float(grid["dy"]), float(dt), int(steps), _stream(stream)),
                     "qed_field_advance")
+
+    def save_start(self, L: "Leptons", out=None, stream=None):
+        """Positions and count of L at the start of a step, for deposit_current
+        (qed_save_start): device tensors (x0, y0, z0, n0), written into `out` (a previous
+        result) when given."""
+        torch = _torch()
+        if out is None:
+            out = tuple(torch.empty(L.capacity, dtype=torch.float64, device=L.x.device) for _ in range(3)) + \
+                (torch.zeros(1, dtype=torch.int64, device=L.x.device),)
+        x0 = (C.c_void_p * 3)(*[t.data_ptr() for t in out[:3]])
+        self._check(lib().qed_save_start(self.h, C.byref(L.c()), x0, _ptr(out[3]), _stream(stream)),
+                    "qed_save_start")
+        return out
+
+    def deposit_current(self, L: "Leptons", start, grid: dict, current, qscale: float, stream=None):
+        """Add the current of leptons [0, n0) that moved from the saved start positions to
+        their current ones over one step of this context's dt to `current` (three float32
+        device tensors [ny][nx]).  `start` = (x0, y0, z0, n0): float64 device tensors of the
+        positions and the int64 device count at the start of the step (save_start)."""
+        x0 = (C.c_void_p * 3)(*[t.data_ptr() for t in start[:3]])
+        cur = (C.c_void_p * 3)(*[j.data_ptr() for j in current])
+        self._check(lib().qed_deposit_current(self.h, C.byref(L.c()), x0, _ptr(start[3]), cur, int(grid["nx"]),
+                                              int(grid["ny"]), float(grid["dx"]), float(grid["dy"]),
+                                              float(grid["gx0"]), float(grid["gy0"]), float(self.cfg.dt), float(qscale),
+                                              _stream(stream)), "qed_deposit_current")
 
     def hist_photons(self, G: "Photons", begin: int, h: HistSpec, out=None, stream=None):
         """Add photons [begin, count) to a detector histogram [n1][n0][5] (float64 device

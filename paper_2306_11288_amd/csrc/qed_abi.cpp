@@ -205,6 +205,10 @@ void free_ctx(qed_ctx *c) {
     hipFree(c->mlp_WT);
     hipFree(c->mlp_work);
     hipFree(c->hist_rep);
+    hipFree(c->dep_cnt);
+    hipFree(c->dep_work);
+    hipFree(c->dep_rec);
+    hipFree(c->dep_acc);
     hipFree(c->ev_in);
     hipFree(c->ev_out);
     if (c->hsegs) hipHostFree(c->hsegs);
@@ -335,13 +339,16 @@ qed_status qed_push_radiative(qed_ctx_t *ctx, const qed_segment *segs, int nseg,
     return launched(ctx, launch_radiative(ctx, sa, *p, mode, step, s), "qed_push_radiative");
 }
 
-qed_status qed_field_advance(qed_ctx_t *ctx, float *const grid[6], int32_t nx, int32_t ny, double dx, double dy,
-                             double dt, int64_t steps, hipStream_t s) {
+qed_status qed_field_advance(qed_ctx_t *ctx, float *const grid[6], const float *const current[3], int32_t nx,
+                             int32_t ny, double dx, double dy, double dt, int64_t steps, hipStream_t s) {
     qed_status st = ready(ctx);
     if (st != QED_OK) return st;
     if (!grid) return fail(ctx, QED_EARG, "qed_field_advance: NULL grid");
     for (int c = 0; c < 6; ++c)
         if (!grid[c]) return fail(ctx, QED_EARG, "qed_field_advance: grid component %d is NULL", c);
+    if (current)
+        for (int c = 0; c < 3; ++c)
+            if (!current[c]) return fail(ctx, QED_EARG, "qed_field_advance: current component %d is NULL", c);
     if (nx < 2 || ny < 2) return fail(ctx, QED_EARG, "qed_field_advance: nx, ny must be >= 2");
     if ((int64_t)nx * ny > (int64_t)1 << 29) return fail(ctx, QED_EARG, "qed_field_advance: more than 2^29 nodes");
     if (!(dx > 0) || !(dy > 0) || !(dt > 0)) return fail(ctx, QED_EARG, "qed_field_advance: dx, dy, dt must be > 0");
@@ -349,7 +356,34 @@ qed_status qed_field_advance(qed_ctx_t *ctx, float *const grid[6], int32_t nx, i
         return fail(ctx, QED_EARG, "qed_field_advance: dt beyond the Courant limit");
     if (steps < 0) return fail(ctx, QED_EARG, "qed_field_advance: steps must be >= 0");
     if (steps == 0) return QED_OK;
-    return launched(ctx, launch_yee(grid, nx, ny, dx, dy, dt, steps, s), "qed_field_advance");
+    return launched(ctx, launch_yee(grid, current, nx, ny, dx, dy, dt, steps, s), "qed_field_advance");
+}
+
+qed_status qed_save_start(qed_ctx_t *ctx, const qed_leptons *l, double *const x0[3], int64_t *n0, hipStream_t s) {
+    qed_status st = ready(ctx);
+    if (st != QED_OK) return st;
+    if ((st = check_leptons(ctx, l, "leptons")) != QED_OK) return st;
+    if (!x0 || !x0[0] || !x0[1] || !x0[2] || !n0) return fail(ctx, QED_EARG, "qed_save_start: NULL output");
+    return launched(ctx, launch_save_start(ctx, *l, x0, n0, s), "qed_save_start");
+}
+
+qed_status qed_deposit_current(qed_ctx_t *ctx, const qed_leptons *l, const double *const x0[3], const int64_t *n0,
+                               float *const current[3], int32_t nx, int32_t ny, double dx, double dy, double gx0,
+                               double gy0, double dt, double qscale, hipStream_t s) {
+    qed_status st = ready(ctx);
+    if (st != QED_OK) return st;
+    if ((st = check_leptons(ctx, l, "leptons")) != QED_OK) return st;
+    if (!x0 || !x0[0] || !x0[1] || !x0[2]) return fail(ctx, QED_EARG, "qed_deposit_current: NULL start positions");
+    if (!n0) return fail(ctx, QED_EARG, "qed_deposit_current: NULL start count");
+    if (!current || !current[0] || !current[1] || !current[2])
+        return fail(ctx, QED_EARG, "qed_deposit_current: NULL current array");
+    if (nx < 2 || ny < 2) return fail(ctx, QED_EARG, "qed_deposit_current: nx, ny must be >= 2");
+    if ((int64_t)nx * ny > (int64_t)1 << 29) return fail(ctx, QED_EARG, "qed_deposit_current: more than 2^29 nodes");
+    if (!(dx > 0) || !(dy > 0) || !(dt > 0)) return fail(ctx, QED_EARG, "qed_deposit_current: dx, dy, dt must be > 0");
+    if (!std::isfinite(gx0) || !std::isfinite(gy0) || !std::isfinite(qscale))
+        return fail(ctx, QED_EARG, "qed_deposit_current: gx0, gy0, qscale must be finite");
+    return launched(ctx, launch_deposit(ctx, *l, x0, n0, current, nx, ny, dx, dy, gx0, gy0, dt, qscale, s),
+                    "qed_deposit_current");
 }
 
 static qed_status hist_args(qed_ctx *ctx, const qed_hist_spec *h, int64_t begin, double *out, bool photon,

@@ -1,0 +1,525 @@
+// Charge-conserving current deposition (Sec. II.C) onto the 2D Yee grid of the GRID2D
+// field: Jx at (i+1/2, j), Jy at (i, j+1/2), Jz at (i, j), array index [j][i], periodic.
+//
+// A particle moving from xa to xb within one step (less than a cell per axis) has TSC
+// shapes (Sec. II.E, node-centred) S0 at the start and S1 at the end, both taken on the
+// 5 x 5 node window centred on the start node; with DS = S1 - S0 (Esirkepov's
+// decomposition of the change of its charge):
+//   Wx = DSx (S0y + DSy/2),  Wy = DSy (S0x + DSx/2),
+//   Wz = S0x S0y + DSx S0y/2 + S0x DSy/2 + DSx DSy/3,
+//   Jx(i+1/2, j) = Jx(i-1/2, j) - Q Wx / (dy dt),  Jy(i, j+1/2) = Jy(i, j-1/2) - Q Wy / (dx dt),
+//   Jz = Q vz Wz / (dx dy),  vz = (zb - za)/dt,  Q = q w qscale,
+// which makes (rho1 - rho0)/dt + div J vanish node by node.  Weights in FP64 (the DS are
+// small differences of O(1) values), contributions rounded to FP32 (the grid's precision)
+// and summed in FP32 in an order that is not fixed; exact zeros are skipped (a particle
+// moving along x at a tenth of a cell per step adds about 25 values).
+//
+// Beams put hundreds of particles on each node, so adding every contribution to HBM with
+// a device-wide atomic serialises on the hot nodes.  The tiled path bins the particles by
+// the tile of T x T nodes that holds their start node and accumulates each tile in LDS:
+//   1. count   : particles per tile (LDS histogram per block, one global add per tile),
+//                largest |w| and |w dz|;
+//   2. scan    : tile offsets, a work list of chunks of at most DEP_CH particles, and the
+//                fixed-point scale of each component (a power of two that maps the largest
+//                possible contribution to 2^32);
+//   3. scatter : a 56-byte record per particle (offsets from the nodes, weight, shifts,
+//                node in the tile) at its tile's place (LDS rank + one reservation per
+//                block and tile);
+//   4. tiles   : one block per chunk adds its records, in 64-bit fixed point, to the
+//                (T+4)^2 LDS window of the tile (two-node halo: LDS integer atomics run at
+//                several times the rate of LDS float atomics here), then adds the non-zero
+//                window sums to a context-owned 64-bit grid with global integer atomics;
+//   5. convert : the 64-bit grid, scaled back, is added to J (FP32) and cleared.
+// Integer sums do not depend on the order of the additions, so the tiled path gives the
+// same J on every run; its only roundings are the fixed-point quantum (2^-32 of the largest
+// contribution) and one FP32 rounding per node.  T is 16 or 32, the smaller one with at
+// most DEP_MAX_TILES tiles; larger grids take the direct path (one thread per particle,
+// FP32 global atomics, order of the sums not fixed).
+#include "qed_internal.hpp"
+
+namespace qed {
+namespace {
+
+constexpr int DBLOCK = 256;
+constexpr int DEP_PT = 4;                  // particles per thread in the count / scatter blocks
+constexpr int DEP_PB = DEP_PT * DBLOCK;    // particles per count / scatter block
+constexpr int DEP_MAX_TILES = 8192;        // tiles of the tiled path (LDS histograms of this many ints)
+constexpr int DEP_CH = 4096;               // records per block of the tile kernel
+
+// a particle's deposit, relative to its start node: offsets of the start and end positions
+// from their nearest nodes (cell units), weight, weight times the z move; code = node in the
+// tile (x | y << 8) | (end node - start node + 1) in x << 16 and in y << 18
+struct DepRec {
+    double ax, ay, bx, by, w, wdz;
+    int32_t code, pad;
+};
+
+struct DepositArgs {
+    const double *x, *y, *z, *w;      // positions at the end of the step, weights
+    const double *x0, *y0, *z0;       // positions at the start of the step
+    const int64_t *n0;                // particles [0, *n0) are deposited
+    int64_t capacity;
+    float *jx, *jy, *jz;
+    int32_t nx, ny;
+    double gx0, gy0, inv_dx, inv_dy;
+    double cx, cy, cz;                // -q qscale/(dy dt), -q qscale/(dx dt), q qscale/(dx dy dt)
+    uint32_t *status;
+    // tiled path
+    int32_t T, ntx, nt;
+    int *cnt, *off, *cur, *nwork;      // per tile: count, offset, cursor; chunks in the work list
+    int4 *work;
+    DepRec *rec;
+    unsigned long long *amax;          // bit patterns of the largest |w| and |w dz| (zero between calls)
+    double *scale;                     // fixed-point scale and its inverse per component [6]
+    unsigned long long *acc;           // 64-bit fixed-point J [3][ny][nx] (zero between calls)
+};
+
+__device__ __forceinline__ int64_t dep_count(const DepositArgs &a) {
+    const int64_t n = *a.n0;
+    return n < 0 ? 0 : (n > a.capacity ? a.capacity : n);
+}
+
+// start node (wrapped into the grid) and record of particle i; false for a particle that
+// is not deposited (non-finite, absurdly far, or a move of a cell or more)
+__device__ __forceinline__ bool classify(const DepositArgs &a, int64_t i, DepRec &r, int &ic, int &lc) {
+    const double Xa = (a.x0[i] - a.gx0) * a.inv_dx, Ya = (a.y0[i] - a.gy0) * a.inv_dy;
+    const double Xb = (a.x[i] - a.gx0) * a.inv_dx, Yb = (a.y[i] - a.gy0) * a.inv_dy;
+    const double dz = a.z[i] - a.z0[i], w = a.w[i];
+    const double lim = 1073741824.0;
+    if (!(fabs(Xa) < lim && fabs(Ya) < lim && fabs(Xb - Xa) < 1.0 && fabs(Yb - Ya) < 1.0 && isfinite(dz) &&
+          isfinite(w)))
+        return false;
+    const double ja = floor(Xa + 0.5), ka = floor(Ya + 0.5);
+    const double jb = floor(Xb + 0.5), kb = floor(Yb + 0.5);
+    r.ax = Xa - ja;
+    r.ay = Ya - ka;
+    r.bx = Xb - jb;
+    r.by = Yb - kb;
+    r.w = w;
+    r.wdz = w * dz;
+    r.code = ((int)(jb - ja) + 1) << 16 | ((int)(kb - ka) + 1) << 18;
+    const int ia = (int)(ja - a.nx * floor(ja / a.nx)), la = (int)(ka - a.ny * floor(ka / a.ny));
+    ic = ia >= a.nx ? ia - a.nx : (ia < 0 ? ia + a.nx : ia);
+    lc = la >= a.ny ? la - a.ny : (la < 0 ? la + a.ny : la);
+    return true;
+}
+
+// TSC weights of nodes j-1, j, j+1 for offset d = X - j in [-1/2, 1/2], on a 4-slot window
+// whose slot k is slot k + o of the 5-slot window, where slot 2 + s holds node j
+__device__ __forceinline__ void window4(double d, int s, int o, double out[4]) {
+    const double a = 0.5 - d, b = 0.5 + d;
+    const double m = 0.5 * a * a, c = 0.75 - d * d, p = 0.5 * b * b;
+    const int k0 = s + 1 - o;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) out[k] = k == k0 ? m : (k == k0 + 1 ? c : (k == k0 + 2 ? p : 0.0));
+}
+
+// adds the record's current through sink.add(component, row slot l, column slot m, value)
+// (slots of the 5 x 5 window centred on the start node).  The start and end shapes of a
+// move of less than a cell cover at most 4 consecutive slots per axis, from o = 1 + min(s, 0).
+template <class Sink>
+__device__ __forceinline__ void deposit_record(const DepositArgs &a, const DepRec &r, Sink &sink) {
+    const int sx = ((r.code >> 16) & 3) - 1, sy = ((r.code >> 18) & 3) - 1;
+    const int ox = 1 + (sx < 0 ? sx : 0), oy = 1 + (sy < 0 ? sy : 0);
+    double S0x[4], S1x[4], S0y[4], S1y[4];
+    window4(r.ax, 0, ox, S0x);
+    window4(r.bx, sx, ox, S1x);
+    window4(r.ay, 0, oy, S0y);
+    window4(r.by, sy, oy, S1y);
+    const double qx = a.cx * r.w, qy = a.cy * r.w, qz = a.cz * r.wdz;
+    // Jx: running sum along x in each row (the sum over the window is zero, so the last
+    // slot carries nothing)
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+        const double wy = S0y[l] + 0.5 * (S1y[l] - S0y[l]);
+        if (wy == 0.0) continue;
+        double run = 0.0;
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            run += qx * (S1x[m] - S0x[m]) * wy;
+            sink.add(0, l + oy, m + ox, run);
+        }
+    }
+    // Jy: running sum along y in each column
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        const double wx = S0x[m] + 0.5 * (S1x[m] - S0x[m]);
+        if (wx == 0.0) continue;
+        double run = 0.0;
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+            run += qy * (S1y[l] - S0y[l]) * wx;
+            sink.add(1, l + oy, m + ox, run);
+        }
+    }
+    // Jz: step average of the product of the linearly interpolated shapes
+    if (qz != 0.0) {
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+            const double s0y = S0y[l], dsy = S1y[l] - S0y[l];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const double s0x = S0x[m], dsx = S1x[m] - S0x[m];
+                const double wz = s0x * s0y + 0.5 * dsx * s0y + 0.5 * s0x * dsy + dsx * dsy * (1.0 / 3.0);
+                sink.add(2, l + oy, m + ox, qz * wz);
+            }
+        }
+    }
+}
+
+// node index of j + m - 2 wrapped into [0, n), m = 0..4 (n >= 2)
+__device__ __forceinline__ int wrap(int j, int m, int n) {
+    int k = j + m - 2;
+    k = k < 0 ? k + n : k;
+    return k >= n ? k - n : k;
+}
+
+struct GlobalSink {
+    float *j[3];
+    int col[5], row[5];
+    __device__ __forceinline__ void add(int c, int l, int m, double v) {
+        if (v != 0.0) unsafeAtomicAdd(j[c] + row[l] + col[m], (float)v);
+    }
+};
+
+// v scaled to a 64-bit fixed-point integer (|v| scale <= 2^33), rounded to nearest
+__device__ __forceinline__ unsigned long long fixed64(double v, double scale) {
+    const double x = rint(v * scale);
+    const double hi = floor(x * 2.3283064365386963e-10);            // x / 2^32
+    const unsigned lo = (unsigned)(x - hi * 4294967296.0);          // in [0, 2^32)
+    return ((unsigned long long)(unsigned)(int)hi << 32) | lo;
+}
+
+struct LdsSink {
+    unsigned long long *acc;   // [3][W * W], W = T + 4
+    int W, base;               // base: LDS index of window slot (0, 0)
+    double sc[3];              // fixed-point scale per component
+    __device__ __forceinline__ void add(int c, int l, int m, double v) {
+        if (v != 0.0) atomicAdd(acc + c * W * W + base + l * W + m, fixed64(v, sc[c]));
+    }
+};
+
+// direct path: one thread per particle, global atomics
+__global__ __launch_bounds__(DBLOCK) void k_deposit(DepositArgs a) {
+    const int64_t i = (int64_t)blockIdx.x * DBLOCK + threadIdx.x;
+    if (i >= dep_count(a)) return;
+    DepRec r;
+    int ic, lc;
+    if (!classify(a, i, r, ic, lc)) {
+        atomicOr(a.status, (uint32_t)QED_ST_DEPOSIT);
+        return;
+    }
+    GlobalSink s{{a.jx, a.jy, a.jz}, {}, {}};
+#pragma unroll
+    for (int m = 0; m < 5; ++m) {
+        s.col[m] = wrap(ic, m, a.nx);
+        s.row[m] = wrap(lc, m, a.ny) * a.nx;
+    }
+    deposit_record(a, r, s);
+}
+
+__device__ __forceinline__ int tile_of(const DepositArgs &a, int ic, int lc) {
+    return (lc / a.T) * a.ntx + ic / a.T;
+}
+
+// 1. particles per tile; largest |w| and |w dz| (non-negative doubles order like their
+// bit patterns)
+__global__ __launch_bounds__(DBLOCK) void k_dep_count(DepositArgs a) {
+    __shared__ int h[DEP_MAX_TILES];
+    __shared__ unsigned long long s_max[2];
+    const int64_t n = dep_count(a), base = (int64_t)blockIdx.x * DEP_PB;
+    if (base >= n) return;
+    for (int k = threadIdx.x; k < a.nt; k += DBLOCK) h[k] = 0;
+    if (threadIdx.x < 2) s_max[threadIdx.x] = 0;
+    __syncthreads();
+    double mw = 0.0, mz = 0.0;
+#pragma unroll
+    for (int j = 0; j < DEP_PT; ++j) {
+        const int64_t i = base + j * DBLOCK + threadIdx.x;
+        if (i >= n) continue;
+        DepRec r;
+        int ic, lc;
+        if (classify(a, i, r, ic, lc)) {
+            atomicAdd(&h[tile_of(a, ic, lc)], 1);
+            mw = fmax(mw, fabs(r.w));
+            mz = fmax(mz, fabs(r.wdz));
+        } else {
+            atomicOr(a.status, (uint32_t)QED_ST_DEPOSIT);
+        }
+    }
+    atomicMax(&s_max[0], (unsigned long long)__double_as_longlong(mw));
+    atomicMax(&s_max[1], (unsigned long long)__double_as_longlong(mz));
+    __syncthreads();
+    for (int k = threadIdx.x; k < a.nt; k += DBLOCK)
+        if (h[k]) atomicAdd(&a.cnt[k], h[k]);
+    if (threadIdx.x < 2 && s_max[threadIdx.x]) atomicMax(&a.amax[threadIdx.x], s_max[threadIdx.x]);
+}
+
+// power-of-two scale that maps |v| <= bound to at most 2^32
+__device__ __forceinline__ double fixed_scale(double bound) {
+    if (!(bound > 0.0)) return 1.0;
+    int e;
+    frexp(bound, &e);          // bound < 2^e
+    return ldexp(1.0, 32 - e);
+}
+
+// 2. tile offsets, chunk work list; clears the counts and the cursors for the next call
+constexpr int SCAN_T = 1024;
+constexpr int SCAN_PER = DEP_MAX_TILES / SCAN_T;
+__global__ __launch_bounds__(SCAN_T) void k_dep_scan(DepositArgs a) {
+    __shared__ int s_cnt[SCAN_T], s_chk[SCAN_T];
+    const int t0 = threadIdx.x * SCAN_PER;
+    int c[SCAN_PER], sc = 0, sk = 0;
+#pragma unroll
+    for (int q = 0; q < SCAN_PER; ++q) {
+        c[q] = t0 + q < a.nt ? a.cnt[t0 + q] : 0;
+        sc += c[q];
+        sk += (c[q] + DEP_CH - 1) / DEP_CH;
+    }
+    s_cnt[threadIdx.x] = sc;
+    s_chk[threadIdx.x] = sk;
+    __syncthreads();
+    for (int d = 1; d < SCAN_T; d <<= 1) {   // inclusive scan (Hillis-Steele)
+        const int vc = threadIdx.x >= d ? s_cnt[threadIdx.x - d] : 0;
+        const int vk = threadIdx.x >= d ? s_chk[threadIdx.x - d] : 0;
+        __syncthreads();
+        s_cnt[threadIdx.x] += vc;
+        s_chk[threadIdx.x] += vk;
+        __syncthreads();
+    }
+    int off = s_cnt[threadIdx.x] - sc, chunk = s_chk[threadIdx.x] - sk;
+#pragma unroll
+    for (int q = 0; q < SCAN_PER; ++q) {
+        const int t = t0 + q;
+        if (t >= a.nt) break;
+        a.off[t] = off;
+        for (int b = 0; b < c[q]; b += DEP_CH) a.work[chunk++] = make_int4(t, off + b, off + min(c[q], b + DEP_CH), 0);
+        off += c[q];
+        a.cnt[t] = 0;
+        a.cur[t] = 0;
+    }
+    if (threadIdx.x == SCAN_T - 1) *a.nwork = s_chk[SCAN_T - 1];
+    if (threadIdx.x == 0) {
+        // bounds of one contribution: running sums of Jx, Jy at most 2 |c w|, Jz at most |c w dz|
+        const double mw = __longlong_as_double((long long)a.amax[0]), mz = __longlong_as_double((long long)a.amax[1]);
+        const double b[3] = {2.0 * fabs(a.cx) * mw, 2.0 * fabs(a.cy) * mw, fabs(a.cz) * mz};
+        for (int c = 0; c < 3; ++c) {
+            const double sc = fixed_scale(b[c]);
+            a.scale[c] = sc;
+            a.scale[3 + c] = 1.0 / sc;
+        }
+        a.amax[0] = 0;
+        a.amax[1] = 0;
+    }
+}
+
+// 3. records sorted by tile
+__global__ __launch_bounds__(DBLOCK) void k_dep_scatter(DepositArgs a) {
+    __shared__ int h[DEP_MAX_TILES];
+    const int64_t n = dep_count(a), base = (int64_t)blockIdx.x * DEP_PB;
+    if (base >= n) return;
+    for (int k = threadIdx.x; k < a.nt; k += DBLOCK) h[k] = 0;
+    __syncthreads();
+    int tile[DEP_PT], rank[DEP_PT];
+#pragma unroll
+    for (int j = 0; j < DEP_PT; ++j) {
+        const int64_t i = base + j * DBLOCK + threadIdx.x;
+        DepRec r;
+        int ic, lc;
+        tile[j] = -1;
+        if (i < n && classify(a, i, r, ic, lc)) {
+            tile[j] = tile_of(a, ic, lc);
+            rank[j] = atomicAdd(&h[tile[j]], 1);
+        }
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < a.nt; k += DBLOCK)
+        if (h[k]) h[k] = a.off[k] + atomicAdd(&a.cur[k], h[k]);
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < DEP_PT; ++j) {
+        if (tile[j] < 0) continue;
+        const int64_t i = base + j * DBLOCK + threadIdx.x;
+        DepRec r;
+        int ic, lc;
+        classify(a, i, r, ic, lc);
+        r.code |= (ic % a.T) | (lc % a.T) << 8;
+        a.rec[h[tile[j]] + rank[j]] = r;
+    }
+}
+
+// 4. one block per chunk of a tile: LDS window of the tile, flushed with global atomics
+// (16 wavefronts per block: a chunk's records are spread over a whole compute unit)
+constexpr int TBLOCK = 1024;
+__global__ __launch_bounds__(TBLOCK) void k_dep_tiles(DepositArgs a) {
+    extern __shared__ unsigned long long acc[];
+    if ((int)blockIdx.x >= *a.nwork) return;
+    const int4 wk = a.work[blockIdx.x];
+    const int W = a.T + 4, WW = W * W;
+    for (int k = threadIdx.x; k < 3 * WW; k += TBLOCK) acc[k] = 0;
+    __syncthreads();
+    const double s0 = a.scale[0], s1 = a.scale[1], s2 = a.scale[2];
+    for (int k = wk.y + threadIdx.x; k < wk.z; k += TBLOCK) {
+        const DepRec r = a.rec[k];
+        LdsSink s{acc, W, ((r.code >> 8) & 255) * W + (r.code & 255), {s0, s1, s2}};
+        deposit_record(a, r, s);
+    }
+    __syncthreads();
+    const int tx0 = (wk.x % a.ntx) * a.T - 2, ty0 = (wk.x / a.ntx) * a.T - 2;
+    const int64_t nodes = (int64_t)a.nx * a.ny;
+    for (int k = threadIdx.x; k < 3 * WW; k += TBLOCK) {
+        const unsigned long long v = acc[k];
+        if (v == 0) continue;
+        const int c = k / WW, rem = k - c * WW, l = rem / W, m = rem - l * W;
+        int gx = (tx0 + m) % a.nx, gy = (ty0 + l) % a.ny;
+        gx = gx < 0 ? gx + a.nx : gx;
+        gy = gy < 0 ? gy + a.ny : gy;
+        atomicAdd(a.acc + c * nodes + (int64_t)gy * a.nx + gx, v);
+    }
+}
+
+// 5. J += fixed-point grid / scale, which is cleared
+__global__ __launch_bounds__(DBLOCK) void k_dep_convert(DepositArgs a) {
+    const int64_t nodes = (int64_t)a.nx * a.ny, stride = (int64_t)gridDim.x * DBLOCK;
+    const double inv[3] = {a.scale[3], a.scale[4], a.scale[5]};
+    for (int64_t k = (int64_t)blockIdx.x * DBLOCK + threadIdx.x; k < 3 * nodes; k += stride) {
+        const unsigned long long v = a.acc[k];
+        if (v == 0) continue;
+        const int c = (int)(k / nodes);
+        const int64_t o = k - c * nodes;
+        float *J = c == 0 ? a.jx : (c == 1 ? a.jy : a.jz);
+        J[o] += (float)((double)(long long)v * inv[c]);
+        a.acc[k] = 0;
+    }
+}
+
+// positions [0, count) and the count, for the deposit after the next step
+__global__ __launch_bounds__(DBLOCK) void k_save_start(const double *x, const double *y, const double *z,
+                                                       const int64_t *count, int64_t capacity, double *x0, double *y0,
+                                                       double *z0, int64_t *n0) {
+    int64_t n = *count;
+    n = n < 0 ? 0 : (n > capacity ? capacity : n);
+    const int64_t stride = (int64_t)gridDim.x * DBLOCK;
+    for (int64_t i = (int64_t)blockIdx.x * DBLOCK + threadIdx.x; i < n; i += stride) {
+        x0[i] = x[i];
+        y0[i] = y[i];
+        z0[i] = z[i];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) *n0 = n;
+}
+
+// tile counters, offsets, cursors [3][DEP_MAX_TILES + 1] ints, then 2 maxima (uint64) and
+// 6 scale factors (double)
+constexpr size_t DEP_CNT_BYTES = 3 * (DEP_MAX_TILES + 1) * sizeof(int) + 8 * sizeof(double) + 8;
+
+hipError_t ensure_deposit(qed_ctx *ctx, int64_t capacity, int64_t nodes) {
+    hipError_t e = hipSuccess;
+    if (!ctx->dep_cnt) {
+        e = hipMalloc(&ctx->dep_cnt, DEP_CNT_BYTES);
+        if (e != hipSuccess) return e;
+        e = hipMemset(ctx->dep_cnt, 0, DEP_CNT_BYTES);
+        if (e != hipSuccess) return e;
+    }
+    if (3 * nodes > ctx->dep_acc_len) {
+        (void)hipFree(ctx->dep_acc);
+        ctx->dep_acc = nullptr;
+        ctx->dep_acc_len = 0;
+        if ((e = hipMalloc(&ctx->dep_acc, 3 * nodes * sizeof(unsigned long long))) != hipSuccess) return e;
+        if ((e = hipMemset(ctx->dep_acc, 0, 3 * nodes * sizeof(unsigned long long))) != hipSuccess) return e;
+        ctx->dep_acc_len = 3 * nodes;
+    }
+    if (capacity > ctx->dep_cap) {
+        (void)hipFree(ctx->dep_rec);
+        (void)hipFree(ctx->dep_work);
+        ctx->dep_rec = nullptr;
+        ctx->dep_work = nullptr;
+        ctx->dep_cap = 0;
+        const int64_t nwork = capacity / DEP_CH + DEP_MAX_TILES + 1;
+        if ((e = hipMalloc(&ctx->dep_rec, capacity * sizeof(DepRec))) != hipSuccess) return e;
+        if ((e = hipMalloc(&ctx->dep_work, nwork * sizeof(int4))) != hipSuccess) return e;
+        ctx->dep_cap = capacity;
+    }
+    return e;
+}
+
+}  // namespace
+
+hipError_t launch_save_start(qed_ctx *ctx, const qed_leptons &L, double *const x0[3], int64_t *n0, hipStream_t s) {
+    int64_t b = (L.capacity + DBLOCK - 1) / DBLOCK;
+    const int64_t cap = 8LL * ctx->num_cu;   // grid-stride: a few blocks per compute unit
+    b = b < 1 ? 1 : (b > cap ? cap : b);
+    hipLaunchKernelGGL(k_save_start, dim3((unsigned)b), dim3(DBLOCK), 0, s, L.x, L.y, L.z, L.count, L.capacity,
+                       x0[0], x0[1], x0[2], n0);
+    return hipGetLastError();
+}
+
+hipError_t launch_deposit(qed_ctx *ctx, const qed_leptons &L, const double *const x0[3], const int64_t *n0,
+                          float *const J[3], int nx, int ny, double dx, double dy, double gx0, double gy0, double dt,
+                          double qscale, hipStream_t s) {
+    DepositArgs a{};
+    a.x = L.x;
+    a.y = L.y;
+    a.z = L.z;
+    a.w = L.w;
+    a.x0 = x0[0];
+    a.y0 = x0[1];
+    a.z0 = x0[2];
+    a.n0 = n0;
+    a.capacity = L.capacity;
+    a.jx = J[0];
+    a.jy = J[1];
+    a.jz = J[2];
+    a.nx = nx;
+    a.ny = ny;
+    a.gx0 = gx0;
+    a.gy0 = gy0;
+    a.inv_dx = 1.0 / dx;
+    a.inv_dy = 1.0 / dy;
+    const double Q = L.charge * qscale;
+    a.cx = -Q / (dy * dt);
+    a.cy = -Q / (dx * dt);
+    a.cz = Q / (dx * dy * dt);
+    a.status = ctx->status;
+    if (L.capacity == 0) return hipGetLastError();
+    for (int T = 16; T <= 32; T *= 2) {
+        const int64_t ntx = (nx + T - 1) / T, nty = (ny + T - 1) / T;
+        if (ntx * nty <= DEP_MAX_TILES) {
+            a.T = T;
+            a.ntx = (int)ntx;
+            a.nt = (int)(ntx * nty);
+            break;
+        }
+    }
+    if (a.T == 0) {
+        const dim3 gd((unsigned)((L.capacity + DBLOCK - 1) / DBLOCK)), bd(DBLOCK);
+        hipLaunchKernelGGL(k_deposit, gd, bd, 0, s, a);
+        return hipGetLastError();
+    }
+    const int64_t nodes = (int64_t)nx * ny;
+    const hipError_t e = ensure_deposit(ctx, L.capacity, nodes);
+    if (e != hipSuccess) return e;
+    a.cnt = ctx->dep_cnt;
+    a.off = ctx->dep_cnt + (DEP_MAX_TILES + 1);
+    a.cur = ctx->dep_cnt + 2 * (DEP_MAX_TILES + 1);
+    a.nwork = a.off + DEP_MAX_TILES;
+    char *tail = (char *)(ctx->dep_cnt + 3 * (DEP_MAX_TILES + 1));
+    tail += (8 - (uintptr_t)tail % 8) % 8;
+    a.amax = (unsigned long long *)tail;
+    a.scale = (double *)(tail + 2 * sizeof(unsigned long long));
+    a.acc = (unsigned long long *)ctx->dep_acc;
+    a.work = (int4 *)ctx->dep_work;
+    a.rec = (DepRec *)ctx->dep_rec;
+    const unsigned pblocks = (unsigned)((L.capacity + DEP_PB - 1) / DEP_PB);
+    const unsigned wblocks = (unsigned)(L.capacity / DEP_CH + DEP_MAX_TILES + 1);
+    const size_t lds = 3 * (size_t)(a.T + 4) * (a.T + 4) * sizeof(unsigned long long);
+    hipLaunchKernelGGL(k_dep_count, dim3(pblocks), dim3(DBLOCK), 0, s, a);
+    hipLaunchKernelGGL(k_dep_scan, dim3(1), dim3(SCAN_T), 0, s, a);
+    hipLaunchKernelGGL(k_dep_scatter, dim3(pblocks), dim3(DBLOCK), 0, s, a);
+    hipLaunchKernelGGL(k_dep_tiles, dim3(wblocks), dim3(TBLOCK), lds, s, a);
+    int64_t cb = (3 * nodes + DBLOCK - 1) / DBLOCK;
+    cb = cb > 8LL * ctx->num_cu ? 8LL * ctx->num_cu : cb;
+    hipLaunchKernelGGL(k_dep_convert, dim3((unsigned)cb), dim3(DBLOCK), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace qed

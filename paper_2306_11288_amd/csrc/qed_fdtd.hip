@@ -1,9 +1,9 @@
-// 2D vacuum field solver on the Yee grid of the GRID2D field (Sec. II.B, z squeezed, no
-// current), periodic in x and y.  Array index [j][i] holds Ex (i+1/2, j), Ey (i, j+1/2),
-// Ez (i, j), Bx (i, j+1/2), By (i+1/2, j), Bz (i+1/2, j+1/2).  One step of dt (leapfrog of
-// Sec. II.F with B split in two half steps, so that E and B are both known at integer
-// times for the gather):
-//   B -= dt/2 curl E;   E += dt curl B;   B -= dt/2 curl E.
+// 2D field solver on the Yee grid of the GRID2D field (Sec. II.B, z squeezed), periodic in
+// x and y.  Array index [j][i] holds Ex (i+1/2, j), Ey (i, j+1/2), Ez (i, j), Bx (i, j+1/2),
+// By (i+1/2, j), Bz (i+1/2, j+1/2); an optional current J has the staggering of E.  One
+// step of dt (leapfrog of Sec. II.F with B split in two half steps, so that E and B are both
+// known at integer times for the gather):
+//   B -= dt/2 curl E;   E += dt (curl B - J);   B -= dt/2 curl E.
 // One thread per node, FP32 like the grid; the stencil neighbours of a row come through
 // the caches (every array is read by the neighbouring rows' threads too).
 #include "qed_internal.hpp"
@@ -13,8 +13,10 @@ namespace {
 
 struct YeeArgs {
     float *g[6];
+    const float *j[3];     // current (E kernel with CUR only)
     int32_t nx, ny, nxb;   // nxb: blocks per row
     float cx, cy;          // h/dx, h/dy with h the (half) step of this kernel
+    float h;               // the step of this kernel
 };
 
 // B -= h curl E:  Bx -= h dEz/dy,  By += h dEz/dx,  Bz -= h (dEy/dx - dEx/dy)   (forward differences)
@@ -31,7 +33,9 @@ __global__ __launch_bounds__(256) void k_yee_b(YeeArgs a) {
     Bz[o] -= a.cx * (Ey[oi] - Ey[o]) - a.cy * (Ex[oj] - Ex[o]);
 }
 
-// E += h curl B:  Ex += h dBz/dy,  Ey -= h dBz/dx,  Ez += h (dBy/dx - dBx/dy)   (backward differences)
+// E += h (curl B - J):  Ex += h (dBz/dy - Jx),  Ey -= h (dBz/dx + Jy),
+//                       Ez += h (dBy/dx - dBx/dy - Jz)   (backward differences)
+template <bool CUR>
 __global__ __launch_bounds__(256) void k_yee_e(YeeArgs a) {
     const int j = blockIdx.x / a.nxb, i = (blockIdx.x % a.nxb) * 256 + threadIdx.x;
     if (i >= a.nx) return;
@@ -43,14 +47,22 @@ __global__ __launch_bounds__(256) void k_yee_e(YeeArgs a) {
     Ex[o] += a.cy * (bz - Bz[oj]);
     Ey[o] -= a.cx * (bz - Bz[oi]);
     Ez[o] += a.cx * (By[o] - By[oi]) - a.cy * (Bx[o] - Bx[oj]);
+    if (CUR) {
+        Ex[o] -= a.h * a.j[0][o];
+        Ey[o] -= a.h * a.j[1][o];
+        Ez[o] -= a.h * a.j[2][o];
+    }
 }
 
 }  // namespace
 
-hipError_t launch_yee(float *const g[6], int nx, int ny, double dx, double dy, double dt, int64_t steps,
-                      hipStream_t s) {
+hipError_t launch_yee(float *const g[6], const float *const J[3], int nx, int ny, double dx, double dy, double dt,
+                      int64_t steps, hipStream_t s) {
     YeeArgs hb{}, fe{};
     for (int c = 0; c < 6; ++c) hb.g[c] = fe.g[c] = g[c];
+    if (J)
+        for (int c = 0; c < 3; ++c) fe.j[c] = J[c];
+    fe.h = (float)dt;
     hb.nx = fe.nx = nx;
     hb.ny = fe.ny = ny;
     hb.nxb = fe.nxb = (nx + 255) / 256;
@@ -61,7 +73,8 @@ hipError_t launch_yee(float *const g[6], int nx, int ny, double dx, double dy, d
     const dim3 gd((unsigned)(((nx + 255) / 256) * (int64_t)ny)), bd(256);   // one block per 256 nodes of a row
     for (int64_t n = 0; n < steps; ++n) {
         hipLaunchKernelGGL(k_yee_b, gd, bd, 0, s, hb);
-        hipLaunchKernelGGL(k_yee_e, gd, bd, 0, s, fe);
+        if (J) hipLaunchKernelGGL(k_yee_e<true>, gd, bd, 0, s, fe);
+        else hipLaunchKernelGGL(k_yee_e<false>, gd, bd, 0, s, fe);
         hipLaunchKernelGGL(k_yee_b, gd, bd, 0, s, hb);
     }
     return hipGetLastError();

@@ -184,6 +184,12 @@ struct qed_ctx {
     float *ev_in, *ev_out;             // learned sampler: per-event network inputs [ev_cap][4], outputs [ev_cap][3]
     double *hist_rep;                  // detector histogram replicas
     int64_t hist_rep_len;
+    int *dep_cnt;                      // current deposition: tile counts, offsets, cursors (zero between calls)
+    void *dep_work;                    // chunk work list
+    void *dep_rec;                     // particle records sorted by tile
+    int64_t dep_cap;                   // particles the records can hold
+    void *dep_acc;                     // 64-bit fixed-point current grid (zero between calls)
+    int64_t dep_acc_len;
     int64_t ev_cap;
     char err[256];
 };
@@ -202,9 +208,15 @@ hipError_t launch_compact(qed_ctx *ctx, const qed_photons &in, const qed_photons
 hipError_t launch_advance_step(int64_t *step, int64_t by, hipStream_t s);
 hipError_t launch_radiative(qed_ctx *ctx, const SegArgs &sa, const qed_leptons &L, uint32_t mode, int64_t step,
                             hipStream_t s);
-// 2D vacuum Yee solver (qed_fdtd.hip): steps of dt, periodic
-hipError_t launch_yee(float *const g[6], int nx, int ny, double dx, double dy, double dt, int64_t steps,
-                      hipStream_t s);
+// 2D Yee solver (qed_fdtd.hip): steps of dt, periodic, optional current J (NULL: vacuum)
+hipError_t launch_yee(float *const g[6], const float *const J[3], int nx, int ny, double dx, double dy, double dt,
+                      int64_t steps, hipStream_t s);
+// positions and count of a lepton list at the start of a step (qed_deposit.hip)
+hipError_t launch_save_start(qed_ctx *ctx, const qed_leptons &L, double *const x0[3], int64_t *n0, hipStream_t s);
+// current deposition (qed_deposit.hip): leptons [0, *n0) from x0 to their current position
+hipError_t launch_deposit(qed_ctx *ctx, const qed_leptons &L, const double *const x0[3], const int64_t *n0,
+                          float *const J[3], int nx, int ny, double dx, double dy, double gx0, double gy0, double dt,
+                          double qscale, hipStream_t s);
 // detector histograms (qed_detector.hip)
 hipError_t launch_hist(qed_ctx *ctx, const HistArgs &a, bool photons, int64_t capacity, hipStream_t s);
 // learned sampler (qed_mlp.hip)
