@@ -387,6 +387,17 @@ def field_eval(spec: dict, t, r):
     return E, B
 
 
+def field_eval_points(spec: dict, t, pts):
+    """E, B ([n][3] each) of the field at the points pts ([n][3]) at time t."""
+    f = make_field(spec)
+    pts = np.ascontiguousarray(np.asarray(pts, dtype=np.float64).reshape(-1, 3))
+    E, B = np.zeros_like(pts), np.zeros_like(pts)
+    ev = lib().orc_field_eval
+    for k in range(len(pts)):
+        ev(C.byref(f), float(t), _p(pts[k]), _p(E[k]), _p(B[k]))
+    return E, B
+
+
 @dataclass
 class LeptonArrays:
     x: np.ndarray

@@ -11,6 +11,17 @@ half steps so that E and B are both known at integer times):
 with J = (Jx, Jy, Jz) at the staggering of E and the half-integer time of the step (zero
 when no current is given).
 The differences are written out with numpy's roll (periodic wrap).
+
+Open x boundaries (first-order absorbing condition of Mur, with an incoming pulse injected
+through x_max): the E update runs as above, then the tangential components Ey, Ez on the
+first and last node columns are replaced by the one-way wave condition of the outgoing
+(scattered) field, (d/dt - d/dx) E = 0 at x_min and (d/dt + d/dx)(E - E_inc) = 0 at x_max,
+discretised between the boundary node and its neighbour over the step:
+  E_0^{n+1} = E_1^n + k (E_1^{n+1} - E_0^n),   k = (dt - dx)/(dt + dx),
+and at x_max the same for E - E_inc with E_inc the analytic incoming field at each node's
+staggered position and time.  The second B half step then sees the corrected E; the
+values the periodic wrap leaves in the cells beyond the boundaries never reach the
+interior.  y stays periodic.
 """
 from __future__ import annotations
 
@@ -61,14 +72,55 @@ def e_full(F, dx, dy, dt, J=None):
         F[EZ] = F[EZ] - dt * J[2]
 
 
-def advance(F, dx: float, dy: float, dt: float, steps: int = 1, J=None):
+def _incoming(spec, t, x, ys):
+    """E of the analytic pulse `spec` at the points (x, y, 0), y in ys, time t: [len(ys)][3]."""
+    import oracle                                  # the C oracle's field evaluation
+    pts = np.stack([np.full(len(ys), x), np.asarray(ys, float), np.zeros(len(ys))], axis=1)
+    return oracle.field_eval_points(spec, t, pts)[0]
+
+
+def _mur(F, old, dx, dy, dt, bc, t0, t1):
+    """Replace Ey, Ez on the first and last node columns (first-order Mur condition; the
+    incoming pulse bc['incoming'] enters through x_max)."""
+    k = (dt - dx) / (dt + dx)
+    ny, nx = F[EY].shape
+    for c in (EY, EZ):
+        L0, L1, R0, R1 = old[c]
+        F[c][:, 0] = L1 + k * (F[c][:, 1] - L0)
+        inc = bc.get("incoming")
+        if inc is None:
+            F[c][:, nx - 1] = R1 + k * (F[c][:, nx - 2] - R0)
+            continue
+        half = 0.5 if c == EY else 0.0              # Ey at (i, j+1/2), Ez at (i, j)
+        ys = bc["gy0"] + (np.arange(ny) + half) * dy
+        xN, xM = bc["gx0"] + (nx - 1) * dx, bc["gx0"] + (nx - 2) * dx
+        comp = 1 if c == EY else 2
+        IN0, IN1 = _incoming(inc, t0, xN, ys)[:, comp], _incoming(inc, t1, xN, ys)[:, comp]
+        IM0, IM1 = _incoming(inc, t0, xM, ys)[:, comp], _incoming(inc, t1, xM, ys)[:, comp]
+        F[c][:, nx - 1] = IN1 + (R1 - IM0) + k * ((F[c][:, nx - 2] - IM1) - (R0 - IN0))
+
+
+def advance(F, dx: float, dy: float, dt: float, steps: int = 1, J=None, bc=None):
     """Advance the six FP64 arrays F[0..5] (each [ny][nx]) by `steps` steps in place, with
-    the current J (three [ny][nx] arrays, held fixed over the steps) if given."""
-    for _ in range(steps):
+    the current J (three [ny][nx] arrays, held fixed over the steps) if given.  bc = None
+    (periodic) or a dict {'open_x': True, 'incoming': pulse spec or None, 'gx0', 'gy0',
+    't0'} for open x boundaries; t0 is the time of F on entry."""
+    open_x = bc is not None and bc.get("open_x")
+    for n in range(steps):
+        if open_x:
+            old = {c: (F[c][:, 0].copy(), F[c][:, 1].copy(), F[c][:, -1].copy(), F[c][:, -2].copy())
+                   for c in (EY, EZ)}
         b_half(F, dx, dy, 0.5 * dt)
         e_full(F, dx, dy, dt, J)
+        if open_x:
+            _mur(F, old, dx, dy, dt, bc, bc["t0"] + n * dt, bc["t0"] + (n + 1) * dt)
         b_half(F, dx, dy, 0.5 * dt)
     return F
+
+
+def energy(F, dx, dy):
+    """Field energy (1/2) sum (E^2 + B^2) dx dy over the grid (normalised units)."""
+    return 0.5 * sum(float((f * f).sum()) for f in F) * dx * dy
 
 
 def div_b(F, dx, dy):
