@@ -327,9 +327,9 @@ def run_cascade(args, torch, Q, W):
     linearly polarised a0 = 300 pulse filled at t = 0): 1e6 electrons at gamma 4000 emit
     photons (NCS + Stokes), photons rotate their Stokes basis, evolve by vacuum
     birefringence and create pairs (NBW); electrons, positrons and photons all stepped, the
-    leptons' current deposited and the field advanced by the Yee solver every step (the
-    PIC loop; --no-deposit: vacuum solver, --static-grid: the snapshot at t = 0).  A
-    warm-up builds the photon population, then the timed steps."""
+    leptons' current deposited and the field advanced by the Yee solver (open x boundaries)
+    every step (the PIC loop; --no-deposit: vacuum solver, --static-grid: the snapshot at
+    t = 0).  A warm-up builds the photon population, then the timed steps."""
     cfg = W.c3()
     grid, pulse = cfg["grid"], dict(cfg["pulse"])
     pulse["phi_start"] = -pulse["ncycles"] * math.pi          # pulse centre at x = 0 for t = 0
@@ -370,7 +370,9 @@ def run_cascade(args, torch, Q, W):
             ctx.deposit_current(ep, start["ep"], grid, J, CASCADE_QSCALE)
         if ev: ev[3].record()
         if solver:
-            ctx.field_advance(spec, cfg["dt"], 1, current=J if deposit else None)
+            ctx.field_advance(spec, cfg["dt"], 1, current=J if deposit else None,
+                              bc={"open_x": 1, "incoming": None, "gx0": grid["gx0"], "gy0": grid["gy0"],
+                                  "t0": s * cfg["dt"]})
         if ev: ev[4].record()
 
     for s in range(warm):
@@ -397,9 +399,9 @@ def run_cascade(args, torch, Q, W):
     fgbs = nodes * BYTES_YEE_NODE / (t_f / steps * 1e-3) / 1e9 if solver and t_f > 0 else None
     lep_mean = sum((counts0[k] + counts1[k]) / 2 for k in (0, 1))
     dgbs = lep_mean * BYTES_DEPOSIT / (t_d / steps * 1e-3) / 1e9 if deposit and t_d > 0 else None
-    field = ({"solver": ("2D Yee, periodic, with the current the leptons deposit each step (charge-conserving, "
-                         f"qscale {CASCADE_QSCALE})" if deposit else
-                         "2D vacuum Yee, periodic (the pulse filled at t = 0 and propagated on the grid)"),
+    field = ({"solver": ("2D Yee, open x (Mur) / periodic y, with the current the leptons deposit each step "
+                         f"(charge-conserving, qscale {CASCADE_QSCALE})" if deposit else
+                         "2D vacuum Yee, open x (Mur) / periodic y (the pulse filled at t = 0 and propagated)"),
               "ms_per_step": t_f / steps,
               "deposit": ({"ms_per_step": t_d / steps, "leptons": lep_mean,
                            "leptons_per_s": lep_mean / (t_d / steps * 1e-3),

@@ -196,16 +196,33 @@ qed_status qed_step_photons(qed_ctx_t *ctx, const qed_segment *segs, int nseg, q
 qed_status qed_compact_photons(qed_ctx_t *ctx, const qed_photons *in, qed_photons *out,
                                hipStream_t stream);
 
+/* Boundaries of qed_field_advance.  open_x = 0: periodic in x.  open_x = 1: the first and
+ * last node columns carry the first-order absorbing condition of Mur on Ey, Ez (one-way
+ * wave equation of the outgoing field, discretised over the step between the boundary
+ * node and its neighbour), and the pulse `incoming` (QED_FIELD_NONE, PW or GAUSS, a wave
+ * along -x as in qed_field) enters through x_max: the condition there applies to E minus
+ * the pulse, evaluated in FP64 at each node's staggered position.  (gx0, gy0): position of
+ * node (0, 0); t0: time of the grid on entry.  y stays periodic.  The paper names boundary
+ * and laser settings without an algorithm; this is the standard absorbing condition.    */
+typedef struct {
+    int32_t open_x, pad;
+    qed_field incoming;
+    double gx0, gy0, t0;
+} qed_field_bc;
+
 /* 2D field solver (Sec. II.B curl equations with z squeezed; leapfrog of Sec. II.F):
  * advances the six FP32 arrays of a GRID2D field ([ny][nx], the staggering of qed_field) in
  * place by `steps` steps of dt, each  B -= dt/2 curl E;  E += dt (curl B - J);
  * B -= dt/2 curl E  (E and B both at integer times for the gather), with periodic wrap in
- * x and y.  `current` is NULL (vacuum) or three FP32 arrays Jx, Jy, Jz [ny][nx] at the
- * staggering of Ex, Ey, Ez (as qed_deposit_current writes them), held fixed over the
- * steps.  dt must satisfy the Courant limit dt < 1/sqrt(1/dx^2 + 1/dy^2) (QED_EARG
- * otherwise); nx, ny >= 2.  Asynchronous on `stream`; 3 launches per step.             */
-qed_status qed_field_advance(qed_ctx_t *ctx, float *const grid[6], const float *const current[3], int32_t nx,
-                             int32_t ny, double dx, double dy, double dt, int64_t steps, hipStream_t stream);
+ * y and, for bc NULL or bc->open_x = 0, in x.  `current` is NULL (vacuum) or three FP32
+ * arrays Jx, Jy, Jz [ny][nx] at the staggering of Ex, Ey, Ez (as qed_deposit_current
+ * writes them), held fixed over the steps.  dt must satisfy the Courant limit
+ * dt < 1/sqrt(1/dx^2 + 1/dy^2) (QED_EARG otherwise); nx, ny >= 2 (nx >= 4 with open x).
+ * Asynchronous on `stream`; 3 launches per step (5 with open x; the first open call
+ * allocates 8 ny floats of context-owned memory).                                       */
+qed_status qed_field_advance(qed_ctx_t *ctx, float *const grid[6], const float *const current[3],
+                             const qed_field_bc *bc, int32_t nx, int32_t ny, double dx, double dy, double dt,
+                             int64_t steps, hipStream_t stream);
 
 /* Charge-conserving current deposition (Sec. II.C, Esirkepov's decomposition with the TSC
  * shapes of Sec. II.E): leptons [0, *n0) that moved from (x0[0], x0[1], x0[2]) (device FP64

@@ -21,7 +21,8 @@ discretised between the boundary node and its neighbour over the step:
 and at x_max the same for E - E_inc with E_inc the analytic incoming field at each node's
 staggered position and time.  The second B half step then sees the corrected E; the
 values the periodic wrap leaves in the cells beyond the boundaries never reach the
-interior.  y stays periodic.
+interior; the components half a cell beyond x_max (Ex, By, Bz of the last column) lie
+outside the box and are kept at zero.  y stays periodic.
 """
 from __future__ import annotations
 
@@ -115,6 +116,9 @@ def advance(F, dx: float, dy: float, dt: float, steps: int = 1, J=None, bc=None)
         if open_x:
             _mur(F, old, dx, dy, dt, bc, bc["t0"] + n * dt, bc["t0"] + (n + 1) * dt)
         b_half(F, dx, dy, 0.5 * dt)
+        if open_x:
+            for c in (EX, BY, BZ):
+                F[c][:, -1] = 0.0
     return F
 
 

@@ -81,6 +81,11 @@ def hist_spec(axes, n, lo, hi, pol_ref=(0.0, 1.0, 0.0)) -> HistSpec:
     return h
 
 
+class FieldBC(C.Structure):
+    _fields_ = [("open_x", C.c_int32), ("pad", C.c_int32), ("incoming", Field), ("gx0", C.c_double),
+                ("gy0", C.c_double), ("t0", C.c_double)]
+
+
 class Tuning(C.Structure):
     _fields_ = [("blocks_per_cu", C.c_int32), ("rate_lds", C.c_int32), ("ev_group", C.c_int32)]
 
@@ -117,7 +122,8 @@ def lib():
             "qed_push_spin": [vp, vp, C.c_int, vp, vp, i64, vp],
             "qed_push_radiative": [vp, vp, C.c_int, vp, C.c_uint32, i64, vp],
             "qed_hist_photons": [vp, vp, i64, vp, vp, vp],
-            "qed_field_advance": [vp, vp, vp, C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_double, i64, vp],
+            "qed_field_advance": [vp, vp, vp, vp, C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_double, i64,
+                                  vp],
             "qed_deposit_current": [vp, vp, vp, vp, vp, C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_double,
                                     C.c_double, C.c_double, C.c_double, vp],
             "qed_save_start": [vp, vp, vp, vp, vp],
@@ -360,15 +366,24 @@ class Context:
         self._check(lib().qed_push_radiative(self.h, arr, n, C.byref(L.c()), int(mode), step, _stream(stream)),
                     "qed_push_radiative")
 
-    def field_advance(self, grid: dict, dt: float, steps: int = 1, current=None, stream=None):
+    def field_advance(self, grid: dict, dt: float, steps: int = 1, current=None, bc=None, stream=None):
         """Advance a GRID2D field (dict with 'grid' = six float32 device tensors [ny][nx],
         'nx', 'ny', 'dx', 'dy') in place by `steps` steps of the Yee solver, with the current
-        `current` (three float32 device tensors [ny][nx]: Jx, Jy, Jz) if given."""
+        `current` (three float32 device tensors [ny][nx]: Jx, Jy, Jz) if given.  bc: None
+        (periodic) or a dict {'open_x': 1, 'incoming': pulse spec or None, 'gx0', 'gy0',
+        't0'} for open x boundaries with a pulse entering through x_max."""
         arr = (C.c_void_p * 6)(*[g.data_ptr() for g in grid["grid"]])
         cur = None if current is None else (C.c_void_p * 3)(*[j.data_ptr() for j in current])
-        self._check(lib().qed_field_advance(self.h, arr, cur, int(grid["nx"]), int(grid["ny"]), float(grid["dx"]),
-                                            float(grid["dy"]), float(dt), int(steps), _stream(stream)),
-                    "qed_field_advance")
+        b = None
+        if bc is not None:
+            b = FieldBC()
+            b.open_x = int(bc.get("open_x", 1))
+            if bc.get("incoming") is not None:
+                b.incoming = make_field(bc["incoming"])
+            b.gx0, b.gy0, b.t0 = float(bc.get("gx0", 0.0)), float(bc.get("gy0", 0.0)), float(bc.get("t0", 0.0))
+        self._check(lib().qed_field_advance(self.h, arr, cur, C.byref(b) if b is not None else None, int(grid["nx"]),
+                                            int(grid["ny"]), float(grid["dx"]), float(grid["dy"]), float(dt),
+                                            int(steps), _stream(stream)), "qed_field_advance")
 
     def save_start(self, L: "Leptons", out=None, stream=None):
         """Positions and count of L at the start of a step, for deposit_current

@@ -209,6 +209,7 @@ void free_ctx(qed_ctx *c) {
     hipFree(c->dep_work);
     hipFree(c->dep_rec);
     hipFree(c->dep_acc);
+    hipFree(c->yee_save);
     hipFree(c->ev_in);
     hipFree(c->ev_out);
     if (c->hsegs) hipHostFree(c->hsegs);
@@ -339,8 +340,9 @@ qed_status qed_push_radiative(qed_ctx_t *ctx, const qed_segment *segs, int nseg,
     return launched(ctx, launch_radiative(ctx, sa, *p, mode, step, s), "qed_push_radiative");
 }
 
-qed_status qed_field_advance(qed_ctx_t *ctx, float *const grid[6], const float *const current[3], int32_t nx,
-                             int32_t ny, double dx, double dy, double dt, int64_t steps, hipStream_t s) {
+qed_status qed_field_advance(qed_ctx_t *ctx, float *const grid[6], const float *const current[3],
+                             const qed_field_bc *bc, int32_t nx, int32_t ny, double dx, double dy, double dt,
+                             int64_t steps, hipStream_t s) {
     qed_status st = ready(ctx);
     if (st != QED_OK) return st;
     if (!grid) return fail(ctx, QED_EARG, "qed_field_advance: NULL grid");
@@ -356,7 +358,25 @@ qed_status qed_field_advance(qed_ctx_t *ctx, float *const grid[6], const float *
         return fail(ctx, QED_EARG, "qed_field_advance: dt beyond the Courant limit");
     if (steps < 0) return fail(ctx, QED_EARG, "qed_field_advance: steps must be >= 0");
     if (steps == 0) return QED_OK;
-    return launched(ctx, launch_yee(grid, current, nx, ny, dx, dy, dt, steps, s), "qed_field_advance");
+    YeeBoundary yb{};
+    if (bc) {
+        if (bc->open_x != 0 && bc->open_x != 1) return fail(ctx, QED_EARG, "qed_field_advance: open_x must be 0 or 1");
+        if (bc->open_x) {
+            if (nx < 4) return fail(ctx, QED_EARG, "qed_field_advance: open x boundaries need nx >= 4");
+            const int k = bc->incoming.kind;
+            if (k != QED_FIELD_NONE && k != QED_FIELD_PW && k != QED_FIELD_GAUSS)
+                return fail(ctx, QED_EARG, "qed_field_advance: the incoming pulse must be NONE, PW or GAUSS");
+            if ((st = check_field(ctx, bc->incoming)) != QED_OK) return st;
+            if (!std::isfinite(bc->gx0) || !std::isfinite(bc->gy0) || !std::isfinite(bc->t0))
+                return fail(ctx, QED_EARG, "qed_field_advance: gx0, gy0, t0 must be finite");
+            yb.inc = field_dev(bc->incoming);
+            yb.gx0 = bc->gx0;
+            yb.gy0 = bc->gy0;
+            yb.t0 = bc->t0;
+        }
+    }
+    const YeeBoundary *ybp = (bc && bc->open_x) ? &yb : nullptr;
+    return launched(ctx, launch_yee(ctx, grid, current, ybp, nx, ny, dx, dy, dt, steps, s), "qed_field_advance");
 }
 
 qed_status qed_save_start(qed_ctx_t *ctx, const qed_leptons *l, double *const x0[3], int64_t *n0, hipStream_t s) {

@@ -190,6 +190,8 @@ struct qed_ctx {
     int64_t dep_cap;                   // particles the records can hold
     void *dep_acc;                     // 64-bit fixed-point current grid (zero between calls)
     int64_t dep_acc_len;
+    float *yee_save;                   // open-boundary columns of the field solver
+    int64_t yee_save_len;
     int64_t ev_cap;
     char err[256];
 };
@@ -208,9 +210,14 @@ hipError_t launch_compact(qed_ctx *ctx, const qed_photons &in, const qed_photons
 hipError_t launch_advance_step(int64_t *step, int64_t by, hipStream_t s);
 hipError_t launch_radiative(qed_ctx *ctx, const SegArgs &sa, const qed_leptons &L, uint32_t mode, int64_t step,
                             hipStream_t s);
-// 2D Yee solver (qed_fdtd.hip): steps of dt, periodic, optional current J (NULL: vacuum)
-hipError_t launch_yee(float *const g[6], const float *const J[3], int nx, int ny, double dx, double dy, double dt,
-                      int64_t steps, hipStream_t s);
+// 2D Yee solver (qed_fdtd.hip): steps of dt, optional current J (NULL: vacuum), periodic
+// or (bc) open in x with an incoming pulse
+struct YeeBoundary {
+    FieldDev inc;          // kind QED_FIELD_NONE: no injection
+    double gx0, gy0, t0;
+};
+hipError_t launch_yee(qed_ctx *ctx, float *const g[6], const float *const J[3], const YeeBoundary *bc, int nx, int ny,
+                      double dx, double dy, double dt, int64_t steps, hipStream_t s);
 // positions and count of a lepton list at the start of a step (qed_deposit.hip)
 hipError_t launch_save_start(qed_ctx *ctx, const qed_leptons &L, double *const x0[3], int64_t *n0, hipStream_t s);
 // current deposition (qed_deposit.hip): leptons [0, *n0) from x0 to their current position
