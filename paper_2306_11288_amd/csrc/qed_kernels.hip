@@ -308,8 +308,9 @@ __global__ __launch_bounds__(BLOCK) void k_leptons_radiative(LeptonArgs a, uint3
     uint32_t st = 0;
     for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK) {
         const uint32_t o = (uint32_t)i * 8u, os = (uint32_t)i * (uint32_t)sizeof(T);
-        V3<double> r = {at(a.L.x, o), at(a.L.y, o), at(a.L.z, o)}, p = {at(a.L.px, o), at(a.L.py, o), at(a.L.pz, o)};
-        V3<T> S = {at((T *)a.L.sx, os), at((T *)a.L.sy, os), at((T *)a.L.sz, os)};
+        V3<double> r = {ld_nt(a.L.x, o), ld_nt(a.L.y, o), ld_nt(a.L.z, o)};
+        V3<double> p = {ld_nt(a.L.px, o), ld_nt(a.L.py, o), ld_nt(a.L.pz, o)};
+        V3<T> S = {ld_nt((T *)a.L.sx, os), ld_nt((T *)a.L.sy, os), ld_nt((T *)a.L.sz, os)};
         V3<double> E, B, pm, pp;
         fields_for<T, FK>(a.sa, i, t, r, E, B);
         const double ign = boris(q, dt, E, B, p, pm, pp);
@@ -551,8 +552,10 @@ __global__ __launch_bounds__(BLOCK) void k_photons_decide(PhotonArgs a) {
         bool ev = false;
         V3<double> E = {0, 0, 0}, B = {0, 0, 0};
         if (j < n && a.G.alive[j]) {
-            const V3<double> x = {a.G.x[j], a.G.y[j], a.G.z[j]}, k = {a.G.kx[j], a.G.ky[j], a.G.kz[j]};
-            V3<T> xi = {xi1[j], xi2[j], xi3[j]}, e1 = {e1x[j], e1y[j], e1z[j]};
+            const uint32_t o = (uint32_t)j * 8u, os = (uint32_t)j * (uint32_t)sizeof(T);
+            const V3<double> x = {ld_nt(a.G.x, o), ld_nt(a.G.y, o), ld_nt(a.G.z, o)};
+            const V3<double> k = {ld_nt(a.G.kx, o), ld_nt(a.G.ky, o), ld_nt(a.G.kz, o)};
+            V3<T> xi = {ld_nt(xi1, os), ld_nt(xi2, os), ld_nt(xi3, os)}, e1 = {ld_nt(e1x, os), ld_nt(e1y, os), ld_nt(e1z, os)};
             field_kind<T, FK>(a.field, t, x.x, x.y, x.z, E, B);
             PhotonFrame f;
             photon_frame(a.c.xi_L, k, E, B, f);
@@ -565,15 +568,15 @@ __global__ __launch_bounds__(BLOCK) void k_photons_decide(PhotonArgs a) {
                 uniform4(a.G.id[j], step, STREAM_NBW, a.c.seed, rr);
                 ev = Ja > (T)0 && rr[1] < P;
             }
-            xi1[j] = xi.x; xi2[j] = xi.y; xi3[j] = xi.z;
-            e1x[j] = e1.x; e1y[j] = e1.y; e1z[j] = e1.z;
+            st_nt(xi1, os, xi.x); st_nt(xi2, os, xi.y); st_nt(xi3, os, xi.z);
+            st_nt(e1x, os, e1.x); st_nt(e1y, os, e1.y); st_nt(e1z, os, e1.z);
             if (ev) {
                 a.G.alive[j] = 0;
             } else if (a.do_move) {
                 const double ie = a.c.dt * f.inv_eps;
-                a.G.x[j] = x.x + ie * k.x;
-                a.G.y[j] = x.y + ie * k.y;
-                a.G.z[j] = x.z + ie * k.z;
+                st_nt(a.G.x, o, x.x + ie * k.x);
+                st_nt(a.G.y, o, x.y + ie * k.y);
+                st_nt(a.G.z, o, x.z + ie * k.z);
             }
         }
         if constexpr (NBW) {
