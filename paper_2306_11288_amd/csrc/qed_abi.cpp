@@ -113,6 +113,9 @@ qed_status seg_args(qed_ctx *ctx, const qed_segment *segs, int nseg, SegArgs &sa
         if (st != QED_OK) return st;
     }
     sa.nseg = nseg;
+    sa.multi_kind = segs[0].field.kind;
+    for (int k = 1; k < nseg; ++k)
+        if (segs[k].field.kind != sa.multi_kind) sa.multi_kind = -1;
     sa.begin0 = segs[0].begin;
     sa.end0 = segs[0].end;
     sa.f0 = field_dev(segs[0].field);

@@ -82,6 +82,7 @@ struct FieldDev {
     ConstDev c;
 };
 constexpr int FK_MULTI = -1;     // kernel template argument: field kind read per segment
+constexpr int FK_MULTI_BASE = 16;  // FK_MULTI_BASE + kind: several segments, all of that kind
 struct DevSegment {
     int64_t begin, end;
     FieldDev f;
@@ -111,6 +112,7 @@ struct LepEvent {
 constexpr int MAX_SEG = 1 << 16;
 struct SegArgs {
     int nseg;
+    int multi_kind;            // nseg > 1: the kind every segment has, or -1 if they differ
     int64_t begin0, end0;
     FieldDev f0;
     const DevSegment *segs;    // device copy when nseg > 1

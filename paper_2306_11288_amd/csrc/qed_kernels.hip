@@ -92,17 +92,37 @@ __device__ __forceinline__ void fields_for(const SegArgs &sa, int64_t i, double 
                                            V3<double> &E, V3<double> &B) {
     E = {0, 0, 0};
     B = {0, 0, 0};
-    if constexpr (FK != FK_MULTI) {
+    if constexpr (FK != FK_MULTI && FK < FK_MULTI_BASE) {
         if (i >= sa.begin0 && i < sa.end0) field_kind<FT, FK>(sa.f0, t, r.x, r.y, r.z, E, B);
     } else {
-        int lo = 0, hi = sa.nseg - 1;   // last segment with begin <= i
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (sa.segs[mid].begin <= i) lo = mid;
-            else hi = mid - 1;
+        // Segments are index ranges and a wavefront holds consecutive indices, so it almost
+        // always lies in one segment.  Waterfall over the segments present: the first lane
+        // still pending picks its segment (a search on wavefront-uniform values, so the
+        // segment descriptor comes through scalar loads and the field kind is uniform), the
+        // lanes inside it evaluate the field; one pass in the usual case.
+        bool done = false;
+        for (;;) {
+            const unsigned long long pending = __ballot(!done);
+            if (pending == 0) break;
+            const int leader = __ffsll((long long)pending) - 1;
+            const int il = __builtin_amdgcn_readlane((int)i, leader);
+            int lo = 0, hi = sa.nseg - 1;   // last segment with begin <= il
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (sa.segs[mid].begin <= il) lo = mid;
+                else hi = mid - 1;
+            }
+            const DevSegment &sg = sa.segs[lo];
+            if (!done) {
+                if (i >= sg.begin && i < sg.end) {
+                    if constexpr (FK == FK_MULTI) field_at<FT>(sg.f, t, r.x, r.y, r.z, E, B);
+                    else field_kind<FT, FK - FK_MULTI_BASE>(sg.f, t, r.x, r.y, r.z, E, B);
+                    done = true;
+                } else if ((int)i == il) {
+                    done = true;   // the leader lies outside every segment: no field
+                }
+            }
         }
-        const DevSegment &sg = sa.segs[lo];
-        if (i >= sg.begin && i < sg.end) field_at<FT>(sg.f, t, r.x, r.y, r.z, E, B);
     }
 }
 
@@ -788,7 +808,13 @@ static hipError_t launch_leptons_t(qed_ctx *ctx, LeptonMode mode, const LeptonAr
         return hipGetLastError();
     }
     if (mode == LM_EMIT) return launch_ncs<T, false, QED_FIELD_NONE>(ctx, a, s);
-    if (M) return launch_ncs<T, true, FK_MULTI>(ctx, a, s);
+    if (M) {   // several segments: specialised on their kind when they share one
+        switch (a.sa.multi_kind) {
+        case QED_FIELD_PW: return launch_ncs<T, true, FK_MULTI_BASE + QED_FIELD_PW>(ctx, a, s);
+        case QED_FIELD_GAUSS: return launch_ncs<T, true, FK_MULTI_BASE + QED_FIELD_GAUSS>(ctx, a, s);
+        default: return launch_ncs<T, true, FK_MULTI>(ctx, a, s);
+        }
+    }
     switch (a.sa.f0.kind) {
     case QED_FIELD_CONST: return launch_ncs<T, true, QED_FIELD_CONST>(ctx, a, s);
     case QED_FIELD_PW: return launch_ncs<T, true, QED_FIELD_PW>(ctx, a, s);
