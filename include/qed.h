@@ -11,8 +11,11 @@
  *   leptons : field gather (Sec. II.D-E) -> Boris push (Sec. II.A, eqs. boris1-boris6)
  *             -> T-BMT spin rotation (Sec. III.B, eqs. bmteqn, bmt-boris1-4) ->
  *             spin/polarisation-resolved nonlinear Compton emission (Sec. III.C.1)
- * in the order of the paper's Spin-QED chain (Sec. IV) without the radiative-correction
- * and bremsstrahlung stages.
+ * in the order of the paper's Spin-QED chain (Sec. IV; bremsstrahlung is not included).
+ * Around it: the radiative-correction push (Sec. III.A-B, qed_push_radiative), the PIC
+ * loop's charge-conserving current deposition and 2D Yee field solver (Sec. II.B-C, F;
+ * qed_save_start, qed_deposit_current, qed_field_advance) and detector histograms
+ * (Sec. III.F; qed_hist_photons, qed_hist_leptons).
  *
  * Conventions
  *  - Units: t in 1/omega, x in 1/k, momenta in m c, energies in m c^2, fields in
