@@ -17,14 +17,15 @@
 // Beams put hundreds of particles on each node, so adding every contribution to HBM with
 // a device-wide atomic serialises on the hot nodes.  The tiled path bins the particles by
 // the tile of T x T nodes that holds their start node and accumulates each tile in LDS:
-//   1. count   : particles per tile (LDS histogram per block, one global add per tile),
-//                largest |w| and |w dz|;
+//   1. count   : particles per tile (LDS histogram per block over its share of the list,
+//                one global add per tile), largest |w| and |w dz|;
 //   2. scan    : tile offsets, a work list of chunks of at most DEP_CH particles, and the
 //                fixed-point scale of each component (a power of two that maps the largest
 //                possible contribution to 2^32);
 //   3. scatter : a 56-byte record per particle (offsets from the nodes, weight, shifts,
-//                node in the tile) at its tile's place (LDS rank + one reservation per
-//                block and tile);
+//                node in the tile) at its tile's place: each block counts its share per
+//                tile, reserves that many slots per tile with one global add, then hands
+//                them out through an LDS cursor;
 //   4. tiles   : one block per chunk adds its records, in 64-bit fixed point, to the
 //                (T+4)^2 LDS window of the tile (two-node halo: LDS integer atomics run at
 //                several times the rate of LDS float atomics here), then adds the non-zero
@@ -41,8 +42,7 @@ namespace qed {
 namespace {
 
 constexpr int DBLOCK = 256;
-constexpr int DEP_PT = 4;                  // particles per thread in the count / scatter blocks
-constexpr int DEP_PB = DEP_PT * DBLOCK;    // particles per count / scatter block
+constexpr int DEP_BPC = 2;                 // blocks per compute unit of the persistent kernels
 constexpr int DEP_MAX_TILES = 8192;        // tiles of the tiled path (LDS histograms of this many ints)
 constexpr int DEP_CH = 4096;               // records per block of the tile kernel
 
@@ -223,20 +223,17 @@ __device__ __forceinline__ int tile_of(const DepositArgs &a, int ic, int lc) {
 }
 
 // 1. particles per tile; largest |w| and |w dz| (non-negative doubles order like their
-// bit patterns)
+// bit patterns).  Persistent: block b takes particles b*DBLOCK + tid + k*gridDim.x*DBLOCK.
 __global__ __launch_bounds__(DBLOCK) void k_dep_count(DepositArgs a) {
     __shared__ int h[DEP_MAX_TILES];
     __shared__ unsigned long long s_max[2];
-    const int64_t n = dep_count(a), base = (int64_t)blockIdx.x * DEP_PB;
-    if (base >= n) return;
+    const int64_t n = dep_count(a), stride = (int64_t)gridDim.x * DBLOCK;
+    if ((int64_t)blockIdx.x * DBLOCK >= n) return;
     for (int k = threadIdx.x; k < a.nt; k += DBLOCK) h[k] = 0;
     if (threadIdx.x < 2) s_max[threadIdx.x] = 0;
     __syncthreads();
     double mw = 0.0, mz = 0.0;
-#pragma unroll
-    for (int j = 0; j < DEP_PT; ++j) {
-        const int64_t i = base + j * DBLOCK + threadIdx.x;
-        if (i >= n) continue;
+    for (int64_t i = (int64_t)blockIdx.x * DBLOCK + threadIdx.x; i < n; i += stride) {
         DepRec r;
         int ic, lc;
         if (classify(a, i, r, ic, lc)) {
@@ -313,68 +310,64 @@ __global__ __launch_bounds__(SCAN_T) void k_dep_scan(DepositArgs a) {
     }
 }
 
-// 3. records sorted by tile
+// 3. records sorted by tile.  Same particles per block as the count kernel: count them
+// per tile, reserve the block's slots of each tile (one global add), then place each
+// record at the next slot of its tile (LDS cursor).
 __global__ __launch_bounds__(DBLOCK) void k_dep_scatter(DepositArgs a) {
     __shared__ int h[DEP_MAX_TILES];
-    const int64_t n = dep_count(a), base = (int64_t)blockIdx.x * DEP_PB;
-    if (base >= n) return;
+    const int64_t n = dep_count(a), stride = (int64_t)gridDim.x * DBLOCK;
+    if ((int64_t)blockIdx.x * DBLOCK >= n) return;
     for (int k = threadIdx.x; k < a.nt; k += DBLOCK) h[k] = 0;
     __syncthreads();
-    int tile[DEP_PT], rank[DEP_PT];
-#pragma unroll
-    for (int j = 0; j < DEP_PT; ++j) {
-        const int64_t i = base + j * DBLOCK + threadIdx.x;
+    for (int64_t i = (int64_t)blockIdx.x * DBLOCK + threadIdx.x; i < n; i += stride) {
         DepRec r;
         int ic, lc;
-        tile[j] = -1;
-        if (i < n && classify(a, i, r, ic, lc)) {
-            tile[j] = tile_of(a, ic, lc);
-            rank[j] = atomicAdd(&h[tile[j]], 1);
-        }
+        if (classify(a, i, r, ic, lc)) atomicAdd(&h[tile_of(a, ic, lc)], 1);
     }
     __syncthreads();
     for (int k = threadIdx.x; k < a.nt; k += DBLOCK)
         if (h[k]) h[k] = a.off[k] + atomicAdd(&a.cur[k], h[k]);
     __syncthreads();
-#pragma unroll
-    for (int j = 0; j < DEP_PT; ++j) {
-        if (tile[j] < 0) continue;
-        const int64_t i = base + j * DBLOCK + threadIdx.x;
+    for (int64_t i = (int64_t)blockIdx.x * DBLOCK + threadIdx.x; i < n; i += stride) {
         DepRec r;
         int ic, lc;
-        classify(a, i, r, ic, lc);
+        if (!classify(a, i, r, ic, lc)) continue;
         r.code |= (ic % a.T) | (lc % a.T) << 8;
-        a.rec[h[tile[j]] + rank[j]] = r;
+        a.rec[atomicAdd(&h[tile_of(a, ic, lc)], 1)] = r;
     }
 }
 
-// 4. one block per chunk of a tile: LDS window of the tile, flushed with global atomics
-// (16 wavefronts per block: a chunk's records are spread over a whole compute unit)
+// 4. one block per chunk of a tile (persistent over the work list): LDS window of the tile,
+// added to the 64-bit grid with global atomics (16 wavefronts per block: a chunk's records
+// are spread over a whole compute unit)
 constexpr int TBLOCK = 1024;
 __global__ __launch_bounds__(TBLOCK) void k_dep_tiles(DepositArgs a) {
     extern __shared__ unsigned long long acc[];
-    if ((int)blockIdx.x >= *a.nwork) return;
-    const int4 wk = a.work[blockIdx.x];
+    const int nw = *a.nwork;
     const int W = a.T + 4, WW = W * W;
-    for (int k = threadIdx.x; k < 3 * WW; k += TBLOCK) acc[k] = 0;
-    __syncthreads();
     const double s0 = a.scale[0], s1 = a.scale[1], s2 = a.scale[2];
-    for (int k = wk.y + threadIdx.x; k < wk.z; k += TBLOCK) {
-        const DepRec r = a.rec[k];
-        LdsSink s{acc, W, ((r.code >> 8) & 255) * W + (r.code & 255), {s0, s1, s2}};
-        deposit_record(a, r, s);
-    }
-    __syncthreads();
-    const int tx0 = (wk.x % a.ntx) * a.T - 2, ty0 = (wk.x / a.ntx) * a.T - 2;
     const int64_t nodes = (int64_t)a.nx * a.ny;
-    for (int k = threadIdx.x; k < 3 * WW; k += TBLOCK) {
-        const unsigned long long v = acc[k];
-        if (v == 0) continue;
-        const int c = k / WW, rem = k - c * WW, l = rem / W, m = rem - l * W;
-        int gx = (tx0 + m) % a.nx, gy = (ty0 + l) % a.ny;
-        gx = gx < 0 ? gx + a.nx : gx;
-        gy = gy < 0 ? gy + a.ny : gy;
-        atomicAdd(a.acc + c * nodes + (int64_t)gy * a.nx + gx, v);
+    for (int w = blockIdx.x; w < nw; w += gridDim.x) {   // persistent over the work list
+        const int4 wk = a.work[w];
+        for (int k = threadIdx.x; k < 3 * WW; k += TBLOCK) acc[k] = 0;
+        __syncthreads();
+        for (int k = wk.y + threadIdx.x; k < wk.z; k += TBLOCK) {
+            const DepRec r = a.rec[k];
+            LdsSink s{acc, W, ((r.code >> 8) & 255) * W + (r.code & 255), {s0, s1, s2}};
+            deposit_record(a, r, s);
+        }
+        __syncthreads();
+        const int tx0 = (wk.x % a.ntx) * a.T - 2, ty0 = (wk.x / a.ntx) * a.T - 2;
+        for (int k = threadIdx.x; k < 3 * WW; k += TBLOCK) {
+            const unsigned long long v = acc[k];
+            if (v == 0) continue;
+            const int c = k / WW, rem = k - c * WW, l = rem / W, m = rem - l * W;
+            int gx = (tx0 + m) % a.nx, gy = (ty0 + l) % a.ny;
+            gx = gx < 0 ? gx + a.nx : gx;
+            gy = gy < 0 ? gy + a.ny : gy;
+            atomicAdd(a.acc + c * nodes + (int64_t)gy * a.nx + gx, v);
+        }
+        __syncthreads();   // the window is cleared for the next work item
     }
 }
 
@@ -509,8 +502,10 @@ hipError_t launch_deposit(qed_ctx *ctx, const qed_leptons &L, const double *cons
     a.acc = (unsigned long long *)ctx->dep_acc;
     a.work = (int4 *)ctx->dep_work;
     a.rec = (DepRec *)ctx->dep_rec;
-    const unsigned pblocks = (unsigned)((L.capacity + DEP_PB - 1) / DEP_PB);
-    const unsigned wblocks = (unsigned)(L.capacity / DEP_CH + DEP_MAX_TILES + 1);
+    const int64_t persist = (int64_t)DEP_BPC * ctx->num_cu;
+    const int64_t pb = (L.capacity + DBLOCK - 1) / DBLOCK, wb = L.capacity / DEP_CH + a.nt + 1;
+    const unsigned pblocks = (unsigned)(pb < persist ? pb : persist);
+    const unsigned wblocks = (unsigned)(wb < persist ? wb : persist);
     const size_t lds = 3 * (size_t)(a.T + 4) * (a.T + 4) * sizeof(unsigned long long);
     hipLaunchKernelGGL(k_dep_count, dim3(pblocks), dim3(DBLOCK), 0, s, a);
     hipLaunchKernelGGL(k_dep_scan, dim3(1), dim3(SCAN_T), 0, s, a);
