@@ -238,11 +238,15 @@ qed_status qed_field_advance(qed_ctx_t *ctx, float *const grid[6], const float *
  * rho = Q Sx Sy/(dx dy), so the solver keeps Gauss's law.  n0 is a device scalar (the
  * list's count at the start of the step: particles appended during the step start with
  * the next one).  A move of a cell or more per axis, or a non-finite position or weight,
- * skips the particle and sets QED_ST_DEPOSIT.  FP32 sums, correct to FP32 rounding in an
- * order that may change from run to run.  nx, ny >= 2, at most 2^29 nodes.  Grids of at
- * most 4096 tiles of 64 x 64 nodes take a binned path with context-owned work memory (tile
- * counters; 56 bytes per lepton of the largest list seen, hipMalloc on first use or
- * growth); calls on one context must not overlap.                                        */
+ * skips the particle and sets QED_ST_DEPOSIT.  nx, ny >= 2, at most 2^29 nodes.
+ * Grids of at most 8192 tiles of 32 x 32 nodes take a binned path: particles sorted by
+ * tile, each tile summed in LDS in 64-bit fixed point (quantum 2^-32 of the largest
+ * possible contribution of the call), the sums converted to FP32 and added to `current`
+ * once per node, so the result is the same on every run.  It uses context-owned work
+ * memory (tile counters; 56 bytes per lepton of the largest list seen; a 64-bit copy of
+ * the grid, 24 bytes per node), allocated with hipMalloc on first use or growth.  Larger
+ * grids add each contribution with FP32 atomics (sums in an order that may change from
+ * run to run).  Calls on one context must not overlap.                                   */
 qed_status qed_deposit_current(qed_ctx_t *ctx, const qed_leptons *l, const double *const x0[3], const int64_t *n0,
                                float *const current[3], int32_t nx, int32_t ny, double dx, double dy, double gx0,
                                double gy0, double dt, double qscale, hipStream_t stream);
