@@ -295,6 +295,14 @@ def run_learned(args, torch, Q, W, cfg, fp64):
         "roofline": {"bound": "mfma", "achieved": tflops, "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": tflops / MFMA_BF16_PEAK_TFLOPS, "kernel": "k_mlp_forward (bf16 MFMA 32x32x16)",
                      "flop_per_sample": MLP_FLOP, "avg_launch_ms": t_mlp},
+        # the vector-unit work the matrix cores cannot take: layer 1 (512 FMA), layer 4
+        # (384), per SiLU 3 full-rate ops + v_exp and v_rcp at a quarter rate (384 SiLU)
+        "roofline_alu": {"bound": "alu", "achieved": n / (t_mlp * 1e-3) * MLP_VALU_OPS / 1e12,
+                         "peak": VALU_LANE_OPS_PEAK / 1e12, "unit": "Tlane-op/s",
+                         "frac": n / (t_mlp * 1e-3) * MLP_VALU_OPS / VALU_LANE_OPS_PEAK,
+                         "lane_ops_per_sample": MLP_VALU_OPS,
+                         "peak_note": "256 CUs x 64 lanes x 2.4 GHz, one FP32 (non-packed) op per lane per clock; "
+                                      "a transcendental counts 4"},
     }
     del X, T64, Y
     c2 = Q.Context(dt=0.01, procs=Q.PROC_NCS | Q.PROC_NCS_STOKES, seed=1, id_start=0, precision=Q.QED_MIXED)
@@ -309,6 +317,11 @@ def run_learned(args, torch, Q, W, cfg, fp64):
         out["step"]["error_vs_fp64"] = error_metrics(fp64, learned, 2000.0, torch)
     return out
 
+
+# vector work of one forward sample in full-rate lane operations: layers 1 and 4 (FMA),
+# and per SiLU 3 ops plus two transcendentals at a quarter of the rate
+MLP_VALU_OPS = 4 * 128 + 128 * 3 + 3 * 128 * (3 + 2 * 4)
+VALU_LANE_OPS_PEAK = 256 * 64 * 2.4e9
 
 # Yee step: three passes, each reading 6 components and writing 3 (FP32)
 BYTES_YEE_NODE = 3 * (6 + 3) * 4
