@@ -121,40 +121,61 @@ qed_status seg_args(qed_ctx *ctx, const qed_segment *segs, int nseg, SegArgs &sa
     sa.f0 = field_dev(segs[0].field);
     sa.segs = nullptr;
     if (nseg == 1) return QED_OK;
-    // several segments: upload unless identical to the list already on the device
-    const size_t bytes = sizeof(DevSegment) * (size_t)nseg;
-    std::vector<DevSegment> dev((size_t)nseg);
+    // several segments: upload unless identical to the list already on the device.  Layout:
+    // the DevSegment array, the segment starts again as a compact int64 array, and for
+    // every 256-particle tile up to the last segment's end the segment that holds the
+    // tile's first index (or the last one starting before it): the kernels read one table
+    // entry per wavefront instead of searching
+    const size_t seg_bytes = sizeof(DevSegment) * (size_t)nseg;
+    const size_t head = seg_bytes + sizeof(int64_t) * (size_t)nseg;
+    const int64_t ntile = (segs[nseg - 1].end + BLOCK - 1) / BLOCK;
+    const size_t bytes = head + sizeof(int32_t) * (size_t)ntile;
+    std::vector<char> dev(head, 0);   // zeroed padding too, for the comparison below
     for (int k = 0; k < nseg; ++k) {
-        std::memset(&dev[k], 0, sizeof(DevSegment));   // padding too, for the comparison below
-        dev[k].begin = segs[k].begin;
-        dev[k].end = segs[k].end;
-        dev[k].f = field_dev(segs[k].field);
+        DevSegment d;
+        std::memset(&d, 0, sizeof(DevSegment));
+        d.begin = segs[k].begin;
+        d.end = segs[k].end;
+        d.f = field_dev(segs[k].field);
+        std::memcpy(dev.data() + sizeof(DevSegment) * k, &d, sizeof(DevSegment));
+        std::memcpy(dev.data() + seg_bytes + sizeof(int64_t) * k, &segs[k].begin, sizeof(int64_t));
     }
-    if (nseg != ctx->nseg_dev || std::memcmp(ctx->hsegs, dev.data(), bytes) != 0) {
+    if (nseg != ctx->nseg_dev || bytes != ctx->seg_bytes || std::memcmp(ctx->hsegs, dev.data(), head) != 0) {
         hipError_t e = hipSuccess;
         if (ctx->nseg_dev > 0) e = hipEventSynchronize(ctx->seg_copied);   // host staging reusable
-        if (e == hipSuccess && nseg > ctx->nseg_cap) {
+        if (e == hipSuccess && bytes > ctx->seg_cap_bytes) {
             hipFree(ctx->dsegs);
             hipHostFree(ctx->hsegs);
             ctx->dsegs = nullptr;
             ctx->hsegs = nullptr;
-            ctx->nseg_cap = 0;
+            ctx->seg_cap_bytes = 0;
             e = hipMalloc(&ctx->dsegs, bytes);
             if (e == hipSuccess) e = hipHostMalloc((void **)&ctx->hsegs, bytes, hipHostMallocDefault);
-            if (e == hipSuccess) ctx->nseg_cap = nseg;
+            if (e == hipSuccess) ctx->seg_cap_bytes = bytes;
         }
         if (e == hipSuccess) {
-            std::memcpy(ctx->hsegs, dev.data(), bytes);
+            std::memcpy(ctx->hsegs, dev.data(), head);
+            int32_t *tab = (int32_t *)((char *)ctx->hsegs + head);
+            int k = 0;
+            for (int64_t t = 0; t < ntile; ++t) {
+                while (k + 1 < nseg && segs[k + 1].begin <= t * BLOCK) ++k;
+                tab[t] = k;
+            }
             e = hipMemcpyAsync(ctx->dsegs, ctx->hsegs, bytes, hipMemcpyHostToDevice, stream);
         }
         if (e == hipSuccess) e = hipEventRecord(ctx->seg_copied, stream);
         if (e != hipSuccess) {
             ctx->nseg_dev = 0;
+            ctx->seg_bytes = 0;
             return hip_fail(ctx, e, "segment upload");
         }
         ctx->nseg_dev = nseg;
+        ctx->seg_bytes = bytes;
     }
     sa.segs = ctx->dsegs;
+    sa.seg_begin = (const int64_t *)((const char *)ctx->dsegs + seg_bytes);
+    sa.tile_seg = (const int32_t *)((const char *)ctx->dsegs + head);
+    sa.ntile_seg = ntile;
     return QED_OK;
 }
 

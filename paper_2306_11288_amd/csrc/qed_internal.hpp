@@ -116,6 +116,9 @@ struct SegArgs {
     int64_t begin0, end0;
     FieldDev f0;
     const DevSegment *segs;    // device copy when nseg > 1
+    const int64_t *seg_begin;  // the segments' starts, compact (same allocation)
+    const int32_t *tile_seg;   // per 256-particle tile: segment of its first index (or the last before it)
+    int64_t ntile_seg;
 };
 FieldDev field_dev(const qed_field &f);   // host: derived constants of a field
 
@@ -168,7 +171,8 @@ struct qed_ctx {
     int64_t staging_cap;               // rounded up to whole tiles
     qed::DevSegment *dsegs;            // device copy of the last multi-segment list
     qed::DevSegment *hsegs;            // pinned host staging of that copy
-    int nseg_cap, nseg_dev;            // capacity and size of the uploaded list
+    int nseg_dev;                      // segments in the uploaded list
+    size_t seg_bytes, seg_cap_bytes;   // bytes of the uploaded list (with its tile table), capacity
     hipEvent_t seg_copied;             // completion of the last upload
     int64_t max_tiles;
     hipEvent_t step_ev[4];             // optional timing events of the NCS launches

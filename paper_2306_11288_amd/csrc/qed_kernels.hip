@@ -96,32 +96,37 @@ __device__ __forceinline__ void fields_for(const SegArgs &sa, int64_t i, double 
         if (i >= sa.begin0 && i < sa.end0) field_kind<FT, FK>(sa.f0, t, r.x, r.y, r.z, E, B);
     } else {
         // Segments are index ranges and a wavefront holds consecutive indices, so it almost
-        // always lies in one segment.  Waterfall over the segments present: the first lane
-        // still pending picks its segment (a search on wavefront-uniform values, so the
-        // segment descriptor comes through scalar loads and the field kind is uniform), the
-        // lanes inside it evaluate the field; one pass in the usual case.
+        // always lies in one segment.  Waterfall over the segments present, starting from the
+        // segment of the first active lane's tile (one table entry): the lanes inside the
+        // current segment evaluate the field (its descriptor comes through scalar loads and
+        // its kind is uniform); if lanes remain, the first of them picks the next segment by
+        // a search on wavefront-uniform values.  One pass in the usual case.
+        const int i0 = __builtin_amdgcn_readfirstlane((int)i), t0 = i0 / BLOCK;
+        int lo = t0 < sa.ntile_seg ? sa.tile_seg[t0] : sa.nseg - 1;
         bool done = false;
         for (;;) {
+            const DevSegment &sg = sa.segs[lo];
+            if (!done && i >= sg.begin && i < sg.end) {
+                if constexpr (FK == FK_MULTI) field_at<FT>(sg.f, t, r.x, r.y, r.z, E, B);
+                else field_kind<FT, FK - FK_MULTI_BASE>(sg.f, t, r.x, r.y, r.z, E, B);
+                done = true;
+            }
             const unsigned long long pending = __ballot(!done);
             if (pending == 0) break;
             const int leader = __ffsll((long long)pending) - 1;
             const int il = __builtin_amdgcn_readlane((int)i, leader);
-            int lo = 0, hi = sa.nseg - 1;   // last segment with begin <= il
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (sa.segs[mid].begin <= il) lo = mid;
-                else hi = mid - 1;
+            int a = 0, b = sa.nseg - 1;   // last segment with begin <= il
+            while (a < b) {
+                const int mid = (a + b + 1) >> 1;
+                if (sa.seg_begin[mid] <= il) a = mid;
+                else b = mid - 1;
             }
-            const DevSegment &sg = sa.segs[lo];
-            if (!done) {
-                if (i >= sg.begin && i < sg.end) {
-                    if constexpr (FK == FK_MULTI) field_at<FT>(sg.f, t, r.x, r.y, r.z, E, B);
-                    else field_kind<FT, FK - FK_MULTI_BASE>(sg.f, t, r.x, r.y, r.z, E, B);
-                    done = true;
-                } else if ((int)i == il) {
-                    done = true;   // the leader lies outside every segment: no field
-                }
+            if (a == lo) {                // the leader lies outside every segment: no field
+                if ((int)i == il) done = true;
+                if (__ballot(!done) == 0) break;
+                continue;
             }
+            lo = a;
         }
     }
 }
