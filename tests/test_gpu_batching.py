@@ -130,6 +130,62 @@ def test_batched_sample_vs_oracle_fp64():
         assert np.max(np.abs(Gb[k] - go[k])) < 1e-10, k
 
 
+def test_mixed_kinds_and_gaps_vs_oracle_fp64():
+    """Segments of different field kinds (plane waves, Gaussian beams, a constant field)
+    with gaps between them, boundaries inside wavefronts: the generic many-kind kernel and
+    the waterfall over segments; particles in a gap see no field.  Against the oracle,
+    which steps the segments and the gaps as separate lists in index order."""
+    _say("mixed kinds and gaps vs oracle")
+    cfg = _cfg(n_collisions=6, n_min=150, n_max=500)
+    segs, pieces, prev = [], [], 0
+    for k, (b, e, spec) in enumerate(cfg["segments"]):
+        spec = dict(spec)
+        if k % 3 == 1:
+            spec.update(kind=W.FIELD_GAUSS, w0=12.0, x_focus=0.0, phi_start=0.0)
+        elif k % 3 == 2 and k == 2:
+            spec = {"kind": W.FIELD_CONST, "e0": (0.0, 30.0, 0.0), "b0": (0.0, 0.0, -30.0)}
+        lo, hi = b + 7 + 3 * k, e - 5                         # gaps at both ends
+        if lo > prev:
+            pieces.append((prev, lo, {"kind": W.FIELD_NONE}))
+        pieces.append((lo, hi, spec))
+        segs.append((lo, hi, spec))
+        prev = hi
+    n = len(cfg["leptons"]["x"])
+    if prev < n:
+        pieces.append((prev, n, {"kind": W.FIELD_NONE}))
+    steps = range(0, 30)
+    ctx = _ctx(cfg, Q.QED_FP64)
+    L = Q.Leptons.from_state(cfg["leptons"], precision=Q.QED_FP64)
+    G = Q.Photons(n * 2, precision=Q.QED_FP64)
+    sg = Q.segments(segs)
+    for s in steps:
+        ctx.step_leptons(sg, L, G, s)
+    torch.cuda.synchronize()
+    Lb, Gb = L.to_numpy(), G.to_numpy()
+    sim = oracle.Sim(dt=cfg["dt"], procs=cfg["procs"], seed=cfg["seed"], next_id=cfg["next_id"])
+    Go = oracle.PhotonArrays.empty(n * 2)
+    Ls = [(oracle.LeptonArrays.from_state({k: v[b:e].copy() for k, v in cfg["leptons"].items()}),
+           oracle.make_field(spec)) for (b, e, spec) in pieces]
+    for s in steps:
+        for Lo, f in Ls:
+            sim.step(f, Lo, None, Go, s)
+    ov = {k: np.concatenate([Lo.view()[k] for Lo, _ in Ls]) for k in Ls[0][0].view()}
+    assert np.array_equal(Lb["id"], ov["id"])
+    pm = np.sqrt(ov["px"] ** 2 + ov["py"] ** 2 + ov["pz"] ** 2) + 1.0
+    for k in ("px", "py", "pz"):
+        assert np.max(np.abs(Lb[k] - ov[k]) / pm) < 1e-10, k
+    for k in ("sx", "sy", "sz"):
+        assert np.max(np.abs(Lb[k] - ov[k])) < 1e-10, k
+    go = Go.view()
+    assert len(go["x"]) == len(Gb["x"]) > 20
+    assert np.array_equal(go["id"], Gb["id"])
+    # gap particles moved on straight lines (no field): p unchanged
+    p0 = cfg["leptons"]
+    for (b, e, spec) in pieces:
+        if spec["kind"] == W.FIELD_NONE:
+            assert np.array_equal(Lb["px"][b:e], p0["px"][b:e])
+
+
 def test_graph_replay_equals_eager():
     """K steps captured once (step calls + device step counter advance) and replayed R
     times, with eager work and synchronisations between the replays, equal R*K eager steps;
