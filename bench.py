@@ -181,6 +181,20 @@ def error_metrics(a, b, gamma0, torch):
     return out
 
 
+# metrics that measure a difference between two runs (the others are values)
+DIFF_METRICS = ("mean_energy_rel", "photon_spectrum_L1", "photon_count_rel", "electron_theta_y_L1",
+                "electron_theta_z_L1", "photon_theta_y_L1", "mean_spin_abs_diff", "photon_xi2_abs_diff",
+                "photon_xi3_abs_diff")
+
+
+def tolerance_check(err: dict, stat: dict) -> dict:
+    """Each difference metric against max(4 x its value between two FP64 runs with different
+    random draws, 1e-3): the accuracy bar the mixed (or learned) run is stated at."""
+    tol = {k: max(4.0 * stat[k], 1e-3) for k in DIFF_METRICS}
+    return {"tolerance": tol, "within": {k: err[k] <= tol[k] for k in DIFF_METRICS},
+            "all_within": all(err[k] <= tol[k] for k in DIFF_METRICS)}
+
+
 class _Cat:
     """Concatenated view of several lepton lists (for the error metrics)."""
 
@@ -260,7 +274,7 @@ MLP_FLOP = 2 * (4 * 128 + 2 * 128 * 128 + 128 * 3)   # multiply-adds x 2 per sam
 MFMA_BF16_PEAK_TFLOPS = 2500.0
 
 
-def run_learned(args, torch, Q, W, cfg, fp64):
+def run_learned(args, torch, Q, W, cfg, fp64, fp64_b=None):
     """The learned sampler: matrix-core inference against the table sampler on the same
     inputs, training throughput of the library's kernels, and the focused-pulse step with
     the network (the shipped one) as sampler against the FP64 table path."""
@@ -315,6 +329,9 @@ def run_learned(args, torch, Q, W, cfg, fp64):
                    "status_bits": learned["status"], "network": "sampler_ncs.npy (5e7 pairs, 2 epochs)"}
     if fp64 is not None:
         out["step"]["error_vs_fp64"] = error_metrics(fp64, learned, 2000.0, torch)
+        if fp64_b is not None:
+            out["step"]["error_tolerance"] = tolerance_check(out["step"]["error_vs_fp64"],
+                                                             error_metrics(fp64, fp64_b, 2000.0, torch))
     return out
 
 
@@ -592,11 +609,14 @@ def main():
     mixed = run_gpu("mixed", cfg, args.steps, args.warmup, torch, Q)
     print(f"[bench] mixed done: {args.steps * args.n / mixed['wall']:.3e} particle-steps/s", file=sys.stderr,
           flush=True)
-    fp64 = None
+    fp64 = fp64_b = None
     if not args.no_fp64:
         fp64 = run_gpu("fp64", cfg, args.steps, args.warmup, torch, Q)
         print(f"[bench] fp64 done: {args.steps * args.n / fp64['wall']:.3e} particle-steps/s", file=sys.stderr,
               flush=True)
+        # the same run with other random draws: the statistical spread of the error metrics
+        fp64_b = run_gpu("fp64", dict(cfg, seed=cfg["seed"] + 1), args.steps, args.warmup, torch, Q,
+                         per_launch_events=False)
 
     ms_per_step = 1e3 * mixed["wall"] / args.steps
     value = args.n * args.steps / mixed["wall"]
@@ -636,6 +656,9 @@ def main():
                           "status_bits": fp64["status"]}
         result["speedup_mixed_over_fp64"] = result["value"] / result["fp64"]["value"]
         result["error_vs_fp64"] = error_metrics(fp64, mixed, 2000.0, torch)
+        stat = error_metrics(fp64, fp64_b, 2000.0, torch)
+        result["error_statistical_fp64_seeds"] = stat
+        result["error_tolerance"] = tolerance_check(result["error_vs_fp64"], stat)
     print("[bench] detector histogram", file=sys.stderr, flush=True)
     result["detector"] = run_detector(torch, Q, mixed)
     if args.radiative_steps > 0:
@@ -646,7 +669,7 @@ def main():
         result["cascade"] = run_cascade(args, torch, Q, W)
     if not args.no_learned:
         print("[bench] learned sampler", file=sys.stderr, flush=True)
-        result["learned"] = run_learned(args, torch, Q, W, cfg, fp64)
+        result["learned"] = run_learned(args, torch, Q, W, cfg, fp64, fp64_b)
     if args.batch_steps > 0:
         print("[bench] batching: many collisions, graph-replayed, vs one at a time in FP64", file=sys.stderr, flush=True)
         result["batched"] = run_batched(args, torch, Q, W)
