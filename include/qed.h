@@ -359,7 +359,9 @@ qed_status qed_mlp_train_step(qed_ctx_t *ctx, const float *X, const float *T, in
  * precision): the reference for the network's error and its fallback                */
 qed_status qed_sampler_table(qed_ctx_t *ctx, const float *X, float *Y, int64_t n, hipStream_t stream);
 /* which sampler later NCS emissions use: QED_SAMPLER_TABLE (default) or QED_SAMPLER_MLP
- * (the network inside its trained chi range, the table outside it)                     */
+ * (the network's t inside its trained chi range where 0.5 <= t < t_max, the table
+ * elsewhere: below t = 0.5 the network's absolute error is a large relative error in the
+ * photon energy u ~ t^3)                                                                 */
 qed_status qed_set_sampler(qed_ctx_t *ctx, int sampler);
 /* Last argument / HIP error of this context as text (empty if none). */
 const char *qed_last_error(const qed_ctx_t *ctx);

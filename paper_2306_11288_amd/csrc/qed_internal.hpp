@@ -127,6 +127,9 @@ constexpr int MLP_OW1 = 0, MLP_OB1 = 512, MLP_OW2 = 640, MLP_OB2 = 17024, MLP_OW
               MLP_OW4 = 33664, MLP_OB4 = 34048, MLP_NPARAM = 34051;
 // input normalisation: x0 = (log10 chi - MID) / HALF over the trained range chi in [1e-3, 50]
 constexpr double MLP_L10_MID = -0.65, MLP_L10_HALF = 2.35, MLP_L10_HI = 1.6989700043360187;
+// below this t (in units of T_MAX) the network's absolute error is a large relative error
+// in the photon energy u ~ t^3, and the step takes t from the table
+constexpr float MLP_Y_LO = 0.5f / 3.4199518933533937f;
 constexpr double MLP_CHI_LO = 1e-3, MLP_CHI_HI = 50.0;
 
 // detector histogram launch (one energy axis at most, HIST_EMAX bins on it)

@@ -509,10 +509,11 @@ __global__ __launch_bounds__(BLOCK) void k_leptons_events(LeptonArgs a) {
                 ((float4 *)a.ev_in)[ge] = x;
                 continue;
             }
-            // the network's t is used where it is a valid sample (0 < t < t_max) inside its
-            // trained chi range; the table decides everywhere else
+            // the network's t is used where it is a valid sample (t_lo <= t < t_max, t_lo =
+            // 0.5: below it the network's absolute error is a large relative error in the
+            // energy) inside its trained chi range; the table decides everywhere else
             const float yn = MODE == EV_FINISH ? a.ev_out[3 * ge] : -1.0f;
-            const T tt = (MODE == EV_FINISH && in_range && yn > 0.0f && yn < 1.0f)
+            const T tt = (MODE == EV_FINISH && in_range && yn >= MLP_Y_LO && yn < 1.0f)
                              ? (T)(yn * (float)T_MAX)
                              : ncs_sample_t<T>(tb, f.chi, f.Ib / f.Ia, f.s, (T)rr[0]);
             NcsPhoton<T> ph;
