@@ -396,8 +396,7 @@ def run_cascade(args, torch, Q, W):
         if deposit:
             for j in J:
                 j.zero_()
-            ctx.deposit_current(em, start["em"], grid, J, CASCADE_QSCALE)
-            ctx.deposit_current(ep, start["ep"], grid, J, CASCADE_QSCALE)
+            ctx.deposit_current([(em, start["em"]), (ep, start["ep"])], grid, J, CASCADE_QSCALE)
         if ev: ev[3].record()
         if solver:
             ctx.field_advance(spec, cfg["dt"], 1, current=J if deposit else None,

@@ -228,28 +228,36 @@ qed_status qed_field_advance(qed_ctx_t *ctx, float *const grid[6], const float *
                              int64_t steps, hipStream_t stream);
 
 /* Charge-conserving current deposition (Sec. II.C, Esirkepov's decomposition with the TSC
- * shapes of Sec. II.E): leptons [0, *n0) that moved from (x0[0], x0[1], x0[2]) (device FP64
- * arrays of the positions at the start of the step, caller-saved) to their current
- * positions over one step dt ADD their current to `current` (three caller-owned device FP32
- * arrays [ny][nx], not cleared: Jx at (i+1/2, j), Jy at (i, j+1/2), Jz at (i, j), node (i, j)
- * at (gx0 + i dx, gy0 + j dy), periodic in x and y).  A particle of weight w carries charge
+ * shapes of Sec. II.E).  Each source is a lepton list with the positions of its first *n0
+ * particles at the start of the step (x0[0..2]: device FP64 arrays, caller-saved, e.g. by
+ * qed_save_start; *n0: device scalar, the list's count then: particles appended during the
+ * step start with the next one).  Those particles, moved to their current positions over
+ * one step dt, ADD their current to `current` (three caller-owned device FP32 arrays
+ * [ny][nx], not cleared: Jx at (i+1/2, j), Jy at (i, j+1/2), Jz at (i, j), node (i, j) at
+ * (gx0 + i dx, gy0 + j dy), periodic in x and y).  A particle of weight w carries charge
  * Q = charge w qscale (qscale: the charge of a unit weight in the units of the field
  * equations); its current satisfies (rho1 - rho0)/dt + div J = 0 at every node with
- * rho = Q Sx Sy/(dx dy), so the solver keeps Gauss's law.  n0 is a device scalar (the
- * list's count at the start of the step: particles appended during the step start with
- * the next one).  A move of a cell or more per axis, or a non-finite position or weight,
- * skips the particle and sets QED_ST_DEPOSIT.  nx, ny >= 2, at most 2^29 nodes.
+ * rho = Q Sx Sy/(dx dy), so the solver keeps Gauss's law.  1 <= nsrc <= 4 (electrons and
+ * positrons in one call cost one pass).  A move of a cell or more per axis, or a
+ * non-finite position or weight, skips the particle and sets QED_ST_DEPOSIT.  nx, ny >= 2,
+ * at most 2^29 nodes.
  * Grids of at most 8192 tiles of 32 x 32 nodes take a binned path: particles sorted by
  * tile, each tile summed in LDS in 64-bit fixed point (quantum 2^-32 of the largest
  * possible contribution of the call), the sums converted to FP32 and added to `current`
  * once per node, so the result is the same on every run.  It uses context-owned work
- * memory (tile counters; 56 bytes per lepton of the largest list seen; a 64-bit copy of
+ * memory (tile counters; 56 bytes per lepton of the sources' capacities; a 64-bit copy of
  * the grid, 24 bytes per node), allocated with hipMalloc on first use or growth.  Larger
  * grids add each contribution with FP32 atomics (sums in an order that may change from
  * run to run).  Calls on one context must not overlap.                                   */
-qed_status qed_deposit_current(qed_ctx_t *ctx, const qed_leptons *l, const double *const x0[3], const int64_t *n0,
-                               float *const current[3], int32_t nx, int32_t ny, double dx, double dy, double gx0,
-                               double gy0, double dt, double qscale, hipStream_t stream);
+#define QED_DEPOSIT_MAX_SRC 4
+typedef struct {
+    const qed_leptons *leptons;
+    const double *x0[3];
+    const int64_t *n0;
+} qed_deposit_src;
+qed_status qed_deposit_current(qed_ctx_t *ctx, const qed_deposit_src *src, int32_t nsrc, float *const current[3],
+                               int32_t nx, int32_t ny, double dx, double dy, double gx0, double gy0, double dt,
+                               double qscale, hipStream_t stream);
 /* The start state qed_deposit_current needs: copies positions [0, count) of `l` into the
  * device FP64 arrays x0[0..2] (capacity entries each, caller-owned) and the count into the
  * device scalar *n0.  Asynchronous on `stream`; call it before the step that moves them.  */

@@ -81,6 +81,10 @@ def hist_spec(axes, n, lo, hi, pol_ref=(0.0, 1.0, 0.0)) -> HistSpec:
     return h
 
 
+class DepositSrc(C.Structure):
+    _fields_ = [("leptons", C.c_void_p), ("x0", C.c_void_p * 3), ("n0", C.c_void_p)]
+
+
 class FieldBC(C.Structure):
     _fields_ = [("open_x", C.c_int32), ("pad", C.c_int32), ("incoming", Field), ("gx0", C.c_double),
                 ("gy0", C.c_double), ("t0", C.c_double)]
@@ -124,7 +128,7 @@ def lib():
             "qed_hist_photons": [vp, vp, i64, vp, vp, vp],
             "qed_field_advance": [vp, vp, vp, vp, C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_double, i64,
                                   vp],
-            "qed_deposit_current": [vp, vp, vp, vp, vp, C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_double,
+            "qed_deposit_current": [vp, vp, C.c_int32, vp, C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_double,
                                     C.c_double, C.c_double, C.c_double, vp],
             "qed_save_start": [vp, vp, vp, vp, vp],
             "qed_hist_leptons": [vp, vp, i64, vp, vp, vp],
@@ -398,17 +402,23 @@ class Context:
                     "qed_save_start")
         return out
 
-    def deposit_current(self, L: "Leptons", start, grid: dict, current, qscale: float, stream=None):
-        """Add the current of leptons [0, n0) that moved from the saved start positions to
-        their current ones over one step of this context's dt to `current` (three float32
-        device tensors [ny][nx]).  `start` = (x0, y0, z0, n0): float64 device tensors of the
-        positions and the int64 device count at the start of the step (save_start)."""
-        x0 = (C.c_void_p * 3)(*[t.data_ptr() for t in start[:3]])
+    def deposit_current(self, sources, grid: dict, current, qscale: float, stream=None):
+        """Add the current of the leptons of each source (L, start) that moved from the saved
+        start positions to their current ones over one step of this context's dt to
+        `current` (three float32 device tensors [ny][nx]); start = (x0, y0, z0, n0) as
+        save_start returns them (float64 positions, int64 count).  One to four sources
+        (electrons and positrons in one call cost one pass)."""
+        arr = (DepositSrc * len(sources))()
+        for k, (L, start) in enumerate(sources):
+            arr[k].leptons = C.addressof(L.c())
+            for c in range(3):
+                arr[k].x0[c] = start[c].data_ptr()
+            arr[k].n0 = start[3].data_ptr()
         cur = (C.c_void_p * 3)(*[j.data_ptr() for j in current])
-        self._check(lib().qed_deposit_current(self.h, C.byref(L.c()), x0, _ptr(start[3]), cur, int(grid["nx"]),
-                                              int(grid["ny"]), float(grid["dx"]), float(grid["dy"]),
-                                              float(grid["gx0"]), float(grid["gy0"]), float(self.cfg.dt), float(qscale),
-                                              _stream(stream)), "qed_deposit_current")
+        self._check(lib().qed_deposit_current(self.h, arr, len(sources), cur, int(grid["nx"]), int(grid["ny"]),
+                                              float(grid["dx"]), float(grid["dy"]), float(grid["gx0"]),
+                                              float(grid["gy0"]), float(self.cfg.dt), float(qscale), _stream(stream)),
+                    "qed_deposit_current")
 
     def hist_photons(self, G: "Photons", begin: int, h: HistSpec, out=None, stream=None):
         """Add photons [begin, count) to a detector histogram [n1][n0][5] (float64 device

@@ -411,14 +411,19 @@ qed_status qed_save_start(qed_ctx_t *ctx, const qed_leptons *l, double *const x0
     return launched(ctx, launch_save_start(ctx, *l, x0, n0, s), "qed_save_start");
 }
 
-qed_status qed_deposit_current(qed_ctx_t *ctx, const qed_leptons *l, const double *const x0[3], const int64_t *n0,
-                               float *const current[3], int32_t nx, int32_t ny, double dx, double dy, double gx0,
-                               double gy0, double dt, double qscale, hipStream_t s) {
+qed_status qed_deposit_current(qed_ctx_t *ctx, const qed_deposit_src *src, int32_t nsrc, float *const current[3],
+                               int32_t nx, int32_t ny, double dx, double dy, double gx0, double gy0, double dt,
+                               double qscale, hipStream_t s) {
     qed_status st = ready(ctx);
     if (st != QED_OK) return st;
-    if ((st = check_leptons(ctx, l, "leptons")) != QED_OK) return st;
-    if (!x0 || !x0[0] || !x0[1] || !x0[2]) return fail(ctx, QED_EARG, "qed_deposit_current: NULL start positions");
-    if (!n0) return fail(ctx, QED_EARG, "qed_deposit_current: NULL start count");
+    if (!src || nsrc < 1 || nsrc > QED_DEPOSIT_MAX_SRC)
+        return fail(ctx, QED_EARG, "qed_deposit_current: need 1 to %d sources", QED_DEPOSIT_MAX_SRC);
+    for (int q = 0; q < nsrc; ++q) {
+        if ((st = check_leptons(ctx, src[q].leptons, "qed_deposit_current: leptons")) != QED_OK) return st;
+        if (!src[q].x0[0] || !src[q].x0[1] || !src[q].x0[2])
+            return fail(ctx, QED_EARG, "qed_deposit_current: source %d: NULL start positions", q);
+        if (!src[q].n0) return fail(ctx, QED_EARG, "qed_deposit_current: source %d: NULL start count", q);
+    }
     if (!current || !current[0] || !current[1] || !current[2])
         return fail(ctx, QED_EARG, "qed_deposit_current: NULL current array");
     if (nx < 2 || ny < 2) return fail(ctx, QED_EARG, "qed_deposit_current: nx, ny must be >= 2");
@@ -426,7 +431,7 @@ qed_status qed_deposit_current(qed_ctx_t *ctx, const qed_leptons *l, const doubl
     if (!(dx > 0) || !(dy > 0) || !(dt > 0)) return fail(ctx, QED_EARG, "qed_deposit_current: dx, dy, dt must be > 0");
     if (!std::isfinite(gx0) || !std::isfinite(gy0) || !std::isfinite(qscale))
         return fail(ctx, QED_EARG, "qed_deposit_current: gx0, gy0, qscale must be finite");
-    return launched(ctx, launch_deposit(ctx, *l, x0, n0, current, nx, ny, dx, dy, gx0, gy0, dt, qscale, s),
+    return launched(ctx, launch_deposit(ctx, src, nsrc, current, nx, ny, dx, dy, gx0, gy0, dt, qscale, s),
                     "qed_deposit_current");
 }
 

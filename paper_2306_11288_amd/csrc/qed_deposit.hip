@@ -54,15 +54,22 @@ struct DepRec {
     int32_t code, pad;
 };
 
-struct DepositArgs {
+// one lepton list of the call
+struct DepSource {
     const double *x, *y, *z, *w;      // positions at the end of the step, weights
     const double *x0, *y0, *z0;       // positions at the start of the step
     const int64_t *n0;                // particles [0, *n0) are deposited
     int64_t capacity;
+    double charge;                    // -1 or +1 (folded into each record's weight)
+};
+
+struct DepositArgs {
+    DepSource src[DEP_MAX_SRC];
+    int32_t nsrc;
     float *jx, *jy, *jz;
     int32_t nx, ny;
     double gx0, gy0, inv_dx, inv_dy;
-    double cx, cy, cz;                // -q qscale/(dy dt), -q qscale/(dx dt), q qscale/(dx dy dt)
+    double cx, cy, cz;                // -qscale/(dy dt), -qscale/(dx dt), qscale/(dx dy dt)
     uint32_t *status;
     // tiled path
     int32_t T, ntx, nt;
@@ -74,17 +81,19 @@ struct DepositArgs {
     unsigned long long *acc;           // 64-bit fixed-point J [3][ny][nx] (zero between calls)
 };
 
-__device__ __forceinline__ int64_t dep_count(const DepositArgs &a) {
-    const int64_t n = *a.n0;
-    return n < 0 ? 0 : (n > a.capacity ? a.capacity : n);
+__device__ __forceinline__ int64_t dep_count(const DepSource &d) {
+    const int64_t n = *d.n0;
+    return n < 0 ? 0 : (n > d.capacity ? d.capacity : n);
 }
 
-// start node (wrapped into the grid) and record of particle i; false for a particle that
-// is not deposited (non-finite, absurdly far, or a move of a cell or more)
-__device__ __forceinline__ bool classify(const DepositArgs &a, int64_t i, DepRec &r, int &ic, int &lc) {
-    const double Xa = (a.x0[i] - a.gx0) * a.inv_dx, Ya = (a.y0[i] - a.gy0) * a.inv_dy;
-    const double Xb = (a.x[i] - a.gx0) * a.inv_dx, Yb = (a.y[i] - a.gy0) * a.inv_dy;
-    const double dz = a.z[i] - a.z0[i], w = a.w[i];
+// start node (wrapped into the grid) and record of particle i of source d (weight times
+// charge); false for a particle that is not deposited (non-finite, absurdly far, or a move
+// of a cell or more)
+__device__ __forceinline__ bool classify(const DepositArgs &a, const DepSource &d, int64_t i, DepRec &r, int &ic,
+                                         int &lc) {
+    const double Xa = (d.x0[i] - a.gx0) * a.inv_dx, Ya = (d.y0[i] - a.gy0) * a.inv_dy;
+    const double Xb = (d.x[i] - a.gx0) * a.inv_dx, Yb = (d.y[i] - a.gy0) * a.inv_dy;
+    const double dz = d.z[i] - d.z0[i], w = d.charge * d.w[i];
     const double lim = 1073741824.0;
     if (!(fabs(Xa) < lim && fabs(Ya) < lim && fabs(Xb - Xa) < 1.0 && fabs(Yb - Ya) < 1.0 && isfinite(dz) &&
           isfinite(w)))
@@ -200,12 +209,13 @@ struct LdsSink {
 };
 
 // direct path: one thread per particle, global atomics
-__global__ __launch_bounds__(DBLOCK) void k_deposit(DepositArgs a) {
+__global__ __launch_bounds__(DBLOCK) void k_deposit(DepositArgs a, int sidx) {
+    const DepSource &d = a.src[sidx];
     const int64_t i = (int64_t)blockIdx.x * DBLOCK + threadIdx.x;
-    if (i >= dep_count(a)) return;
+    if (i >= dep_count(d)) return;
     DepRec r;
     int ic, lc;
-    if (!classify(a, i, r, ic, lc)) {
+    if (!classify(a, d, i, r, ic, lc)) {
         atomicOr(a.status, (uint32_t)QED_ST_DEPOSIT);
         return;
     }
@@ -227,21 +237,24 @@ __device__ __forceinline__ int tile_of(const DepositArgs &a, int ic, int lc) {
 __global__ __launch_bounds__(DBLOCK) void k_dep_count(DepositArgs a) {
     __shared__ int h[DEP_MAX_TILES];
     __shared__ unsigned long long s_max[2];
-    const int64_t n = dep_count(a), stride = (int64_t)gridDim.x * DBLOCK;
-    if ((int64_t)blockIdx.x * DBLOCK >= n) return;
+    const int64_t stride = (int64_t)gridDim.x * DBLOCK;
     for (int k = threadIdx.x; k < a.nt; k += DBLOCK) h[k] = 0;
     if (threadIdx.x < 2) s_max[threadIdx.x] = 0;
     __syncthreads();
     double mw = 0.0, mz = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * DBLOCK + threadIdx.x; i < n; i += stride) {
-        DepRec r;
-        int ic, lc;
-        if (classify(a, i, r, ic, lc)) {
-            atomicAdd(&h[tile_of(a, ic, lc)], 1);
-            mw = fmax(mw, fabs(r.w));
-            mz = fmax(mz, fabs(r.wdz));
-        } else {
-            atomicOr(a.status, (uint32_t)QED_ST_DEPOSIT);
+    for (int q = 0; q < a.nsrc; ++q) {
+        const DepSource &d = a.src[q];
+        const int64_t n = dep_count(d);
+        for (int64_t i = (int64_t)blockIdx.x * DBLOCK + threadIdx.x; i < n; i += stride) {
+            DepRec r;
+            int ic, lc;
+            if (classify(a, d, i, r, ic, lc)) {
+                atomicAdd(&h[tile_of(a, ic, lc)], 1);
+                mw = fmax(mw, fabs(r.w));
+                mz = fmax(mz, fabs(r.wdz));
+            } else {
+                atomicOr(a.status, (uint32_t)QED_ST_DEPOSIT);
+            }
         }
     }
     atomicMax(&s_max[0], (unsigned long long)__double_as_longlong(mw));
@@ -315,25 +328,32 @@ __global__ __launch_bounds__(SCAN_T) void k_dep_scan(DepositArgs a) {
 // record at the next slot of its tile (LDS cursor).
 __global__ __launch_bounds__(DBLOCK) void k_dep_scatter(DepositArgs a) {
     __shared__ int h[DEP_MAX_TILES];
-    const int64_t n = dep_count(a), stride = (int64_t)gridDim.x * DBLOCK;
-    if ((int64_t)blockIdx.x * DBLOCK >= n) return;
+    const int64_t stride = (int64_t)gridDim.x * DBLOCK;
     for (int k = threadIdx.x; k < a.nt; k += DBLOCK) h[k] = 0;
     __syncthreads();
-    for (int64_t i = (int64_t)blockIdx.x * DBLOCK + threadIdx.x; i < n; i += stride) {
-        DepRec r;
-        int ic, lc;
-        if (classify(a, i, r, ic, lc)) atomicAdd(&h[tile_of(a, ic, lc)], 1);
+    for (int q = 0; q < a.nsrc; ++q) {
+        const DepSource &d = a.src[q];
+        const int64_t n = dep_count(d);
+        for (int64_t i = (int64_t)blockIdx.x * DBLOCK + threadIdx.x; i < n; i += stride) {
+            DepRec r;
+            int ic, lc;
+            if (classify(a, d, i, r, ic, lc)) atomicAdd(&h[tile_of(a, ic, lc)], 1);
+        }
     }
     __syncthreads();
     for (int k = threadIdx.x; k < a.nt; k += DBLOCK)
         if (h[k]) h[k] = a.off[k] + atomicAdd(&a.cur[k], h[k]);
     __syncthreads();
-    for (int64_t i = (int64_t)blockIdx.x * DBLOCK + threadIdx.x; i < n; i += stride) {
-        DepRec r;
-        int ic, lc;
-        if (!classify(a, i, r, ic, lc)) continue;
-        r.code |= (ic % a.T) | (lc % a.T) << 8;
-        a.rec[atomicAdd(&h[tile_of(a, ic, lc)], 1)] = r;
+    for (int q = 0; q < a.nsrc; ++q) {
+        const DepSource &d = a.src[q];
+        const int64_t n = dep_count(d);
+        for (int64_t i = (int64_t)blockIdx.x * DBLOCK + threadIdx.x; i < n; i += stride) {
+            DepRec r;
+            int ic, lc;
+            if (!classify(a, d, i, r, ic, lc)) continue;
+            r.code |= (ic % a.T) | (lc % a.T) << 8;
+            a.rec[atomicAdd(&h[tile_of(a, ic, lc)], 1)] = r;
+        }
     }
 }
 
@@ -446,19 +466,26 @@ hipError_t launch_save_start(qed_ctx *ctx, const qed_leptons &L, double *const x
     return hipGetLastError();
 }
 
-hipError_t launch_deposit(qed_ctx *ctx, const qed_leptons &L, const double *const x0[3], const int64_t *n0,
-                          float *const J[3], int nx, int ny, double dx, double dy, double gx0, double gy0, double dt,
-                          double qscale, hipStream_t s) {
+hipError_t launch_deposit(qed_ctx *ctx, const qed_deposit_src *src, int nsrc, float *const J[3], int nx, int ny,
+                          double dx, double dy, double gx0, double gy0, double dt, double qscale, hipStream_t s) {
     DepositArgs a{};
-    a.x = L.x;
-    a.y = L.y;
-    a.z = L.z;
-    a.w = L.w;
-    a.x0 = x0[0];
-    a.y0 = x0[1];
-    a.z0 = x0[2];
-    a.n0 = n0;
-    a.capacity = L.capacity;
+    int64_t total = 0;
+    for (int q = 0; q < nsrc; ++q) {
+        const qed_leptons &L = *src[q].leptons;
+        DepSource &d = a.src[q];
+        d.x = L.x;
+        d.y = L.y;
+        d.z = L.z;
+        d.w = L.w;
+        d.x0 = src[q].x0[0];
+        d.y0 = src[q].x0[1];
+        d.z0 = src[q].x0[2];
+        d.n0 = src[q].n0;
+        d.capacity = L.capacity;
+        d.charge = (double)L.charge;
+        total += L.capacity;
+    }
+    a.nsrc = nsrc;
     a.jx = J[0];
     a.jy = J[1];
     a.jz = J[2];
@@ -468,12 +495,11 @@ hipError_t launch_deposit(qed_ctx *ctx, const qed_leptons &L, const double *cons
     a.gy0 = gy0;
     a.inv_dx = 1.0 / dx;
     a.inv_dy = 1.0 / dy;
-    const double Q = L.charge * qscale;
-    a.cx = -Q / (dy * dt);
-    a.cy = -Q / (dx * dt);
-    a.cz = Q / (dx * dy * dt);
+    a.cx = -qscale / (dy * dt);
+    a.cy = -qscale / (dx * dt);
+    a.cz = qscale / (dx * dy * dt);
     a.status = ctx->status;
-    if (L.capacity == 0) return hipGetLastError();
+    if (total == 0) return hipGetLastError();
     for (int T = 16; T <= 32; T *= 2) {
         const int64_t ntx = (nx + T - 1) / T, nty = (ny + T - 1) / T;
         if (ntx * nty <= DEP_MAX_TILES) {
@@ -484,12 +510,15 @@ hipError_t launch_deposit(qed_ctx *ctx, const qed_leptons &L, const double *cons
         }
     }
     if (a.T == 0) {
-        const dim3 gd((unsigned)((L.capacity + DBLOCK - 1) / DBLOCK)), bd(DBLOCK);
-        hipLaunchKernelGGL(k_deposit, gd, bd, 0, s, a);
+        for (int q = 0; q < nsrc; ++q) {
+            if (a.src[q].capacity == 0) continue;
+            const dim3 gd((unsigned)((a.src[q].capacity + DBLOCK - 1) / DBLOCK)), bd(DBLOCK);
+            hipLaunchKernelGGL(k_deposit, gd, bd, 0, s, a, q);
+        }
         return hipGetLastError();
     }
     const int64_t nodes = (int64_t)nx * ny;
-    const hipError_t e = ensure_deposit(ctx, L.capacity, nodes);
+    const hipError_t e = ensure_deposit(ctx, total, nodes);
     if (e != hipSuccess) return e;
     a.cnt = ctx->dep_cnt;
     a.off = ctx->dep_cnt + (DEP_MAX_TILES + 1);
@@ -503,7 +532,7 @@ hipError_t launch_deposit(qed_ctx *ctx, const qed_leptons &L, const double *cons
     a.work = (int4 *)ctx->dep_work;
     a.rec = (DepRec *)ctx->dep_rec;
     const int64_t persist = (int64_t)DEP_BPC * ctx->num_cu;
-    const int64_t pb = (L.capacity + DBLOCK - 1) / DBLOCK, wb = L.capacity / DEP_CH + a.nt + 1;
+    const int64_t pb = (total + DBLOCK - 1) / DBLOCK, wb = total / DEP_CH + a.nt + 1;
     const unsigned pblocks = (unsigned)(pb < persist ? pb : persist);
     const unsigned wblocks = (unsigned)(wb < persist ? wb : persist);
     const size_t lds = 3 * (size_t)(a.T + 4) * (a.T + 4) * sizeof(unsigned long long);

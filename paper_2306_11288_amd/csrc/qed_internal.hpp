@@ -229,10 +229,11 @@ hipError_t launch_yee(qed_ctx *ctx, float *const g[6], const float *const J[3], 
                       double dx, double dy, double dt, int64_t steps, hipStream_t s);
 // positions and count of a lepton list at the start of a step (qed_deposit.hip)
 hipError_t launch_save_start(qed_ctx *ctx, const qed_leptons &L, double *const x0[3], int64_t *n0, hipStream_t s);
-// current deposition (qed_deposit.hip): leptons [0, *n0) from x0 to their current position
-hipError_t launch_deposit(qed_ctx *ctx, const qed_leptons &L, const double *const x0[3], const int64_t *n0,
-                          float *const J[3], int nx, int ny, double dx, double dy, double gx0, double gy0, double dt,
-                          double qscale, hipStream_t s);
+// current deposition (qed_deposit.hip): for each source, leptons [0, *n0) from x0 to their
+// current position
+constexpr int DEP_MAX_SRC = QED_DEPOSIT_MAX_SRC;
+hipError_t launch_deposit(qed_ctx *ctx, const qed_deposit_src *src, int nsrc, float *const J[3], int nx, int ny,
+                          double dx, double dy, double gx0, double gy0, double dt, double qscale, hipStream_t s);
 // detector histograms (qed_detector.hip)
 hipError_t launch_hist(qed_ctx *ctx, const HistArgs &a, bool photons, int64_t capacity, hipStream_t s);
 // learned sampler (qed_mlp.hip)

@@ -77,7 +77,7 @@ def test_deposit_matches_oracle(charge, gx0, gy0, nx, ny):
     start = (_dev(xa), _dev(ya), _dev(za), torch.tensor([n0], dtype=torch.int64, device="cuda"))
     J = _zeros(ny, nx)
     grid = {"nx": nx, "ny": ny, "dx": dx, "dy": dy, "gx0": gx0, "gy0": gy0}
-    ctx.deposit_current(L, start, grid, J, qs)
+    ctx.deposit_current([(L, start)], grid, J, qs)
     assert ctx.read_status() == 0
     want = D.deposit(xa[:n0], ya[:n0], za[:n0], xb[:n0], yb[:n0], zb[:n0], w[:n0], charge, qs, dt, nx, ny, dx, dy,
                      gx0, gy0)
@@ -90,9 +90,38 @@ def test_deposit_matches_oracle(charge, gx0, gy0, nx, ny):
         assert np.abs(want[c]).max() > 0.3 * scale[c]
         assert np.all(np.abs(got - want[c]) < 1e-6 * scale[c] + 1.2e-7 * np.abs(want[c])), c
     # deposit adds: a second call doubles
-    ctx.deposit_current(L, start, grid, J, qs)
+    ctx.deposit_current([(L, start)], grid, J, qs)
     got2 = J[0].cpu().numpy().astype(np.float64)
     assert np.all(np.abs(got2 - 2 * want[0]) < 2e-6 * scale[0] + 3e-7 * np.abs(want[0]))
+
+
+def test_two_species_in_one_call():
+    """Electrons and positrons (separate lists, each with its own start count) in one call:
+    the oracle's deposit of the two added."""
+    _say("two species")
+    nx, ny, dx, dy, dt, qs = 48, 40, 0.2, 0.25, 0.05, 0.4
+    ctx = Q.Context(dt=dt, procs=Q.PROC_NCS, seed=1, id_start=0, precision=Q.QED_MIXED)
+    srcs, want = [], [np.zeros((ny, nx)) for _ in range(3)]
+    for charge, seed, n, n0 in ((-1, 21, 2500, 2400), (1, 22, 900, 900)):
+        xa, ya, za, xb, yb, zb, w = _random_moves(n, nx, ny, dx, dy, 0.0, 0.0, seed=seed)
+        L = _leptons(xb, yb, zb, w, charge)
+        start = (_dev(xa), _dev(ya), _dev(za), torch.tensor([n0], dtype=torch.int64, device="cuda"))
+        srcs.append((L, start))
+        d = D.deposit(xa[:n0], ya[:n0], za[:n0], xb[:n0], yb[:n0], zb[:n0], w[:n0], charge, qs, dt, nx, ny, dx, dy)
+        for c in range(3):
+            want[c] += d[c]
+    J = _zeros(ny, nx)
+    grid = {"nx": nx, "ny": ny, "dx": dx, "dy": dy, "gx0": 0.0, "gy0": 0.0}
+    ctx.deposit_current(srcs, grid, J, qs)
+    assert ctx.read_status() == 0
+    scale = (qs / (dy * dt), qs / (dx * dt), qs * 0.05 / dt / (dx * dy))
+    for c in range(3):
+        got = J[c].cpu().numpy().astype(np.float64)
+        assert np.all(np.abs(got - want[c]) < 1e-6 * scale[c] + 1.2e-7 * np.abs(want[c])), c
+    with pytest.raises(Q.QedError):
+        ctx.deposit_current([], grid, J, qs)
+    with pytest.raises(Q.QedError):
+        ctx.deposit_current(srcs * 3, grid, J, qs)       # more than four sources
 
 
 def test_dense_cluster_spans_several_chunks():
@@ -112,7 +141,7 @@ def test_dense_cluster_spans_several_chunks():
     start = (_dev(xa), _dev(ya), _dev(za), torch.tensor([n], dtype=torch.int64, device="cuda"))
     J = _zeros(ny, nx)
     grid = {"nx": nx, "ny": ny, "dx": dx, "dy": dy, "gx0": 0.0, "gy0": 0.0}
-    ctx.deposit_current(L, start, grid, J, qs)
+    ctx.deposit_current([(L, start)], grid, J, qs)
     want = D.deposit(xa, ya, za, xb, yb, zb, w, -1, qs, dt, nx, ny, dx, dy)
     for c in range(3):
         got = J[c].cpu().numpy().astype(np.float64)
@@ -131,7 +160,7 @@ def test_direct_path_on_a_grid_too_large_to_tile():
     start = (_dev(xa), _dev(ya), _dev(za), torch.tensor([4000], dtype=torch.int64, device="cuda"))
     J = _zeros(ny, nx)
     grid = {"nx": nx, "ny": ny, "dx": dx, "dy": dy, "gx0": 0.0, "gy0": 0.0}
-    ctx.deposit_current(L, start, grid, J, qs)
+    ctx.deposit_current([(L, start)], grid, J, qs)
     assert ctx.read_status() == 0
     want = D.deposit(xa, ya, za, xb, yb, zb, w, 1, qs, dt, nx, ny, dx, dy)
     qmax = qs * w.max()
@@ -160,10 +189,10 @@ def test_cascade_size_moments_and_continuity():
     ctx.push_spin(Q.whole(spec), L, 100)
     J = _zeros(grid["ny"], grid["nx"])
     qs = 1e-4
-    ctx.deposit_current(L, start, grid, J, qs)
+    ctx.deposit_current([(L, start)], grid, J, qs)
     assert ctx.read_status() == 0
     J2 = _zeros(grid["ny"], grid["nx"])
-    ctx.deposit_current(L, start, grid, J2, qs)
+    ctx.deposit_current([(L, start)], grid, J2, qs)
     for c in range(3):                              # integer sums in the binned path: same bits every run
         assert torch.equal(J[c], J2[c]), c
     xa, ya, za = (t.cpu().numpy() for t in start[:3])
@@ -232,7 +261,7 @@ def test_self_consistent_loop_keeps_gauss_law():
         ctx.push_spin(segs, L, s)
         for j in J:
             j.zero_()
-        ctx.deposit_current(L, start, grid, J, qs)
+        ctx.deposit_current([(L, start)], grid, J, qs)
         ctx.field_advance(spec, dt, 1, current=J)
     assert ctx.read_status() == 0
     F = [c.cpu().numpy().astype(np.float64) for c in comps]
@@ -258,14 +287,14 @@ def test_large_moves_are_skipped_and_flagged():
              torch.tensor([2], dtype=torch.int64, device="cuda"))
     J = _zeros(ny, nx)
     grid = {"nx": nx, "ny": ny, "dx": dx, "dy": dy, "gx0": 0.0, "gy0": 0.0}
-    ctx.deposit_current(L, start, grid, J, 1.0)
+    ctx.deposit_current([(L, start)], grid, J, 1.0)
     assert ctx.read_status() & Q.ST_DEPOSIT
     want = D.deposit([0.5 + 0.1 * dx], [0.5], [0.0], [0.5], [0.5], [0.0], [1.0], -1, 1.0, 0.05, nx, ny, dx, dy)
     assert np.allclose(J[0].cpu().numpy(), want[0], rtol=1e-6, atol=1e-6 * np.abs(want[0]).max())
     ctx.clear_status()
     with pytest.raises(Q.QedError):
-        ctx.deposit_current(L, start, dict(grid, nx=1), J, 1.0)
+        ctx.deposit_current([(L, start)], dict(grid, nx=1), J, 1.0)
     with pytest.raises(Q.QedError):
-        ctx.deposit_current(L, start, dict(grid, dx=0.0), J, 1.0)
+        ctx.deposit_current([(L, start)], dict(grid, dx=0.0), J, 1.0)
     with pytest.raises(Q.QedError):
-        ctx.deposit_current(L, start, grid, J, float("nan"))
+        ctx.deposit_current([(L, start)], grid, J, float("nan"))
