@@ -19,6 +19,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "qed_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+# another build of the same source (e.g. instrumented by sanitizers) can stand in for it
+_LIB_OVERRIDE = os.environ.get("QED_ORACLE_LIB")
 
 PROC_NCS, PROC_NCS_STOKES, PROC_NBW, PROC_VB = 1, 2, 4, 8
 ST_OVERFLOW, ST_NAN, ST_PMAX, ST_EPS_LT1, ST_CLAMP = 1, 2, 4, 8, 16
@@ -33,6 +35,8 @@ A_E = 1.15965218128e-3               # electron anomalous magnetic moment (CODAT
 
 def build(force: bool = False) -> str:
     """Compile the oracle with gcc (-O2, no fast-math)."""
+    if _LIB_OVERRIDE:
+        return _LIB_OVERRIDE
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", _LIB, _SRC, "-lm"])
     return _LIB
@@ -44,8 +48,7 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        build()
-        L = C.CDLL(_LIB)
+        L = C.CDLL(build())
         d, i64, u32, u64, vp = C.c_double, C.c_int64, C.c_uint32, C.c_uint64, C.c_void_p
         dp = C.POINTER(C.c_double)
         sig = {
