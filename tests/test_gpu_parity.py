@@ -190,6 +190,27 @@ def test_status_bits_pmax_clamp_nan():
     assert ctx2.read_status() == 0
 
 
+def test_status_bit_pair_member_below_rest_mass():
+    """Photons of 2.5 m c^2 in a crossed field strong enough that pair creation is certain
+    within the step: an uneven energy split leaves one member below m c^2 (momentum zero,
+    QED_ST_EPS_LT1) and the pair energies still add up to the photon's."""
+    _say("eps < 1")
+    n = 400
+    st = W.photons(n, seed=8, eps0=2.5, eps_rel_spread=0.0, divergence=0.0, x_mean=0, x_sigma=0.1, r_sigma=0.1,
+                   id0=0)
+    spec = {"kind": W.FIELD_CONST, "e0": (0, 8.2e4, 0), "b0": (0, 0, -8.2e4)}   # chi_gamma ~ 1
+    ctx = Q.Context(dt=0.05, procs=Q.PROC_NBW, seed=3, id_start=1 << 40, p_max=10.0)
+    G = Q.Photons.from_state(st)
+    em, ep = Q.Leptons(n, -1), Q.Leptons(n, 1)
+    ctx.step_photons(Q.whole(spec), G, em, ep, 0)
+    assert ctx.read_status() & Q.ST_EPS_LT1
+    assert em.count == ep.count > n // 2
+    e, p = em.to_numpy(), ep.to_numpy()
+    ge = np.sqrt(1 + e["px"] ** 2 + e["py"] ** 2 + e["pz"] ** 2)
+    gp = np.sqrt(1 + p["px"] ** 2 + p["py"] ** 2 + p["pz"] ** 2)
+    assert np.any(ge == 1.0) or np.any(gp == 1.0)                      # a member clamped at rest
+
+
 def test_bitwise_repeatable():
     """The ordered append makes two runs bit-identical (race detector for the scan)."""
     _say("repeatability")
