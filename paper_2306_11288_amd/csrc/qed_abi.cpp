@@ -292,7 +292,7 @@ qed_status qed_init_tables(qed_ctx_t **out, const qed_config *cfg, hipStream_t s
         c->num_cu < 1)
         c->num_cu = 1;
     const bool ok = hipMalloc(&c->tab64, TAB_TOTAL * sizeof(double)) == hipSuccess &&
-                    hipMalloc(&c->tab32, TAB_TOTAL * sizeof(float)) == hipSuccess &&
+                    hipMalloc(&c->tab32, TAB32_TOTAL * sizeof(float)) == hipSuccess &&
                     hipMalloc(&c->status, sizeof(uint32_t)) == hipSuccess &&
                     hipMalloc(&c->next_id, sizeof(unsigned long long)) == hipSuccess &&
                     hipMalloc(&c->tile_counts, MAX_TILES * sizeof(int)) == hipSuccess &&

@@ -32,6 +32,13 @@ constexpr int64_t OFF_VB = OFF_NBW_CDF + 2LL * NDR * NDD;         // [NV][2]  M+
 constexpr int64_t OFF_RAD = OFF_VB + 2 * NV;                      // [NR][4]  g (1+chi)^(4/3),
                                                                   //          psi1..3 (1+chi)^(7/3) / chi^3
 constexpr int64_t TAB_TOTAL = OFF_RAD + 4 * NR;
+// FP32 copy only, after the shared layout: the two spectrum CDFs again with each pair of
+// adjacent rows interleaved, entry [r][col] = {A_r, B_r, A_r+1, B_r+1} (the same rounded
+// values), so an inverse-CDF probe, which mixes rows r and r+1, is one 16-byte load
+constexpr int64_t OFF_NCS_CDF_PAIR = TAB_TOTAL;                                  // [NCR-1][NCT][4]
+constexpr int64_t OFF_NBW_CDF_PAIR = OFF_NCS_CDF_PAIR + 4LL * (NCR - 1) * NCT;  // [NDR-1][NDD][4]
+constexpr int64_t TAB32_TOTAL = OFF_NBW_CDF_PAIR + 4LL * (NDR - 1) * NDD;
+static_assert(TAB_TOTAL % 4 == 0, "paired rows must start 16-byte aligned");
 
 template <class T>
 struct Tabs {
@@ -43,6 +50,9 @@ struct Tabs {
     __device__ __forceinline__ const T *nbw_cdf() const { return base + OFF_NBW_CDF; }
     __device__ __forceinline__ const T *vb() const { return base + OFF_VB; }
     __device__ __forceinline__ const T *rad() const { return base + OFF_RAD; }
+    // FP32 tables only (T = float)
+    __device__ __forceinline__ const float4 *ncs_cdf_pair() const { return (const float4 *)(base + OFF_NCS_CDF_PAIR); }
+    __device__ __forceinline__ const float4 *nbw_cdf_pair() const { return (const float4 *)(base + OFF_NBW_CDF_PAIR); }
 };
 
 // ------------------------------------------------------------------ constants per context

@@ -334,6 +334,16 @@ __global__ void k_to_f32(const double *a, float *b, int64_t n) {
         b[i] = (float)a[i];
 }
 
+// the paired-row copy of an FP32 spectrum CDF: out[r][c] = {A_r, B_r, A_r+1, B_r+1}[c]
+__global__ void k_pair_rows(const float *src, float4 *out, int nrow, int ncol) {
+    const int64_t n = (int64_t)(nrow - 1) * ncol;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = i / ncol, c = i - r * ncol;
+        const float *a = src + 2 * (r * ncol + c), *b = src + 2 * ((r + 1) * ncol + c);
+        out[i] = make_float4(a[0], a[1], b[0], b[1]);
+    }
+}
+
 }  // namespace
 
 hipError_t build_tables(qed_ctx *ctx, hipStream_t s) {
@@ -361,6 +371,10 @@ hipError_t build_tables(qed_ctx *ctx, hipStream_t s) {
     hipLaunchKernelGGL(k_vb, dim3(NV), dim3(256), 0, s, tab, g);
     hipLaunchKernelGGL(k_rad_rate, dim3(NR), dim3(256), 0, s, tab, g);
     hipLaunchKernelGGL(k_to_f32, dim3(1024), dim3(256), 0, s, (const double *)tab, ctx->tab32, TAB_TOTAL);
+    hipLaunchKernelGGL(k_pair_rows, dim3(1024), dim3(256), 0, s, (const float *)(ctx->tab32 + OFF_NCS_CDF),
+                       (float4 *)(ctx->tab32 + OFF_NCS_CDF_PAIR), NCR, NCT);
+    hipLaunchKernelGGL(k_pair_rows, dim3(1024), dim3(256), 0, s, (const float *)(ctx->tab32 + OFF_NBW_CDF),
+                       (float4 *)(ctx->tab32 + OFF_NBW_CDF_PAIR), NDR, NDD);
     e = hipGetLastError();
     const hipError_t e2 = hipStreamSynchronize(s);
     hipFree(scratch);
