@@ -148,33 +148,64 @@ struct ScanArgs {
 };
 constexpr int SCAN_THREADS = 1024, SCAN_UNROLL = 8;
 // One block: exclusive prefix sums of the unit counts and the launch bases.  Each thread
-// owns a contiguous run of units.
+// owns a contiguous run of units; the first SCAN_UNROLL counts of its run stay in
+// registers between the two passes (the whole run when there are at most 8192 units).
+// The per-thread sums are scanned within each wavefront by lane shuffles and across the
+// 16 wavefronts through LDS (one barrier).  The last thread reads the output counts and
+// the id counter at the start, so their latency overlaps the scan.
 __global__ __launch_bounds__(SCAN_THREADS) void k_scan(ScanArgs a) {
-    __shared__ int64_t s_part[SCAN_THREADS];
+    __shared__ int64_t s_wave[SCAN_THREADS / 64];
+    const int tid = (int)threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const bool last = tid == SCAN_THREADS - 1;
+    int64_t base[2] = {0, 0};
+    unsigned long long id0 = 0;
+    if (last) {
+        for (int k = 0; k < 2; ++k) base[k] = a.out_count[k] ? *a.out_count[k] : 0;
+        id0 = *a.next_id;
+    }
     const int64_t n = clamp_count(a.in_count, a.in_capacity);
     const int64_t nunits = (n + a.unit - 1) / a.unit;
     const int64_t per = (nunits + SCAN_THREADS - 1) / SCAN_THREADS;
-    const int64_t lo = threadIdx.x * per, hi = lo + per < nunits ? lo + per : nunits;
+    const int64_t lo = tid * per, hi = lo + per < nunits ? lo + per : nunits;
     // each thread sums its run, SCAN_UNROLL loads in flight
+    int first[SCAN_UNROLL];
+#pragma unroll
+    for (int k = 0; k < SCAN_UNROLL; ++k) first[k] = lo + k < hi ? a.counts[lo + k] : 0;
     int64_t sum = 0;
-    for (int64_t t0 = lo; t0 < hi; t0 += SCAN_UNROLL) {
+#pragma unroll
+    for (int k = 0; k < SCAN_UNROLL; ++k) sum += first[k];
+    for (int64_t t0 = lo + SCAN_UNROLL; t0 < hi; t0 += SCAN_UNROLL) {
         int v[SCAN_UNROLL];
 #pragma unroll
         for (int k = 0; k < SCAN_UNROLL; ++k) v[k] = t0 + k < hi ? a.counts[t0 + k] : 0;
 #pragma unroll
         for (int k = 0; k < SCAN_UNROLL; ++k) sum += v[k];
     }
-    s_part[threadIdx.x] = sum;
-    __syncthreads();
-    // Hillis-Steele inclusive scan of the 1024 partial sums
-    for (int o = 1; o < SCAN_THREADS; o <<= 1) {
-        const int64_t v = (int)threadIdx.x >= o ? s_part[threadIdx.x - o] : 0;
-        __syncthreads();
-        s_part[threadIdx.x] += v;
-        __syncthreads();
+    int64_t incl = sum;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int64_t v = __shfl_up(incl, d);
+        if (lane >= d) incl += v;
     }
-    int64_t run = s_part[threadIdx.x] - sum;
-    for (int64_t t0 = lo; t0 < hi; t0 += SCAN_UNROLL) {
+    if (lane == 63) s_wave[wid] = incl;
+    __syncthreads();
+    int64_t before = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < SCAN_THREADS / 64; ++w) {
+        const int64_t x = s_wave[w];
+        before += w < wid ? x : 0;
+        tot += x;
+    }
+    int64_t run = before + incl - sum;
+#pragma unroll
+    for (int k = 0; k < SCAN_UNROLL; ++k) {
+        if (lo + k < hi) {
+            a.off[lo + k] = run;
+            if (a.clear) a.counts[lo + k] = 0;
+        }
+        run += first[k];
+    }
+    for (int64_t t0 = lo + SCAN_UNROLL; t0 < hi; t0 += SCAN_UNROLL) {
         int v[SCAN_UNROLL];
 #pragma unroll
         for (int k = 0; k < SCAN_UNROLL; ++k) v[k] = t0 + k < hi ? a.counts[t0 + k] : 0;
@@ -187,22 +218,20 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan(ScanArgs a) {
             run += v[k];
         }
     }
-    if (threadIdx.x == SCAN_THREADS - 1) {
-        const int64_t tot = s_part[SCAN_THREADS - 1];
+    if (last) {
         a.off[nunits] = tot;
         uint32_t st = 0;
         for (int k = 0; k < 2; ++k) {
-            const int64_t base = a.out_count[k] ? *a.out_count[k] : 0;
-            a.launch[k] = base;
+            a.launch[k] = base[k];
             if (a.out_count[k]) {
-                const int64_t c = base + tot;
+                const int64_t c = base[k] + tot;
                 if (c > a.out_cap[k]) st |= QED_ST_OVERFLOW;
                 *a.out_count[k] = c < a.out_cap[k] ? c : a.out_cap[k];
             }
         }
-        a.launch[2] = (int64_t)*a.next_id;
+        a.launch[2] = (int64_t)id0;
         a.launch[3] = tot;
-        *a.next_id += (unsigned long long)(a.ids_per_event * tot);
+        *a.next_id = id0 + (unsigned long long)(a.ids_per_event * tot);
         if (st) atomicOr(a.status, st);
     }
 }
