@@ -382,16 +382,13 @@ def run_cascade(args, torch, Q, W):
     start = {"em": ctx.save_start(em), "ep": ctx.save_start(ep)}
 
     def pic_step(s, ev=None):
-        """photons; save the lepton positions; leptons; current; field (the order of the
-        PIC loop: pairs born this step are pushed and deposited from their birth point)"""
+        """save the lepton positions; the QED step in the order of the Spin-QED chain (pairs
+        born this step are pushed and deposited from the next step on); current; field"""
         if ev: ev[0].record()
-        ctx.step_photons(segs, G, em, ep, s)
-        if ev: ev[1].record()
         if deposit:
             ctx.save_start(em, start["em"])
             ctx.save_start(ep, start["ep"])
-        ctx.step_leptons(segs, em, G, s)
-        ctx.step_leptons(segs, ep, G, s)
+        ctx.step(segs, em, ep, G, s)
         if ev: ev[2].record()
         if deposit:
             for j in J:
@@ -409,12 +406,14 @@ def run_cascade(args, torch, Q, W):
     torch.cuda.synchronize()
     counts0 = (em.count, ep.count, G.count)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+    ph_ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ctx.set_photon_events(ph_ev)   # around the photon stage inside each qed_step
     t_ph = t_all = t_f = t_d = 0.0
     t0 = time.perf_counter()
     for s in range(warm, warm + steps):
         pic_step(s, ev)
         torch.cuda.synchronize()
-        t_ph += ev[0].elapsed_time(ev[1])
+        t_ph += ph_ev[0].elapsed_time(ph_ev[1])
         t_all += ev[0].elapsed_time(ev[4])
         t_d += ev[2].elapsed_time(ev[3])
         t_f += ev[3].elapsed_time(ev[4])

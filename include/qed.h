@@ -11,7 +11,9 @@
  *   leptons : field gather (Sec. II.D-E) -> Boris push (Sec. II.A, eqs. boris1-boris6)
  *             -> T-BMT spin rotation (Sec. III.B, eqs. bmteqn, bmt-boris1-4) ->
  *             spin/polarisation-resolved nonlinear Compton emission (Sec. III.C.1)
- * in the order of the paper's Spin-QED chain (Sec. IV; bremsstrahlung is not included).
+ * qed_step runs one whole step with the result of the paper's Spin-QED chain (Sec. IV:
+ * Lorentz push and T-BMT -> vacuum birefringence -> NBW -> NCS; bremsstrahlung is not
+ * included): particles created in step n are first stepped in step n + 1.
  * Around it: the radiative-correction push (Sec. III.A-B, qed_push_radiative), the PIC
  * loop's charge-conserving current deposition and 2D Yee field solver (Sec. II.B-C, F;
  * qed_save_start, qed_deposit_current, qed_field_advance) and detector histograms
@@ -146,20 +148,29 @@ typedef struct {
 } qed_segment;
 
 /* Create a context and build the rate / spectrum / Bessel / birefringence tables on the
- * current device (FP64 quadrature, FP32 copies for QED_MIXED).  Synchronises `stream`.
+ * current device (FP64 quadrature, FP32 copies for QED_MIXED): the NCS rate and photon
+ * spectrum integrals of eqs. (Wspin2) and (F0) (Sec. III.C.1), the NBW rate and pair
+ * spectrum of eqs. (BW), (BWprob) (Sec. III.D), the birefringence coefficients of eq.
+ * (eqnn) (Sec. III.F) and the radiative-correction factors of Sec. III.A.2 and III.B.2.
+ * Synchronises `stream`.  The context owns every table (freed by qed_destroy).
  * Errors: QED_EARG (null pointers, non-positive dt or xi_L, unknown precision),
- * QED_ENOMEM, QED_EHIP.                                                                   */
+ * QED_ENOMEM, QED_EHIP; *ctx_out is NULL then.                                            */
 qed_status qed_init_tables(qed_ctx_t **ctx_out, const qed_config *cfg, hipStream_t stream);
 qed_status qed_destroy(qed_ctx_t *ctx);
 
-/* E6[6 i + (0..5)] = Ex, Ey, Ez, Bx, By, Bz at x_i, t^n (doubles, caller-owned device
- * buffer of 6 * capacity).  Fields of lepton i come from the segment containing i
- * (segments sorted by begin; indices outside every segment see no field).               */
+/* Field gather (Sec. II.D-E: force at the particle from the grid with the TSC weights of
+ * Sec. II.E; or the analytic pulse of qed_field): E6[6 i + (0..5)] = Ex, Ey, Ez, Bx, By, Bz
+ * at x_i, t^n for leptons [0, *count) (doubles, caller-owned device buffer of 6 * capacity,
+ * row per lepton).  Fields of lepton i come from the segment containing i (segments sorted
+ * by begin; indices outside every segment see no field).  Errors: QED_EARG for a NULL
+ * array or E6, bad segments or a capacity outside [0, 2^28].                             */
 qed_status qed_gather(qed_ctx_t *ctx, const qed_segment *segs, int nseg, const qed_leptons *p,
                       double *E6, int64_t step, hipStream_t stream);
-/* Boris push and T-BMT rotation: p^{n-1/2} -> p^{n+1/2}, S^{n-1/2} -> S^{n+1/2},
- * x^n -> x^{n+1}.  Fields from E6 (as written by qed_gather) or, if E6 is NULL, gathered
- * in the same kernel.                                                                    */
+/* Boris push (Sec. II.A, eqs. boris1-boris6, leapfrog of Sec. II.F) and T-BMT rotation
+ * (Sec. III.B, eqs. bmteqn, bmt-boris1-4) of leptons [0, *count), in place:
+ * p^{n-1/2} -> p^{n+1/2}, S^{n-1/2} -> S^{n+1/2}, x^n -> x^{n+1}.  Fields from E6 (as
+ * written by qed_gather) or, if E6 is NULL, gathered in the same kernel.  Momenta and
+ * positions are FP64 in both precisions.  A non-finite result sets QED_ST_NAN.           */
 qed_status qed_push_spin(qed_ctx_t *ctx, const qed_segment *segs, int nseg, qed_leptons *p,
                          const double *E6, int64_t step, hipStream_t stream);
 /* Radiative push (Sec. III.A.3) and radiative T-BMT (Sec. III.B.3): the push of
@@ -176,26 +187,52 @@ qed_status qed_push_spin(qed_ctx_t *ctx, const qed_segment *segs, int nseg, qed_
 enum { QED_RR_LL = 1, QED_RR_MLL = 2, QED_RR_RBMT = 4 };
 qed_status qed_push_radiative(qed_ctx_t *ctx, const qed_segment *segs, int nseg, qed_leptons *p, uint32_t mode,
                               int64_t step, hipStream_t stream);
-/* Nonlinear Compton step for leptons already pushed in this step, using the fields E6 of
- * x^n (required).  Photons are appended to `out` (may be NULL: recoil and spin only).   */
+/* Nonlinear Compton step (Sec. III.C.1: event probability from eq. (Wspin2), photon energy
+ * by inverse CDF of that spectrum, final spin along the SQA of the (w, f, g) form, photon
+ * Stokes from eqs. (F0)-(F3); without an event the no-emission spin update) for leptons
+ * [0, *count) already pushed in this step, using the fields E6 of x^n (required).  Photons
+ * are appended to `out` (may be NULL: recoil and spin only) at x^{n+1}, in lepton order.
+ * Uses the context's staging area (grown with hipMalloc to the list's capacity on first
+ * use).                                                                                  */
 qed_status qed_emit(qed_ctx_t *ctx, const qed_segment *segs, int nseg, qed_leptons *p,
                     const double *E6, qed_photons *out, int64_t step, hipStream_t stream);
-/* Fused gather + push + T-BMT + NCS (the production path): a decide kernel over all
- * leptons, a scan of the event counts and an event kernel over the emitting leptons.   */
+/* Fused gather + push + T-BMT + NCS of leptons [0, *count) (Sec. II.A, II.D-E, III.B,
+ * III.C.1, as qed_gather + qed_push_spin + qed_emit): a decide kernel over all leptons, a
+ * scan of the event counts and an event kernel over the emitting leptons.               */
 qed_status qed_step_leptons(qed_ctx_t *ctx, const qed_segment *segs, int nseg, qed_leptons *p,
                             qed_photons *out, int64_t step, hipStream_t stream);
-/* Photon polarisation transport: basis rotation to E_red and, if QED_PROC_VB, the
- * birefringent phase.  Does not move photons.                                           */
+/* Photon polarisation transport of the live photons [0, *count): rotation of the Stokes
+ * vector to the frame of E_red (Sec. III.C.2, eq. rotation) and, if QED_PROC_VB, the
+ * birefringent phase retardation (Sec. III.F, eqs. eqnn, rotation2; Algorithm 1).  Does
+ * not move photons.                                                                      */
 qed_status qed_birefringence(qed_ctx_t *ctx, const qed_segment *segs, int nseg, qed_photons *g,
                              int64_t step, hipStream_t stream);
-/* Basis rotation, NBW pair creation (if QED_PROC_NBW; pairs appended to em / ep, the
- * photon marked dead) and the straight-line move x += n dt of surviving photons.        */
+/* Basis rotation (eq. rotation), NBW pair creation (Sec. III.D: event probability from eq.
+ * (BWprob), pair energy by inverse CDF of eq. (BW), spins along the axes of eqs.
+ * (BWposAxis), (BWeleAxis); if QED_PROC_NBW: pairs appended to em / ep in photon order at
+ * the photon's position, the photon marked dead) and the straight-line move x += n dt of
+ * surviving photons, for the live photons [0, *count).                                  */
 qed_status qed_pair(qed_ctx_t *ctx, const qed_segment *segs, int nseg, qed_photons *g,
                     qed_leptons *em, qed_leptons *ep, int64_t step, hipStream_t stream);
 /* Whole photon step in one kernel (= qed_birefringence then qed_pair, one rotation). */
 qed_status qed_step_photons(qed_ctx_t *ctx, const qed_segment *segs, int nseg, qed_photons *g,
                             qed_leptons *em, qed_leptons *ep, int64_t step, hipStream_t stream);
-/* Stable compaction of the live photons of `in` into `out` (distinct buffers). */
+/* One whole step of the electrons em, the positrons ep and the photons g (each may be
+ * NULL) with the result of the paper's Spin-QED chain (Sec. IV): Lorentz push and T-BMT of
+ * the leptons alive at the start of the step, VB and NBW of the photons alive at the start
+ * of the step, NCS of the pushed leptons.  Pairs created in the step are placed at their
+ * photon and first pushed, and tested for NCS, in step n + 1; photons emitted in the step
+ * see VB and NBW from step n + 1 on; pair ids precede the step's photon ids.  On the
+ * device the photon stage runs first (it records the lepton counts before its appends)
+ * and the lepton stage covers only the leptons counted then; the two stages touch
+ * disjoint particles, so the outcome is the chain's.  The photon stage needs nseg = 1.
+ * Asynchronous; capturable like the calls it is made of.  Errors as those calls.        */
+qed_status qed_step(qed_ctx_t *ctx, const qed_segment *segs, int nseg, qed_leptons *em, qed_leptons *ep,
+                    qed_photons *g, int64_t step, hipStream_t stream);
+/* Stable compaction of the live photons of `in` into `out` (distinct buffers): `out`
+ * receives them in their order, count = number of live photons (its previous contents and
+ * count are replaced).  Live photons beyond out's capacity are dropped and set
+ * QED_ST_OVERFLOW.                                                                      */
 qed_status qed_compact_photons(qed_ctx_t *ctx, const qed_photons *in, qed_photons *out,
                                hipStream_t stream);
 
@@ -312,13 +349,22 @@ qed_status qed_table_export(qed_ctx_t *ctx, int which, double *host_out, int64_t
  * events belong to the caller (created with hipEventCreate, alive while set); the array
  * is copied.  NULL switches the recording off.                                         */
 qed_status qed_set_step_events(qed_ctx_t *ctx, const hipEvent_t *ev);
+/* Optional timing of the photon stage: with ev non-NULL, every later call that runs the
+ * photon kernels (qed_step, qed_step_photons, qed_pair, qed_birefringence) records ev[0]
+ * before its first photon kernel and ev[1] after its last, on the call's stream.  Events
+ * and lifetime as for qed_set_step_events; NULL switches the recording off.             */
+qed_status qed_set_photon_events(qed_ctx_t *ctx, const hipEvent_t *ev);
 /* Batching and graph capture (many collisions as segments of one list, step loops
  * captured in a hipGraph).  With a device step counter registered, every later call uses
  * step + *dev_step as its step number, so one captured sequence of calls can be replayed
  * for consecutive steps; qed_advance_step adds `by` to the counter on the stream (a kernel,
  * capturable).  dev_step is caller-owned device memory (one int64); NULL unregisters.
  * Calls stay capturable as long as they do not grow the staging area or upload a new
- * segment list: make one call with the same list sizes and segments before capturing.  */
+ * segment list: make one call with the same list sizes and segments before capturing.
+ * Captured graphs read the context's staging area and uploaded segment list in place, so
+ * while a counter is registered a call that would replace the segment list or grow the
+ * staging area is refused with QED_ESTATE (unregister first; graphs captured before such
+ * a change must not be replayed after it).                                              */
 qed_status qed_set_step_counter(qed_ctx_t *ctx, int64_t *dev_step);
 qed_status qed_advance_step(qed_ctx_t *ctx, int64_t by, hipStream_t stream);
 /* Current launch shape / set one (rejects unknown values). */

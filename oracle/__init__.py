@@ -496,9 +496,13 @@ class PhotonArrays:
 
 
 class Sim:
-    """Whole-step driver in the step order of the library:
-    photons (frame rotation, VB, NBW, move) -> electrons (push, spin, NCS) ->
-    positrons (push, spin, NCS)."""
+    """Whole-step driver in the order of the paper's Spin-QED chain (Sec. IV):
+    Lorentz push and T-BMT of the electrons, then the positrons alive at the start of the
+    step -> vacuum birefringence and NBW of the photons alive at the start of the step
+    (frame rotation, VB, pair creation, move) -> NCS of the leptons pushed in this step
+    (electrons, then positrons).  Pairs born by NBW in step n are neither pushed nor
+    tested for NCS before step n + 1; photons born by NCS in step n see VB and NBW from
+    step n + 1 on."""
 
     def __init__(self, *, dt, procs, seed, next_id, p_max=0.1, xi_L=XI_L, alpha=ALPHA, a_e=A_E,
                  tables_obj: Tables | None = None):
@@ -525,8 +529,11 @@ class Sim:
         tab = self.tab if self.tab is not None else tables()
         lib().orc_push_radiative(C.byref(self.cfg), tab.h, C.byref(field), C.byref(s), step, mode)
 
-    def emit(self, L: LeptonArrays, E6: np.ndarray, G: PhotonArrays | None, step: int):
+    def emit(self, L: LeptonArrays, E6: np.ndarray, G: PhotonArrays | None, step: int, count: int | None = None):
+        """NCS of leptons [0, count) (default: all) with the fields E6 of x^n."""
         s = L.ctype()
+        if count is not None:
+            s.count = count
         g = G.ctype() if G is not None else None
         lib().orc_emit(C.byref(self.cfg), self.tab.h if self.tab else None, C.byref(s), _p(E6),
                        C.byref(g) if g is not None else None, step)
@@ -554,12 +561,15 @@ class Sim:
              photon_procs: bool | None = None):
         if photon_procs is None:
             photon_procs = bool(self.cfg.procs & (PROC_NBW | PROC_VB))
-        if G is not None and photon_procs:
-            self.photon_step(field, G, em, ep, step)
-        for L in (em, ep):
+        pushed = []
+        for L in (em, ep):          # Lorentz & T-BMT
             if L is None or L.count == 0:
                 continue
             E6 = np.zeros(6 * L.count)
             self.push_spin(field, L, step, E6)
-            if self.cfg.procs & PROC_NCS:
-                self.emit(L, E6, G, step)
+            pushed.append((L, L.count, E6))
+        if G is not None and photon_procs:   # VB, NBW (pairs appended after the pushed leptons)
+            self.photon_step(field, G, em, ep, step)
+        if self.cfg.procs & PROC_NCS:        # NCS of the leptons pushed above
+            for L, n0, E6 in pushed:
+                self.emit(L, E6, G, step, count=n0)

@@ -23,9 +23,9 @@ TAB_BESSEL, TAB_NCS_RATE, TAB_NCS_CDF, TAB_NBW_RATE, TAB_NBW_CDF, TAB_VB, TAB_RA
 RR_LL, RR_MLL, RR_RBMT = 1, 2, 4
 EXPORTED = ["qed_init_tables", "qed_destroy", "qed_gather", "qed_push_spin", "qed_push_radiative", "qed_emit",
             "qed_step_leptons",
-            "qed_birefringence", "qed_pair", "qed_step_photons", "qed_compact_photons", "qed_read_status",
+            "qed_birefringence", "qed_pair", "qed_step_photons", "qed_step", "qed_compact_photons", "qed_read_status",
             "qed_clear_status", "qed_get_next_id", "qed_set_next_id", "qed_table_size", "qed_table_export",
-            "qed_set_step_events", "qed_set_step_counter", "qed_advance_step", "qed_get_tuning",
+            "qed_set_step_events", "qed_set_photon_events", "qed_set_step_counter", "qed_advance_step", "qed_get_tuning",
             "qed_set_tuning", "qed_autotune", "qed_mlp_init", "qed_mlp_set_params", "qed_mlp_get_params",
             "qed_mlp_samples", "qed_mlp_forward", "qed_mlp_gradient", "qed_mlp_train_step", "qed_set_sampler",
             "qed_sampler_table", "qed_hist_photons", "qed_hist_leptons", "qed_field_advance",
@@ -137,6 +137,7 @@ def lib():
             "qed_birefringence": [vp, vp, C.c_int, vp, i64, vp],
             "qed_pair": [vp, vp, C.c_int, vp, vp, vp, i64, vp],
             "qed_step_photons": [vp, vp, C.c_int, vp, vp, vp, i64, vp],
+            "qed_step": [vp, vp, C.c_int, vp, vp, vp, i64, vp],
             "qed_compact_photons": [vp, vp, vp, vp],
             "qed_read_status": [vp, C.POINTER(C.c_uint32), vp],
             "qed_clear_status": [vp, vp],
@@ -144,6 +145,7 @@ def lib():
             "qed_set_next_id": [vp, C.c_uint64, vp],
             "qed_table_export": [vp, C.c_int, vp, i64],
             "qed_set_step_events": [vp, vp],
+            "qed_set_photon_events": [vp, vp],
             "qed_set_step_counter": [vp, vp],
             "qed_advance_step": [vp, i64, vp],
             "qed_get_tuning": [vp, vp],
@@ -594,19 +596,27 @@ class Context:
         arr = (C.c_void_p * 4)(*[C.c_void_p(e.cuda_event) for e in events])
         self._check(lib().qed_set_step_events(self.h, arr), "qed_set_step_events")
 
+    def set_photon_events(self, events=None):
+        """Record two torch.cuda.Event around the photon kernels of every later photon
+        stage (None switches it off); the events must outlive their use."""
+        if events is None:
+            self._check(lib().qed_set_photon_events(self.h, None), "qed_set_photon_events")
+            return
+        for e in events:
+            if not e.cuda_event:
+                e.record()
+        arr = (C.c_void_p * 2)(*[C.c_void_p(e.cuda_event) for e in events])
+        self._check(lib().qed_set_photon_events(self.h, arr), "qed_set_photon_events")
+
     def table_export(self, which: int) -> np.ndarray:
         n = lib().qed_table_size(which)
         out = np.zeros(n)
         self._check(lib().qed_table_export(self.h, which, out.ctypes.data_as(C.c_void_p), n), "qed_table_export")
         return out
 
-    # whole step in the library's order: photons, then electrons, then positrons
-    def step(self, segs, em: Leptons | None, ep: Leptons | None, G: Photons | None, step: int, stream=None,
-             photon_procs: bool | None = None):
-        if photon_procs is None:
-            photon_procs = bool(self.cfg.procs & (PROC_NBW | PROC_VB))
-        if G is not None and photon_procs:
-            self.step_photons(segs, G, em, ep, step, stream)
-        for L in (em, ep):
-            if L is not None:
-                self.step_leptons(segs, L, G, step, stream)
+    def step(self, segs, em: Leptons | None, ep: Leptons | None, G: Photons | None, step: int, stream=None):
+        """One whole step with the result of the Spin-QED chain (qed_step)."""
+        arr, n = segs
+        self._check(lib().qed_step(self.h, arr, n, C.byref(em.c()) if em else None,
+                                   C.byref(ep.c()) if ep else None, C.byref(G.c()) if G else None, step,
+                                   _stream(stream)), "qed_step")

@@ -141,6 +141,12 @@ qed_status seg_args(qed_ctx *ctx, const qed_segment *segs, int nseg, SegArgs &sa
         std::memcpy(dev.data() + seg_bytes + sizeof(int64_t) * k, &segs[k].begin, sizeof(int64_t));
     }
     if (nseg != ctx->nseg_dev || bytes != ctx->seg_bytes || std::memcmp(ctx->hsegs, dev.data(), head) != 0) {
+        // graphs captured while a device step counter is registered read the uploaded list
+        // in place: replacing it would change (or free) what their replays read
+        if (ctx->step_dev && ctx->nseg_dev > 0)
+            return fail(ctx, QED_ESTATE,
+                        "segments: a different segment list while a device step counter is registered "
+                        "(captured graphs read the uploaded one); unregister the counter first");
         hipError_t e = hipSuccess;
         if (ctx->nseg_dev > 0) e = hipEventSynchronize(ctx->seg_copied);   // host staging reusable
         if (e == hipSuccess && bytes > ctx->seg_cap_bytes) {
@@ -220,6 +226,7 @@ void free_ctx(qed_ctx *c) {
     hipFree(c->group_tot);
     hipFree(c->tile_off);
     hipFree(c->launch);
+    hipFree(c->lep_start);
     hipFree(c->staging);
     hipFree(c->dsegs);
     hipFree(c->mlp_P);
@@ -245,6 +252,13 @@ void free_ctx(qed_ctx *c) {
 // Growing it synchronises the device (hipFree); lists of a fixed size allocate once.
 qed_status ensure_staging(qed_ctx *ctx, int64_t capacity) {
     const int64_t need = ((capacity + BLOCK - 1) / BLOCK) * BLOCK;
+    // graphs captured while a device step counter is registered hold these buffers' addresses
+    if (ctx->step_dev && ((need > ctx->staging_cap && ctx->staging_cap > 0) ||
+                          (ctx->sampler == QED_SAMPLER_MLP && need > ctx->ev_cap && ctx->ev_cap > 0)))
+        return fail(ctx, QED_ESTATE,
+                    "a list of %lld particles would reallocate the event staging area while a device step "
+                    "counter is registered (captured graphs use it); unregister the counter first",
+                    (long long)capacity);
     if (ctx->sampler == QED_SAMPLER_MLP && need > ctx->ev_cap) {   // per-event network inputs / outputs
         hipFree(ctx->ev_in);
         hipFree(ctx->ev_out);
@@ -299,6 +313,7 @@ qed_status qed_init_tables(qed_ctx_t **out, const qed_config *cfg, hipStream_t s
                     hipMalloc(&c->group_tot, GROUP_TOT_LEN * sizeof(int)) == hipSuccess &&
                     hipMalloc(&c->tile_off, (MAX_TILES + 1) * sizeof(int64_t)) == hipSuccess &&
                     hipMalloc(&c->launch, 4 * sizeof(int64_t)) == hipSuccess &&
+                    hipMalloc(&c->lep_start, 2 * sizeof(int64_t)) == hipSuccess &&
                     hipEventCreateWithFlags(&c->seg_copied, hipEventDisableTiming) == hipSuccess;
     if (!ok) {
         free_ctx(c);
@@ -514,6 +529,45 @@ qed_status qed_step_leptons(qed_ctx_t *ctx, const qed_segment *segs, int nseg, q
     if (out && (st = check_photons(ctx, out, "photons")) != QED_OK) return st;
     if ((st = ensure_staging(ctx, p->capacity)) != QED_OK) return st;
     return launched(ctx, launch_leptons(ctx, LM_FUSED, sa, *p, nullptr, out, step, s), "qed_step_leptons");
+}
+
+qed_status qed_step(qed_ctx_t *ctx, const qed_segment *segs, int nseg, qed_leptons *em, qed_leptons *ep,
+                    qed_photons *g, int64_t step, hipStream_t s) {
+    qed_status st = ready(ctx);
+    if (st != QED_OK) return st;
+    if (!em && !ep && !g) return fail(ctx, QED_EARG, "qed_step: no particle list");
+    SegArgs sa{};
+    if ((st = seg_args(ctx, segs, nseg, sa, s)) != QED_OK) return st;
+    if (em && (st = check_leptons(ctx, em, "electrons")) != QED_OK) return st;
+    if (ep && (st = check_leptons(ctx, ep, "positrons")) != QED_OK) return st;
+    if (em && em->charge != -1) return fail(ctx, QED_EARG, "qed_step: em must have charge -1");
+    if (ep && ep->charge != 1) return fail(ctx, QED_EARG, "qed_step: ep must have charge +1");
+    if (g && (st = check_photons(ctx, g, "photons")) != QED_OK) return st;
+    const uint32_t procs = ctx->cfg.procs;
+    const bool photon_stage = g && (procs & (QED_PROC_VB | QED_PROC_NBW));
+    if (photon_stage && nseg != 1) return fail(ctx, QED_EARG, "qed_step: the photon stage takes exactly one segment");
+    int64_t need = 0;
+    for (int64_t c : {em ? em->capacity : 0, ep ? ep->capacity : 0, photon_stage ? g->capacity : 0})
+        need = c > need ? c : need;
+    if ((st = ensure_staging(ctx, need)) != QED_OK) return st;
+    // The photon stage (VB, NBW) runs first on the device: it only touches photons alive at
+    // the start of the step and appends pairs behind the leptons, whose counts before the
+    // append it records; the lepton stage then pushes and tests only those leptons.  The
+    // two stages touch disjoint particles, and the ids come out in the chain's order (pairs,
+    // then NCS photons), so the result is that of the chain push -> VB -> NBW -> NCS.
+    const bool pairs = photon_stage && (procs & QED_PROC_NBW) && (em || ep);
+    if (photon_stage) {
+        const hipError_t e = launch_photons(ctx, PM_FULL, sa, *g, em, ep, step, s, pairs ? ctx->lep_start : nullptr);
+        if (e != hipSuccess) return hip_fail(ctx, e, "qed_step (photons)");
+    }
+    qed_leptons *Ls[2] = {em, ep};
+    for (int k = 0; k < 2; ++k) {
+        if (!Ls[k]) continue;
+        const hipError_t e = launch_leptons(ctx, LM_FUSED, sa, *Ls[k], nullptr, g, step, s,
+                                            pairs ? ctx->lep_start + k : nullptr);
+        if (e != hipSuccess) return hip_fail(ctx, e, "qed_step (leptons)");
+    }
+    return QED_OK;
 }
 
 static qed_status photon_call(qed_ctx *ctx, PhotonMode mode, const qed_segment *segs, int nseg, qed_photons *g,
@@ -854,6 +908,20 @@ qed_status qed_set_sampler(qed_ctx_t *ctx, int sampler) {
     if (sampler == QED_SAMPLER_MLP && !ctx->mlp_P)
         return fail(ctx, QED_ESTATE, "qed_set_sampler: no network (qed_mlp_init or qed_mlp_set_params first)");
     ctx->sampler = sampler;
+    return QED_OK;
+}
+
+qed_status qed_set_photon_events(qed_ctx_t *ctx, const hipEvent_t *ev) {
+    if (!ctx) return QED_EARG;
+    if (!ev) {
+        ctx->ph_ev_on = 0;
+        return QED_OK;
+    }
+    for (int k = 0; k < 2; ++k) {
+        if (!ev[k]) return fail(ctx, QED_EARG, "qed_set_photon_events: event %d is NULL", k);
+        ctx->ph_ev[k] = ev[k];
+    }
+    ctx->ph_ev_on = 1;
     return QED_OK;
 }
 

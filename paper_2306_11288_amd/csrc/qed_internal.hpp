@@ -180,6 +180,7 @@ struct qed_ctx {
                                        // zero between launches (the scan clears what it reads)
     int64_t *tile_off;                 // exclusive prefix of tile_counts [max_tiles + 1]
     int64_t *launch;                   // bases of the last append launch [4]
+    int64_t *lep_start;                // lepton counts before the pair appends of qed_step [2]
     void *staging;                     // one STAGING_SLOT per particle of the largest list seen,
     int64_t staging_cap;               // rounded up to whole tiles
     qed::DevSegment *dsegs;            // device copy of the last multi-segment list
@@ -190,6 +191,8 @@ struct qed_ctx {
     int64_t max_tiles;
     hipEvent_t step_ev[4];             // optional timing events of the NCS launches
     int step_ev_on;
+    hipEvent_t ph_ev[2];               // optional timing events around each photon stage
+    int ph_ev_on;
     int64_t *step_dev;                 // optional device step counter (caller-owned)
     int num_cu;                        // compute units of the device
     qed_tuning tune;                   // launch shape of the lepton step (qed_autotune)
@@ -220,11 +223,15 @@ namespace qed {
 hipError_t build_tables(qed_ctx *ctx, hipStream_t s);
 // launches (qed_kernels.hip)
 enum LeptonMode { LM_GATHER = 0, LM_PUSH = 1, LM_EMIT = 2, LM_FUSED = 3 };
+// n_in (device scalar, optional): the launch covers leptons [0, *n_in) instead of [0, *L.count)
 hipError_t launch_leptons(qed_ctx *ctx, LeptonMode mode, const SegArgs &sa, const qed_leptons &L,
-                          double *E6, const qed_photons *out, int64_t step, hipStream_t s);
+                          double *E6, const qed_photons *out, int64_t step, hipStream_t s,
+                          const int64_t *n_in = nullptr);
 enum PhotonMode { PM_BIREF = 0, PM_PAIR = 1, PM_FULL = 2 };
+// lep_start (device [2], optional): receives the counts of em / ep before the pair appends
 hipError_t launch_photons(qed_ctx *ctx, PhotonMode mode, const SegArgs &sa, const qed_photons &G,
-                          const qed_leptons *em, const qed_leptons *ep, int64_t step, hipStream_t s);
+                          const qed_leptons *em, const qed_leptons *ep, int64_t step, hipStream_t s,
+                          int64_t *lep_start = nullptr);
 hipError_t launch_compact(qed_ctx *ctx, const qed_photons &in, const qed_photons &out, hipStream_t s);
 hipError_t launch_advance_step(int64_t *step, int64_t by, hipStream_t s);
 hipError_t launch_radiative(qed_ctx *ctx, const SegArgs &sa, const qed_leptons &L, uint32_t mode, int64_t step,

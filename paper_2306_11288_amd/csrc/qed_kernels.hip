@@ -143,6 +143,8 @@ struct ScanArgs {
     int64_t out_cap[2];
     unsigned long long *next_id;
     int ids_per_event;        // 0 (compaction), 1 (photon), 2 (pair)
+    int zero_base;            // output lists are replaced, not appended to (compaction)
+    int64_t *base_out;        // optional [2]: receives the output counts before the append
     int64_t *launch;          // [0] out0 base, [1] out1 base, [2] id base, [3] events
     uint32_t *status;
 };
@@ -160,7 +162,7 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan(ScanArgs a) {
     int64_t base[2] = {0, 0};
     unsigned long long id0 = 0;
     if (last) {
-        for (int k = 0; k < 2; ++k) base[k] = a.out_count[k] ? *a.out_count[k] : 0;
+        for (int k = 0; k < 2; ++k) base[k] = (a.out_count[k] && !a.zero_base) ? *a.out_count[k] : 0;
         id0 = *a.next_id;
     }
     const int64_t n = clamp_count(a.in_count, a.in_capacity);
@@ -229,6 +231,8 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan(ScanArgs a) {
                 *a.out_count[k] = c < a.out_cap[k] ? c : a.out_cap[k];
             }
         }
+        if (a.base_out)
+            for (int k = 0; k < 2; ++k) a.base_out[k] = base[k];
         a.launch[2] = (int64_t)id0;
         a.launch[3] = tot;
         *a.next_id = id0 + (unsigned long long)(a.ids_per_event * tot);
@@ -242,6 +246,7 @@ struct LeptonArgs {
     const void *tab;
     SegArgs sa;
     qed_leptons L;
+    const int64_t *n_in;       // optional: process leptons [0, *n_in) (those alive when a step began)
     qed_photons out;
     int has_out;
     double *E6;
@@ -257,6 +262,12 @@ struct LeptonArgs {
     const int64_t *tile_off;
     const int64_t *launch;
 };
+
+// leptons a launch covers: [0, *n_in) when given (the list's count at the start of a
+// whole step, before pairs were appended to it), else the whole list
+__device__ __forceinline__ int64_t lepton_count(const LeptonArgs &a) {
+    return clamp_count(a.n_in ? a.n_in : a.L.count, a.L.capacity);
+}
 
 // push + T-BMT + drift; returns 1/gamma^{n+1/2}
 template <class T>
@@ -275,7 +286,7 @@ __device__ __forceinline__ double push_one(const LeptonArgs &a, double q, double
 // gather and/or push, no NCS: grid-stride loop
 template <class T, bool WRITE_E6, bool PUSH, bool E6_IN, bool MULTI>
 __global__ __launch_bounds__(BLOCK) void k_leptons_simple(LeptonArgs a) {
-    const int64_t n = clamp_count(a.L.count, a.L.capacity);
+    const int64_t n = lepton_count(a);
     const double dt = a.c.dt, t = (double)step_of(a) * dt, q = (double)a.L.charge;
     T *sx = (T *)a.L.sx, *sy = (T *)a.L.sy, *sz = (T *)a.L.sz;
     uint32_t st = 0;
@@ -354,7 +365,7 @@ __device__ __forceinline__ void rbmt_half_kick(T P, const RadCoef<T> &rc, const 
 }
 template <class T, int FK>
 __global__ __launch_bounds__(BLOCK) void k_leptons_radiative(LeptonArgs a, uint32_t mode) {
-    const int64_t n = clamp_count(a.L.count, a.L.capacity);
+    const int64_t n = lepton_count(a);
     const double dt = a.c.dt, t = (double)step_of(a) * dt, q = (double)a.L.charge;
     const Tabs<T> tb = {(const T *)a.tab};
     const uint32_t force = mode & (QED_RR_LL | QED_RR_MLL);
@@ -423,7 +434,7 @@ __global__ __launch_bounds__(BLOCK) void k_leptons_decide(LeptonArgs a) {
     __shared__ int s_wave[2][BLOCK / 64];
     __shared__ T s_rate[RATE_LDS ? 2 * NR : 1];
     // 32-bit indices: lists hold at most 2^28 particles
-    const int n = (int)clamp_count(a.L.count, a.L.capacity);
+    const int n = (int)lepton_count(a);
     const int ntiles = (n + BLOCK - 1) / BLOCK;
     if ((int)blockIdx.x >= ntiles) return;
     const Tabs<T> tb = {(const T *)a.tab};
@@ -487,7 +498,7 @@ enum { EV_FULL = 0, EV_PREP = 1, EV_FINISH = 2 };
 template <class T, int G, int MODE>
 __global__ __launch_bounds__(BLOCK) void k_leptons_events(LeptonArgs a) {
     static_assert(G <= 64, "one group = at most one wave of tiles");
-    const int64_t n = clamp_count(a.L.count, a.L.capacity);
+    const int64_t n = lepton_count(a);
     const int64_t ntiles = (n + BLOCK - 1) / BLOCK;
     const int64_t ngroups = (ntiles + G - 1) / G;
     const int64_t obase = a.launch[0], id0 = a.launch[2];
@@ -750,8 +761,10 @@ static int stride_grid(int64_t cap, int64_t limit) {
 }
 static hipError_t launch_scan(qed_ctx *ctx, const int64_t *in_count, int64_t in_cap, int *counts, int clear,
                               int unit, int64_t *c0, int64_t cap0, int64_t *c1, int64_t cap1, int ids,
-                              hipStream_t s) {
+                              hipStream_t s, int zero_base = 0, int64_t *base_out = nullptr) {
     ScanArgs sa{};
+    sa.zero_base = zero_base;
+    sa.base_out = base_out;
     sa.counts = counts;
     sa.clear = clear;
     sa.off = ctx->tile_off;
@@ -811,7 +824,7 @@ static hipError_t launch_ncs(qed_ctx *ctx, const LeptonArgs &a0, hipStream_t s) 
     if (ctx->tune.rate_lds) hipLaunchKernelGGL((k_leptons_decide<T, PUSH, FK, true>), gd, dim3(BLOCK), 0, s, a);
     else hipLaunchKernelGGL((k_leptons_decide<T, PUSH, FK, false>), gd, dim3(BLOCK), 0, s, a);
     if ((e = hipGetLastError()) != hipSuccess || (e = mark(1)) != hipSuccess) return e;
-    e = launch_scan(ctx, a.L.count, a.L.capacity, ctx->group_tot, 1, BLOCK * a.ev_group,
+    e = launch_scan(ctx, a.n_in ? a.n_in : a.L.count, a.L.capacity, ctx->group_tot, 1, BLOCK * a.ev_group,
                     a.has_out ? a.out.count : nullptr, a.has_out ? a.out.capacity : 0, nullptr, 0, 1, s);
     if (e != hipSuccess || (e = mark(2)) != hipSuccess) return e;
     switch (a.ev_group) {
@@ -860,11 +873,12 @@ static hipError_t launch_leptons_t(qed_ctx *ctx, LeptonMode mode, const LeptonAr
 }
 
 hipError_t launch_leptons(qed_ctx *ctx, LeptonMode mode, const SegArgs &sa, const qed_leptons &L, double *E6,
-                          const qed_photons *out, int64_t step, hipStream_t s) {
+                          const qed_photons *out, int64_t step, hipStream_t s, const int64_t *n_in) {
     LeptonArgs a{};
     a.c = consts_of(ctx);
     a.sa = sa;
     a.L = L;
+    a.n_in = n_in;
     a.has_out = out != nullptr;
     if (out) a.out = *out;
     a.E6 = E6;
@@ -897,7 +911,7 @@ static void launch_photons_decide(const PhotonArgs &a, hipStream_t s) {
         hipLaunchKernelGGL((k_photons_decide<T, true, FK>), dim3(tiles_grid(a.G.capacity)), dim3(BLOCK), 0, s, a);
 }
 template <class T>
-static hipError_t launch_photons_t(qed_ctx *ctx, const PhotonArgs &a, hipStream_t s) {
+static hipError_t launch_photons_stage(qed_ctx *ctx, const PhotonArgs &a, hipStream_t s, int64_t *lep_start) {
     switch (a.field.kind) {
     case QED_FIELD_CONST: launch_photons_decide<T, QED_FIELD_CONST>(a, s); break;
     case QED_FIELD_PW: launch_photons_decide<T, QED_FIELD_PW>(a, s); break;
@@ -907,15 +921,28 @@ static hipError_t launch_photons_t(qed_ctx *ctx, const PhotonArgs &a, hipStream_
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !a.do_nbw) return e;
-    e = launch_scan(ctx, a.G.count, a.G.capacity, ctx->tile_counts, 0, BLOCK, a.has_em ? a.em.count : nullptr, a.has_em ? a.em.capacity : 0,
-                    a.has_ep ? a.ep.count : nullptr, a.has_ep ? a.ep.capacity : 0, 2, s);
+    e = launch_scan(ctx, a.G.count, a.G.capacity, ctx->tile_counts, 0, BLOCK, a.has_em ? a.em.count : nullptr,
+                    a.has_em ? a.em.capacity : 0, a.has_ep ? a.ep.count : nullptr, a.has_ep ? a.ep.capacity : 0, 2, s,
+                    0, lep_start);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_photons_events<T>, dim3(stride_grid(a.G.capacity, 2048)), dim3(BLOCK), 0, s, a);
     return hipGetLastError();
 }
 
+template <class T>
+static hipError_t launch_photons_t(qed_ctx *ctx, const PhotonArgs &a, hipStream_t s, int64_t *lep_start) {
+    if (ctx->ph_ev_on) {
+        const hipError_t e = hipEventRecord(ctx->ph_ev[0], s);
+        if (e != hipSuccess) return e;
+    }
+    hipError_t e = launch_photons_stage<T>(ctx, a, s, lep_start);
+    if (e == hipSuccess && ctx->ph_ev_on) e = hipEventRecord(ctx->ph_ev[1], s);
+    return e;
+}
+
 hipError_t launch_photons(qed_ctx *ctx, PhotonMode mode, const SegArgs &sa, const qed_photons &G,
-                          const qed_leptons *em, const qed_leptons *ep, int64_t step, hipStream_t s) {
+                          const qed_leptons *em, const qed_leptons *ep, int64_t step, hipStream_t s,
+                          int64_t *lep_start) {
     PhotonArgs a{};
     a.c = consts_of(ctx);
     a.field = sa.f0;
@@ -936,10 +963,10 @@ hipError_t launch_photons(qed_ctx *ctx, PhotonMode mode, const SegArgs &sa, cons
     a.launch = ctx->launch;
     if (ctx->cfg.precision == QED_MIXED) {
         a.tab = ctx->tab32;
-        return launch_photons_t<float>(ctx, a, s);
+        return launch_photons_t<float>(ctx, a, s, lep_start);
     }
     a.tab = ctx->tab64;
-    return launch_photons_t<double>(ctx, a, s);
+    return launch_photons_t<double>(ctx, a, s, lep_start);
 }
 
 template <class T>
@@ -988,7 +1015,9 @@ hipError_t launch_compact(qed_ctx *ctx, const qed_photons &in, const qed_photons
     hipLaunchKernelGGL(k_compact_mark, dim3(tiles_grid(in.capacity)), dim3(BLOCK), 0, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    e = launch_scan(ctx, in.count, in.capacity, ctx->tile_counts, 0, BLOCK, out.count, out.capacity, nullptr, 0, 0, s);
+    // the live photons replace the contents of `out` (its count on entry is not a base)
+    e = launch_scan(ctx, in.count, in.capacity, ctx->tile_counts, 0, BLOCK, out.count, out.capacity, nullptr, 0, 0, s,
+                    1);
     if (e != hipSuccess) return e;
     if (ctx->cfg.precision == QED_MIXED)
         hipLaunchKernelGGL(k_compact_copy<float>, dim3(stride_grid(in.capacity, 2048)), dim3(BLOCK), 0, s, a);

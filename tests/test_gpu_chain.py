@@ -1,0 +1,138 @@
+"""The whole step (qed_step) in the order of the Spin-QED chain (Sec. IV), on the GPU
+against the oracle: newborn pairs first pushed and tested in the next step, photons emitted
+in a step untouched by VB and NBW until the next, pair ids before photon ids.  The
+setup makes every NBW and NCS test certain (uniform B, per-step probabilities above one),
+so each ordering rule decides the outcome.  Also: compaction into a list that is not empty
+replaces it; calls that would change what a captured graph reads are refused while a device
+step counter is registered."""
+import ctypes as C
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+import paper_2306_11288_amd as Q  # noqa: E402
+import workloads as W  # noqa: E402
+
+from test_gpu_parity import _close_lep, _close_pho  # noqa: E402
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    Q.lib()
+
+
+def _say(msg):
+    print(f"[gpu-chain] {msg}", flush=True)
+
+
+B0, DT = 206.0, 20.0
+PROCS = oracle.PROC_NCS | oracle.PROC_NCS_STOKES | oracle.PROC_NBW | oracle.PROC_VB
+
+
+def _states():
+    g = 1.0e4
+    pm = math.sqrt(g * g - 1)
+    n = 3
+    lep = {"x": np.zeros(n), "y": np.linspace(0, 1, n), "z": np.zeros(n), "px": np.full(n, pm),
+           "py": np.zeros(n), "pz": np.zeros(n), "w": np.ones(n), "sx": np.zeros(n), "sy": np.zeros(n),
+           "sz": np.ones(n), "id": np.arange(n, dtype=np.uint64)}
+    m = 4
+    pho = {"x": np.full(m, 5.0), "y": np.linspace(-1, 1, m), "z": np.zeros(m), "kx": np.linspace(8e3, 1.2e4, m),
+           "ky": np.zeros(m), "kz": np.zeros(m), "w": np.ones(m), "xi1": np.zeros(m), "xi2": np.zeros(m),
+           "xi3": np.ones(m), "e1x": np.zeros(m), "e1y": np.ones(m), "e1z": np.zeros(m),
+           "id": np.arange(10, 10 + m, dtype=np.uint64)}
+    return lep, pho
+
+
+@pytest.mark.parametrize("prec", [Q.QED_FP64, Q.QED_MIXED])
+def test_chain_order_matches_oracle(prec):
+    _say(f"chain order, precision {prec}")
+    lep, pho = _states()
+    cap = 64
+    em = oracle.LeptonArrays.from_state(lep, capacity=cap, charge=-1)
+    ep = oracle.LeptonArrays.empty(cap, 1)
+    G = oracle.PhotonArrays.from_state(pho, capacity=4 * cap)
+    sim = oracle.Sim(dt=DT, procs=PROCS, seed=9, next_id=100, p_max=1e9)
+    f = oracle.make_field({"kind": oracle.FIELD_CONST, "b0": (0.0, 0.0, B0)})
+    ctx = Q.Context(dt=DT, procs=PROCS, seed=9, id_start=100, precision=prec, p_max=1e9)
+    emg = Q.Leptons.from_state(lep, capacity=cap, charge=-1, precision=prec)
+    epg = Q.Leptons(cap, 1, precision=prec)
+    Gg = Q.Photons.from_state(pho, capacity=4 * cap, precision=prec)
+    segs = Q.whole({"kind": Q.FIELD_CONST, "b0": (0.0, 0.0, B0)})
+    for s in (5, 6, 7):
+        n_em, n_ep = em.count, ep.count
+        sim.step(f, em, ep, G, s)
+        ctx.step(segs, emg, epg, Gg, s)
+        if s == 5:   # every photon converted; no newborn lepton moved or emitted
+            assert em.count == n_em + 4 and ep.count == 4 and G.count == 4 + n_em
+        if prec == Q.QED_FP64:
+            _close_lep(emg.to_numpy(), em.view(), what=f"electrons step {s}")
+            _close_lep(epg.to_numpy(), ep.view(), what=f"positrons step {s}")
+            _close_pho(Gg.to_numpy(), G.view(), what=f"photons step {s}")
+        else:   # same decisions, ids and birth positions; values to single precision
+            a, b = Gg.to_numpy(), G.view()
+            assert np.array_equal(a["id"], b["id"]) and np.array_equal(a["alive"], b["alive"])
+            for L, O in ((emg, em), (epg, ep)):
+                x, y = L.to_numpy(), O.view()
+                assert np.array_equal(x["id"], y["id"])
+                assert np.max(np.abs(x["px"] - y["px"]) / np.abs(y["px"])) < 1e-4
+    assert ctx.next_id() == sim.next_id
+
+
+def test_compaction_replaces_a_non_empty_destination():
+    """ADVICE: compaction into a list that already holds photons must replace it (count =
+    live photons, contents from index 0), as the oracle's compaction does."""
+    _say("compaction into a non-empty list")
+    st = W.photons(3000, seed=44, eps0=3000.0, eps_rel_spread=0.2, divergence=2e-3, x_mean=-2.0, x_sigma=1.0,
+                   r_sigma=1.0, id0=0)
+    st["alive"] = (np.arange(3000) % 3 != 1).astype(np.uint8)
+    ctx = Q.Context(dt=0.01, procs=15, seed=1, id_start=1 << 40)
+    Gs = Q.Photons.from_state(st)
+    Gd = Q.Photons(4000)
+    ctx.compact_photons(Gs, Gd)
+    first = Gd.to_numpy()
+    assert Gd.count == 2000
+    ctx.compact_photons(Gs, Gd)    # destination now holds 2000 photons
+    assert Gd.count == 2000
+    second = Gd.to_numpy()
+    for k in first:
+        assert np.array_equal(first[k], second[k]), k
+    G = oracle.PhotonArrays.from_state(st)
+    oracle.Sim(dt=0.01, procs=15, seed=1, next_id=0).compact(G)
+    _close_pho(second, G.view(), what="compacted")
+
+
+def test_capture_safety_refusals():
+    """While a device step counter is registered, a different segment list or a list that
+    would grow the staging area is refused with QED_ESTATE (captured graphs read both in
+    place); after unregistering, both go through."""
+    _say("graph safety refusals")
+    cfg = W.c4(4, n_min=1e3, n_max=1e4, start_step=100)
+    ctx = Q.Context(dt=cfg["dt"], procs=cfg["procs"], seed=cfg["seed"], id_start=cfg["next_id"],
+                    precision=Q.QED_MIXED)
+    L = Q.Leptons.from_state(cfg["leptons"], precision=Q.QED_MIXED)
+    G = Q.Photons(len(cfg["leptons"]["x"]), precision=Q.QED_MIXED)
+    segs = Q.segments(cfg["segments"])
+    ctr = torch.zeros(1, dtype=torch.int64, device="cuda")
+    ctx.set_step_counter(ctr)
+    ctx.step_leptons(segs, L, G, 10)                 # first upload, staging sized
+    other = list(cfg["segments"])
+    b0, e0, f0 = other[0]
+    other[0] = (b0, e0, dict(f0, a0=f0["a0"] * 1.5))
+    with pytest.raises(Q.QedError) as e:
+        ctx.step_leptons(Q.segments(other), L, G, 11)
+    assert "step counter" in str(e.value)
+    big = Q.Leptons(4 * len(cfg["leptons"]["x"]), -1, precision=Q.QED_MIXED)
+    with pytest.raises(Q.QedError):
+        ctx.step_leptons(segs, big, G, 11)
+    ctx.set_step_counter(None)
+    ctx.step_leptons(Q.segments(other), L, G, 11)
+    ctx.step_leptons(segs, big, G, 11)
+    torch.cuda.synchronize()
