@@ -173,6 +173,18 @@ qed_status qed_gather(qed_ctx_t *ctx, const qed_segment *segs, int nseg, const q
  * positions are FP64 in both precisions.  A non-finite result sets QED_ST_NAN.           */
 qed_status qed_push_spin(qed_ctx_t *ctx, const qed_segment *segs, int nseg, qed_leptons *p,
                          const double *E6, int64_t step, hipStream_t stream);
+/* qed_step_leptons for callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the same kernels and results,
+ * with the event staging and scan work memory in a fixed device array of the library
+ * (about 76 MB on every GPU the library runs on, held until the process ends) instead of
+ * context-owned buffers.  Nothing is allocated or freed.  Limits: exactly one segment,
+ * p->capacity <= QED_NOALLOC_MAX_LEPTONS (QED_EARG otherwise), the table sampler
+ * (QED_ESTATE with the learned sampler), the context's device current.  All calls on one
+ * GPU share that array: calls that overlap on one GPU (other streams, other contexts,
+ * other host threads) race and must not be made.                                       */
+#define QED_NOALLOC_MAX_LEPTONS 524288
+qed_status qed_step_leptons_noalloc(qed_ctx_t *ctx, const qed_segment *segs, int nseg, qed_leptons *p,
+                                    qed_photons *out, int64_t step, hipStream_t stream);
 /* Radiative push (Sec. III.A.3) and radiative T-BMT (Sec. III.B.3): the push of
  * qed_push_spin (fields gathered in the kernel) with, at the time-centred gamma^n =
  * sqrt(1+|p-|^2), beta^n = (p- + p+)/(2 gamma^n) and chi^n,

@@ -22,7 +22,7 @@ FIELD_NONE, FIELD_CONST, FIELD_PW, FIELD_GAUSS, FIELD_GRID2D = 0, 1, 2, 3, 4
 TAB_BESSEL, TAB_NCS_RATE, TAB_NCS_CDF, TAB_NBW_RATE, TAB_NBW_CDF, TAB_VB, TAB_RAD = range(7)
 RR_LL, RR_MLL, RR_RBMT = 1, 2, 4
 EXPORTED = ["qed_init_tables", "qed_destroy", "qed_gather", "qed_push_spin", "qed_push_radiative", "qed_emit",
-            "qed_step_leptons",
+            "qed_step_leptons", "qed_step_leptons_noalloc",
             "qed_birefringence", "qed_pair", "qed_step_photons", "qed_step", "qed_compact_photons", "qed_read_status",
             "qed_clear_status", "qed_get_next_id", "qed_set_next_id", "qed_table_size", "qed_table_export",
             "qed_set_step_events", "qed_set_photon_events", "qed_set_step_counter", "qed_advance_step", "qed_get_tuning",
@@ -32,6 +32,7 @@ EXPORTED = ["qed_init_tables", "qed_destroy", "qed_gather", "qed_push_spin", "qe
             "qed_deposit_current", "qed_save_start", "qed_last_error"]
 
 MLP_NPARAM = 34051
+NOALLOC_MAX_LEPTONS = 524288
 SAMPLER_TABLE, SAMPLER_MLP = 0, 1
 
 ALPHA = 1.0 / 137.035999084
@@ -134,6 +135,7 @@ def lib():
             "qed_hist_leptons": [vp, vp, i64, vp, vp, vp],
             "qed_emit": [vp, vp, C.c_int, vp, vp, vp, i64, vp],
             "qed_step_leptons": [vp, vp, C.c_int, vp, vp, i64, vp],
+            "qed_step_leptons_noalloc": [vp, vp, C.c_int, vp, vp, i64, vp],
             "qed_birefringence": [vp, vp, C.c_int, vp, i64, vp],
             "qed_pair": [vp, vp, C.c_int, vp, vp, vp, i64, vp],
             "qed_step_photons": [vp, vp, C.c_int, vp, vp, vp, i64, vp],
@@ -451,6 +453,12 @@ class Context:
         o = C.byref(out.c()) if out is not None else None
         self._check(lib().qed_step_leptons(self.h, arr, n, C.byref(L.c()), o, step, _stream(stream)),
                     "qed_step_leptons")
+
+    def step_leptons_noalloc(self, segs, L: Leptons, out: Photons | None, step: int, stream=None):
+        arr, n = segs
+        o = C.byref(out.c()) if out is not None else None
+        self._check(lib().qed_step_leptons_noalloc(self.h, arr, n, C.byref(L.c()), o, step, _stream(stream)),
+                    "qed_step_leptons_noalloc")
 
     def birefringence(self, segs, G: Photons, step: int, stream=None):
         arr, n = segs

@@ -332,6 +332,9 @@ qed_status qed_init_tables(qed_ctx_t **out, const qed_config *cfg, hipStream_t s
         free_ctx(c);
         return QED_EHIP;
     }
+    // the allocation-free step's scratch array on this device (address taken once per
+    // device); a failure here only disables that entry point
+    if (noalloc_scratch(&c->na_scratch) != hipSuccess) c->na_scratch = nullptr;
     *out = c;
     return QED_OK;
 }
@@ -568,6 +571,31 @@ qed_status qed_step(qed_ctx_t *ctx, const qed_segment *segs, int nseg, qed_lepto
         if (e != hipSuccess) return hip_fail(ctx, e, "qed_step (leptons)");
     }
     return QED_OK;
+}
+
+qed_status qed_step_leptons_noalloc(qed_ctx_t *ctx, const qed_segment *segs, int nseg, qed_leptons *p,
+                                    qed_photons *out, int64_t step, hipStream_t s) {
+    qed_status st = ready(ctx);
+    if (st != QED_OK) return st;
+    if (nseg != 1) return fail(ctx, QED_EARG, "qed_step_leptons_noalloc: exactly one segment");
+    SegArgs sa{};
+    if ((st = seg_args(ctx, segs, nseg, sa, s)) != QED_OK) return st;
+    if ((st = check_leptons(ctx, p, "leptons")) != QED_OK) return st;
+    if (out && (st = check_photons(ctx, out, "photons")) != QED_OK) return st;
+    if (p->capacity > NOALLOC_MAX)
+        return fail(ctx, QED_EARG, "qed_step_leptons_noalloc: capacity %lld above the limit of %lld leptons",
+                    (long long)p->capacity, (long long)NOALLOC_MAX);
+    if (ctx->sampler == QED_SAMPLER_MLP)
+        return fail(ctx, QED_ESTATE, "qed_step_leptons_noalloc: the learned sampler needs allocated buffers");
+    if (!ctx->na_scratch)
+        return fail(ctx, QED_ESTATE, "qed_step_leptons_noalloc: no scratch address for this device");
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != ctx->device)
+        return fail(ctx, QED_ESTATE, "qed_step_leptons_noalloc: the context's device is not current");
+    const ScanState ss = noalloc_state(ctx->na_scratch);
+    hipError_t e = noalloc_clear(ss, s);
+    if (e == hipSuccess) e = launch_leptons(ctx, LM_FUSED, sa, *p, nullptr, out, step, s, nullptr, &ss);
+    return launched(ctx, e, "qed_step_leptons_noalloc");
 }
 
 static qed_status photon_call(qed_ctx *ctx, PhotonMode mode, const qed_segment *segs, int nseg, qed_photons *g,

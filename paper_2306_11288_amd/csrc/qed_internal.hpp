@@ -181,6 +181,7 @@ struct qed_ctx {
     int64_t *tile_off;                 // exclusive prefix of tile_counts [max_tiles + 1]
     int64_t *launch;                   // bases of the last append launch [4]
     int64_t *lep_start;                // lepton counts before the pair appends of qed_step [2]
+    void *na_scratch;                  // device address of this device's allocation-free scratch array
     void *staging;                     // one STAGING_SLOT per particle of the largest list seen,
     int64_t staging_cap;               // rounded up to whole tiles
     qed::DevSegment *dsegs;            // device copy of the last multi-segment list
@@ -219,14 +220,31 @@ struct qed_ctx {
 };
 
 namespace qed {
+// the work memory of one ordered-append launch sequence (decide -> scan -> events)
+struct ScanState {
+    void *staging;         // one STAGING_SLOT per particle
+    int *tile_counts;      // events per tile
+    int *group_tot;        // events per event group (zero between launches)
+    int64_t *tile_off;     // exclusive prefix of the counts
+    int64_t *launch;       // bases of the launch [4]
+};
 // table construction (qed_tables.hip); returns hipSuccess or the first HIP error
 hipError_t build_tables(qed_ctx *ctx, hipStream_t s);
 // launches (qed_kernels.hip)
 enum LeptonMode { LM_GATHER = 0, LM_PUSH = 1, LM_EMIT = 2, LM_FUSED = 3 };
 // n_in (device scalar, optional): the launch covers leptons [0, *n_in) instead of [0, *L.count)
+// ss (optional): work memory to use instead of the context's
 hipError_t launch_leptons(qed_ctx *ctx, LeptonMode mode, const SegArgs &sa, const qed_leptons &L,
                           double *E6, const qed_photons *out, int64_t step, hipStream_t s,
-                          const int64_t *n_in = nullptr);
+                          const int64_t *n_in = nullptr, const ScanState *ss = nullptr);
+// allocation-free lepton step (qed_noalloc.hip): the file-scope scratch array of the current
+// device (its address taken once per device), its size limit, and the clearing of the
+// part that must start at zero
+constexpr int64_t NOALLOC_MAX = QED_NOALLOC_MAX_LEPTONS;   // leptons per call
+static_assert(NOALLOC_MAX % BLOCK == 0, "whole tiles");
+hipError_t noalloc_scratch(void **ptr);
+ScanState noalloc_state(void *scratch);
+hipError_t noalloc_clear(const ScanState &ss, hipStream_t s);
 enum PhotonMode { PM_BIREF = 0, PM_PAIR = 1, PM_FULL = 2 };
 // lep_start (device [2], optional): receives the counts of em / ep before the pair appends
 hipError_t launch_photons(qed_ctx *ctx, PhotonMode mode, const SegArgs &sa, const qed_photons &G,

@@ -761,13 +761,14 @@ static int stride_grid(int64_t cap, int64_t limit) {
 }
 static hipError_t launch_scan(qed_ctx *ctx, const int64_t *in_count, int64_t in_cap, int *counts, int clear,
                               int unit, int64_t *c0, int64_t cap0, int64_t *c1, int64_t cap1, int ids,
-                              hipStream_t s, int zero_base = 0, int64_t *base_out = nullptr) {
+                              hipStream_t s, int zero_base = 0, int64_t *base_out = nullptr,
+                              int64_t *off = nullptr, int64_t *launch = nullptr) {
     ScanArgs sa{};
     sa.zero_base = zero_base;
     sa.base_out = base_out;
     sa.counts = counts;
     sa.clear = clear;
-    sa.off = ctx->tile_off;
+    sa.off = off ? off : ctx->tile_off;
     sa.unit = unit;
     sa.in_count = in_count;
     sa.in_capacity = in_cap;
@@ -777,7 +778,7 @@ static hipError_t launch_scan(qed_ctx *ctx, const int64_t *in_count, int64_t in_
     sa.out_cap[1] = cap1;
     sa.next_id = ctx->next_id;
     sa.ids_per_event = ids;
-    sa.launch = ctx->launch;
+    sa.launch = launch ? launch : ctx->launch;
     sa.status = ctx->status;
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(SCAN_THREADS), 0, s, sa);
     return hipGetLastError();
@@ -824,8 +825,9 @@ static hipError_t launch_ncs(qed_ctx *ctx, const LeptonArgs &a0, hipStream_t s) 
     if (ctx->tune.rate_lds) hipLaunchKernelGGL((k_leptons_decide<T, PUSH, FK, true>), gd, dim3(BLOCK), 0, s, a);
     else hipLaunchKernelGGL((k_leptons_decide<T, PUSH, FK, false>), gd, dim3(BLOCK), 0, s, a);
     if ((e = hipGetLastError()) != hipSuccess || (e = mark(1)) != hipSuccess) return e;
-    e = launch_scan(ctx, a.n_in ? a.n_in : a.L.count, a.L.capacity, ctx->group_tot, 1, BLOCK * a.ev_group,
-                    a.has_out ? a.out.count : nullptr, a.has_out ? a.out.capacity : 0, nullptr, 0, 1, s);
+    e = launch_scan(ctx, a.n_in ? a.n_in : a.L.count, a.L.capacity, a.group_tot, 1, BLOCK * a.ev_group,
+                    a.has_out ? a.out.count : nullptr, a.has_out ? a.out.capacity : 0, nullptr, 0, 1, s, 0, nullptr,
+                    const_cast<int64_t *>(a.tile_off), const_cast<int64_t *>(a.launch));
     if (e != hipSuccess || (e = mark(2)) != hipSuccess) return e;
     switch (a.ev_group) {
     case 4: e = launch_events<T, 4>(ctx, a, s); break;
@@ -873,7 +875,8 @@ static hipError_t launch_leptons_t(qed_ctx *ctx, LeptonMode mode, const LeptonAr
 }
 
 hipError_t launch_leptons(qed_ctx *ctx, LeptonMode mode, const SegArgs &sa, const qed_leptons &L, double *E6,
-                          const qed_photons *out, int64_t step, hipStream_t s, const int64_t *n_in) {
+                          const qed_photons *out, int64_t step, hipStream_t s, const int64_t *n_in,
+                          const ScanState *ss) {
     LeptonArgs a{};
     a.c = consts_of(ctx);
     a.sa = sa;
@@ -885,12 +888,11 @@ hipError_t launch_leptons(qed_ctx *ctx, LeptonMode mode, const SegArgs &sa, cons
     a.step = step;
     a.step_dev = ctx->step_dev;
     a.status = ctx->status;
-    a.stg = (EventRec *)ctx->staging;
-    a.tile_counts = ctx->tile_counts;
-    a.group_tot = ctx->group_tot;
-    a.tile_off = ctx->tile_off;
-    a.launch = ctx->launch;
-    a.step_dev = ctx->step_dev;
+    a.stg = (EventRec *)(ss ? ss->staging : ctx->staging);
+    a.tile_counts = ss ? ss->tile_counts : ctx->tile_counts;
+    a.group_tot = ss ? ss->group_tot : ctx->group_tot;
+    a.tile_off = ss ? ss->tile_off : ctx->tile_off;
+    a.launch = ss ? ss->launch : ctx->launch;
     a.ev_in = ctx->ev_in;
     a.ev_out = ctx->ev_out;
     const bool multi = sa.nseg > 1;
