@@ -352,14 +352,64 @@ CASCADE_QSCALE = 1e-4
 BYTES_PHOTON_STEP = {"mixed": 24 + 24 + 12 + 12 + 8 + 1 + 24 + 12 + 12, "fp64": 24 + 24 + 24 + 24 + 8 + 1 + 24 + 24 + 24}
 
 
-def run_cascade(args, torch, Q, W):
-    """Cascade on a 2D Yee grid (2048 x 512 cells, 40 per wavelength, fp32 fields of a
-    linearly polarised a0 = 300 pulse filled at t = 0): 1e6 electrons at gamma 4000 emit
+def cascade_summary(em, ep, G, gamma0, torch):
+    """Histograms and means of one cascade run's final lists (for the error metrics)."""
+    def hist(x, lo, hi, bins):
+        h = torch.histc(x.float(), bins=bins, min=lo, max=hi).double()
+        return h / max(float(h.sum()), 1.0)
+
+    out = {}
+    for name, L in (("electron", em), ("positron", ep)):
+        n = L.count
+        p = torch.stack([L.px[:n], L.py[:n], L.pz[:n]]).double()
+        e = torch.sqrt(1 + (p * p).sum(0))
+        out[name + "_count"] = n
+        out[name + "_mean_energy"] = float(e.mean()) if n else 0.0
+        out[name + "_mean_spin"] = (torch.stack([L.sx[:n], L.sy[:n], L.sz[:n]]).double().mean(1).cpu()
+                                    if n else torch.zeros(3, dtype=torch.float64))
+        out[name + "_theta_y"] = hist(torch.atan2(p[1], p[0]), -math.pi, math.pi, 200)
+    n = G.count
+    k = torch.stack([G.kx[:n], G.ky[:n], G.kz[:n]]).double()
+    w = torch.sqrt((k * k).sum(0))
+    out["photon_count"] = n
+    out["photon_spectrum"] = hist(torch.log10((w / gamma0).clamp_min(1e-300)), -5.0, 0.0, 100)
+    out["photon_theta_y"] = hist(torch.atan2(k[1], k[0]), -math.pi, math.pi, 200)
+    out["photon_xi_detector"] = detector_stokes(G, 0, torch).mean(1).cpu()
+    out["photons_alive"] = int(G.alive[:n].sum())
+    return out
+
+
+# difference metrics of the cascade (mixed against FP64, or FP64 between two seeds)
+CASCADE_DIFF = ("electron_mean_energy_rel", "positron_count_rel", "positron_mean_energy_rel", "photon_count_rel",
+                "photon_spectrum_L1", "electron_theta_y_L1", "photon_theta_y_L1", "electron_mean_spin_abs_diff",
+                "positron_mean_spin_abs_diff", "photon_xi2_abs_diff", "photon_xi3_abs_diff")
+
+
+def cascade_metrics(a, b):
+    rel = lambda x, y: abs(x / y - 1) if y else abs(x - y)
+    l1 = lambda h1, h2: float((h1 - h2).abs().sum())
+    return {"electron_mean_energy_rel": rel(b["electron_mean_energy"], a["electron_mean_energy"]),
+            "positron_count_rel": rel(b["positron_count"], a["positron_count"]),
+            "positron_mean_energy_rel": rel(b["positron_mean_energy"], a["positron_mean_energy"]),
+            "photon_count_rel": rel(b["photon_count"], a["photon_count"]),
+            "photon_spectrum_L1": l1(a["photon_spectrum"], b["photon_spectrum"]),
+            "electron_theta_y_L1": l1(a["electron_theta_y"], b["electron_theta_y"]),
+            "photon_theta_y_L1": l1(a["photon_theta_y"], b["photon_theta_y"]),
+            "electron_mean_spin_abs_diff": float((a["electron_mean_spin"] - b["electron_mean_spin"]).norm()),
+            "positron_mean_spin_abs_diff": float((a["positron_mean_spin"] - b["positron_mean_spin"]).norm()),
+            "photon_xi2_abs_diff": abs(float(a["photon_xi_detector"][1] - b["photon_xi_detector"][1])),
+            "photon_xi3_abs_diff": abs(float(a["photon_xi_detector"][2] - b["photon_xi_detector"][2]))}
+
+
+def cascade_once(args, torch, Q, W, prec, seed_offset=0, timed=True):
+    """One cascade run on a 2D Yee grid (2048 x 512 cells, 40 per wavelength, fp32 fields of
+    a linearly polarised a0 = 300 pulse filled at t = 0): 1e6 electrons at gamma 4000 emit
     photons (NCS + Stokes), photons rotate their Stokes basis, evolve by vacuum
-    birefringence and create pairs (NBW); electrons, positrons and photons all stepped, the
-    leptons' current deposited and the field advanced by the Yee solver (open x boundaries)
-    every step (the PIC loop; --no-deposit: vacuum solver, --static-grid: the snapshot at
-    t = 0).  A warm-up builds the photon population, then the timed steps."""
+    birefringence and create pairs (NBW); electrons, positrons and photons all stepped in
+    the order of the Spin-QED chain (qed_step), the leptons' current deposited and the field
+    advanced by the Yee solver (open x boundaries) every step (the PIC loop; --no-deposit:
+    vacuum solver, --static-grid: the snapshot at t = 0).  A warm-up builds the photon
+    population, then the timed steps."""
     cfg = W.c3()
     grid, pulse = cfg["grid"], dict(cfg["pulse"])
     pulse["phi_start"] = -pulse["ncycles"] * math.pi          # pulse centre at x = 0 for t = 0
@@ -368,23 +418,35 @@ def run_cascade(args, torch, Q, W):
     n = len(cfg["leptons"]["x"])
     st = dict(cfg["leptons"])
     st["x"] = st["x"] - st["x"].mean()                          # bunch at the pulse centre
-    prec = Q.QED_MIXED
-    ctx = Q.Context(dt=cfg["dt"], procs=cfg["procs"], seed=cfg["seed"], id_start=cfg["next_id"], precision=prec)
+    precision = Q.QED_MIXED if prec == "mixed" else Q.QED_FP64
+    ctx = Q.Context(dt=cfg["dt"], procs=cfg["procs"], seed=cfg["seed"] + seed_offset, id_start=cfg["next_id"],
+                    precision=precision)
     cap_g, cap_l = 20_000_000, 4_000_000
-    em = Q.Leptons.from_state(st, capacity=cap_l, charge=-1, precision=prec)
-    ep = Q.Leptons(cap_l, 1, precision=prec)
-    G = Q.Photons(cap_g, precision=prec)
+    lists = {"em": Q.Leptons.from_state(st, capacity=cap_l, charge=-1, precision=precision),
+             "ep": Q.Leptons(cap_l, 1, precision=precision), "G": Q.Photons(cap_g, precision=precision)}
+    sort_every = args.sort_every
+    spare = ({"em": Q.Leptons(cap_l, -1, precision=precision), "ep": Q.Leptons(cap_l, 1, precision=precision),
+              "G": Q.Photons(cap_g, precision=precision)} if sort_every > 0 else None)
     segs = Q.whole(spec)
     warm, steps = args.cascade_warmup, args.cascade_steps
     solver = not args.static_grid
     deposit = solver and not args.no_deposit
     J = [torch.zeros((grid["ny"], grid["nx"]), dtype=torch.float32, device="cuda") for _ in range(3)]
-    start = {"em": ctx.save_start(em), "ep": ctx.save_start(ep)}
+    start = {"em": ctx.save_start(lists["em"]), "ep": ctx.save_start(lists["ep"])}
 
     def pic_step(s, ev=None):
-        """save the lepton positions; the QED step in the order of the Spin-QED chain (pairs
-        born this step are pushed and deposited from the next step on); current; field"""
+        """every sort_every steps, the lists reordered by grid bin (4 x 4 cells; dead photons
+        dropped); save the lepton positions; the QED step in the order of the Spin-QED chain
+        (pairs born this step are pushed and deposited from the next step on); current; field"""
         if ev: ev[0].record()
+        if sort_every > 0 and s % sort_every == 0:
+            ctx.sort_photons(lists["G"], spare["G"], spec, 4)
+            ctx.sort_leptons(lists["em"], spare["em"], spec, 4)
+            ctx.sort_leptons(lists["ep"], spare["ep"], spec, 4)
+            for k in lists:
+                lists[k], spare[k] = spare[k], lists[k]
+        if ev: ev[1].record()
+        em, ep, G = lists["em"], lists["ep"], lists["G"]
         if deposit:
             ctx.save_start(em, start["em"])
             ctx.save_start(ep, start["ep"])
@@ -404,53 +466,103 @@ def run_cascade(args, torch, Q, W):
     for s in range(warm):
         pic_step(s)
     torch.cuda.synchronize()
-    counts0 = (em.count, ep.count, G.count)
+    # launch shape of the lepton step for these lists (far below their capacity)
+    tuning = ctx.autotune(segs, lists["em"], warm, reps=2)
+    counts0 = tuple(lists[k].count for k in ("em", "ep", "G"))
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
     ph_ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     ctx.set_photon_events(ph_ev)   # around the photon stage inside each qed_step
-    t_ph = t_all = t_f = t_d = 0.0
+    t_ph = t_all = t_f = t_d = t_sort = 0.0
     t0 = time.perf_counter()
     for s in range(warm, warm + steps):
-        pic_step(s, ev)
-        torch.cuda.synchronize()
-        t_ph += ph_ev[0].elapsed_time(ph_ev[1])
-        t_all += ev[0].elapsed_time(ev[4])
-        t_d += ev[2].elapsed_time(ev[3])
-        t_f += ev[3].elapsed_time(ev[4])
+        pic_step(s, ev if timed else None)
+        if timed:
+            torch.cuda.synchronize()
+            t_ph += ph_ev[0].elapsed_time(ph_ev[1])
+            t_sort += ev[0].elapsed_time(ev[1])
+            t_all += ev[0].elapsed_time(ev[4])
+            t_d += ev[2].elapsed_time(ev[3])
+            t_f += ev[3].elapsed_time(ev[4])
+    torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    ctx.set_photon_events(None)
+    em, ep, G = lists["em"], lists["ep"], lists["G"]
     counts1 = (em.count, ep.count, G.count)
+    summary = cascade_summary(em, ep, G, 4000.0, torch)
+    res = {"summary": summary, "counts0": counts0, "counts1": counts1, "status_bits": ctx.read_status(),
+           "t_ph": t_ph, "t_all": t_all, "t_d": t_d, "t_f": t_f, "t_sort": t_sort, "sort_every": sort_every,
+           "wall": wall, "n": n, "warm": warm,
+           "steps": steps, "solver": solver, "deposit": deposit, "grid": grid, "tuning": tuning}
+    ctx.close()
+    del em, ep, G, J, comps, lists, spare
+    torch.cuda.empty_cache()
+    return res
+
+
+def cascade_rates(r, prec):
+    steps, counts0, counts1 = r["steps"], r["counts0"], r["counts1"]
     lep_steps = sum((counts0[k] + counts1[k]) / 2 * steps for k in (0, 1))
     pho_steps = (counts0[2] + counts1[2]) / 2 * steps
-    ph_ms = t_ph / steps
-    ph_bytes = (counts0[2] + counts1[2]) / 2 * BYTES_PHOTON_STEP["mixed"]
+    ph_ms = r["t_ph"] / steps
+    ph_bytes = (counts0[2] + counts1[2]) / 2 * BYTES_PHOTON_STEP[prec]
+    gbs = ph_bytes / (ph_ms * 1e-3) / 1e9
+    return {"particle_steps_per_s": (lep_steps + pho_steps) / (r["t_all"] * 1e-3),
+            "photon_steps_per_s": pho_steps / (r["t_ph"] * 1e-3),
+            "ms_per_step": r["t_all"] / steps, "photon_step_ms": ph_ms, "wall_ms_per_step": 1e3 * r["wall"] / steps,
+            "sort": {"every_steps": r["sort_every"], "ms_per_step": r["t_sort"] / steps,
+                     "what": "photons, electrons, positrons reordered by 4 x 4-cell grid bin (stable; dead "
+                             "photons dropped)"} if r["sort_every"] else None,
+            "photon_step_roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                     "frac": gbs / HBM_PEAK_GBS, "bytes_per_photon_step": BYTES_PHOTON_STEP[prec]},
+            "counts_start": {"electrons": counts0[0], "positrons": counts0[1], "photons": counts0[2]},
+            "counts_end": {"electrons": counts1[0], "positrons": counts1[1], "photons": counts1[2],
+                           "photons_alive": r["summary"]["photons_alive"]},
+            "status_bits": r["status_bits"], "lepton_tuning": r["tuning"]}
+
+
+def run_cascade(args, torch, Q, W):
+    """The cascade in mixed precision (the timed result), the same run in FP64 (same draws)
+    and FP64 with other draws: the mixed result stated at its error against FP64, each metric
+    against max(4 x its difference between the two FP64 runs, 1e-3)."""
+    mixed = cascade_once(args, torch, Q, W, "mixed")
+    r = mixed
+    if not args.cascade_mixed_only:
+        fp64 = cascade_once(args, torch, Q, W, "fp64")
+        fp64_b = cascade_once(args, torch, Q, W, "fp64", seed_offset=1, timed=False)
+    steps, grid = r["steps"], r["grid"]
     nodes = grid["nx"] * grid["ny"]
-    fgbs = nodes * BYTES_YEE_NODE / (t_f / steps * 1e-3) / 1e9 if solver and t_f > 0 else None
-    lep_mean = sum((counts0[k] + counts1[k]) / 2 for k in (0, 1))
-    dgbs = lep_mean * BYTES_DEPOSIT / (t_d / steps * 1e-3) / 1e9 if deposit and t_d > 0 else None
+    t_f, t_d = r["t_f"], r["t_d"]
+    lep_mean = sum((r["counts0"][k] + r["counts1"][k]) / 2 for k in (0, 1))
+    fgbs = nodes * BYTES_YEE_NODE / (t_f / steps * 1e-3) / 1e9 if r["solver"] and t_f > 0 else None
+    dgbs = lep_mean * BYTES_DEPOSIT / (t_d / steps * 1e-3) / 1e9 if r["deposit"] and t_d > 0 else None
     field = ({"solver": ("2D Yee, open x (Mur) / periodic y, with the current the leptons deposit each step "
-                         f"(charge-conserving, qscale {CASCADE_QSCALE})" if deposit else
+                         f"(charge-conserving, qscale {CASCADE_QSCALE})" if r["deposit"] else
                          "2D vacuum Yee, open x (Mur) / periodic y (the pulse filled at t = 0 and propagated)"),
               "ms_per_step": t_f / steps,
               "deposit": ({"ms_per_step": t_d / steps, "leptons": lep_mean,
                            "leptons_per_s": lep_mean / (t_d / steps * 1e-3),
                            "roofline": {"bound": "hbm", "achieved": dgbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                         "frac": dgbs / HBM_PEAK_GBS, "bytes_per_lepton": BYTES_DEPOSIT},
-                           "note": "includes zeroing J and saving the start positions"} if deposit else None),
+                           "note": "includes zeroing J and saving the start positions"} if r["deposit"] else None),
               "roofline": {"bound": "hbm", "achieved": fgbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": fgbs / HBM_PEAK_GBS, "bytes_per_node_step": BYTES_YEE_NODE}}
-             if solver else {"solver": "none (static snapshot of the pulse)"})
-    return {"workload": f"{n} electrons gamma 4000 in an LP a0 = 300 pulse on a 2048 x 512 grid; "
-                        f"NCS + Stokes + NBW + VB; steps {warm}..{warm + steps - 1}",
-            "field": field,
-            "counts_start": {"electrons": counts0[0], "positrons": counts0[1], "photons": counts0[2]},
-            "counts_end": {"electrons": counts1[0], "positrons": counts1[1], "photons": counts1[2]},
-            "particle_steps_per_s": (lep_steps + pho_steps) / (t_all * 1e-3),
-            "photon_steps_per_s": pho_steps / (t_ph * 1e-3), "ms_per_step": t_all / steps,
-            "photon_step_ms": ph_ms, "wall_ms_per_step": 1e3 * wall / steps,
-            "photon_step_roofline": {"bound": "hbm", "achieved": ph_bytes / (ph_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
-                                     "unit": "GB/s", "frac": ph_bytes / (ph_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                                     "bytes_per_photon_step": BYTES_PHOTON_STEP["mixed"]},
-            "status_bits": ctx.read_status()}
+             if r["solver"] else {"solver": "none (static snapshot of the pulse)"})
+    out = {"workload": f"{r['n']} electrons gamma 4000 in an LP a0 = 300 pulse on a 2048 x 512 grid; "
+                       f"NCS + Stokes + NBW + VB; steps {r['warm']}..{r['warm'] + steps - 1}",
+           "field": field}
+    out.update(cascade_rates(mixed, "mixed"))
+    if args.cascade_mixed_only:
+        return out
+    err = cascade_metrics(fp64["summary"], mixed["summary"])
+    stat = cascade_metrics(fp64["summary"], fp64_b["summary"])
+    tol = {k: max(4.0 * stat[k], 1e-3) for k in CASCADE_DIFF}
+    out["fp64"] = cascade_rates(fp64, "fp64")
+    out["speedup_mixed_over_fp64"] = out["particle_steps_per_s"] / out["fp64"]["particle_steps_per_s"]
+    out["error_vs_fp64"] = err
+    out["error_statistical_fp64_seeds"] = stat
+    out["tolerance_check"] = {"tolerance": tol, "within": {k: err[k] <= tol[k] for k in CASCADE_DIFF},
+                              "all_within": all(err[k] <= tol[k] for k in CASCADE_DIFF)}
+    return out
 
 
 BYTES_HIST_PHOTON = {"mixed": 24 + 12 + 12 + 8 + 1, "fp64": 24 + 24 + 24 + 8 + 1}   # read k, xi, e1, w, alive
@@ -521,32 +633,73 @@ def run_radiative(args, torch, Q, cfg):
     return out
 
 
-def cpu_baseline(cfg_small, budget_s=15.0):
-    """The oracle as it stands (single-threaded C, FP64 tables) on a bounded sample of the
-    same workload: the first `n` electrons of the bunch, stepped until the budget is used."""
-    import numpy as np
-
+def _oracle_run(st, cfg, steps, budget_s=None):
+    """The oracle as it stands (C, FP64 tables) on the electrons `st`: `steps` steps, or as
+    many as `budget_s` seconds allow (at most `steps`).  Returns (particle-steps, seconds)."""
     import oracle
-    st = cfg_small["leptons"]
     n = len(st["x"])
-    max_steps = 400
     L = oracle.LeptonArrays.from_state(st)
-    G = oracle.PhotonArrays.empty(int(0.03 * n * max_steps) + 1000)
-    sim = oracle.Sim(dt=cfg_small["dt"], procs=cfg_small["procs"], seed=cfg_small["seed"],
-                     next_id=cfg_small["next_id"])
-    f = oracle.make_field(cfg_small["field"])
-    oracle.tables()
-    s0 = cfg_small["start_step"]
-    steps = 0
+    G = oracle.PhotonArrays.empty(int(0.03 * n * steps) + 1000)
+    sim = oracle.Sim(dt=cfg["dt"], procs=cfg["procs"], seed=cfg["seed"], next_id=cfg["next_id"])
+    f = oracle.make_field(cfg["field"])
+    s0 = cfg["start_step"]
+    done = 0
     t0 = time.perf_counter()
-    while time.perf_counter() - t0 < budget_s and steps < max_steps:
-        sim.step(f, L, None, G, s0 + steps)
-        steps += 1
-    el = time.perf_counter() - t0
-    del np
-    return {"value": n * steps / el, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n} electrons of the same bunch x {steps} steps from step {s0} "
-                      f"(single-threaded C oracle, FP64 tables), {el:.1f} s"}
+    while done < steps and (budget_s is None or time.perf_counter() - t0 < budget_s):
+        sim.step(f, L, None, G, s0 + done)
+        done += 1
+    return n * done, time.perf_counter() - t0
+
+
+_CPU_JOB = {}
+
+
+def _cpu_worker(k):
+    """One process of the all-core baseline: slice k of the sample, a fixed step count."""
+    job = _CPU_JOB
+    m = job["per"]
+    st = {key: v[k * m:(k + 1) * m] for key, v in job["cfg"]["leptons"].items()}
+    return _oracle_run(st, job["cfg"], job["steps"])
+
+
+def cpu_baseline(W, start, n1=200_000, budget_s=15.0):
+    """The oracle as it stands, timed on the host cores, before this process touches the
+    GPU: (1) single-threaded on the first n1 electrons of the bunch, stepped until the budget
+    is used; (2) one process per core of the machine's CPU share (at most 16), each stepping its
+    own n1 electrons (disjoint slices of a larger bunch of the same recipe) for the same
+    number of steps.  Particles are independent and the draws are keyed by particle id, so
+    the processes need no communication; the rate is all particle-steps over the wall time
+    of the slowest process."""
+    import multiprocessing as mp
+    import oracle
+    oracle.build()
+    oracle.tables()
+    nproc = os.cpu_count() or 1
+    try:
+        share = len(os.sched_getaffinity(0))
+    except AttributeError:
+        share = nproc
+    ncores = max(1, min(16, share))
+    cfg = W.c2(n1 * ncores, start_step=start)
+    st1 = {k: v[:n1] for k, v in cfg["leptons"].items()}
+    ps, el = _oracle_run(st1, cfg, 400, budget_s)
+    steps = max(1, ps // n1)
+    single = {"value": ps / el, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+              "sample": f"{n1} electrons of the focused-pulse bunch x {steps} steps from step {start} "
+                        f"(single-threaded C oracle, FP64 tables), {el:.1f} s"}
+    _CPU_JOB.update(cfg=cfg, per=n1, steps=steps)
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(ncores) as pool:   # forked before any GPU use
+        res = pool.map(_cpu_worker, range(ncores))
+    wall = time.perf_counter() - t0
+    _CPU_JOB.clear()
+    total = sum(r[0] for r in res)
+    return {"value": total / wall, "unit": "particle-steps/s", "cores": ncores, "kind": "oracle",
+            "sample": f"{ncores} processes x {n1} electrons (disjoint slices of a {n1 * ncores}-electron bunch of "
+                      f"the focused-pulse recipe) x {steps} steps from step {start}, {wall:.1f} s wall "
+                      f"(slowest process {max(r[1] for r in res):.1f} s)",
+            "host": {"nproc": nproc, "cpu_share": share, "processes": ncores},
+            "single_core": single}
 
 
 def main():
@@ -564,6 +717,10 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-sampler measurements")
     ap.add_argument("--cascade-steps", type=int, default=40, help="timed steps of the cascade (0: skip it)")
     ap.add_argument("--cascade-warmup", type=int, default=150)
+    ap.add_argument("--sort-every", type=int, default=20,
+                    help="cascade: reorder the particle lists by grid bin every N steps (0: never)")
+    ap.add_argument("--cascade-mixed-only", action="store_true",
+                    help="cascade: only the timed mixed-precision run (no FP64 runs, no error metrics)")
     ap.add_argument("--no-deposit", action="store_true",
                     help="cascade: vacuum field solver, no current deposition")
     ap.add_argument("--static-grid", action="store_true",
@@ -581,6 +738,15 @@ def main():
                                    "range with no per-step communication, and no multi-GPU run is part of it",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+
+    cpu = None
+    if not args.no_cpu_baseline and not args.copy_probe:
+        import workloads as W
+        print("[bench] CPU baseline (oracle), single core and all cores, before the GPU is used",
+              file=sys.stderr, flush=True)
+        cpu = cpu_baseline(W, 2400 + args.warmup, args.cpu_sample, args.cpu_budget)
+        print(f"[bench] CPU baseline: {cpu['value']:.3e} particle-steps/s on {cpu['cores']} cores, "
+              f"{cpu['single_core']['value']:.3e} on one", file=sys.stderr, flush=True)
 
     import torch
 
@@ -671,9 +837,8 @@ def main():
     if args.batch_steps > 0:
         print("[bench] batching: many collisions, graph-replayed, vs one at a time in FP64", file=sys.stderr, flush=True)
         result["batched"] = run_batched(args, torch, Q, W)
-    if not args.no_cpu_baseline:
-        small = W.c2(args.cpu_sample, start_step=start + args.warmup)
-        result["cpu_baseline"] = cpu_baseline(small, args.cpu_budget)
+    if cpu is not None:
+        result["cpu_baseline"] = cpu
     print(json.dumps(result))
 
 

@@ -248,6 +248,23 @@ qed_status qed_step(qed_ctx_t *ctx, const qed_segment *segs, int nseg, qed_lepto
 qed_status qed_compact_photons(qed_ctx_t *ctx, const qed_photons *in, qed_photons *out,
                                hipStream_t stream);
 
+/* Reordering of a list by grid bin (a data-layout step, no physics): the live particles
+ * of `in` are written to `out` (distinct buffers, out->capacity >= in->capacity; out's
+ * previous contents and count are replaced) sorted by the bin of their (x, y) on the grid
+ * of `grid` (kind QED_FIELD_GRID2D; only nx, ny, dx, dy, gx0, gy0 are used): bins of
+ * bin_cells x bin_cells cells, bx = floor((x - gx0) / (bin_cells dx)) clamped to
+ * [0, nbx - 1] (NaN to 0), by likewise, key = by nbx + bx, at most 65536 bins.  The sort
+ * is stable (particles of one bin keep their order) and the same on every run; dead
+ * photons (alive = 0) are dropped, so the photon call also compacts.  Neighbouring
+ * particles then share the cache lines of the TSC gather (Sec. II.D-E), which otherwise
+ * bounds the step on grid fields.  It changes the order in which later appends (photons,
+ * pairs in parent order) and their ids come out.  Context-owned work memory of 16 bytes
+ * per particle of in's capacity plus 3 MB (hipMalloc on first use or growth).       */
+qed_status qed_sort_photons(qed_ctx_t *ctx, const qed_photons *in, qed_photons *out, const qed_field *grid,
+                            int32_t bin_cells, hipStream_t stream);
+qed_status qed_sort_leptons(qed_ctx_t *ctx, const qed_leptons *in, qed_leptons *out, const qed_field *grid,
+                            int32_t bin_cells, hipStream_t stream);
+
 /* Boundaries of qed_field_advance.  open_x = 0: periodic in x.  open_x = 1: the first and
  * last node columns carry the first-order absorbing condition of Mur on Ey, Ez (one-way
  * wave equation of the outgoing field, discretised over the step between the boundary

@@ -495,6 +495,33 @@ class PhotonArrays:
         return {k: getattr(self, k)[:n].copy() for k in self.KEYS + ("id", "alive")}
 
 
+def sort_by_bin(arrs, grid: dict, bin_cells: int):
+    """The list `arrs` (LeptonArrays or PhotonArrays) reordered by grid bin, as a new list
+    of the same capacity: the particles (photons: the live ones) stably sorted by key =
+    by nbx + bx, with bx = floor((x - gx0) / (bin_cells dx)) clamped to [0, nbx - 1] (NaN
+    to 0), by likewise, nbx = ceil(nx / bin_cells).  This is the plain definition of the
+    library's data-layout sort: numpy's stable argsort on that key."""
+    n = arrs.count
+    nbx = -(-int(grid["nx"]) // bin_cells)
+    nby = -(-int(grid["ny"]) // bin_cells)
+
+    def bins(v, v0, d, nb):
+        f = np.floor((v - v0) * (1.0 / (bin_cells * d)))
+        f = np.where(f >= 0.0, f, 0.0)            # negative and NaN to 0
+        return np.minimum(f, nb - 1).astype(np.int64)
+
+    x, y = arrs.x[:n], arrs.y[:n]
+    key = bins(y, grid["gy0"], grid["dy"], nby) * nbx + bins(x, grid["gx0"], grid["dx"], nbx)
+    sel = np.arange(n)
+    if isinstance(arrs, PhotonArrays):
+        sel = sel[arrs.alive[:n] != 0]
+    order = sel[np.argsort(key[sel], kind="stable")]
+    st = {k: v[order] for k, v in arrs.view().items()}
+    if isinstance(arrs, PhotonArrays):
+        return PhotonArrays.from_state(st, capacity=len(arrs.x))
+    return LeptonArrays.from_state(st, capacity=len(arrs.x), charge=arrs.charge)
+
+
 class Sim:
     """Whole-step driver in the order of the paper's Spin-QED chain (Sec. IV):
     Lorentz push and T-BMT of the electrons, then the positrons alive at the start of the

@@ -23,7 +23,7 @@ TAB_BESSEL, TAB_NCS_RATE, TAB_NCS_CDF, TAB_NBW_RATE, TAB_NBW_CDF, TAB_VB, TAB_RA
 RR_LL, RR_MLL, RR_RBMT = 1, 2, 4
 EXPORTED = ["qed_init_tables", "qed_destroy", "qed_gather", "qed_push_spin", "qed_push_radiative", "qed_emit",
             "qed_step_leptons", "qed_step_leptons_noalloc",
-            "qed_birefringence", "qed_pair", "qed_step_photons", "qed_step", "qed_compact_photons", "qed_read_status",
+            "qed_birefringence", "qed_pair", "qed_step_photons", "qed_step", "qed_compact_photons", "qed_sort_photons", "qed_sort_leptons", "qed_read_status",
             "qed_clear_status", "qed_get_next_id", "qed_set_next_id", "qed_table_size", "qed_table_export",
             "qed_set_step_events", "qed_set_photon_events", "qed_set_step_counter", "qed_advance_step", "qed_get_tuning",
             "qed_set_tuning", "qed_autotune", "qed_mlp_init", "qed_mlp_set_params", "qed_mlp_get_params",
@@ -141,6 +141,8 @@ def lib():
             "qed_step_photons": [vp, vp, C.c_int, vp, vp, vp, i64, vp],
             "qed_step": [vp, vp, C.c_int, vp, vp, vp, i64, vp],
             "qed_compact_photons": [vp, vp, vp, vp],
+            "qed_sort_photons": [vp, vp, vp, vp, C.c_int32, vp],
+            "qed_sort_leptons": [vp, vp, vp, vp, C.c_int32, vp],
             "qed_read_status": [vp, C.POINTER(C.c_uint32), vp],
             "qed_clear_status": [vp, vp],
             "qed_get_next_id": [vp, C.POINTER(C.c_uint64), vp],
@@ -479,6 +481,18 @@ class Context:
     def compact_photons(self, src: Photons, dst: Photons, stream=None):
         self._check(lib().qed_compact_photons(self.h, C.byref(src.c()), C.byref(dst.c()), _stream(stream)),
                     "qed_compact_photons")
+
+    def sort_photons(self, src: Photons, dst: Photons, grid_spec: dict, bin_cells: int = 4, stream=None):
+        """Live photons of src into dst, stably sorted by grid bin (dead ones dropped)."""
+        f = make_field(grid_spec)
+        self._check(lib().qed_sort_photons(self.h, C.byref(src.c()), C.byref(dst.c()), C.byref(f), bin_cells,
+                                           _stream(stream)), "qed_sort_photons")
+
+    def sort_leptons(self, src: Leptons, dst: Leptons, grid_spec: dict, bin_cells: int = 4, stream=None):
+        """Leptons of src into dst, stably sorted by grid bin."""
+        f = make_field(grid_spec)
+        self._check(lib().qed_sort_leptons(self.h, C.byref(src.c()), C.byref(dst.c()), C.byref(f), bin_cells,
+                                           _stream(stream)), "qed_sort_leptons")
 
     def read_status(self, stream=None) -> int:
         v = C.c_uint32()

@@ -13,7 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libqed.so")
-SOURCES = ["qed_abi.cpp", "qed_tables.hip", "qed_kernels.hip", "qed_mlp.hip", "qed_detector.hip", "qed_fdtd.hip", "qed_deposit.hip", "qed_noalloc.hip"]
+SOURCES = ["qed_abi.cpp", "qed_tables.hip", "qed_kernels.hip", "qed_mlp.hip", "qed_detector.hip", "qed_fdtd.hip", "qed_deposit.hip", "qed_noalloc.hip",
+           "qed_sort.hip"]
 ARCH = os.environ.get("QED_OFFLOAD_ARCH", "gfx950")
 
 

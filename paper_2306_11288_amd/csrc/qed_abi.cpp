@@ -227,6 +227,7 @@ void free_ctx(qed_ctx *c) {
     hipFree(c->tile_off);
     hipFree(c->launch);
     hipFree(c->lep_start);
+    hipFree(c->scan_sums);
     hipFree(c->staging);
     hipFree(c->dsegs);
     hipFree(c->mlp_P);
@@ -241,6 +242,7 @@ void free_ctx(qed_ctx *c) {
     hipFree(c->dep_rec);
     hipFree(c->dep_acc);
     hipFree(c->yee_save);
+    hipFree(c->sort_work);
     hipFree(c->ev_in);
     hipFree(c->ev_out);
     if (c->hsegs) hipHostFree(c->hsegs);
@@ -314,6 +316,7 @@ qed_status qed_init_tables(qed_ctx_t **out, const qed_config *cfg, hipStream_t s
                     hipMalloc(&c->tile_off, (MAX_TILES + 1) * sizeof(int64_t)) == hipSuccess &&
                     hipMalloc(&c->launch, 4 * sizeof(int64_t)) == hipSuccess &&
                     hipMalloc(&c->lep_start, 2 * sizeof(int64_t)) == hipSuccess &&
+                    hipMalloc(&c->scan_sums, SCAN_MAX_BLOCKS * sizeof(int64_t)) == hipSuccess &&
                     hipEventCreateWithFlags(&c->seg_copied, hipEventDisableTiming) == hipSuccess;
     if (!ok) {
         free_ctx(c);
@@ -636,6 +639,59 @@ qed_status qed_compact_photons(qed_ctx_t *ctx, const qed_photons *in, qed_photon
         return fail(ctx, QED_EARG, "qed_compact_photons: in and out must be distinct buffers");
     if ((st = ensure_staging(ctx, in->capacity)) != QED_OK) return st;
     return launched(ctx, launch_compact(ctx, *in, *out, s), "qed_compact_photons");
+}
+
+static qed_status sort_grid(qed_ctx *ctx, const qed_field *f, int32_t bin_cells, SortGrid &g, const char *name) {
+    if (!f || f->kind != QED_FIELD_GRID2D)
+        return fail(ctx, QED_EARG, "%s: needs a GRID2D field (its nx, ny, dx, dy, gx0, gy0)", name);
+    if (f->nx < 1 || f->ny < 1 || !(f->dx > 0) || !(f->dy > 0) || !std::isfinite(f->gx0) || !std::isfinite(f->gy0))
+        return fail(ctx, QED_EARG, "%s: bad grid geometry", name);
+    if (bin_cells < 1) return fail(ctx, QED_EARG, "%s: bin_cells must be >= 1", name);
+    const int64_t nbx = (f->nx + bin_cells - 1) / bin_cells, nby = (f->ny + bin_cells - 1) / bin_cells;
+    if (nbx * nby > 65536) return fail(ctx, QED_EARG, "%s: %lld bins (more than 65536): use larger bins", name,
+                                       (long long)(nbx * nby));
+    g.gx0 = f->gx0;
+    g.gy0 = f->gy0;
+    g.inv_bx = 1.0 / ((double)bin_cells * f->dx);
+    g.inv_by = 1.0 / ((double)bin_cells * f->dy);
+    g.nbx = (int32_t)nbx;
+    g.nby = (int32_t)nby;
+    return QED_OK;
+}
+
+qed_status qed_sort_photons(qed_ctx_t *ctx, const qed_photons *in, qed_photons *out, const qed_field *grid,
+                            int32_t bin_cells, hipStream_t s) {
+    qed_status st = ready(ctx);
+    if (st != QED_OK) return st;
+    if ((st = check_photons(ctx, in, "in")) != QED_OK) return st;
+    if ((st = check_photons(ctx, out, "out")) != QED_OK) return st;
+    if (in->x == out->x || in->count == out->count)
+        return fail(ctx, QED_EARG, "qed_sort_photons: in and out must be distinct buffers");
+    if (out->capacity < in->capacity) return fail(ctx, QED_EARG, "qed_sort_photons: out is smaller than in");
+    SortGrid g{};
+    if ((st = sort_grid(ctx, grid, bin_cells, g, "qed_sort_photons")) != QED_OK) return st;
+    if (ctx->step_dev && in->capacity > ctx->sort_cap && ctx->sort_cap > 0)
+        return fail(ctx, QED_ESTATE, "qed_sort_photons: would reallocate its work memory while a device step "
+                                     "counter is registered");
+    return launched(ctx, launch_sort_photons(ctx, *in, *out, g, s), "qed_sort_photons");
+}
+
+qed_status qed_sort_leptons(qed_ctx_t *ctx, const qed_leptons *in, qed_leptons *out, const qed_field *grid,
+                            int32_t bin_cells, hipStream_t s) {
+    qed_status st = ready(ctx);
+    if (st != QED_OK) return st;
+    if ((st = check_leptons(ctx, in, "in")) != QED_OK) return st;
+    if ((st = check_leptons(ctx, out, "out")) != QED_OK) return st;
+    if (in->x == out->x || in->count == out->count)
+        return fail(ctx, QED_EARG, "qed_sort_leptons: in and out must be distinct buffers");
+    if (out->capacity < in->capacity) return fail(ctx, QED_EARG, "qed_sort_leptons: out is smaller than in");
+    if (out->charge != in->charge) return fail(ctx, QED_EARG, "qed_sort_leptons: in and out differ in charge");
+    SortGrid g{};
+    if ((st = sort_grid(ctx, grid, bin_cells, g, "qed_sort_leptons")) != QED_OK) return st;
+    if (ctx->step_dev && in->capacity > ctx->sort_cap && ctx->sort_cap > 0)
+        return fail(ctx, QED_ESTATE, "qed_sort_leptons: would reallocate its work memory while a device step "
+                                     "counter is registered");
+    return launched(ctx, launch_sort_leptons(ctx, *in, *out, g, s), "qed_sort_leptons");
 }
 
 qed_status qed_read_status(qed_ctx_t *ctx, uint32_t *flags, hipStream_t s) {

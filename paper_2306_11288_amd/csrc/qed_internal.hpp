@@ -176,10 +176,11 @@ struct qed_ctx {
     uint32_t *status;                  // sticky status word
     unsigned long long *next_id;       // id counter
     int *tile_counts;                  // events per 256-particle tile   [max_tiles]
-    int *group_tot;                    // events per group of EV_GROUP tiles [max_tiles / EV_GROUP + 1];
+    int *group_tot;                    // events per group of ev_group tiles [max_tiles / 4 + 1];
                                        // zero between launches (the scan clears what it reads)
     int64_t *tile_off;                 // exclusive prefix of tile_counts [max_tiles + 1]
     int64_t *launch;                   // bases of the last append launch [4]
+    int64_t *scan_sums;                // block totals of the prefix scan [SCAN_MAX_BLOCKS]
     int64_t *lep_start;                // lepton counts before the pair appends of qed_step [2]
     void *na_scratch;                  // device address of this device's allocation-free scratch array
     void *staging;                     // one STAGING_SLOT per particle of the largest list seen,
@@ -213,6 +214,8 @@ struct qed_ctx {
     int64_t dep_cap;                   // particles the records can hold
     void *dep_acc;                     // 64-bit fixed-point current grid (zero between calls)
     int64_t dep_acc_len;
+    void *sort_work;                   // particle sort: keys, indices, digit counts and offsets
+    int64_t sort_cap;                  // particles the sort work memory holds
     float *yee_save;                   // open-boundary columns of the field solver
     int64_t yee_save_len;
     int64_t ev_cap;
@@ -227,7 +230,9 @@ struct ScanState {
     int *group_tot;        // events per event group (zero between launches)
     int64_t *tile_off;     // exclusive prefix of the counts
     int64_t *launch;       // bases of the launch [4]
+    int64_t *sums;         // block totals of the scan [SCAN_MAX_BLOCKS]
 };
+constexpr int SCAN_MAX_BLOCKS = 64;   // blocks of the prefix scan
 // table construction (qed_tables.hip); returns hipSuccess or the first HIP error
 hipError_t build_tables(qed_ctx *ctx, hipStream_t s);
 // launches (qed_kernels.hip)
@@ -238,8 +243,8 @@ hipError_t launch_leptons(qed_ctx *ctx, LeptonMode mode, const SegArgs &sa, cons
                           double *E6, const qed_photons *out, int64_t step, hipStream_t s,
                           const int64_t *n_in = nullptr, const ScanState *ss = nullptr);
 // allocation-free lepton step (qed_noalloc.hip): the file-scope scratch array of the current
-// device (its address taken once per device), its size limit, and the clearing of the
-// part that must start at zero
+// device (its address taken once per device), its size limit, and the clearing of the part
+// that must start at zero
 constexpr int64_t NOALLOC_MAX = QED_NOALLOC_MAX_LEPTONS;   // leptons per call
 static_assert(NOALLOC_MAX % BLOCK == 0, "whole tiles");
 hipError_t noalloc_scratch(void **ptr);
@@ -251,6 +256,20 @@ hipError_t launch_photons(qed_ctx *ctx, PhotonMode mode, const SegArgs &sa, cons
                           const qed_leptons *em, const qed_leptons *ep, int64_t step, hipStream_t s,
                           int64_t *lep_start = nullptr);
 hipError_t launch_compact(qed_ctx *ctx, const qed_photons &in, const qed_photons &out, hipStream_t s);
+// exclusive prefix of n ints (counts) into off[0..n], the total also into *total and
+// launch[3] (launch: 4 int64 of scratch)
+hipError_t launch_scan_ints(qed_ctx *ctx, const int *counts, int64_t n, int64_t *off, int64_t *total,
+                            int64_t *launch, hipStream_t s);
+// particle sort by grid bin (qed_sort.hip): the key of every particle, then two stable
+// counting-sort passes over 8-bit digits, then the gather into the output list
+struct SortGrid {
+    double gx0, gy0, inv_bx, inv_by;   // bin of (x, y): floor((x - gx0) inv_bx), clamped
+    int32_t nbx, nby;
+};
+hipError_t launch_sort_photons(qed_ctx *ctx, const qed_photons &in, const qed_photons &out, const SortGrid &g,
+                               hipStream_t s);
+hipError_t launch_sort_leptons(qed_ctx *ctx, const qed_leptons &in, const qed_leptons &out, const SortGrid &g,
+                               hipStream_t s);
 hipError_t launch_advance_step(int64_t *step, int64_t by, hipStream_t s);
 hipError_t launch_radiative(qed_ctx *ctx, const SegArgs &sa, const qed_leptons &L, uint32_t mode, int64_t step,
                             hipStream_t s);

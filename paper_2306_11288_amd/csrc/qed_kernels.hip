@@ -133,12 +133,12 @@ __device__ __forceinline__ void fields_for(const SegArgs &sa, int64_t i, double 
 
 // ------------------------------------------------------------------------- scan kernel
 struct ScanArgs {
-    int *counts;              // events per unit (a tile, or a group of tiles)
-    int clear;                // set the counts read back to zero
+    const int *counts;        // events per unit (a 256-particle tile)
     int64_t *off;             // [nunits + 1]: exclusive prefix
-    const int64_t *in_count;  // list whose units were counted
+    const int64_t *in_count;  // list whose units were counted (null: in_capacity particles)
     int64_t in_capacity;
     int unit;                 // particles per unit
+    int64_t chunk;            // units per block (a multiple of SCAN_THREADS)
     int64_t *out_count[2];    // output lists (may be null)
     int64_t out_cap[2];
     unsigned long long *next_id;
@@ -146,81 +146,131 @@ struct ScanArgs {
     int zero_base;            // output lists are replaced, not appended to (compaction)
     int64_t *base_out;        // optional [2]: receives the output counts before the append
     int64_t *launch;          // [0] out0 base, [1] out1 base, [2] id base, [3] events
+    int64_t *sums;            // [SCAN_MAX_BLOCKS]: total of each block
+    int clear;                // set the counts to zero once read (accumulated by atomics)
     uint32_t *status;
 };
-constexpr int SCAN_THREADS = 1024, SCAN_UNROLL = 8;
-// One block: exclusive prefix sums of the unit counts and the launch bases.  Each thread
-// owns a contiguous run of units; the first SCAN_UNROLL counts of its run stay in
-// registers between the two passes (the whole run when there are at most 8192 units).
-// The per-thread sums are scanned within each wavefront by lane shuffles and across the
-// 16 wavefronts through LDS (one barrier).  The last thread reads the output counts and
-// the id counter at the start, so their latency overlaps the scan.
-__global__ __launch_bounds__(SCAN_THREADS) void k_scan(ScanArgs a) {
-    __shared__ int64_t s_wave[SCAN_THREADS / 64];
+constexpr int SCAN_THREADS = 256, SCAN_MIN_CHUNK = 2048, SCAN_ONE_THREADS = 1024;
+constexpr int64_t SCAN_ONE_BLOCK = 65536;   // units a single block scans
+static_assert(SCAN_MAX_BLOCKS <= SCAN_THREADS, "one block total per thread");
+
+// sum over the block of NT threads (every thread gets it)
+template <int NT>
+__device__ __forceinline__ int64_t block_sum(int64_t v, int64_t *s_w) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d);
+    __syncthreads();
+    if (lane == 0) s_w[wid] = v;
+    __syncthreads();
+    int64_t t = 0;
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) t += s_w[w];
+    return t;
+}
+
+// The unit counts a thread owns: `per` consecutive units from t0 (fewer at the end),
+// loaded eight at a time so that the loads of a batch are in flight together.
+__device__ __forceinline__ int64_t run_sum(const int *c, int64_t t0, int64_t per, int64_t nunits) {
+    int64_t sum = 0;
+    for (int64_t b = 0; b < per; b += 8) {
+        int v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int64_t u = t0 + b + k;
+            v[k] = (b + k < per && u < nunits) ? c[u] : 0;
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) sum += v[k];
+    }
+    return sum;
+}
+__device__ __forceinline__ int64_t scan_units(const ScanArgs &a, int64_t &nunits) {
+    const int64_t n = a.in_count ? clamp_count(a.in_count, a.in_capacity) : a.in_capacity;
+    nunits = (n + a.unit - 1) / a.unit;
+    return nunits > 0 ? (nunits - 1) / a.chunk : 0;   // the block holding the last unit
+}
+
+// Exclusive prefix sums of the unit counts and the launch bases.  A list of at most
+// SCAN_ONE_BLOCK units is scanned by one block of 1024 threads in one launch.  A longer one
+// takes two launches over blocks of 256 threads and `chunk` units: k_scan_sums writes each
+// block's total, k_scan then gives block b the total of blocks [0, b) (at most
+// SCAN_MAX_BLOCKS values).  In k_scan each thread owns a run of chunk / threads units
+// (wave shuffles, then the waves through LDS) and writes their offsets; the block holding
+// the last unit also writes the total, the launch bases, the new output counts and the id
+// counter.  With `clear`, k_scan zeroes the units it read (only its own block's: no other
+// block of k_scan reads them), so counts accumulated by atomics start at zero next time.
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_sums(ScanArgs a) {
+    __shared__ int64_t s_w[SCAN_THREADS / 64];
+    int64_t nunits;
+    const int64_t lastb = scan_units(a, nunits);
+    if ((int64_t)blockIdx.x > lastb) return;
+    const int64_t per = a.chunk / SCAN_THREADS;
+    const int64_t t0 = (int64_t)blockIdx.x * a.chunk + threadIdx.x * per;
+    const int64_t tot = block_sum<SCAN_THREADS>(run_sum(a.counts, t0, per, nunits), s_w);
+    if (threadIdx.x == 0) a.sums[blockIdx.x] = tot;
+}
+template <int NT>
+__global__ __launch_bounds__(NT) void k_scan(ScanArgs a) {
+    __shared__ int64_t s_w[NT / 64];
     const int tid = (int)threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    const bool last = tid == SCAN_THREADS - 1;
+    int64_t nunits;
+    const int64_t lastb = scan_units(a, nunits);
+    if ((int64_t)blockIdx.x > lastb) return;
+    const bool finisher = (int64_t)blockIdx.x == lastb && tid == NT - 1;
     int64_t base[2] = {0, 0};
     unsigned long long id0 = 0;
-    if (last) {
+    if (finisher) {   // read early: the latency overlaps the scan
         for (int k = 0; k < 2; ++k) base[k] = (a.out_count[k] && !a.zero_base) ? *a.out_count[k] : 0;
         id0 = *a.next_id;
     }
-    const int64_t n = clamp_count(a.in_count, a.in_capacity);
-    const int64_t nunits = (n + a.unit - 1) / a.unit;
-    const int64_t per = (nunits + SCAN_THREADS - 1) / SCAN_THREADS;
-    const int64_t lo = tid * per, hi = lo + per < nunits ? lo + per : nunits;
-    // each thread sums its run, SCAN_UNROLL loads in flight
-    int first[SCAN_UNROLL];
+    // the total of the blocks before this one
+    const int64_t before = gridDim.x > 1 ? block_sum<NT>(tid < (int)blockIdx.x ? a.sums[tid] : 0, s_w) : 0;
+    const int64_t per = a.chunk / NT;
+    const int64_t t0 = (int64_t)blockIdx.x * a.chunk + tid * per;
+    // the first eight counts of the run stay in registers for the second pass
+    int v0[8];
 #pragma unroll
-    for (int k = 0; k < SCAN_UNROLL; ++k) first[k] = lo + k < hi ? a.counts[lo + k] : 0;
-    int64_t sum = 0;
+    for (int k = 0; k < 8; ++k) v0[k] = (k < per && t0 + k < nunits) ? a.counts[t0 + k] : 0;
+    int64_t sum = per > 8 ? run_sum(a.counts, t0 + 8, per - 8, nunits) : 0;
 #pragma unroll
-    for (int k = 0; k < SCAN_UNROLL; ++k) sum += first[k];
-    for (int64_t t0 = lo + SCAN_UNROLL; t0 < hi; t0 += SCAN_UNROLL) {
-        int v[SCAN_UNROLL];
-#pragma unroll
-        for (int k = 0; k < SCAN_UNROLL; ++k) v[k] = t0 + k < hi ? a.counts[t0 + k] : 0;
-#pragma unroll
-        for (int k = 0; k < SCAN_UNROLL; ++k) sum += v[k];
-    }
+    for (int k = 0; k < 8; ++k) sum += v0[k];
     int64_t incl = sum;
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
         const int64_t v = __shfl_up(incl, d);
         if (lane >= d) incl += v;
     }
-    if (lane == 63) s_wave[wid] = incl;
     __syncthreads();
-    int64_t before = 0, tot = 0;
+    if (lane == 63) s_w[wid] = incl;
+    __syncthreads();
+    int64_t wbefore = 0, btot = 0;
 #pragma unroll
-    for (int w = 0; w < SCAN_THREADS / 64; ++w) {
-        const int64_t x = s_wave[w];
-        before += w < wid ? x : 0;
-        tot += x;
+    for (int w = 0; w < NT / 64; ++w) {
+        const int64_t x = s_w[w];
+        wbefore += w < wid ? x : 0;
+        btot += x;
     }
-    int64_t run = before + incl - sum;
+    int64_t run = before + wbefore + incl - sum;
+    for (int64_t b = 0; b < per; b += 8) {   // the offsets, a batch of eight counts at a time
+        int v[8];
 #pragma unroll
-    for (int k = 0; k < SCAN_UNROLL; ++k) {
-        if (lo + k < hi) {
-            a.off[lo + k] = run;
-            if (a.clear) a.counts[lo + k] = 0;
+        for (int k = 0; k < 8; ++k) {
+            const int64_t u = t0 + b + k;
+            v[k] = b == 0 ? v0[k] : ((b + k < per && u < nunits) ? a.counts[u] : 0);
         }
-        run += first[k];
-    }
-    for (int64_t t0 = lo + SCAN_UNROLL; t0 < hi; t0 += SCAN_UNROLL) {
-        int v[SCAN_UNROLL];
 #pragma unroll
-        for (int k = 0; k < SCAN_UNROLL; ++k) v[k] = t0 + k < hi ? a.counts[t0 + k] : 0;
-#pragma unroll
-        for (int k = 0; k < SCAN_UNROLL; ++k) {
-            if (t0 + k < hi) {
-                a.off[t0 + k] = run;
-                if (a.clear) a.counts[t0 + k] = 0;
+        for (int k = 0; k < 8; ++k) {
+            const int64_t u = t0 + b + k;
+            if (b + k < per && u < nunits) {
+                a.off[u] = run;
+                if (a.clear) const_cast<int *>(a.counts)[u] = 0;
             }
             run += v[k];
         }
     }
-    if (last) {
+    if (finisher) {
+        const int64_t tot = before + btot;
         a.off[nunits] = tot;
         uint32_t st = 0;
         for (int k = 0; k < 2; ++k) {
@@ -255,8 +305,9 @@ struct LeptonArgs {
     uint32_t *status;
     void *stg;
     int *tile_counts;
-    int *group_tot;
-    int ev_group, ev_shift;    // tiles per event group and its log2
+    int *group_tot;            // events per group of ev_group tiles (zero between launches)
+    int64_t *scan_sums;        // block totals of the scan
+    int ev_group, ev_shift;    // tiles per wavefront of the event kernel and its log2
     float *ev_in;              // learned sampler: per-event network inputs [events][4]
     const float *ev_out;       // and outputs [events][3]
     const int64_t *tile_off;
@@ -427,8 +478,8 @@ __global__ __launch_bounds__(BLOCK) void k_leptons_radiative(LeptonArgs a, uint3
 // also park their state in a LepEvent record at their tile's staging slot tile*BLOCK +
 // rank (rank in index order: wave ballot + popcount, waves combined in LDS); the tile's
 // event count goes to tile_counts and is added to its group's total (integer atomics: the
-// sum does not depend on their order).  RATE_LDS: the NCS rate table is staged in LDS
-// once per block instead of being read through the caches.
+// sum does not depend on their order; the scan clears the totals it reads).  RATE_LDS: the
+// NCS rate table is staged in LDS once per block instead of being read through the caches.
 template <class T, bool PUSH, int FK, bool RATE_LDS>
 __global__ __launch_bounds__(BLOCK) void k_leptons_decide(LeptonArgs a) {
     __shared__ int s_wave[2][BLOCK / 64];
@@ -599,22 +650,27 @@ struct PhotonArgs {
     const int64_t *launch;
 };
 
-// transport (+ NBW test): one tile per block when NBW is on, grid-stride otherwise;
-// specialised on the field kind
+// transport (+ NBW test), specialised on the field kind: a persistent grid sweeps the
+// 256-photon tiles of the live list (blocks beyond the list's tiles exit at once, so a
+// list far below its capacity costs no empty waves); with NBW each tile ranks its events
+// in photon order (wave ballot + popcount, waves combined in LDS) and parks their records
+// at the tile's staging slots
 template <class T, bool NBW, int FK>
 __global__ __launch_bounds__(BLOCK) void k_photons_decide(PhotonArgs a) {
-    __shared__ int s_wave[BLOCK / 64];
-    const int64_t n = clamp_count(a.G.count, a.G.capacity);
-    if (NBW && (int64_t)blockIdx.x * BLOCK >= n) return;
+    __shared__ int s_wave[2][BLOCK / 64];
+    // 32-bit indices: lists hold at most 2^28 particles
+    const int n = (int)clamp_count(a.G.count, a.G.capacity);
+    const int ntiles = (n + BLOCK - 1) / BLOCK;
+    if ((int)blockIdx.x >= ntiles) return;
     const Tabs<T> tb = {(const T *)a.tab};
     const int64_t step = step_of(a);
     const double t = (double)step * a.c.dt;
     T *xi1 = (T *)a.G.xi1, *xi2 = (T *)a.G.xi2, *xi3 = (T *)a.G.xi3;
     T *e1x = (T *)a.G.e1x, *e1y = (T *)a.G.e1y, *e1z = (T *)a.G.e1z;
     uint32_t st = 0;
-    const int64_t stride = (int64_t)gridDim.x * BLOCK;
-    for (int64_t j = (int64_t)blockIdx.x * BLOCK + threadIdx.x;; j += stride) {
-        if (!NBW && j >= n) break;
+    int par = 0;
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x, par ^= 1) {
+        const int j = tile * BLOCK + (int)threadIdx.x;
         bool ev = false;
         V3<double> E = {0, 0, 0}, B = {0, 0, 0};
         if (j < n && a.G.alive[j]) {
@@ -631,7 +687,7 @@ __global__ __launch_bounds__(BLOCK) void k_photons_decide(PhotonArgs a) {
                 T Ja, kappa;
                 const double P = nbw_prob<T>(a.c, tb, eps, chi, xi.z, Ja, kappa, st);
                 double rr[4];
-                uniform4(a.G.id[j], step, STREAM_NBW, a.c.seed, rr);
+                uniform4(at(a.G.id, o), step, STREAM_NBW, a.c.seed, rr);
                 ev = Ja > (T)0 && rr[1] < P;
             }
             st_nt(xi1, os, xi.x); st_nt(xi2, os, xi.y); st_nt(xi3, os, xi.z);
@@ -647,10 +703,9 @@ __global__ __launch_bounds__(BLOCK) void k_photons_decide(PhotonArgs a) {
         }
         if constexpr (NBW) {
             int total;
-            const int rank = block_rank(ev, total, s_wave);
-            if (ev) stage(a.stg, (int64_t)blockIdx.x * BLOCK + rank, j, E, B);
-            if (threadIdx.x == 0) a.tile_counts[blockIdx.x] = total;
-            break;   // one tile per block
+            const int rank = block_rank(ev, total, s_wave[par]);
+            if (ev) stage(a.stg, (int64_t)tile * BLOCK + rank, j, E, B);
+            if (threadIdx.x == 0) a.tile_counts[tile] = total;
         }
     }
     if (st) atomicOr(a.status, st);
@@ -759,17 +814,20 @@ static int stride_grid(int64_t cap, int64_t limit) {
     if (b > limit) b = limit;
     return b < 1 ? 1 : (int)b;
 }
-static hipError_t launch_scan(qed_ctx *ctx, const int64_t *in_count, int64_t in_cap, int *counts, int clear,
-                              int unit, int64_t *c0, int64_t cap0, int64_t *c1, int64_t cap1, int ids,
+// scan of per-tile counts (256 particles per unit) of a list of capacity in_cap
+static hipError_t launch_scan(qed_ctx *ctx, const int64_t *in_count, int64_t in_cap, const int *counts,
+                              int64_t *c0, int64_t cap0, int64_t *c1, int64_t cap1, int ids,
                               hipStream_t s, int zero_base = 0, int64_t *base_out = nullptr,
-                              int64_t *off = nullptr, int64_t *launch = nullptr) {
+                              int64_t *off = nullptr, int64_t *launch = nullptr, int unit = BLOCK,
+                              int64_t *sums = nullptr, int clear = 0) {
     ScanArgs sa{};
+    sa.clear = clear;
     sa.zero_base = zero_base;
     sa.base_out = base_out;
     sa.counts = counts;
-    sa.clear = clear;
     sa.off = off ? off : ctx->tile_off;
     sa.unit = unit;
+    sa.sums = sums ? sums : ctx->scan_sums;
     sa.in_count = in_count;
     sa.in_capacity = in_cap;
     sa.out_count[0] = c0;
@@ -780,8 +838,32 @@ static hipError_t launch_scan(qed_ctx *ctx, const int64_t *in_count, int64_t in_
     sa.ids_per_event = ids;
     sa.launch = launch ? launch : ctx->launch;
     sa.status = ctx->status;
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(SCAN_THREADS), 0, s, sa);
+    // every pointer the kernel dereferences unconditionally must be set before a launch
+    if (!sa.counts || !sa.off || !sa.sums || !sa.next_id || !sa.launch || !sa.status || unit < 1)
+        return hipErrorInvalidValue;
+    const int64_t units = (in_cap + unit - 1) / unit;
+    if (units <= SCAN_ONE_BLOCK) {   // one block, one launch
+        sa.chunk = (units + SCAN_ONE_THREADS - 1) / SCAN_ONE_THREADS * SCAN_ONE_THREADS;
+        if (sa.chunk < SCAN_ONE_THREADS) sa.chunk = SCAN_ONE_THREADS;
+        hipLaunchKernelGGL(k_scan<SCAN_ONE_THREADS>, dim3(1), dim3(SCAN_ONE_THREADS), 0, s, sa);
+        return hipGetLastError();
+    }
+    // blocks of at least SCAN_MIN_CHUNK units, at most SCAN_MAX_BLOCKS of them
+    int64_t nb = (units + SCAN_MIN_CHUNK - 1) / SCAN_MIN_CHUNK;
+    nb = nb > SCAN_MAX_BLOCKS ? SCAN_MAX_BLOCKS : nb;
+    int64_t chunk = (units + nb - 1) / nb;
+    chunk = (chunk + SCAN_THREADS - 1) / SCAN_THREADS * SCAN_THREADS;
+    sa.chunk = chunk;
+    hipLaunchKernelGGL(k_scan_sums, dim3((unsigned)nb), dim3(SCAN_THREADS), 0, s, sa);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_scan<SCAN_THREADS>, dim3((unsigned)nb), dim3(SCAN_THREADS), 0, s, sa);
     return hipGetLastError();
+}
+
+hipError_t launch_scan_ints(qed_ctx *ctx, const int *counts, int64_t n, int64_t *off, int64_t *total,
+                            int64_t *launch, hipStream_t s) {
+    return launch_scan(ctx, nullptr, n, counts, total, (int64_t)1 << 62, nullptr, 0, 0, s, 1, nullptr, off, launch, 1);
 }
 
 // decide + scan + events of a step with NCS; FK as in fields_for (PUSH = false: fields
@@ -825,9 +907,10 @@ static hipError_t launch_ncs(qed_ctx *ctx, const LeptonArgs &a0, hipStream_t s) 
     if (ctx->tune.rate_lds) hipLaunchKernelGGL((k_leptons_decide<T, PUSH, FK, true>), gd, dim3(BLOCK), 0, s, a);
     else hipLaunchKernelGGL((k_leptons_decide<T, PUSH, FK, false>), gd, dim3(BLOCK), 0, s, a);
     if ((e = hipGetLastError()) != hipSuccess || (e = mark(1)) != hipSuccess) return e;
-    e = launch_scan(ctx, a.n_in ? a.n_in : a.L.count, a.L.capacity, a.group_tot, 1, BLOCK * a.ev_group,
+    e = launch_scan(ctx, a.n_in ? a.n_in : a.L.count, a.L.capacity, a.group_tot,
                     a.has_out ? a.out.count : nullptr, a.has_out ? a.out.capacity : 0, nullptr, 0, 1, s, 0, nullptr,
-                    const_cast<int64_t *>(a.tile_off), const_cast<int64_t *>(a.launch));
+                    const_cast<int64_t *>(a.tile_off), const_cast<int64_t *>(a.launch), BLOCK * a.ev_group,
+                    a.scan_sums, 1);
     if (e != hipSuccess || (e = mark(2)) != hipSuccess) return e;
     switch (a.ev_group) {
     case 4: e = launch_events<T, 4>(ctx, a, s); break;
@@ -893,6 +976,7 @@ hipError_t launch_leptons(qed_ctx *ctx, LeptonMode mode, const SegArgs &sa, cons
     a.group_tot = ss ? ss->group_tot : ctx->group_tot;
     a.tile_off = ss ? ss->tile_off : ctx->tile_off;
     a.launch = ss ? ss->launch : ctx->launch;
+    a.scan_sums = ss ? ss->sums : ctx->scan_sums;
     a.ev_in = ctx->ev_in;
     a.ev_out = ctx->ev_out;
     const bool multi = sa.nseg > 1;
@@ -904,26 +988,27 @@ hipError_t launch_leptons(qed_ctx *ctx, LeptonMode mode, const SegArgs &sa, cons
     return multi ? launch_leptons_t<double, true>(ctx, mode, a, s) : launch_leptons_t<double, false>(ctx, mode, a, s);
 }
 
+// persistent photon grid: PHOTON_BLOCKS_PER_CU blocks per compute unit, at most one per tile
+constexpr int PHOTON_BLOCKS_PER_CU = 8;
 template <class T, int FK>
-static void launch_photons_decide(const PhotonArgs &a, hipStream_t s) {
-    if (!a.do_nbw)
-        hipLaunchKernelGGL((k_photons_decide<T, false, FK>), dim3(stride_grid(a.G.capacity, 65536)), dim3(BLOCK), 0, s,
-                           a);
-    else
-        hipLaunchKernelGGL((k_photons_decide<T, true, FK>), dim3(tiles_grid(a.G.capacity)), dim3(BLOCK), 0, s, a);
+static void launch_photons_decide(const qed_ctx *ctx, const PhotonArgs &a, hipStream_t s) {
+    const int64_t ntiles = (a.G.capacity + BLOCK - 1) / BLOCK, pg = (int64_t)PHOTON_BLOCKS_PER_CU * ctx->num_cu;
+    const dim3 gd((unsigned)(ntiles < 1 ? 1 : (ntiles < pg ? ntiles : pg)));
+    if (!a.do_nbw) hipLaunchKernelGGL((k_photons_decide<T, false, FK>), gd, dim3(BLOCK), 0, s, a);
+    else hipLaunchKernelGGL((k_photons_decide<T, true, FK>), gd, dim3(BLOCK), 0, s, a);
 }
 template <class T>
 static hipError_t launch_photons_stage(qed_ctx *ctx, const PhotonArgs &a, hipStream_t s, int64_t *lep_start) {
     switch (a.field.kind) {
-    case QED_FIELD_CONST: launch_photons_decide<T, QED_FIELD_CONST>(a, s); break;
-    case QED_FIELD_PW: launch_photons_decide<T, QED_FIELD_PW>(a, s); break;
-    case QED_FIELD_GAUSS: launch_photons_decide<T, QED_FIELD_GAUSS>(a, s); break;
-    case QED_FIELD_GRID2D: launch_photons_decide<T, QED_FIELD_GRID2D>(a, s); break;
-    default: launch_photons_decide<T, QED_FIELD_NONE>(a, s); break;
+    case QED_FIELD_CONST: launch_photons_decide<T, QED_FIELD_CONST>(ctx, a, s); break;
+    case QED_FIELD_PW: launch_photons_decide<T, QED_FIELD_PW>(ctx, a, s); break;
+    case QED_FIELD_GAUSS: launch_photons_decide<T, QED_FIELD_GAUSS>(ctx, a, s); break;
+    case QED_FIELD_GRID2D: launch_photons_decide<T, QED_FIELD_GRID2D>(ctx, a, s); break;
+    default: launch_photons_decide<T, QED_FIELD_NONE>(ctx, a, s); break;
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !a.do_nbw) return e;
-    e = launch_scan(ctx, a.G.count, a.G.capacity, ctx->tile_counts, 0, BLOCK, a.has_em ? a.em.count : nullptr,
+    e = launch_scan(ctx, a.G.count, a.G.capacity, ctx->tile_counts, a.has_em ? a.em.count : nullptr,
                     a.has_em ? a.em.capacity : 0, a.has_ep ? a.ep.count : nullptr, a.has_ep ? a.ep.capacity : 0, 2, s,
                     0, lep_start);
     if (e != hipSuccess) return e;
@@ -1018,8 +1103,7 @@ hipError_t launch_compact(qed_ctx *ctx, const qed_photons &in, const qed_photons
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     // the live photons replace the contents of `out` (its count on entry is not a base)
-    e = launch_scan(ctx, in.count, in.capacity, ctx->tile_counts, 0, BLOCK, out.count, out.capacity, nullptr, 0, 0, s,
-                    1);
+    e = launch_scan(ctx, in.count, in.capacity, ctx->tile_counts, out.count, out.capacity, nullptr, 0, 0, s, 1);
     if (e != hipSuccess) return e;
     if (ctx->cfg.precision == QED_MIXED)
         hipLaunchKernelGGL(k_compact_copy<float>, dim3(stride_grid(in.capacity, 2048)), dim3(BLOCK), 0, s, a);

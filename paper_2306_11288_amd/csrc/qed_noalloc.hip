@@ -12,14 +12,17 @@ namespace {
 
 constexpr int64_t NA_TILES = NOALLOC_MAX / BLOCK;
 constexpr int64_t al256(int64_t b) { return (b + 255) / 256 * 256; }
-// layout: staging slots, tile counts, group totals (smallest group: 4 tiles), offsets, bases
+// layout: staging slots, tile counts, group totals (smallest group: 4 tiles), offsets,
+// bases, scan block totals.  The group totals are accumulated by atomics and must start at
+// zero; every other part is written before it is read within a call.
 constexpr int64_t NA_OFF_STAGING = 0;
 constexpr int64_t NA_OFF_COUNTS = NA_OFF_STAGING + al256(NOALLOC_MAX * (int64_t)STAGING_SLOT);
 constexpr int64_t NA_GROUPS = NA_TILES / 4 + 1;
 constexpr int64_t NA_OFF_GROUPS = NA_OFF_COUNTS + al256(NA_TILES * 4);
 constexpr int64_t NA_OFF_TILEOFF = NA_OFF_GROUPS + al256(NA_GROUPS * 4);
 constexpr int64_t NA_OFF_LAUNCH = NA_OFF_TILEOFF + al256((NA_TILES + 1) * 8);
-constexpr int64_t NA_BYTES = NA_OFF_LAUNCH + al256(4 * 8);
+constexpr int64_t NA_OFF_SUMS = NA_OFF_LAUNCH + al256(4 * 8);
+constexpr int64_t NA_BYTES = NA_OFF_SUMS + al256(SCAN_MAX_BLOCKS * 8);
 
 static __device__ __align__(256) unsigned char scratch[NA_BYTES];
 
@@ -59,12 +62,13 @@ ScanState noalloc_state(void *base) {
     ss.group_tot = (int *)(b + NA_OFF_GROUPS);
     ss.tile_off = (int64_t *)(b + NA_OFF_TILEOFF);
     ss.launch = (int64_t *)(b + NA_OFF_LAUNCH);
+    ss.sums = (int64_t *)(b + NA_OFF_SUMS);
     return ss;
 }
 
-// The group totals are accumulated by integer atomics and must start at zero; the scan
-// clears what it reads, but the array keeps whatever an earlier (possibly interrupted)
-// call left, so every call clears them first (a kernel, not a memset: capturable).
+// The group totals must start at zero.  The scan clears what it reads, but the array keeps
+// whatever an earlier (possibly interrupted) call left, so every call clears them first (a
+// kernel, not a memset: capturable).
 hipError_t noalloc_clear(const ScanState &ss, hipStream_t s) {
     hipLaunchKernelGGL(k_zero_i32, dim3(2), dim3(256), 0, s, ss.group_tot, (int)NA_GROUPS);
     return hipGetLastError();

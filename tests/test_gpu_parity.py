@@ -129,6 +129,20 @@ def test_c1_plane_wave_lp_fp64(mode):
     assert ctx.read_status() == sim.status
 
 
+def test_c1_full_length_fp64():
+    """The plane-wave workload in full: 1e4 electrons through all 3000 steps (the whole
+    8-cycle pulse and the free flight after it), FP64 GPU against the oracle to 1e-10 with
+    identical event decisions, photon order and ids."""
+    _say("c1 full length: 1e4 electrons x 3000 steps")
+    cfg = W.c1(10000, start_step=0)
+    L, G, sim, Lg, Gg, ctx = _run_leptons(cfg, 10000, cfg["steps"], "fused", cap_factor=8)
+    assert G.count > 10000, G.count
+    _close_lep(Lg.to_numpy(), L.view(), what="leptons")
+    _close_pho(Gg.to_numpy(), _oracle_photons(G), what="photons")
+    assert ctx.next_id() == sim.next_id
+    assert ctx.read_status() == sim.status == 0
+
+
 def test_c2_focused_cp_stokes_fp64():
     _say("c2 focused CP fp64 with Stokes")
     cfg = W.c2(3000, start_step=2300)

@@ -1,10 +1,11 @@
-"""Ordered stream compaction of photon lists whose tile count passes the scan kernel's
-register path.  Each of the scan's 1024 threads keeps the first 8 counts of its run in
-registers between its two passes; past 8192 tiles of 256 photons a run is longer and the
-rest is read again.  For lists just at, just past and well past that size, the compacted
-list must hold the alive photons in index order, every array bit for bit, with an exact
-count.  The expected result is numpy's boolean selection, which is the plain definition
-of a stable compaction."""
+"""Ordered stream compaction of photon lists at the sizes where the scan's block layout
+changes.  The scan kernel gives each block a chunk of at least 2048 tiles of 256 photons
+(at most 64 blocks, larger chunks beyond that) and each block sums the tiles before its
+chunk itself.  For lists inside one chunk, at a chunk boundary, across several chunks and
+with a capacity large enough to lengthen the chunks (and for an empty list), the
+compacted list must hold the alive photons in index order, every array bit for bit, with
+an exact count.  The expected result is numpy's boolean selection, which is the plain
+definition of a stable compaction."""
 import numpy as np
 import pytest
 
@@ -32,15 +33,18 @@ def _photon_state(n, seed, alive_frac):
     return st
 
 
-@pytest.mark.parametrize("n,prec", [(8192 * 256, Q.QED_FP64), (8192 * 256 + 1, Q.QED_FP64),
-                                    (3_000_077, Q.QED_FP64), (3_000_077, Q.QED_MIXED)],
-                         ids=["8192-tiles", "8192-tiles+1", "11719-tiles", "11719-tiles-mixed"])
-def test_compaction_past_the_register_path(n, prec):
-    _say(f"compact n={n} prec={prec}")
+@pytest.mark.parametrize("n,prec,cap", [(1000 * 256 + 17, Q.QED_FP64, None), (2048 * 256, Q.QED_FP64, None),
+                                        (2048 * 256 + 1, Q.QED_FP64, None), (3_000_077, Q.QED_FP64, None),
+                                        (3_000_077, Q.QED_MIXED, None), (3_000_077, Q.QED_FP64, 40_000_000),
+                                        (0, Q.QED_FP64, 1000)],
+                         ids=["1001-tiles", "2048-tiles", "2048-tiles+1", "11719-tiles", "11719-tiles-mixed",
+                              "11719-tiles-long-chunks", "empty"])
+def test_compaction_across_scan_blocks(n, prec, cap):
+    _say(f"compact n={n} prec={prec} capacity={cap}")
     st = _photon_state(n, seed=n % 1000 + prec, alive_frac=0.61)
     keep = st["alive"].astype(bool)
-    src = Q.Photons.from_state(st, precision=prec)
-    dst = Q.Photons(n, precision=prec)
+    src = Q.Photons.from_state(st, capacity=cap, precision=prec)
+    dst = Q.Photons(max(n, 1), precision=prec)
     ctx = Q.Context(dt=0.01, procs=Q.PROC_VB, seed=1, id_start=0, precision=prec)
     ctx.compact_photons(src, dst)
     torch.cuda.synchronize()
