@@ -272,6 +272,10 @@ def run_batched(args, torch, Q, W):
 
 MLP_FLOP = 2 * (4 * 128 + 2 * 128 * 128 + 128 * 3)   # multiply-adds x 2 per sample (forward)
 MFMA_BF16_PEAK_TFLOPS = 2500.0
+# training, matrix-core work per sample: the two 128 x 128 layers forward, backward through
+# the activations, and their weight gradients (the VALU layers 1 and 4 not counted)
+MLP_TRAIN_MFMA_FLOP = 3 * 2 * (2 * 128 * 128)
+MFMA_FP32_PEAK_TFLOPS = 157.3
 
 
 def run_learned(args, torch, Q, W, cfg, fp64, fp64_b=None):
@@ -320,6 +324,30 @@ def run_learned(args, torch, Q, W, cfg, fp64, fp64_b=None):
     }
     del X, T64, Y
     c2 = Q.Context(dt=0.01, procs=Q.PROC_NCS | Q.PROC_NCS_STOKES, seed=1, id_start=0, precision=Q.QED_MIXED)
+    # the training step alone (three launches: forward + backward through the activations,
+    # weight gradients, ordered sum + Adam), pairs resident, at the trainer's batch and at
+    # a batch that fills the chip
+    c2.mlp_init(seed=4)
+    Xt, Tt = c2.mlp_samples(1 << 20, seed=6)
+    lossb = torch.empty(1, dtype=torch.float32, device="cuda")
+    steps_out = {}
+    for B in (8192, 65536):
+        reps = 20
+
+        def run_steps():
+            for k in range(reps):
+                j = (k * B) % (Xt.shape[0] - B + 1)
+                c2.mlp_train_step(Xt[j:j + B], Tt[j:j + B], 1e-5, (1.0, 0.3, 0.3), lossb)
+        run_steps()
+        ms = best_ms(run_steps, reps=3) / reps
+        tf = MLP_TRAIN_MFMA_FLOP * B / (ms * 1e-3) / 1e12
+        steps_out[str(B)] = {"us_per_step": 1e3 * ms, "samples_per_s": B / (ms * 1e-3),
+                             "roofline": {"bound": "mfma", "achieved": tf, "peak": MFMA_FP32_PEAK_TFLOPS,
+                                          "unit": "TFLOP/s", "frac": tf / MFMA_FP32_PEAK_TFLOPS,
+                                          "flop_per_sample": MLP_TRAIN_MFMA_FLOP,
+                                          "kernels": "k_train_fb + k_train_dw (FP32 MFMA 32x32x2) + k_train_reduce"}}
+    out["training_step"] = steps_out
+    del Xt, Tt
     tr = train(c2, n_samples=args.train_samples, epochs=1.0, batch=8192, seed=5)
     out["training"] = {"samples": tr["samples"], "steps": tr["steps"], "batch": tr["batch"], "seconds": tr["seconds"],
                        "samples_per_s": tr["samples"] / tr["seconds"], "val_mae_after": tr["val_after"]["mae"],

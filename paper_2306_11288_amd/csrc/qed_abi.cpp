@@ -235,6 +235,7 @@ void free_ctx(qed_ctx *c) {
     hipFree(c->mlp_v);
     hipFree(c->mlp_G);
     hipFree(c->mlp_WT);
+    hipFree(c->mlp_W32);
     hipFree(c->mlp_work);
     hipFree(c->hist_rep);
     hipFree(c->dep_cnt);
@@ -971,10 +972,13 @@ qed_status qed_mlp_gradient(qed_ctx_t *ctx, const float *X, const float *T, int6
 
 qed_status qed_mlp_train_step(qed_ctx_t *ctx, const float *X, const float *T, int64_t n, const float *w, float lr,
                               float *loss_out, hipStream_t s) {
-    qed_status st = qed_mlp_gradient(ctx, X, T, n, w, nullptr, loss_out, s);
+    qed_status st = ready(ctx);
     if (st != QED_OK) return st;
+    if (!ctx->mlp_P) return fail(ctx, QED_ESTATE, "qed_mlp_train_step: no network (qed_mlp_init first)");
+    if (n < 1 || n > (1 << 24) || !X || !T || !w || !loss_out)
+        return fail(ctx, QED_EARG, "qed_mlp_train_step: bad arguments (1 <= n <= 2^24)");
     if (!(lr > 0)) return fail(ctx, QED_EARG, "qed_mlp_train_step: lr must be positive");
-    return launched(ctx, mlp_adam(ctx, lr, s), "qed_mlp_train_step");
+    return launched(ctx, mlp_train(ctx, X, T, n, w, lr, loss_out, s), "qed_mlp_train_step");
 }
 
 qed_status qed_sampler_table(qed_ctx_t *ctx, const float *X, float *Y, int64_t n, hipStream_t s) {

@@ -201,6 +201,7 @@ struct qed_ctx {
     // learned sampler
     float *mlp_P, *mlp_m, *mlp_v, *mlp_G;   // parameters, Adam moments, gradient [MLP_NPARAM]
     void *mlp_WT;                      // bf16 transposed W2, W3 for the forward kernel
+    float *mlp_W32;                    // FP32 transposed W2, W3 for the backward pass
     int mlp_t;                         // Adam step count
     float *mlp_work;                   // training work buffers
     int64_t mlp_work_len;
@@ -299,6 +300,7 @@ hipError_t mlp_forward(qed_ctx *ctx, const float *X, float *Y, int64_t n, const 
                        hipStream_t s);
 hipError_t mlp_grad(qed_ctx *ctx, const float *X, const float *T, int64_t n, const float w[3], float *loss,
                     hipStream_t s);
-hipError_t mlp_adam(qed_ctx *ctx, float lr, hipStream_t s);
+hipError_t mlp_train(qed_ctx *ctx, const float *X, const float *T, int64_t n, const float w[3], float lr,
+                     float *loss, hipStream_t s);
 hipError_t table_sampler_run(qed_ctx *ctx, const float *X, float *Y, int64_t n, hipStream_t s);
 }  // namespace qed

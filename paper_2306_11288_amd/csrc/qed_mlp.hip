@@ -8,8 +8,9 @@
 //     accumulation for the two 128 x 128 layers, weights and activations in LDS;
 //   * training data: k_mlp_samples draws inputs with Philox and computes the targets with
 //     the FP64 tables and the F formulas of the library itself;
-//   * training: FP32 kernels (tiled GEMM with a deterministic split-K for the weight
-//     gradients, SiLU and its derivative, loss, column sums, Adam).
+//   * training: three FP32 launches per step, the dense layers on FP32 matrix cores
+//     (v_mfma_f32_32x32x2_f32), the weight gradients split over the batch and summed in a
+//     fixed order, Adam fused with the sum.
 #include "qed_dev.hpp"
 
 namespace qed {
@@ -238,135 +239,388 @@ __global__ void k_mlp_pack(const float *P, __bf16 *WT) {
 }
 
 // ------------------------------------------------------------------------- training (FP32)
-// C[m][n] (+)= sum_k A(m, k) B(k, n) over k in [k0, k1), A(m, k) = A[m sam + k sak],
-// B(k, n) = B[k sbk + n sbn]; 64 x 64 tile per block (256 threads, 4 x 4 outputs each),
-// K in chunks of 16 through LDS.  Epilogue: + bias[n] if bias; Z stored to C; if H, also
-// H = SiLU(C).  Split-K: blockIdx.z selects a K slice, C += ldc_slice * z.
-struct GemmArgs {
-    const float *A, *B, *bias;
-    float *C, *H;
-    int M, N, K;
-    int64_t sam, sak, sbk, sbn;
-    int ldc;
-    int kslice;            // K per slice (split-K), K if no split
-    int64_t slice_stride;  // floats between the C slices
+// Three launches per step, the dense layers on FP32 matrix cores (v_mfma_f32_32x32x2_f32:
+// FP32 operands, FP32 accumulation), everything else on the vector unit in FP32:
+//  k_train_fb     one block per tile of 32 samples, each wavefront owning 32 of the 128
+//                 outputs of a layer: forward (layers 1 and 4 on the VALU, 2 and 3 on the
+//                 matrix cores), the loss and its gradient dY, and the backward pass through
+//                 the activations (dZ3 = dY W4^T * SiLU'(Z3); dZ2 = dZ3 W3^T * SiLU'(Z2) and
+//                 dZ1 = dZ2 W2^T * SiLU'(Z1) on the matrix cores).  A layer's input tile sits
+//                 in LDS; H1, H2, H3, dZ1, dZ2, dZ3 and dY go to global memory feature-major
+//                 ([feature][sample]) for the weight gradients, with the tile's loss.
+//  k_train_dw     the weight and bias gradients as sums over TR_NS slices of consecutive
+//                 samples: dW2 = H1^T dZ2 and dW3 = H2^T dZ3 on the matrix cores (TR_CH-sample
+//                 chunks of both operands staged in LDS, 32 input rows per block), dW1 = X^T
+//                 dZ1, dW4 = H3^T dY and the bias gradients on the VALU; each slice writes its
+//                 partial sums.
+//  k_train_reduce per parameter the sum of the slice partials in slice order, and the loss as
+//                 a fixed-order sum of the tile losses, so results do not depend on
+//                 scheduling; when training, the Adam update and the copies of the weights
+//                 the kernels read (W2, W3 transposed in FP32 for the backward pass, and in
+//                 bf16 for inference).
+// Matrix-core operand layout: lane l supplies A[l % 32][k + l / 32] and B[k + l / 32][l % 32]
+// and holds D[8 (v / 4) + 4 (l / 32) + v % 4][l % 32] in accumulator v.
+constexpr int TR_NS = 64;         // batch slices of the weight gradients
+constexpr int TR_CH = 64;         // samples per staged chunk of the weight gradients
+constexpr int TR_TP = 129;        // LDS row of a tile (floats): a column read hits distinct banks
+constexpr int TR_CP = TR_CH + 1;  // LDS row of a staged chunk
+
+struct TrainArgs {
+    const float *P;                   // parameters (flat)
+    const float *W2T, *W3T;           // W2, W3 transposed ([out][in]) in FP32
+    const float *X, *T;               // [n][4], [n][3]
+    int64_t n, Bp;                    // samples; the padded batch (a multiple of TR_NS TR_CH)
+    float w0, w1, w2;                 // loss weights
+    float *H1T, *H2T, *H3T, *dZ1T, *dZ2T, *dZ3T;   // [128][Bp]
+    float *dYT;                       // [3][Bp]
+    float *lossp;                     // per 32-sample tile
+    float *part;                      // [TR_NS][MLP_NPARAM]
 };
 
-__global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
-    __shared__ float sA[16][65], sBt[16][65];
-    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-    const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
-    const int kb = blockIdx.z * g.kslice, ke = kb + g.kslice < g.K ? kb + g.kslice : g.K;
-    const bool a_k_fast = g.sak == 1 && g.sam != 1, b_k_fast = g.sbk == 1 && g.sbn != 1;
-    float acc[4][4] = {};
-    for (int k0 = kb; k0 < ke; k0 += 16) {
-        // consecutive threads walk the operand's contiguous dimension (coalesced loads)
-        for (int e = threadIdx.x; e < 16 * 64; e += 256) {
-            const int kk = a_k_fast ? e % 16 : e / 64, mm = a_k_fast ? e / 16 : e % 64;
-            const int m = m0 + mm, k = k0 + kk;
-            sA[kk][mm] = (m < g.M && k < ke) ? g.A[(int64_t)m * g.sam + (int64_t)k * g.sak] : 0.0f;
-            const int kb2 = b_k_fast ? e % 16 : e / 64, nn = b_k_fast ? e / 16 : e % 64;
-            const int n = n0 + nn, k2 = k0 + kb2;
-            sBt[kb2][nn] = (n < g.N && k2 < ke) ? g.B[(int64_t)k2 * g.sbk + (int64_t)n * g.sbn] : 0.0f;
-        }
-        __syncthreads();
+// row of accumulator v (within a 32 x 32 block) for this lane's half h
+__device__ __forceinline__ int acc_row(int v, int h) { return 8 * (v >> 2) + 4 * h + (v & 3); }
+
+// acc[v] += sum over in of W[in][o0 + row] Bt[j][in]: outputs o0 .. o0+31 of a 128 x 128
+// layer for the 32 samples of the tile Bt (LDS, [sample][in]); W row-major [in][out] from
+// global memory (L2 resident) through buffer loads (one lane offset register, the row in
+// a scalar offset), 16 weights in flight while the previous 16 products run
+__device__ __forceinline__ void wload(float *w, __amdgpu_buffer_rsrc_t rs, int vo, int k0) {
 #pragma unroll
-        for (int kk = 0; kk < 16; ++kk) {
-            float av[4], bv[4];
+    for (int i = 0; i < 16; ++i)
+        w[i] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, vo, (k0 + 2 * i) * 512, 0));
+}
+__device__ __forceinline__ f32x16 wmul(const float *w, const float *br, int k0, f32x16 acc) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) av[i] = sA[kk][ty * 4 + i];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) bv[j] = sBt[kk][tx * 4 + j];
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] += av[i] * bv[j];
-        }
-        __syncthreads();
-    }
-    float *C = g.C + (int64_t)blockIdx.z * g.slice_stride;
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int m = m0 + ty * 4 + i, n = n0 + tx * 4 + j;
-            if (m >= g.M || n >= g.N) continue;
-            const float z = acc[i][j] + (g.bias ? g.bias[n] : 0.0f);
-            C[(int64_t)m * g.ldc + n] = z;
-            if (g.H) g.H[(int64_t)m * g.ldc + n] = silu(z);
-        }
+    for (int i = 0; i < 16; ++i) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(w[i], br[k0 + 2 * i], acc, 0, 0, 0);
+    return acc;
+}
+__device__ __forceinline__ f32x16 tile_layer(const float *__restrict__ W, const float *Bt, int o0, int j, int h,
+                                             f32x16 acc) {
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void *)W, 0, 128 * 128 * 4, 0x00020000);
+    const int vo = (h * 128 + o0 + j) * 4;
+    const float *br = Bt + j * TR_TP + h;
+    float wa[16], wb[16];
+    wload(wa, rs, vo, 0);
+    wload(wb, rs, vo, 32);
+    acc = wmul(wa, br, 0, acc);
+    __builtin_amdgcn_sched_barrier(0);
+    wload(wa, rs, vo, 64);
+    acc = wmul(wb, br, 32, acc);
+    __builtin_amdgcn_sched_barrier(0);
+    wload(wb, rs, vo, 96);
+    acc = wmul(wa, br, 64, acc);
+    __builtin_amdgcn_sched_barrier(0);
+    return wmul(wb, br, 96, acc);
 }
 
-// dY = 2 w (Y - T) / B; loss partial sums per block
-__global__ __launch_bounds__(256) void k_loss(const float *Y, const float *T, int64_t n, float w0, float w1, float w2,
-                                              float *dY, float *part) {
-    __shared__ float s[256];
-    const float w[3] = {w0, w1, w2};
-    float acc = 0;
-    for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < n * 3; k += (int64_t)gridDim.x * 256) {
-        const float d = Y[k] - T[k], wk = w[k % 3];
-        acc += wk * d * d;
-        dY[k] = 2.0f * wk * d / (float)n;
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_train_fb(TrainArgs a) {
+    __shared__ float sA[32 * TR_TP], sC[32 * TR_TP];
+    __shared__ float sW1[4 * 128], sB[3 * 128], sW4[128 * 3], sB4[4], sY[4][32][3];
+    const int tid = threadIdx.x;
+    for (int k = tid; k < 4 * 128; k += 256) sW1[k] = a.P[MLP_OW1 + k];
+    for (int k = tid; k < 128; k += 256) {
+        sB[k] = a.P[MLP_OB1 + k];
+        sB[128 + k] = a.P[MLP_OB2 + k];
+        sB[256 + k] = a.P[MLP_OB3 + k];
     }
-    s[threadIdx.x] = acc;
+    for (int k = tid; k < 128 * 3; k += 256) sW4[k] = a.P[MLP_OW4 + k];
+    if (tid < 3) sB4[tid] = a.P[MLP_OB4 + tid];
     __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+    const float inv_n = 1.0f / (float)a.n, wl[3] = {a.w0, a.w1, a.w2};
+    const int64_t ntile = a.Bp / 32;
+    for (int64_t tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
+        // the thread index and the row stride taken afresh in every tile: otherwise the
+        // row indices and store addresses (the same in every tile) are computed once before
+        // the loop and held in ~200 registers for its whole length
+        int tid = threadIdx.x;
+        int64_t Bp = a.Bp;
+        asm volatile("" : "+v"(tid), "+s"(Bp));
+        const int lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6), j = lane & 31, h = lane >> 5,
+                  o0 = wv * 32;
+        const int64_t base = tile * 32;
+        {   // layer 1 (VALU): thread -> sample tid % 32, outputs 16 (tid / 32) .. +16
+            const int s = tid & 31, q0 = (tid >> 5) * 16;
+            const int64_t smp = base + s;
+            float x[4] = {0, 0, 0, 0};
+            if (smp < a.n) {
+                const float4 v = ((const float4 *)a.X)[smp];
+                x[0] = v.x; x[1] = v.y; x[2] = v.z; x[3] = v.w;
+            }
+            for (int q = q0; q < q0 + 16; ++q) {
+                float z = sB[q];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) z += x[i] * sW1[i * 128 + q];
+                const float hv = silu(z);
+                sA[s * TR_TP + q] = hv;
+                a.H1T[(int64_t)q * Bp + smp] = hv;
+            }
+        }
         __syncthreads();
+        const int64_t smp = base + j;    // this lane's sample from here on
+        const bool live = smp < a.n;
+        // layer 2: H1 (sA) -> H2 (sC); Z2 stays in registers for SiLU'(Z2)
+        f32x16 z2, z3, g;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) z2[v] = sB[128 + o0 + acc_row(v, h)];
+        z2 = tile_layer(a.P + MLP_OW2, sA, o0, j, h, z2);
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int o = o0 + acc_row(v, h);
+            const float hv = silu(z2[v]);
+            a.H2T[(int64_t)o * Bp + smp] = hv;
+            sC[j * TR_TP + o] = hv;
+        }
+        __syncthreads();
+        // layer 3: H2 (sC) -> H3; layer 4 partial sums over this wave's 32 outputs
+#pragma unroll
+        for (int v = 0; v < 16; ++v) z3[v] = sB[256 + o0 + acc_row(v, h)];
+        z3 = tile_layer(a.P + MLP_OW3, sC, o0, j, h, z3);
+        float y[3] = {0, 0, 0};
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int o = o0 + acc_row(v, h);
+            const float hv = silu(z3[v]);
+            a.H3T[(int64_t)o * Bp + smp] = hv;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) y[c] += hv * sW4[o * 3 + c];
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) y[c] += __shfl_xor(y[c], 32);
+        if (h == 0)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) sY[wv][j][c] = y[c];
+        __syncthreads();
+        // outputs, loss and dY (the four waves' partial sums added in a fixed order)
+        float dy[3], l = 0.0f;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const float yc = sB4[c] + ((sY[0][j][c] + sY[1][j][c]) + (sY[2][j][c] + sY[3][j][c]));
+            const float d = live ? yc - a.T[3 * smp + c] : 0.0f;
+            dy[c] = 2.0f * wl[c] * d * inv_n;
+            l += wl[c] * d * d;
+        }
+        if (wv == 0) {
+            if (h == 0)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) a.dYT[(int64_t)c * Bp + smp] = dy[c];
+            l = h == 0 ? l : 0.0f;
+#pragma unroll
+            for (int d = 32; d >= 1; d >>= 1) l += __shfl_xor(l, d);
+            if (lane == 0) a.lossp[tile] = l;
+        }
+        // dZ3 = (dY W4^T) * SiLU'(Z3) -> sA
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int o = o0 + acc_row(v, h);
+            const float dh = dy[0] * sW4[o * 3] + dy[1] * sW4[o * 3 + 1] + dy[2] * sW4[o * 3 + 2];
+            const float dz = dh * silu_prime(z3[v]);
+            a.dZ3T[(int64_t)o * Bp + smp] = dz;
+            sA[j * TR_TP + o] = dz;
+        }
+        __syncthreads();
+        // dZ2 = (dZ3 W3^T) * SiLU'(Z2) -> sC
+#pragma unroll
+        for (int v = 0; v < 16; ++v) g[v] = 0.0f;
+        g = tile_layer(a.W3T, sA, o0, j, h, g);
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int o = o0 + acc_row(v, h);
+            const float dz = g[v] * silu_prime(z2[v]);
+            a.dZ2T[(int64_t)o * Bp + smp] = dz;
+            sC[j * TR_TP + o] = dz;
+        }
+        __syncthreads();
+        // dZ1 = (dZ2 W2^T) * SiLU'(Z1), Z1 recomputed at this lane's outputs
+#pragma unroll
+        for (int v = 0; v < 16; ++v) g[v] = 0.0f;
+        g = tile_layer(a.W2T, sC, o0, j, h, g);
+        float x[4] = {0, 0, 0, 0};
+        if (live) {
+            const float4 xv = ((const float4 *)a.X)[smp];
+            x[0] = xv.x; x[1] = xv.y; x[2] = xv.z; x[3] = xv.w;
+        }
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int o = o0 + acc_row(v, h);
+            float z = sB[o];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) z += x[i] * sW1[i * 128 + o];
+            a.dZ1T[(int64_t)o * Bp + smp] = g[v] * silu_prime(z);
+        }
+        // the next tile's first writes (sA) follow this tile's last read of sA (before the
+        // barrier above); its next write of sC follows its own first barrier
     }
-    if (threadIdx.x == 0) part[blockIdx.x] = s[0];
-}
-__global__ void k_loss_total(const float *part, int nb, int64_t n, float *loss) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    float s = 0;
-    for (int k = 0; k < nb; ++k) s += part[k];
-    *loss = s / (float)n;
 }
 
-// dZ = dH * SiLU'(Z), elementwise
-__global__ void k_silu_back(const float *dH, const float *Z, float *dZ, int64_t n) {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < n) dZ[k] = dH[k] * silu_prime(Z[k]);
+// Weight and bias gradients of one batch slice (blockIdx.x).  blockIdx.y < 8: matrix
+// y / 4 (dW2 from H1, dZ2; dW3 from H2, dZ3), input rows 32 (y % 4) .. +32 on the matrix
+// cores, each wavefront 32 of the outputs, the next chunk loaded into registers while the
+// current one is multiplied; blockIdx.y = 8 + q: the small gradients of features
+// 32 q .. 32 q + 31 (VALU).
+constexpr int TR_DW_Y = 8 + 4;
+__global__ __launch_bounds__(256) void k_train_dw(TrainArgs a) {
+    __shared__ float sH[32 * TR_CP], sD[128 * TR_CP];
+    const int sl = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, j = lane & 31, h = lane >> 5;
+    const int64_t Bp = a.Bp, len = Bp / TR_NS, s0 = (int64_t)sl * len;
+    float *part = a.part + (int64_t)sl * MLP_NPARAM;
+    if (blockIdx.y < 8) {
+        const int m = blockIdx.y >> 2, rb = (blockIdx.y & 3) * 32;
+        const float *HT = m == 0 ? a.H1T : a.H2T, *DT = m == 0 ? a.dZ2T : a.dZ3T;
+        f32x16 acc;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
+        constexpr int Q = TR_CH / 4;                 // float4 per row of a chunk
+        constexpr int NH = 32 * Q / 256, ND = 128 * Q / 256;
+        float4 rh[NH], rd[ND];
+        auto fetch = [&](int64_t c0) {
+#pragma unroll
+            for (int i = 0; i < NH; ++i) {
+                const int e = tid + 256 * i, r = e / Q, c = (e % Q) * 4;
+                rh[i] = *(const float4 *)(HT + (int64_t)(rb + r) * Bp + c0 + c);
+            }
+#pragma unroll
+            for (int i = 0; i < ND; ++i) {
+                const int e = tid + 256 * i, r = e / Q, c = (e % Q) * 4;
+                rd[i] = *(const float4 *)(DT + (int64_t)r * Bp + c0 + c);
+            }
+        };
+        fetch(s0);
+        for (int64_t c0 = s0; c0 < s0 + len; c0 += TR_CH) {
+#pragma unroll
+            for (int i = 0; i < NH; ++i) {
+                const int e = tid + 256 * i;
+                float *d = sH + (e / Q) * TR_CP + (e % Q) * 4;
+                d[0] = rh[i].x; d[1] = rh[i].y; d[2] = rh[i].z; d[3] = rh[i].w;
+            }
+#pragma unroll
+            for (int i = 0; i < ND; ++i) {
+                const int e = tid + 256 * i;
+                float *d = sD + (e / Q) * TR_CP + (e % Q) * 4;
+                d[0] = rd[i].x; d[1] = rd[i].y; d[2] = rd[i].z; d[3] = rd[i].w;
+            }
+            __syncthreads();
+            if (c0 + TR_CH < s0 + len) fetch(c0 + TR_CH);
+            // D[in][out] += sum over the chunk's samples of H[in][s] dZ[out][s]
+#pragma unroll 8
+            for (int k = 0; k < TR_CH; k += 2)
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(sH[j * TR_CP + k + h], sD[(wv * 32 + j) * TR_CP + k + h], acc,
+                                                          0, 0, 0);
+            __syncthreads();
+        }
+        const int ow = m == 0 ? MLP_OW2 : MLP_OW3;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) part[ow + (rb + acc_row(v, h)) * 128 + wv * 32 + j] = acc[v];
+        return;
+    }
+    // small gradients: wavefront wv takes 8 features, its lanes stride over the slice's
+    // samples (all 8 features' loads of a sample in flight together) and the lanes' sums
+    // are added across the wavefront in a fixed pattern
+    constexpr int NR = 8;
+    const int f0 = (blockIdx.y - 8) * 32 + wv * NR;
+    float r[NR][10];          // dW1[0..3][o], db1, db2, db3, dW4[o][0..2]
+    float r4[3] = {0, 0, 0};  // db4 (kept by the first wavefront of feature block 0)
+#pragma unroll
+    for (int f = 0; f < NR; ++f)
+#pragma unroll
+        for (int q = 0; q < 10; ++q) r[f][q] = 0.0f;
+    for (int64_t k = s0 + lane; k < s0 + len; k += 64) {
+        float4 xv = {0, 0, 0, 0};
+        if (k < a.n) xv = ((const float4 *)a.X)[k];
+        const float dy0 = a.dYT[k], dy1 = a.dYT[Bp + k], dy2 = a.dYT[2 * Bp + k];
+        r4[0] += dy0; r4[1] += dy1; r4[2] += dy2;
+#pragma unroll
+        for (int f = 0; f < NR; ++f) {
+            const int64_t ro = (int64_t)(f0 + f) * Bp + k;
+            const float d1 = a.dZ1T[ro], hv = a.H3T[ro];
+            r[f][0] += xv.x * d1; r[f][1] += xv.y * d1; r[f][2] += xv.z * d1; r[f][3] += xv.w * d1;
+            r[f][4] += d1;
+            r[f][5] += a.dZ2T[ro];
+            r[f][6] += a.dZ3T[ro];
+            r[f][7] += hv * dy0; r[f][8] += hv * dy1; r[f][9] += hv * dy2;
+        }
+    }
+#pragma unroll
+    for (int f = 0; f < NR; ++f) {
+#pragma unroll
+        for (int q = 0; q < 10; ++q)
+#pragma unroll
+            for (int d = 32; d >= 1; d >>= 1) r[f][q] += __shfl_xor(r[f][q], d);
+        if (lane == 0) {
+            const int o = f0 + f;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) part[MLP_OW1 + i * 128 + o] = r[f][i];
+            part[MLP_OB1 + o] = r[f][4];
+            part[MLP_OB2 + o] = r[f][5];
+            part[MLP_OB3 + o] = r[f][6];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) part[MLP_OW4 + o * 3 + c] = r[f][7 + c];
+        }
+    }
+    if (f0 == 0) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+#pragma unroll
+            for (int d = 32; d >= 1; d >>= 1) r4[c] += __shfl_xor(r4[c], d);
+            if (lane == 0) part[MLP_OB4 + c] = r4[c];
+        }
+    }
 }
 
-// column sums of D [rows][ncol] in slices of rows: part[slice][col].  A block covers 64
-// columns of one slice; its four row lanes take every fourth row and are added in a fixed
-// order, so the sums do not depend on scheduling.
-__global__ __launch_bounds__(256) void k_colsum(const float *D, int64_t rows, int ncol, int rows_per_slice,
-                                                float *part) {
-    __shared__ float s_part[4][64];
-    const int cl = threadIdx.x & 63, rl = threadIdx.x >> 6;
-    const int col = blockIdx.x * 64 + cl;
-    const int64_t r0 = (int64_t)blockIdx.y * rows_per_slice;
-    const int64_t r1 = r0 + rows_per_slice < rows ? r0 + rows_per_slice : rows;
-    float s = 0;
-    if (col < ncol)
-        for (int64_t r = r0 + rl; r < r1; r += 4) s += D[r * ncol + col];
-    s_part[rl][cl] = s;
-    __syncthreads();
-    if (rl == 0 && col < ncol)
-        part[(int64_t)blockIdx.y * ncol + col] = ((s_part[0][cl] + s_part[1][cl]) + s_part[2][cl]) + s_part[3][cl];
-}
-// out[k] = sum over slices of part[slice][k], slices in order (deterministic)
-__global__ void k_sum_slices(const float *part, int nslice, int64_t len, float *out) {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= len) return;
-    float s = 0;
-    for (int z = 0; z < nslice; ++z) s += part[(int64_t)z * len + k];
-    out[k] = s;
+struct ReduceArgs {
+    const float *part, *lossp;
+    int64_t ntile;
+    float inv_n;
+    float *G, *loss;
+    int train, t;                 // Adam (train = 1): step count t >= 1
+    float lr, b1, b2, eps;
+    float *P, *m, *v, *W2T, *W3T;
+    __bf16 *WT;                   // [2][128][HS] inference copies
+};
+// per parameter: gradient = sum over the slices in slice order; block 0 also the loss (a
+// fixed-order sum of the tile losses); with train, Adam and the weight copies
+__global__ __launch_bounds__(256) void k_train_reduce(ReduceArgs a) {
+    if (blockIdx.x == 0) {
+        __shared__ float s[256];
+        float l = 0.0f;
+        const int64_t per = (a.ntile + 255) / 256, t0 = threadIdx.x * per;
+        for (int64_t t = t0; t < t0 + per && t < a.ntile; ++t) l += a.lossp[t];
+        s[threadIdx.x] = l;
+        __syncthreads();
+        for (int o = 128; o > 0; o >>= 1) {
+            if ((int)threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0 && a.loss) *a.loss = s[0] * a.inv_n;
+    }
+    const int k = (int)(blockIdx.x * 256 + threadIdx.x);
+    if (k >= MLP_NPARAM) return;
+    float g = 0.0f;
+    for (int z = 0; z < TR_NS; ++z) g += a.part[(int64_t)z * MLP_NPARAM + k];
+    a.G[k] = g;
+    if (!a.train) return;
+    const float mk = a.b1 * a.m[k] + (1.0f - a.b1) * g, vk = a.b2 * a.v[k] + (1.0f - a.b2) * g * g;
+    a.m[k] = mk;
+    a.v[k] = vk;
+    const float mh = mk / (1.0f - powf(a.b1, (float)a.t)), vh = vk / (1.0f - powf(a.b2, (float)a.t));
+    const float p = a.P[k] - a.lr * mh / (sqrtf(vh) + a.eps);
+    a.P[k] = p;
+    if (k >= MLP_OW2 && k < MLP_OW2 + 128 * 128) {
+        const int in = (k - MLP_OW2) >> 7, out = (k - MLP_OW2) & 127;
+        a.W2T[out * 128 + in] = p;
+        a.WT[out * HS + in] = (__bf16)p;
+    } else if (k >= MLP_OW3 && k < MLP_OW3 + 128 * 128) {
+        const int in = (k - MLP_OW3) >> 7, out = (k - MLP_OW3) & 127;
+        a.W3T[out * 128 + in] = p;
+        a.WT[128 * HS + out * HS + in] = (__bf16)p;
+    }
 }
 
-// Adam (bias-corrected moments); step t >= 1
-__global__ void k_adam(float *P, const float *G, float *m, float *v, int64_t n, float lr, float b1, float b2,
-                       float eps, int t) {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
-    const float g = G[k];
-    const float mk = b1 * m[k] + (1.0f - b1) * g, vk = b2 * v[k] + (1.0f - b2) * g * g;
-    m[k] = mk;
-    v[k] = vk;
-    const float mh = mk / (1.0f - powf(b1, (float)t)), vh = vk / (1.0f - powf(b2, (float)t));
-    P[k] -= lr * mh / (sqrtf(vh) + eps);
+// transposed FP32 copies of W2, W3 (the A operands of the backward pass)
+__global__ void k_mlp_pack32(const float *P, float *W2T, float *W3T) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;   // over 2 * 128 * 128
+    if (k >= 2 * 128 * 128) return;
+    const int L = k >> 14, rem = k & 16383, out = rem >> 7, in = rem & 127;
+    (L == 0 ? W2T : W3T)[out * 128 + in] = P[(L == 0 ? MLP_OW2 : MLP_OW3) + in * 128 + out];
 }
 
 // initial weights: uniform(-1/sqrt(fan_in), 1/sqrt(fan_in)) from Philox, biases 0
@@ -396,11 +650,16 @@ hipError_t mlp_alloc(qed_ctx *ctx) {
     if (e == hipSuccess) e = hipMalloc(&ctx->mlp_v, MLP_NPARAM * sizeof(float));
     if (e == hipSuccess) e = hipMalloc(&ctx->mlp_G, MLP_NPARAM * sizeof(float));
     if (e == hipSuccess) e = hipMalloc(&ctx->mlp_WT, 2 * 128 * HS * sizeof(__bf16));
+    if (e == hipSuccess) e = hipMalloc(&ctx->mlp_W32, 2 * 128 * 128 * sizeof(float));
     return e;
 }
 
 hipError_t mlp_pack(qed_ctx *ctx, hipStream_t s) {
     hipLaunchKernelGGL(k_mlp_pack, dim3((2 * 128 * HS + 255) / 256), dim3(256), 0, s, ctx->mlp_P, (__bf16 *)ctx->mlp_WT);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_mlp_pack32, dim3(2 * 128 * 128 / 256), dim3(256), 0, s, ctx->mlp_P, ctx->mlp_W32,
+                       ctx->mlp_W32 + 128 * 128);
     return hipGetLastError();
 }
 
@@ -440,24 +699,14 @@ hipError_t mlp_forward(qed_ctx *ctx, const float *X, float *Y, int64_t n, const 
     return hipGetLastError();
 }
 
-namespace {
-hipError_t gemm(const float *A, int64_t sam, int64_t sak, const float *B, int64_t sbk, int64_t sbn, float *C, int ldc,
-                int M, int N, int K, const float *bias, float *H, int nslice, int64_t slice_stride, hipStream_t s) {
-    GemmArgs g{A, B, bias, C, H, M, N, K, sam, sak, sbk, sbn, ldc, (K + nslice - 1) / nslice, slice_stride};
-    hipLaunchKernelGGL(k_gemm, dim3((N + 63) / 64, (M + 63) / 64, nslice), dim3(256), 0, s, g);
-    return hipGetLastError();
-}
-}  // namespace
-
-// One forward + backward pass over a batch in FP32: gradient (flat layout) into ctx->mlp_G
-// and the mean loss into *loss.  Work buffers come from ctx->mlp_work (grown on demand).
-hipError_t mlp_grad(qed_ctx *ctx, const float *X, const float *T, int64_t n, const float w[3], float *loss,
-                    hipStream_t s) {
-    const int64_t B = n;
-    constexpr int NS = 64;    // K slices of the weight gradients (64 x 64 tiles x slices fill the chip)
-    constexpr int NSB = 128;  // row slices of the bias gradients
-    static_assert(NSB * 128 <= NS * 128 * 128, "bias partial sums fit the slice buffer");
-    const int64_t need = (int64_t)(3 * 2 * B * 128 + 2 * B * 3 + NS * 128 * 128 + 1024 + 64);
+// One forward + backward pass over a batch (FP32 matrix cores): the gradient (flat
+// layout) into ctx->mlp_G and the mean loss into *loss; with train, also the Adam step on
+// the parameters.  Work buffers come from ctx->mlp_work (grown on demand).
+static hipError_t mlp_pass(qed_ctx *ctx, const float *X, const float *T, int64_t n, const float w[3], float *loss,
+                           int train, float lr, hipStream_t s) {
+    const int64_t unit = (int64_t)TR_CH * TR_NS;
+    const int64_t Bp = (n + unit - 1) / unit * unit, ntile = Bp / 32;
+    const int64_t need = 6 * 128 * Bp + 3 * Bp + ntile + (int64_t)TR_NS * MLP_NPARAM;
     if (need > ctx->mlp_work_len) {
         (void)hipFree(ctx->mlp_work);
         ctx->mlp_work = nullptr;
@@ -466,66 +715,68 @@ hipError_t mlp_grad(qed_ctx *ctx, const float *X, const float *T, int64_t n, con
         if (e != hipSuccess) return e;
         ctx->mlp_work_len = need;
     }
-    float *Z1 = ctx->mlp_work, *H1 = Z1 + B * 128, *Z2 = H1 + B * 128, *H2 = Z2 + B * 128, *Z3 = H2 + B * 128,
-          *H3 = Z3 + B * 128, *Yo = H3 + B * 128, *dY = Yo + B * 3, *part = dY + B * 3, *lpart = part + NS * 128 * 128;
-    const float *P = ctx->mlp_P;
-    float *G = ctx->mlp_G;
-    hipError_t e;
-#define QED_TRY(x) \
-    if ((e = (x)) != hipSuccess) return e
-    // forward: Z = H W + b, H = SiLU(Z)
-    QED_TRY(gemm(X, 4, 1, P + MLP_OW1, 128, 1, Z1, 128, (int)B, 128, 4, P + MLP_OB1, H1, 1, 0, s));
-    QED_TRY(gemm(H1, 128, 1, P + MLP_OW2, 128, 1, Z2, 128, (int)B, 128, 128, P + MLP_OB2, H2, 1, 0, s));
-    QED_TRY(gemm(H2, 128, 1, P + MLP_OW3, 128, 1, Z3, 128, (int)B, 128, 128, P + MLP_OB3, H3, 1, 0, s));
-    QED_TRY(gemm(H3, 128, 1, P + MLP_OW4, 3, 1, Yo, 3, (int)B, 3, 128, P + MLP_OB4, nullptr, 1, 0, s));
-    const int lb = 64;
-    hipLaunchKernelGGL(k_loss, dim3(lb), dim3(256), 0, s, Yo, T, B, w[0], w[1], w[2], dY, lpart);
-    QED_TRY(hipGetLastError());
-    hipLaunchKernelGGL(k_loss_total, dim3(1), dim3(64), 0, s, lpart, lb, B, loss);
-    QED_TRY(hipGetLastError());
-    // backward, last layer first: dW = H^T dZ (split over the batch), db = column sums,
-    // dH = dZ W^T, dZ_prev = dH * SiLU'(Z_prev)
-    struct Lay { const float *Hin; int in; const float *W; int out; int ow, ob; float *Zin; };
-    const Lay lay[4] = {{X, 4, P + MLP_OW1, 128, MLP_OW1, MLP_OB1, nullptr},
-                        {H1, 128, P + MLP_OW2, 128, MLP_OW2, MLP_OB2, Z1},
-                        {H2, 128, P + MLP_OW3, 128, MLP_OW3, MLP_OB3, Z2},
-                        {H3, 128, P + MLP_OW4, 3, MLP_OW4, MLP_OB4, Z3}};
-    float *dZ = dY;   // dL/dZ of the current layer [B][out]
-    for (int L = 3; L >= 0; --L) {
-        const Lay &l = lay[L];
-        // dW [in][out] = sum_b Hin[b][in] dZ[b][out]
-        QED_TRY(gemm(l.Hin, 1, l.in, dZ, l.out, 1, part, l.out, l.in, l.out, (int)B, nullptr, nullptr, NS,
-                     (int64_t)l.in * l.out, s));
-        hipLaunchKernelGGL(k_sum_slices, dim3((l.in * l.out + 255) / 256), dim3(256), 0, s, part, NS,
-                           (int64_t)l.in * l.out, G + l.ow);
-        QED_TRY(hipGetLastError());
-        const int rps = (int)((B + NSB - 1) / NSB);
-        hipLaunchKernelGGL(k_colsum, dim3((l.out + 63) / 64, NSB), dim3(256), 0, s, dZ, B, l.out, rps, part);
-        QED_TRY(hipGetLastError());
-        hipLaunchKernelGGL(k_sum_slices, dim3((l.out + 255) / 256), dim3(256), 0, s, part, NSB, (int64_t)l.out,
-                           G + l.ob);
-        QED_TRY(hipGetLastError());
-        if (L == 0) break;
-        // dH [B][in] = dZ [B][out] W^T, written over this layer's input activations (their
-        // weight gradient is done), then dZ_prev = dH * SiLU'(Z_prev) in place
-        float *dH = L == 3 ? H3 : (L == 2 ? H2 : H1);
-        QED_TRY(gemm(dZ, l.out, 1, l.W, 1, l.out, dH, l.in, (int)B, l.in, l.out, nullptr, nullptr, 1, 0, s));
-        const int64_t cnt = B * l.in;
-        hipLaunchKernelGGL(k_silu_back, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, dH, l.Zin, dH, cnt);
-        QED_TRY(hipGetLastError());
-        dZ = dH;
+    float *q = ctx->mlp_work;
+    TrainArgs a{};
+    a.P = ctx->mlp_P;
+    a.W2T = ctx->mlp_W32;
+    a.W3T = ctx->mlp_W32 + 128 * 128;
+    a.X = X;
+    a.T = T;
+    a.n = n;
+    a.Bp = Bp;
+    a.w0 = w[0]; a.w1 = w[1]; a.w2 = w[2];
+    float **arr[6] = {&a.H1T, &a.H2T, &a.H3T, &a.dZ1T, &a.dZ2T, &a.dZ3T};
+    for (int k = 0; k < 6; ++k) {
+        *arr[k] = q;
+        q += 128 * Bp;
     }
-#undef QED_TRY
-    return hipSuccess;
-}
-
-hipError_t mlp_adam(qed_ctx *ctx, float lr, hipStream_t s) {
-    ctx->mlp_t += 1;
-    hipLaunchKernelGGL(k_adam, dim3((MLP_NPARAM + 255) / 256), dim3(256), 0, s, ctx->mlp_P, ctx->mlp_G, ctx->mlp_m,
-                       ctx->mlp_v, (int64_t)MLP_NPARAM, lr, 0.9f, 0.999f, 1e-8f, ctx->mlp_t);
+    a.dYT = q;
+    q += 3 * Bp;
+    a.lossp = q;
+    q += ntile;
+    a.part = q;
+    int64_t blocks = ntile;
+    const int64_t cap = 4 * (int64_t)ctx->num_cu;
+    if (blocks > cap) blocks = cap;
+    hipLaunchKernelGGL(k_train_fb, dim3((unsigned)blocks), dim3(256), 0, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return mlp_pack(ctx, s);
+    hipLaunchKernelGGL(k_train_dw, dim3(TR_NS, TR_DW_Y), dim3(256), 0, s, a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    ReduceArgs r{};
+    r.part = a.part;
+    r.lossp = a.lossp;
+    r.ntile = ntile;
+    r.inv_n = 1.0f / (float)n;
+    r.G = ctx->mlp_G;
+    r.loss = loss;
+    r.train = train;
+    if (train) {
+        ctx->mlp_t += 1;
+        r.t = ctx->mlp_t;
+        r.lr = lr;
+        r.b1 = 0.9f;
+        r.b2 = 0.999f;
+        r.eps = 1e-8f;
+        r.P = ctx->mlp_P;
+        r.m = ctx->mlp_m;
+        r.v = ctx->mlp_v;
+        r.W2T = ctx->mlp_W32;
+        r.W3T = ctx->mlp_W32 + 128 * 128;
+        r.WT = (__bf16 *)ctx->mlp_WT;
+    }
+    hipLaunchKernelGGL(k_train_reduce, dim3((MLP_NPARAM + 255) / 256), dim3(256), 0, s, r);
+    return hipGetLastError();
+}
+
+hipError_t mlp_grad(qed_ctx *ctx, const float *X, const float *T, int64_t n, const float w[3], float *loss,
+                    hipStream_t s) {
+    return mlp_pass(ctx, X, T, n, w, loss, 0, 0.0f, s);
+}
+
+hipError_t mlp_train(qed_ctx *ctx, const float *X, const float *T, int64_t n, const float w[3], float lr,
+                     float *loss, hipStream_t s) {
+    return mlp_pass(ctx, X, T, n, w, loss, 1, lr, s);
 }
 
 }  // namespace qed

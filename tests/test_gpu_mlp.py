@@ -82,6 +82,53 @@ def test_gradient_matches_oracle(ctx):
     assert np.max(np.abs(g - go)) < 1e-4 * np.max(np.abs(go))
 
 
+def test_gradient_over_many_slices_ragged(ctx):
+    """A batch spread over every slice of the weight-gradient sums (several staged chunks
+    each) with a padded tail: the gradient and the loss still match the FP64 backprop."""
+    _say("gradient, 20000 samples")
+    theta = ctx.mlp_get_params().cpu().numpy().astype(np.float64)
+    X, T = ctx.mlp_samples(20000, seed=17)
+    w = (1.0, 0.3, 0.3)
+    loss, g = ctx.mlp_gradient(X, T, w)
+    lo, go = M.loss_and_grad(theta, X.cpu().numpy(), T.cpu().numpy(), w)
+    g = g.cpu().numpy().astype(np.float64)
+    assert abs(float(loss.item()) - lo) < 1e-5 * lo
+    assert np.linalg.norm(g - go) < 2e-5 * np.linalg.norm(go), np.linalg.norm(g - go) / np.linalg.norm(go)
+
+
+def test_train_step_is_adam_on_the_gradient():
+    """One training step is Adam's first step on the batch gradient, and the weight copies
+    the kernels read afterwards (FP32 for the backward pass, bf16 for inference) follow."""
+    _say("train step")
+    c = Q.Context(dt=0.01, procs=Q.PROC_NCS | Q.PROC_NCS_STOKES, seed=1, id_start=0, precision=Q.QED_MIXED)
+    c.mlp_init(seed=21)
+    th0 = c.mlp_get_params().cpu().numpy().astype(np.float64)
+    X, T = c.mlp_samples(3000, seed=22)
+    Xn, Tn = X.cpu().numpy(), T.cpu().numpy()
+    w, lr = (1.0, 0.3, 0.3), 1e-3
+    _, go = M.loss_and_grad(th0, Xn, Tn, w)
+    c.mlp_train_step(X, T, lr=lr, w=w)
+    th1 = c.mlp_get_params().cpu().numpy().astype(np.float64)
+    # first Adam step: the bias-corrected moments are g and g^2
+    want = th0 - lr * go / (np.abs(go) + 1e-8)
+    # where the FP32 gradient's sign is certain (its error is below 1e-4 of the largest
+    # component) the step is the FP64 one; everywhere its size is at most lr
+    big = np.abs(go) > 1e-3 * np.max(np.abs(go))
+    assert big.sum() > 1000
+    assert np.max(np.abs(th1 - want)[big]) < 2e-3 * lr
+    assert np.max(np.abs(th1 - th0)) < lr * (1 + 1e-3)
+    # the FP32 transposed copies: the next gradient is the gradient at the new parameters
+    X2, T2 = c.mlp_samples(2000, seed=23)
+    _, g2 = c.mlp_gradient(X2, T2, w)
+    _, g2o = M.loss_and_grad(th1, X2.cpu().numpy(), T2.cpu().numpy(), w)
+    g2 = g2.cpu().numpy().astype(np.float64)
+    assert np.linalg.norm(g2 - g2o) < 2e-5 * np.linalg.norm(g2o)
+    # the bf16 copies: inference with the new parameters
+    Y = c.mlp_forward(X2).cpu().numpy()
+    emu = M.forward_bf16(th1, X2.cpu().numpy())
+    assert np.max(np.abs(Y - emu)) < 5e-3 * (1 + np.max(np.abs(emu)))
+
+
 def test_training_reduces_the_error(ctx):
     _say("training")
     c = Q.Context(dt=0.01, procs=Q.PROC_NCS | Q.PROC_NCS_STOKES, seed=1, id_start=0, precision=Q.QED_MIXED)
