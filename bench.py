@@ -206,7 +206,9 @@ class _Cat:
 def run_batched(args, torch, Q, W):
     """Many collisions (64, log-uniform 1e3..2e6 electrons, own laser each) in one list:
     autotuned launch shape, K steps captured in a hipGraph with a device step counter and
-    replayed; against the same collisions stepped one at a time in plain FP64."""
+    replayed, in both precisions; against the same collisions stepped one at a time (eager,
+    FP64).  The batching gain is batched FP64 over one-by-one FP64 (same arithmetic); the
+    precision gain is batched mixed over batched FP64."""
     start = 100
     cfg = W.c4(start_step=start)
     n = len(cfg["leptons"]["x"])
@@ -215,29 +217,34 @@ def run_batched(args, torch, Q, W):
     steps = K * reps
     cap = int(n * 0.04 * (steps + 2)) + 100_000
     segs = Q.segments(cfg["segments"])
-    # batched, mixed precision, graph-replayed
-    ctx = Q.Context(dt=cfg["dt"], procs=cfg["procs"], seed=cfg["seed"], id_start=cfg["next_id"], precision=Q.QED_MIXED)
-    L = Q.Leptons.from_state(cfg["leptons"], precision=Q.QED_MIXED)
-    G = Q.Photons(cap, precision=Q.QED_MIXED)
-    tuning = ctx.autotune(segs, L, start, reps=2)
-    ctx.step_leptons(segs, L, G, start)   # eager step: staging sized, segments uploaded
-    counter = torch.zeros(1, dtype=torch.int64, device="cuda")
-    torch.cuda.synchronize()
-    ctx.set_step_counter(counter)
-    g = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(g):
-        for _ in range(K):
-            ctx.step_leptons(segs, L, G, start + 1)
-            ctx.advance_step(1)
-    torch.cuda.synchronize()
-    n0 = G.count
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        g.replay()
-    torch.cuda.synchronize()
-    wall_b = time.perf_counter() - t0
-    ctx.set_step_counter(None)
-    status_b = ctx.read_status()
+
+    def batched(precision):
+        ctx = Q.Context(dt=cfg["dt"], procs=cfg["procs"], seed=cfg["seed"], id_start=cfg["next_id"],
+                        precision=precision)
+        L = Q.Leptons.from_state(cfg["leptons"], precision=precision)
+        G = Q.Photons(cap, precision=precision)
+        tuning = ctx.autotune(segs, L, start, reps=2)
+        ctx.step_leptons(segs, L, G, start)   # eager step: staging sized, segments uploaded
+        counter = torch.zeros(1, dtype=torch.int64, device="cuda")
+        torch.cuda.synchronize()
+        ctx.set_step_counter(counter)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            for _ in range(K):
+                ctx.step_leptons(segs, L, G, start + 1)
+                ctx.advance_step(1)
+        torch.cuda.synchronize()
+        n0 = G.count
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            g.replay()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ctx.set_step_counter(None)
+        return {"wall": wall, "L": L, "G": G, "n0": n0, "status": ctx.read_status(), "tuning": tuning}
+
+    bm = batched(Q.QED_MIXED)
+    bd = batched(Q.QED_FP64)
     # one collision at a time, FP64, eager
     ctx64 = Q.Context(dt=cfg["dt"], procs=cfg["procs"], seed=cfg["seed"], id_start=cfg["next_id"], precision=Q.QED_FP64)
     lists, fsegs = [], []
@@ -255,19 +262,28 @@ def run_batched(args, torch, Q, W):
             ctx64.step_leptons(sk, Lk, G64, s)
     torch.cuda.synchronize()
     wall_1 = time.perf_counter() - t0
-    a = {"L": _Cat(lists, torch), "G": G64, "n": n, "photon_start": m0}
-    b = {"L": L, "G": G, "n": n, "photon_start": n0}
-    err = error_metrics(a, b, 5000.0, torch)
+    one = {"L": _Cat(lists, torch), "G": G64, "n": n, "photon_start": m0}
+
+    def view(r):
+        return {"L": r["L"], "G": r["G"], "n": n, "photon_start": r["n0"]}
+
+    def line(r, bytes_per):
+        v = n * steps / r["wall"]
+        return {"value": v, "ms_per_step": 1e3 * r["wall"] / steps, "status_bits": r["status"],
+                "tuning": r["tuning"], "hbm_frac": v * bytes_per / (HBM_PEAK_GBS * 1e9)}
     return {"workload": f"{len(cfg['sizes'])} collisions, {n} electrons (log-uniform 1e3..2e6 each), plane-wave "
                         f"sin^2 8-cycle lasers, a0 U(10,200), gamma0 U(500,5000), LP/CP; dt = T0/400, steps "
                         f"{start + 1}..{start + steps}",
-            "electrons": n, "steps": steps, "graph_steps_per_replay": K, "tuning": tuning,
-            "batched_graph_mixed": {"value": n * steps / wall_b, "ms_per_step": 1e3 * wall_b / steps,
-                                    "status_bits": status_b},
+            "electrons": n, "steps": steps, "graph_steps_per_replay": K,
+            "batched_graph_mixed": line(bm, BYTES_LEPTON["mixed"]),
+            "batched_graph_fp64": line(bd, BYTES_LEPTON["fp64"]),
             "one_by_one_fp64": {"value": n * steps / wall_1, "ms_per_step": 1e3 * wall_1 / steps,
                                 "launches_per_step": 3 * len(lists)},
-            "speedup": wall_1 / wall_b, "error_vs_fp64": err,
-            "photons_per_step": (G.count - n0) / steps}
+            "batching_gain_fp64": wall_1 / bd["wall"],
+            "precision_gain_batched": bd["wall"] / bm["wall"],
+            "error_batched_fp64_vs_one_by_one": error_metrics(one, view(bd), 5000.0, torch),
+            "error_batched_mixed_vs_one_by_one_fp64": error_metrics(one, view(bm), 5000.0, torch),
+            "photons_per_step": (bm["G"].count - bm["n0"]) / steps}
 
 
 MLP_FLOP = 2 * (4 * 128 + 2 * 128 * 128 + 128 * 3)   # multiply-adds x 2 per sample (forward)
@@ -824,7 +840,7 @@ def main():
         "metric": "particle-steps/s (push+spin+QED) mixed vs FP64 GPU at stated spectrum error",
         "value": value, "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32+f64 (x, p, event probability f64; rates, sampling, spin, Stokes f32)",
+        "dtype": "f32+f64 (x, p, event probability, field phase f64; fields, rates, sampling, spin, Stokes f32)",
         "data": "synthetic (seeded numpy Philox bunch; analytic focused pulse)",
         "config": {"workload": "c2_focused_cp_pulse_a0_100_1e7_electrons_gamma2000", "electrons": args.n,
                    "gamma0": 2000, "a0": 100, "w0_um": 3.0, "ncycles": 10, "dt": "T0/500",

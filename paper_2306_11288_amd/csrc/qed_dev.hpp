@@ -85,9 +85,11 @@ __device__ __forceinline__ void tsc_w(double xg, int half, int &j0, double w[3])
     j0 = j - 1;
 }
 
-template <class FT>
-__device__ __forceinline__ double grid_gather(const GridDev &f, const float *__restrict__ g, int hx, int hy,
-                                              double x, double y) {
+// TSC gather of one staggered component at (x, y); row(j, on_grid, s) gives the three
+// consecutive nodes s, s+1, s+2 of grid row j (any finite values where on_grid is false:
+// they get weight zero)
+template <class FT, class RowFn>
+__device__ __forceinline__ double tsc_gather(const GridDev &f, int hx, int hy, double x, double y, RowFn row) {
     int i0, j0;
     double wx[3], wy[3];
     tsc_w((x - f.gx0) * f.inv_dx, hx, i0, wx);
@@ -95,29 +97,39 @@ __device__ __forceinline__ double grid_gather(const GridDev &f, const float *__r
     // A row's three taps are read by one load of three consecutive nodes s, s+1, s+2, with
     // s = i0 clamped into [0, nx - 3] (nx >= 3).  Node s + k is tap k - (i0 - s); every tap
     // on the grid falls in this window and every tap off it falls outside, so slot k takes
-    // that tap's weight, or zero when there is no such tap.  Rows off the grid are read at
-    // row 0 with weight zero.  Zero-weighted terms add exactly zero.
+    // that tap's weight, or zero when there is no such tap.  Rows off the grid are read
+    // with weight zero.  Zero-weighted terms add exactly zero.
     const int s = min(max(i0, 0), f.nx - 3), d = i0 - s;
     FT ws[3], wr[3];
     int jj[3];
+    bool on[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         const int a = k - d, j = j0 + k;
         ws[k] = (FT)(a == 0 ? wx[0] : a == 1 ? wx[1] : a == 2 ? wx[2] : 0.0);
-        const bool iny = j >= 0 && j < f.ny;
-        jj[k] = iny ? j : 0;
-        wr[k] = iny ? (FT)wy[k] : (FT)0;
+        on[k] = j >= 0 && j < f.ny;
+        jj[k] = j;
+        wr[k] = on[k] ? (FT)wy[k] : (FT)0;
     }
-    // 32-bit byte offsets from the array base (grids hold fewer than 2^29 nodes)
-    const char *gb = (const char *)g;
     FT sum = 0;
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
-        const float *row = (const float *)(gb + 4u * ((uint32_t)jj[b] * (uint32_t)f.nx + (uint32_t)s));
-        const float v0 = row[0], v1 = row[1], v2 = row[2];
+        const float *r = row(jj[b], on[b], s);
+        const float v0 = r[0], v1 = r[1], v2 = r[2];
         sum += wr[b] * (ws[0] * (FT)v0 + ws[1] * (FT)v1 + ws[2] * (FT)v2);
     }
     return (double)sum;
+}
+
+// from the grid in global memory (rows off the grid read at row 0)
+template <class FT>
+__device__ __forceinline__ double grid_gather(const GridDev &f, const float *__restrict__ g, int hx, int hy,
+                                              double x, double y) {
+    // 32-bit byte offsets from the array base (grids hold fewer than 2^29 nodes)
+    const char *gb = (const char *)g;
+    return tsc_gather<FT>(f, hx, hy, x, y, [&](int j, bool on, int s) {
+        return (const float *)(gb + 4u * ((uint32_t)(on ? j : 0) * (uint32_t)f.nx + (uint32_t)s));
+    });
 }
 
 // Laser pulses (plane wave E = -dA/dphi with a sin^2 envelope; paraxial Gaussian beam at
@@ -432,8 +444,9 @@ __device__ __forceinline__ T ncs_sample_t(const Tabs<T> &tb, double chi, T kappa
     return col * (T)(T_MAX / (NCT - 1));
 }
 
-template <class T>
-__device__ __forceinline__ void nbw_rate(const Tabs<T> &tb, double chi, T &Ja, T &Jb, T &kappa, uint32_t &st) {
+// tb: any table source with nbw_rate() (the global tables, or a copy of that table in LDS)
+template <class T, class TB>
+__device__ __forceinline__ void nbw_rate(const TB &tb, double chi, T &Ja, T &Jb, T &kappa, uint32_t &st) {
     const T c = (T)chi, l = chi > 0.0 ? log(c) : (T)-1e30;
     if (l < (T)P_LO) {
         Ja = 0;
@@ -473,8 +486,9 @@ __device__ __forceinline__ T nbw_sample_delta(const Tabs<T> &tb, double chi, T k
     }
     return lower ? col * hd : (T)1 - col * hd;
 }
-template <class T>
-__device__ __forceinline__ void vb_M(const Tabs<T> &tb, double chi, T &Mp, T &Mm, uint32_t &st) {
+// tb: any table source with vb()
+template <class T, class TB>
+__device__ __forceinline__ void vb_M(const TB &tb, double chi, T &Mp, T &Mm, uint32_t &st) {
     const T c = (T)chi, l = chi > 0.0 ? log(c) : (T)-1e30;
     if (l < (T)V_LO) {
         Mp = 4;
@@ -705,8 +719,8 @@ __device__ __forceinline__ void sincos_small(T d, T &sd, T &cd) {
 // of E_red (eq. rotation) and, if do_vb, the birefringent phase (eq. rotation2), whose
 // chi^2 / (eps xi_L) is written chi |E_red|.  Returns chi_gamma (0 where E_red vanishes:
 // nothing changes then).
-template <class T>
-__device__ __forceinline__ double photon_transport(const Consts &c, const Tabs<T> &tb, const PhotonFrame &f, V3<T> &xi,
+template <class T, class TB>
+__device__ __forceinline__ double photon_transport(const Consts &c, const TB &tb, const PhotonFrame &f, V3<T> &xi,
                                                    V3<T> &e1, bool do_vb, uint32_t &st) {
     if (!(f.an > 0.0)) return 0.0;
     const double chi = f.chi;
@@ -735,8 +749,8 @@ __device__ __forceinline__ double photon_transport(const Consts &c, const Tabs<T
     return chi;
 }
 // NBW event probability W_pair dt (eq. BWprob with the rate normalisation of the readings)
-template <class T>
-__device__ __forceinline__ double nbw_prob(const Consts &c, const Tabs<T> &tb, double eps, double chi, T xi3, T &Ja,
+template <class T, class TB>
+__device__ __forceinline__ double nbw_prob(const Consts &c, const TB &tb, double eps, double chi, T xi3, T &Ja,
                                            T &kappa, uint32_t &st) {
     T Jb;
     nbw_rate<T>(tb, chi, Ja, Jb, kappa, st);

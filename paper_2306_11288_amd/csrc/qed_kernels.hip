@@ -655,14 +655,30 @@ struct PhotonArgs {
 // list far below its capacity costs no empty waves); with NBW each tile ranks its events
 // in photon order (wave ballot + popcount, waves combined in LDS) and parks their records
 // at the tile's staging slots
+// the photon step's two rate tables (NBW rates, VB indices) copied to LDS by each block:
+// their lookups come after the gather on every photon's dependent chain
+template <class T>
+struct PhotonTabsLds {
+    const T *nbw, *vbt;
+    __device__ __forceinline__ const T *nbw_rate() const { return nbw; }
+    __device__ __forceinline__ const T *vb() const { return vbt; }
+};
+
 template <class T, bool NBW, int FK>
 __global__ __launch_bounds__(BLOCK) void k_photons_decide(PhotonArgs a) {
     __shared__ int s_wave[2][BLOCK / 64];
+    __shared__ T s_tab[2 * NP + 2 * NV];
     // 32-bit indices: lists hold at most 2^28 particles
     const int n = (int)clamp_count(a.G.count, a.G.capacity);
     const int ntiles = (n + BLOCK - 1) / BLOCK;
     if ((int)blockIdx.x >= ntiles) return;
-    const Tabs<T> tb = {(const T *)a.tab};
+    {
+        const Tabs<T> tg = {(const T *)a.tab};
+        for (int k = threadIdx.x; k < 2 * NP; k += BLOCK) s_tab[k] = tg.nbw_rate()[k];
+        for (int k = threadIdx.x; k < 2 * NV; k += BLOCK) s_tab[2 * NP + k] = tg.vb()[k];
+        __syncthreads();
+    }
+    const PhotonTabsLds<T> tb = {s_tab, s_tab + 2 * NP};
     const int64_t step = step_of(a);
     const double t = (double)step * a.c.dt;
     T *xi1 = (T *)a.G.xi1, *xi2 = (T *)a.G.xi2, *xi3 = (T *)a.G.xi3;
@@ -673,11 +689,21 @@ __global__ __launch_bounds__(BLOCK) void k_photons_decide(PhotonArgs a) {
         const int j = tile * BLOCK + (int)threadIdx.x;
         bool ev = false;
         V3<double> E = {0, 0, 0}, B = {0, 0, 0};
-        if (j < n && a.G.alive[j]) {
-            const uint32_t o = (uint32_t)j * 8u, os = (uint32_t)j * (uint32_t)sizeof(T);
-            const V3<double> x = {ld_nt(a.G.x, o), ld_nt(a.G.y, o), ld_nt(a.G.z, o)};
-            const V3<double> k = {ld_nt(a.G.kx, o), ld_nt(a.G.ky, o), ld_nt(a.G.kz, o)};
-            V3<T> xi = {ld_nt(xi1, os), ld_nt(xi2, os), ld_nt(xi3, os)}, e1 = {ld_nt(e1x, os), ld_nt(e1y, os), ld_nt(e1z, os)};
+        // the photon's record is read together with its alive flag (not after it), so the
+        // gather waits for one memory round trip, not two
+        const bool inr = j < n;
+        const uint32_t o = (uint32_t)j * 8u, os = (uint32_t)j * (uint32_t)sizeof(T);
+        V3<double> x = {0, 0, 0}, k = {0, 0, 0};
+        V3<T> xi = {0, 0, 0}, e1 = {0, 0, 0};
+        bool live = false;
+        if (inr) {
+            live = a.G.alive[j] != 0;
+            x = {ld_nt(a.G.x, o), ld_nt(a.G.y, o), ld_nt(a.G.z, o)};
+            k = {ld_nt(a.G.kx, o), ld_nt(a.G.ky, o), ld_nt(a.G.kz, o)};
+            xi = {ld_nt(xi1, os), ld_nt(xi2, os), ld_nt(xi3, os)};
+            e1 = {ld_nt(e1x, os), ld_nt(e1y, os), ld_nt(e1z, os)};
+        }
+        if (live) {
             field_kind<T, FK>(a.field, t, x.x, x.y, x.z, E, B);
             PhotonFrame f;
             photon_frame(a.c.xi_L, k, E, B, f);
@@ -686,9 +712,13 @@ __global__ __launch_bounds__(BLOCK) void k_photons_decide(PhotonArgs a) {
             if (NBW && chi > 0.0 && eps >= 2.0) {
                 T Ja, kappa;
                 const double P = nbw_prob<T>(a.c, tb, eps, chi, xi.z, Ja, kappa, st);
-                double rr[4];
-                uniform4(at(a.G.id, o), step, STREAM_NBW, a.c.seed, rr);
-                ev = Ja > (T)0 && rr[1] < P;
+                // a draw is at least 2^-33 (the generator's smallest uniform), so below that
+                // probability there is no event whatever the draw: the generator is skipped
+                if (Ja > (T)0 && P > 0x1p-33) {
+                    double rr[4];
+                    uniform4(at(a.G.id, o), step, STREAM_NBW, a.c.seed, rr);
+                    ev = rr[1] < P;
+                }
             }
             st_nt(xi1, os, xi.x); st_nt(xi2, os, xi.y); st_nt(xi3, os, xi.z);
             st_nt(e1x, os, e1.x); st_nt(e1y, os, e1.y); st_nt(e1z, os, e1.z);
