@@ -248,6 +248,46 @@ qed_status qed_step(qed_ctx_t *ctx, const qed_segment *segs, int nseg, qed_lepto
 qed_status qed_compact_photons(qed_ctx_t *ctx, const qed_photons *in, qed_photons *out,
                                hipStream_t stream);
 
+/* ---------------------------------------------------------------- bremsstrahlung
+ * High-energy bremsstrahlung of electrons in a target (Sec. III.E): the cross-section of
+ * that section with the screening functions of Tsai's Thomas-Fermi fits (the paper's
+ * choice for Z >= 5; lighter targets need tabulated scaled cross-sections and are
+ * refused), a Coulomb correction, and the direct Monte Carlo of the free path.  The
+ * material is one slab x_lo <= x < x_hi (all y, z) of n_atoms atoms of charge Z per
+ * (c / omega_L)^3; photons below k_cut (m c^2; the paper's minimum-energy threshold) are not
+ * produced.  Positrons (whose cross-section the paper scales by a factor from another
+ * code) and Bethe-Heitler pair creation (not written out in the paper) are not covered. */
+typedef struct qed_material {
+    int32_t Z;            /* atomic number, 5..100                                          */
+    int32_t reserved;
+    double n_atoms;       /* atoms per (c / omega_L)^3                                      */
+    double x_lo, x_hi;    /* the slab                                                       */
+    double k_cut;         /* lowest photon energy produced (m c^2), 0 < k_cut < 1e6 - 1     */
+} qed_material;
+/* Tables of the material (FP64 on the device, with an FP32 copy): sigma(E) on 256 nodes of
+ * ln E from ln((k_cut + 1)(1 + 1e-6)) to ln 4e6, and per node the cumulative cross-section
+ * at 128 nodes of u in [0, 1], u mapping linearly to the logit ln(y / (1 - y)) of the photon
+ * fraction y between y = k_cut / E and y = 1 - 1/E (8-point Gauss-Legendre per interval).
+ * Allocates on first use (not capturable); replaces an earlier material.  EARG: Z outside
+ * [5, 100], a non-positive density, an empty slab or k_cut out of range.                */
+qed_status qed_brems_init(qed_ctx_t *ctx, const qed_material *m, hipStream_t stream);
+/* Copies of the FP64 tables into device memory: sigma [256] (per atom, (c / omega_L)^2)
+ * and the cumulative rows [256][128].  ESTATE without a material.                        */
+qed_status qed_brems_tables(qed_ctx_t *ctx, double *sigma, double *cdf, hipStream_t stream);
+/* One bremsstrahlung step over the electrons of em (charge -1).  An electron inside the
+ * slab with total energy E emits with probability P = 1 - exp(-n sigma(E) |v| dt) (the
+ * paper's free-path probability; sigma linear in ln E between nodes, 0 below the table,
+ * the top node and QED_ST_CLAMP above 4e6 m c^2; QED_ST_PMAX when P > cfg.p_max), decided
+ * by r[0] < P with r = the Philox draws of (id, step, stream 3).  The photon energy
+ * k = y E: r[1] inverts the CDF of the two nodes around E mixed at E's weight (the last
+ * node at or below r, u linear between nodes), y from u at E.  The photon, appended to g
+ * in electron order with the next ids (past capacity: dropped, id consumed,
+ * QED_ST_OVERFLOW), starts at the electron's position along its velocity with weight w,
+ * unpolarised (xi = 0), e1 = unit(y_hat - (y_hat.n) n) (of z_hat when n is along y); the
+ * electron keeps its direction with energy E - k.  Asynchronous; capturable once the
+ * staging area covers em's capacity.  ESTATE without a material; EARG for bad lists.    */
+qed_status qed_step_brems(qed_ctx_t *ctx, qed_leptons *em, qed_photons *g, int64_t step, hipStream_t stream);
+
 /* Reordering of a list by grid bin (a data-layout step, no physics): the live particles
  * of `in` are written to `out` (distinct buffers, out->capacity >= in->capacity; out's
  * previous contents and count are replaced) sorted by the bin of their (x, y) on the grid

@@ -201,7 +201,7 @@ def brems_step(sim: "oracle.Sim", tab: Tables, mat: Material, L: "oracle.LeptonA
                G: "oracle.PhotonArrays", step: int) -> int:
     """One bremsstrahlung step over the electrons of L (photons appended to G in electron
     order, ids from sim's counter).  Returns the status bits it raised (1: an electron above
-    the table's top energy, 2: photon list full)."""
+    the table's top energy, 2: photon list full, 4: a probability above sim's p_max)."""
     status = 0
     dt, seed, n_at = sim.cfg.dt, sim.cfg.seed, mat.n_atoms
     for i in range(L.count):
@@ -216,6 +216,8 @@ def brems_step(sim: "oracle.Sim", tab: Tables, mat: Material, L: "oracle.LeptonA
         if not sig > 0.0:
             continue
         P = -np.expm1(-n_at * sig * (pp / E) * dt)
+        if P > sim.cfg.p_max:
+            status |= 4
         r = oracle.uniform4(int(L.id[i]), step, STREAM_BREMS, seed)
         if not r[0] < P:
             continue

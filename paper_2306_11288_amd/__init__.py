@@ -29,9 +29,11 @@ EXPORTED = ["qed_init_tables", "qed_destroy", "qed_gather", "qed_push_spin", "qe
             "qed_set_tuning", "qed_autotune", "qed_mlp_init", "qed_mlp_set_params", "qed_mlp_get_params",
             "qed_mlp_samples", "qed_mlp_forward", "qed_mlp_gradient", "qed_mlp_train_step", "qed_set_sampler",
             "qed_sampler_table", "qed_hist_photons", "qed_hist_leptons", "qed_field_advance",
-            "qed_deposit_current", "qed_save_start", "qed_last_error"]
+            "qed_deposit_current", "qed_save_start", "qed_brems_init", "qed_brems_tables", "qed_step_brems",
+            "qed_last_error"]
 
 MLP_NPARAM = 34051
+BREMS_NE, BREMS_NU = 256, 128
 NOALLOC_MAX_LEPTONS = 524288
 SAMPLER_TABLE, SAMPLER_MLP = 0, 1
 
@@ -91,6 +93,11 @@ class FieldBC(C.Structure):
                 ("gy0", C.c_double), ("t0", C.c_double)]
 
 
+class Material(C.Structure):
+    _fields_ = [("Z", C.c_int32), ("reserved", C.c_int32), ("n_atoms", C.c_double), ("x_lo", C.c_double),
+                ("x_hi", C.c_double), ("k_cut", C.c_double)]
+
+
 class Tuning(C.Structure):
     _fields_ = [("blocks_per_cu", C.c_int32), ("rate_lds", C.c_int32), ("ev_group", C.c_int32)]
 
@@ -141,6 +148,9 @@ def lib():
             "qed_step_photons": [vp, vp, C.c_int, vp, vp, vp, i64, vp],
             "qed_step": [vp, vp, C.c_int, vp, vp, vp, i64, vp],
             "qed_compact_photons": [vp, vp, vp, vp],
+            "qed_brems_init": [vp, vp, vp],
+            "qed_brems_tables": [vp, vp, vp, vp],
+            "qed_step_brems": [vp, vp, vp, i64, vp],
             "qed_sort_photons": [vp, vp, vp, vp, C.c_int32, vp],
             "qed_sort_leptons": [vp, vp, vp, vp, C.c_int32, vp],
             "qed_read_status": [vp, C.POINTER(C.c_uint32), vp],
@@ -481,6 +491,23 @@ class Context:
     def compact_photons(self, src: Photons, dst: Photons, stream=None):
         self._check(lib().qed_compact_photons(self.h, C.byref(src.c()), C.byref(dst.c()), _stream(stream)),
                     "qed_compact_photons")
+
+    def brems_init(self, Z: int, n_atoms: float, x_lo: float, x_hi: float, k_cut: float, stream=None):
+        """Bremsstrahlung tables of one target slab (atoms per (c / omega_L)^3; k_cut in m c^2)."""
+        m = Material(Z, 0, n_atoms, x_lo, x_hi, k_cut)
+        self._check(lib().qed_brems_init(self.h, C.byref(m), _stream(stream)), "qed_brems_init")
+
+    def brems_tables(self, stream=None):
+        """(sigma [256], cumulative rows [256, 128]) of the material, FP64 device tensors."""
+        t = _torch()
+        sig = t.empty(BREMS_NE, dtype=t.float64, device="cuda")
+        cdf = t.empty((BREMS_NE, BREMS_NU), dtype=t.float64, device="cuda")
+        self._check(lib().qed_brems_tables(self.h, _ptr(sig), _ptr(cdf), _stream(stream)), "qed_brems_tables")
+        return sig, cdf
+
+    def step_brems(self, em: Leptons, G: Photons, step: int, stream=None):
+        self._check(lib().qed_step_brems(self.h, C.byref(em.c()), C.byref(G.c()), step, _stream(stream)),
+                    "qed_step_brems")
 
     def sort_photons(self, src: Photons, dst: Photons, grid_spec: dict, bin_cells: int = 4, stream=None):
         """Live photons of src into dst, stably sorted by grid bin (dead ones dropped)."""

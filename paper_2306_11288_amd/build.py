@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libqed.so")
 SOURCES = ["qed_abi.cpp", "qed_tables.hip", "qed_kernels.hip", "qed_mlp.hip", "qed_detector.hip", "qed_fdtd.hip", "qed_deposit.hip", "qed_noalloc.hip",
-           "qed_sort.hip"]
+           "qed_sort.hip", "qed_brems.hip"]
 ARCH = os.environ.get("QED_OFFLOAD_ARCH", "gfx950")
 
 

@@ -236,6 +236,8 @@ void free_ctx(qed_ctx *c) {
     hipFree(c->mlp_G);
     hipFree(c->mlp_WT);
     hipFree(c->mlp_W32);
+    hipFree(c->br_tab64);
+    hipFree(c->br_tab32);
     hipFree(c->mlp_work);
     hipFree(c->hist_rep);
     hipFree(c->dep_cnt);
@@ -640,6 +642,63 @@ qed_status qed_compact_photons(qed_ctx_t *ctx, const qed_photons *in, qed_photon
         return fail(ctx, QED_EARG, "qed_compact_photons: in and out must be distinct buffers");
     if ((st = ensure_staging(ctx, in->capacity)) != QED_OK) return st;
     return launched(ctx, launch_compact(ctx, *in, *out, s), "qed_compact_photons");
+}
+
+// ------------------------------------------------------------------ bremsstrahlung
+qed_status qed_brems_init(qed_ctx_t *ctx, const qed_material *m, hipStream_t s) {
+    qed_status st = ready(ctx);
+    if (st != QED_OK) return st;
+    if (!m) return fail(ctx, QED_EARG, "qed_brems_init: NULL material");
+    if (m->Z < 5 || m->Z > 100) return fail(ctx, QED_EARG, "qed_brems_init: Z = %d outside [5, 100]", (int)m->Z);
+    if (!(m->n_atoms > 0) || !std::isfinite(m->n_atoms) || !(m->x_lo < m->x_hi) || std::isnan(m->x_lo) ||
+        std::isnan(m->x_hi))
+        return fail(ctx, QED_EARG, "qed_brems_init: bad density or slab");
+    if (!(m->k_cut > 0) || !((m->k_cut + 1.0) * 4.0 < BR_E_HI))
+        return fail(ctx, QED_EARG, "qed_brems_init: k_cut must lie in (0, %g) m c^2", BR_E_HI / 4.0 - 1.0);
+    if (!ctx->br_tab64) {
+        hipError_t e = hipMalloc(&ctx->br_tab64, BR_TAB_LEN * sizeof(double));
+        if (e == hipSuccess) e = hipMalloc(&ctx->br_tab32, BR_TAB_LEN * sizeof(float));
+        if (e != hipSuccess) return hip_fail(ctx, e, "qed_brems_init");
+    }
+    BremsDev &b = ctx->br;
+    const double Z = (double)m->Z, a = ctx->cfg.alpha, a2 = (a * Z) * (a * Z);
+    b.Z = Z;
+    b.lnZ = std::log(Z);
+    b.z13 = std::pow(Z, 1.0 / 3.0);
+    b.z23 = std::pow(Z, 2.0 / 3.0);
+    b.f = a2 * (1.0 / (1.0 + a2) + 0.20206 - 0.0369 * a2 + 0.0083 * a2 * a2 - 0.002 * a2 * a2 * a2);
+    b.n_atoms = m->n_atoms;
+    b.x_lo = m->x_lo;
+    b.x_hi = m->x_hi;
+    b.k_cut = m->k_cut;
+    const double r0 = a * ctx->cfg.xi_L;
+    b.ar02 = a * r0 * r0;
+    b.lnE0 = std::log((m->k_cut + 1.0) * (1.0 + 1e-6));
+    b.lnE_hi = std::log(BR_E_HI);
+    b.inv_dlnE = (BR_NE - 1) / (b.lnE_hi - b.lnE0);
+    return launched(ctx, build_brems_tables(ctx, s), "qed_brems_init");
+}
+
+qed_status qed_brems_tables(qed_ctx_t *ctx, double *sigma, double *cdf, hipStream_t s) {
+    qed_status st = ready(ctx);
+    if (st != QED_OK) return st;
+    if (!ctx->br_tab64) return fail(ctx, QED_ESTATE, "qed_brems_tables: no material (qed_brems_init first)");
+    if (!sigma || !cdf) return fail(ctx, QED_EARG, "qed_brems_tables: NULL");
+    hipError_t e = hipMemcpyAsync(sigma, ctx->br_tab64, BR_NE * sizeof(double), hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(cdf, ctx->br_tab64 + BR_NE, (size_t)BR_NE * BR_NU * sizeof(double), hipMemcpyDeviceToDevice, s);
+    return launched(ctx, e, "qed_brems_tables");
+}
+
+qed_status qed_step_brems(qed_ctx_t *ctx, qed_leptons *em, qed_photons *g, int64_t step, hipStream_t s) {
+    qed_status st = ready(ctx);
+    if (st != QED_OK) return st;
+    if (!ctx->br_tab64) return fail(ctx, QED_ESTATE, "qed_step_brems: no material (qed_brems_init first)");
+    if ((st = check_leptons(ctx, em, "electrons")) != QED_OK) return st;
+    if (em->charge != -1) return fail(ctx, QED_EARG, "qed_step_brems: electrons only (charge -1)");
+    if ((st = check_photons(ctx, g, "photons")) != QED_OK) return st;
+    if ((st = ensure_staging(ctx, em->capacity)) != QED_OK) return st;
+    return launched(ctx, launch_brems(ctx, *em, *g, step, s), "qed_step_brems");
 }
 
 static qed_status sort_grid(qed_ctx *ctx, const qed_field *f, int32_t bin_cells, SortGrid &g, const char *name) {

@@ -803,4 +803,72 @@ __device__ __forceinline__ void nbw_pair(const Tabs<T> &tb, const V3<double> &k,
     po.Sm = ((sel & 1) == 0 ? (T)1 : (T)-1) * zm;
 }
 
+// ------------------------------------------------------------------------- list access, ranks
+// step number of a launch: the argument plus the optional device counter
+template <class A>
+__device__ __forceinline__ int64_t step_of(const A &a) {
+    return a.step + (a.step_dev ? *a.step_dev : 0);
+}
+
+// element of an array at a 32-bit byte offset
+template <class T>
+__device__ __forceinline__ T &at(T *base, uint32_t off) {
+    return *(T *)((char *)base + off);
+}
+// streaming access to the particle arrays (read once, written once per step): the
+// non-temporal hint on both the loads and the stores keeps the stream from displacing the
+// tables and the staging records in the caches; together (not either alone) they make the
+// decide kernel about 20 % faster at 1e7 leptons
+template <class T>
+__device__ __forceinline__ T ld_nt(T *base, uint32_t off) {
+    return __builtin_nontemporal_load(&at(base, off));
+}
+template <class T>
+__device__ __forceinline__ void st_nt(T *base, uint32_t off, T v) {
+    __builtin_nontemporal_store(v, &at(base, off));
+}
+
+// device list counts are trusted only up to the list capacity
+__device__ __forceinline__ int64_t clamp_count(const int64_t *count, int64_t capacity) {
+    const int64_t n = *count;
+    return n < 0 ? 0 : (n > capacity ? capacity : n);
+}
+
+// Block-wide exclusive rank of a 0/1 flag: wave ballot + popcount, waves combined in LDS.
+__device__ __forceinline__ int block_rank(bool flag, int &total, int *s_wave) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const unsigned long long m = __ballot(flag);
+    const int below = __popcll(m & ((1ull << lane) - 1ull));
+    if (lane == 0) s_wave[wid] = __popcll(m);
+    __syncthreads();
+    int pre = 0;
+    total = 0;
+#pragma unroll
+    for (int w = 0; w < BLOCK / 64; ++w) {
+        const int v = s_wave[w];
+        pre += w < wid ? v : 0;
+        total += v;
+    }
+    return pre + below;
+}
+
+__device__ __forceinline__ void stage(EventRec *stg, int64_t slot, int64_t idx, const V3<double> &E,
+                                      const V3<double> &B) {
+    EventRec &r = stg[slot];
+    r.idx = idx;
+    r.f[0] = E.x; r.f[1] = E.y; r.f[2] = E.z;
+    r.f[3] = B.x; r.f[4] = B.y; r.f[5] = B.z;
+}
+
+// tile whose event range [off[t], off[t+1]) holds global event e (last t with off[t] <= e)
+__device__ __forceinline__ int64_t tile_of(const int64_t *off, int64_t ntiles, int64_t e) {
+    int64_t lo = 0, hi = ntiles - 1;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= e) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
 }  // namespace qed

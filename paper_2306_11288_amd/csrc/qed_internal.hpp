@@ -55,6 +55,21 @@ struct Tabs {
     __device__ __forceinline__ const float4 *nbw_cdf_pair() const { return (const float4 *)(base + OFF_NBW_CDF_PAIR); }
 };
 
+// ------------------------------------------------------------------ bremsstrahlung
+// Tables of one material: sigma(E) on BR_NE nodes of ln E in [ln E_lo, ln BR_E_HI]
+// (E_lo = (k_cut + 1)(1 + 1e-6)), then the cumulative integrals C_j(u_i) of each node on
+// BR_NU nodes of u in [0, 1] (row-major).  u maps to the logit t = ln(y / (1 - y)) of the
+// photon fraction y linearly between logit(k_cut / E) and ln(E - 1).
+constexpr int BR_NE = 256, BR_NU = 128;
+constexpr double BR_E_HI = 4.0e6;
+constexpr int64_t BR_TAB_LEN = BR_NE + (int64_t)BR_NE * BR_NU;
+struct BremsDev {
+    double Z, lnZ, z13, z23, f;        // Z, ln Z, Z^(1/3), Z^(2/3), Coulomb correction
+    double n_atoms, x_lo, x_hi, k_cut; // atoms per (c / omega_L)^3, target slab in x, photon cut
+    double ar02;                       // alpha r0^2, r0 = alpha xi_L (c / omega_L units)
+    double lnE0, lnE_hi, inv_dlnE;     // table energy range
+};
+
 // ------------------------------------------------------------------ constants per context
 struct Consts {
     double xi_L, alpha, a_e, dt, p_max;
@@ -171,6 +186,9 @@ constexpr size_t STAGING_SLOT = sizeof(LepEvent<double>) > sizeof(EventRec) ? si
 struct qed_ctx {
     qed_config cfg;
     int device;
+    double *br_tab64;                  // bremsstrahlung tables of the material (null: none)
+    float *br_tab32;
+    qed::BremsDev br;
     double *tab64;                     // FP64 master tables
     float *tab32;                      // FP32 copies (mixed precision)
     uint32_t *status;                  // sticky status word
@@ -236,6 +254,13 @@ struct ScanState {
 constexpr int SCAN_MAX_BLOCKS = 64;   // blocks of the prefix scan
 // table construction (qed_tables.hip); returns hipSuccess or the first HIP error
 hipError_t build_tables(qed_ctx *ctx, hipStream_t s);
+Consts consts_of(const qed_ctx *ctx);     // the per-launch constants of the context's configuration
+// bremsstrahlung (Sec. III.E): tables of the context's material (ctx->br), then the step
+hipError_t build_brems_tables(qed_ctx *ctx, hipStream_t s);
+hipError_t launch_brems(qed_ctx *ctx, const qed_leptons &L, const qed_photons &G, int64_t step, hipStream_t s);
+// ordered append of per-tile event counts of a list to one output list (ids per event)
+hipError_t launch_scan_events(qed_ctx *ctx, const int64_t *in_count, int64_t in_cap, const int *counts, int64_t *c0,
+                              int64_t cap0, int ids, hipStream_t s);
 // launches (qed_kernels.hip)
 enum LeptonMode { LM_GATHER = 0, LM_PUSH = 1, LM_EMIT = 2, LM_FUSED = 3 };
 // n_in (device scalar, optional): the launch covers leptons [0, *n_in) instead of [0, *L.count)

@@ -17,73 +17,6 @@
 
 namespace qed {
 
-// step number of a launch: the argument plus the optional device counter
-template <class A>
-__device__ __forceinline__ int64_t step_of(const A &a) {
-    return a.step + (a.step_dev ? *a.step_dev : 0);
-}
-
-// element of an array at a 32-bit byte offset
-template <class T>
-__device__ __forceinline__ T &at(T *base, uint32_t off) {
-    return *(T *)((char *)base + off);
-}
-// streaming access to the particle arrays (read once, written once per step): the
-// non-temporal hint on both the loads and the stores keeps the stream from displacing the
-// tables and the staging records in the caches; together (not either alone) they make the
-// decide kernel about 20 % faster at 1e7 leptons
-template <class T>
-__device__ __forceinline__ T ld_nt(T *base, uint32_t off) {
-    return __builtin_nontemporal_load(&at(base, off));
-}
-template <class T>
-__device__ __forceinline__ void st_nt(T *base, uint32_t off, T v) {
-    __builtin_nontemporal_store(v, &at(base, off));
-}
-
-// device list counts are trusted only up to the list capacity
-__device__ __forceinline__ int64_t clamp_count(const int64_t *count, int64_t capacity) {
-    const int64_t n = *count;
-    return n < 0 ? 0 : (n > capacity ? capacity : n);
-}
-
-// Block-wide exclusive rank of a 0/1 flag: wave ballot + popcount, waves combined in LDS.
-__device__ __forceinline__ int block_rank(bool flag, int &total, int *s_wave) {
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const unsigned long long m = __ballot(flag);
-    const int below = __popcll(m & ((1ull << lane) - 1ull));
-    if (lane == 0) s_wave[wid] = __popcll(m);
-    __syncthreads();
-    int pre = 0;
-    total = 0;
-#pragma unroll
-    for (int w = 0; w < BLOCK / 64; ++w) {
-        const int v = s_wave[w];
-        pre += w < wid ? v : 0;
-        total += v;
-    }
-    return pre + below;
-}
-
-__device__ __forceinline__ void stage(EventRec *stg, int64_t slot, int64_t idx, const V3<double> &E,
-                                      const V3<double> &B) {
-    EventRec &r = stg[slot];
-    r.idx = idx;
-    r.f[0] = E.x; r.f[1] = E.y; r.f[2] = E.z;
-    r.f[3] = B.x; r.f[4] = B.y; r.f[5] = B.z;
-}
-
-// tile whose event range [off[t], off[t+1]) holds global event e (last t with off[t] <= e)
-__device__ __forceinline__ int64_t tile_of(const int64_t *off, int64_t ntiles, int64_t e) {
-    int64_t lo = 0, hi = ntiles - 1;
-    while (lo < hi) {
-        const int64_t mid = (lo + hi + 1) >> 1;
-        if (off[mid] <= e) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
-}
-
 // ------------------------------------------------------------------------- segments
 // FK: the kind of the single segment (fields read at constant offsets of the kernel
 // arguments) or FK_MULTI (segment found per particle, kind read from it).
@@ -830,7 +763,7 @@ __global__ __launch_bounds__(BLOCK) void k_compact_copy(CompactArgs a) {
 }
 
 // ------------------------------------------------------------------------- launchers
-static Consts consts_of(const qed_ctx *ctx) {
+Consts consts_of(const qed_ctx *ctx) {
     const qed_config &g = ctx->cfg;
     return {g.xi_L, g.alpha, g.a_e, g.dt, g.p_max, g.alpha / (SQRT3 * PI * g.xi_L), g.seed, g.procs,
             (float)g.a_e, (float)(0.5 * g.dt)};
@@ -889,6 +822,11 @@ static hipError_t launch_scan(qed_ctx *ctx, const int64_t *in_count, int64_t in_
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_scan<SCAN_THREADS>, dim3((unsigned)nb), dim3(SCAN_THREADS), 0, s, sa);
     return hipGetLastError();
+}
+
+hipError_t launch_scan_events(qed_ctx *ctx, const int64_t *in_count, int64_t in_cap, const int *counts, int64_t *c0,
+                              int64_t cap0, int ids, hipStream_t s) {
+    return launch_scan(ctx, in_count, in_cap, counts, c0, cap0, nullptr, 0, ids, s);
 }
 
 hipError_t launch_scan_ints(qed_ctx *ctx, const int *counts, int64_t n, int64_t *off, int64_t *total,

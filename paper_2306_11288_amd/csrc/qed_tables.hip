@@ -344,7 +344,71 @@ __global__ void k_pair_rows(const float *src, float4 *out, int nrow, int ncol) {
     }
 }
 
+// ------------------------------------------------------------------ bremsstrahlung
+// The braces of the cross-section of Sec. III.E with Tsai's screening functions (his fitted
+// forms for Z >= 5), y dsigma/dy = alpha r0^2 max(braces, 0): near the tip of heavy atoms
+// the Coulomb correction drives the braces below zero, where there is no cross-section.
+__device__ double br_braces(double y, double E, const BremsDev &m) {
+    const double q = 100.0 * y / ((1.0 - y) * E);
+    const double g = q / m.z13, e = q / m.z23;
+    const double p1 = 20.863 - 2.0 * log(1.0 + (0.55846 * g) * (0.55846 * g)) -
+                      4.0 * (1.0 - 0.6 * exp(-0.9 * g) - 0.4 * exp(-1.5 * g));
+    const double p2 = p1 - (2.0 / 3.0) / (1.0 + 6.5 * g + 6.0 * g * g);
+    const double s1 = 28.340 - 2.0 * log(1.0 + (3.621 * e) * (3.621 * e)) -
+                      4.0 * (1.0 - 0.7 * exp(-8.0 * e) - 0.3 * exp(-29.2 * e));
+    const double s2 = s1 - (2.0 / 3.0) / (1.0 + 40.0 * e + 400.0 * e * e);
+    const double Z = m.Z;
+    const double a = (4.0 / 3.0 - 4.0 / 3.0 * y + y * y) *
+                     (Z * Z * (p1 - 4.0 / 3.0 * m.lnZ - 4.0 * m.f) + Z * (s1 - 8.0 / 3.0 * m.lnZ));
+    const double b = (2.0 / 3.0) * (1.0 - y) * (Z * Z * (p1 - p2) + Z * (s1 - s2));
+    return fmax(a + b, 0.0);
+}
+
+// one block per energy node: the u intervals' integrals (one 8-point Gauss-Legendre rule in
+// the logit t each, integrand y (1 - y) dsigma/dy), then their running sum in u order
+__global__ void k_brems_rows(double *tab, BremsDev m, GaussRule g) {
+    __shared__ double s_int[BR_NU];
+    const int j = blockIdx.x;
+    const double lnE = m.lnE0 + (m.lnE_hi - m.lnE0) * j / (BR_NE - 1);
+    const double E = exp(lnE);
+    const double ymin = m.k_cut / E;
+    const double t0 = log(ymin / (1.0 - ymin)), t1 = log(E - 1.0);
+    for (int i = threadIdx.x; i < BR_NU; i += blockDim.x) {
+        double v = 0.0;
+        if (i > 0) {
+            const double a = t0 + (t1 - t0) * ((double)(i - 1) / (BR_NU - 1));
+            const double b = t0 + (t1 - t0) * ((double)i / (BR_NU - 1));
+            double sum = 0.0;
+            for (int k = 0; k < GQ; ++k) {
+                const double t = 0.5 * (a + b) + 0.5 * (b - a) * g.x[k];
+                const double y = 1.0 / (1.0 + exp(-t));
+                sum += g.w[k] * (m.ar02 * br_braces(y, E, m) * (1.0 - y));
+            }
+            v = 0.5 * (b - a) * sum;
+        }
+        s_int[i] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double *row = tab + BR_NE + (int64_t)j * BR_NU;
+        double acc = 0.0;
+        row[0] = 0.0;
+        for (int i = 1; i < BR_NU; ++i) {
+            acc += s_int[i];
+            row[i] = acc;
+        }
+        tab[j] = acc;
+    }
+}
+
 }  // namespace
+
+hipError_t build_brems_tables(qed_ctx *ctx, hipStream_t s) {
+    const GaussRule g = make_rule();
+    hipLaunchKernelGGL(k_brems_rows, dim3(BR_NE), dim3(BR_NU), 0, s, ctx->br_tab64, ctx->br, g);
+    hipLaunchKernelGGL(k_to_f32, dim3(64), dim3(256), 0, s, (const double *)ctx->br_tab64, ctx->br_tab32, BR_TAB_LEN);
+    return hipGetLastError();
+}
 
 hipError_t build_tables(qed_ctx *ctx, hipStream_t s) {
     const GaussRule g = make_rule();

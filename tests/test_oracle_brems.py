@@ -146,7 +146,7 @@ def test_monte_carlo_step_statistics(gold):
           "sz": np.zeros(n), "id": np.arange(n, dtype=np.uint64)}
     sig, _ = BR.sigma_at(tab, E0)
     dt = 0.2 / (mat.n_atoms * sig)                   # P = 1 - e^-0.2 (v ~ 1)
-    sim = oracle.Sim(dt=dt, procs=0, seed=77, next_id=1 << 40)
+    sim = oracle.Sim(dt=dt, procs=0, seed=77, next_id=1 << 40, p_max=1.0)
     L = oracle.LeptonArrays.from_state(st)
     G = oracle.PhotonArrays.empty(n)
     status = BR.brems_step(sim, tab, mat, L, G, step=3)
