@@ -677,6 +677,88 @@ def run_radiative(args, torch, Q, cfg):
     return out
 
 
+# bremsstrahlung decide kernel per electron-step in the target: read x, p (32 B) and the id
+# (8 B) for the draws; an emitting electron is re-read and written by the event kernel
+BYTES_BREMS = 8 + 24 + 8
+
+
+def run_brems(args, torch, Q):
+    """Bremsstrahlung in a target (Sec. III.E): the paper's check configuration, 1e5
+    electrons of 1 GeV normally incident on 5 mm of gold and of aluminium (field-free push +
+    bremsstrahlung step until every electron has left the slab, photons above 1 MeV), with
+    the mean energy left against the radiation-length estimate exp(-L / X0); and the step's
+    throughput on 1e7 electrons inside gold (mixed and FP64) against the HBM roofline of its
+    decide kernel."""
+    import numpy as np
+    out = {}
+    um = 1e-6 / (2 * math.pi)                       # length unit c / omega_L at 1 um, metres
+    mev = 1.0 / 0.51099895
+    thick = 5e-3 / um
+    targets = {"Au": (79, 5.90e28, 0.3344), "Al": (13, 6.026e28, 8.897)}   # Z, atoms / m^3, X0 (cm)
+    dt = 20.0
+    n = 100_000
+    E0 = 1000.0 * mev
+    for name, (Z, dens, x0_cm) in targets.items():
+        ctx = Q.Context(dt=dt, procs=0, seed=5, id_start=0, precision=Q.QED_FP64, p_max=1.0)
+        ctx.brems_init(Z, dens * um ** 3, 0.0, thick, 1.0 * mev)
+        pz = math.sqrt(E0 * E0 - 1.0)
+        st = {"x": np.zeros(n), "y": np.zeros(n), "z": np.zeros(n), "px": np.full(n, pz), "py": np.zeros(n),
+              "pz": np.zeros(n), "w": np.ones(n), "sx": np.zeros(n), "sy": np.zeros(n), "sz": np.zeros(n),
+              "id": np.arange(n, dtype=np.uint64)}
+        L = Q.Leptons.from_state(st)
+        G = Q.Photons(40 * n)
+        segs = Q.whole({"kind": Q.FIELD_NONE})
+        steps = int(thick / dt) + 2
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s in range(steps):
+            ctx.push_spin(segs, L, s)
+            ctx.step_brems(L, G, s)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        e = torch.sqrt(1 + L.px[:n] ** 2 + L.py[:n] ** 2 + L.pz[:n] ** 2)
+        k = torch.sqrt(G.kx[:G.count] ** 2 + G.ky[:G.count] ** 2 + G.kz[:G.count] ** 2)
+        out[name] = {"photons_per_electron": G.count / n, "mean_energy_left": float(e.mean()) / E0,
+                     "radiation_length_estimate": math.exp(-0.5 / x0_cm),
+                     "photon_energy_fraction": float(k.sum()) / (n * E0),
+                     "photons_above_100MeV_per_electron": float((k > 100 * mev).sum()) / n,
+                     "steps": steps, "wall_s": wall, "status_bits": ctx.read_status()}
+    # throughput: 1e7 electrons of 100 MeV..10 GeV inside gold, the step alone
+    nt = 10_000_000
+    g = np.random.default_rng(11)
+    Ee = np.exp(g.uniform(math.log(100 * mev), math.log(1e4 * mev), nt))
+    st = {"x": g.uniform(0.0, thick, nt), "y": np.zeros(nt), "z": np.zeros(nt), "px": np.sqrt(Ee * Ee - 1.0),
+          "py": np.zeros(nt), "pz": np.zeros(nt), "w": np.ones(nt), "sx": np.zeros(nt), "sy": np.zeros(nt),
+          "sz": np.zeros(nt), "id": np.arange(nt, dtype=np.uint64)}
+    for prec, pname in ((Q.QED_MIXED, "mixed"), (Q.QED_FP64, "fp64")):
+        ctx = Q.Context(dt=dt, procs=0, seed=6, id_start=0, precision=prec, p_max=1.0)
+        ctx.brems_init(79, 5.90e28 * um ** 3, 0.0, thick, 1.0 * mev)
+        L = Q.Leptons.from_state(st, precision=prec)
+        G = Q.Photons(nt // 2, precision=prec)
+        ctx.step_brems(L, G, 0)
+        torch.cuda.synchronize()
+        c0 = G.count
+        K = args.brems_steps
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * K)]
+        for j in range(K):
+            ev[2 * j].record()
+            ctx.step_brems(L, G, 1 + j)
+            ev[2 * j + 1].record()
+        torch.cuda.synchronize()
+        ms = sum(ev[2 * j].elapsed_time(ev[2 * j + 1]) for j in range(K)) / K
+        gbs = nt * BYTES_BREMS / (ms * 1e-3) / 1e9
+        out["throughput_" + pname] = {
+            "electron_steps_per_s": nt / (ms * 1e-3), "ms_per_step": ms, "photons_per_step": (G.count - c0) / K,
+            "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": gbs / HBM_PEAK_GBS, "bytes_per_electron_step": BYTES_BREMS,
+                         "note": "whole step (decide + scan + events) against the decide kernel's bytes"},
+            "status_bits": ctx.read_status()}
+        del L, G
+    out["workload"] = ("1e5 electrons of 1 GeV through 5 mm of Au and of Al (k > 1 MeV, dt = 20 c/omega_L); "
+                       "1e7 electrons of 100 MeV..10 GeV inside Au for the throughput")
+    return out
+
+
 def _oracle_run(st, cfg, steps, budget_s=None):
     """The oracle as it stands (C, FP64 tables) on the electrons `st`: `steps` steps, or as
     many as `budget_s` seconds allow (at most `steps`).  Returns (particle-steps, seconds)."""
@@ -772,6 +854,8 @@ def main():
     ap.add_argument("--radiative-steps", type=int, default=20,
                     help="timed steps of the radiative push (MLL + radiative T-BMT; 0: skip it)")
     ap.add_argument("--train-samples", type=int, default=10_000_000)
+    ap.add_argument("--brems-steps", type=int, default=20,
+                    help="timed bremsstrahlung steps on 1e7 electrons (0: skip the bremsstrahlung leg)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device to device three times (a plain copy kernel of known size, "
                          "the reference for the HBM byte counters)")
@@ -872,6 +956,9 @@ def main():
     if args.radiative_steps > 0:
         print("[bench] radiative push", file=sys.stderr, flush=True)
         result["radiative"] = run_radiative(args, torch, Q, cfg)
+    if args.brems_steps > 0:
+        print("[bench] bremsstrahlung", file=sys.stderr, flush=True)
+        result["brems"] = run_brems(args, torch, Q)
     if args.cascade_steps > 0:
         print("[bench] cascade on the grid", file=sys.stderr, flush=True)
         result["cascade"] = run_cascade(args, torch, Q, W)
