@@ -58,9 +58,12 @@ __global__ __launch_bounds__(BLOCK) void k_brems_decide(BremsArgs a) {
     bool ev = false;
     double r1 = 0.0;
     if (i < n) {
-        const double x = a.L.x[i];
+        // the electron's record is read in one round trip (x, p and id together, streaming:
+        // read once per step) even though electrons outside the slab need only x
+        const uint32_t o = (uint32_t)i * 8u;
+        const double x = ld_nt(a.L.x, o), px = ld_nt(a.L.px, o), py = ld_nt(a.L.py, o), pz = ld_nt(a.L.pz, o);
+        const unsigned long long id = ld_nt(a.L.id, o);
         if (a.m.x_lo <= x && x < a.m.x_hi) {
-            const double px = a.L.px[i], py = a.L.py[i], pz = a.L.pz[i];
             const double pp = sqrt(px * px + py * py + pz * pz), E = sqrt(1.0 + pp * pp);
             int j;
             double w;
@@ -70,7 +73,7 @@ __global__ __launch_bounds__(BLOCK) void k_brems_decide(BremsArgs a) {
                     const double P = -expm1(-(a.m.n_atoms * sig * (pp / E) * a.c.dt));
                     if (P > a.c.p_max) st |= QED_ST_PMAX;
                     double r[4];
-                    uniform4(a.L.id[i], step_of(a), STREAM_BREMS, a.c.seed, r);
+                    uniform4(id, step_of(a), STREAM_BREMS, a.c.seed, r);
                     ev = r[0] < P;
                     r1 = r[1];
                 }
@@ -107,16 +110,49 @@ __device__ double br_sample_u(const T *tab, int j, double w, double r) {
     return (lo + f) / (BR_NU - 1);
 }
 
+// one wavefront per group of BR_GROUP tiles: the lanes' running sum of the group's tile
+// counts gives each event its tile and record (events are sparse, a few per tile, so a
+// group's events fill about one wavefront)
+constexpr int BR_GROUP = 16;
+
 template <class T>
 __global__ __launch_bounds__(BLOCK) void k_brems_events(BremsArgs a) {
     const int64_t n = clamp_count(a.L.count, a.L.capacity);
     const int64_t ntiles = (n + BLOCK - 1) / BLOCK;
-    const int64_t nev = a.launch[3], base = a.launch[0], id0 = a.launch[2];
+    const int lane = threadIdx.x & 63;
+    const int64_t t0 = ((int64_t)blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6)) * BR_GROUP;
+    if (t0 >= ntiles) return;
+    const int64_t base = a.launch[0], id0 = a.launch[2];
+    const int cnt = lane < BR_GROUP && t0 + lane < ntiles ? a.tile_counts[t0 + lane] : 0;
+    int incl = cnt;
+#pragma unroll
+    for (int d = 1; d < BR_GROUP; d <<= 1) {
+        const int v = __shfl_up(incl, d);
+        if (lane >= d) incl += v;
+    }
+    const int excl = incl - cnt;
+    // every tile's first event rank in scalar registers (read while all lanes are active)
+    int exs[BR_GROUP];
+#pragma unroll
+    for (int k = 0; k < BR_GROUP; ++k) exs[k] = __builtin_amdgcn_readlane(excl, k);
+    const int total = __builtin_amdgcn_readlane(incl, BR_GROUP - 1);
+    const int64_t e0 = a.tile_off[t0];      // global rank of the group's first event
     const T *tab = (const T *)a.tab;
     uint32_t st = 0;
-    for (int64_t e = (int64_t)blockIdx.x * BLOCK + threadIdx.x; e < nev; e += (int64_t)gridDim.x * BLOCK) {
-        const int64_t tile = tile_of(a.tile_off, ntiles, e);
-        const EventRec &rec = a.stg[tile * BLOCK + (e - a.tile_off[tile])];
+    for (int le = lane; le < total; le += 64) {
+        // the event's tile: the last one whose first event is at or before it (a tile with
+        // no events shares its first rank with the next one, so this is never an empty tile)
+        int kk = 0, ek = 0;
+#pragma unroll
+        for (int k = 0; k < BR_GROUP; ++k) {
+            const int x = exs[k];
+            if (x <= le) {
+                kk = k;
+                ek = x;
+            }
+        }
+        const int64_t e = e0 + le;
+        const EventRec &rec = a.stg[(t0 + kk) * BLOCK + (le - ek)];
         const int64_t i = rec.idx;
         const double px = a.L.px[i], py = a.L.py[i], pz = a.L.pz[i];
         const double pp = sqrt(px * px + py * py + pz * pz), E = sqrt(1.0 + pp * pp);
@@ -172,9 +208,9 @@ hipError_t launch_brems_t(qed_ctx *ctx, BremsArgs &a, hipStream_t s) {
     if (e != hipSuccess) return e;
     e = launch_scan_events(ctx, a.L.count, a.L.capacity, ctx->tile_counts, a.G.count, a.G.capacity, 1, s);
     if (e != hipSuccess) return e;
-    int64_t nb = (a.L.capacity + BLOCK - 1) / BLOCK;
-    nb = nb > 1024 ? 1024 : (nb < 1 ? 1 : nb);
-    hipLaunchKernelGGL(k_brems_events<T>, dim3((unsigned)nb), dim3(BLOCK), 0, s, a);
+    const int64_t groups = (ntiles + BR_GROUP - 1) / BR_GROUP, per = BLOCK / 64;
+    const int64_t nb = (groups + per - 1) / per;
+    hipLaunchKernelGGL(k_brems_events<T>, dim3((unsigned)(nb < 1 ? 1 : nb)), dim3(BLOCK), 0, s, a);
     return hipGetLastError();
 }
 

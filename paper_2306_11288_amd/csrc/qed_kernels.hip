@@ -84,7 +84,10 @@ struct ScanArgs {
     uint32_t *status;
 };
 constexpr int SCAN_THREADS = 256, SCAN_MIN_CHUNK = 2048, SCAN_ONE_THREADS = 1024;
-constexpr int64_t SCAN_ONE_BLOCK = 65536;   // units a single block scans
+// units a single block scans: up to eight per thread, all held in registers; a longer run
+// per thread strides through memory (39k tile counts took 65 us in one block, 11 us in the
+// two-launch form)
+constexpr int64_t SCAN_ONE_BLOCK = 8 * SCAN_ONE_THREADS;
 static_assert(SCAN_MAX_BLOCKS <= SCAN_THREADS, "one block total per thread");
 
 // sum over the block of NT threads (every thread gets it)
@@ -125,7 +128,7 @@ __device__ __forceinline__ int64_t scan_units(const ScanArgs &a, int64_t &nunits
 }
 
 // Exclusive prefix sums of the unit counts and the launch bases.  A list of at most
-// SCAN_ONE_BLOCK units is scanned by one block of 1024 threads in one launch.  A longer one
+// SCAN_ONE_BLOCK (8192) units is scanned by one block of 1024 threads in one launch.  A longer one
 // takes two launches over blocks of 256 threads and `chunk` units: k_scan_sums writes each
 // block's total, k_scan then gives block b the total of blocks [0, b) (at most
 // SCAN_MAX_BLOCKS values).  In k_scan each thread owns a run of chunk / threads units
@@ -413,8 +416,10 @@ __global__ __launch_bounds__(BLOCK) void k_leptons_radiative(LeptonArgs a, uint3
 // event count goes to tile_counts and is added to its group's total (integer atomics: the
 // sum does not depend on their order; the scan clears the totals it reads).  RATE_LDS: the
 // NCS rate table is staged in LDS once per block instead of being read through the caches.
+// The FP64 instances are held to six wavefronts per SIMD (79 VGPRs, a few spilled; five
+// wavefronts at 93 otherwise): measured 2 % faster.
 template <class T, bool PUSH, int FK, bool RATE_LDS>
-__global__ __launch_bounds__(BLOCK) void k_leptons_decide(LeptonArgs a) {
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 6 : 1))) void k_leptons_decide(LeptonArgs a) {
     __shared__ int s_wave[2][BLOCK / 64];
     __shared__ T s_rate[RATE_LDS ? 2 * NR : 1];
     // 32-bit indices: lists hold at most 2^28 particles
