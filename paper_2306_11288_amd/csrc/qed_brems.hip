@@ -110,8 +110,7 @@ __device__ double br_sample_u(const T *tab, int j, double w, double r) {
     return (lo + f) / (BR_NU - 1);
 }
 
-// one wavefront per group of BR_GROUP tiles: the lanes' running sum of the group's tile
-// counts gives each event its tile and record (events are sparse, a few per tile, so a
+// one wavefront per group of BR_GROUP tiles (events are sparse, a few per tile, so a
 // group's events fill about one wavefront)
 constexpr int BR_GROUP = 16;
 
@@ -119,40 +118,13 @@ template <class T>
 __global__ __launch_bounds__(BLOCK) void k_brems_events(BremsArgs a) {
     const int64_t n = clamp_count(a.L.count, a.L.capacity);
     const int64_t ntiles = (n + BLOCK - 1) / BLOCK;
-    const int lane = threadIdx.x & 63;
     const int64_t t0 = ((int64_t)blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6)) * BR_GROUP;
     if (t0 >= ntiles) return;
     const int64_t base = a.launch[0], id0 = a.launch[2];
-    const int cnt = lane < BR_GROUP && t0 + lane < ntiles ? a.tile_counts[t0 + lane] : 0;
-    int incl = cnt;
-#pragma unroll
-    for (int d = 1; d < BR_GROUP; d <<= 1) {
-        const int v = __shfl_up(incl, d);
-        if (lane >= d) incl += v;
-    }
-    const int excl = incl - cnt;
-    // every tile's first event rank in scalar registers (read while all lanes are active)
-    int exs[BR_GROUP];
-#pragma unroll
-    for (int k = 0; k < BR_GROUP; ++k) exs[k] = __builtin_amdgcn_readlane(excl, k);
-    const int total = __builtin_amdgcn_readlane(incl, BR_GROUP - 1);
-    const int64_t e0 = a.tile_off[t0];      // global rank of the group's first event
     const T *tab = (const T *)a.tab;
     uint32_t st = 0;
-    for (int le = lane; le < total; le += 64) {
-        // the event's tile: the last one whose first event is at or before it (a tile with
-        // no events shares its first rank with the next one, so this is never an empty tile)
-        int kk = 0, ek = 0;
-#pragma unroll
-        for (int k = 0; k < BR_GROUP; ++k) {
-            const int x = exs[k];
-            if (x <= le) {
-                kk = k;
-                ek = x;
-            }
-        }
-        const int64_t e = e0 + le;
-        const EventRec &rec = a.stg[(t0 + kk) * BLOCK + (le - ek)];
+    group_events<BR_GROUP>(a.tile_counts, a.tile_off, ntiles, t0, [&](int64_t e, int64_t slot) {
+        const EventRec &rec = a.stg[slot];
         const int64_t i = rec.idx;
         const double px = a.L.px[i], py = a.L.py[i], pz = a.L.pz[i];
         const double pp = sqrt(px * px + py * py + pz * pz), E = sqrt(1.0 + pp * pp);
@@ -161,8 +133,8 @@ __global__ __launch_bounds__(BLOCK) void k_brems_events(BremsArgs a) {
         br_locate(a.m, E, j, w, st);      // as in the decide kernel (an event implies a node)
         const double u = br_sample_u<T>(tab, j, w, rec.f[0]);
         const double ymin = a.m.k_cut / E;
-        const double t0 = log(ymin / (1.0 - ymin)), t1 = log(E - 1.0);
-        const double y = 1.0 / (1.0 + exp(-(t0 + u * (t1 - t0))));
+        const double ta = log(ymin / (1.0 - ymin)), tb = log(E - 1.0);   // logit range at E
+        const double y = 1.0 / (1.0 + exp(-(ta + u * (tb - ta))));
         const double k = y * E, Ep = E - k;
         const double nx = px / pp, ny = py / pp, nz = pz / pp;
         const double s = sqrt(Ep * Ep - 1.0) / pp;
@@ -170,7 +142,7 @@ __global__ __launch_bounds__(BLOCK) void k_brems_events(BremsArgs a) {
         a.L.py[i] = py * s;
         a.L.pz[i] = pz * s;
         const int64_t pos = base + e;
-        if (pos >= a.G.capacity) continue;
+        if (pos >= a.G.capacity) return;
         a.G.x[pos] = a.L.x[i];
         a.G.y[pos] = a.L.y[i];
         a.G.z[pos] = a.L.z[i];
@@ -196,7 +168,7 @@ __global__ __launch_bounds__(BLOCK) void k_brems_events(BremsArgs a) {
         ((T *)a.G.e1z)[pos] = (T)(ez * inv);
         a.G.id[pos] = (unsigned long long)(id0 + e);
         a.G.alive[pos] = 1;
-    }
+    });
     if (st) atomicOr(a.status, st);
 }
 

@@ -871,4 +871,42 @@ __device__ __forceinline__ int64_t tile_of(const int64_t *off, int64_t ntiles, i
     return lo;
 }
 
+
+// The events of one group of G consecutive tiles, handled by one wavefront (call it with all
+// 64 lanes active and a wavefront-uniform first tile t0 < ntiles): the lanes' running sum of
+// the G tile counts gives each event its tile (no per-event search); f(e, slot) is called
+// for every event, e its global rank (off[t0] + rank in the group), slot its staging slot
+// tile * BLOCK + rank in the tile.  Suits sparse events (a few per tile).
+template <int G, class F>
+__device__ __forceinline__ void group_events(const int *counts, const int64_t *off, int64_t ntiles, int64_t t0,
+                                             F &&f) {
+    static_assert(G <= 64, "one count per lane");
+    const int lane = threadIdx.x & 63;
+    const int cnt = lane < G && t0 + lane < ntiles ? counts[t0 + lane] : 0;
+    int incl = cnt;
+#pragma unroll
+    for (int d = 1; d < G; d <<= 1) {
+        const int v = __shfl_up(incl, d);
+        if (lane >= d) incl += v;
+    }
+    const int excl = incl - cnt;
+    int exs[G];   // every tile's first rank, in scalar registers (read while all lanes are active)
+#pragma unroll
+    for (int k = 0; k < G; ++k) exs[k] = __builtin_amdgcn_readlane(excl, k);
+    const int total = __builtin_amdgcn_readlane(incl, G - 1);
+    const int64_t e0 = off[t0];
+    for (int le = lane; le < total; le += 64) {
+        // the last tile whose first rank is at or before the event (a tile without events
+        // shares its first rank with the next, so this is never an empty tile)
+        int kk = 0, ek = 0;
+#pragma unroll
+        for (int k = 0; k < G; ++k)
+            if (exs[k] <= le) {
+                kk = k;
+                ek = exs[k];
+            }
+        f(e0 + le, (t0 + kk) * BLOCK + (le - ek));
+    }
+}
+
 }  // namespace qed

@@ -679,19 +679,22 @@ __global__ __launch_bounds__(BLOCK) void k_photons_decide(PhotonArgs a) {
     if (st) atomicOr(a.status, st);
 }
 
-// pair events: electron to em, positron to ep, in photon order
+// pair events: electron to em, positron to ep, in photon order; one wavefront per group
+// of PH_GROUP tiles (pairs are rare: well under one per tile)
+constexpr int PH_GROUP = 32;
 template <class T>
 __global__ __launch_bounds__(BLOCK) void k_photons_events(PhotonArgs a) {
     const int64_t n = clamp_count(a.G.count, a.G.capacity);
     const int64_t ntiles = (n + BLOCK - 1) / BLOCK;
-    const int64_t nev = a.launch[3], id0 = a.launch[2];
+    const int64_t t0 = ((int64_t)blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6)) * PH_GROUP;
+    if (t0 >= ntiles) return;
+    const int64_t id0 = a.launch[2];
     const Tabs<T> tb = {(const T *)a.tab};
     const T *xi1 = (const T *)a.G.xi1, *xi2 = (const T *)a.G.xi2, *xi3 = (const T *)a.G.xi3;
     const T *e1x = (const T *)a.G.e1x, *e1y = (const T *)a.G.e1y, *e1z = (const T *)a.G.e1z;
     uint32_t st = 0;
-    for (int64_t e = (int64_t)blockIdx.x * BLOCK + threadIdx.x; e < nev; e += (int64_t)gridDim.x * BLOCK) {
-        const int64_t tile = tile_of(a.tile_off, ntiles, e);
-        const EventRec &rec = a.stg[tile * BLOCK + (e - a.tile_off[tile])];
+    group_events<PH_GROUP>(a.tile_counts, a.tile_off, ntiles, t0, [&](int64_t e, int64_t slot) {
+        const EventRec &rec = a.stg[slot];
         const int64_t j = rec.idx;
         const V3<double> E = {rec.f[0], rec.f[1], rec.f[2]}, B = {rec.f[3], rec.f[4], rec.f[5]};
         const V3<double> k = {a.G.kx[j], a.G.ky[j], a.G.kz[j]};
@@ -720,7 +723,7 @@ __global__ __launch_bounds__(BLOCK) void k_photons_events(PhotonArgs a) {
             L.w[pos] = a.G.w[j];
             L.id[pos] = (unsigned long long)(id0 + 2 * e + s);
         }
-    }
+    });
     if (st) atomicOr(a.status, st);
 }
 
@@ -985,7 +988,9 @@ static hipError_t launch_photons_stage(qed_ctx *ctx, const PhotonArgs &a, hipStr
                     a.has_em ? a.em.capacity : 0, a.has_ep ? a.ep.count : nullptr, a.has_ep ? a.ep.capacity : 0, 2, s,
                     0, lep_start);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_photons_events<T>, dim3(stride_grid(a.G.capacity, 2048)), dim3(BLOCK), 0, s, a);
+    const int64_t groups = (a.G.capacity + (int64_t)BLOCK * PH_GROUP - 1) / ((int64_t)BLOCK * PH_GROUP);
+    const int64_t nb = (groups + BLOCK / 64 - 1) / (BLOCK / 64);
+    hipLaunchKernelGGL(k_photons_events<T>, dim3((unsigned)(nb < 1 ? 1 : nb)), dim3(BLOCK), 0, s, a);
     return hipGetLastError();
 }
 
