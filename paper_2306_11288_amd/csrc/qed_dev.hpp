@@ -76,12 +76,15 @@ __device__ __forceinline__ double frac_rev(double a) { return a - rint(a); }
 __device__ __forceinline__ float rsq(float v) { return rsqrtf(v); }
 __device__ __forceinline__ double rsq(double v) { return rsqrt(v); }
 
-__device__ __forceinline__ void tsc_w(double xg, int half, int &j0, double w[3]) {
+// TSC weights of a node-centred (half = 0) or half-staggered (half = 1) component at grid
+// position xg: the node and the offset from it in FP64 (positions), the weights in FT
+template <class FT>
+__device__ __forceinline__ void tsc_w(double xg, int half, int &j0, FT w[3]) {
     const int j = half ? (int)floor(xg) : (int)floor(xg + 0.5);
-    const double d = xg - ((double)j + (half ? 0.5 : 0.0));
-    w[0] = 0.5 * (0.5 - d) * (0.5 - d);
-    w[1] = 0.75 - d * d;
-    w[2] = 0.5 * (0.5 + d) * (0.5 + d);
+    const FT d = (FT)(xg - ((double)j + (half ? 0.5 : 0.0)));
+    w[0] = (FT)0.5 * ((FT)0.5 - d) * ((FT)0.5 - d);
+    w[1] = (FT)0.75 - d * d;
+    w[2] = (FT)0.5 * ((FT)0.5 + d) * ((FT)0.5 + d);
     j0 = j - 1;
 }
 
@@ -91,9 +94,9 @@ __device__ __forceinline__ void tsc_w(double xg, int half, int &j0, double w[3])
 template <class FT, class RowFn>
 __device__ __forceinline__ double tsc_gather(const GridDev &f, int hx, int hy, double x, double y, RowFn row) {
     int i0, j0;
-    double wx[3], wy[3];
-    tsc_w((x - f.gx0) * f.inv_dx, hx, i0, wx);
-    tsc_w((y - f.gy0) * f.inv_dy, hy, j0, wy);
+    FT wx[3], wy[3];
+    tsc_w<FT>((x - f.gx0) * f.inv_dx, hx, i0, wx);
+    tsc_w<FT>((y - f.gy0) * f.inv_dy, hy, j0, wy);
     // A row's three taps are read by one load of three consecutive nodes s, s+1, s+2, with
     // s = i0 clamped into [0, nx - 3] (nx >= 3).  Node s + k is tap k - (i0 - s); every tap
     // on the grid falls in this window and every tap off it falls outside, so slot k takes
@@ -106,10 +109,12 @@ __device__ __forceinline__ double tsc_gather(const GridDev &f, int hx, int hy, d
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         const int a = k - d, j = j0 + k;
-        ws[k] = (FT)(a == 0 ? wx[0] : a == 1 ? wx[1] : a == 2 ? wx[2] : 0.0);
+        // selects, not branches: a is the same for every lane away from the grid's edges
+        const FT s01 = a == 0 ? wx[0] : wx[1], s2 = a == 2 ? wx[2] : (FT)0;
+        ws[k] = (a == 0 || a == 1) ? s01 : s2;
         on[k] = j >= 0 && j < f.ny;
         jj[k] = j;
-        wr[k] = on[k] ? (FT)wy[k] : (FT)0;
+        wr[k] = on[k] ? wy[k] : (FT)0;
     }
     FT sum = 0;
 #pragma unroll
@@ -221,6 +226,8 @@ __device__ __forceinline__ void field_kind(const FieldDev &f, double t, double x
         E.x = grid_gather<FT>(f.g, f.g.g[0], 1, 0, x, y);
         E.y = grid_gather<FT>(f.g, f.g.g[1], 0, 1, x, y);
         E.z = grid_gather<FT>(f.g, f.g.g[2], 0, 0, x, y);
+        // E's nine loads, then B's: all eighteen in flight at once would hold 54 registers
+        __builtin_amdgcn_sched_barrier(0);
         B.x = grid_gather<FT>(f.g, f.g.g[3], 0, 1, x, y);
         B.y = grid_gather<FT>(f.g, f.g.g[4], 1, 0, x, y);
         B.z = grid_gather<FT>(f.g, f.g.g[5], 1, 1, x, y);
