@@ -66,9 +66,18 @@ __device__ __forceinline__ void uniform4(uint64_t id, int64_t step, uint32_t str
 // FT: real type of the transcendental work (double, or float after an FP64 reduction of
 // the carrier phase).  Output fields are double.
 // Reciprocal and natural log: FP32 uses the hardware approximations (v_rcp_f32, v_log_f32,
-// about 1 ulp), FP64 the correctly rounded library forms.
+// about 1 ulp).  FP64: the hardware reciprocal estimate (v_rcp_f64) refined by two Newton
+// steps, e = 1 - v r, r += r e, each squaring the relative error, so within an ulp or two
+// of 1/v for the finite non-zero v it is used on (five instructions instead of the
+// correctly rounded division's ten); the library log.
 __device__ __forceinline__ float rcp(float v) { return __builtin_amdgcn_rcpf(v); }
-__device__ __forceinline__ double rcp(double v) { return 1.0 / v; }
+__device__ __forceinline__ double rcp(double v) {
+    double r = __builtin_amdgcn_rcp(v);
+    double e = fma(-v, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-v, r, 1.0);
+    return fma(r, e, r);
+}
 __device__ __forceinline__ float lnx(float v) { return __builtin_amdgcn_logf(v) * 0.69314718055994531f; }
 __device__ __forceinline__ double lnx(double v) { return log(v); }
 // a - round(a) for a phase given in revolutions, i.e. the phase reduced to [-1/2, 1/2]
@@ -190,12 +199,13 @@ __device__ __forceinline__ void field_pulse(const FieldDev &f, double t, double 
             c1 = -P.a0 * (denv * ss + env * cs);
             c2 = f.circular ? -P.a0 * (denv * cs - env * ss) : 0.0;
         } else {
-            const double zr = P.zr;
             const double xi = P.x_focus - x;
             const double rho2 = y * y + z * z;
-            const double q = xi / zr, opq = 1.0 + q * q;
-            const double amp = P.a0 / sqrt(opq) * exp(-rho2 / (P.w0sq * opq));
-            const double small = atan(q) - rho2 * xi / (2.0 * (xi * xi + zr * zr));
+            // xi / (xi^2 + zr^2) = (q / zr) / (1 + q^2): one reciprocal serves the width, the
+            // Gaussian and the curvature term
+            const double q = xi * P.inv_zr, opq = 1.0 + q * q, iopq = rcp(opq);
+            const double amp = P.a0 * rsqrt(opq) * exp(-rho2 * P.inv_w0sq * iopq);
+            const double small = atan(q) - 0.5 * rho2 * q * P.inv_zr * iopq;
             double ss, cs;
             sincospi(2.0 * frac_rev((phi + P.phase0) * (0.5 * INV_PI)) + small * INV_PI, &ss, &cs);
             c1 = amp * env * cs;
@@ -260,7 +270,7 @@ __device__ __forceinline__ double boris(double q, double dt, const V3<double> &E
     pm = p + h * E;
     const double ig = rsqrt(1.0 + dot(pm, pm));
     const V3<double> tau = (h * ig) * B;
-    const V3<double> sig = (2.0 / (1.0 + dot(tau, tau))) * tau;
+    const V3<double> sig = (2.0 * rcp(1.0 + dot(tau, tau))) * tau;
     const V3<double> pr = pm + cross(pm, tau);
     pp = pm + cross(pr, sig);
     p = pp + h * E;
