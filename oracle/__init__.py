@@ -76,6 +76,7 @@ def lib():
             "orc_sampler_targets_n": (None, [vp, i64, vp, vp, vp, vp, vp]),
             "orc_tab_nbw_rate": (None, [vp, d, dp, dp]),
             "orc_tab_nbw_sample_delta": (d, [vp, d, d, d]),
+            "orc_nbw_sampler_targets_n": (None, [vp, i64, vp, vp, vp, vp]),
             "orc_tab_vb_M": (None, [vp, d, vp]),
             "orc_field_eval": (None, [vp, d, vp, vp, vp]),
             "orc_push_spin": (None, [vp, vp, vp, i64, vp]),
@@ -309,6 +310,14 @@ class Tables:
 
     def nbw_sample_delta(self, chi, xi3, r):
         return lib().orc_tab_nbw_sample_delta(self.h, float(chi), float(xi3), float(r))
+
+    def nbw_sampler_targets(self, chi, xi3, r) -> np.ndarray:
+        """[n, 3]: table-sampler delta and the mean positron / electron spin along b
+        (orc_nbw_sampler_targets)."""
+        chi, xi3, r = (_f64(v) for v in (chi, xi3, r))
+        out = np.zeros((len(chi), 3))
+        lib().orc_nbw_sampler_targets_n(self.h, len(chi), _p(chi), _p(xi3), _p(r), _p(out))
+        return out
 
     def rad(self, chi) -> np.ndarray:
         """g(chi) (emitted / Larmor power) and psi1..psi3 from the RAD table."""

@@ -711,6 +711,31 @@ double orc_tab_nbw_sample_delta(const orc_tables *T, double chi, double xi3, dou
     if (r <= 0.5) return cdf_invert(A0, A1, B0, B1, NDD, f, m, r * (1 - m)) * hd;
     return 1.0 - cdf_invert(A0, A1, B0, B1, NDD, f, m, (1 - r) * (1 - m)) * hd;
 }
+/* Targets of the learned NBW sampler (a function the library's second network is trained
+ * to reproduce; not a step of the paper's algorithm).  For a pair creation at chi_gamma by
+ * a photon with Stokes parameter xi3 (in its basis e1 = a_+, Sec. III.D) and energy draw r:
+ * out[0] = delta, the positron's energy fraction, from the tabulated spectrum (the table
+ * sampler); out[1], out[2] = the mean spin of the positron and of the electron along
+ * b = v x a at that delta with xi1 = xi2 = 0, summed over the partner's spin.  Summing
+ * eqs. (G0)-(G3) over S_- = +-zeta drops every term linear in S_-; what is left at S_+ is
+ * 2 [A + S_+ . B_+] with A = I + (rs - xi3) K2 and B_+ . b = K1 (xi3 / e_- - 1 / e_+), so
+ * <S_+ . b> = B_+ . b / A; for the electron B_- . b = K1 (1 / e_- - xi3 / e_+) by the same
+ * sum over S_+.  (e_+ = delta, e_- = 1 - delta, rs = (e_+^2 + e_-^2) / (e_+ e_-).)          */
+void orc_nbw_sampler_targets(const orc_tables *T, double chi, double xi3, double r, double out[3]) {
+    const double d = orc_tab_nbw_sample_delta(T, chi, xi3, r);
+    const double ep = d, em = 1 - d;
+    double I, K1, K2;
+    tab_bessel_scaled(T, 2 / (3 * chi * ep * em), &I, &K1, &K2);
+    const double rs = (ep * ep + em * em) / (ep * em);
+    const double A = I + (rs - xi3) * K2;
+    out[0] = d;
+    out[1] = K1 * (xi3 / em - 1 / ep) / A;
+    out[2] = K1 * (1 / em - xi3 / ep) / A;
+}
+void orc_nbw_sampler_targets_n(const orc_tables *T, int64_t n, const double *chi, const double *xi3, const double *r,
+                               double *out) {
+    for (int64_t k = 0; k < n; ++k) orc_nbw_sampler_targets(T, chi[k], xi3[k], r[k], out + 3 * k);
+}
 static void vb_lookup(const orc_tables *T, double chi, double M[2], uint32_t *st) {
     double l = chi > 0 ? log(chi) : -1e300;
     if (l < V_LO) { M[0] = 4.0; M[1] = 7.0; return; }

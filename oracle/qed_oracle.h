@@ -76,6 +76,10 @@ void orc_sampler_targets_n(const orc_tables *t, int64_t n, const double *chi, co
                            const double *r, double *out);
 void orc_tab_nbw_rate(const orc_tables *t, double chi, double *Ja, double *Jb);
 double orc_tab_nbw_sample_delta(const orc_tables *t, double chi, double xi3, double r);
+/* learned NBW sampler targets: delta from the table sampler, mean positron / electron spin along b */
+void orc_nbw_sampler_targets(const orc_tables *t, double chi, double xi3, double r, double out[3]);
+void orc_nbw_sampler_targets_n(const orc_tables *t, int64_t n, const double *chi, const double *xi3, const double *r,
+                               double *out);
 void orc_tab_vb_M(const orc_tables *t, double chi, double M[2]);
 /* radiative coefficients: out = {g(chi), psi1, psi2, psi3}                          */
 void orc_tab_rad(const orc_tables *t, double chi, double out[4]);

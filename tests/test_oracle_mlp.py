@@ -106,3 +106,63 @@ def test_targets_classical_limit_of_photon_polarisation(tab):
     T = tab.sampler_targets(np.full(m, 1e-3), np.zeros(m), np.zeros(m), r)
     assert abs(T[:, 1].mean() - 0.6) < 5e-3
     assert np.max(np.abs(T[:, 2])) == 0.0
+
+
+def _nbw_explicit_means(chi, xi3, d, zeta):
+    """<S+ . b>, <S- . b> at delta = d by summing eqs. (G0)-(G3) (exact Bessel functions,
+    orc_nbw_G) over both spins, the partner's along an arbitrary axis zeta."""
+    a, b, v = np.eye(3)[0], np.eye(3)[1], np.eye(3)[2]     # b = v x a
+    xi = np.array([0.0, 0.0, xi3])
+
+    def W(Sp, Sm):
+        G = oracle.nbw_G(d, chi, Sp, Sm, a, b, v)
+        return G[0] + xi @ G[1:]
+    num_p = num_m = den = 0.0
+    for s in (1.0, -1.0):
+        for t in (1.0, -1.0):
+            wp = W(s * b, t * zeta)          # positron along +-b, electron along +-zeta
+            wm = W(t * zeta, s * b)          # electron along +-b, positron along +-zeta
+            num_p += s * wp
+            num_m += s * wm
+            den += wp
+    return num_p / den, num_m / den
+
+
+def test_nbw_targets_equal_explicit_spin_sum(tab):
+    """NBW sampler targets: delta is the table sampler's, bit for bit; the mean positron and
+    electron spins along b equal the explicit sums of the G functions over both spins."""
+    g = np.random.default_rng(11)
+    done = 0
+    while done < 20:
+        chi = 10 ** g.uniform(np.log10(0.2), np.log10(50))
+        xi3 = g.uniform(-1, 1)
+        r = g.uniform(0.02, 0.98)
+        T = tab.nbw_sampler_targets([chi], [xi3], [r])[0]
+        assert T[0] == tab.nbw_sample_delta(chi, xi3, r)
+        d = T[0]
+        if 2 / (3 * chi * d * (1 - d)) > 900:       # beyond the Bessel table
+            continue
+        zeta = g.normal(size=3)
+        zeta /= np.linalg.norm(zeta)
+        mp, mm = _nbw_explicit_means(chi, xi3, d, zeta)
+        assert abs(T[1] - mp) < 1e-6, (chi, xi3, r, T, mp)
+        assert abs(T[2] - mm) < 1e-6, (chi, xi3, r, T, mm)
+        done += 1
+
+
+def test_nbw_targets_charge_conjugation_and_bounds(tab):
+    """Draws r and 1 - r give delta and 1 - delta (the spectrum's mirror), and the positron's
+    mean spin at one is minus the electron's at the other; every mean spin within [-1, 1]."""
+    m = 64
+    g = np.random.default_rng(12)
+    chi = 10 ** g.uniform(np.log10(0.1), np.log10(50), m)
+    xi3 = g.uniform(-1, 1, m)
+    r = g.uniform(0.01, 0.49, m)
+    A = tab.nbw_sampler_targets(chi, xi3, r)
+    B = tab.nbw_sampler_targets(chi, xi3, 1 - r)
+    assert np.allclose(A[:, 0] + B[:, 0], 1.0, rtol=0, atol=1e-12)
+    assert np.allclose(A[:, 1], -B[:, 2], rtol=0, atol=1e-9)
+    assert np.allclose(A[:, 2], -B[:, 1], rtol=0, atol=1e-9)
+    assert np.all(np.abs(np.concatenate([A[:, 1:], B[:, 1:]])) <= 1 + 1e-12)
+    # a soft positron (delta < 1/2, so xi3 / e_- < 1 / e_+) is polarised against b
+    assert np.all(A[:, 1] < 0)
