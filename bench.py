@@ -339,6 +339,7 @@ def run_learned(args, torch, Q, W, cfg, fp64, fp64_b=None):
                                       "a transcendental counts 4"},
     }
     del X, T64, Y
+    out["nbw"] = run_learned_nbw(torch, Q, W, best_ms)
     c2 = Q.Context(dt=0.01, procs=Q.PROC_NCS | Q.PROC_NCS_STOKES, seed=1, id_start=0, precision=Q.QED_MIXED)
     # the training step alone (three launches: forward + backward through the activations,
     # weight gradients, ordered sum + Adam), pairs resident, at the trainer's batch and at
@@ -376,6 +377,80 @@ def run_learned(args, torch, Q, W, cfg, fp64, fp64_b=None):
         if fp64_b is not None:
             out["step"]["error_tolerance"] = tolerance_check(out["step"]["error_vs_fp64"],
                                                              error_metrics(fp64, fp64_b, 2000.0, torch))
+    return out
+
+
+def run_learned_nbw(torch, Q, W, best_ms) -> dict:
+    """The NBW network (the shipped one): inference against the NBW table sampler on the
+    same inputs, and the pair step with the network against the table on the same photons
+    and draws (plane wave a0 = 300 at its peak, 2e6 photons of 1.5 GeV, mixed precision)."""
+    import numpy as np
+    out = {}
+    ctx = Q.Context(dt=0.01, procs=Q.PROC_NBW, seed=1, id_start=0, precision=Q.QED_MIXED)
+    ctx.mlp_load_pretrained(net=Q.NET_NBW)
+    n = 1 << 23
+    X, T64 = ctx.mlp_samples(n, seed=78)
+    Y = torch.empty((n, 3), dtype=torch.float32, device="cuda")
+    t_mlp = best_ms(lambda: ctx.mlp_forward(X, Y))
+    err_mlp = (Y - T64).abs().mean(0).cpu().tolist()
+    t_tab = best_ms(lambda: ctx.sampler_table(X, Y))
+    err_tab = (Y - T64).abs().mean(0).cpu().tolist()
+    out["sampler"] = {"samples": n, "network_samples_per_s": n / (t_mlp * 1e-3),
+                      "table_samples_per_s": n / (t_tab * 1e-3),
+                      "network_mean_abs_error_vs_fp64_table": err_mlp,
+                      "fp32_table_mean_abs_error_vs_fp64_table": err_tab,
+                      "network_bytes_bf16": Q.MLP_NPARAM * 2, "table_bytes_fp32": 4 * 2 * 256 * 512,
+                      "outputs": "delta, mean positron / electron spin along b"}
+    del X, T64, Y
+    npho, steps, s0 = 2_000_000, 20, 2000
+    st = W.photons(npho, seed=45, eps0=3000.0, eps_rel_spread=0.2, divergence=2e-3, x_mean=-2.0, x_sigma=1.0,
+                   r_sigma=1.0, id0=0)
+    spec = {"kind": W.FIELD_PW, "circular": 0, "a0": 300.0, "ncycles": 8.0, "phase0": 0.3, "pol_angle": 0.4,
+            "phi_start": 0.0}
+    k = torch.as_tensor(np.sqrt(st["kx"] ** 2 + st["ky"] ** 2 + st["kz"] ** 2), device="cuda")
+    res = {}
+    for name, sampler in (("table", Q.SAMPLER_TABLE), ("network", Q.SAMPLER_MLP_NBW)):
+        c = Q.Context(dt=W.TWO_PI / 500, procs=Q.PROC_VB | Q.PROC_NBW, seed=9, id_start=1 << 41,
+                      precision=Q.QED_MIXED)
+        c.mlp_load_pretrained(net=Q.NET_NBW)
+        c.set_sampler(sampler)
+        G = Q.Photons.from_state(st, precision=Q.QED_MIXED)
+        em, ep = Q.Leptons(400_000, -1, precision=Q.QED_MIXED), Q.Leptons(400_000, 1, precision=Q.QED_MIXED)
+        segs = Q.whole(spec)
+        c.step_photons(segs, G, em, ep, s0)          # warm-up (first launch of each kernel)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s in range(s0 + 1, s0 + 1 + steps):
+            c.step_photons(segs, G, em, ep, s)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        res[name] = {"ms_per_step": 1e3 * wall / steps, "pairs": int(ep.count), "status_bits": c.read_status(),
+                     "ep": ep, "alive": G.alive[:npho].clone()}
+    same_pairs = (res["table"]["pairs"] == res["network"]["pairs"] and
+                  bool(torch.equal(res["table"]["alive"], res["network"]["alive"])))
+    # the same photons convert in both runs and the pairs come in the same order, so the
+    # positron energies compare pair by pair and as spectra
+    dead = torch.nonzero(res["table"]["alive"] == 0).flatten()
+    step_err = None
+    if same_pairs:
+        en = {}
+        for name in ("table", "network"):
+            ep = res[name]["ep"]
+            m = ep.count
+            en[name] = torch.sqrt(1 + ep.px[:m].double() ** 2 + ep.py[:m].double() ** 2 + ep.pz[:m].double() ** 2)
+        scale = en["table"].mean()
+        ht = torch.histc(en["table"] / scale, bins=40, min=0, max=4)
+        hn = torch.histc(en["network"] / scale, bins=40, min=0, max=4)
+        step_err = {"positron_energy_hist_L1": float((ht - hn).abs().sum() / ht.sum()),
+                    "positron_mean_energy_rel": float((en["network"].mean() / scale - 1).abs()),
+                    "positron_energy_mean_abs_rel_diff": float(((en["network"] - en["table"]) / en["table"]).abs().mean())}
+    out["pair_step"] = {"photons": npho, "steps": steps, "start_step": s0, "converted": int(dead.numel()),
+                        "pairs_per_step": res["table"]["pairs"] / (steps + 1),
+                        "ms_per_step_table": res["table"]["ms_per_step"],
+                        "ms_per_step_network": res["network"]["ms_per_step"],
+                        "same_decisions": same_pairs, "error_vs_table": step_err,
+                        "status_bits": [res["table"]["status_bits"], res["network"]["status_bits"]],
+                        "what": "photon VB + NBW step, plane wave a0 = 300 near its peak, mixed precision"}
     return out
 
 

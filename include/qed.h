@@ -447,27 +447,43 @@ qed_status qed_set_tuning(qed_ctx_t *ctx, const qed_tuning *t);
  * outside graph capture, typically once per workload.                                  */
 qed_status qed_autotune(qed_ctx_t *ctx, const qed_segment *segs, int nseg, const qed_leptons *p,
                         int64_t step, int reps, qed_tuning *chosen, hipStream_t stream);
-/* ---- learned NCS sampler ------------------------------------------------------------
- * A 4-128-128-128-3 perceptron (SiLU after each hidden layer) per context.  Inputs of an
- * emission: x0 = (log10 chi + 0.65)/2.35 (chi in [1e-3, 50]), x1 = S.b, x2 = S.n (spin in
- * the local frame of Sec. III.C.1), x3 = 2 r - 1 (the energy draw); outputs: y0 = t/40^(1/3)
- * with t = (2u/(3 chi))^(1/3) the photon-fraction variable of the spectrum tables, y1, y2 =
- * the mean photon Stokes xi3, xi2 at that energy summed over the final spins (eqs. F0-F3).
+/* ---- learned samplers (NCS and NBW) -------------------------------------------------
+ * A 4-128-128-128-3 perceptron (SiLU after each hidden layer) per process and context.
+ * NCS network (QED_NET_NCS), inputs of an emission: x0 = (log10 chi + 0.65)/2.35 (chi in
+ * [1e-3, 50]), x1 = S.b, x2 = S.n (spin in the local frame of Sec. III.C.1), x3 = 2 r - 1
+ * (the energy draw); outputs: y0 = t/40^(1/3) with t = (2u/(3 chi))^(1/3) the
+ * photon-fraction variable of the spectrum tables, y1, y2 = the mean photon Stokes xi3, xi2
+ * at that energy summed over the final spins (eqs. F0-F3).
+ * NBW network (QED_NET_NBW), inputs of a pair creation (Sec. III.D): x0 = (log10 chi_gamma
+ * - m) / h with m, h the centre and half width of log10 chi_gamma over [0.1, 50], x1 = xi3
+ * (the photon's Stokes parameter in its basis e1), x2 = 0, x3 = 2 r - 1; outputs: y0 =
+ * delta, the positron's energy fraction, y1, y2 = the mean positron and electron spin
+ * along b = v x e1 at that delta with xi1 = xi2 = 0, summed over the partner's spin
+ * (eqs. G0-G3).
  * Parameters: one flat FP32 vector of QED_MLP_NPARAM = 34051 numbers, W1 (4 x 128, row =
  * input), b1, W2 (128 x 128), b2, W3, b3, W4 (128 x 3), b4.  Inference runs on BF16
- * matrix cores with FP32 accumulation; training (gradient, Adam) in FP32.  All pointers
- * below are device pointers unless stated; X is [n][4], Y / T are [n][3] floats.        */
+ * matrix cores with FP32 accumulation; training (gradient, Adam) in FP32.  The qed_mlp_*
+ * calls and qed_sampler_table act on the network chosen by qed_mlp_select (QED_NET_NCS
+ * by default).  All pointers below are device pointers unless stated; X is [n][4], Y / T
+ * are [n][3] floats.                                                                   */
 #define QED_MLP_NPARAM 34051
+#define QED_NET_NCS 0
+#define QED_NET_NBW 1
 #define QED_SAMPLER_TABLE 0
 #define QED_SAMPLER_MLP 1
+#define QED_SAMPLER_MLP_NBW 2
+/* the network the following qed_mlp_* / qed_sampler_table calls act on (QED_EARG for
+ * another value); a host-side setting, no device work                                   */
+qed_status qed_mlp_select(qed_ctx_t *ctx, int net);
 /* fresh weights (uniform +-1/sqrt(fan-in) from Philox(seed)), zero biases and Adam state */
 qed_status qed_mlp_init(qed_ctx_t *ctx, uint64_t seed, hipStream_t stream);
 /* copy parameters in / out (QED_MLP_NPARAM floats each) */
 qed_status qed_mlp_set_params(qed_ctx_t *ctx, const float *params, hipStream_t stream);
 qed_status qed_mlp_get_params(qed_ctx_t *ctx, float *params_out, hipStream_t stream);
-/* n training pairs from the library's FP64 tables: inputs drawn with Philox(seed) (chi
- * log-uniform on [1e-3, 50], isotropic spin, uniform draw), targets = the table sampler's
- * t and the exact spin-summed mean Stokes at that energy, computed from the rounded X   */
+/* n training pairs from the library's FP64 tables: inputs drawn with Philox(seed) (NCS: chi
+ * log-uniform on [1e-3, 50], isotropic spin, uniform draw; NBW: chi_gamma log-uniform on
+ * [0.1, 50], xi3 uniform on [-1, 1], uniform draw), targets = the table sampler's t (delta)
+ * and the exact spin-summed means at that energy, computed from the rounded X            */
 qed_status qed_mlp_samples(qed_ctx_t *ctx, int64_t n, uint64_t seed, float *X, float *Y, hipStream_t stream);
 /* inference: Y = net(X) */
 qed_status qed_mlp_forward(qed_ctx_t *ctx, const float *X, float *Y, int64_t n, hipStream_t stream);
@@ -481,10 +497,14 @@ qed_status qed_mlp_train_step(qed_ctx_t *ctx, const float *X, const float *T, in
 /* the table sampler on the same normalised inputs and outputs (tables of the context's
  * precision): the reference for the network's error and its fallback                */
 qed_status qed_sampler_table(qed_ctx_t *ctx, const float *X, float *Y, int64_t n, hipStream_t stream);
-/* which sampler later NCS emissions use: QED_SAMPLER_TABLE (default) or QED_SAMPLER_MLP
- * (the network's t inside its trained chi range where 0.5 <= t < t_max, the table
- * elsewhere: below t = 0.5 the network's absolute error is a large relative error in the
- * photon energy u ~ t^3)                                                                 */
+/* which samplers later events use: QED_SAMPLER_TABLE (default), or the bits
+ * QED_SAMPLER_MLP (NCS emissions: the network's t inside its trained chi range where
+ * 0.5 <= t < t_max, the table elsewhere: below t = 0.5 the network's absolute error is a
+ * large relative error in the photon energy u ~ t^3) and QED_SAMPLER_MLP_NBW (pair
+ * creations: the network's delta inside its trained chi_gamma range where
+ * 0.05 <= delta <= 0.95, the table elsewhere).  The final spins and the photon's Stokes
+ * state are always drawn from the exact F / G at the sampled energy.  QED_ESTATE if the
+ * network a bit asks for has no parameters.                                              */
 qed_status qed_set_sampler(qed_ctx_t *ctx, int sampler);
 /* Last argument / HIP error of this context as text (empty if none). */
 const char *qed_last_error(const qed_ctx_t *ctx);

@@ -27,7 +27,7 @@ EXPORTED = ["qed_init_tables", "qed_destroy", "qed_gather", "qed_push_spin", "qe
             "qed_clear_status", "qed_get_next_id", "qed_set_next_id", "qed_table_size", "qed_table_export",
             "qed_set_step_events", "qed_set_photon_events", "qed_set_step_counter", "qed_advance_step", "qed_get_tuning",
             "qed_set_tuning", "qed_autotune", "qed_mlp_init", "qed_mlp_set_params", "qed_mlp_get_params",
-            "qed_mlp_samples", "qed_mlp_forward", "qed_mlp_gradient", "qed_mlp_train_step", "qed_set_sampler",
+            "qed_mlp_samples", "qed_mlp_forward", "qed_mlp_gradient", "qed_mlp_train_step", "qed_set_sampler", "qed_mlp_select",
             "qed_sampler_table", "qed_hist_photons", "qed_hist_leptons", "qed_field_advance",
             "qed_deposit_current", "qed_save_start", "qed_brems_init", "qed_brems_tables", "qed_step_brems",
             "qed_last_error"]
@@ -35,7 +35,8 @@ EXPORTED = ["qed_init_tables", "qed_destroy", "qed_gather", "qed_push_spin", "qe
 MLP_NPARAM = 34051
 BREMS_NE, BREMS_NU = 256, 128
 NOALLOC_MAX_LEPTONS = 524288
-SAMPLER_TABLE, SAMPLER_MLP = 0, 1
+SAMPLER_TABLE, SAMPLER_MLP, SAMPLER_MLP_NBW = 0, 1, 2
+NET_NCS, NET_NBW = 0, 1
 
 ALPHA = 1.0 / 137.035999084
 XI_L = 2.42631023867e-6
@@ -173,6 +174,7 @@ def lib():
             "qed_mlp_gradient": [vp, vp, vp, i64, vp, vp, vp, vp],
             "qed_mlp_train_step": [vp, vp, vp, i64, vp, C.c_float, vp, vp],
             "qed_set_sampler": [vp, C.c_int],
+            "qed_mlp_select": [vp, C.c_int],
             "qed_sampler_table": [vp, vp, vp, i64, vp],
         }
         for name, args in sig.items():
@@ -623,11 +625,21 @@ class Context:
                     "qed_sampler_table")
         return Y
 
-    def mlp_load_pretrained(self, path: str | None = None):
-        """Parameters of the network shipped with the package (sampler_ncs.npy: trained by
+    def mlp_select(self, net: int):
+        """The network later mlp_* / sampler_table calls act on: NET_NCS or NET_NBW."""
+        self._check(lib().qed_mlp_select(self.h, int(net)), "qed_mlp_select")
+
+    def mlp_load_pretrained(self, path: str | None = None, net: int | None = None):
+        """Parameters of a network shipped with the package into that network (the selected
+        one if net is None; the selection is left at net): sampler_ncs.npy, trained by
         `python -m paper_2306_11288_amd.train_sampler --samples 50000000 --epochs 2
-        --batch 4096 --seed 0`), or of another .npy file."""
-        p = np.load(path or os.path.join(_HERE, "sampler_ncs.npy"), allow_pickle=False)
+        --batch 4096 --seed 0`; sampler_nbw.npy, by `python -m
+        paper_2306_11288_amd.train_sampler --net nbw --samples 50000000 --epochs 4 --batch
+        4096 --seed 0`; or another .npy file."""
+        if net is not None:
+            self.mlp_select(net)
+        name = "sampler_nbw.npy" if net == NET_NBW else "sampler_ncs.npy"
+        p = np.load(path or os.path.join(_HERE, name), allow_pickle=False)
         self.mlp_set_params(p.astype(np.float32))
 
     def set_sampler(self, sampler: int):

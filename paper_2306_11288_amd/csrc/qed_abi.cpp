@@ -230,12 +230,7 @@ void free_ctx(qed_ctx *c) {
     hipFree(c->scan_sums);
     hipFree(c->staging);
     hipFree(c->dsegs);
-    hipFree(c->mlp_P);
-    hipFree(c->mlp_m);
-    hipFree(c->mlp_v);
-    hipFree(c->mlp_G);
-    hipFree(c->mlp_WT);
-    hipFree(c->mlp_W32);
+    for (int k = 0; k < MLP_NETS; ++k) mlp_free(c->nets[k]);
     hipFree(c->br_tab64);
     hipFree(c->br_tab32);
     hipFree(c->mlp_work);
@@ -259,12 +254,12 @@ qed_status ensure_staging(qed_ctx *ctx, int64_t capacity) {
     const int64_t need = ((capacity + BLOCK - 1) / BLOCK) * BLOCK;
     // graphs captured while a device step counter is registered hold these buffers' addresses
     if (ctx->step_dev && ((need > ctx->staging_cap && ctx->staging_cap > 0) ||
-                          (ctx->sampler == QED_SAMPLER_MLP && need > ctx->ev_cap && ctx->ev_cap > 0)))
+                          (ctx->sampler != QED_SAMPLER_TABLE && need > ctx->ev_cap && ctx->ev_cap > 0)))
         return fail(ctx, QED_ESTATE,
                     "a list of %lld particles would reallocate the event staging area while a device step "
                     "counter is registered (captured graphs use it); unregister the counter first",
                     (long long)capacity);
-    if (ctx->sampler == QED_SAMPLER_MLP && need > ctx->ev_cap) {   // per-event network inputs / outputs
+    if (ctx->sampler != QED_SAMPLER_TABLE && need > ctx->ev_cap) {   // per-event network inputs / outputs
         hipFree(ctx->ev_in);
         hipFree(ctx->ev_out);
         ctx->ev_in = ctx->ev_out = nullptr;
@@ -591,7 +586,7 @@ qed_status qed_step_leptons_noalloc(qed_ctx_t *ctx, const qed_segment *segs, int
     if (p->capacity > NOALLOC_MAX)
         return fail(ctx, QED_EARG, "qed_step_leptons_noalloc: capacity %lld above the limit of %lld leptons",
                     (long long)p->capacity, (long long)NOALLOC_MAX);
-    if (ctx->sampler == QED_SAMPLER_MLP)
+    if (ctx->sampler & QED_SAMPLER_MLP)
         return fail(ctx, QED_ESTATE, "qed_step_leptons_noalloc: the learned sampler needs allocated buffers");
     if (!ctx->na_scratch)
         return fail(ctx, QED_ESTATE, "qed_step_leptons_noalloc: no scratch address for this device");
@@ -980,13 +975,13 @@ qed_status qed_mlp_set_params(qed_ctx_t *ctx, const float *params, hipStream_t s
     qed_status st = ready(ctx);
     if (st != QED_OK) return st;
     if (!params) return fail(ctx, QED_EARG, "qed_mlp_set_params: NULL");
-    hipError_t e = mlp_alloc(ctx);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(ctx->mlp_P, params, MLP_NPARAM * sizeof(float), hipMemcpyDeviceToDevice, s);
-    if (e == hipSuccess) e = hipMemsetAsync(ctx->mlp_m, 0, MLP_NPARAM * sizeof(float), s);
-    if (e == hipSuccess) e = hipMemsetAsync(ctx->mlp_v, 0, MLP_NPARAM * sizeof(float), s);
-    if (e == hipSuccess) e = mlp_pack(ctx, s);
-    ctx->mlp_t = 0;
+    MlpNet &N = ctx->nets[ctx->mlp_sel];
+    hipError_t e = mlp_alloc(N);
+    if (e == hipSuccess) e = hipMemcpyAsync(N.P, params, MLP_NPARAM * sizeof(float), hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = hipMemsetAsync(N.m, 0, MLP_NPARAM * sizeof(float), s);
+    if (e == hipSuccess) e = hipMemsetAsync(N.v, 0, MLP_NPARAM * sizeof(float), s);
+    if (e == hipSuccess) e = mlp_pack(N, s);
+    N.t = 0;
     return launched(ctx, e, "qed_mlp_set_params");
 }
 
@@ -994,8 +989,8 @@ qed_status qed_mlp_get_params(qed_ctx_t *ctx, float *out, hipStream_t s) {
     qed_status st = ready(ctx);
     if (st != QED_OK) return st;
     if (!out) return fail(ctx, QED_EARG, "qed_mlp_get_params: NULL");
-    if (!ctx->mlp_P) return fail(ctx, QED_ESTATE, "qed_mlp_get_params: no network (qed_mlp_init first)");
-    return launched(ctx, hipMemcpyAsync(out, ctx->mlp_P, MLP_NPARAM * sizeof(float), hipMemcpyDeviceToDevice, s),
+    if (!ctx->nets[ctx->mlp_sel].P) return fail(ctx, QED_ESTATE, "qed_mlp_get_params: no network (qed_mlp_init first)");
+    return launched(ctx, hipMemcpyAsync(out, ctx->nets[ctx->mlp_sel].P, MLP_NPARAM * sizeof(float), hipMemcpyDeviceToDevice, s),
                     "qed_mlp_get_params");
 }
 
@@ -1010,22 +1005,22 @@ qed_status qed_mlp_samples(qed_ctx_t *ctx, int64_t n, uint64_t seed, float *X, f
 qed_status qed_mlp_forward(qed_ctx_t *ctx, const float *X, float *Y, int64_t n, hipStream_t s) {
     qed_status st = ready(ctx);
     if (st != QED_OK) return st;
-    if (!ctx->mlp_P) return fail(ctx, QED_ESTATE, "qed_mlp_forward: no network (qed_mlp_init first)");
+    if (!ctx->nets[ctx->mlp_sel].P) return fail(ctx, QED_ESTATE, "qed_mlp_forward: no network (qed_mlp_init first)");
     if (n < 0 || (n > 0 && (!X || !Y))) return fail(ctx, QED_EARG, "qed_mlp_forward: bad arguments");
     if (n == 0) return QED_OK;
-    return launched(ctx, mlp_forward(ctx, X, Y, n, nullptr, n, s), "qed_mlp_forward");
+    return launched(ctx, mlp_forward(ctx, ctx->nets[ctx->mlp_sel], X, Y, n, nullptr, n, s), "qed_mlp_forward");
 }
 
 qed_status qed_mlp_gradient(qed_ctx_t *ctx, const float *X, const float *T, int64_t n, const float *w,
                             float *grad_out, float *loss_out, hipStream_t s) {
     qed_status st = ready(ctx);
     if (st != QED_OK) return st;
-    if (!ctx->mlp_P) return fail(ctx, QED_ESTATE, "qed_mlp_gradient: no network (qed_mlp_init first)");
+    if (!ctx->nets[ctx->mlp_sel].P) return fail(ctx, QED_ESTATE, "qed_mlp_gradient: no network (qed_mlp_init first)");
     if (n < 1 || n > (1 << 24) || !X || !T || !w || !loss_out)
         return fail(ctx, QED_EARG, "qed_mlp_gradient: bad arguments (1 <= n <= 2^24)");
     hipError_t e = mlp_grad(ctx, X, T, n, w, loss_out, s);
     if (e == hipSuccess && grad_out)
-        e = hipMemcpyAsync(grad_out, ctx->mlp_G, MLP_NPARAM * sizeof(float), hipMemcpyDeviceToDevice, s);
+        e = hipMemcpyAsync(grad_out, ctx->nets[ctx->mlp_sel].G, MLP_NPARAM * sizeof(float), hipMemcpyDeviceToDevice, s);
     return launched(ctx, e, "qed_mlp_gradient");
 }
 
@@ -1033,7 +1028,7 @@ qed_status qed_mlp_train_step(qed_ctx_t *ctx, const float *X, const float *T, in
                               float *loss_out, hipStream_t s) {
     qed_status st = ready(ctx);
     if (st != QED_OK) return st;
-    if (!ctx->mlp_P) return fail(ctx, QED_ESTATE, "qed_mlp_train_step: no network (qed_mlp_init first)");
+    if (!ctx->nets[ctx->mlp_sel].P) return fail(ctx, QED_ESTATE, "qed_mlp_train_step: no network (qed_mlp_init first)");
     if (n < 1 || n > (1 << 24) || !X || !T || !w || !loss_out)
         return fail(ctx, QED_EARG, "qed_mlp_train_step: bad arguments (1 <= n <= 2^24)");
     if (!(lr > 0)) return fail(ctx, QED_EARG, "qed_mlp_train_step: lr must be positive");
@@ -1050,11 +1045,21 @@ qed_status qed_sampler_table(qed_ctx_t *ctx, const float *X, float *Y, int64_t n
 
 qed_status qed_set_sampler(qed_ctx_t *ctx, int sampler) {
     if (!ctx) return QED_EARG;
-    if (sampler != QED_SAMPLER_TABLE && sampler != QED_SAMPLER_MLP)
+    if (sampler & ~(QED_SAMPLER_MLP | QED_SAMPLER_MLP_NBW))
         return fail(ctx, QED_EARG, "qed_set_sampler: unknown sampler %d", sampler);
-    if (sampler == QED_SAMPLER_MLP && !ctx->mlp_P)
-        return fail(ctx, QED_ESTATE, "qed_set_sampler: no network (qed_mlp_init or qed_mlp_set_params first)");
+    if ((sampler & QED_SAMPLER_MLP) && !ctx->nets[QED_NET_NCS].P)
+        return fail(ctx, QED_ESTATE, "qed_set_sampler: no NCS network (qed_mlp_init or qed_mlp_set_params first)");
+    if ((sampler & QED_SAMPLER_MLP_NBW) && !ctx->nets[QED_NET_NBW].P)
+        return fail(ctx, QED_ESTATE, "qed_set_sampler: no NBW network (qed_mlp_select(QED_NET_NBW), then "
+                                     "qed_mlp_init or qed_mlp_set_params)");
     ctx->sampler = sampler;
+    return QED_OK;
+}
+
+qed_status qed_mlp_select(qed_ctx_t *ctx, int net) {
+    if (!ctx) return QED_EARG;
+    if (net != QED_NET_NCS && net != QED_NET_NBW) return fail(ctx, QED_EARG, "qed_mlp_select: unknown network %d", net);
+    ctx->mlp_sel = net;
     return QED_OK;
 }
 

@@ -778,13 +778,14 @@ __device__ __forceinline__ double nbw_prob(const Consts &c, const TB &tb, double
 // pair creation (given the draws r, the rotated xi and basis e1): delta by the inverse
 // spectrum (r1), SQAs D/|D|, D'/|D'| (eqs. BWposAxis, BWeleAxis), spin pair picked by r3
 // from the weights of eqs. G0-G3 in the order (+,+),(+,-),(-,+),(-,-).
+// nbw_pair_d: the same with delta already drawn (by the table inverse CDF with r1, or by
+// the learned sampler).
 template <class T>
-__device__ __forceinline__ void nbw_pair(const Tabs<T> &tb, const V3<double> &k, double chi, T kappa, const V3<T> &xi,
-                                         const V3<T> &e1, const double r[4], uint32_t &st, PairOut<T> &po) {
+__device__ __forceinline__ void nbw_pair_d(const Tabs<T> &tb, const V3<double> &k, double chi, T d, const V3<T> &xi,
+                                           const V3<T> &e1, const double r[4], uint32_t &st, PairOut<T> &po) {
     const double eps = sqrt(dot(k, k));
     const V3<double> n = (1.0 / eps) * k;
     const V3<T> nt = cvt<T>(n);
-    const T d = nbw_sample_delta<T>(tb, chi, kappa, xi.z, (T)r[0]);
     const double epl = (double)d * eps, emi = eps - epl;
     T I, K1, K2;
     bessel_scaled<T>(tb, (T)(2.0 / (3.0 * chi * (double)d * (1.0 - (double)d))), I, K1, K2);
@@ -818,6 +819,11 @@ __device__ __forceinline__ void nbw_pair(const Tabs<T> &tb, const V3<double> &k,
     po.pm = qm * n;
     po.Sp = (sel < 2 ? (T)1 : (T)-1) * zp;
     po.Sm = ((sel & 1) == 0 ? (T)1 : (T)-1) * zm;
+}
+template <class T>
+__device__ __forceinline__ void nbw_pair(const Tabs<T> &tb, const V3<double> &k, double chi, T kappa, const V3<T> &xi,
+                                         const V3<T> &e1, const double r[4], uint32_t &st, PairOut<T> &po) {
+    nbw_pair_d<T>(tb, k, chi, nbw_sample_delta<T>(tb, chi, kappa, xi.z, (T)r[0]), xi, e1, r, st, po);
 }
 
 // ------------------------------------------------------------------------- list access, ranks

@@ -156,6 +156,23 @@ constexpr double MLP_L10_MID = -0.65, MLP_L10_HALF = 2.35, MLP_L10_HI = 1.698970
 // in the photon energy u ~ t^3, and the step takes t from the table
 constexpr float MLP_Y_LO = 0.5f / 3.4199518933533937f;
 constexpr double MLP_CHI_LO = 1e-3, MLP_CHI_HI = 50.0;
+// the NBW network: chi_gamma in [0.1, 50] (pair creation below 0.1 is suppressed by
+// exp(-8 / (3 chi)) < 3e-12), x0 = (log10 chi - MID) / HALF; its delta is used inside
+// [MLP_D_LO, 1 - MLP_D_LO], where an absolute error is a small relative one in both
+// members' energies, the table's elsewhere
+constexpr double MLP_NBW_L10_LO = -1.0, MLP_NBW_L10_HI = 1.6989700043360187;
+constexpr double MLP_NBW_L10_MID = 0.5 * (MLP_NBW_L10_LO + MLP_NBW_L10_HI),
+                 MLP_NBW_L10_HALF = 0.5 * (MLP_NBW_L10_HI - MLP_NBW_L10_LO);
+constexpr double MLP_NBW_CHI_LO = 0.1, MLP_NBW_CHI_HI = 50.0;
+constexpr float MLP_D_LO = 0.05f;
+// one network per process: QED_NET_NCS (0), QED_NET_NBW (1)
+constexpr int MLP_NETS = 2;
+struct MlpNet {
+    float *P, *m, *v, *G;              // parameters, Adam moments, gradient [MLP_NPARAM]
+    void *WT;                          // bf16 transposed W2, W3 for the forward kernel
+    float *W32;                        // FP32 transposed W2, W3 for the backward pass
+    int t;                             // Adam step count
+};
 
 // detector histogram launch (one energy axis at most, HIST_EMAX bins on it)
 constexpr int HIST_EMAX = 256;
@@ -216,14 +233,12 @@ struct qed_ctx {
     int64_t *step_dev;                 // optional device step counter (caller-owned)
     int num_cu;                        // compute units of the device
     qed_tuning tune;                   // launch shape of the lepton step (qed_autotune)
-    // learned sampler
-    float *mlp_P, *mlp_m, *mlp_v, *mlp_G;   // parameters, Adam moments, gradient [MLP_NPARAM]
-    void *mlp_WT;                      // bf16 transposed W2, W3 for the forward kernel
-    float *mlp_W32;                    // FP32 transposed W2, W3 for the backward pass
-    int mlp_t;                         // Adam step count
+    // learned samplers
+    qed::MlpNet nets[qed::MLP_NETS];   // the NCS and the NBW network
+    int mlp_sel;                       // the network the qed_mlp_* calls act on
     float *mlp_work;                   // training work buffers
     int64_t mlp_work_len;
-    int sampler;                       // QED_SAMPLER_TABLE or QED_SAMPLER_MLP
+    int sampler;                       // QED_SAMPLER_TABLE, or bits QED_SAMPLER_MLP (NCS), QED_SAMPLER_MLP_NBW
     float *ev_in, *ev_out;             // learned sampler: per-event network inputs [ev_cap][4], outputs [ev_cap][3]
     double *hist_rep;                  // detector histogram replicas
     int64_t hist_rep_len;
@@ -317,12 +332,15 @@ hipError_t launch_deposit(qed_ctx *ctx, const qed_deposit_src *src, int nsrc, fl
 // detector histograms (qed_detector.hip)
 hipError_t launch_hist(qed_ctx *ctx, const HistArgs &a, bool photons, int64_t capacity, hipStream_t s);
 // learned sampler (qed_mlp.hip)
-hipError_t mlp_alloc(qed_ctx *ctx);
+// (the network is ctx->nets[ctx->mlp_sel] except where one is passed; samples and the
+// table sampler follow the selected network's process)
+hipError_t mlp_alloc(MlpNet &N);
+void mlp_free(MlpNet &N);
 hipError_t mlp_init(qed_ctx *ctx, uint64_t seed, hipStream_t s);
-hipError_t mlp_pack(qed_ctx *ctx, hipStream_t s);
+hipError_t mlp_pack(MlpNet &N, hipStream_t s);
 hipError_t mlp_samples(qed_ctx *ctx, int64_t n, uint64_t seed, float *X, float *Y, hipStream_t s);
-hipError_t mlp_forward(qed_ctx *ctx, const float *X, float *Y, int64_t n, const int64_t *n_dev, int64_t n_max,
-                       hipStream_t s);
+hipError_t mlp_forward(qed_ctx *ctx, const MlpNet &N, const float *X, float *Y, int64_t n, const int64_t *n_dev,
+                       int64_t n_max, hipStream_t s);
 hipError_t mlp_grad(qed_ctx *ctx, const float *X, const float *T, int64_t n, const float w[3], float *loss,
                     hipStream_t s);
 hipError_t mlp_train(qed_ctx *ctx, const float *X, const float *T, int64_t n, const float w[3], float lr,

@@ -586,6 +586,8 @@ struct PhotonArgs {
     int *tile_counts;
     const int64_t *tile_off;
     const int64_t *launch;
+    float *ev_in;              // learned NBW sampler: per-pair network inputs [pairs][4]
+    const float *ev_out;       // and outputs [pairs][3]
 };
 
 // transport (+ NBW test), specialised on the field kind: a persistent grid sweeps the
@@ -680,9 +682,11 @@ __global__ __launch_bounds__(BLOCK) void k_photons_decide(PhotonArgs a) {
 }
 
 // pair events: electron to em, positron to ep, in photon order; one wavefront per group
-// of PH_GROUP tiles (pairs are rare: well under one per tile)
+// of PH_GROUP tiles (pairs are rare: well under one per tile).  MODE as for the lepton
+// events: EV_FULL (table delta), EV_PREP (the NBW network's inputs of every pair at its
+// rank, nothing else written), EV_FINISH (the network's delta where valid).
 constexpr int PH_GROUP = 32;
-template <class T>
+template <class T, int MODE>
 __global__ __launch_bounds__(BLOCK) void k_photons_events(PhotonArgs a) {
     const int64_t n = clamp_count(a.G.count, a.G.capacity);
     const int64_t ntiles = (n + BLOCK - 1) / BLOCK;
@@ -706,8 +710,23 @@ __global__ __launch_bounds__(BLOCK) void k_photons_events(PhotonArgs a) {
         nbw_prob<T>(a.c, tb, eps, chi, xi.z, Ja, kappa, st);
         double rr[4];
         uniform4(a.G.id[j], step_of(a), STREAM_NBW, a.c.seed, rr);
+        const bool in_range = chi >= MLP_NBW_CHI_LO && chi <= MLP_NBW_CHI_HI;
+        if constexpr (MODE == EV_PREP) {
+            float4 x = {0.0f, 0.0f, 0.0f, 0.0f};
+            if (in_range) x = {(float)((log10(chi) - MLP_NBW_L10_MID) / MLP_NBW_L10_HALF), (float)xi.z, 0.0f,
+                               (float)(2.0 * rr[0] - 1.0)};
+            ((float4 *)a.ev_in)[e] = x;
+            return;
+        }
+        // the network's delta inside its trained chi range where it lies in [MLP_D_LO,
+        // 1 - MLP_D_LO] (away from the ends, where an absolute error is a large relative
+        // one in the softer member's energy); the table everywhere else
+        const float dn = MODE == EV_FINISH ? a.ev_out[3 * e] : -1.0f;
+        const T d = (MODE == EV_FINISH && in_range && dn >= MLP_D_LO && dn <= 1.0f - MLP_D_LO)
+                        ? (T)dn
+                        : nbw_sample_delta<T>(tb, chi, kappa, xi.z, (T)rr[0]);
         PairOut<T> po;
-        nbw_pair<T>(tb, k, chi, kappa, xi, e1, rr, st, po);
+        nbw_pair_d<T>(tb, k, chi, d, xi, e1, rr, st, po);
         const qed_leptons *Ls[2] = {&a.em, &a.ep};
         const int has[2] = {a.has_em, a.has_ep};
         for (int s = 0; s < 2; ++s) {
@@ -849,7 +868,7 @@ static hipError_t launch_events(qed_ctx *ctx, const LeptonArgs &a, hipStream_t s
     const int64_t groups = ((a.L.capacity + BLOCK - 1) / BLOCK + G - 1) / G;
     const int64_t nb = (groups + BLOCK / 64 - 1) / (BLOCK / 64);
     const dim3 gd(nb < 1 ? 1 : (unsigned)nb);
-    if (ctx->sampler != QED_SAMPLER_MLP) {
+    if (!(ctx->sampler & QED_SAMPLER_MLP)) {
         hipLaunchKernelGGL((k_leptons_events<T, G, EV_FULL>), gd, dim3(BLOCK), 0, s, a);
         return hipGetLastError();
     }
@@ -857,7 +876,9 @@ static hipError_t launch_events(qed_ctx *ctx, const LeptonArgs &a, hipStream_t s
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     // the network over all events of the launch (count from the scan, on the device)
-    if ((e = mlp_forward(ctx, a.ev_in, ctx->ev_out, 0, a.launch + 3, a.L.capacity, s)) != hipSuccess) return e;
+    if ((e = mlp_forward(ctx, ctx->nets[QED_NET_NCS], a.ev_in, ctx->ev_out, 0, a.launch + 3, a.L.capacity, s)) !=
+        hipSuccess)
+        return e;
     hipLaunchKernelGGL((k_leptons_events<T, G, EV_FINISH>), gd, dim3(BLOCK), 0, s, a);
     return hipGetLastError();
 }
@@ -990,7 +1011,19 @@ static hipError_t launch_photons_stage(qed_ctx *ctx, const PhotonArgs &a, hipStr
     if (e != hipSuccess) return e;
     const int64_t groups = (a.G.capacity + (int64_t)BLOCK * PH_GROUP - 1) / ((int64_t)BLOCK * PH_GROUP);
     const int64_t nb = (groups + BLOCK / 64 - 1) / (BLOCK / 64);
-    hipLaunchKernelGGL(k_photons_events<T>, dim3((unsigned)(nb < 1 ? 1 : nb)), dim3(BLOCK), 0, s, a);
+    const dim3 gd((unsigned)(nb < 1 ? 1 : nb));
+    if (!(ctx->sampler & QED_SAMPLER_MLP_NBW)) {
+        hipLaunchKernelGGL((k_photons_events<T, EV_FULL>), gd, dim3(BLOCK), 0, s, a);
+        return hipGetLastError();
+    }
+    // learned delta: the network's inputs of every pair at its rank, the network over the
+    // device pair count, then the events
+    hipLaunchKernelGGL((k_photons_events<T, EV_PREP>), gd, dim3(BLOCK), 0, s, a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = mlp_forward(ctx, ctx->nets[QED_NET_NBW], a.ev_in, ctx->ev_out, 0, a.launch + 3, a.G.capacity, s)) !=
+        hipSuccess)
+        return e;
+    hipLaunchKernelGGL((k_photons_events<T, EV_FINISH>), gd, dim3(BLOCK), 0, s, a);
     return hipGetLastError();
 }
 
@@ -1026,6 +1059,8 @@ hipError_t launch_photons(qed_ctx *ctx, PhotonMode mode, const SegArgs &sa, cons
     a.tile_counts = ctx->tile_counts;
     a.tile_off = ctx->tile_off;
     a.launch = ctx->launch;
+    a.ev_in = ctx->ev_in;
+    a.ev_out = ctx->ev_out;
     if (ctx->cfg.precision == QED_MIXED) {
         a.tab = ctx->tab32;
         return launch_photons_t<float>(ctx, a, s, lep_start);

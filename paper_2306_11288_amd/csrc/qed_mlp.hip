@@ -1,8 +1,11 @@
-// Learned NCS sampler: a 4-128-128-128-3 perceptron (SiLU) that maps an emission's
-// (log chi, S.b, S.n, energy draw) to the photon-fraction variable t = (2u/(3 chi))^(1/3)
-// and the spin-summed mean photon Stokes xi3, xi2 (eqs. F0-F3 of Sec. III.C.1 summed over
-// the final spins).  It replaces the table inverse-CDF search of an emission; the table
-// sampler stays as the fallback outside the trained range and as the reference for its error.
+// Learned samplers: a 4-128-128-128-3 perceptron (SiLU) per process.  The NCS network maps
+// an emission's (log chi, S.b, S.n, energy draw) to the photon-fraction variable
+// t = (2u/(3 chi))^(1/3) and the spin-summed mean photon Stokes xi3, xi2 (eqs. F0-F3 of
+// Sec. III.C.1 summed over the final spins); the NBW network maps a pair creation's
+// (log chi_gamma, xi3, 0, energy draw) to the positron's energy fraction delta and the mean
+// positron and electron spin along b (eqs. G0-G3 of Sec. III.D summed over the partner's
+// spin).  Each replaces the table inverse-CDF search of an event; the table sampler stays
+// as the fallback outside the trained range and as the reference for its error.
 //
 //   * inference: k_mlp_forward, BF16 MFMA (v_mfma_f32_32x32x16_bf16) with FP32
 //     accumulation for the two 128 x 128 layers, weights and activations in LDS;
@@ -80,14 +83,53 @@ __global__ __launch_bounds__(BLOCK) void k_mlp_samples(SampleArgs a) {
     for (int j = 0; j < 3; ++j) a.Y[3 * k + j] = y[j];
 }
 
+// The NBW table sampler on normalised inputs (the function the NBW network learns): delta
+// from the tabulated pair spectrum at xi3; with xi1 = xi2 = 0, the sum of eqs. G0-G3 over the
+// partner's spin leaves A + S.B at the member's spin S, A = I + (rs - xi3) K2,
+// B_+ . b = K1 (xi3 / e_- - 1 / e_+), B_- . b = K1 (1 / e_- - xi3 / e_+) (e_+ = delta,
+// e_- = 1 - delta, rs = (e_+^2 + e_-^2) / (e_+ e_-)); the mean spins along b are B.b / A.
 template <class T>
+__device__ __forceinline__ void nbw_table_sampler(const T *tab, const float x[4], float y[3]) {
+    const double chi = exp10(MLP_NBW_L10_HALF * (double)x[0] + MLP_NBW_L10_MID);
+    const T xi3 = (T)x[1], rr = (T)(0.5 * ((double)x[3] + 1.0));
+    const Tabs<T> tb = {tab};
+    T Ja, Jb, kappa;
+    uint32_t st = 0;
+    nbw_rate<T>(tb, chi, Ja, Jb, kappa, st);
+    const T d = nbw_sample_delta<T>(tb, chi, kappa, xi3, rr);
+    T I, K1, K2;
+    bessel_scaled<T>(tb, (T)(2.0 / (3.0 * chi * (double)d * (1.0 - (double)d))), I, K1, K2);
+    const T ep = d, em = (T)1 - d, rs = (ep * ep + em * em) / (ep * em), A = I + (rs - xi3) * K2;
+    y[0] = (float)d;
+    y[1] = (float)(K1 * (xi3 / em - (T)1 / ep) / A);
+    y[2] = (float)(K1 * ((T)1 / em - xi3 / ep) / A);
+}
+
+// NBW training pairs: log10 chi_gamma uniform on the trained range, xi3 uniform on [-1, 1],
+// x2 = 0, the energy draw; targets from the rounded inputs
+__global__ __launch_bounds__(BLOCK) void k_nbw_samples(SampleArgs a) {
+    const int64_t k = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (k >= a.n) return;
+    double r[4];
+    uniform4((uint64_t)k, 0, STREAM_MLP + 1, a.seed, r);
+    const double l10 = MLP_NBW_L10_LO + r[0] * (MLP_NBW_L10_HI - MLP_NBW_L10_LO);
+    const float x[4] = {(float)((l10 - MLP_NBW_L10_MID) / MLP_NBW_L10_HALF), (float)(2.0 * r[1] - 1.0), 0.0f,
+                        (float)(2.0 * r[3] - 1.0)};
+    float y[3];
+    nbw_table_sampler<double>(a.tab64, x, y);
+    for (int j = 0; j < 4; ++j) a.X[4 * k + j] = x[j];
+    for (int j = 0; j < 3; ++j) a.Y[3 * k + j] = y[j];
+}
+
+template <class T, int NET>
 __global__ __launch_bounds__(BLOCK) void k_table_sampler(const T *tab, const float *X, float *Y, int64_t n) {
     const int64_t k = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     if (k >= n) return;
     const float4 v = ((const float4 *)X)[k];
     const float x[4] = {v.x, v.y, v.z, v.w};
     float y[3];
-    table_sampler<T>(tab, x, y);
+    if constexpr (NET == QED_NET_NBW) nbw_table_sampler<T>(tab, x, y);
+    else table_sampler<T>(tab, x, y);
     for (int j = 0; j < 3; ++j) Y[3 * k + j] = y[j];
 }
 
@@ -643,53 +685,71 @@ __global__ void k_mlp_init(float *P, uint64_t seed) {
 }  // namespace
 
 // ------------------------------------------------------------------------- host side
-hipError_t mlp_alloc(qed_ctx *ctx) {
-    if (ctx->mlp_P) return hipSuccess;
-    hipError_t e = hipMalloc(&ctx->mlp_P, MLP_NPARAM * sizeof(float));
-    if (e == hipSuccess) e = hipMalloc(&ctx->mlp_m, MLP_NPARAM * sizeof(float));
-    if (e == hipSuccess) e = hipMalloc(&ctx->mlp_v, MLP_NPARAM * sizeof(float));
-    if (e == hipSuccess) e = hipMalloc(&ctx->mlp_G, MLP_NPARAM * sizeof(float));
-    if (e == hipSuccess) e = hipMalloc(&ctx->mlp_WT, 2 * 128 * HS * sizeof(__bf16));
-    if (e == hipSuccess) e = hipMalloc(&ctx->mlp_W32, 2 * 128 * 128 * sizeof(float));
+hipError_t mlp_alloc(MlpNet &N) {
+    if (N.P) return hipSuccess;
+    hipError_t e = hipMalloc(&N.P, MLP_NPARAM * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc(&N.m, MLP_NPARAM * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc(&N.v, MLP_NPARAM * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc(&N.G, MLP_NPARAM * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc(&N.WT, 2 * 128 * HS * sizeof(__bf16));
+    if (e == hipSuccess) e = hipMalloc(&N.W32, 2 * 128 * 128 * sizeof(float));
     return e;
 }
 
-hipError_t mlp_pack(qed_ctx *ctx, hipStream_t s) {
-    hipLaunchKernelGGL(k_mlp_pack, dim3((2 * 128 * HS + 255) / 256), dim3(256), 0, s, ctx->mlp_P, (__bf16 *)ctx->mlp_WT);
+void mlp_free(MlpNet &N) {
+    (void)hipFree(N.P);
+    (void)hipFree(N.m);
+    (void)hipFree(N.v);
+    (void)hipFree(N.G);
+    (void)hipFree(N.WT);
+    (void)hipFree(N.W32);
+    N = MlpNet{};
+}
+
+hipError_t mlp_pack(MlpNet &N, hipStream_t s) {
+    hipLaunchKernelGGL(k_mlp_pack, dim3((2 * 128 * HS + 255) / 256), dim3(256), 0, s, N.P, (__bf16 *)N.WT);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_mlp_pack32, dim3(2 * 128 * 128 / 256), dim3(256), 0, s, ctx->mlp_P, ctx->mlp_W32,
-                       ctx->mlp_W32 + 128 * 128);
+    hipLaunchKernelGGL(k_mlp_pack32, dim3(2 * 128 * 128 / 256), dim3(256), 0, s, N.P, N.W32, N.W32 + 128 * 128);
     return hipGetLastError();
 }
 
 hipError_t mlp_init(qed_ctx *ctx, uint64_t seed, hipStream_t s) {
-    hipError_t e = mlp_alloc(ctx);
+    MlpNet &N = ctx->nets[ctx->mlp_sel];
+    hipError_t e = mlp_alloc(N);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_mlp_init, dim3((MLP_NPARAM + 255) / 256), dim3(256), 0, s, ctx->mlp_P, seed);
+    hipLaunchKernelGGL(k_mlp_init, dim3((MLP_NPARAM + 255) / 256), dim3(256), 0, s, N.P, seed);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if ((e = hipMemsetAsync(ctx->mlp_m, 0, MLP_NPARAM * sizeof(float), s)) != hipSuccess) return e;
-    if ((e = hipMemsetAsync(ctx->mlp_v, 0, MLP_NPARAM * sizeof(float), s)) != hipSuccess) return e;
-    ctx->mlp_t = 0;
-    return mlp_pack(ctx, s);
+    if ((e = hipMemsetAsync(N.m, 0, MLP_NPARAM * sizeof(float), s)) != hipSuccess) return e;
+    if ((e = hipMemsetAsync(N.v, 0, MLP_NPARAM * sizeof(float), s)) != hipSuccess) return e;
+    N.t = 0;
+    return mlp_pack(N, s);
 }
 
 hipError_t mlp_samples(qed_ctx *ctx, int64_t n, uint64_t seed, float *X, float *Y, hipStream_t s) {
     SampleArgs a{ctx->tab64, n, seed, X, Y};
-    hipLaunchKernelGGL(k_mlp_samples, dim3((unsigned)((n + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, s, a);
-    return hipGetLastError();
-}
-
-hipError_t table_sampler_run(qed_ctx *ctx, const float *X, float *Y, int64_t n, hipStream_t s) {
     const dim3 g((unsigned)((n + BLOCK - 1) / BLOCK));
-    if (ctx->cfg.precision == QED_MIXED) hipLaunchKernelGGL(k_table_sampler<float>, g, dim3(BLOCK), 0, s, ctx->tab32, X, Y, n);
-    else hipLaunchKernelGGL(k_table_sampler<double>, g, dim3(BLOCK), 0, s, ctx->tab64, X, Y, n);
+    if (ctx->mlp_sel == QED_NET_NBW) hipLaunchKernelGGL(k_nbw_samples, g, dim3(BLOCK), 0, s, a);
+    else hipLaunchKernelGGL(k_mlp_samples, g, dim3(BLOCK), 0, s, a);
     return hipGetLastError();
 }
 
-hipError_t mlp_forward(qed_ctx *ctx, const float *X, float *Y, int64_t n, const int64_t *n_dev, int64_t n_max,
-                       hipStream_t s) {
-    FwdArgs a{ctx->mlp_P, (const __bf16 *)ctx->mlp_WT, X, Y, n, n_dev};
+template <int NET>
+static void table_sampler_launch(qed_ctx *ctx, const float *X, float *Y, int64_t n, hipStream_t s) {
+    const dim3 g((unsigned)((n + BLOCK - 1) / BLOCK));
+    if (ctx->cfg.precision == QED_MIXED)
+        hipLaunchKernelGGL((k_table_sampler<float, NET>), g, dim3(BLOCK), 0, s, ctx->tab32, X, Y, n);
+    else hipLaunchKernelGGL((k_table_sampler<double, NET>), g, dim3(BLOCK), 0, s, ctx->tab64, X, Y, n);
+}
+hipError_t table_sampler_run(qed_ctx *ctx, const float *X, float *Y, int64_t n, hipStream_t s) {
+    if (ctx->mlp_sel == QED_NET_NBW) table_sampler_launch<QED_NET_NBW>(ctx, X, Y, n, s);
+    else table_sampler_launch<QED_NET_NCS>(ctx, X, Y, n, s);
+    return hipGetLastError();
+}
+
+hipError_t mlp_forward(qed_ctx *ctx, const MlpNet &N, const float *X, float *Y, int64_t n, const int64_t *n_dev,
+                       int64_t n_max, hipStream_t s) {
+    FwdArgs a{N.P, (const __bf16 *)N.WT, X, Y, n, n_dev};
     const int64_t tiles = (n_max + 31) / 32, per = MB / 64;
     int64_t blocks = (tiles + per - 1) / per;
     const int64_t cap = 4 * (int64_t)ctx->num_cu;
@@ -700,7 +760,7 @@ hipError_t mlp_forward(qed_ctx *ctx, const float *X, float *Y, int64_t n, const 
 }
 
 // One forward + backward pass over a batch (FP32 matrix cores): the gradient (flat
-// layout) into ctx->mlp_G and the mean loss into *loss; with train, also the Adam step on
+// layout) into the selected network's G and the mean loss into *loss; with train, also the Adam step on
 // the parameters.  Work buffers come from ctx->mlp_work (grown on demand).
 static hipError_t mlp_pass(qed_ctx *ctx, const float *X, const float *T, int64_t n, const float w[3], float *loss,
                            int train, float lr, hipStream_t s) {
@@ -716,10 +776,11 @@ static hipError_t mlp_pass(qed_ctx *ctx, const float *X, const float *T, int64_t
         ctx->mlp_work_len = need;
     }
     float *q = ctx->mlp_work;
+    MlpNet &N = ctx->nets[ctx->mlp_sel];
     TrainArgs a{};
-    a.P = ctx->mlp_P;
-    a.W2T = ctx->mlp_W32;
-    a.W3T = ctx->mlp_W32 + 128 * 128;
+    a.P = N.P;
+    a.W2T = N.W32;
+    a.W3T = N.W32 + 128 * 128;
     a.X = X;
     a.T = T;
     a.n = n;
@@ -748,22 +809,22 @@ static hipError_t mlp_pass(qed_ctx *ctx, const float *X, const float *T, int64_t
     r.lossp = a.lossp;
     r.ntile = ntile;
     r.inv_n = 1.0f / (float)n;
-    r.G = ctx->mlp_G;
+    r.G = N.G;
     r.loss = loss;
     r.train = train;
     if (train) {
-        ctx->mlp_t += 1;
-        r.t = ctx->mlp_t;
+        N.t += 1;
+        r.t = N.t;
         r.lr = lr;
         r.b1 = 0.9f;
         r.b2 = 0.999f;
         r.eps = 1e-8f;
-        r.P = ctx->mlp_P;
-        r.m = ctx->mlp_m;
-        r.v = ctx->mlp_v;
-        r.W2T = ctx->mlp_W32;
-        r.W3T = ctx->mlp_W32 + 128 * 128;
-        r.WT = (__bf16 *)ctx->mlp_WT;
+        r.P = N.P;
+        r.m = N.m;
+        r.v = N.v;
+        r.W2T = N.W32;
+        r.W3T = N.W32 + 128 * 128;
+        r.WT = (__bf16 *)N.WT;
     }
     hipLaunchKernelGGL(k_train_reduce, dim3((MLP_NPARAM + 255) / 256), dim3(256), 0, s, r);
     return hipGetLastError();

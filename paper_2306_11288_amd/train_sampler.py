@@ -1,11 +1,14 @@
-"""Train the learned NCS sampler of a context on the GPU with the library's own kernels.
+"""Train a learned sampler of a context (NCS or NBW) on the GPU with the library's own kernels.
 
-The training pairs come from the library's FP64 tables (qed_mlp_samples: chi log-uniform
-on [1e-3, 50], isotropic spin, uniform energy draw -> the table sampler's t and the exact
-spin-summed mean photon Stokes); the loss weights t by 1 and the two Stokes outputs by 0.3;
-Adam with a learning rate decaying geometrically from lr to lr_final.
+The training pairs come from the library's FP64 tables (qed_mlp_samples; NCS: chi
+log-uniform on [1e-3, 50], isotropic spin, uniform energy draw -> the table sampler's t and
+the exact spin-summed mean photon Stokes; NBW: chi_gamma log-uniform on [0.1, 50], xi3
+uniform, uniform draw -> the table sampler's delta and the mean pair spins along b); the
+loss weights the energy output by 1 and the two others by 0.3; Adam with a learning rate
+decaying geometrically from lr to lr_final.
 
     python -m paper_2306_11288_amd.train_sampler --samples 50000000 --out sampler.npy
+    python -m paper_2306_11288_amd.train_sampler --net nbw --samples 50000000 --out sampler_nbw.npy
 """
 from __future__ import annotations
 
@@ -56,6 +59,7 @@ def main():
     ap.add_argument("--epochs", type=float, default=1.0)
     ap.add_argument("--batch", type=int, default=8192)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--net", choices=("ncs", "nbw"), default="ncs")
     ap.add_argument("--out", default="")
     args = ap.parse_args()
     import numpy as np
@@ -64,6 +68,7 @@ def main():
     import paper_2306_11288_amd as Q
     torch.cuda.set_device(0)
     ctx = Q.Context(dt=0.01, procs=Q.PROC_NCS | Q.PROC_NCS_STOKES, seed=1, id_start=0, precision=Q.QED_MIXED)
+    ctx.mlp_select(Q.NET_NBW if args.net == "nbw" else Q.NET_NCS)
     res = train(ctx, args.samples, args.epochs, args.batch, seed=args.seed, log=lambda m: print(m, flush=True))
     if args.out:
         np.save(args.out, ctx.mlp_get_params().cpu().numpy())

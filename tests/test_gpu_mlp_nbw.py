@@ -1,0 +1,203 @@
+"""GPU tests of the learned NBW sampler (the pair spectrum of Sec. III.D) against the
+oracle: training pairs (inputs and targets), the table sampler on the same inputs, the
+plumbing of the learned pair step (network inputs at each pair's rank, the forward pass
+over the device pair count, the network's delta used where it is valid, the table
+elsewhere), and the network shipped with the package against the table sampler."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+import paper_2306_11288_amd as Q  # noqa: E402
+
+L10_LO, L10_HI = -1.0, math.log10(50.0)
+MID, HALF = 0.5 * (L10_LO + L10_HI), 0.5 * (L10_HI - L10_LO)
+D_LO = 0.05                               # the network's delta is used inside [D_LO, 1 - D_LO]
+SHIPPED = os.path.join(os.path.dirname(Q.__file__), "sampler_nbw.npy")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    Q.lib()
+
+
+def _say(msg):
+    print(f"[gpu-mlp-nbw] {msg}", flush=True)
+
+
+def _nbw_ctx(precision=Q.QED_MIXED, **kw):
+    c = Q.Context(dt=kw.get("dt", 0.01), procs=kw.get("procs", Q.PROC_NBW), seed=kw.get("seed", 1),
+                  id_start=kw.get("id_start", 0), precision=precision, p_max=kw.get("p_max", 0.1))
+    c.mlp_select(Q.NET_NBW)
+    return c
+
+
+def _denorm(X):
+    X = X.astype(np.float64)
+    return 10.0 ** (HALF * X[:, 0] + MID), X[:, 1], 0.5 * (X[:, 3] + 1.0)
+
+
+def test_training_pairs_match_oracle():
+    _say("training pairs")
+    c = _nbw_ctx()
+    X, Y = c.mlp_samples(3000, seed=5)
+    X, Y = X.cpu().numpy(), Y.cpu().numpy()
+    chi, xi3, r = _denorm(X)
+    assert chi.min() >= 0.0999 and chi.max() <= 50.01
+    assert np.all(np.abs(xi3) <= 1) and np.all(X[:, 2] == 0) and np.all((r > 0) & (r < 1))
+    want = oracle.tables().nbw_sampler_targets(chi, xi3, r)
+    err = np.abs(Y - want)
+    assert err[:, 0].max() < 2e-6, err[:, 0].max()
+    assert err[:, 1:].max() < 2e-6, err[:, 1:].max()
+    assert X[:, 0].min() < -0.95 and X[:, 0].max() > 0.95 and abs(X[:, 3].mean()) < 0.05
+    # the NCS network's pairs are untouched by the selection of the other one
+    c.mlp_select(Q.NET_NCS)
+    Xn, _ = c.mlp_samples(100, seed=5)
+    assert not np.array_equal(Xn.cpu().numpy()[:, 2], np.zeros(100))
+
+
+def test_table_sampler_fp32_against_fp64_targets():
+    """qed_sampler_table with the NBW network selected: the FP32 tables of a mixed context
+    against the FP64 targets (the reference the network is measured against)."""
+    _say("table sampler")
+    c = _nbw_ctx()
+    X, T64 = c.mlp_samples(1 << 15, seed=6)
+    Yt = c.sampler_table(X)
+    d = (Yt - T64).abs()
+    _say(f"FP32 table vs FP64: mean {d.mean(0).cpu().numpy()}, max {d.max(0).values.cpu().numpy()}")
+    assert float(d[:, 0].max()) < 1e-4
+    assert float(d[:, 1:].mean()) < 1e-4
+
+
+def _const_params(c0):
+    """A network whose output is (c0, 0, 0) for every input: all weights zero, b4 = c0."""
+    p = np.zeros(Q.MLP_NPARAM, dtype=np.float32)
+    p[Q.MLP_NPARAM - 3] = c0
+    return p
+
+
+def _pair_run(sampler, params, steps=40, n=40000, s0=2000):
+    """The photon VB + NBW step of the plane-wave case (a0 = 300, 1.5 GeV photons) near the
+    pulse's peak, FP64; per step the photons that converted (index order) and the pairs
+    appended."""
+    st = W.photons(n, seed=44, eps0=3000.0, eps_rel_spread=0.2, divergence=2e-3, x_mean=-2.0, x_sigma=1.0,
+                   r_sigma=1.0, id0=0)
+    spec = {"kind": W.FIELD_PW, "circular": 0, "a0": 300.0, "ncycles": 8.0, "phase0": 0.3, "pol_angle": 0.4,
+            "phi_start": 0.0}
+    c = _nbw_ctx(Q.QED_FP64, dt=W.TWO_PI / 500, procs=Q.PROC_VB | Q.PROC_NBW, seed=9, id_start=1 << 41)
+    c.mlp_set_params(params)
+    c.set_sampler(sampler)
+    G = Q.Photons.from_state(st)
+    em, ep = Q.Leptons(n, -1), Q.Leptons(n, 1)
+    k = np.sqrt(st["kx"] ** 2 + st["ky"] ** 2 + st["kz"] ** 2)   # photon energies never change
+    alive = np.ones(n, dtype=bool)
+    parents = []
+    for s in range(s0, s0 + steps):
+        c.step_photons(Q.whole(spec), G, em, ep, s)
+        now = G.to_numpy()["alive"].astype(bool)
+        parents.append(np.flatnonzero(alive & ~now))
+        alive = now
+    return c, np.concatenate(parents), k, em.to_numpy(), ep.to_numpy(), G
+
+
+def test_learned_pair_step_plumbing():
+    """With a constant network the step's pairs show the plumbing exactly: delta = 0.3 (inside
+    the valid window) gives every positron 0.3 of its photon's energy; delta = 0.02 (outside
+    it) leaves the table's delta everywhere, so the run equals the table run bit for bit;
+    pair counts, ids and birth places are the table run's in both."""
+    _say("plumbing")
+    ref = _pair_run(Q.SAMPLER_TABLE, _const_params(0.3))
+    a = _pair_run(Q.SAMPLER_MLP_NBW, _const_params(0.3))
+    b = _pair_run(Q.SAMPLER_MLP_NBW, _const_params(0.02))
+    _, par, k, em0, ep0, _ = ref
+    _say(f"{len(par)} pairs")
+    assert len(par) > 300 and len(ep0["x"]) == len(par), (len(par), len(ep0["x"]))
+    for run in (a, b):
+        c, par_r, _, em, ep, _ = run
+        assert np.array_equal(par_r, par)
+        assert np.array_equal(em["id"], em0["id"]) and np.array_equal(ep["id"], ep0["id"])
+        assert np.array_equal(ep["x"], ep0["x"]) and c.read_status() == 0
+    _, _, _, em, ep, _ = a
+    Ep = np.sqrt(1 + ep["px"] ** 2 + ep["py"] ** 2 + ep["pz"] ** 2)
+    Em = np.sqrt(1 + em["px"] ** 2 + em["py"] ** 2 + em["pz"] ** 2)
+    d = float(np.float32(0.3))              # the network's FP32 output
+    assert np.max(np.abs(Ep / (d * k[par]) - 1)) < 1e-12
+    assert np.max(np.abs(Em / ((1 - d) * k[par]) - 1)) < 1e-12
+    _, _, _, em, ep, _ = b
+    for key in ("px", "py", "pz", "sx", "sy", "sz"):
+        assert np.array_equal(ep[key], ep0[key]) and np.array_equal(em[key], em0[key]), key
+
+
+def test_selector_and_sampler_errors():
+    c = Q.Context(dt=0.01, procs=Q.PROC_NBW, seed=1, id_start=0, precision=Q.QED_MIXED)
+    with pytest.raises(RuntimeError):
+        c.set_sampler(Q.SAMPLER_MLP_NBW)                     # no NBW network yet
+    with pytest.raises(RuntimeError):
+        c.mlp_select(2)
+    with pytest.raises(RuntimeError):
+        c.set_sampler(4)
+    c.mlp_select(Q.NET_NBW)
+    c.mlp_init(seed=3)
+    c.set_sampler(Q.SAMPLER_MLP_NBW)
+    with pytest.raises(RuntimeError):
+        c.set_sampler(Q.SAMPLER_MLP | Q.SAMPLER_MLP_NBW)    # no NCS network
+
+
+@pytest.fixture(scope="module")
+def shipped():
+    """The NBW network shipped with the package (trained by the library on 5e7 pairs)."""
+    return np.load(SHIPPED, allow_pickle=False).astype(np.float32)
+
+
+def test_shipped_network_against_table_sampler(shipped):
+    """On fresh inputs: the network's delta and mean spins against the FP64 table sampler,
+    beside the FP32 table's own error; the network's bf16 weights against the FP32 pair
+    spectrum table it replaces (the memory it saves)."""
+    _say("shipped network")
+    c = _nbw_ctx()
+    c.mlp_set_params(shipped)
+    X, T64 = c.mlp_samples(1 << 16, seed=21)
+    d_mlp = (c.mlp_forward(X) - T64).abs().mean(0).cpu().numpy()
+    d_tab = (c.sampler_table(X) - T64).abs().mean(0).cpu().numpy()
+    _say(f"mean abs error: network {d_mlp}, FP32 table {d_tab}")
+    assert d_mlp[0] < 2e-3 and d_mlp[1] < 4e-3 and d_mlp[2] < 4e-3
+    assert d_tab[0] < 1e-5
+    net_bytes = Q.MLP_NPARAM * 2
+    table_bytes = 4 * 2 * 256 * 512                        # FP32 NBW spectrum table (A, B)
+    assert table_bytes > 15 * net_bytes
+
+
+def test_shipped_network_in_the_pair_step(shipped):
+    """The pair step with the shipped network against the table, pair by pair on the same
+    draws: the same photons convert (the decision does not depend on delta), ids and birth
+    places are equal, each pair's delta is within the network's error of the table's
+    (bitwise the table's where the network's delta falls outside [0.05, 0.95]), and the
+    positron spectra agree."""
+    _say("shipped network in the step")
+    ref = _pair_run(Q.SAMPLER_TABLE, shipped)
+    run = _pair_run(Q.SAMPLER_MLP_NBW, shipped)
+    _, par, k, em0, ep0, _ = ref
+    c, par_r, _, em, ep, _ = run
+    assert np.array_equal(par_r, par) and np.array_equal(ep["id"], ep0["id"]) and c.read_status() == 0
+    assert np.array_equal(ep["x"], ep0["x"]) and np.array_equal(em["x"], em0["x"])
+
+    def delta(L):
+        return np.sqrt(1 + L["px"] ** 2 + L["py"] ** 2 + L["pz"] ** 2) / k[par]
+    dt, dn = delta(ep0), delta(ep)
+    same = dn == dt
+    diff = np.abs(dn - dt)
+    _say(f"{len(par)} pairs, {int(same.sum())} from the table, mean |delta - table| {diff[~same].mean():.2e}")
+    assert (~same).sum() > 0.8 * len(par)
+    assert diff[~same].mean() < 3e-3 and diff.max() < 0.1
+    assert np.all((dn[~same] >= D_LO - 1e-6) & (dn[~same] <= 1 - D_LO + 1e-6))
+    hn, _ = np.histogram(dn, bins=20, range=(0, 1))
+    ht, _ = np.histogram(dt, bins=20, range=(0, 1))
+    assert np.abs(hn - ht).sum() < 0.05 * len(par)
