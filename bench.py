@@ -550,6 +550,9 @@ def cascade_once(args, torch, Q, W, prec, seed_offset=0, timed=True):
     warm, steps = args.cascade_warmup, args.cascade_steps
     solver = not args.static_grid
     deposit = solver and not args.no_deposit
+    # the lists are kept in cell order by the periodic sort: the local deposition path
+    dep_path = "local" if (sort_every > 0 and args.deposit_path == "local") else "binned"
+    ctx.set_deposit_path(Q.DEPOSIT_LOCAL if dep_path == "local" else Q.DEPOSIT_BINNED)
     J = [torch.zeros((grid["ny"], grid["nx"]), dtype=torch.float32, device="cuda") for _ in range(3)]
     start = {"em": ctx.save_start(lists["em"]), "ep": ctx.save_start(lists["ep"])}
 
@@ -611,7 +614,8 @@ def cascade_once(args, torch, Q, W, prec, seed_offset=0, timed=True):
     res = {"summary": summary, "counts0": counts0, "counts1": counts1, "status_bits": ctx.read_status(),
            "t_ph": t_ph, "t_all": t_all, "t_d": t_d, "t_f": t_f, "t_sort": t_sort, "sort_every": sort_every,
            "wall": wall, "n": n, "warm": warm,
-           "steps": steps, "solver": solver, "deposit": deposit, "grid": grid, "tuning": tuning}
+           "steps": steps, "solver": solver, "deposit": deposit, "grid": grid, "tuning": tuning,
+           "deposit_path": dep_path}
     ctx.close()
     del em, ep, G, J, comps, lists, spare
     torch.cuda.empty_cache()
@@ -662,7 +666,9 @@ def run_cascade(args, torch, Q, W):
                            "leptons_per_s": lep_mean / (t_d / steps * 1e-3),
                            "roofline": {"bound": "hbm", "achieved": dgbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                         "frac": dgbs / HBM_PEAK_GBS, "bytes_per_lepton": BYTES_DEPOSIT},
-                           "note": "includes zeroing J and saving the start positions"} if r["deposit"] else None),
+                           "path": r["deposit_path"],
+                           "note": "includes zeroing J (the start positions are saved inside the QED step's interval)"}
+                          if r["deposit"] else None),
               "roofline": {"bound": "hbm", "achieved": fgbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": fgbs / HBM_PEAK_GBS, "bytes_per_node_step": BYTES_YEE_NODE}}
              if r["solver"] else {"solver": "none (static snapshot of the pulse)"})
@@ -922,6 +928,8 @@ def main():
                     help="cascade: reorder the particle lists by grid bin every N steps (0: never)")
     ap.add_argument("--cascade-mixed-only", action="store_true",
                     help="cascade: only the timed mixed-precision run (no FP64 runs, no error metrics)")
+    ap.add_argument("--deposit-path", choices=("local", "binned"), default="local",
+                    help="cascade: deposition path for the cell-ordered lists (binned: any order)")
     ap.add_argument("--no-deposit", action="store_true",
                     help="cascade: vacuum field solver, no current deposition")
     ap.add_argument("--static-grid", action="store_true",

@@ -356,6 +356,18 @@ qed_status qed_field_advance(qed_ctx_t *ctx, float *const grid[6], const float *
  * grids add each contribution with FP32 atomics (sums in an order that may change from
  * run to run).  Calls on one context must not overlap.                                   */
 #define QED_DEPOSIT_MAX_SRC 4
+#define QED_DEPOSIT_BINNED 0
+#define QED_DEPOSIT_LOCAL 1
+/* The tiled grids' path of later qed_deposit_current calls on this context.
+ * QED_DEPOSIT_BINNED (default): the binned path above, for particles in any order.
+ * QED_DEPOSIT_LOCAL: for lists kept in cell order (qed_sort_leptons every few steps): no
+ * binning; each block of 256 consecutive particles of a source adds its contributions to
+ * an LDS window over the box of its particles' start nodes (with the two-node halo) and
+ * then the window's sums to the 64-bit grid; a block whose box exceeds 1024 nodes adds its
+ * contributions to the 64-bit grid directly (slower, still exact).  The same fixed-point
+ * contributions as the binned path, so the same J bit for bit; it needs no per-particle
+ * work memory.  QED_EARG for another value; a host-side setting, no device work.          */
+qed_status qed_set_deposit_path(qed_ctx_t *ctx, int path);
 typedef struct {
     const qed_leptons *leptons;
     const double *x0[3];

@@ -27,7 +27,7 @@ EXPORTED = ["qed_init_tables", "qed_destroy", "qed_gather", "qed_push_spin", "qe
             "qed_clear_status", "qed_get_next_id", "qed_set_next_id", "qed_table_size", "qed_table_export",
             "qed_set_step_events", "qed_set_photon_events", "qed_set_step_counter", "qed_advance_step", "qed_get_tuning",
             "qed_set_tuning", "qed_autotune", "qed_mlp_init", "qed_mlp_set_params", "qed_mlp_get_params",
-            "qed_mlp_samples", "qed_mlp_forward", "qed_mlp_gradient", "qed_mlp_train_step", "qed_set_sampler", "qed_mlp_select",
+            "qed_mlp_samples", "qed_mlp_forward", "qed_mlp_gradient", "qed_mlp_train_step", "qed_set_sampler", "qed_mlp_select", "qed_set_deposit_path",
             "qed_sampler_table", "qed_hist_photons", "qed_hist_leptons", "qed_field_advance",
             "qed_deposit_current", "qed_save_start", "qed_brems_init", "qed_brems_tables", "qed_step_brems",
             "qed_last_error"]
@@ -37,6 +37,7 @@ BREMS_NE, BREMS_NU = 256, 128
 NOALLOC_MAX_LEPTONS = 524288
 SAMPLER_TABLE, SAMPLER_MLP, SAMPLER_MLP_NBW = 0, 1, 2
 NET_NCS, NET_NBW = 0, 1
+DEPOSIT_BINNED, DEPOSIT_LOCAL = 0, 1
 
 ALPHA = 1.0 / 137.035999084
 XI_L = 2.42631023867e-6
@@ -175,6 +176,7 @@ def lib():
             "qed_mlp_train_step": [vp, vp, vp, i64, vp, C.c_float, vp, vp],
             "qed_set_sampler": [vp, C.c_int],
             "qed_mlp_select": [vp, C.c_int],
+            "qed_set_deposit_path": [vp, C.c_int],
             "qed_sampler_table": [vp, vp, vp, i64, vp],
         }
         for name, args in sig.items():
@@ -419,6 +421,11 @@ class Context:
         self._check(lib().qed_save_start(self.h, C.byref(L.c()), x0, _ptr(out[3]), _stream(stream)),
                     "qed_save_start")
         return out
+
+    def set_deposit_path(self, path: int):
+        """DEPOSIT_BINNED (any order) or DEPOSIT_LOCAL (lists kept in cell order) for later
+        deposit_current calls (qed_set_deposit_path)."""
+        self._check(lib().qed_set_deposit_path(self.h, int(path)), "qed_set_deposit_path")
 
     def deposit_current(self, sources, grid: dict, current, qscale: float, stream=None):
         """Add the current of the leptons of each source (L, start) that moved from the saved

@@ -1056,6 +1056,14 @@ qed_status qed_set_sampler(qed_ctx_t *ctx, int sampler) {
     return QED_OK;
 }
 
+qed_status qed_set_deposit_path(qed_ctx_t *ctx, int path) {
+    if (!ctx) return QED_EARG;
+    if (path != QED_DEPOSIT_BINNED && path != QED_DEPOSIT_LOCAL)
+        return fail(ctx, QED_EARG, "qed_set_deposit_path: unknown path %d", path);
+    ctx->dep_path = path;
+    return QED_OK;
+}
+
 qed_status qed_mlp_select(qed_ctx_t *ctx, int net) {
     if (!ctx) return QED_EARG;
     if (net != QED_NET_NCS && net != QED_NET_NBW) return fail(ctx, QED_EARG, "qed_mlp_select: unknown network %d", net);

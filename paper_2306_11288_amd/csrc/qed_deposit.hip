@@ -18,7 +18,7 @@
 // a device-wide atomic serialises on the hot nodes.  The tiled path bins the particles by
 // the tile of T x T nodes that holds their start node and accumulates each tile in LDS:
 //   1. count   : particles per tile (LDS histogram per block over its share of the list,
-//                one global add per tile), largest |w| and |w dz|;
+//                one global add per tile), largest |w| and |w dz| (bound_terms);
 //   2. scan    : tile offsets, a work list of chunks of at most DEP_CH particles, and the
 //                fixed-point scale of each component (a power of two that maps the largest
 //                possible contribution to 2^32);
@@ -35,7 +35,9 @@
 // same J on every run; its only roundings are the fixed-point quantum (2^-32 of the largest
 // contribution) and one FP32 rounding per node.  T is 16 or 32, the smaller one with at
 // most DEP_MAX_TILES tiles; larger grids take the direct path (one thread per particle,
-// FP32 global atomics, order of the sums not fixed).
+// FP32 global atomics, order of the sums not fixed).  Lists kept in cell order can take
+// the local path instead (QED_DEPOSIT_LOCAL, below): no binning, a window per block of
+// consecutive particles, the same integer sums.
 #include "qed_internal.hpp"
 
 namespace qed {
@@ -90,7 +92,7 @@ __device__ __forceinline__ int64_t dep_count(const DepSource &d) {
 // charge); false for a particle that is not deposited (non-finite, absurdly far, or a move
 // of a cell or more)
 __device__ __forceinline__ bool classify(const DepositArgs &a, const DepSource &d, int64_t i, DepRec &r, int &ic,
-                                         int &lc) {
+                                         int &lc, int *raw = nullptr) {
     const double Xa = (d.x0[i] - a.gx0) * a.inv_dx, Ya = (d.y0[i] - a.gy0) * a.inv_dy;
     const double Xb = (d.x[i] - a.gx0) * a.inv_dx, Yb = (d.y[i] - a.gy0) * a.inv_dy;
     const double dz = d.z[i] - d.z0[i], w = d.charge * d.w[i];
@@ -107,10 +109,40 @@ __device__ __forceinline__ bool classify(const DepositArgs &a, const DepSource &
     r.w = w;
     r.wdz = w * dz;
     r.code = ((int)(jb - ja) + 1) << 16 | ((int)(kb - ka) + 1) << 18;
+    if (raw) {                        // the start node before wrapping (|ja|, |ka| < 2^30)
+        raw[0] = (int)ja;
+        raw[1] = (int)ka;
+    }
     const int ia = (int)(ja - a.nx * floor(ja / a.nx)), la = (int)(ka - a.ny * floor(ka / a.ny));
     ic = ia >= a.nx ? ia - a.nx : (ia < 0 ? ia + a.nx : ia);
     lc = la >= a.ny ? la - a.ny : (la < 0 ? la + a.ny : la);
     return true;
+}
+
+// the largest |w| and |w dz| that set the fixed-point scales, over every particle of the
+// call with a finite weight and z move (deposited or not: the maxima then need only w and
+// z, and both paths find the same ones); the same products as the records' w and wdz
+__device__ __forceinline__ void bound_terms(const DepSource &d, int64_t i, double &mw, double &mz) {
+    const double w = d.charge * d.w[i], wdz = w * (d.z[i] - d.z0[i]);
+    if (isfinite(w) && isfinite(wdz)) {
+        mw = fmax(mw, fabs(w));
+        mz = fmax(mz, fabs(wdz));
+    }
+}
+
+// the block's maxima of mw, mz (non-negative) into s_max[2] (zeroed before the block's
+// barrier that precedes this call; a barrier must follow): a wavefront reduction, then one
+// LDS atomic per wavefront (non-negative doubles order like their bit patterns)
+__device__ __forceinline__ void block_max2(double mw, double mz, unsigned long long *s_max) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        mw = fmax(mw, __shfl_xor(mw, d));
+        mz = fmax(mz, __shfl_xor(mz, d));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicMax(&s_max[0], (unsigned long long)__double_as_longlong(mw));
+        atomicMax(&s_max[1], (unsigned long long)__double_as_longlong(mz));
+    }
 }
 
 // TSC weights of nodes j-1, j, j+1 for offset d = X - j in [-1/2, 1/2], on a 4-slot window
@@ -200,11 +232,21 @@ __device__ __forceinline__ unsigned long long fixed64(double v, double scale) {
 }
 
 struct LdsSink {
-    unsigned long long *acc;   // [3][W * W], W = T + 4
-    int W, base;               // base: LDS index of window slot (0, 0)
+    unsigned long long *acc;   // [3][plane]: a window of rows of `stride` nodes
+    int stride, plane, base;   // base: LDS index of window slot (0, 0)
     double sc[3];              // fixed-point scale per component
     __device__ __forceinline__ void add(int c, int l, int m, double v) {
-        if (v != 0.0) atomicAdd(acc + c * W * W + base + l * W + m, fixed64(v, sc[c]));
+        if (v != 0.0) atomicAdd(acc + c * plane + base + l * stride + m, fixed64(v, sc[c]));
+    }
+};
+// fixed-point contributions straight to the 64-bit grid (global integer atomics)
+struct FixedSink {
+    unsigned long long *acc;   // [3][nodes]
+    int64_t nodes;
+    int col[5], row[5];
+    double sc[3];
+    __device__ __forceinline__ void add(int c, int l, int m, double v) {
+        if (v != 0.0) atomicAdd(acc + c * nodes + row[l] + col[m], fixed64(v, sc[c]));
     }
 };
 
@@ -248,17 +290,12 @@ __global__ __launch_bounds__(DBLOCK) void k_dep_count(DepositArgs a) {
         for (int64_t i = (int64_t)blockIdx.x * DBLOCK + threadIdx.x; i < n; i += stride) {
             DepRec r;
             int ic, lc;
-            if (classify(a, d, i, r, ic, lc)) {
-                atomicAdd(&h[tile_of(a, ic, lc)], 1);
-                mw = fmax(mw, fabs(r.w));
-                mz = fmax(mz, fabs(r.wdz));
-            } else {
-                atomicOr(a.status, (uint32_t)QED_ST_DEPOSIT);
-            }
+            bound_terms(d, i, mw, mz);
+            if (classify(a, d, i, r, ic, lc)) atomicAdd(&h[tile_of(a, ic, lc)], 1);
+            else atomicOr(a.status, (uint32_t)QED_ST_DEPOSIT);
         }
     }
-    atomicMax(&s_max[0], (unsigned long long)__double_as_longlong(mw));
-    atomicMax(&s_max[1], (unsigned long long)__double_as_longlong(mz));
+    block_max2(mw, mz, s_max);
     __syncthreads();
     for (int k = threadIdx.x; k < a.nt; k += DBLOCK)
         if (h[k]) atomicAdd(&a.cnt[k], h[k]);
@@ -271,6 +308,14 @@ __device__ __forceinline__ double fixed_scale(double bound) {
     int e;
     frexp(bound, &e);          // bound < 2^e
     return ldexp(1.0, 32 - e);
+}
+// the fixed-point scales of the three components from the largest |w| and |w dz|: running
+// sums of Jx, Jy are at most 2 |c w|, Jz at most |c w dz|
+__device__ __forceinline__ void fixed_scales(const DepositArgs &a, double sc[3]) {
+    const double mw = __longlong_as_double((long long)a.amax[0]), mz = __longlong_as_double((long long)a.amax[1]);
+    sc[0] = fixed_scale(2.0 * fabs(a.cx) * mw);
+    sc[1] = fixed_scale(2.0 * fabs(a.cy) * mw);
+    sc[2] = fixed_scale(fabs(a.cz) * mz);
 }
 
 // 2. tile offsets, chunk work list; clears the counts and the cursors for the next call
@@ -310,13 +355,11 @@ __global__ __launch_bounds__(SCAN_T) void k_dep_scan(DepositArgs a) {
     }
     if (threadIdx.x == SCAN_T - 1) *a.nwork = s_chk[SCAN_T - 1];
     if (threadIdx.x == 0) {
-        // bounds of one contribution: running sums of Jx, Jy at most 2 |c w|, Jz at most |c w dz|
-        const double mw = __longlong_as_double((long long)a.amax[0]), mz = __longlong_as_double((long long)a.amax[1]);
-        const double b[3] = {2.0 * fabs(a.cx) * mw, 2.0 * fabs(a.cy) * mw, fabs(a.cz) * mz};
+        double sc[3];
+        fixed_scales(a, sc);
         for (int c = 0; c < 3; ++c) {
-            const double sc = fixed_scale(b[c]);
-            a.scale[c] = sc;
-            a.scale[3 + c] = 1.0 / sc;
+            a.scale[c] = sc[c];
+            a.scale[3 + c] = 1.0 / sc[c];
         }
         a.amax[0] = 0;
         a.amax[1] = 0;
@@ -373,7 +416,7 @@ __global__ __launch_bounds__(TBLOCK) void k_dep_tiles(DepositArgs a) {
         __syncthreads();
         for (int k = wk.y + threadIdx.x; k < wk.z; k += TBLOCK) {
             const DepRec r = a.rec[k];
-            LdsSink s{acc, W, ((r.code >> 8) & 255) * W + (r.code & 255), {s0, s1, s2}};
+            LdsSink s{acc, W, WW, ((r.code >> 8) & 255) * W + (r.code & 255), {s0, s1, s2}};
             deposit_record(a, r, s);
         }
         __syncthreads();
@@ -391,10 +434,164 @@ __global__ __launch_bounds__(TBLOCK) void k_dep_tiles(DepositArgs a) {
     }
 }
 
+// Local path (lists kept in cell order, e.g. by qed_sort_leptons): the same fixed-point
+// contributions without binning.
+//   L1. amax  : the largest |w| and |w dz| (bound_terms, as the count kernel: w and z only);
+//   L2. local : a chunk of 256 consecutive particles of a source per block and turn; the
+//               chunk's start nodes span a box; if the box and its two-node halo fit LWIN
+//               nodes the block adds its records to that LDS window and then the window's
+//               non-zero sums to the 64-bit grid, otherwise each contribution goes to the
+//               64-bit grid;
+//   then the convert kernel.  Integer sums: the same J as the binned path, bit for bit.
+constexpr int LWIN = 1024;   // nodes of a block's LDS window (3 x 8 bytes each: 24 KB)
+constexpr int DEP_LOCAL_BPC = 6;   // blocks per compute unit of the local path (LDS: six fit)
+
+// Chunks of 256 particles of the sources' live counts, sources in order: live_chunks is
+// their number, chunk_at maps chunk g to its source and the chunk within that source.  The
+// kernels below sweep them persistently (a grid sized by the capacities would be mostly
+// empty blocks, and launching those costs more than the work).
+__device__ __forceinline__ int64_t live_chunks(const DepositArgs &a) {
+    int64_t t = 0;
+    for (int q = 0; q < a.nsrc; ++q) t += (dep_count(a.src[q]) + DBLOCK - 1) / DBLOCK;
+    return t;
+}
+__device__ __forceinline__ int chunk_at(const DepositArgs &a, int64_t g, int64_t &c) {
+    int q = 0;
+    for (; q < a.nsrc - 1; ++q) {
+        const int64_t nc = (dep_count(a.src[q]) + DBLOCK - 1) / DBLOCK;
+        if (g < nc) break;
+        g -= nc;
+    }
+    c = g;
+    return q;
+}
+
+__global__ __launch_bounds__(DBLOCK) void k_dep_amax(DepositArgs a) {
+    __shared__ unsigned long long s_max[2];
+    const int64_t nch = live_chunks(a);
+    if (threadIdx.x < 2) s_max[threadIdx.x] = 0;
+    __syncthreads();
+    double mw = 0.0, mz = 0.0;
+    for (int64_t g = blockIdx.x; g < nch; g += gridDim.x) {
+        int64_t c;
+        const DepSource &d = a.src[chunk_at(a, g, c)];
+        const int64_t i = c * DBLOCK + threadIdx.x;
+        if (i < dep_count(d)) bound_terms(d, i, mw, mz);
+    }
+    block_max2(mw, mz, s_max);
+    __syncthreads();
+    // only blocks above the running maximum add an atomic on its one address (the value
+    // read can only be below the final one, so none is missed)
+    if (threadIdx.x < 2) {
+        const unsigned long long v = s_max[threadIdx.x];
+        if (v > *(volatile unsigned long long *)&a.amax[threadIdx.x]) atomicMax(&a.amax[threadIdx.x], v);
+    }
+}
+
+__device__ __forceinline__ int wave_min(int v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v = min(v, __shfl_xor(v, d));
+    return v;
+}
+
+// one chunk of the local path (s_box: this chunk's LDS slots for the box reduction; the
+// caller alternates two sets, so no barrier is needed before they are written again)
+__device__ __forceinline__ void local_chunk(const DepositArgs &a, const DepSource &d, int64_t c, const double sc[3],
+                                            unsigned long long *win, int (*s_box)[DBLOCK / 64]) {
+    const int64_t n = dep_count(d);
+    const int64_t i = c * DBLOCK + threadIdx.x;
+    DepRec r;
+    int ic = 0, lc = 0, raw[2] = {0, 0};
+    const bool ok = i < n && classify(a, d, i, r, ic, lc, raw);
+    if (i < n && !ok) atomicOr(a.status, (uint32_t)QED_ST_DEPOSIT);
+    // box of the block's start nodes (min of j, k, -j, -k; INT_MAX where no particle)
+    constexpr int BIG = 0x7fffffff;
+    const int v[4] = {ok ? raw[0] : BIG, ok ? raw[1] : BIG, ok ? -raw[0] : BIG, ok ? -raw[1] : BIG};
+    const int wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int m = wave_min(v[k]);
+        if ((threadIdx.x & 63) == 0) s_box[k][wv] = m;
+    }
+    __syncthreads();
+    int b[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        b[k] = s_box[k][0];
+        for (int w = 1; w < DBLOCK / 64; ++w) b[k] = min(b[k], s_box[k][w]);
+    }
+    if (b[0] == BIG) return;                        // no particle of this chunk is deposited
+    const int j0 = b[0], k0 = b[1];
+    const int64_t bw = (int64_t)(-b[2]) - j0 + 5, bh = (int64_t)(-b[3]) - k0 + 5;
+    const int64_t nodes = (int64_t)a.nx * a.ny;
+    if (bw * bh > LWIN) {                           // spread out: straight to the 64-bit grid
+        if (!ok) return;
+        FixedSink s{a.acc, nodes, {}, {}, {sc[0], sc[1], sc[2]}};
+#pragma unroll
+        for (int m = 0; m < 5; ++m) {
+            s.col[m] = wrap(ic, m, a.nx);
+            s.row[m] = wrap(lc, m, a.ny) * a.nx;
+        }
+        deposit_record(a, r, s);
+        return;
+    }
+    const int W = (int)bw, plane = (int)(bw * bh);
+    for (int k = threadIdx.x; k < 3 * plane; k += DBLOCK) win[k] = 0;
+    __syncthreads();
+    if (ok) {
+        LdsSink s{win, W, plane, (raw[1] - k0) * W + (raw[0] - j0), {sc[0], sc[1], sc[2]}};
+        deposit_record(a, r, s);
+    }
+    __syncthreads();
+    // window slot (l, m) is node (j0 - 2 + m, k0 - 2 + l), wrapped into the grid; the slot
+    // of entry k is stepped along without divisions (k grows by DBLOCK = dl rows + dm)
+    int ox = (j0 - 2) % a.nx, oy = (k0 - 2) % a.ny;
+    ox = ox < 0 ? ox + a.nx : ox;
+    oy = oy < 0 ? oy + a.ny : oy;
+    const int dl = DBLOCK / W, dm = DBLOCK - dl * W;
+    int l = (int)threadIdx.x / W, m = (int)threadIdx.x - l * W;
+    for (int k = threadIdx.x; k < plane; k += DBLOCK) {
+        int gx = ox + m, gy = oy + l;
+        while (gx >= a.nx) gx -= a.nx;     // a window wider than the grid wraps more than once
+        while (gy >= a.ny) gy -= a.ny;
+        const int64_t g = (int64_t)gy * a.nx + gx;
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) {
+            const unsigned long long val = win[cc * plane + k];
+            if (val != 0) atomicAdd(a.acc + cc * nodes + g, val);
+        }
+        m += dm;
+        l += dl;
+        if (m >= W) {
+            m -= W;
+            ++l;
+        }
+    }
+}
+
+__global__ __launch_bounds__(DBLOCK) void k_dep_local(DepositArgs a) {
+    __shared__ unsigned long long win[3 * LWIN];
+    __shared__ int s_box[2][4][DBLOCK / 64];
+    double sc[3];
+    fixed_scales(a, sc);
+    if (blockIdx.x == 0 && threadIdx.x < 3) {       // the scales the convert kernel divides by
+        a.scale[threadIdx.x] = sc[threadIdx.x];
+        a.scale[3 + threadIdx.x] = 1.0 / sc[threadIdx.x];
+    }
+    const int64_t nch = live_chunks(a);
+    int par = 0;
+    for (int64_t g = blockIdx.x; g < nch; g += gridDim.x, par ^= 1) {
+        int64_t c;
+        const DepSource &d = a.src[chunk_at(a, g, c)];
+        local_chunk(a, d, c, sc, win, s_box[par]);
+    }
+}
+
 // 5. J += fixed-point grid / scale, which is cleared
 __global__ __launch_bounds__(DBLOCK) void k_dep_convert(DepositArgs a) {
     const int64_t nodes = (int64_t)a.nx * a.ny, stride = (int64_t)gridDim.x * DBLOCK;
     const double inv[3] = {a.scale[3], a.scale[4], a.scale[5]};
+    if (blockIdx.x == 0 && threadIdx.x < 2) a.amax[threadIdx.x] = 0;   // zero for the next call
     for (int64_t k = (int64_t)blockIdx.x * DBLOCK + threadIdx.x; k < 3 * nodes; k += stride) {
         const unsigned long long v = a.acc[k];
         if (v == 0) continue;
@@ -425,7 +622,7 @@ __global__ __launch_bounds__(DBLOCK) void k_save_start(const double *x, const do
 // 6 scale factors (double)
 constexpr size_t DEP_CNT_BYTES = 3 * (DEP_MAX_TILES + 1) * sizeof(int) + 8 * sizeof(double) + 8;
 
-hipError_t ensure_deposit(qed_ctx *ctx, int64_t capacity, int64_t nodes) {
+hipError_t ensure_deposit(qed_ctx *ctx, int64_t capacity, int64_t nodes, bool binned) {
     hipError_t e = hipSuccess;
     if (!ctx->dep_cnt) {
         e = hipMalloc(&ctx->dep_cnt, DEP_CNT_BYTES);
@@ -441,7 +638,7 @@ hipError_t ensure_deposit(qed_ctx *ctx, int64_t capacity, int64_t nodes) {
         if ((e = hipMemset(ctx->dep_acc, 0, 3 * nodes * sizeof(unsigned long long))) != hipSuccess) return e;
         ctx->dep_acc_len = 3 * nodes;
     }
-    if (capacity > ctx->dep_cap) {
+    if (binned && capacity > ctx->dep_cap) {   // records and work list: the binned path only
         (void)hipFree(ctx->dep_rec);
         (void)hipFree(ctx->dep_work);
         ctx->dep_rec = nullptr;
@@ -518,7 +715,8 @@ hipError_t launch_deposit(qed_ctx *ctx, const qed_deposit_src *src, int nsrc, fl
         return hipGetLastError();
     }
     const int64_t nodes = (int64_t)nx * ny;
-    const hipError_t e = ensure_deposit(ctx, total, nodes);
+    const bool local = ctx->dep_path == QED_DEPOSIT_LOCAL;
+    const hipError_t e = ensure_deposit(ctx, total, nodes, !local);
     if (e != hipSuccess) return e;
     a.cnt = ctx->dep_cnt;
     a.off = ctx->dep_cnt + (DEP_MAX_TILES + 1);
@@ -536,10 +734,20 @@ hipError_t launch_deposit(qed_ctx *ctx, const qed_deposit_src *src, int nsrc, fl
     const unsigned pblocks = (unsigned)(pb < persist ? pb : persist);
     const unsigned wblocks = (unsigned)(wb < persist ? wb : persist);
     const size_t lds = 3 * (size_t)(a.T + 4) * (a.T + 4) * sizeof(unsigned long long);
-    hipLaunchKernelGGL(k_dep_count, dim3(pblocks), dim3(DBLOCK), 0, s, a);
-    hipLaunchKernelGGL(k_dep_scan, dim3(1), dim3(SCAN_T), 0, s, a);
-    hipLaunchKernelGGL(k_dep_scatter, dim3(pblocks), dim3(DBLOCK), 0, s, a);
-    hipLaunchKernelGGL(k_dep_tiles, dim3(wblocks), dim3(TBLOCK), lds, s, a);
+    if (local) {
+        int64_t chunks = 0;
+        for (int q = 0; q < nsrc; ++q) chunks += (a.src[q].capacity + DBLOCK - 1) / DBLOCK;
+        // persistent over the live chunks (their number is on the device)
+        const int64_t cap = (int64_t)DEP_LOCAL_BPC * ctx->num_cu;
+        const unsigned lb = (unsigned)(chunks < cap ? (chunks < 1 ? 1 : chunks) : cap);
+        hipLaunchKernelGGL(k_dep_amax, dim3(lb), dim3(DBLOCK), 0, s, a);
+        hipLaunchKernelGGL(k_dep_local, dim3(lb), dim3(DBLOCK), 0, s, a);
+    } else {
+        hipLaunchKernelGGL(k_dep_count, dim3(pblocks), dim3(DBLOCK), 0, s, a);
+        hipLaunchKernelGGL(k_dep_scan, dim3(1), dim3(SCAN_T), 0, s, a);
+        hipLaunchKernelGGL(k_dep_scatter, dim3(pblocks), dim3(DBLOCK), 0, s, a);
+        hipLaunchKernelGGL(k_dep_tiles, dim3(wblocks), dim3(TBLOCK), lds, s, a);
+    }
     int64_t cb = (3 * nodes + DBLOCK - 1) / DBLOCK;
     cb = cb > 8LL * ctx->num_cu ? 8LL * ctx->num_cu : cb;
     hipLaunchKernelGGL(k_dep_convert, dim3((unsigned)cb), dim3(DBLOCK), 0, s, a);

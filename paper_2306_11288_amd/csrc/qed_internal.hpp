@@ -242,6 +242,7 @@ struct qed_ctx {
     float *ev_in, *ev_out;             // learned sampler: per-event network inputs [ev_cap][4], outputs [ev_cap][3]
     double *hist_rep;                  // detector histogram replicas
     int64_t hist_rep_len;
+    int dep_path;                      // QED_DEPOSIT_BINNED or QED_DEPOSIT_LOCAL (qed_set_deposit_path)
     int *dep_cnt;                      // current deposition: tile counts, offsets, cursors (zero between calls)
     void *dep_work;                    // chunk work list
     void *dep_rec;                     // particle records sorted by tile

@@ -212,6 +212,82 @@ def test_cascade_size_moments_and_continuity():
     assert np.abs(res).max() < 2e-4 * drho * 40     # FP32 sums over ~1e3 contributions per node
 
 
+def _both_paths(srcs, grid, qs, dt):
+    """J from the binned and from the local path (fresh contexts), and the status words."""
+    out = []
+    for path in (Q.DEPOSIT_BINNED, Q.DEPOSIT_LOCAL):
+        ctx = Q.Context(dt=dt, procs=Q.PROC_NCS, seed=1, id_start=0, precision=Q.QED_MIXED)
+        ctx.set_deposit_path(path)
+        J = _zeros(grid["ny"], grid["nx"])
+        ctx.deposit_current(srcs, grid, J, qs)
+        ctx.deposit_current(srcs, grid, J, qs)         # a second call adds the same again
+        out.append((J, ctx.read_status()))
+    return out
+
+
+@pytest.mark.parametrize("order", ["sorted", "random"])
+def test_local_path_equals_binned_at_cascade_size(order):
+    """The cascade's 1e6 electrons pushed one step on the 2048 x 512 grid: sorted by 4 x 4-cell
+    bin (blocks of 256 consecutive electrons fit their LDS windows) or in random order (every
+    block too spread out: contributions straight to the 64-bit grid).  Either way the local
+    path adds the binned path's integer sums, so J is the same bit for bit."""
+    cfg = W.c3()
+    grid, pulse = cfg["grid"], dict(cfg["pulse"])
+    pulse["phi_start"] = -pulse["ncycles"] * math.pi
+    comps = [torch.as_tensor(c).cuda() for c in W.grid_fill(grid, pulse, 0.0)]
+    spec = dict(kind=Q.FIELD_GRID2D, grid=comps, **grid)
+    st = dict(cfg["leptons"])
+    st["x"] = st["x"] - st["x"].mean()
+    n = len(st["x"])
+    _say(f"local vs binned, {order}, n={n}")
+    if order == "random":
+        perm = np.random.default_rng(3).permutation(n)
+        st = {k: v[perm] for k, v in st.items()}
+    ctx = Q.Context(dt=cfg["dt"], procs=Q.PROC_NCS, seed=1, id_start=0, precision=Q.QED_MIXED)
+    L = Q.Leptons.from_state(st, charge=-1, precision=Q.QED_MIXED)
+    if order == "sorted":
+        Ls = Q.Leptons(n, -1, precision=Q.QED_MIXED)
+        ctx.sort_leptons(L, Ls, spec)
+        L = Ls
+    start = ctx.save_start(L)
+    ctx.push_spin(Q.whole(spec), L, 100)
+    (Jb, sb), (Jl, sl) = _both_paths([(L, start)], grid, 1e-4, cfg["dt"])
+    assert sb == sl == 0
+    for c in range(3):
+        assert float(Jb[c].abs().max()) > 0
+        assert torch.equal(Jb[c], Jl[c]), c
+
+
+@pytest.mark.parametrize("nx,ny,gx0,gy0", [(37, 20, -5.1, 2.3), (5, 3, 0.4, -0.2), (256, 64, 0.0, 0.0)])
+def test_local_path_equals_binned_small(nx, ny, gx0, gy0):
+    """Two sources of different charge, particles across the periodic seams and outside the
+    box, a few moves of more than a cell (skipped and flagged by both), appended particles
+    left out; clusters sorted by cell beside scattered ones: the same J bit for bit."""
+    _say(f"local vs binned {nx}x{ny}")
+    dx, dy, dt, qs = 0.19, 0.23, 0.05, 0.7
+    srcs = []
+    for charge, seed, n, n0 in ((-1, 31, 5000, 4600), (1, 32, 3000, 3000)):
+        xa, ya, za, xb, yb, zb, w = _random_moves(n, nx, ny, dx, dy, gx0, gy0, seed=seed)
+        k = n // 2                                         # first half: a cluster, sorted by cell
+        rng = np.random.default_rng(seed + 100)
+        xa[:k] = gx0 + (nx * 0.5 + rng.normal(0, 2.0, k)) * dx
+        ya[:k] = gy0 + (ny * 0.5 + rng.normal(0, 2.0, k)) * dy
+        o = np.lexsort((np.floor((xa[:k] - gx0) / dx), np.floor((ya[:k] - gy0) / dy)))
+        xa[:k], ya[:k] = xa[:k][o], ya[:k][o]
+        xb[:k] = xa[:k] + rng.uniform(-0.9, 0.9, k) * dx
+        yb[:k] = ya[:k] + rng.uniform(-0.9, 0.9, k) * dy
+        xb[k + 7] = xa[k + 7] + 1.5 * dx                    # skipped: a move of more than a cell
+        L = _leptons(xb, yb, zb, w, charge)
+        srcs.append((L, (_dev(xa), _dev(ya), _dev(za), torch.tensor([n0], dtype=torch.int64, device="cuda"))))
+    grid = {"nx": nx, "ny": ny, "dx": dx, "dy": dy, "gx0": gx0, "gy0": gy0}
+    (Jb, sb), (Jl, sl) = _both_paths(srcs, grid, qs, dt)
+    assert sb == sl == Q.ST_DEPOSIT
+    for c in range(3):
+        assert torch.equal(Jb[c], Jl[c]), c
+    with pytest.raises(Q.QedError):
+        Q.Context(dt=dt, procs=Q.PROC_NCS, seed=1, id_start=0, precision=Q.QED_MIXED).set_deposit_path(2)
+
+
 def test_solver_current_term_matches_oracle():
     _say("solver with J")
     rng = np.random.default_rng(3)
