@@ -416,10 +416,10 @@ __global__ __launch_bounds__(BLOCK) void k_leptons_radiative(LeptonArgs a, uint3
 // event count goes to tile_counts and is added to its group's total (integer atomics: the
 // sum does not depend on their order; the scan clears the totals it reads).  RATE_LDS: the
 // NCS rate table is staged in LDS once per block instead of being read through the caches.
-// The FP64 instances are held to six wavefronts per SIMD (79 VGPRs, a few spilled; five
-// wavefronts at 93 otherwise): measured 2 % faster.
+// The FP64 instances are held to at least five wavefronts per SIMD (83-94 VGPRs, no
+// spills): forcing six (79 VGPRs with spills) measured 4 % slower, seven 25 % slower.
 template <class T, bool PUSH, int FK, bool RATE_LDS>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 6 : 1))) void k_leptons_decide(LeptonArgs a) {
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 5 : 1))) void k_leptons_decide(LeptonArgs a) {
     __shared__ int s_wave[2][BLOCK / 64];
     __shared__ T s_rate[RATE_LDS ? 2 * NR : 1];
     // 32-bit indices: lists hold at most 2^28 particles
