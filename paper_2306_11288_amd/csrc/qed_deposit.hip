@@ -223,12 +223,14 @@ struct GlobalSink {
     }
 };
 
-// v scaled to a 64-bit fixed-point integer (|v| scale <= 2^33), rounded to nearest
+// v scaled to a 64-bit fixed-point integer (|v| scale <= 2^33), rounded to nearest even.
+// The scale is a power of two, so v scale is exact and one fused add of 1.5 2^52 rounds it
+// to an integer held in the low mantissa bits (the sum has exponent 52 for |v scale| < 2^51);
+// subtracting the constant's bit pattern leaves it as a two's-complement 64-bit integer.
 __device__ __forceinline__ unsigned long long fixed64(double v, double scale) {
-    const double x = rint(v * scale);
-    const double hi = floor(x * 2.3283064365386963e-10);            // x / 2^32
-    const unsigned lo = (unsigned)(x - hi * 4294967296.0);          // in [0, 2^32)
-    return ((unsigned long long)(unsigned)(int)hi << 32) | lo;
+    constexpr double MAGIC = 6755399441055744.0;                     // 1.5 * 2^52
+    return (unsigned long long)__double_as_longlong(fma(v, scale, MAGIC)) -
+           (unsigned long long)__double_as_longlong(MAGIC);
 }
 
 struct LdsSink {
