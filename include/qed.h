@@ -178,8 +178,8 @@ qed_status qed_push_spin(qed_ctx_t *ctx, const qed_segment *segs, int nseg, qed_
  * with the event staging and scan work memory in a fixed device array of the library
  * (about 76 MB on every GPU the library runs on, held until the process ends) instead of
  * context-owned buffers.  Nothing is allocated or freed.  Limits: exactly one segment,
- * p->capacity <= QED_NOALLOC_MAX_LEPTONS (QED_EARG otherwise), the table sampler
- * (QED_ESTATE with the learned sampler), the context's device current.  All calls on one
+ * p->capacity <= QED_NOALLOC_MAX_LEPTONS (QED_EARG otherwise), the table sampler for NCS
+ * (QED_ESTATE with the QED_SAMPLER_MLP bit set), the context's device current.  All calls on one
  * GPU share that array: calls that overlap on one GPU (other streams, other contexts,
  * other host threads) race and must not be made.                                       */
 #define QED_NOALLOC_MAX_LEPTONS 524288

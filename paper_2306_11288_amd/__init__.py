@@ -650,6 +650,8 @@ class Context:
         self.mlp_set_params(p.astype(np.float32))
 
     def set_sampler(self, sampler: int):
+        """SAMPLER_TABLE, or the bits SAMPLER_MLP (NCS emissions) and SAMPLER_MLP_NBW (pair
+        creations) for the learned samplers (qed_set_sampler)."""
         self._check(lib().qed_set_sampler(self.h, int(sampler)), "qed_set_sampler")
 
     def set_step_events(self, events=None):
