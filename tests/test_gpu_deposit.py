@@ -212,12 +212,15 @@ def test_cascade_size_moments_and_continuity():
     assert np.abs(res).max() < 2e-4 * drho * 40     # FP32 sums over ~1e3 contributions per node
 
 
-def _both_paths(srcs, grid, qs, dt):
-    """J from the binned and from the local path (fresh contexts), and the status words."""
+def _both_paths(srcs, grid, qs, dt, first=None):
+    """J from the binned and from the local path (fresh contexts), and the status words;
+    `first`: sources of an earlier call on the same context (its J is discarded)."""
     out = []
     for path in (Q.DEPOSIT_BINNED, Q.DEPOSIT_LOCAL):
         ctx = Q.Context(dt=dt, procs=Q.PROC_NCS, seed=1, id_start=0, precision=Q.QED_MIXED)
         ctx.set_deposit_path(path)
+        if first is not None:
+            ctx.deposit_current(first, grid, _zeros(grid["ny"], grid["nx"]), qs)
         J = _zeros(grid["ny"], grid["nx"])
         ctx.deposit_current(srcs, grid, J, qs)
         ctx.deposit_current(srcs, grid, J, qs)         # a second call adds the same again
@@ -284,6 +287,19 @@ def test_local_path_equals_binned_small(nx, ny, gx0, gy0):
     assert sb == sl == Q.ST_DEPOSIT
     for c in range(3):
         assert torch.equal(Jb[c], Jl[c]), c
+    # after a call with 8x the weights (a coarser fixed-point scale) each call sets its own
+    # scale: the same bits as the binned path again
+    heavy = []
+    for L, start in srcs:
+        H = Q.Leptons(L.capacity, L.charge, precision=Q.QED_MIXED)
+        for k in ("x", "y", "z", "px", "py", "pz", "w", "sx", "sy", "sz", "id"):
+            getattr(H, k).copy_(getattr(L, k))
+        H.w.mul_(8.0)
+        H.count_t.copy_(L.count_t)
+        heavy.append((H, start))
+    (Jb2, _), (Jl2, _) = _both_paths(srcs, grid, qs, dt, first=heavy)
+    for c in range(3):
+        assert torch.equal(Jb2[c], Jl2[c]) and torch.equal(Jb2[c], Jb[c]), c
     with pytest.raises(Q.QedError):
         Q.Context(dt=dt, procs=Q.PROC_NCS, seed=1, id_start=0, precision=Q.QED_MIXED).set_deposit_path(2)
 
