@@ -122,13 +122,35 @@ qed_status seg_args(qed_ctx *ctx, const qed_segment *segs, int nseg, SegArgs &sa
     sa.segs = nullptr;
     if (nseg == 1) return QED_OK;
     // several segments: upload unless identical to the list already on the device.  Layout:
-    // the DevSegment array, the segment starts again as a compact int64 array, and for
-    // every 256-particle tile up to the last segment's end the segment that holds the
-    // tile's first index (or the last one starting before it): the kernels read one table
-    // entry per wavefront instead of searching
+    // the DevSegment array, the segment starts again as a compact int64 array, for every
+    // 256-particle tile up to the last segment's end the segment that holds the tile's first
+    // index (or the last one starting before it) with the flags SEG_NONE (no index of the tile
+    // in a segment) and SEG_MIXED (the tile's indices not all in that segment): the kernels
+    // read one table entry per wavefront instead of searching, and only a SEG_MIXED tile
+    // needs the per-lane test and the waterfall over segments
     const size_t seg_bytes = sizeof(DevSegment) * (size_t)nseg;
     const size_t head = seg_bytes + sizeof(int64_t) * (size_t)nseg;
     const int64_t ntile = (segs[nseg - 1].end + BLOCK - 1) / BLOCK;
+    // the tile table with its flags (derived from the head)
+    std::vector<int32_t> tab((size_t)ntile);
+    {
+        int k = 0;
+        for (int64_t t = 0; t < ntile; ++t) {
+            const int64_t lo = t * BLOCK, hi = lo + BLOCK;
+            while (k + 1 < nseg && segs[k + 1].begin <= lo) ++k;
+            int32_t e = k;
+            if (segs[k].begin <= lo && hi <= segs[k].end) {
+                // every index in segment k
+            } else if (lo >= segs[k].end && (k + 1 >= nseg || hi <= segs[k + 1].begin)) {
+                e |= SEG_NONE;                        // every index in the gap after segment k
+            } else if (lo < segs[0].begin && hi <= segs[0].begin) {
+                e |= SEG_NONE;                        // every index before the first segment
+            } else {
+                e |= SEG_MIXED;
+            }
+            tab[(size_t)t] = e;
+        }
+    }
     const size_t bytes = head + sizeof(int32_t) * (size_t)ntile;
     std::vector<char> dev(head, 0);   // zeroed padding too, for the comparison below
     for (int k = 0; k < nseg; ++k) {
@@ -161,12 +183,7 @@ qed_status seg_args(qed_ctx *ctx, const qed_segment *segs, int nseg, SegArgs &sa
         }
         if (e == hipSuccess) {
             std::memcpy(ctx->hsegs, dev.data(), head);
-            int32_t *tab = (int32_t *)((char *)ctx->hsegs + head);
-            int k = 0;
-            for (int64_t t = 0; t < ntile; ++t) {
-                while (k + 1 < nseg && segs[k + 1].begin <= t * BLOCK) ++k;
-                tab[t] = k;
-            }
+            std::memcpy((char *)ctx->hsegs + head, tab.data(), sizeof(int32_t) * (size_t)ntile);
             e = hipMemcpyAsync(ctx->dsegs, ctx->hsegs, bytes, hipMemcpyHostToDevice, stream);
         }
         if (e == hipSuccess) e = hipEventRecord(ctx->seg_copied, stream);

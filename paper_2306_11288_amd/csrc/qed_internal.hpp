@@ -142,9 +142,13 @@ struct SegArgs {
     FieldDev f0;
     const DevSegment *segs;    // device copy when nseg > 1
     const int64_t *seg_begin;  // the segments' starts, compact (same allocation)
-    const int32_t *tile_seg;   // per 256-particle tile: segment of its first index (or the last before it)
+    const int32_t *tile_seg;   // per 256-particle tile: segment of its first index (or the last
+                               // before it) in the low bits, SEG_NONE / SEG_MIXED flags above
     int64_t ntile_seg;
 };
+// tile table entries: the segment index, and whether the tile's indices all lie in no
+// segment (SEG_NONE) or not all in that one segment (SEG_MIXED: across a boundary or a gap)
+constexpr int32_t SEG_INDEX = 0xffff, SEG_NONE = 1 << 29, SEG_MIXED = 1 << 30;
 FieldDev field_dev(const qed_field &f);   // host: derived constants of a field
 
 // learned sampler: 4-128-128-128-3 perceptron, flat FP32 parameters W1 b1 W2 b2 W3 b3 W4 b4

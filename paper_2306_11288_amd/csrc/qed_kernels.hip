@@ -18,8 +18,48 @@
 namespace qed {
 
 // ------------------------------------------------------------------------- segments
+// Lanes of a wavefront over several segments: a waterfall from segment lo (the segment of
+// the wavefront's first tile index, or the last one before it): the lanes inside the
+// current segment evaluate its field (the descriptor comes through scalar loads and its
+// kind is uniform); if lanes remain, the first of them picks the next segment by a search on
+// wavefront-uniform values.  KIND < 0: the kind is read from each segment.
+template <class FT, int KIND>
+__device__ __forceinline__ void fields_waterfall(const SegArgs &sa, int64_t i, double t, const V3<double> &r,
+                                                 int lo, V3<double> &E, V3<double> &B) {
+    bool done = false;
+    for (;;) {
+        const DevSegment &sg = sa.segs[lo];
+        if (!done && i >= sg.begin && i < sg.end) {
+            if constexpr (KIND < 0) field_at<FT>(sg.f, t, r.x, r.y, r.z, E, B);
+            else field_kind<FT, KIND>(sg.f, t, r.x, r.y, r.z, E, B);
+            done = true;
+        }
+        const unsigned long long pending = __ballot(!done);
+        if (pending == 0) break;
+        const int leader = __ffsll((long long)pending) - 1;
+        const int il = __builtin_amdgcn_readlane((int)i, leader);
+        int a = 0, b = sa.nseg - 1;   // last segment with begin <= il
+        while (a < b) {
+            const int mid = (a + b + 1) >> 1;
+            if (sa.seg_begin[mid] <= il) a = mid;
+            else b = mid - 1;
+        }
+        if (a == lo) {                // the leader lies outside every segment: no field
+            if ((int)i == il) done = true;
+            if (__ballot(!done) == 0) break;
+            continue;
+        }
+        lo = a;
+    }
+}
+
 // FK: the kind of the single segment (fields read at constant offsets of the kernel
-// arguments) or FK_MULTI (segment found per particle, kind read from it).
+// arguments), FK_MULTI (several segments, kind read from each) or FK_MULTI_BASE + kind
+// (several segments of that one kind).  Segments are index ranges and a wavefront holds
+// consecutive indices, so it almost always lies in one segment: with several segments the
+// tile's table entry (read after the particle loads are on their way) tells; for
+// FK_MULTI_BASE + kind a tile inside one segment or one gap takes straight-line code with no
+// per-lane test, only a SEG_MIXED tile (across a boundary or a gap edge) the waterfall.
 template <class FT, int FK>
 __device__ __forceinline__ void fields_for(const SegArgs &sa, int64_t i, double t, const V3<double> &r,
                                            V3<double> &E, V3<double> &B) {
@@ -28,38 +68,14 @@ __device__ __forceinline__ void fields_for(const SegArgs &sa, int64_t i, double 
     if constexpr (FK != FK_MULTI && FK < FK_MULTI_BASE) {
         if (i >= sa.begin0 && i < sa.end0) field_kind<FT, FK>(sa.f0, t, r.x, r.y, r.z, E, B);
     } else {
-        // Segments are index ranges and a wavefront holds consecutive indices, so it almost
-        // always lies in one segment.  Waterfall over the segments present, starting from the
-        // segment of the first active lane's tile (one table entry): the lanes inside the
-        // current segment evaluate the field (its descriptor comes through scalar loads and
-        // its kind is uniform); if lanes remain, the first of them picks the next segment by
-        // a search on wavefront-uniform values.  One pass in the usual case.
-        const int i0 = __builtin_amdgcn_readfirstlane((int)i), t0 = i0 / BLOCK;
-        int lo = t0 < sa.ntile_seg ? sa.tile_seg[t0] : sa.nseg - 1;
-        bool done = false;
-        for (;;) {
-            const DevSegment &sg = sa.segs[lo];
-            if (!done && i >= sg.begin && i < sg.end) {
-                if constexpr (FK == FK_MULTI) field_at<FT>(sg.f, t, r.x, r.y, r.z, E, B);
-                else field_kind<FT, FK - FK_MULTI_BASE>(sg.f, t, r.x, r.y, r.z, E, B);
-                done = true;
-            }
-            const unsigned long long pending = __ballot(!done);
-            if (pending == 0) break;
-            const int leader = __ffsll((long long)pending) - 1;
-            const int il = __builtin_amdgcn_readlane((int)i, leader);
-            int a = 0, b = sa.nseg - 1;   // last segment with begin <= il
-            while (a < b) {
-                const int mid = (a + b + 1) >> 1;
-                if (sa.seg_begin[mid] <= il) a = mid;
-                else b = mid - 1;
-            }
-            if (a == lo) {                // the leader lies outside every segment: no field
-                if ((int)i == il) done = true;
-                if (__ballot(!done) == 0) break;
-                continue;
-            }
-            lo = a;
+        const int t0 = __builtin_amdgcn_readfirstlane((int)i) / BLOCK;
+        const int32_t seg = t0 < sa.ntile_seg ? sa.tile_seg[t0] : (sa.nseg - 1) | SEG_MIXED;
+        if constexpr (FK == FK_MULTI) {
+            fields_waterfall<FT, -1>(sa, i, t, r, seg & SEG_INDEX, E, B);
+        } else if (seg & SEG_MIXED) {
+            fields_waterfall<FT, FK - FK_MULTI_BASE>(sa, i, t, r, seg & SEG_INDEX, E, B);
+        } else if (!(seg & SEG_NONE)) {
+            field_kind<FT, FK - FK_MULTI_BASE>(sa.segs[seg & SEG_INDEX].f, t, r.x, r.y, r.z, E, B);
         }
     }
 }

@@ -130,17 +130,26 @@ def test_batched_sample_vs_oracle_fp64():
         assert np.max(np.abs(Gb[k] - go[k])) < 1e-10, k
 
 
-def test_mixed_kinds_and_gaps_vs_oracle_fp64():
-    """Segments of different field kinds (plane waves, Gaussian beams, a constant field)
-    with gaps between them, boundaries inside wavefronts: the generic many-kind kernel and
-    the waterfall over segments; particles in a gap see no field.  Against the oracle,
-    which steps the segments and the gaps as separate lists in index order."""
-    _say("mixed kinds and gaps vs oracle")
-    cfg = _cfg(n_collisions=6, n_min=150, n_max=500)
+@pytest.mark.parametrize("kinds", ["mixed", "common"])
+def test_mixed_kinds_and_gaps_vs_oracle_fp64(kinds):
+    """Segments with gaps between them, boundaries inside wavefronts; particles in a gap see
+    no field.  mixed: segments of different field kinds (plane waves, Gaussian beams, a
+    constant field), the generic many-kind kernel and the waterfall over segments.  common:
+    plane waves only, the kernel specialised on their kind, whose tiles inside one segment or
+    one gap take the straight-line path and whose tiles across a boundary or a gap edge take
+    a launch of their own; the first collision and the third are whole gaps (tiles with no
+    segment at all).  Against the oracle, which steps the segments and the gaps as separate
+    lists in index order."""
+    _say(f"{kinds} kinds and gaps vs oracle")
+    cfg = _cfg(n_collisions=6, n_min=150, n_max=500) if kinds == "mixed" else \
+        _cfg(n_collisions=6, n_min=600, n_max=900)
     segs, pieces, prev = [], [], 0
     for k, (b, e, spec) in enumerate(cfg["segments"]):
         spec = dict(spec)
-        if k % 3 == 1:
+        if kinds == "common":
+            if k in (0, 2):
+                continue                                       # a whole collision as a gap
+        elif k % 3 == 1:
             spec.update(kind=W.FIELD_GAUSS, w0=12.0, x_focus=0.0, phi_start=0.0)
         elif k % 3 == 2 and k == 2:
             spec = {"kind": W.FIELD_CONST, "e0": (0.0, 30.0, 0.0), "b0": (0.0, 0.0, -30.0)}
