@@ -84,19 +84,19 @@ def _const_params(c0):
     return p
 
 
-def _pair_run(sampler, params, steps=40, n=40000, s0=2000):
+def _pair_run(sampler, params, steps=40, n=40000, s0=2000, precision=Q.QED_FP64):
     """The photon VB + NBW step of the plane-wave case (a0 = 300, 1.5 GeV photons) near the
-    pulse's peak, FP64; per step the photons that converted (index order) and the pairs
+    pulse's peak; per step the photons that converted (index order) and the pairs
     appended."""
     st = W.photons(n, seed=44, eps0=3000.0, eps_rel_spread=0.2, divergence=2e-3, x_mean=-2.0, x_sigma=1.0,
                    r_sigma=1.0, id0=0)
     spec = {"kind": W.FIELD_PW, "circular": 0, "a0": 300.0, "ncycles": 8.0, "phase0": 0.3, "pol_angle": 0.4,
             "phi_start": 0.0}
-    c = _nbw_ctx(Q.QED_FP64, dt=W.TWO_PI / 500, procs=Q.PROC_VB | Q.PROC_NBW, seed=9, id_start=1 << 41)
+    c = _nbw_ctx(precision, dt=W.TWO_PI / 500, procs=Q.PROC_VB | Q.PROC_NBW, seed=9, id_start=1 << 41)
     c.mlp_set_params(params)
     c.set_sampler(sampler)
-    G = Q.Photons.from_state(st)
-    em, ep = Q.Leptons(n, -1), Q.Leptons(n, 1)
+    G = Q.Photons.from_state(st, precision=precision)
+    em, ep = Q.Leptons(n, -1, precision=precision), Q.Leptons(n, 1, precision=precision)
     k = np.sqrt(st["kx"] ** 2 + st["ky"] ** 2 + st["kz"] ** 2)   # photon energies never change
     alive = np.ones(n, dtype=bool)
     parents = []
@@ -175,15 +175,16 @@ def test_shipped_network_against_table_sampler(shipped):
     assert table_bytes > 15 * net_bytes
 
 
-def test_shipped_network_in_the_pair_step(shipped):
+@pytest.mark.parametrize("precision", [Q.QED_FP64, Q.QED_MIXED], ids=["fp64", "mixed"])
+def test_shipped_network_in_the_pair_step(shipped, precision):
     """The pair step with the shipped network against the table, pair by pair on the same
     draws: the same photons convert (the decision does not depend on delta), ids and birth
     places are equal, each pair's delta is within the network's error of the table's
     (bitwise the table's where the network's delta falls outside [0.05, 0.95]), and the
     positron spectra agree."""
-    _say("shipped network in the step")
-    ref = _pair_run(Q.SAMPLER_TABLE, shipped)
-    run = _pair_run(Q.SAMPLER_MLP_NBW, shipped)
+    _say(f"shipped network in the step ({precision})")
+    ref = _pair_run(Q.SAMPLER_TABLE, shipped, precision=precision)
+    run = _pair_run(Q.SAMPLER_MLP_NBW, shipped, precision=precision)
     _, par, k, em0, ep0, _ = ref
     c, par_r, _, em, ep, _ = run
     assert np.array_equal(par_r, par) and np.array_equal(ep["id"], ep0["id"]) and c.read_status() == 0
