@@ -87,8 +87,8 @@ def test_chain_order_matches_oracle(prec):
 
 
 def test_compaction_replaces_a_non_empty_destination():
-    """ADVICE: compaction into a list that already holds photons must replace it (count =
-    live photons, contents from index 0), as the oracle's compaction does."""
+    """Compaction into a list that already holds photons replaces it (count = live
+    photons, contents from index 0), as the oracle's compaction does."""
     _say("compaction into a non-empty list")
     st = W.photons(3000, seed=44, eps0=3000.0, eps_rel_spread=0.2, divergence=2e-3, x_mean=-2.0, x_sigma=1.0,
                    r_sigma=1.0, id0=0)
