@@ -59,7 +59,7 @@ def measured_traffic(prec: str):
     return d.get(prec, {}).get("bytes_per_launch")
 
 
-def run_gpu(prec, cfg, steps, warmup, torch, Q, per_launch_events=True, learned=False):
+def run_gpu(prec, cfg, steps, warmup, torch, Q, per_launch_events=True, learned=False, photon_cap=None):
     precision = Q.QED_MIXED if prec == "mixed" else Q.QED_FP64
     n = len(cfg["leptons"]["x"])
     ctx = Q.Context(dt=cfg["dt"], procs=cfg["procs"], seed=cfg["seed"], id_start=cfg["next_id"],
@@ -68,7 +68,7 @@ def run_gpu(prec, cfg, steps, warmup, torch, Q, per_launch_events=True, learned=
         ctx.mlp_load_pretrained()
         ctx.set_sampler(Q.SAMPLER_MLP)
     L = Q.Leptons.from_state(cfg["leptons"], precision=precision)
-    cap = int(n * 0.03 * (steps + warmup)) + 1_000_000
+    cap = photon_cap or int(n * 0.03 * (steps + warmup)) + 1_000_000
     G = Q.Photons(cap, precision=precision)
     segs = Q.whole(cfg["field"])
     s0 = cfg["start_step"]
@@ -451,6 +451,33 @@ def run_learned_nbw(torch, Q, W, best_ms) -> dict:
                         "same_decisions": same_pairs, "error_vs_table": step_err,
                         "status_bits": [res["table"]["status_bits"], res["network"]["status_bits"]],
                         "what": "photon VB + NBW step, plane wave a0 = 300 near its peak, mixed precision"}
+    return out
+
+
+def run_full_interaction(args, torch, Q, W) -> dict:
+    """The whole focused-pulse interaction (the workload's 6000 steps, from before the bunch
+    meets the pulse until after it has left) on a bunch of fewer electrons, in mixed
+    precision, in FP64 and in FP64 with other random draws: the mixed result's error after
+    the full interaction, against the statistical spread of two FP64 runs."""
+    n, steps = args.full_n, args.full_steps
+    cfg = W.c2(n, start_step=0)
+    runs = {}
+    for name, prec, c in (("mixed", "mixed", cfg), ("fp64", "fp64", cfg),
+                          ("fp64_b", "fp64", dict(cfg, seed=cfg["seed"] + 1))):
+        runs[name] = run_gpu(prec, c, steps, 0, torch, Q, per_launch_events=False, photon_cap=40 * n)
+    err = error_metrics(runs["fp64"], runs["mixed"], 2000.0, torch)
+    stat = error_metrics(runs["fp64"], runs["fp64_b"], 2000.0, torch)
+    out = {"workload": f"{n} electrons of the focused-pulse recipe, steps 0..{steps - 1} (the whole interaction)",
+           "photons_per_electron": {k: runs[k]["G"].count / n for k in runs},
+           "mixed_particle_steps_per_s": n * steps / runs["mixed"]["wall"],
+           "fp64_particle_steps_per_s": n * steps / runs["fp64"]["wall"],
+           "status_bits": {k: runs[k]["status"] for k in runs},
+           "error_vs_fp64": err, "error_statistical_fp64_seeds": stat,
+           "error_tolerance": tolerance_check(err, stat)}
+    for k in list(runs):
+        runs[k]["ctx"].close()
+    del runs
+    torch.cuda.empty_cache()
     return out
 
 
@@ -928,6 +955,9 @@ def main():
                     help="cascade: reorder the particle lists by grid bin every N steps (0: never)")
     ap.add_argument("--cascade-mixed-only", action="store_true",
                     help="cascade: only the timed mixed-precision run (no FP64 runs, no error metrics)")
+    ap.add_argument("--full-steps", type=int, default=6000,
+                    help="steps of the whole-interaction accuracy leg (0: skip it)")
+    ap.add_argument("--full-n", type=int, default=1_000_000, help="electrons of the whole-interaction leg")
     ap.add_argument("--deposit-path", choices=("local", "binned"), default="local",
                     help="cascade: deposition path for the cell-ordered lists (binned: any order)")
     ap.add_argument("--no-deposit", action="store_true",
@@ -1051,6 +1081,9 @@ def main():
     if args.batch_steps > 0:
         print("[bench] batching: many collisions, graph-replayed, vs one at a time in FP64", file=sys.stderr, flush=True)
         result["batched"] = run_batched(args, torch, Q, W)
+    if args.full_steps > 0:
+        print("[bench] the whole interaction, mixed vs FP64", file=sys.stderr, flush=True)
+        result["full_interaction"] = run_full_interaction(args, torch, Q, W)
     if cpu is not None:
         result["cpu_baseline"] = cpu
     print(json.dumps(result))
