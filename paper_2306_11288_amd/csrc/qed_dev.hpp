@@ -146,6 +146,116 @@ __device__ __forceinline__ double grid_gather(const GridDev &f, const float *__r
     });
 }
 
+// The grid gather of a wavefront whose particles lie close together (a list sorted by grid
+// bin): the w x h nodes that the live lanes' stencils touch (any stagger), for all six
+// components, are staged in the wavefront's own LDS box (at most WB_NODES nodes per
+// component) with one or two coalesced loads per component, one float per lane each, and
+// the taps are read from there.  Six to twelve vector memory instructions per wavefront
+// instead of eighteen three-float loads per lane, which the texture-address unit otherwise
+// works through lane by lane.  No block barrier: the box is the wavefront's, whose LDS
+// writes are ordered before its reads by a wavefront-scope fence.  Returns false (nothing
+// done) when the stencils do not fit one box inside the grid; the caller then gathers from
+// global memory.  Every lane of the wavefront must call it.
+constexpr int WB_NODES = 128;                   // nodes per component, two loads per lane
+constexpr int WB_FLOATS = 6 * WB_NODES;         // per wavefront
+// minimum over the wavefront (all 64 lanes active): running minima over 2, 4, 8, 16 lanes
+// of each row by row shifts, then across rows by the row broadcasts; lane 63 holds the
+// result.  Lanes without a source keep the identity.
+__device__ __forceinline__ int wave_min_i(int v) {
+    constexpr int ID = 0x7fffffff;
+    v = min(v, __builtin_amdgcn_update_dpp(ID, v, 0x111, 0xf, 0xf, false));   // row_shr:1
+    v = min(v, __builtin_amdgcn_update_dpp(ID, v, 0x112, 0xf, 0xf, false));   // row_shr:2
+    v = min(v, __builtin_amdgcn_update_dpp(ID, v, 0x114, 0xf, 0xf, false));   // row_shr:4
+    v = min(v, __builtin_amdgcn_update_dpp(ID, v, 0x118, 0xf, 0xf, false));   // row_shr:8
+    v = min(v, __builtin_amdgcn_update_dpp(ID, v, 0x142, 0xa, 0xf, false));   // row_bcast:15
+    v = min(v, __builtin_amdgcn_update_dpp(ID, v, 0x143, 0xc, 0xf, false));   // row_bcast:31
+    return __builtin_amdgcn_readlane(v, 63);
+}
+template <class FT>
+__device__ __forceinline__ bool grid_fields_wavebox(const GridDev &f, float *box, bool live, double x, double y,
+                                                    V3<double> &E, V3<double> &B) {
+    // stencil nodes of any staggering: columns floor(X) - 1 .. floor(X + 1/2) + 1, rows alike
+    const double X = (x - f.gx0) * f.inv_dx, Y = (y - f.gy0) * f.inv_dy;
+    constexpr int BIG = 0x3fffffff;
+    int v[4] = {BIG, BIG, BIG, BIG};
+    if (live) {
+        if (fabs(X) < 1e9 && fabs(Y) < 1e9) {
+            v[0] = (int)floor(X) - 1;
+            v[1] = (int)floor(Y) - 1;
+            v[2] = -((int)floor(X + 0.5) + 1);
+            v[3] = -((int)floor(Y + 0.5) + 1);
+        } else {
+            v[0] = -BIG;                        // far off the grid or not finite: no box
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = wave_min_i(v[k]);
+    const int i0 = v[0], j0 = v[1], i1 = -v[2], j1 = -v[3];
+    // no live lane (i0 = BIG), a lane off the grid, or a box too large
+    if (i0 < 0 || j0 < 0 || i0 == BIG || i1 >= f.nx || j1 >= f.ny)
+        return false;
+    const int w = i1 - i0 + 1, h = j1 - j0 + 1;
+    if (w > WB_NODES || h > WB_NODES || w * h > WB_NODES)
+        return false;
+    // fill: element c WB_NODES + e of the box, e = r w + q < w h, is node (i0 + q, j0 + r)
+    // of component c; lane l loads e = l and, where w h > 64, e = l + 64 (elements past
+    // w h repeat the last node: in bounds, never read)
+    static_assert(WB_NODES > 64 && WB_NODES <= 128, "at most two loads per lane and component");
+    const int wh = w * h, l0 = threadIdx.x & 63, l1 = l0 + 64;
+    const int e0 = min(l0, wh - 1), e1 = min(l1, wh - 1);
+    // e / w as floor((e + 1/2) / w) in FP32: exact, the quotient being at least 1/(2w)
+    // away from an integer (e < 128, w <= 128) and the FP32 error far below that
+    const float iw = __builtin_amdgcn_rcpf((float)w);
+    const int r0 = (int)(((float)e0 + 0.5f) * iw), r1 = (int)(((float)e1 + 0.5f) * iw);
+    // 32-bit byte offsets from the arrays' bases (grids hold fewer than 2^29 nodes)
+    const uint32_t o0 = 4u * (uint32_t)((j0 + r0) * f.nx + i0 + e0 - r0 * w);
+    const uint32_t o1 = 4u * (uint32_t)((j0 + r1) * f.nx + i0 + e1 - r1 * w);
+    float u[12];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) u[2 * c] = *(const float *)((const char *)f.g[c] + o0);
+    if (wh > 64) {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) u[2 * c + 1] = *(const float *)((const char *)f.g[c] + o1);
+    }
+#pragma unroll
+    for (int c = 0; c < 6; ++c) box[c * WB_NODES + l0] = u[2 * c];
+    if (wh > 64) {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) box[c * WB_NODES + l1] = u[2 * c + 1];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (live) {
+        // the TSC taps of each stagger (every tap inside the box: no edge handling), summed
+        // in the order of tsc_gather
+        int ix[2], jy[2];
+        FT wx[2][3], wy[2][3];
+#pragma unroll
+        for (int hf = 0; hf < 2; ++hf) {
+            tsc_w<FT>(X, hf, ix[hf], wx[hf]);
+            tsc_w<FT>(Y, hf, jy[hf], wy[hf]);
+        }
+        auto from = [&](int c, int hx, int hy) {
+            const float *r = box + c * WB_NODES + (jy[hy] - j0) * w + (ix[hx] - i0);
+            FT sum = 0;
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                const float *rb = r + b * w;
+                sum += wy[hy][b] * (wx[hx][0] * (FT)rb[0] + wx[hx][1] * (FT)rb[1] + wx[hx][2] * (FT)rb[2]);
+            }
+            return (double)sum;
+        };
+        E = {from(0, 1, 0), from(1, 0, 1), from(2, 0, 0)};
+        __builtin_amdgcn_sched_barrier(0);
+        B = {from(3, 0, 1), from(4, 1, 0), from(5, 1, 1)};
+    }
+    // the box is read before the next tile's fill overwrites it
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    return true;
+}
+
 // Laser pulses (plane wave E = -dA/dphi with a sin^2 envelope; paraxial Gaussian beam at
 // zeroth order), KIND = QED_FIELD_PW or QED_FIELD_GAUSS.  In single precision every phase
 // is reduced in FP64 and handed to the hardware sine / cosine in revolutions (v_sin_f32

@@ -620,10 +620,13 @@ struct PhotonTabsLds {
     __device__ __forceinline__ const T *vb() const { return vbt; }
 };
 
+// FP64: held to four wavefronts per SIMD (at most 128 VGPRs)
 template <class T, bool NBW, int FK>
-__global__ __launch_bounds__(BLOCK) void k_photons_decide(PhotonArgs a) {
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 4 : 1))) void k_photons_decide(PhotonArgs a) {
     __shared__ int s_wave[2][BLOCK / 64];
     __shared__ T s_tab[2 * NP + 2 * NV];
+    // grid fields: each wavefront's LDS box of stencil nodes (grid_fields_wavebox)
+    __shared__ float s_box[FK == QED_FIELD_GRID2D ? BLOCK / 64 : 1][FK == QED_FIELD_GRID2D ? WB_FLOATS : 1];
     // 32-bit indices: lists hold at most 2^28 particles
     const int n = (int)clamp_count(a.G.count, a.G.capacity);
     const int ntiles = (n + BLOCK - 1) / BLOCK;
@@ -659,8 +662,11 @@ __global__ __launch_bounds__(BLOCK) void k_photons_decide(PhotonArgs a) {
             xi = {ld_nt(xi1, os), ld_nt(xi2, os), ld_nt(xi3, os)};
             e1 = {ld_nt(e1x, os), ld_nt(e1y, os), ld_nt(e1z, os)};
         }
+        bool have = false;
+        if constexpr (FK == QED_FIELD_GRID2D)
+            have = grid_fields_wavebox<T>(a.field.g, s_box[threadIdx.x >> 6], live, x.x, x.y, E, B);
         if (live) {
-            field_kind<T, FK>(a.field, t, x.x, x.y, x.z, E, B);
+            if (!have) field_kind<T, FK>(a.field, t, x.x, x.y, x.z, E, B);
             PhotonFrame f;
             photon_frame(a.c.xi_L, k, E, B, f);
             const double chi = photon_transport<T>(a.c, tb, f, xi, e1, a.do_vb, st);

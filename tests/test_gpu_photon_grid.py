@@ -1,7 +1,8 @@
 """GPU photon step on a 2D grid against the oracle: the TSC gather of the photon kernel for
-photons inside, on the border of and beyond the grid, in random order and sorted by cell
-(tiles whose taps span a few cells, or the whole grid), random field values; one VB + NBW
-step.  FP64 to the parity bar; mixed within single-precision error of the FP64 path."""
+photons inside, on the border of and beyond the grid, in random order, sorted by x, and in
+wavefront-sized clusters (the kernel's LDS box path, with live and dead outliers that send
+a wavefront back to the global gather), random field values; one VB + NBW step.  FP64 to
+the parity bar; mixed within single-precision error of the FP64 path."""
 import numpy as np
 import pytest
 
@@ -14,8 +15,8 @@ import paper_2306_11288_amd as Q  # noqa: E402
 
 from test_gpu_parity import _close_lep, _ctx, _sim  # noqa: E402
 
-TILE = 256                 # photons per block of the photon kernel
-PATCH_NODES = 1024         # nodes of a compact tile box (a tile of photons close together)
+WAVE = 64                  # photons per wavefront of the photon kernel
+WB_NODES = 128             # nodes per component of a wavefront's LDS box of grid nodes
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -29,29 +30,27 @@ def _say(msg):
     print(f"[gpu-photon-grid] {msg}", flush=True)
 
 
-def _tile_fits(x, y, nx, ny, dx, dy, gx0, gy0):
-    """Whether each 256-photon tile's taps (node windows of both staggers, rows on the grid,
-    rows padded to a power of two) fit in a box of PATCH_NODES nodes: the test covers both
-    compact tiles and tiles spread over the whole grid."""
-    fits = []
-    for b in range(0, len(x), TILE):
-        xg = np.clip((x[b:b + TILE] - gx0) / dx, -8, nx + 8)
-        yg = np.clip((y[b:b + TILE] - gy0) / dy, -8, ny + 8)
-        ic, jc = np.floor(xg).astype(int), np.floor(yg).astype(int)
-        xl = np.clip(ic - 1, 0, nx - 3).min()
-        xh = (np.clip(ic, 0, nx - 3) + 2).max()
-        r0, r1 = np.maximum(jc - 1, 0), np.minimum(jc + 2, ny - 1)
-        on = r0 <= r1
-        if not on.any():
-            fits.append(False)
+def _wave_box(x, y, alive, nx, ny, dx, dy, gx0, gy0, limit=WB_NODES):
+    """Whether each wavefront of 64 photons takes the kernel's LDS box path: the stencil
+    nodes of every live photon (either stagger) span a box of at most `limit` nodes inside
+    the grid (WB_NODES; a box of 64 nodes or fewer is filled by one load per lane)."""
+    res = []
+    for b in range(0, len(x), WAVE):
+        a = alive[b:b + WAVE] != 0
+        if not a.any():
+            res.append(False)
             continue
-        w, h = xh - xl + 1, r1[on].max() - r0[on].min() + 1
-        fits.append(6 * h * (1 << int(np.ceil(np.log2(w)))) <= 6 * PATCH_NODES)
-    return np.array(fits)
+        X, Y = (x[b:b + WAVE][a] - gx0) * (1.0 / dx), (y[b:b + WAVE][a] - gy0) * (1.0 / dy)
+        i0, i1 = np.floor(X).min() - 1, np.floor(X + 0.5).max() + 1
+        j0, j1 = np.floor(Y).min() - 1, np.floor(Y + 0.5).max() + 1
+        w, h = i1 - i0 + 1, j1 - j0 + 1
+        res.append(bool(i0 >= 0 and j0 >= 0 and i1 < nx and j1 < ny and w * h <= limit))
+    return np.array(res)
 
 
 @pytest.mark.parametrize("nx,ny,order", [(3, 1, "random"), (7, 5, "random"), (40, 24, "random"),
-                                         (200, 30, "random"), (200, 30, "by_x")])
+                                         (200, 30, "random"), (200, 30, "by_x"), (40, 24, "clusters"),
+                                         (200, 30, "clusters")])
 def test_photon_step_on_grid_matches_oracle(nx, ny, order):
     _say(f"photons on a {nx}x{ny} grid, {order}")
     rng = np.random.default_rng(100 + nx + ny)
@@ -68,13 +67,26 @@ def test_photon_step_on_grid_matches_oracle(nx, ny, order):
         o = np.argsort(st["x"], kind="stable")
         st = {k: v[o].copy() for k, v in st.items()}
         st["id"] = np.arange(n, dtype=np.uint64)
-    fits = _tile_fits(st["x"], st["y"], nx, ny, dx, dy, gx0, gy0)
-    if (1 << int(np.ceil(np.log2(nx)))) * ny <= PATCH_NODES:     # the whole grid fits
-        assert fits.all()
-    elif order == "random":
-        assert not fits.any()
+    elif order == "clusters":
+        # each wavefront's photons within +-2.5 nodes of a centre anywhere over the grid and
+        # its border; every third wavefront has an outlier, live or dead
+        nw = (n + WAVE - 1) // WAVE
+        cx, cy = rng.uniform(-1.0, nx + 1.0, nw), rng.uniform(-1.0, ny + 1.0, nw)
+        w = np.arange(n) // WAVE
+        st["x"] = gx0 + dx * (cx[w] + rng.uniform(-2.5, 2.5, n))
+        st["y"] = gy0 + dy * (cy[w] + rng.uniform(-2.5, 2.5, n))
+        for b in range(0, nw, 3):
+            lane = b * WAVE + int(rng.integers(0, min(WAVE, n - b * WAVE)))
+            st["x"][lane] = gx0 + dx * rng.uniform(-3.0, nx + 2.0)
+            st["alive"][lane] = b % 2
+    fits = _wave_box(st["x"], st["y"], st["alive"], nx, ny, dx, dy, gx0, gy0)
+    _say(f"{int(fits.sum())} of {len(fits)} wavefronts on the LDS box path")
+    if order == "clusters":
+        one = _wave_box(st["x"], st["y"], st["alive"], nx, ny, dx, dy, gx0, gy0, limit=64).sum()
+        assert 0.15 * len(fits) < fits.sum() < 0.9 * len(fits)
+        assert one >= 3 and fits.sum() - one >= 3          # boxes filled by one and two loads
     else:
-        assert fits.sum() >= len(fits) - 1
+        assert not fits.any()
     cfg = {"dt": W.TWO_PI / 500, "procs": oracle.PROC_VB | oracle.PROC_NBW, "seed": 21, "next_id": 1 << 41}
     step = 40
     f = oracle.make_field(spec_o)
