@@ -123,7 +123,7 @@ __global__ __launch_bounds__(BLOCK) void k_brems_events(BremsArgs a) {
     const int64_t base = a.launch[0], id0 = a.launch[2];
     const T *tab = (const T *)a.tab;
     uint32_t st = 0;
-    group_events<BR_GROUP>(a.tile_counts, a.tile_off, ntiles, t0, [&](int64_t e, int64_t slot) {
+    group_events<BR_GROUP>(a.tile_counts, a.tile_off[t0], ntiles, t0, [&](int64_t e, int64_t slot) {
         const EventRec &rec = a.stg[slot];
         const int64_t i = rec.idx;
         const double px = a.L.px[i], py = a.L.py[i], pz = a.L.pz[i];

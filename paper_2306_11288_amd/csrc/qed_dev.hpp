@@ -545,6 +545,61 @@ __device__ __forceinline__ T cdf_invert(const Rows &R, int ncol, T f, T m, T tar
     tau = tau < (T)0 ? (T)0 : (tau > (T)1 ? (T)1 : tau);
     return (T)lo + tau;
 }
+// The same inversion by a K-ary search: each round reads K - 1 columns inside (lo, hi) at
+// once and keeps the interval before the first of them above the target, so a row of 512
+// columns takes three rounds of memory latency instead of nine.  On a non-decreasing row it
+// brackets the same pair of columns as the bisection (the last column at or below the
+// target, capped at ncol - 2); for the rare events, where the latency of one lane's
+// dependent reads is the kernel's time.
+template <class T, int K, class Rows>
+__device__ __forceinline__ T cdf_invert_wide(const Rows &R, int ncol, T f, T m, T target) {
+    int lo = 0, hi = ncol - 1;
+    const T g = (T)1 - f;
+    T dlo, dhi;
+    // one round of K - 1 columns inside (lo, hi): the interval before the first one above
+    // the target
+    auto round = [&](T lo_v, T hi_v, bool first) {
+        int p[K - 1];
+        T d[K - 1];
+#pragma unroll
+        for (int q = 0; q < K - 1; ++q) {
+            p[q] = lo + 1 + ((hi - lo - 1) * (q + 1)) / K;   // in [lo + 1, hi - 1]
+            d[q] = cdf_at<T>(R, p[q], g, f, m);
+        }
+        if (first) {   // the ends, read together with the first round's columns
+            lo_v = cdf_at<T>(R, lo, g, f, m);
+            hi_v = cdf_at<T>(R, hi, g, f, m);
+        }
+        int nlo = lo, nhi = hi;
+        T vlo = lo_v, vhi = hi_v;
+        bool above = false;
+#pragma unroll
+        for (int q = 0; q < K - 1; ++q) {
+            if (!above && d[q] > target) {
+                above = true;
+                nhi = p[q];
+                vhi = d[q];
+            } else if (!above) {
+                nlo = p[q];
+                vlo = d[q];
+            }
+        }
+        lo = nlo;
+        hi = nhi;
+        dlo = vlo;
+        dhi = vhi;
+    };
+    if (hi - lo > 1) {
+        round((T)0, (T)0, true);
+    } else {
+        dlo = cdf_at<T>(R, lo, g, f, m);
+        dhi = cdf_at<T>(R, hi, g, f, m);
+    }
+    while (hi - lo > 1) round(dlo, dhi, false);
+    T tau = dhi > dlo ? (target - dlo) / (dhi - dlo) : (T)0;
+    tau = tau < (T)0 ? (T)0 : (tau > (T)1 ? (T)1 : tau);
+    return (T)lo + tau;
+}
 template <class T>
 __device__ __forceinline__ void row_pos(T l, double lo, double hi, int n, int &r0, T &f) {
     T q = gridpos<T>(l, lo, hi, n);
@@ -606,10 +661,10 @@ __device__ __forceinline__ T nbw_sample_delta(const Tabs<T> &tb, double chi, T k
     const T target = (lower ? r : (T)1 - r) * ((T)1 - m);
     T col;
     if constexpr (sizeof(T) == 4) {
-        col = cdf_invert<T>(CdfPairs{tb.nbw_cdf_pair() + (int64_t)r0 * NDD}, NDD, f, m, target);
+        col = cdf_invert_wide<T, 8>(CdfPairs{tb.nbw_cdf_pair() + (int64_t)r0 * NDD}, NDD, f, m, target);
     } else {
         const T *R0 = tb.nbw_cdf() + (int64_t)r0 * NDD * 2;
-        col = cdf_invert<T>(CdfRows<T>{R0, R0 + 2 * NDD}, NDD, f, m, target);
+        col = cdf_invert_wide<T, 8>(CdfRows<T>{R0, R0 + 2 * NDD}, NDD, f, m, target);
     }
     return lower ? col * hd : (T)1 - col * hd;
 }
@@ -993,6 +1048,16 @@ __device__ __forceinline__ void stage(EventRec *stg, int64_t slot, int64_t idx, 
     r.f[3] = B.x; r.f[4] = B.y; r.f[5] = B.z;
 }
 
+// photon events: the photon index of the event of rank r (bytes [0, 8) of staging slot r)
+// and the record of photon j's event (bytes [8, ...) of slot j)
+__device__ __forceinline__ int64_t *event_index(void *stg, int64_t r) {
+    return (int64_t *)((char *)stg + r * (int64_t)STAGING_SLOT);
+}
+template <class T>
+__device__ __forceinline__ PhotonEvent<T> *photon_event(void *stg, int64_t j) {
+    return (PhotonEvent<T> *)((char *)stg + j * (int64_t)STAGING_SLOT + 8);
+}
+
 // tile whose event range [off[t], off[t+1]) holds global event e (last t with off[t] <= e)
 __device__ __forceinline__ int64_t tile_of(const int64_t *off, int64_t ntiles, int64_t e) {
     int64_t lo = 0, hi = ntiles - 1;
@@ -1008,11 +1073,11 @@ __device__ __forceinline__ int64_t tile_of(const int64_t *off, int64_t ntiles, i
 // The events of one group of G consecutive tiles, handled by one wavefront (call it with all
 // 64 lanes active and a wavefront-uniform first tile t0 < ntiles): the lanes' running sum of
 // the G tile counts gives each event its tile (no per-event search); f(e, slot) is called
-// for every event, e its global rank (off[t0] + rank in the group), slot its staging slot
-// tile * BLOCK + rank in the tile.  Suits sparse events (a few per tile).
+// for every event, e its global rank (e0, the rank of the group's first event, + rank in
+// the group), slot its staging slot tile * BLOCK + rank in the tile.  Suits sparse events
+// (a few per tile).
 template <int G, class F>
-__device__ __forceinline__ void group_events(const int *counts, const int64_t *off, int64_t ntiles, int64_t t0,
-                                             F &&f) {
+__device__ __forceinline__ void group_events(const int *counts, int64_t e0, int64_t ntiles, int64_t t0, F &&f) {
     static_assert(G <= 64, "one count per lane");
     const int lane = threadIdx.x & 63;
     const int cnt = lane < G && t0 + lane < ntiles ? counts[t0 + lane] : 0;
@@ -1027,7 +1092,6 @@ __device__ __forceinline__ void group_events(const int *counts, const int64_t *o
 #pragma unroll
     for (int k = 0; k < G; ++k) exs[k] = __builtin_amdgcn_readlane(excl, k);
     const int total = __builtin_amdgcn_readlane(incl, G - 1);
-    const int64_t e0 = off[t0];
     for (int le = lane; le < total; le += 64) {
         // the last tile whose first rank is at or before the event (a tile without events
         // shares its first rank with the next, so this is never an empty tile)

@@ -198,9 +198,22 @@ struct HistArgs {
 constexpr int BLOCK = 256;             // threads per block = particles per tile
 constexpr int EV_GROUP_MAX = 16;       // lepton step: largest tiles-per-group of the event kernel
 
+// photon (pair) event record: what the decide kernel reached for a converting photon (its
+// momentum and place, chi, kappa, the two draws the pair needs, Stokes vector and basis
+// after this step's rotation)
+template <class T>
+struct PhotonEvent {
+    double k[3], x[3];
+    double chi, r0, r2;
+    T xi[3], e1[3], kappa;
+};
+
 // bytes of one staging slot: the largest record any kernel parks there
 constexpr size_t STAGING_SLOT = sizeof(LepEvent<double>) > sizeof(EventRec) ? sizeof(LepEvent<double>)
                                                                              : sizeof(EventRec);
+// a photon event sits in bytes [8, ...) of the converting photon's own slot, the photon
+// index of the event of rank r in bytes [0, 8) of slot r: the two never overlap
+static_assert(8 + sizeof(PhotonEvent<double>) <= STAGING_SLOT, "a photon event fits a staging slot");
 
 }  // namespace qed
 

@@ -600,10 +600,12 @@ struct PhotonArgs {
     uint32_t *status;
     EventRec *stg;
     int *tile_counts;
-    const int64_t *tile_off;
+    int *group_tot;            // events per group of PH_GROUP tiles (zero between launches)
+    const int64_t *tile_off;   // exclusive prefix of group_tot
     const int64_t *launch;
     float *ev_in;              // learned NBW sampler: per-pair network inputs [pairs][4]
     const float *ev_out;       // and outputs [pairs][3]
+    int ev_net;                // pair events: the network's delta used where valid
 };
 
 // transport (+ NBW test), specialised on the field kind: a persistent grid sweeps the
@@ -621,6 +623,9 @@ struct PhotonTabsLds {
 };
 
 // FP64: held to four wavefronts per SIMD (at most 128 VGPRs)
+// pairs are rare (well under one per tile): the event kernel takes groups of PH_GROUP tiles,
+// one per wavefront, and the event scan runs over these groups
+constexpr int PH_GROUP = 32;
 template <class T, bool NBW, int FK>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 4 : 1))) void k_photons_decide(PhotonArgs a) {
     __shared__ int s_wave[2][BLOCK / 64];
@@ -680,6 +685,15 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(T)
                     double rr[4];
                     uniform4(at(a.G.id, o), step, STREAM_NBW, a.c.seed, rr);
                     ev = rr[1] < P;
+                    if (ev) {   // the event's record, in this photon's own staging slot
+                        PhotonEvent<T> &r = *photon_event<T>(a.stg, j);
+                        r.k[0] = k.x; r.k[1] = k.y; r.k[2] = k.z;
+                        r.x[0] = x.x; r.x[1] = x.y; r.x[2] = x.z;
+                        r.chi = chi; r.r0 = rr[0]; r.r2 = rr[2];
+                        r.xi[0] = xi.x; r.xi[1] = xi.y; r.xi[2] = xi.z;
+                        r.e1[0] = e1.x; r.e1[1] = e1.y; r.e1[2] = e1.z;
+                        r.kappa = kappa;
+                    }
                 }
             }
             st_nt(xi1, os, xi.x); st_nt(xi2, os, xi.y); st_nt(xi3, os, xi.z);
@@ -696,18 +710,22 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(T)
         if constexpr (NBW) {
             int total;
             const int rank = block_rank(ev, total, s_wave[par]);
-            if (ev) stage(a.stg, (int64_t)tile * BLOCK + rank, j, E, B);
-            if (threadIdx.x == 0) a.tile_counts[tile] = total;
+            if (ev) *event_index(a.stg, (int64_t)tile * BLOCK + rank) = j;
+            if (threadIdx.x == 0) {
+                a.tile_counts[tile] = total;
+                if (total) atomicAdd(a.group_tot + tile / PH_GROUP, total);
+            }
         }
     }
     if (st) atomicOr(a.status, st);
 }
 
 // pair events: electron to em, positron to ep, in photon order; one wavefront per group
-// of PH_GROUP tiles (pairs are rare: well under one per tile).  MODE as for the lepton
-// events: EV_FULL (table delta), EV_PREP (the NBW network's inputs of every pair at its
-// rank, nothing else written), EV_FINISH (the network's delta where valid).
-constexpr int PH_GROUP = 32;
+// of PH_GROUP tiles.  MODE EV_PREP writes the NBW
+// network's inputs of every pair at its rank, nothing else; EV_FINISH writes the pairs,
+// with the network's delta where valid when ev_net is set.  The table sampler runs the
+// same EV_FINISH code with ev_net clear, so that its pairs are bitwise those of the
+// learned sampler wherever the network's delta is not used.
 template <class T, int MODE>
 __global__ __launch_bounds__(BLOCK) void k_photons_events(PhotonArgs a) {
     const int64_t n = clamp_count(a.G.count, a.G.capacity);
@@ -716,22 +734,18 @@ __global__ __launch_bounds__(BLOCK) void k_photons_events(PhotonArgs a) {
     if (t0 >= ntiles) return;
     const int64_t id0 = a.launch[2];
     const Tabs<T> tb = {(const T *)a.tab};
-    const T *xi1 = (const T *)a.G.xi1, *xi2 = (const T *)a.G.xi2, *xi3 = (const T *)a.G.xi3;
-    const T *e1x = (const T *)a.G.e1x, *e1y = (const T *)a.G.e1y, *e1z = (const T *)a.G.e1z;
     uint32_t st = 0;
-    group_events<PH_GROUP>(a.tile_counts, a.tile_off, ntiles, t0, [&](int64_t e, int64_t slot) {
-        const EventRec &rec = a.stg[slot];
-        const int64_t j = rec.idx;
-        const V3<double> E = {rec.f[0], rec.f[1], rec.f[2]}, B = {rec.f[3], rec.f[4], rec.f[5]};
-        const V3<double> k = {a.G.kx[j], a.G.ky[j], a.G.kz[j]};
-        const V3<T> xi = {xi1[j], xi2[j], xi3[j]}, e1 = {e1x[j], e1y[j], e1z[j]};
-        PhotonFrame f;   // the same arithmetic as in the decide kernel
-        photon_frame(a.c.xi_L, k, E, B, f);
-        const double chi = f.chi, eps = f.eps;
-        T Ja, kappa;
-        nbw_prob<T>(a.c, tb, eps, chi, xi.z, Ja, kappa, st);
-        double rr[4];
-        uniform4(a.G.id[j], step_of(a), STREAM_NBW, a.c.seed, rr);
+    group_events<PH_GROUP>(a.tile_counts, a.tile_off[t0 / PH_GROUP], ntiles, t0, [&](int64_t e, int64_t slot) {
+        // the decide kernel's record of the event (no frame, rate or generator recomputed:
+        // one lane's chain of dependent reads and arithmetic is this kernel's time)
+        const int64_t j = *event_index(a.stg, slot);
+        const PhotonEvent<T> &r = *photon_event<T>(a.stg, j);
+        const V3<double> k = {r.k[0], r.k[1], r.k[2]};
+        const V3<T> xi = {r.xi[0], r.xi[1], r.xi[2]}, e1 = {r.e1[0], r.e1[1], r.e1[2]};
+        const double bx = r.x[0], by = r.x[1], bz = r.x[2], bw = a.G.w[j];
+        const double chi = r.chi;
+        const T kappa = r.kappa;
+        const double rr[4] = {r.r0, 0.0, r.r2, 0.0};   // the delta and spin draws
         const bool in_range = chi >= MLP_NBW_CHI_LO && chi <= MLP_NBW_CHI_HI;
         if constexpr (MODE == EV_PREP) {
             float4 x = {0.0f, 0.0f, 0.0f, 0.0f};
@@ -743,8 +757,8 @@ __global__ __launch_bounds__(BLOCK) void k_photons_events(PhotonArgs a) {
         // the network's delta inside its trained chi range where it lies in [MLP_D_LO,
         // 1 - MLP_D_LO] (away from the ends, where an absolute error is a large relative
         // one in the softer member's energy); the table everywhere else
-        const float dn = MODE == EV_FINISH ? a.ev_out[3 * e] : -1.0f;
-        const T d = (MODE == EV_FINISH && in_range && dn >= MLP_D_LO && dn <= 1.0f - MLP_D_LO)
+        const float dn = a.ev_net ? a.ev_out[3 * e] : -1.0f;
+        const T d = (a.ev_net && in_range && dn >= MLP_D_LO && dn <= 1.0f - MLP_D_LO)
                         ? (T)dn
                         : nbw_sample_delta<T>(tb, chi, kappa, xi.z, (T)rr[0]);
         PairOut<T> po;
@@ -758,10 +772,10 @@ __global__ __launch_bounds__(BLOCK) void k_photons_events(PhotonArgs a) {
             if (pos >= L.capacity) continue;
             const V3<double> &p = s == 0 ? po.pm : po.pp;
             const V3<T> &S = s == 0 ? po.Sm : po.Sp;
-            L.x[pos] = a.G.x[j]; L.y[pos] = a.G.y[j]; L.z[pos] = a.G.z[j];
+            L.x[pos] = bx; L.y[pos] = by; L.z[pos] = bz;
             L.px[pos] = p.x; L.py[pos] = p.y; L.pz[pos] = p.z;
             ((T *)L.sx)[pos] = S.x; ((T *)L.sy)[pos] = S.y; ((T *)L.sz)[pos] = S.z;
-            L.w[pos] = a.G.w[j];
+            L.w[pos] = bw;
             L.id[pos] = (unsigned long long)(id0 + 2 * e + s);
         }
     });
@@ -1027,25 +1041,27 @@ static hipError_t launch_photons_stage(qed_ctx *ctx, const PhotonArgs &a, hipStr
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !a.do_nbw) return e;
-    e = launch_scan(ctx, a.G.count, a.G.capacity, ctx->tile_counts, a.has_em ? a.em.count : nullptr,
+    // over the groups' totals (zeroed by the scan for the next launch): a list of up to
+    // 2^26 photons takes one scan launch
+    e = launch_scan(ctx, a.G.count, a.G.capacity, a.group_tot, a.has_em ? a.em.count : nullptr,
                     a.has_em ? a.em.capacity : 0, a.has_ep ? a.ep.count : nullptr, a.has_ep ? a.ep.capacity : 0, 2, s,
-                    0, lep_start);
+                    0, lep_start, nullptr, nullptr, BLOCK * PH_GROUP, nullptr, 1);
     if (e != hipSuccess) return e;
     const int64_t groups = (a.G.capacity + (int64_t)BLOCK * PH_GROUP - 1) / ((int64_t)BLOCK * PH_GROUP);
     const int64_t nb = (groups + BLOCK / 64 - 1) / (BLOCK / 64);
     const dim3 gd((unsigned)(nb < 1 ? 1 : nb));
-    if (!(ctx->sampler & QED_SAMPLER_MLP_NBW)) {
-        hipLaunchKernelGGL((k_photons_events<T, EV_FULL>), gd, dim3(BLOCK), 0, s, a);
-        return hipGetLastError();
+    PhotonArgs b = a;
+    b.ev_net = (ctx->sampler & QED_SAMPLER_MLP_NBW) != 0;
+    if (b.ev_net) {
+        // learned delta: the network's inputs of every pair at its rank, the network over
+        // the device pair count, then the events
+        hipLaunchKernelGGL((k_photons_events<T, EV_PREP>), gd, dim3(BLOCK), 0, s, b);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if ((e = mlp_forward(ctx, ctx->nets[QED_NET_NBW], b.ev_in, ctx->ev_out, 0, b.launch + 3, b.G.capacity, s)) !=
+            hipSuccess)
+            return e;
     }
-    // learned delta: the network's inputs of every pair at its rank, the network over the
-    // device pair count, then the events
-    hipLaunchKernelGGL((k_photons_events<T, EV_PREP>), gd, dim3(BLOCK), 0, s, a);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    if ((e = mlp_forward(ctx, ctx->nets[QED_NET_NBW], a.ev_in, ctx->ev_out, 0, a.launch + 3, a.G.capacity, s)) !=
-        hipSuccess)
-        return e;
-    hipLaunchKernelGGL((k_photons_events<T, EV_FINISH>), gd, dim3(BLOCK), 0, s, a);
+    hipLaunchKernelGGL((k_photons_events<T, EV_FINISH>), gd, dim3(BLOCK), 0, s, b);
     return hipGetLastError();
 }
 
@@ -1079,6 +1095,7 @@ hipError_t launch_photons(qed_ctx *ctx, PhotonMode mode, const SegArgs &sa, cons
     a.status = ctx->status;
     a.stg = (EventRec *)ctx->staging;
     a.tile_counts = ctx->tile_counts;
+    a.group_tot = ctx->group_tot;
     a.tile_off = ctx->tile_off;
     a.launch = ctx->launch;
     a.ev_in = ctx->ev_in;
