@@ -325,16 +325,17 @@ __global__ __launch_bounds__(BLOCK) void k_leptons_simple(LeptonArgs a) {
 // fields of x^n taken from E6 (emission only).  Returns 1/gamma of the resulting momentum.  Lepton arrays are addressed with 32-bit byte
 // offsets from the array base (lists hold at most 2^28 particles), which lets every load
 // and store use the scalar-base + vector-offset form.
-template <class T, bool PUSH, int FK>
+// PRE: r, E and B given (the grid fields gathered by the wavefront beforehand)
+template <class T, bool PUSH, int FK, bool PRE = false>
 __device__ __forceinline__ double lepton_state(const LeptonArgs &a, int64_t i, double t, double q, V3<double> &r,
                                                V3<double> &p, V3<T> &S, V3<double> &E, V3<double> &B,
                                                uint32_t &st) {
     const uint32_t o = (uint32_t)i * 8u, os = (uint32_t)i * (uint32_t)sizeof(T);
-    r = {ld_nt(a.L.x, o), ld_nt(a.L.y, o), ld_nt(a.L.z, o)};
+    if constexpr (!PRE) r = {ld_nt(a.L.x, o), ld_nt(a.L.y, o), ld_nt(a.L.z, o)};
     p = {ld_nt(a.L.px, o), ld_nt(a.L.py, o), ld_nt(a.L.pz, o)};
     S = {ld_nt((T *)a.L.sx, os), ld_nt((T *)a.L.sy, os), ld_nt((T *)a.L.sz, os)};
     if constexpr (PUSH) {
-        fields_for<T, FK>(a.sa, i, t, r, E, B);
+        if constexpr (!PRE) fields_for<T, FK>(a.sa, i, t, r, E, B);
         return push_one<T>(a, q, a.c.dt, E, B, r, p, S, st);
     } else {
         const double *e = a.E6 + 6 * i;
@@ -433,11 +434,16 @@ __global__ __launch_bounds__(BLOCK) void k_leptons_radiative(LeptonArgs a, uint3
 // sum does not depend on their order; the scan clears the totals it reads).  RATE_LDS: the
 // NCS rate table is staged in LDS once per block instead of being read through the caches.
 // The FP64 instances are held to at least five wavefronts per SIMD (83-94 VGPRs, no
-// spills): forcing six (79 VGPRs with spills) measured 4 % slower, seven 25 % slower.
+// spills): forcing six (79 VGPRs with spills) measured 4 % slower, seven 25 % slower.  So
+// is the FP32 grid instance with its LDS box (96 VGPRs, no spills; 100 unconstrained).
 template <class T, bool PUSH, int FK, bool RATE_LDS>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 5 : 1))) void k_leptons_decide(LeptonArgs a) {
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu((sizeof(T) == 8 || (PUSH && FK == QED_FIELD_GRID2D)) ? 5 : 1))) void k_leptons_decide(LeptonArgs a) {
     __shared__ int s_wave[2][BLOCK / 64];
     __shared__ T s_rate[RATE_LDS ? 2 * NR : 1];
+    // a grid field of one segment: each wavefront's LDS box of stencil nodes
+    // (grid_fields_wavebox), the global gather where the box does not serve
+    constexpr bool WBOX = PUSH && FK == QED_FIELD_GRID2D;
+    __shared__ float s_box[WBOX ? BLOCK / 64 : 1][WBOX ? WB_FLOATS : 1];
     // 32-bit indices: lists hold at most 2^28 particles
     const int n = (int)lepton_count(a);
     const int ntiles = (n + BLOCK - 1) / BLOCK;
@@ -458,8 +464,21 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(T)
         bool ev = false;
         V3<double> r, p, E, B;
         V3<T> S;
+        if constexpr (WBOX) {
+            r = {0, 0, 0};
+            E = {0, 0, 0};
+            B = {0, 0, 0};
+            bool in = false;
+            if (i < n) {
+                const uint32_t o = (uint32_t)i * 8u;
+                r = {ld_nt(a.L.x, o), ld_nt(a.L.y, o), ld_nt(a.L.z, o)};
+                in = i >= a.sa.begin0 && i < a.sa.end0;
+            }
+            const bool have = grid_fields_wavebox<T>(a.sa.f0.g, s_box[threadIdx.x >> 6], in, r.x, r.y, E, B);
+            if (in && !have) field_kind<T, FK>(a.sa.f0, t, r.x, r.y, r.z, E, B);
+        }
         if (i < n) {
-            const double ig = lepton_state<T, PUSH, FK>(a, i, t, q, r, p, S, E, B, st);
+            const double ig = lepton_state<T, PUSH, FK, WBOX>(a, i, t, q, r, p, S, E, B, st);
             if constexpr (PUSH) store_xp<T>(a, (uint32_t)i * 8u, r, p);
             NcsFrame<T> f;
             if (ncs_frame<T>(a.c, rate, q, p, ig, S, E, B, st, f)) {
