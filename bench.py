@@ -580,7 +580,9 @@ def cascade_once(args, torch, Q, W, prec, seed_offset=0, timed=True):
     # the lists are kept in cell order by the periodic sort: the local deposition path
     dep_path = "local" if (sort_every > 0 and args.deposit_path == "local") else "binned"
     ctx.set_deposit_path(Q.DEPOSIT_LOCAL if dep_path == "local" else Q.DEPOSIT_BINNED)
-    J = [torch.zeros((grid["ny"], grid["nx"]), dtype=torch.float32, device="cuda") for _ in range(3)]
+    # Jx, Jy, Jz: views of one array, cleared by one fill per step
+    J_all = torch.zeros((3, grid["ny"], grid["nx"]), dtype=torch.float32, device="cuda")
+    J = [J_all[0], J_all[1], J_all[2]]
     start = {"em": ctx.save_start(lists["em"]), "ep": ctx.save_start(lists["ep"])}
 
     def pic_step(s, ev=None):
@@ -602,8 +604,7 @@ def cascade_once(args, torch, Q, W, prec, seed_offset=0, timed=True):
         ctx.step(segs, em, ep, G, s)
         if ev: ev[2].record()
         if deposit:
-            for j in J:
-                j.zero_()
+            J_all.zero_()
             ctx.deposit_current([(em, start["em"]), (ep, start["ep"])], grid, J, CASCADE_QSCALE)
         if ev: ev[3].record()
         if solver:
@@ -644,7 +645,7 @@ def cascade_once(args, torch, Q, W, prec, seed_offset=0, timed=True):
            "steps": steps, "solver": solver, "deposit": deposit, "grid": grid, "tuning": tuning,
            "deposit_path": dep_path}
     ctx.close()
-    del em, ep, G, J, comps, lists, spare
+    del em, ep, G, J, J_all, comps, lists, spare
     torch.cuda.empty_cache()
     return res
 
