@@ -619,29 +619,47 @@ def cascade_once(args, torch, Q, W, prec, seed_offset=0, timed=True):
     # launch shape of the lepton step for these lists (far below their capacity)
     tuning = ctx.autotune(segs, lists["em"], warm, reps=2)
     counts0 = tuple(lists[k].count for k in ("em", "ep", "G"))
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
-    ph_ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
-    ctx.set_photon_events(ph_ev)   # around the photon stage inside each qed_step
+    # HIP events of every timed step (five around the step's parts, two around the photon
+    # stage inside qed_step), read once after the loop: no synchronisation between steps,
+    # so the host queues ahead of the device as in a production loop and no stage waits
+    # for the host's launch of its first kernel
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(steps)]
+    ph_ev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(steps)]
+    for e in [x for row in ev + ph_ev for x in row]:
+        e.record()                 # creates the HIP event before the timed loop
+    torch.cuda.synchronize()
+    # what one timing marker itself adds to an interval: back-to-back records behind a busy
+    # kernel (each interval between two events holds one such marker's own time)
+    busy = torch.empty(1 << 26, dtype=torch.float32, device="cuda")
+    busy.fill_(1.0)
+    mk = [torch.cuda.Event(enable_timing=True) for _ in range(11)]
+    for e in mk:
+        e.record()
+    torch.cuda.synchronize()
+    marker_ms = sum(mk[i].elapsed_time(mk[i + 1]) for i in range(10)) / 10
+    del busy
     t_ph = t_all = t_f = t_d = t_sort = 0.0
     t0 = time.perf_counter()
-    for s in range(warm, warm + steps):
-        pic_step(s, ev if timed else None)
+    for k, s in enumerate(range(warm, warm + steps)):
         if timed:
-            torch.cuda.synchronize()
-            t_ph += ph_ev[0].elapsed_time(ph_ev[1])
-            t_sort += ev[0].elapsed_time(ev[1])
-            t_all += ev[0].elapsed_time(ev[4])
-            t_d += ev[2].elapsed_time(ev[3])
-            t_f += ev[3].elapsed_time(ev[4])
+            ctx.set_photon_events(ph_ev[k])
+        pic_step(s, ev[k] if timed else None)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ctx.set_photon_events(None)
+    if timed:
+        for e, p in zip(ev, ph_ev):
+            t_ph += p[0].elapsed_time(p[1])
+            t_sort += e[0].elapsed_time(e[1])
+            t_all += e[0].elapsed_time(e[4])
+            t_d += e[2].elapsed_time(e[3])
+            t_f += e[3].elapsed_time(e[4])
     em, ep, G = lists["em"], lists["ep"], lists["G"]
     counts1 = (em.count, ep.count, G.count)
     summary = cascade_summary(em, ep, G, 4000.0, torch)
     res = {"summary": summary, "counts0": counts0, "counts1": counts1, "status_bits": ctx.read_status(),
            "t_ph": t_ph, "t_all": t_all, "t_d": t_d, "t_f": t_f, "t_sort": t_sort, "sort_every": sort_every,
-           "wall": wall, "n": n, "warm": warm,
+           "wall": wall, "n": n, "warm": warm, "marker_ms": marker_ms,
            "steps": steps, "solver": solver, "deposit": deposit, "grid": grid, "tuning": tuning,
            "deposit_path": dep_path}
     ctx.close()
@@ -657,6 +675,7 @@ def cascade_rates(r, prec):
     ph_ms = r["t_ph"] / steps
     ph_bytes = (counts0[2] + counts1[2]) / 2 * BYTES_PHOTON_STEP[prec]
     gbs = ph_bytes / (ph_ms * 1e-3) / 1e9
+    gbs_net = ph_bytes / ((ph_ms - r["marker_ms"]) * 1e-3) / 1e9
     return {"particle_steps_per_s": (lep_steps + pho_steps) / (r["t_all"] * 1e-3),
             "photon_steps_per_s": pho_steps / (r["t_ph"] * 1e-3),
             "ms_per_step": r["t_all"] / steps, "photon_step_ms": ph_ms, "wall_ms_per_step": 1e3 * r["wall"] / steps,
@@ -664,7 +683,9 @@ def cascade_rates(r, prec):
                      "what": "photons, electrons, positrons reordered by 4 x 4-cell grid bin (stable; dead "
                              "photons dropped)"} if r["sort_every"] else None,
             "photon_step_roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                     "frac": gbs / HBM_PEAK_GBS, "bytes_per_photon_step": BYTES_PHOTON_STEP[prec]},
+                                     "frac": gbs / HBM_PEAK_GBS, "bytes_per_photon_step": BYTES_PHOTON_STEP[prec],
+                                     "frac_net_of_marker": gbs_net / HBM_PEAK_GBS},
+            "timing_marker_ms": r["marker_ms"],
             "counts_start": {"electrons": counts0[0], "positrons": counts0[1], "photons": counts0[2]},
             "counts_end": {"electrons": counts1[0], "positrons": counts1[1], "photons": counts1[2],
                            "photons_alive": r["summary"]["photons_alive"]},
