@@ -127,6 +127,10 @@ __global__ __launch_bounds__(BLOCK) void k_brems_events(BremsArgs a) {
         const EventRec &rec = a.stg[slot];
         const int64_t i = rec.idx;
         const double px = a.L.px[i], py = a.L.py[i], pz = a.L.pz[i];
+        // the photon's birth place and weight read here, with p: read after the stores below
+        // (which may alias them, for all the compiler knows) each would wait for the store
+        // before it, four round trips in a row
+        const double bx = a.L.x[i], by = a.L.y[i], bz = a.L.z[i], bw = a.L.w[i];
         const double pp = sqrt(px * px + py * py + pz * pz), E = sqrt(1.0 + pp * pp);
         int j;
         double w;
@@ -143,13 +147,13 @@ __global__ __launch_bounds__(BLOCK) void k_brems_events(BremsArgs a) {
         a.L.pz[i] = pz * s;
         const int64_t pos = base + e;
         if (pos >= a.G.capacity) return;
-        a.G.x[pos] = a.L.x[i];
-        a.G.y[pos] = a.L.y[i];
-        a.G.z[pos] = a.L.z[i];
+        a.G.x[pos] = bx;
+        a.G.y[pos] = by;
+        a.G.z[pos] = bz;
         a.G.kx[pos] = k * nx;
         a.G.ky[pos] = k * ny;
         a.G.kz[pos] = k * nz;
-        a.G.w[pos] = a.L.w[i];
+        a.G.w[pos] = bw;
         // unpolarised; basis e1 = unit(y_hat - (y_hat . n) n), else from z_hat
         double ex = -ny * nx, ey = 1.0 - ny * ny, ez = -ny * nz;
         double nn = ex * ex + ey * ey + ez * ez;

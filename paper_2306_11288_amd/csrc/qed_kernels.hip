@@ -559,6 +559,10 @@ __global__ __launch_bounds__(BLOCK) void k_leptons_events(LeptonArgs a) {
             V3<double> p = {o.p[0], o.p[1], o.p[2]};
             const V3<double> E = {o.E[0], o.E[1], o.E[2]}, B = {o.B[0], o.B[1], o.B[2]};
             V3<T> S = {o.S[0], o.S[1], o.S[2]};
+            // the photon's birth place and weight, read with the rest of the record: read after
+            // the lepton's write-back (which may alias the record, for all the compiler
+            // knows), each would wait for the store before it, four round trips in a row
+            const double bx = o.r[0], by = o.r[1], bz = o.r[2], bw = o.w;
             NcsFrame<T> f;
             ncs_frame<T>(a.c, tb.ncs_rate(), q, p, rsqrt(1.0 + dot(p, p)), S, E, B, st, f);
             double rr[4];
@@ -587,9 +591,9 @@ __global__ __launch_bounds__(BLOCK) void k_leptons_events(LeptonArgs a) {
             store_s<T>(a, (uint32_t)i * (uint32_t)sizeof(T), S);
             const int64_t pos = obase + ge;
             if (a.has_out && pos < a.out.capacity) {
-                a.out.x[pos] = o.r[0]; a.out.y[pos] = o.r[1]; a.out.z[pos] = o.r[2];
+                a.out.x[pos] = bx; a.out.y[pos] = by; a.out.z[pos] = bz;
                 a.out.kx[pos] = ph.k.x; a.out.ky[pos] = ph.k.y; a.out.kz[pos] = ph.k.z;
-                a.out.w[pos] = o.w;
+                a.out.w[pos] = bw;
                 ((T *)a.out.xi1)[pos] = ph.xi.x; ((T *)a.out.xi2)[pos] = ph.xi.y; ((T *)a.out.xi3)[pos] = ph.xi.z;
                 ((T *)a.out.e1x)[pos] = ph.e1.x; ((T *)a.out.e1y)[pos] = ph.e1.y; ((T *)a.out.e1z)[pos] = ph.e1.z;
                 a.out.id[pos] = (unsigned long long)(id0 + ge);
