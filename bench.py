@@ -578,14 +578,17 @@ def cascade_once(args, torch, Q, W, prec, seed_offset=0, timed=True):
     lists = {"em": Q.Leptons.from_state(st, capacity=cap_l, charge=-1, precision=precision),
              "ep": Q.Leptons(cap_l, 1, precision=precision), "G": Q.Photons(cap_g, precision=precision)}
     sort_every = args.sort_every
+    # the lepton lists are short beside the photons' and feed the deposition, whose
+    # 256-particle blocks want compact boxes: they may be sorted more often
+    sort_lep = args.sort_leptons_every
     spare = ({"em": Q.Leptons(cap_l, -1, precision=precision), "ep": Q.Leptons(cap_l, 1, precision=precision),
-              "G": Q.Photons(cap_g, precision=precision)} if sort_every > 0 else None)
+              "G": Q.Photons(cap_g, precision=precision)} if (sort_every > 0 or sort_lep > 0) else None)
     segs = Q.whole(spec)
     warm, steps = args.cascade_warmup, args.cascade_steps
     solver = not args.static_grid
     deposit = solver and not args.no_deposit
     # the lists are kept in cell order by the periodic sort: the local deposition path
-    dep_path = "local" if (sort_every > 0 and args.deposit_path == "local") else "binned"
+    dep_path = "local" if (sort_lep > 0 and args.deposit_path == "local") else "binned"
     ctx.set_deposit_path(Q.DEPOSIT_LOCAL if dep_path == "local" else Q.DEPOSIT_BINNED)
     # Jx, Jy, Jz: views of one array, cleared by one fill per step
     J_all = torch.zeros((3, grid["ny"], grid["nx"]), dtype=torch.float32, device="cuda")
@@ -593,15 +596,16 @@ def cascade_once(args, torch, Q, W, prec, seed_offset=0, timed=True):
     start = {"em": ctx.save_start(lists["em"]), "ep": ctx.save_start(lists["ep"])}
 
     def pic_step(s, ev=None):
-        """every sort_every steps, the lists reordered by grid bin (4 x 4 cells; dead photons
-        dropped); save the lepton positions; the QED step in the order of the Spin-QED chain
+        """every sort_every steps the photons, every sort_lep steps the leptons, reordered by
+        grid bin (4 x 4 cells; dead photons dropped); save the lepton positions; the QED step in the order of the Spin-QED chain
         (pairs born this step are pushed and deposited from the next step on); current; field"""
         if ev: ev[0].record()
         if sort_every > 0 and s % sort_every == 0:
             ctx.sort_photons(lists["G"], spare["G"], spec, 4)
-            ctx.sort_leptons(lists["em"], spare["em"], spec, 4)
-            ctx.sort_leptons(lists["ep"], spare["ep"], spec, 4)
-            for k in lists:
+            lists["G"], spare["G"] = spare["G"], lists["G"]
+        if sort_lep > 0 and s % sort_lep == 0:
+            for k in ("em", "ep"):
+                ctx.sort_leptons(lists[k], spare[k], spec, 4)
                 lists[k], spare[k] = spare[k], lists[k]
         if ev: ev[1].record()
         em, ep, G = lists["em"], lists["ep"], lists["G"]
@@ -665,7 +669,7 @@ def cascade_once(args, torch, Q, W, prec, seed_offset=0, timed=True):
     counts1 = (em.count, ep.count, G.count)
     summary = cascade_summary(em, ep, G, 4000.0, torch)
     res = {"summary": summary, "counts0": counts0, "counts1": counts1, "status_bits": ctx.read_status(),
-           "t_ph": t_ph, "t_all": t_all, "t_d": t_d, "t_f": t_f, "t_sort": t_sort, "sort_every": sort_every,
+           "t_ph": t_ph, "t_all": t_all, "t_d": t_d, "t_f": t_f, "t_sort": t_sort, "sort_every": sort_every, "sort_lep": sort_lep,
            "wall": wall, "n": n, "warm": warm, "marker_ms": marker_ms,
            "steps": steps, "solver": solver, "deposit": deposit, "grid": grid, "tuning": tuning,
            "deposit_path": dep_path}
@@ -686,9 +690,11 @@ def cascade_rates(r, prec):
     return {"particle_steps_per_s": (lep_steps + pho_steps) / (r["t_all"] * 1e-3),
             "photon_steps_per_s": pho_steps / (r["t_ph"] * 1e-3),
             "ms_per_step": r["t_all"] / steps, "photon_step_ms": ph_ms, "wall_ms_per_step": 1e3 * r["wall"] / steps,
-            "sort": {"every_steps": r["sort_every"], "ms_per_step": r["t_sort"] / steps,
-                     "what": "photons, electrons, positrons reordered by 4 x 4-cell grid bin (stable; dead "
-                             "photons dropped)"} if r["sort_every"] else None,
+            "sort": {"every_steps": r["sort_every"], "leptons_every_steps": r["sort_lep"],
+                     "ms_per_step": r["t_sort"] / steps,
+                     "what": "photons (every_steps) and electrons, positrons (leptons_every_steps) reordered "
+                             "by 4 x 4-cell grid bin (stable; dead photons dropped)"}
+            if (r["sort_every"] or r["sort_lep"]) else None,
             "photon_step_roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                      "frac": gbs / HBM_PEAK_GBS, "bytes_per_photon_step": BYTES_PHOTON_STEP[prec],
                                      "frac_net_of_marker": gbs_net / HBM_PEAK_GBS},
@@ -982,6 +988,8 @@ def main():
     ap.add_argument("--cascade-warmup", type=int, default=150)
     ap.add_argument("--sort-every", type=int, default=20,
                     help="cascade: reorder the particle lists by grid bin every N steps (0: never)")
+    ap.add_argument("--sort-leptons-every", type=int, default=10,
+                    help="cascade: reorder the lepton lists by grid bin every N steps (0: never)")
     ap.add_argument("--cascade-mixed-only", action="store_true",
                     help="cascade: only the timed mixed-precision run (no FP64 runs, no error metrics)")
     ap.add_argument("--full-steps", type=int, default=6000,
