@@ -15,6 +15,7 @@ namespace {
 
 constexpr int64_t MAX_TILES = 1 << 20;   // ordered-append tiles: lists up to 2^28 particles
 constexpr int64_t GROUP_TOT_LEN = MAX_TILES / 4 + 1;   // the smallest event group is 4 tiles
+static_assert(MAX_TILES / PH_GROUP + 1 <= PH_GROUPS_MAX, "photon event groups of the largest list");
 
 qed_status fail(qed_ctx *ctx, qed_status code, const char *fmt, ...) {
     if (ctx) {
@@ -241,6 +242,7 @@ void free_ctx(qed_ctx *c) {
     hipFree(c->next_id);
     hipFree(c->tile_counts);
     hipFree(c->group_tot);
+    hipFree(c->ph_tot);
     hipFree(c->tile_off);
     hipFree(c->launch);
     hipFree(c->lep_start);
@@ -328,8 +330,9 @@ qed_status qed_init_tables(qed_ctx_t **out, const qed_config *cfg, hipStream_t s
                     hipMalloc(&c->next_id, sizeof(unsigned long long)) == hipSuccess &&
                     hipMalloc(&c->tile_counts, MAX_TILES * sizeof(int)) == hipSuccess &&
                     hipMalloc(&c->group_tot, GROUP_TOT_LEN * sizeof(int)) == hipSuccess &&
+                    hipMalloc(&c->ph_tot, PH_TOT_LEN * sizeof(int)) == hipSuccess &&
                     hipMalloc(&c->tile_off, (MAX_TILES + 1) * sizeof(int64_t)) == hipSuccess &&
-                    hipMalloc(&c->launch, 4 * sizeof(int64_t)) == hipSuccess &&
+                    hipMalloc(&c->launch, 8 * sizeof(int64_t)) == hipSuccess &&
                     hipMalloc(&c->lep_start, 2 * sizeof(int64_t)) == hipSuccess &&
                     hipMalloc(&c->scan_sums, SCAN_MAX_BLOCKS * sizeof(int64_t)) == hipSuccess &&
                     hipEventCreateWithFlags(&c->seg_copied, hipEventDisableTiming) == hipSuccess;
@@ -338,8 +341,9 @@ qed_status qed_init_tables(qed_ctx_t **out, const qed_config *cfg, hipStream_t s
         return QED_ENOMEM;
     }
     e = hipMemsetAsync(c->status, 0, sizeof(uint32_t), s);
-    if (e == hipSuccess) e = hipMemsetAsync(c->launch, 0, 4 * sizeof(int64_t), s);
+    if (e == hipSuccess) e = hipMemsetAsync(c->launch, 0, 8 * sizeof(int64_t), s);
     if (e == hipSuccess) e = hipMemsetAsync(c->group_tot, 0, GROUP_TOT_LEN * sizeof(int), s);
+    if (e == hipSuccess) e = hipMemsetAsync(c->ph_tot, 0, PH_TOT_LEN * sizeof(int), s);
     if (e == hipSuccess) {
         const unsigned long long v = cfg->id_start;
         e = hipMemcpyAsync(c->next_id, &v, sizeof v, hipMemcpyHostToDevice, s);

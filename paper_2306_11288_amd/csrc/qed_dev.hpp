@@ -171,6 +171,13 @@ __device__ __forceinline__ int wave_min_i(int v) {
     v = min(v, __builtin_amdgcn_update_dpp(ID, v, 0x143, 0xc, 0xf, false));   // row_bcast:31
     return __builtin_amdgcn_readlane(v, 63);
 }
+// sum over the wavefront (all 64 lanes active); every lane gets the total
+__device__ __forceinline__ int64_t wave_sum_i64(int64_t v) {
+    long long x = (long long)v;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d);
+    return (int64_t)x;
+}
 template <class FT>
 __device__ __forceinline__ bool grid_fields_wavebox(const GridDev &f, float *box, bool live, double x, double y,
                                                     V3<double> &E, V3<double> &B) {

@@ -113,8 +113,8 @@ struct DevSegment {
     FieldDev f;
 };
 
-// staging record of one photon event (decide kernel -> event kernel): particle index and
-// the fields of x^n at which the event was decided
+// staging record of one event of the compaction or bremsstrahlung kernels (decide kernel ->
+// event kernel): particle index and up to six values the event needs
 struct EventRec {
     long long idx;
     double f[6];
@@ -208,6 +208,13 @@ struct PhotonEvent {
     T xi[3], e1[3], kappa;
 };
 
+// photon stage: pair events are counted per group of PH_GROUP tiles and per 64 groups
+// (lists of at most 2^28 photons)
+constexpr int PH_GROUP = 32;
+constexpr int64_t PH_GROUPS_MAX = ((int64_t)1 << 20) / PH_GROUP + 1;
+constexpr int64_t PH_SUPER_MAX = PH_GROUPS_MAX / 64 + 1;
+constexpr int64_t PH_TOT_LEN = 2 * PH_GROUPS_MAX + 2 * PH_SUPER_MAX + 3;
+
 // bytes of one staging slot: the largest record any kernel parks there
 constexpr size_t STAGING_SLOT = sizeof(LepEvent<double>) > sizeof(EventRec) ? sizeof(LepEvent<double>)
                                                                              : sizeof(EventRec);
@@ -228,10 +235,14 @@ struct qed_ctx {
     uint32_t *status;                  // sticky status word
     unsigned long long *next_id;       // id counter
     int *tile_counts;                  // events per 256-particle tile   [max_tiles]
+    int *ph_tot;                       // photon stage: pair events per group of PH_GROUP tiles
+                                       // [2][PH_GROUPS_MAX], then per 64 groups [2][PH_SUPER_MAX]
+                                       // (two parities), the parity and the groups each used [3]
     int *group_tot;                    // events per group of ev_group tiles [max_tiles / 4 + 1];
                                        // zero between launches (the scan clears what it reads)
     int64_t *tile_off;                 // exclusive prefix of tile_counts [max_tiles + 1]
-    int64_t *launch;                   // bases of the last append launch [4]
+    int64_t *launch;                   // bases of the last append launch [8]: out0, out1, id, events;
+                                       // [4] the photon stage's parity
     int64_t *scan_sums;                // block totals of the prefix scan [SCAN_MAX_BLOCKS]
     int64_t *lep_start;                // lepton counts before the pair appends of qed_step [2]
     void *na_scratch;                  // device address of this device's allocation-free scratch array

@@ -623,12 +623,14 @@ struct PhotonArgs {
     uint32_t *status;
     EventRec *stg;
     int *tile_counts;
-    int *group_tot;            // events per group of PH_GROUP tiles (zero between launches)
-    const int64_t *tile_off;   // exclusive prefix of group_tot
-    const int64_t *launch;
+    int *ph_tot;               // pair events per group and per 64 groups, two parities (ctx)
+    int64_t *launch;           // [0] em base, [1] ep base, [2] id base, [3] pairs, [4] parity
+    int64_t *base_out;         // optional [2]: the lepton counts before the append
+    unsigned long long *next_id;
     float *ev_in;              // learned NBW sampler: per-pair network inputs [pairs][4]
     const float *ev_out;       // and outputs [pairs][3]
     int ev_net;                // pair events: the network's delta used where valid
+    int ev_update;             // pair events: this pass sets the counts, the id counter, the parity
 };
 
 // transport (+ NBW test), specialised on the field kind: a persistent grid sweeps the
@@ -646,9 +648,17 @@ struct PhotonTabsLds {
 };
 
 // FP64: held to four wavefronts per SIMD (at most 128 VGPRs)
-// pairs are rare (well under one per tile): the event kernel takes groups of PH_GROUP tiles,
-// one per wavefront, and the event scan runs over these groups
-constexpr int PH_GROUP = 32;
+// Pair events are rare (well under one per tile).  The decide kernel adds each tile's count
+// to its group of PH_GROUP tiles and to its run of 64 groups (integer atomics: the sums do
+// not depend on their order), in the buffers of the current parity; the event kernel, one
+// wavefront per group, takes the group's first rank from those sums itself (no scan
+// launch).  The buffers of the other parity, read by the previous stage's event kernel,
+// are cleared by this stage's decide kernel, and the event kernel flips the parity.  Block
+// 0 of the decide kernel also records the lepton counts and the id counter before the
+// append, which the event kernel's wavefronts read while its wavefront 0 advances them.
+__device__ __forceinline__ int *ph_groups(int *t, int p) { return t + p * PH_GROUPS_MAX; }
+__device__ __forceinline__ int *ph_super(int *t, int p) { return t + 2 * PH_GROUPS_MAX + p * PH_SUPER_MAX; }
+__device__ __forceinline__ int *ph_state(int *t) { return t + 2 * PH_GROUPS_MAX + 2 * PH_SUPER_MAX; }
 template <class T, bool NBW, int FK>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 4 : 1))) void k_photons_decide(PhotonArgs a) {
     __shared__ int s_wave[2][BLOCK / 64];
@@ -658,6 +668,30 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(T)
     // 32-bit indices: lists hold at most 2^28 particles
     const int n = (int)clamp_count(a.G.count, a.G.capacity);
     const int ntiles = (n + BLOCK - 1) / BLOCK;
+    int ph_par = 0;
+    if constexpr (NBW) {   // the pair-event bookkeeping (before any block leaves)
+        int *state = ph_state(a.ph_tot);
+        ph_par = state[0];
+        const int q = 1 - ph_par;
+        // groups [0, used) and their runs of 64 (used <= 2^15: inside the buffers)
+        const int64_t used = state[1 + q], uses = (used + 63) / 64;
+        int *og = ph_groups(a.ph_tot, q), *os = ph_super(a.ph_tot, q);
+        for (int64_t u = (int64_t)blockIdx.x * BLOCK + threadIdx.x; u < used; u += (int64_t)gridDim.x * BLOCK)
+            og[u] = 0;
+        for (int64_t u = (int64_t)blockIdx.x * BLOCK + threadIdx.x; u < uses; u += (int64_t)gridDim.x * BLOCK)
+            os[u] = 0;
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            const int64_t b0 = a.has_em ? *a.em.count : 0, b1 = a.has_ep ? *a.ep.count : 0;
+            a.launch[0] = b0;
+            a.launch[1] = b1;
+            a.launch[2] = (int64_t)*a.next_id;
+            a.launch[4] = ph_par;
+            if (a.base_out) {
+                a.base_out[0] = b0;
+                a.base_out[1] = b1;
+            }
+        }
+    }
     if ((int)blockIdx.x >= ntiles) return;
     {
         const Tabs<T> tg = {(const T *)a.tab};
@@ -736,7 +770,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(T)
             if (ev) *event_index(a.stg, (int64_t)tile * BLOCK + rank) = j;
             if (threadIdx.x == 0) {
                 a.tile_counts[tile] = total;
-                if (total) atomicAdd(a.group_tot + tile / PH_GROUP, total);
+                if (total) {
+                    atomicAdd(ph_groups(a.ph_tot, ph_par) + tile / PH_GROUP, total);
+                    atomicAdd(ph_super(a.ph_tot, ph_par) + tile / (PH_GROUP * 64), total);
+                }
             }
         }
     }
@@ -752,13 +789,45 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(T)
 template <class T, int MODE>
 __global__ __launch_bounds__(BLOCK) void k_photons_events(PhotonArgs a) {
     const int64_t n = clamp_count(a.G.count, a.G.capacity);
-    const int64_t ntiles = (n + BLOCK - 1) / BLOCK;
-    const int64_t t0 = ((int64_t)blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6)) * PH_GROUP;
+    const int64_t ntiles = (n + BLOCK - 1) / BLOCK, ngroups = (ntiles + PH_GROUP - 1) / PH_GROUP;
+    const int64_t wv = (int64_t)blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6), t0 = wv * PH_GROUP;
+    const int lane = threadIdx.x & 63;
+    const int p = (int)a.launch[4];
+    const int *gt = ph_groups(a.ph_tot, p), *su = ph_super(a.ph_tot, p);
+    if (wv == 0 && a.ev_update) {   // the append: new counts, id counter, pair total, parity
+        int64_t tot = 0;
+        for (int64_t u = lane; u < (ngroups + 63) / 64; u += 64) tot += su[u];
+        tot = wave_sum_i64(tot);
+        if (lane == 0) {
+            uint32_t so = 0;
+            const qed_leptons *Ls[2] = {&a.em, &a.ep};
+            const int has[2] = {a.has_em, a.has_ep};
+            for (int k = 0; k < 2; ++k) {
+                if (!has[k]) continue;
+                const int64_t c = a.launch[k] + tot;
+                if (c > Ls[k]->capacity) so |= QED_ST_OVERFLOW;
+                *Ls[k]->count = c < Ls[k]->capacity ? c : Ls[k]->capacity;
+            }
+            *a.next_id = (unsigned long long)a.launch[2] + 2ull * (unsigned long long)tot;
+            a.launch[3] = tot;
+            int *state = ph_state(a.ph_tot);
+            state[0] = 1 - p;
+            state[1 + p] = (int)ngroups;
+            if (so) atomicOr(a.status, so);
+        }
+    }
     if (t0 >= ntiles) return;
+    // the group's first rank: its runs of 64 groups before it, then its own run's groups
+    // before it
+    const int64_t sg = wv / 64;
+    int64_t pre = 0;
+    for (int64_t u = lane; u < sg; u += 64) pre += su[u];
+    if (sg * 64 + lane < wv) pre += gt[sg * 64 + lane];
+    pre = wave_sum_i64(pre);
     const int64_t id0 = a.launch[2];
     const Tabs<T> tb = {(const T *)a.tab};
     uint32_t st = 0;
-    group_events<PH_GROUP>(a.tile_counts, a.tile_off[t0 / PH_GROUP], ntiles, t0, [&](int64_t e, int64_t slot) {
+    group_events<PH_GROUP>(a.tile_counts, pre, ntiles, t0, [&](int64_t e, int64_t slot) {
         // the decide kernel's record of the event (no frame, rate or generator recomputed:
         // one lane's chain of dependent reads and arithmetic is this kernel's time)
         const int64_t j = *event_index(a.stg, slot);
@@ -1054,7 +1123,7 @@ static void launch_photons_decide(const qed_ctx *ctx, const PhotonArgs &a, hipSt
     else hipLaunchKernelGGL((k_photons_decide<T, true, FK>), gd, dim3(BLOCK), 0, s, a);
 }
 template <class T>
-static hipError_t launch_photons_stage(qed_ctx *ctx, const PhotonArgs &a, hipStream_t s, int64_t *lep_start) {
+static hipError_t launch_photons_stage(qed_ctx *ctx, const PhotonArgs &a, hipStream_t s) {
     switch (a.field.kind) {
     case QED_FIELD_CONST: launch_photons_decide<T, QED_FIELD_CONST>(ctx, a, s); break;
     case QED_FIELD_PW: launch_photons_decide<T, QED_FIELD_PW>(ctx, a, s); break;
@@ -1064,37 +1133,34 @@ static hipError_t launch_photons_stage(qed_ctx *ctx, const PhotonArgs &a, hipStr
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !a.do_nbw) return e;
-    // over the groups' totals (zeroed by the scan for the next launch): a list of up to
-    // 2^26 photons takes one scan launch
-    e = launch_scan(ctx, a.G.count, a.G.capacity, a.group_tot, a.has_em ? a.em.count : nullptr,
-                    a.has_em ? a.em.capacity : 0, a.has_ep ? a.ep.count : nullptr, a.has_ep ? a.ep.capacity : 0, 2, s,
-                    0, lep_start, nullptr, nullptr, BLOCK * PH_GROUP, nullptr, 1);
-    if (e != hipSuccess) return e;
+    // no scan launch: the event kernel ranks the groups itself (k_photons_decide)
     const int64_t groups = (a.G.capacity + (int64_t)BLOCK * PH_GROUP - 1) / ((int64_t)BLOCK * PH_GROUP);
     const int64_t nb = (groups + BLOCK / 64 - 1) / (BLOCK / 64);
     const dim3 gd((unsigned)(nb < 1 ? 1 : nb));
     PhotonArgs b = a;
     b.ev_net = (ctx->sampler & QED_SAMPLER_MLP_NBW) != 0;
+    b.ev_update = 1;
     if (b.ev_net) {
-        // learned delta: the network's inputs of every pair at its rank, the network over
-        // the device pair count, then the events
+        // learned delta: the network's inputs of every pair at its rank (this pass also
+        // makes the append), the network over the device pair count, then the events
         hipLaunchKernelGGL((k_photons_events<T, EV_PREP>), gd, dim3(BLOCK), 0, s, b);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if ((e = mlp_forward(ctx, ctx->nets[QED_NET_NBW], b.ev_in, ctx->ev_out, 0, b.launch + 3, b.G.capacity, s)) !=
             hipSuccess)
             return e;
+        b.ev_update = 0;
     }
     hipLaunchKernelGGL((k_photons_events<T, EV_FINISH>), gd, dim3(BLOCK), 0, s, b);
     return hipGetLastError();
 }
 
 template <class T>
-static hipError_t launch_photons_t(qed_ctx *ctx, const PhotonArgs &a, hipStream_t s, int64_t *lep_start) {
+static hipError_t launch_photons_t(qed_ctx *ctx, const PhotonArgs &a, hipStream_t s) {
     if (ctx->ph_ev_on) {
         const hipError_t e = hipEventRecord(ctx->ph_ev[0], s);
         if (e != hipSuccess) return e;
     }
-    hipError_t e = launch_photons_stage<T>(ctx, a, s, lep_start);
+    hipError_t e = launch_photons_stage<T>(ctx, a, s);
     if (e == hipSuccess && ctx->ph_ev_on) e = hipEventRecord(ctx->ph_ev[1], s);
     return e;
 }
@@ -1118,17 +1184,18 @@ hipError_t launch_photons(qed_ctx *ctx, PhotonMode mode, const SegArgs &sa, cons
     a.status = ctx->status;
     a.stg = (EventRec *)ctx->staging;
     a.tile_counts = ctx->tile_counts;
-    a.group_tot = ctx->group_tot;
-    a.tile_off = ctx->tile_off;
+    a.ph_tot = ctx->ph_tot;
     a.launch = ctx->launch;
+    a.base_out = lep_start;
+    a.next_id = ctx->next_id;
     a.ev_in = ctx->ev_in;
     a.ev_out = ctx->ev_out;
     if (ctx->cfg.precision == QED_MIXED) {
         a.tab = ctx->tab32;
-        return launch_photons_t<float>(ctx, a, s, lep_start);
+        return launch_photons_t<float>(ctx, a, s);
     }
     a.tab = ctx->tab64;
-    return launch_photons_t<double>(ctx, a, s, lep_start);
+    return launch_photons_t<double>(ctx, a, s);
 }
 
 template <class T>

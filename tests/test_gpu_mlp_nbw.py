@@ -202,3 +202,34 @@ def test_shipped_network_in_the_pair_step(shipped, precision):
     hn, _ = np.histogram(dn, bins=20, range=(0, 1))
     ht, _ = np.histogram(dt, bins=20, range=(0, 1))
     assert np.abs(hn - ht).sum() < 0.05 * len(par)
+
+
+def test_pair_append_overflow():
+    """Lepton lists too short for the pairs of the run: the counts stop at the capacity, the
+    overflow bit is set, the ids are still consumed, and the pairs that fit are those of the
+    run with room for all (the append is the event kernel's own bookkeeping: group ranks,
+    counts, id counter)."""
+    _say("pair append overflow")
+
+    def run(cap):
+        st = W.photons(40000, seed=44, eps0=3000.0, eps_rel_spread=0.2, divergence=2e-3, x_mean=-2.0, x_sigma=1.0,
+                       r_sigma=1.0, id0=0)
+        spec = {"kind": W.FIELD_PW, "circular": 0, "a0": 300.0, "ncycles": 8.0, "phase0": 0.3, "pol_angle": 0.4,
+                "phi_start": 0.0}
+        c = _nbw_ctx(Q.QED_FP64, dt=W.TWO_PI / 500, procs=Q.PROC_VB | Q.PROC_NBW, seed=9, id_start=1 << 41)
+        G = Q.Photons.from_state(st, precision=Q.QED_FP64)
+        em, ep = Q.Leptons(cap, -1, precision=Q.QED_FP64), Q.Leptons(cap, 1, precision=Q.QED_FP64)
+        for s in range(2000, 2040):
+            c.step_photons(Q.whole(spec), G, em, ep, s)
+        return c, em.to_numpy(), ep.to_numpy(), G.to_numpy()
+
+    cf, emf, epf, Gf = run(40000)
+    cc, emc, epc, Gc = run(1000)
+    assert len(epf["x"]) > 3000 and cf.read_status() == 0
+    assert len(emc["x"]) == 1000 and len(epc["x"]) == 1000
+    assert cc.read_status() & Q.ST_OVERFLOW
+    assert cc.next_id() == cf.next_id()
+    for L, Lf in ((emc, emf), (epc, epf)):
+        for key in ("id", "x", "y", "z", "px", "py", "pz", "sx", "sy", "sz", "w"):
+            assert np.array_equal(L[key], Lf[key][:1000]), key
+    assert np.array_equal(Gc["alive"], Gf["alive"])
